@@ -1,0 +1,370 @@
+"""Pins of the CPU oracle against what the paper's definitions and plain
+mathematics fix (no GPU).  Each test names the definition it follows:
+Sect. 2 (atoms, Boolean operators, N, rho, derived operators), Sect. 3 (rho
+computed through connected components; the CCL invariant).
+"""
+import itertools
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from tests import brute
+
+K3 = np.ones((3, 3), bool)
+
+
+def rand_mask(rng, h, w, p=0.5):
+    return (rng.random((h, w)) < p).astype(np.uint8)
+
+
+def all_masks(h, w):
+    for bits in range(1 << (h * w)):
+        yield np.array([(bits >> i) & 1 for i in range(h * w)], np.uint8).reshape(h, w)
+
+
+def z_closed_form(a, b):
+    """Union of the 8-components of b that meet N a (Sect. 3, rho via CCL)."""
+    lab, n = ndimage.label(b, structure=K3)
+    na = ndimage.binary_dilation(a, structure=K3, border_value=0)
+    hit = np.unique(lab[(na > 0) & (b > 0)])
+    return np.isin(lab, hit[hit > 0]).astype(np.uint8)
+
+
+# ---------------------------------------------------------------- atoms
+
+@pytest.mark.parametrize("op", [">", "<", ">=", "<="])
+def test_threshold_f32_matches_numpy(op):
+    rng = np.random.default_rng(1)
+    img = rng.random((2, 17, 23)).astype(np.float32)
+    t = 0.1  # not representable: rounded once to float32
+    img[1, 3, 4] = np.float32(t)  # a pixel exactly at the rounded threshold
+    ref = {">": np.greater, "<": np.less, ">=": np.greater_equal, "<=": np.less_equal}[op]
+    for c in (0, 1):
+        got = oracle.threshold(img, c, op, t)
+        want = ref(img[c], np.float32(t)).astype(np.uint8)
+        assert np.array_equal(got, want)
+
+
+def test_threshold_rounds_constant_once_to_float32():
+    # 0.1 as double lies between two float32 values; the pixel equal to
+    # float32(0.1) is not > float32(0.1) but is >= it.
+    img = np.full((1, 1, 3), np.float32(0.1), np.float32)
+    img[0, 0, 1] = np.nextafter(np.float32(0.1), np.float32(1))
+    img[0, 0, 2] = np.nextafter(np.float32(0.1), np.float32(0))
+    assert oracle.threshold(img, 0, ">", 0.1).tolist() == [[0, 1, 0]]
+    assert oracle.threshold(img, 0, ">=", 0.1).tolist() == [[1, 1, 0]]
+    src = 'output "a" intensity(img) >. 0.1\noutput "b" intensity(img) >=. 0.1'
+    a, b = oracle.run(src, img)
+    assert a.tolist() == [[0, 1, 0]] and b.tolist() == [[1, 1, 0]]
+
+
+def test_threshold_u8_exact():
+    img = np.arange(256, dtype=np.uint8).reshape(1, 16, 16)
+    got = oracle.threshold(img, 0, ">", 127.5)
+    assert np.array_equal(got, (img[0] > 127).astype(np.uint8))
+    got = oracle.threshold(img, 0, ">=", 128)
+    assert np.array_equal(got, (img[0] >= 128).astype(np.uint8))
+
+
+@pytest.mark.parametrize("q", [0.0, 1e-9, 0.01, 0.3, 0.5, 0.86, 0.95, 0.999, 1.0])
+def test_percentile_nearest_rank(q):
+    rng = np.random.default_rng(7)
+    img = rng.random((2, 13, 31)).astype(np.float32)
+    img[1, :3] = 0.25  # ties
+    for c in (0, 1):
+        v = np.sort(img[c].reshape(-1))
+        n = v.size
+        k = min(max(int(np.ceil(q * n)) - 1, 0), n - 1)
+        assert oracle.percentile(img, c, q) == v[k]
+
+
+def test_percentile_u8_and_threshold_use():
+    rng = np.random.default_rng(8)
+    img = rng.integers(0, 256, (1, 20, 20), dtype=np.uint8)
+    t = np.sort(img.reshape(-1))[int(np.ceil(0.9 * 400)) - 1]
+    assert oracle.percentile(img, 0, 0.9) == np.float32(t)
+    (m,) = oracle.run('output "m" intensity(img) >. percentile(img, 0, 0.9)', img)
+    assert np.array_equal(m, (img[0] > t).astype(np.uint8))
+
+
+# ---------------------------------------------------------------- Boolean operators
+
+def test_boolean_truth_tables():
+    a = np.array([[0, 0, 1, 1]], np.uint8)
+    b = np.array([[0, 1, 0, 1]], np.uint8)
+    assert oracle.lnot(a).tolist() == [[1, 1, 0, 0]]
+    assert oracle.land(a, b).tolist() == [[0, 0, 0, 1]]
+    assert oracle.lor(a, b).tolist() == [[0, 1, 1, 1]]
+    img = np.stack([a, b]).astype(np.float32)
+    src = ('let A = intensity(img, 0) >. 0.5\nlet B = intensity(img, 1) >. 0.5\n'
+           'output "not" !A\noutput "and" A & B\noutput "or" A | B\n'
+           'output "t" true\noutput "f" false\noutput "prec" !A & B | A & !B')
+    n, an, o, t, f, x = oracle.run(src, img)
+    assert n.tolist() == [[1, 1, 0, 0]] and an.tolist() == [[0, 0, 0, 1]]
+    assert o.tolist() == [[0, 1, 1, 1]] and t.tolist() == [[1] * 4] and f.tolist() == [[0] * 4]
+    assert x.tolist() == [[0, 1, 1, 0]]  # '!' binds tighter than '&', '&' than '|'
+
+
+# ---------------------------------------------------------------- near
+
+def test_near_bruteforce_and_scipy():
+    rng = np.random.default_rng(2)
+    for h, w in [(1, 1), (1, 5), (5, 1), (2, 2), (3, 7), (6, 6)]:
+        for _ in range(20):
+            a = rand_mask(rng, h, w, rng.uniform(0.05, 0.6))
+            assert np.array_equal(oracle.near(a), brute.near(a))
+    for h, w in [(64, 64), (65, 127), (129, 63)]:
+        a = rand_mask(rng, h, w, 0.1)
+        want = ndimage.binary_dilation(a, structure=K3, border_value=0).astype(np.uint8)
+        assert np.array_equal(oracle.near(a), want)
+
+
+def test_near_invariants():
+    rng = np.random.default_rng(3)
+    for _ in range(30):
+        a = rand_mask(rng, 9, 11, 0.2)
+        b = a | rand_mask(rng, 9, 11, 0.2)
+        na = oracle.near(a)
+        assert np.all(na >= a)                       # extensive
+        assert np.all(oracle.near(b) >= na)          # monotone
+    one = np.zeros((5, 5), np.uint8)
+    one[0, 0] = 1
+    assert oracle.near(one).sum() == 4               # corner: no pixels outside
+    one[0, 0], one[2, 2] = 0, 1
+    assert oracle.near(one).sum() == 9
+
+
+def test_interior_is_erosion_with_border_kept():
+    rng = np.random.default_rng(4)
+    for h, w in [(1, 1), (4, 9), (33, 17)]:
+        for _ in range(10):
+            a = rand_mask(rng, h, w, 0.8)
+            want = ndimage.binary_erosion(a, structure=K3, border_value=1).astype(np.uint8)
+            got = oracle.interior(a)
+            assert np.array_equal(got, want)
+            assert np.all(got <= a)
+            assert np.array_equal(got, 1 - oracle.near(1 - a))
+    full = np.ones((4, 6), np.uint8)
+    assert np.array_equal(oracle.interior(full), full)
+
+
+# ---------------------------------------------------------------- reach
+
+def test_reach_exhaustive_small_against_path_enumeration():
+    # every pair of masks on 2x3 and 3x2 images
+    for h, w in [(2, 3), (3, 2)]:
+        masks = list(all_masks(h, w))
+        for a, b in itertools.product(masks, masks):
+            assert np.array_equal(oracle.reach(a, b), brute.reach_paths(a, b)), (a, b)
+
+
+def test_reach_random_against_paths_and_walks():
+    rng = np.random.default_rng(5)
+    for h, w in [(3, 3), (4, 4), (3, 5)]:
+        for _ in range(120):
+            a = rand_mask(rng, h, w, rng.uniform(0.0, 0.3))
+            b = rand_mask(rng, h, w, rng.uniform(0.2, 0.7))
+            got = oracle.reach(a, b)
+            assert np.array_equal(got, brute.reach_paths(a, b))
+            assert np.array_equal(got, brute.reach_walks(a, b))
+    for h, w in [(5, 5), (6, 7), (8, 8)]:
+        for _ in range(40):
+            a = rand_mask(rng, h, w, rng.uniform(0.0, 0.15))
+            b = rand_mask(rng, h, w, rng.uniform(0.3, 0.7))
+            assert np.array_equal(oracle.reach(a, b), brute.reach_walks(a, b))
+
+
+def test_reach_equals_ccl_closed_form():
+    # rho a[b] = N(a | Z), Z = components of b meeting N a (Sect. 3)
+    rng = np.random.default_rng(6)
+    for h, w in [(1, 9), (9, 1), (16, 16), (31, 65), (64, 70)]:
+        for _ in range(15):
+            a = rand_mask(rng, h, w, 0.01)
+            b = rand_mask(rng, h, w, rng.uniform(0.3, 0.6))
+            want = ndimage.binary_dilation(a | z_closed_form(a, b), structure=K3,
+                                           border_value=0).astype(np.uint8)
+            assert np.array_equal(oracle.reach(a, b), want)
+
+
+def test_reach_invariants_and_special_cases():
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        a = rand_mask(rng, 12, 10, 0.03)
+        b = rand_mask(rng, 12, 10, 0.5)
+        r = oracle.reach(a, b)
+        assert np.all(a <= oracle.near(a)) and np.all(oracle.near(a) <= r)
+        a2 = a | rand_mask(rng, 12, 10, 0.02)
+        b2 = b | rand_mask(rng, 12, 10, 0.1)
+        assert np.all(oracle.reach(a2, b) >= r)       # monotone in a
+        assert np.all(oracle.reach(a, b2) >= r)       # monotone in b
+    z = np.zeros((7, 9), np.uint8)
+    o = np.ones((7, 9), np.uint8)
+    a = rand_mask(rng, 7, 9, 0.1)
+    a[3, 3] = 1
+    assert not oracle.reach(z, rand_mask(rng, 7, 9)).any()         # rho empty[b] = empty
+    assert np.array_equal(oracle.reach(a, z), oracle.near(a))      # rho a[empty] = N a
+    assert np.array_equal(oracle.reach(a, o), o)                   # rho a[all] = all
+
+
+def test_reach_serpentine_maze():
+    from synth.images import serpentine_maze
+    m = serpentine_maze(41, 37).astype(np.uint8)
+    seed = np.zeros_like(m)
+    seed[0, 0] = 1
+    assert np.array_equal(oracle.reach(seed, m), oracle.near(m | seed))
+    assert np.array_equal(oracle.grow(seed, m), m)
+    cut = m.copy()
+    cut[21, 36] = 0   # close one opening: the corridor below row 21 is unreachable
+    g = oracle.grow(seed, cut)
+    assert g[:21].sum() == cut[:21].sum() and g[22:].sum() == 0
+
+
+# ---------------------------------------------------------------- surrounded / grow
+
+def test_surrounded_against_direct_definition():
+    rng = np.random.default_rng(10)
+    for h, w in [(2, 3), (3, 3)]:
+        masks = list(all_masks(h, w))
+        for a in masks:
+            for _ in range(8):
+                b = masks[int(rng.integers(0, len(masks)))]
+                assert np.array_equal(oracle.surrounded(a, b), brute.surrounded_paths(a, b))
+    for h, w in [(5, 5), (8, 9), (12, 12)]:
+        for _ in range(60):
+            a = rand_mask(rng, h, w, rng.uniform(0.3, 0.9))
+            b = rand_mask(rng, h, w, rng.uniform(0.1, 0.5))
+            got = oracle.surrounded(a, b)
+            assert np.array_equal(got, brute.surrounded_paths(a, b))
+            assert np.all(got <= a)
+            b2 = b | rand_mask(rng, h, w, 0.2)
+            assert np.all(oracle.surrounded(a, b2) >= got)   # monotone in b
+
+
+def test_surrounded_disc_in_ring():
+    n = 11
+    yy, xx = np.mgrid[:n, :n]
+    ring = ((np.maximum(abs(yy - 5), abs(xx - 5)) == 4)).astype(np.uint8)
+    disc = (np.maximum(abs(yy - 5), abs(xx - 5)) <= 3).astype(np.uint8)
+    assert np.array_equal(oracle.surrounded(disc, ring), disc)
+    gap = ring.copy()
+    gap[1, 5] = 0
+    assert not oracle.surrounded(disc, gap).any()
+    # surrounded(a, empty) is empty unless a is the whole image
+    assert not oracle.surrounded(disc, np.zeros_like(disc)).any()
+    full = np.ones_like(disc)
+    assert np.array_equal(oracle.surrounded(full, np.zeros_like(disc)), full)
+
+
+def test_grow_is_a_union_touching_components():
+    rng = np.random.default_rng(11)
+    for h, w in [(3, 3), (10, 13), (40, 40)]:
+        for _ in range(20):
+            a = rand_mask(rng, h, w, 0.02)
+            b = rand_mask(rng, h, w, 0.5)
+            assert np.array_equal(oracle.grow(a, b), a | z_closed_form(a, b))
+
+
+# ---------------------------------------------------------------- CCL (Sect. 3)
+
+def test_ccl_partition_and_canonical_labels():
+    rng = np.random.default_rng(12)
+    for h, w in [(1, 1), (1, 50), (50, 1), (7, 7), (64, 64), (33, 129)]:
+        for p in (0.2, 0.45, 0.6):
+            a = rand_mask(rng, h, w, p)
+            lab = oracle.ccl(a)
+            ref, n = ndimage.label(a, structure=K3)
+            assert (lab >= 0).sum() == (ref > 0).sum()
+            # same partition: bijection between labels
+            pairs = set(zip(lab[a > 0].tolist(), ref[a > 0].tolist()))
+            assert len(pairs) == n == len(set(lab[a > 0].tolist()))
+            # canonical label = smallest row-major index of the component
+            for comp in brute.components(a):
+                m = min(y * w + x for y, x in comp)
+                assert all(lab[y, x] == m for y, x in comp)
+            # the paper's invariant: a pixel's label lies in its own component
+            flat = lab.reshape(-1)
+            for idx in np.flatnonzero(flat >= 0)[:200]:
+                assert flat[flat[idx]] == flat[idx]
+
+
+def test_ccl_concave_corner_is_one_component():
+    # pixels (a,b), (a+1,b), (a,b+1) without (a+1,b+1): the case the paper's
+    # pointer-jumping iteration can leave split (Sect. 3)
+    a = np.zeros((4, 4), np.uint8)
+    a[1, 1] = a[2, 1] = a[1, 2] = 1
+    lab = oracle.ccl(a)
+    assert set(lab[a > 0].tolist()) == {1 * 4 + 1}
+
+
+# ---------------------------------------------------------------- language
+
+def test_macros_let_and_sharing():
+    rng = np.random.default_rng(13)
+    img = rng.random((2, 9, 12)).astype(np.float32)
+    A = (img[0] > np.float32(0.5)).astype(np.uint8)
+    B = (img[1] < np.float32(0.4)).astype(np.uint8)
+    src = """
+    // a parametric macro, expanded at each use
+    let A = intensity(img, 0) >. 0.5
+    let B = intensity(img, 1) <. 0.4
+    let diff(x, y) = x & !y
+    let twice(x) = near(near(x))
+    output "d" diff(A, B)
+    output "d2" diff(B, A)
+    output "t" twice(diff(A, B))
+    let A = !A   // rebinding shadows the earlier A from here on
+    output "nA" A
+    """
+    d, d2, t, na = oracle.run(src, img)
+    assert np.array_equal(d, A & (1 - B))
+    assert np.array_equal(d2, B & (1 - A))
+    assert np.array_equal(t, brute.near(brute.near(A & (1 - B))))
+    assert np.array_equal(na, 1 - A)
+
+
+@pytest.mark.parametrize("src,where", [
+    ('output "x" foo', "undefined name"),
+    ('let a = intensity(img) >. \noutput "x" a', "expected a number"),
+    ('output "x" near(true', "expected ')'"),
+    ('let near = true', "built-in"),
+    ('output x true', "quoted"),
+])
+def test_parse_errors_have_positions(src, where):
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.run(src, np.zeros((1, 2, 2), np.float32))
+    assert where in str(e.value) and "line" in str(e.value)
+
+
+def test_composed_formula_matches_independent_composition():
+    rng = np.random.default_rng(14)
+    for trial in range(20):
+        img = rng.random((2, 14, 19)).astype(np.float32)
+        t0, t1, t2 = (float(np.float32(v)) for v in rng.uniform(0.2, 0.8, 3))
+        A = (img[0] > np.float32(t0)).astype(np.uint8)
+        B = (img[1] <= np.float32(t1)).astype(np.uint8)
+        C = (img[0] >= np.float32(t2)).astype(np.uint8)
+        src = (f"let A = intensity(img) >. {t0!r}\nlet B = intensity(img, 1) <=. {t1!r}\n"
+               f"let C = intensity(img, 0) >=. {t2!r}\n"
+               'output "o1" reach(A & !C, B | C)\n'
+               'output "o2" interior(near(A) | B) & !C\n'
+               'output "o3" surrounded(A | B, C)\n'
+               'output "o4" grow(A, !B)')
+        o1, o2, o3, o4 = oracle.run(src, img)
+        a1 = A & (1 - C)
+        b1 = B | C
+        w1 = ndimage.binary_dilation(a1 | z_closed_form(a1, b1), structure=K3,
+                                     border_value=0).astype(np.uint8)
+        assert np.array_equal(o1, w1)
+        nb = ndimage.binary_dilation(A, structure=K3, border_value=0).astype(np.uint8) | B
+        w2 = ndimage.binary_erosion(nb, structure=K3, border_value=1).astype(np.uint8) & (1 - C)
+        assert np.array_equal(o2, w2)
+        assert np.array_equal(o3, brute.surrounded_paths(A | B, C))
+        assert np.array_equal(o4, A | z_closed_form(A, 1 - B))
+
+
+def test_empty_image():
+    img = np.zeros((1, 0, 5), np.float32)
+    outs = oracle.run('output "r" reach(intensity(img) >. 0, true)', img)
+    assert outs[0].shape == (0, 5)
