@@ -1,0 +1,186 @@
+/*
+ * vlg.h -- C ABI of the MI355X spatial model checker.
+ *
+ * Evaluates SLCS formulas (paper "A spatial model checker in GPU", Sect. 2,
+ * Eq. def:syntax) pixel-wise over 2-D images on one AMD Instinct MI355X
+ * (gfx950).  Every operator runs in hand-written HIP kernels on 1-bit-packed
+ * masks; the host side only parses, plans and launches.
+ *
+ * Conventions
+ *   - Every call returns an int status: VLG_OK (0) or a negative VLG_E* code.
+ *     The message of the last failure on the calling thread is returned by
+ *     vlg_last_error().  No C++ exception crosses this interface.
+ *   - Handles (vlg_ctx, vlg_image, vlg_formula) are owned by the library and
+ *     released by the matching *_free / vlg_destroy call.
+ *   - A context is bound to one device and one HIP stream and is not
+ *     thread-safe.  Formulas are immutable after compilation and may be used
+ *     with any image and any context.
+ *   - Work is enqueued asynchronously on the context's stream.  Results in
+ *     device memory are complete once vlg_sync() returns (or once the caller
+ *     synchronises that stream).  Calls that read or write host memory
+ *     synchronise the stream before returning.
+ *
+ * Packed mask format (VLG_PACKED64): row-major uint64 words, wpr =
+ * ceil(W/64) words per row, pixel (y, x) is bit (x % 64) of word
+ * y*wpr + x/64 (least significant bit first); bits for x >= W are zero.
+ * Size: H * wpr * 8 bytes.
+ * Byte mask format (VLG_U8MASK): row-major uint8, one byte (0 or 1) per
+ * pixel, H * W bytes.
+ */
+#ifndef VLG_H
+#define VLG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define VLG_OK 0
+#define VLG_EINVAL (-1)  /* bad argument (null handle, bad enum, index out of range) */
+#define VLG_EPARSE (-2)  /* formula text does not parse; message has line and column */
+#define VLG_ESHAPE (-3)  /* image shape/channel mismatch or size beyond limits */
+#define VLG_ENOMEM (-4)  /* device or host allocation failed */
+#define VLG_EHIP (-5)    /* a HIP runtime call failed */
+#define VLG_ENOCONV (-6) /* a bounded device loop hit its iteration cap */
+
+/* ---- enums ---- */
+#define VLG_F32 0        /* image pixel types */
+#define VLG_U8 1
+#define VLG_HOST 0       /* where a caller buffer lives */
+#define VLG_DEVICE 1
+#define VLG_PACKED64 0   /* mask formats, see above */
+#define VLG_U8MASK 1
+
+/* Executor modes (vlg_set_mode).
+ *   VLG_MODE_PEROP: one kernel launch per operator of the expanded formula,
+ *     derived operators (interior, surrounded, grow) expanded into primitive
+ *     operators as their definitions read, as the paper's tool schedules them
+ *     (Sect. 3, Implementation details).
+ *   VLG_MODE_FUSED: the same results with fewer launches and fewer bytes:
+ *     all atoms of one channel read the channel once, negations are folded
+ *     into the consuming kernel, interior is one erosion kernel, surrounded
+ *     and grow run the reachability kernels without materialising their
+ *     complemented operands.
+ *   VLG_MODE_GRAPH: the fused schedule captured once per (formula, image,
+ *     output buffers) as a hipGraph and replayed.  Default. */
+#define VLG_MODE_PEROP 0
+#define VLG_MODE_FUSED 1
+#define VLG_MODE_GRAPH 2
+
+typedef struct vlg_ctx vlg_ctx;
+typedef struct vlg_image vlg_image;
+typedef struct vlg_formula vlg_formula;
+
+typedef struct vlg_formula_stats {
+    int64_t parsed_nodes;   /* operator applications before hash-consing */
+    int64_t nodes;          /* distinct DAG nodes after hash-consing: atoms,
+                               true/false, !, &, |, N, interior, reach,
+                               surrounded, grow each count as one */
+    int64_t reach_nodes;    /* reach + surrounded + grow nodes */
+    int64_t atoms;          /* threshold atoms (incl. percentile atoms) */
+    int64_t outputs;        /* number of `output` statements */
+    int64_t steps_perop;    /* kernel steps of the per-operator schedule */
+    int64_t steps_fused;    /* kernel steps of the fused schedule */
+    int64_t peak_masks;     /* peak live intermediate masks (fused schedule) */
+} vlg_formula_stats;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on, or NULL for a stream owned by the context.  The library does not
+ * take ownership of a caller stream. */
+int vlg_create(vlg_ctx **out, int device, void *hip_stream);
+void vlg_destroy(vlg_ctx *ctx);
+/* Block until all work enqueued by this context has finished. */
+int vlg_sync(vlg_ctx *ctx);
+/* Select the executor mode (VLG_MODE_*); see above. */
+int vlg_set_mode(vlg_ctx *ctx, int mode);
+
+/* Copy an image into a device buffer owned by the library (paper Sect. 3:
+ * images stay on the device and values are passed by buffer reference).
+ *   data: pixels, channel-planar [channels][height][pitch], in host memory
+ *     (where = VLG_HOST) or device memory (VLG_DEVICE, e.g. a torch tensor's
+ *     data pointer); pitch_elems >= width is the row stride in elements (0
+ *     means width).  dtype is VLG_F32 or VLG_U8.
+ *   channels >= 1, height >= 0, width >= 0; height*width < 2^31.
+ * The copy is complete when the call returns (host source) or in stream order
+ * (device source): the caller may free a host source at once and a device
+ * source after synchronising the context's stream. */
+int vlg_load_image(vlg_ctx *ctx, const void *data, int dtype, int channels, int height, int width,
+                   int64_t pitch_elems, int where, vlg_image **out);
+int vlg_image_free(vlg_image *img);
+int vlg_image_shape(const vlg_image *img, int *channels, int *height, int *width);
+
+/* Parse and compile formula text (ImgQL subset, paper Sect. 3 Syntax):
+ *   let NAME = expr | let NAME(p1, ..., pk) = expr | output "name" expr
+ *   expr: e | e, e & e, !e, (e), true, false,
+ *         intensity(img[, c]) CMP t with CMP one of >. <. >=. <=. and t a
+ *         number or percentile(img, c, q),
+ *         near(e) (also N(e)), interior(e), reach(a, b) = rho a[b],
+ *         surrounded(a, b), grow(a, b), and calls of user macros.
+ * Macros are expanded and identical sub-expressions become one DAG node
+ * (hash-consing; & and | are commutative), as in the paper's memoised macro
+ * expansion into a task DAG (Sect. 3, Implementation details).  On a parse
+ * error returns VLG_EPARSE with "line L col C: ..." in vlg_last_error(). */
+int vlg_compile_formula(vlg_ctx *ctx, const char *src, vlg_formula **out);
+int vlg_formula_info(const vlg_formula *f, vlg_formula_stats *stats);
+/* Name of output `index` (pointer valid while f lives), or NULL. */
+const char *vlg_formula_output_name(const vlg_formula *f, int index);
+int vlg_formula_free(vlg_formula *f);
+
+/* Evaluate output `output_index` of f on img and write the mask to `out_mask`
+ * (caller-owned, format fmt, in host or device memory).  Only the DAG nodes
+ * that output needs are evaluated.  Device outputs complete in stream order;
+ * host outputs are complete on return. */
+int vlg_check(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int output_index,
+              void *out_mask, int fmt, int where);
+/* Evaluate every output of f on img in one pass (shared sub-expressions are
+ * evaluated once).  outs[i] receives output i; a NULL entry skips it. */
+int vlg_check_all(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, void *const *outs,
+                  int fmt, int where);
+/* Evaluate every output of f on each of n images (sizes may differ).
+ * outs[i * n_outputs + k] receives output k of image i (NULL skips it). */
+int vlg_check_batch(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *const *imgs, int n,
+                    void *const *outs, int fmt, int where);
+
+/* Connected-component labelling of a packed device mask (8-connectivity, the
+ * labelling the paper uses to compute reachability, Sect. 3).  labels_dev is a
+ * device int32 [height][width] array; each foreground pixel receives the
+ * smallest row-major index y*width+x of its component, background -1.  Runs on
+ * the context's stream. */
+int vlg_ccl_labels(vlg_ctx *ctx, const uint64_t *mask_dev, int height, int width,
+                   int32_t *labels_dev);
+
+/* Counters of the last reachability labelling run on ctx (for measurement):
+ * union attempts and retry iterations of the cross-tile merge, and the
+ * number of kernel launches per labelling. */
+typedef struct vlg_ccl_counters {
+    int64_t merge_unions;
+    int64_t merge_retries;
+    int64_t launches_per_ccl;
+} vlg_ccl_counters;
+int vlg_ccl_read_counters(vlg_ctx *ctx, vlg_ccl_counters *out);
+
+/* Measurement.  Runs the fused schedule of every output of f on img `iters`
+ * times, one launch at a time, with a HIP event recorded on the context's
+ * stream before and after each step, and reports per kernel kind its number
+ * of launches, total time and algorithmic bytes (what the operator must read
+ * and write: image channels, input and output masks, labelling arrays).
+ * Writes at most max_out entries and the number of kinds to *n_out. */
+typedef struct vlg_kernel_time {
+    char name[32];   /* "atoms", "logic", "near", "ccl_local", "ccl_merge",
+                        "ccl_flag", "ccl_gather", "percentile" */
+    int64_t launches;
+    double ms;       /* total over all launches */
+    double bytes;    /* algorithmic bytes over all launches */
+} vlg_kernel_time;
+int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_kernel_time *out,
+                int max_out, int *n_out);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *vlg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLG_H */

@@ -1,0 +1,209 @@
+"""Python binding of libvlg, the MI355X spatial model checker (C ABI in
+include/vlg.h).  Argument marshalling only: parsing, planning and every
+operator run inside the library and its HIP kernels.  PyTorch provides device
+memory and the stream.
+
+    ctx = create()                       # device 0, torch's current stream
+    img = load_image(ctx, tensor)        # (C,H,W) or (H,W), float32 / uint8
+    f = compile_formula(ctx, src)
+    masks = check_all(ctx, f, img)       # list of packed int64 [H, ceil(W/64)] tensors
+    m = check(ctx, f, img, 0, fmt="u8")  # uint8 [H, W] tensor of 0/1
+"""
+import ctypes
+
+from . import _lib
+from ._lib import LIB_PATH, VlgError  # noqa: F401
+
+MODES = {"perop": 0, "fused": 1, "graph": 2}
+FMTS = {"packed": 0, "u8": 1}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    def __init__(self, handle, device, stream):
+        self.handle = handle
+        self.device = device
+        self.stream = stream
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib.loaded():
+            _lib.lib().vlg_destroy(h)
+
+
+class Image:
+    def __init__(self, handle, shape, dtype):
+        self.handle = handle
+        self.shape = shape  # (C, H, W)
+        self.dtype = dtype
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib.loaded():
+            _lib.lib().vlg_image_free(h)
+
+
+class Formula:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib.loaded():
+            _lib.lib().vlg_formula_free(h)
+
+
+def create(device=0, stream=None):
+    """vlg_create on `device`, enqueueing on `stream` (a torch.cuda.Stream;
+    default: a new stream, since graph capture needs a non-default stream).
+    Results are ready after sync(ctx) or after waiting on ctx.stream."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.Stream(device)
+    h = ctypes.c_void_p()
+    _lib.call("vlg_create", ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+    return Context(h, device, stream)
+
+
+def sync(ctx):
+    _lib.call("vlg_sync", ctx.handle)
+
+
+def set_mode(ctx, mode):
+    _lib.call("vlg_set_mode", ctx.handle, MODES[mode] if isinstance(mode, str) else int(mode))
+
+
+def load_image(ctx, t):
+    """vlg_load_image from a torch tensor or numpy array, (C,H,W) or (H,W),
+    float32 or uint8, host or device."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.from_numpy(t)
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.dtype not in (torch.float32, torch.uint8):
+        raise ValueError("image must be (C,H,W) float32 or uint8")
+    t = t.contiguous()
+    C, H, W = t.shape
+    dtype = 0 if t.dtype == torch.float32 else 1
+    where = 1 if t.is_cuda else 0
+    h = ctypes.c_void_p()
+    _lib.call("vlg_load_image", ctx.handle, ctypes.c_void_p(t.data_ptr()), dtype, C, H, W, W, where,
+              ctypes.byref(h))
+    if where == 1:
+        sync(ctx)  # the source tensor may be released by the caller
+    return Image(h, (C, H, W), t.dtype)
+
+
+def compile_formula(ctx, src):
+    h = ctypes.c_void_p()
+    _lib.call("vlg_compile_formula", ctx.handle if ctx else None, src.encode(), ctypes.byref(h))
+    return Formula(h)
+
+
+def formula_info(f):
+    st = _lib.FormulaStats()
+    _lib.call("vlg_formula_info", f.handle, ctypes.byref(st))
+    return {name: getattr(st, name) for name, _ in _lib.FormulaStats._fields_}
+
+
+def output_names(f):
+    n = formula_info(f)["outputs"]
+    L = _lib.lib()
+    return [L.vlg_formula_output_name(f.handle, i).decode() for i in range(n)]
+
+
+def _alloc_out(img, fmt, device):
+    torch = _torch()
+    C, H, W = img.shape
+    if fmt == "packed":
+        return torch.empty((H, (W + 63) // 64), dtype=torch.int64, device=device)
+    return torch.empty((H, W), dtype=torch.uint8, device=device)
+
+
+def check(ctx, f, img, output_index=0, out=None, fmt="packed"):
+    """vlg_check: one output into a device tensor (allocated if `out` is None)."""
+    if out is None:
+        out = _alloc_out(img, fmt, f"cuda:{ctx.device}")
+    where = 1 if out.is_cuda else 0
+    _lib.call("vlg_check", ctx.handle, f.handle, img.handle, output_index, ctypes.c_void_p(out.data_ptr()),
+              FMTS[fmt], where)
+    return out
+
+
+def check_all(ctx, f, img, outs=None, fmt="packed"):
+    """vlg_check_all: every output in one evaluation."""
+    n = formula_info(f)["outputs"]
+    if outs is None:
+        outs = [_alloc_out(img, fmt, f"cuda:{ctx.device}") for _ in range(n)]
+    where = 1 if outs[0].is_cuda else 0
+    arr = (ctypes.c_void_p * n)(*[o.data_ptr() if o is not None else None for o in outs])
+    _lib.call("vlg_check_all", ctx.handle, f.handle, img.handle, arr, FMTS[fmt], where)
+    return outs
+
+
+def check_batch(ctx, f, imgs, outs=None, fmt="packed"):
+    """vlg_check_batch: every output of f on each image; returns a list (per
+    image) of lists (per output)."""
+    n = formula_info(f)["outputs"]
+    if outs is None:
+        outs = [[_alloc_out(im, fmt, f"cuda:{ctx.device}") for _ in range(n)] for im in imgs]
+    where = 1 if outs[0][0].is_cuda else 0
+    flat = [o.data_ptr() if o is not None else None for row in outs for o in row]
+    arr = (ctypes.c_void_p * len(flat))(*flat)
+    harr = (ctypes.c_void_p * len(imgs))(*[im.handle.value for im in imgs])
+    _lib.call("vlg_check_batch", ctx.handle, f.handle, harr, len(imgs), arr, FMTS[fmt], where)
+    return outs
+
+
+def ccl_labels(ctx, mask, height, width, out=None):
+    """vlg_ccl_labels of a packed device mask -> int32 [H, W] labels (smallest
+    row-major index of each component, -1 for background)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((height, width), dtype=torch.int32, device=mask.device)
+    _lib.call("vlg_ccl_labels", ctx.handle, ctypes.c_void_p(mask.data_ptr()), height, width,
+              ctypes.c_void_p(out.data_ptr()))
+    return out
+
+
+def ccl_counters(ctx):
+    c = _lib.CclCounters()
+    _lib.call("vlg_ccl_read_counters", ctx.handle, ctypes.byref(c))
+    return {name: getattr(c, name) for name, _ in _lib.CclCounters._fields_}
+
+
+def profile(ctx, f, img, iters=5):
+    """vlg_profile: per kernel kind {name: (launches, ms_total, algorithmic_bytes)}
+    from HIP events around each step of the fused schedule."""
+    arr = (_lib.KernelTime * 16)()
+    n = ctypes.c_int()
+    _lib.call("vlg_profile", ctx.handle, f.handle, img.handle, iters, arr, 16, ctypes.byref(n))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
+
+
+def unpack(words, height, width):
+    """Packed int64 words (torch or numpy, [H, ceil(W/64)]) -> numpy uint8 [H, W]."""
+    import numpy as np
+    a = words.cpu().numpy() if hasattr(words, "cpu") else np.asarray(words)
+    bits = np.unpackbits(a.astype("<i8").view(np.uint8).reshape(height, -1), axis=1, bitorder="little")
+    return bits[:, :width].copy()
+
+
+def pack(mask):
+    """numpy uint8 [H, W] of 0/1 -> numpy int64 [H, ceil(W/64)] packed words."""
+    import numpy as np
+    H, W = mask.shape
+    wpr = (W + 63) // 64
+    padded = np.zeros((H, wpr * 64), np.uint8)
+    padded[:, :W] = mask
+    return np.packbits(padded, axis=1, bitorder="little").view("<i8").reshape(H, wpr).copy()
+
+
+__all__ = ["create", "sync", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
+           "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "unpack", "pack", "VlgError",
+           "LIB_PATH"]

@@ -1,0 +1,89 @@
+"""ctypes loader for libvlg.so.  Fails loudly when the library is missing and
+cannot be built: there is no fallback implementation."""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvlg.so")
+
+# every symbol declared in include/vlg.h
+EXPORTS = [
+    "vlg_create", "vlg_destroy", "vlg_sync", "vlg_set_mode", "vlg_load_image", "vlg_image_free",
+    "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name",
+    "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels",
+    "vlg_ccl_read_counters", "vlg_profile", "vlg_last_error",
+]
+
+ERRORS = {-1: "VLG_EINVAL", -2: "VLG_EPARSE", -3: "VLG_ESHAPE", -4: "VLG_ENOMEM", -5: "VLG_EHIP",
+          -6: "VLG_ENOCONV"}
+
+
+class VlgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class FormulaStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("parsed_nodes", "nodes", "reach_nodes", "atoms", "outputs", "steps_perop", "steps_fused",
+                 "peak_masks")]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class CclCounters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("merge_unions", "merge_retries", "launches_per_ccl")]
+
+
+_lib = None
+
+
+def loaded():
+    return _lib is not None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from .build import build
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        sig = {
+            "vlg_create": ([P, I, P], I),
+            "vlg_destroy": ([P], None),
+            "vlg_sync": ([P], I),
+            "vlg_set_mode": ([P, I], I),
+            "vlg_load_image": ([P, P, I, I, I, I, I64, I, P], I),
+            "vlg_image_free": ([P], I),
+            "vlg_image_shape": ([P, P, P, P], I),
+            "vlg_compile_formula": ([P, ctypes.c_char_p, P], I),
+            "vlg_formula_info": ([P, P], I),
+            "vlg_formula_output_name": ([P, I], ctypes.c_char_p),
+            "vlg_formula_free": ([P], I),
+            "vlg_check": ([P, P, P, I, P, I, I], I),
+            "vlg_check_all": ([P, P, P, P, I, I], I),
+            "vlg_check_batch": ([P, P, P, I, P, I, I], I),
+            "vlg_ccl_labels": ([P, P, I, I, P], I),
+            "vlg_ccl_read_counters": ([P, P], I),
+            "vlg_profile": ([P, P, P, I, P, I, P], I),
+            "vlg_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def call(name, *args):
+    L = lib()
+    rc = getattr(L, name)(*args)
+    if rc != 0:
+        raise VlgError(rc, (L.vlg_last_error() or b"").decode())
+    return rc

@@ -1,0 +1,668 @@
+// capi.cpp -- the C ABI (include/vlg.h): contexts, resident images, formula
+// compilation, and the executor that runs a schedule on a HIP stream, either
+// launch by launch or as a captured hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "compiler.h"
+#include "kernels.h"
+#include "vlg.h"
+
+using namespace vlg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(VLG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+std::atomic<uint64_t> g_serial{1};
+
+struct vlg_formula {
+    uint64_t serial = g_serial.fetch_add(1);
+    Dag dag;
+    int32_t max_chan = -1;
+    std::mutex mu;
+    std::map<std::pair<std::vector<int>, int>, std::unique_ptr<Plan>> plans;
+
+    const Plan &plan(const std::vector<int> &which, Mode m) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto key = std::make_pair(which, (int)m);
+        auto it = plans.find(key);
+        if (it != plans.end()) return *it->second;
+        auto p = std::make_unique<Plan>(build_plan(dag, which, m));
+        const Plan &ref = *p;
+        plans.emplace(key, std::move(p));
+        return ref;
+    }
+};
+
+struct vlg_image {
+    int device;
+    int dtype, C, H, W;
+    int64_t pitch;  // elements per row (wpr * 64)
+    void *dev;
+    size_t bytes;
+    size_t esize() const { return dtype == VLG_U8 ? 1 : 4; }
+    const char *chan(int c) const { return (const char *)dev + (size_t)c * H * pitch * esize(); }
+};
+
+struct GraphKey {
+    std::vector<uintptr_t> v;
+    bool operator<(const GraphKey &o) const { return v < o.v; }
+};
+
+struct vlg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int mode = VLG_MODE_GRAPH;
+    void *ws = nullptr;
+    size_t ws_size = 0;
+    unsigned long long *counters = nullptr;  // device [2]
+    bool count_ccl = false;         // collect merge counters (VLG_CCL_COUNTERS=1)
+    std::map<GraphKey, hipGraphExec_t> graphs;
+
+    void drop_graphs() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+};
+
+namespace {
+
+// Workspace layout of one evaluation.
+struct Layout {
+    size_t mask_bytes = 0;
+    size_t off_slots = 0, off_stage = 0, off_u8 = 0, off_glab = 0, off_gflag = 0, off_pct = 0,
+           off_pctst = 0, total = 0;
+};
+
+Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8) {
+    Layout L;
+    L.mask_bytes = align256((size_t)g.nwords * 8);
+    size_t off = 0;
+    L.off_slots = off;
+    off += (size_t)P.nslots * L.mask_bytes;
+    L.off_stage = off;
+    if (stage_packed) off += (size_t)P.noutputs * L.mask_bytes;
+    L.off_u8 = off;
+    if (stage_u8) off += (size_t)P.noutputs * align256((size_t)g.H * g.W);
+    L.off_glab = off;
+    const size_t nb = (size_t)g.BH * g.BW;
+    if (P.ccl_count > 0) off += align256(nb * 4);
+    L.off_gflag = off;
+    if (P.ccl_count > 0) off += align256(nb);
+    L.off_pct = off;
+    off += align256((size_t)P.npct * 4);
+    L.off_pctst = off;
+    off += (size_t)P.npct * kPctStateBytes;
+    L.total = off + 256;
+    return L;
+}
+
+int ensure_ws(vlg_ctx *c, size_t need) {
+    if (c->ws_size >= need) return VLG_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->drop_graphs();
+    if (c->ws) HIP_TRY(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_size = 0;
+    size_t sz = std::max(need, c->ws_size + c->ws_size / 4);
+    if (hipMalloc(&c->ws, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        c->ws = nullptr;
+        return fail(VLG_ENOMEM, "workspace allocation of " + std::to_string(sz) + " bytes failed");
+    }
+    c->ws_size = sz;
+    return VLG_OK;
+}
+
+uint32_t pct_rank(double q, int64_t n) {
+    // k = clamp(ceil(q * n) - 1, 0, n - 1)
+    double kk = std::ceil(q * (double)n) - 1.0;
+    if (kk < 0.0 || n == 0) return 0;
+    if (kk > (double)(n - 1)) return (uint32_t)(n - 1);
+    return (uint32_t)kk;
+}
+
+const char *kind_name(SK k) {
+    switch (k) {
+    case SK::Pct: return "percentile";
+    case SK::Atoms: return "atoms";
+    case SK::Logic: return "logic";
+    case SK::Near: return "near";
+    case SK::CclLocal: return "ccl_local";
+    case SK::CclMerge: return "ccl_merge";
+    case SK::CclFlag: return "ccl_flag";
+    case SK::CclGather: return "ccl_gather";
+    }
+    return "?";
+}
+
+// Bytes a step must move at the least: its image channel or input masks
+// read once, its outputs written once (and the labelling arrays it owns).
+double algorithmic_bytes(const Step &s, const Geo &g, int dtype) {
+    const double mb = (double)g.nwords * 8.0, npix = (double)g.H * g.W;
+    const double nb = (double)g.BH * g.BW;
+    auto ins = [&](std::initializer_list<Ref> rs) {
+        double n = 0;
+        for (const Ref &r : rs) n += r.slot != kNone ? mb : 0.0;
+        return n;
+    };
+    switch (s.kind) {
+    case SK::Pct: return npix * (dtype == VLG_U8 ? 1.0 : 3.0 * 4.0);
+    case SK::Atoms: return npix * (dtype == VLG_U8 ? 1.0 : 4.0) + s.natoms * mb;
+    case SK::Logic: return ins({s.x, s.y}) + mb;
+    case SK::Near: return ins({s.x, s.z}) + mb;
+    case SK::CclLocal: return ins({s.x, s.y, s.z}) + nb * 5.0;      // labels + flags written
+    case SK::CclMerge: {
+        const double ntiles = std::ceil(g.BH / (double)kTileBH) * std::ceil(g.BW / (double)kTileBW);
+        return ntiles * (kTileBW + 2 * kTileBH) * 16.0;               // border words read
+    }
+    case SK::CclFlag: return nb;                                      // flags read
+    case SK::CclGather: return ins({s.x, s.y, s.z}) + nb * 4.0 + mb;  // labels read
+    }
+    return 0.0;
+}
+
+using StepHook = void (*)(void *, size_t, bool);
+
+// Enqueue every step of P on the stream.  ext[k] is the packed device buffer
+// of external slot k.  hook (optional) runs before and after each step.
+int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &L,
+                 const std::vector<uint64_t *> &ext, StepHook hook = nullptr, void *hook_ctx = nullptr) {
+    const Geo g = make_geo(img->H, img->W);
+    char *base = (char *)c->ws;
+    auto slot_ptr = [&](int32_t s) -> uint64_t * {
+        if (s == kNone) return nullptr;
+        if (is_ext(s)) return ext[(size_t)ext_index(s)];
+        return (uint64_t *)(base + L.off_slots + (size_t)s * L.mask_bytes);
+    };
+    auto mref = [&](const Ref &r) {
+        MRef m;
+        m.p = slot_ptr(r.slot);
+        m.inv = r.inv ? ~0ull : 0ull;
+        return m;
+    };
+    float *pct = (float *)(base + L.off_pct);
+    CclWork w;
+    w.glab = (int32_t *)(base + L.off_glab);
+    w.gflag = (uint8_t *)(base + L.off_gflag);
+    w.counters = c->count_ccl ? c->counters : nullptr;
+    const int64_t npix = (int64_t)img->H * img->W;
+    for (size_t si = 0; si < P.steps.size(); si++) {
+        const Step &s = P.steps[si];
+        if (hook) hook(hook_ctx, si, true);
+        hipError_t e = hipSuccess;
+        switch (s.kind) {
+        case SK::Pct:
+            e = launch_percentile(c->stream, g, img->chan(s.chan), img->dtype, img->pitch, pct_rank(s.q, npix),
+                                  base + L.off_pctst + (size_t)s.pct_out * kPctStateBytes, pct + s.pct_out);
+            break;
+        case SK::Atoms: {
+            AtomLaunch a;
+            std::memset(&a, 0, sizeof a);
+            a.n = s.natoms;
+            for (int j = 0; j < s.natoms; j++) {
+                a.cmp[j] = s.atoms[j].cmp;
+                a.thr[j] = s.atoms[j].thr;
+                a.thr_dev[j] = s.atoms[j].use_pct ? pct + s.atoms[j].pct : nullptr;
+                a.out[j] = slot_ptr(s.atoms[j].out);
+            }
+            e = launch_atoms(c->stream, g, img->chan(s.chan), img->dtype, a);
+            break;
+        }
+        case SK::Logic:
+            e = launch_logic(c->stream, g, mref(s.x), mref(s.y), s.op, s.inv_out, slot_ptr(s.out));
+            break;
+        case SK::Near:
+            e = launch_near(c->stream, g, mref(s.x), s.inv_out, mref(s.z), slot_ptr(s.out));
+            break;
+        case SK::CclLocal:
+            e = launch_ccl_local(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w);
+            break;
+        case SK::CclMerge:
+            e = launch_ccl_merge(c->stream, g, mref(s.x), w);
+            break;
+        case SK::CclFlag:
+            e = launch_ccl_flag(c->stream, g, w);
+            break;
+        case SK::CclGather:
+            e = launch_ccl_gather(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w, slot_ptr(s.out));
+            break;
+        }
+        if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        if (hook) hook(hook_ctx, si, false);
+    }
+    return VLG_OK;
+}
+
+// Evaluate the outputs `which` of f on img.  outs[k] receives output which[k].
+int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int> &which,
+        const std::vector<void *> &outs, int fmt, int where) {
+    if (fmt != VLG_PACKED64 && fmt != VLG_U8MASK) return fail(VLG_EINVAL, "bad mask format");
+    if (where != VLG_HOST && where != VLG_DEVICE) return fail(VLG_EINVAL, "bad memory kind");
+    if (f->max_chan >= img->C)
+        return fail(VLG_ESHAPE, "formula uses channel " + std::to_string(f->max_chan) + " but the image has " +
+                                    std::to_string(img->C));
+    if (img->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
+    DeviceGuard dg(c->device);
+    const Mode m = c->mode == VLG_MODE_PEROP ? Mode::PerOp : Mode::Fused;
+    const Plan &P = f->plan(which, m);
+    const Geo g = make_geo(img->H, img->W);
+    if (g.nwords == 0 || which.empty()) return VLG_OK;
+    const bool direct = fmt == VLG_PACKED64 && where == VLG_DEVICE;
+    const bool stage_u8 = fmt == VLG_U8MASK && where == VLG_HOST;
+    Layout L = layout_for(P, g, !direct, stage_u8);
+    int rc = ensure_ws(c, L.total);
+    if (rc != VLG_OK) return rc;
+    char *base = (char *)c->ws;
+    std::vector<uint64_t *> ext(which.size());
+    for (size_t k = 0; k < which.size(); k++)
+        ext[k] = direct && outs[k] ? (uint64_t *)outs[k]
+                                   : (uint64_t *)(base + L.off_stage + k * L.mask_bytes);
+    const size_t u8_bytes = align256((size_t)g.H * g.W);
+
+    auto enqueue_all = [&]() -> int {
+        int r = enqueue_plan(c, P, img, L, ext);
+        if (r != VLG_OK) return r;
+        if (fmt == VLG_U8MASK) {
+            for (size_t k = 0; k < which.size(); k++) {
+                if (!outs[k]) continue;
+                uint8_t *dst = where == VLG_DEVICE ? (uint8_t *)outs[k] : (uint8_t *)(base + L.off_u8 + k * u8_bytes);
+                hipError_t e = launch_unpack(c->stream, g, ext[k], dst);
+                if (e != hipSuccess) return fail(VLG_EHIP, hipGetErrorString(e));
+            }
+        }
+        return VLG_OK;
+    };
+
+    if (c->mode == VLG_MODE_GRAPH) {
+        GraphKey key;
+        key.v = {(uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)img->dev, (uintptr_t)img->H, (uintptr_t)img->W,
+                 (uintptr_t)img->dtype, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)c->ws};
+        for (size_t k = 0; k < which.size(); k++) key.v.push_back((uintptr_t)outs[k]);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            int r = enqueue_all();
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(c->stream, &graph);
+            if (r != VLG_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return r;
+            }
+            if (e != hipSuccess) return fail(VLG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(VLG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            if (c->graphs.size() >= 64) c->drop_graphs();
+            it = c->graphs.emplace(key, exec).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second, c->stream));
+    } else {
+        rc = enqueue_all();
+        if (rc != VLG_OK) return rc;
+    }
+
+    if (where == VLG_HOST) {
+        for (size_t k = 0; k < which.size(); k++) {
+            if (!outs[k]) continue;
+            if (fmt == VLG_PACKED64)
+                HIP_TRY(hipMemcpyAsync(outs[k], ext[k], (size_t)g.nwords * 8, hipMemcpyDeviceToHost, c->stream));
+            else
+                HIP_TRY(hipMemcpyAsync(outs[k], base + L.off_u8 + k * u8_bytes, (size_t)g.H * g.W,
+                                       hipMemcpyDeviceToHost, c->stream));
+        }
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return VLG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vlg_last_error(void) { return g_err.c_str(); }
+
+int vlg_create(vlg_ctx **out, int device, void *hip_stream) {
+    if (!out) return fail(VLG_EINVAL, "null output handle");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return fail(VLG_EINVAL, "no HIP device " + std::to_string(device));
+    }
+    DeviceGuard dg(device);
+    auto c = std::make_unique<vlg_ctx>();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    const char *cc = std::getenv("VLG_CCL_COUNTERS");
+    c->count_ccl = cc && cc[0] == '1';
+    HIP_TRY(hipMalloc(&c->counters, 2 * sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *out = c.release();
+    return VLG_OK;
+}
+
+void vlg_destroy(vlg_ctx *c) {
+    if (!c) return;
+    DeviceGuard dg(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    c->drop_graphs();
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->counters) (void)hipFree(c->counters);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int vlg_sync(vlg_ctx *c) {
+    if (!c) return fail(VLG_EINVAL, "null context");
+    DeviceGuard dg(c->device);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return VLG_OK;
+}
+
+int vlg_set_mode(vlg_ctx *c, int mode) {
+    if (!c || mode < VLG_MODE_PEROP || mode > VLG_MODE_GRAPH) return fail(VLG_EINVAL, "bad mode");
+    c->mode = mode;
+    return VLG_OK;
+}
+
+int vlg_load_image(vlg_ctx *c, const void *data, int dtype, int channels, int height, int width,
+                   int64_t pitch_elems, int where, vlg_image **out) {
+    if (!c || !out) return fail(VLG_EINVAL, "null handle");
+    *out = nullptr;
+    if (dtype != VLG_F32 && dtype != VLG_U8) return fail(VLG_EINVAL, "dtype must be VLG_F32 or VLG_U8");
+    if (where != VLG_HOST && where != VLG_DEVICE) return fail(VLG_EINVAL, "bad memory kind");
+    if (channels < 1 || height < 0 || width < 0) return fail(VLG_ESHAPE, "bad image shape");
+    if ((int64_t)height * width >= (1ll << 31)) return fail(VLG_ESHAPE, "image too large (H*W >= 2^31)");
+    if (pitch_elems == 0) pitch_elems = width;
+    if (pitch_elems < width) return fail(VLG_ESHAPE, "pitch smaller than width");
+    if (!data && (int64_t)height * width > 0) return fail(VLG_EINVAL, "null image data");
+    DeviceGuard dg(c->device);
+    auto im = std::make_unique<vlg_image>();
+    im->device = c->device;
+    im->dtype = dtype;
+    im->C = channels;
+    im->H = height;
+    im->W = width;
+    im->pitch = (int64_t)((width + 63) / 64) * 64;
+    const size_t es = im->esize();
+    im->bytes = std::max<size_t>(256, (size_t)channels * height * im->pitch * es);
+    if (hipMalloc(&im->dev, im->bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(VLG_ENOMEM, "image allocation failed");
+    }
+    HIP_TRY(hipMemsetAsync(im->dev, 0, im->bytes, c->stream));
+    if ((int64_t)height * width > 0) {
+        const hipMemcpyKind kind = where == VLG_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        for (int ch = 0; ch < channels; ch++) {
+            const char *src = (const char *)data + (size_t)ch * height * pitch_elems * es;
+            HIP_TRY(hipMemcpy2DAsync((char *)im->dev + (size_t)ch * height * im->pitch * es, im->pitch * es, src,
+                                     (size_t)pitch_elems * es, (size_t)width * es, (size_t)height, kind,
+                                     c->stream));
+        }
+    }
+    if (where == VLG_HOST) HIP_TRY(hipStreamSynchronize(c->stream));
+    *out = im.release();
+    return VLG_OK;
+}
+
+int vlg_image_free(vlg_image *img) {
+    if (!img) return VLG_OK;
+    DeviceGuard dg(img->device);
+    (void)hipDeviceSynchronize();
+    hipError_t e = hipFree(img->dev);
+    delete img;
+    if (e != hipSuccess) return fail(VLG_EHIP, hipGetErrorString(e));
+    return VLG_OK;
+}
+
+int vlg_image_shape(const vlg_image *img, int *channels, int *height, int *width) {
+    if (!img) return fail(VLG_EINVAL, "null image");
+    if (channels) *channels = img->C;
+    if (height) *height = img->H;
+    if (width) *width = img->W;
+    return VLG_OK;
+}
+
+int vlg_compile_formula(vlg_ctx *c, const char *src, vlg_formula **out) {
+    (void)c;
+    if (!src || !out) return fail(VLG_EINVAL, "null argument");
+    *out = nullptr;
+    auto f = std::make_unique<vlg_formula>();
+    std::string err;
+    try {
+        if (!parse_formula(src, f->dag, err)) return fail(VLG_EPARSE, err);
+    } catch (const std::bad_alloc &) {
+        return fail(VLG_ENOMEM, "out of host memory while compiling");
+    }
+    for (const Node &n : f->dag.nodes) {
+        if (n.op == Op::Atom) {
+            f->max_chan = std::max(f->max_chan, n.chan);
+            if (n.pct) f->max_chan = std::max(f->max_chan, n.pchan);
+        }
+    }
+    *out = f.release();
+    return VLG_OK;
+}
+
+int vlg_formula_info(const vlg_formula *cf, vlg_formula_stats *st) {
+    if (!cf || !st) return fail(VLG_EINVAL, "null argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    std::vector<int> all(f->dag.outputs.size());
+    for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
+    const Plan &pp = f->plan(all, Mode::PerOp);
+    const Plan &pf = f->plan(all, Mode::Fused);
+    st->parsed_nodes = f->dag.parsed_nodes;
+    st->nodes = (int64_t)f->dag.nodes.size();
+    st->reach_nodes = count_op(f->dag, true);
+    st->atoms = count_op(f->dag, false);
+    st->outputs = (int64_t)f->dag.outputs.size();
+    st->steps_perop = (int64_t)pp.steps.size();
+    st->steps_fused = (int64_t)pf.steps.size();
+    st->peak_masks = pf.nslots;
+    return VLG_OK;
+}
+
+const char *vlg_formula_output_name(const vlg_formula *f, int index) {
+    if (!f || index < 0 || index >= (int)f->dag.output_names.size()) return nullptr;
+    return f->dag.output_names[(size_t)index].c_str();
+}
+
+int vlg_formula_free(vlg_formula *f) {
+    delete f;
+    return VLG_OK;
+}
+
+int vlg_check(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int output_index, void *out_mask,
+              int fmt, int where) {
+    if (!c || !cf || !img || !out_mask) return fail(VLG_EINVAL, "null argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    if (output_index < 0 || output_index >= (int)f->dag.outputs.size())
+        return fail(VLG_EINVAL, "output index out of range");
+    try {
+        return run(c, f, img, {output_index}, {out_mask}, fmt, where);
+    } catch (const std::bad_alloc &) {
+        return fail(VLG_ENOMEM, "out of host memory");
+    }
+}
+
+int vlg_check_all(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, void *const *outs, int fmt,
+                  int where) {
+    if (!c || !cf || !img || !outs) return fail(VLG_EINVAL, "null argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    std::vector<int> which;
+    std::vector<void *> o;
+    for (size_t i = 0; i < f->dag.outputs.size(); i++) {
+        if (!outs[i]) continue;
+        which.push_back((int)i);
+        o.push_back(outs[i]);
+    }
+    try {
+        return run(c, f, img, which, o, fmt, where);
+    } catch (const std::bad_alloc &) {
+        return fail(VLG_ENOMEM, "out of host memory");
+    }
+}
+
+int vlg_check_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *imgs, int n, void *const *outs,
+                    int fmt, int where) {
+    if (!c || !cf || (!imgs && n > 0) || (!outs && n > 0) || n < 0) return fail(VLG_EINVAL, "null argument");
+    const size_t nout = cf->dag.outputs.size();
+    for (int i = 0; i < n; i++) {
+        if (!imgs[i]) return fail(VLG_EINVAL, "null image in batch");
+        int rc = vlg_check_all(c, cf, imgs[i], outs + (size_t)i * nout, fmt, where);
+        if (rc != VLG_OK) return rc;
+    }
+    return VLG_OK;
+}
+
+int vlg_ccl_labels(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, int32_t *labels_dev) {
+    if (!c || (!mask_dev && (int64_t)height * width > 0) || (!labels_dev && (int64_t)height * width > 0))
+        return fail(VLG_EINVAL, "null argument");
+    if (height < 0 || width < 0 || (int64_t)height * width >= (1ll << 31)) return fail(VLG_ESHAPE, "bad shape");
+    DeviceGuard dg(c->device);
+    const Geo g = make_geo(height, width);
+    if (g.nwords == 0) return VLG_OK;
+    const size_t nb = (size_t)g.BH * g.BW;
+    int rc = ensure_ws(c, align256(nb * 4) + align256(nb) + 256);
+    if (rc != VLG_OK) return rc;
+    CclWork w;
+    w.glab = (int32_t *)c->ws;
+    w.gflag = (uint8_t *)c->ws + align256(nb * 4);
+    w.counters = c->counters;
+    MRef b{mask_dev, 0ull}, none{nullptr, 0ull};
+    HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
+    HIP_TRY(launch_ccl_local(c->stream, g, b, none, none, w));
+    HIP_TRY(launch_ccl_merge(c->stream, g, b, w));
+    HIP_TRY(launch_ccl_flag(c->stream, g, w));
+    HIP_TRY(launch_ccl_labels(c->stream, g, b, w, labels_dev));
+    return VLG_OK;
+}
+
+int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int iters, vlg_kernel_time *out,
+                int max_out, int *n_out) {
+    if (!c || !cf || !img || !out || !n_out || iters < 1) return fail(VLG_EINVAL, "bad argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    if (f->max_chan >= img->C) return fail(VLG_ESHAPE, "formula uses a channel the image lacks");
+    DeviceGuard dg(c->device);
+    std::vector<int> which(f->dag.outputs.size());
+    for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
+    const Plan &P = f->plan(which, Mode::Fused);
+    const Geo g = make_geo(img->H, img->W);
+    *n_out = 0;
+    if (g.nwords == 0 || which.empty()) return VLG_OK;
+    Layout L = layout_for(P, g, true, false);
+    int rc = ensure_ws(c, L.total);
+    if (rc != VLG_OK) return rc;
+    std::vector<uint64_t *> ext(which.size());
+    for (size_t k = 0; k < which.size(); k++) ext[k] = (uint64_t *)((char *)c->ws + L.off_stage + k * L.mask_bytes);
+    struct Ev {
+        std::vector<hipEvent_t> ev;
+    } E;
+    E.ev.resize(2 * P.steps.size());
+    for (auto &e : E.ev) HIP_TRY(hipEventCreate(&e));
+    std::vector<double> ms(P.steps.size(), 0.0);
+    struct Tr {
+        Ev *e;
+        hipStream_t s;
+    } tr{&E, c->stream};
+    auto hook2 = [](void *p, size_t si, bool before) {
+        Tr *t = (Tr *)p;
+        (void)hipEventRecord(t->e->ev[2 * si + (before ? 0 : 1)], t->s);
+    };
+    for (int it = 0; it < iters && rc == VLG_OK; it++) {
+        rc = enqueue_plan(c, P, img, L, ext, hook2, &tr);
+        if (rc != VLG_OK) break;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            rc = fail(VLG_EHIP, "synchronize failed");
+            break;
+        }
+        for (size_t si = 0; si < P.steps.size(); si++) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, E.ev[2 * si], E.ev[2 * si + 1]) == hipSuccess) ms[si] += t;
+        }
+    }
+    for (auto &e : E.ev) (void)hipEventDestroy(e);
+    if (rc != VLG_OK) return rc;
+    std::vector<vlg_kernel_time> kinds;
+    for (size_t si = 0; si < P.steps.size(); si++) {
+        const char *nm = kind_name(P.steps[si].kind);
+        auto it = std::find_if(kinds.begin(), kinds.end(),
+                               [&](const vlg_kernel_time &k) { return std::strcmp(k.name, nm) == 0; });
+        if (it == kinds.end()) {
+            vlg_kernel_time k;
+            std::memset(&k, 0, sizeof k);
+            std::snprintf(k.name, sizeof k.name, "%s", nm);
+            kinds.push_back(k);
+            it = kinds.end() - 1;
+        }
+        it->launches += iters;
+        it->ms += ms[si];
+        it->bytes += iters * algorithmic_bytes(P.steps[si], g, img->dtype);
+    }
+    for (size_t i = 0; i < kinds.size() && (int)i < max_out; i++) out[i] = kinds[i];
+    *n_out = (int)kinds.size();
+    return VLG_OK;
+}
+
+int vlg_ccl_read_counters(vlg_ctx *c, vlg_ccl_counters *out) {
+    if (!c || !out) return fail(VLG_EINVAL, "null argument");
+    DeviceGuard dg(c->device);
+    unsigned long long h[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(h, c->counters, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out->merge_unions = h[0];
+    out->merge_retries = h[1];
+    HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
+    out->launches_per_ccl = 4;
+    return VLG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,879 @@
+// compiler.cpp -- parser, hash-consing DAG builder and schedule builder.
+//
+// The front end follows the paper's tool (Sect. 3, Implementation details):
+// parametric macros are expanded and identical sub-expressions are shared, so
+// the result is a DAG of operator tasks.  Here the sharing is hash-consing on
+// (operator, operands, parameters), with & and | commutative.
+#include "compiler.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <unordered_map>
+
+namespace vlg {
+namespace {
+
+// ---------------------------------------------------------------- lexer
+
+enum TokKind { T_END, T_IDENT, T_NUM, T_STR, T_PUNCT };
+
+struct Tok {
+    TokKind k;
+    std::string s;
+    double num = 0.0;
+    int line = 1, col = 1;
+};
+
+std::string at(int line, int col, const std::string &msg) {
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "line %d col %d: ", line, col);
+    return buf + msg;
+}
+
+bool lex(const char *src, std::vector<Tok> &out, std::string &err) {
+    static const char *puncts[] = {">=.", "<=.", ">.", "<.", "(", ")", ",", "=", "!", "&", "|", "-"};
+    int line = 1, col = 1;
+    size_t i = 0;
+    auto step = [&](size_t n) {
+        for (size_t k = 0; k < n; k++) {
+            if (src[i] == '\n') {
+                line++;
+                col = 1;
+            } else {
+                col++;
+            }
+            i++;
+        }
+    };
+    while (true) {
+        char c = src[i];
+        if (c == ' ' || c == '\t' || c == '\r' || c == '\n' || c == ';') {
+            step(1);
+            continue;
+        }
+        if (c == '/' && src[i + 1] == '/') {
+            while (src[i] && src[i] != '\n') step(1);
+            continue;
+        }
+        Tok t;
+        t.line = line;
+        t.col = col;
+        if (c == 0) {
+            t.k = T_END;
+            out.push_back(t);
+            return true;
+        }
+        if (std::isalpha((unsigned char)c) || c == '_') {
+            size_t n = 0;
+            while (std::isalnum((unsigned char)src[i + n]) || src[i + n] == '_') n++;
+            t.k = T_IDENT;
+            t.s.assign(src + i, n);
+            step(n);
+        } else if (std::isdigit((unsigned char)c) || (c == '.' && std::isdigit((unsigned char)src[i + 1]))) {
+            char *end = nullptr;
+            t.k = T_NUM;
+            t.num = std::strtod(src + i, &end);
+            t.s.assign(src + i, (size_t)(end - (src + i)));
+            step((size_t)(end - (src + i)));
+        } else if (c == '"') {
+            size_t n = 1;
+            while (src[i + n] && src[i + n] != '"' && src[i + n] != '\n') n++;
+            if (src[i + n] != '"') {
+                err = at(line, col, "unterminated string");
+                return false;
+            }
+            t.k = T_STR;
+            t.s.assign(src + i + 1, n - 1);
+            step(n + 1);
+        } else {
+            bool ok = false;
+            for (const char *p : puncts) {
+                size_t n = std::strlen(p);
+                if (std::strncmp(src + i, p, n) == 0) {
+                    t.k = T_PUNCT;
+                    t.s = p;
+                    step(n);
+                    ok = true;
+                    break;
+                }
+            }
+            if (!ok) {
+                err = at(line, col, std::string("unexpected character '") + c + "'");
+                return false;
+            }
+        }
+        out.push_back(std::move(t));
+    }
+}
+
+// ---------------------------------------------------------------- hash-consing
+
+struct Key {
+    uint8_t op, cmp, pct;
+    int32_t a, b, chan, pchan;
+    uint32_t thr_bits;
+    uint64_t q_bits;
+    bool operator==(const Key &o) const {
+        return op == o.op && cmp == o.cmp && pct == o.pct && a == o.a && b == o.b &&
+               chan == o.chan && pchan == o.pchan && thr_bits == o.thr_bits && q_bits == o.q_bits;
+    }
+};
+
+struct KeyHash {
+    size_t operator()(const Key &k) const {
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](uint64_t v) {
+            h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+        };
+        mix(k.op | (uint64_t)k.cmp << 8 | (uint64_t)k.pct << 16);
+        mix((uint32_t)k.a | (uint64_t)(uint32_t)k.b << 32);
+        mix((uint32_t)k.chan | (uint64_t)(uint32_t)k.pchan << 32);
+        mix(k.thr_bits);
+        mix(k.q_bits);
+        return (size_t)h;
+    }
+};
+
+struct Builder {
+    Dag &dag;
+    std::unordered_map<Key, int32_t, KeyHash> memo;
+    explicit Builder(Dag &d) : dag(d) {}
+
+    int32_t make(Node n) {
+        dag.parsed_nodes++;
+        if ((n.op == Op::And || n.op == Op::Or) && n.a > n.b) std::swap(n.a, n.b);
+        Key k;
+        std::memset(&k, 0, sizeof k);
+        k.op = (uint8_t)n.op;
+        k.a = n.a;
+        k.b = n.b;
+        if (n.op == Op::Atom) {
+            k.cmp = n.cmp;
+            k.pct = n.pct;
+            k.chan = n.chan;
+            if (n.pct) {
+                k.pchan = n.pchan;
+                std::memcpy(&k.q_bits, &n.q, sizeof n.q);
+            } else {
+                std::memcpy(&k.thr_bits, &n.thr, sizeof n.thr);
+            }
+        }
+        auto it = memo.find(k);
+        if (it != memo.end()) return it->second;
+        int32_t id = (int32_t)dag.nodes.size();
+        dag.nodes.push_back(n);
+        memo.emplace(k, id);
+        return id;
+    }
+};
+
+// ---------------------------------------------------------------- parser
+
+bool is_builtin(const std::string &s) {
+    static const char *names[] = {"let", "output", "true", "false", "intensity", "percentile",
+                                  "img", "near", "N", "interior", "reach", "surrounded", "grow"};
+    for (const char *n : names)
+        if (s == n) return true;
+    return false;
+}
+
+struct Macro {
+    std::vector<std::string> params;
+    size_t body_begin = 0, body_end = 0;
+    int def_pos = 0;
+};
+
+struct Binding {
+    int pos;
+    int32_t node;   // constant binding
+    int macro;      // >= 0 for a macro binding
+};
+
+struct Parser {
+    const std::vector<Tok> &t;
+    Builder &B;
+    size_t p = 0;
+    bool failed = false;
+    std::string err;
+    bool dry = false;  // syntax check of a macro body: build no nodes
+    std::unordered_map<std::string, std::vector<Binding>> binds;
+    std::vector<Macro> macros;
+    const std::vector<std::string> *env_names = nullptr;
+    const std::vector<int32_t> *env_nodes = nullptr;
+    int limit = INT_MAX;  // only bindings with pos < limit are visible
+
+    Parser(const std::vector<Tok> &toks, Builder &b) : t(toks), B(b) {}
+
+    const Tok &cur() const { return t[p]; }
+    void fail(const std::string &msg) {
+        if (failed) return;
+        failed = true;
+        err = at(cur().line, cur().col, msg);
+    }
+    bool is_punct(const char *s) const { return cur().k == T_PUNCT && cur().s == s; }
+    bool accept(const char *s) {
+        if (is_punct(s)) {
+            p++;
+            return true;
+        }
+        return false;
+    }
+    void expect(const char *s) {
+        if (!accept(s)) fail(std::string("expected '") + s + "'");
+    }
+    int32_t make(const Node &n) { return dry ? 0 : B.make(n); }
+
+    const Binding *lookup(const std::string &name) const {
+        auto it = binds.find(name);
+        if (it == binds.end()) return nullptr;
+        for (auto r = it->second.rbegin(); r != it->second.rend(); ++r)
+            if (r->pos < limit) return &*r;
+        return nullptr;
+    }
+
+    int read_channel() {
+        if (cur().k != T_NUM || cur().s.find_first_not_of("0123456789") != std::string::npos) {
+            fail("expected channel index");
+            return 0;
+        }
+        int c = (int)cur().num;
+        p++;
+        return c;
+    }
+
+    void img_channel(int32_t &chan, bool allow_default) {
+        if (cur().k != T_IDENT || cur().s != "img") {
+            fail("expected 'img'");
+            return;
+        }
+        p++;
+        chan = 0;
+        if (accept(",")) {
+            chan = read_channel();
+        } else if (!allow_default) {
+            fail("expected ','");
+        }
+    }
+
+    int32_t atom() {
+        Node n;
+        n.op = Op::Atom;
+        expect("(");
+        if (failed) return -1;
+        img_channel(n.chan, true);
+        if (failed) return -1;
+        expect(")");
+        if (failed) return -1;
+        if (accept(">=.")) n.cmp = CMP_GE;
+        else if (accept("<=.")) n.cmp = CMP_LE;
+        else if (accept(">.")) n.cmp = CMP_GT;
+        else if (accept("<.")) n.cmp = CMP_LT;
+        else {
+            fail("expected a comparison '>.', '<.', '>=.' or '<=.'");
+            return -1;
+        }
+        if (cur().k == T_IDENT) {
+            if (cur().s != "percentile") {
+                fail("expected a number or percentile(...)");
+                return -1;
+            }
+            p++;
+            expect("(");
+            if (failed) return -1;
+            img_channel(n.pchan, false);
+            if (failed) return -1;
+            expect(",");
+            if (failed) return -1;
+            if (cur().k != T_NUM) {
+                fail("expected a percentile fraction");
+                return -1;
+            }
+            n.q = cur().num;
+            p++;
+            expect(")");
+            n.pct = 1;
+        } else {
+            bool neg = accept("-");
+            if (cur().k != T_NUM) {
+                fail("expected a number");
+                return -1;
+            }
+            double v = cur().num;
+            p++;
+            // the constant is read as double and rounded once to float32
+            n.thr = (float)(neg ? -v : v);
+        }
+        if (failed) return -1;
+        return make(n);
+    }
+
+    int32_t call(Op op, int nargs) {
+        expect("(");
+        int32_t a = expr(), b = -1;
+        if (nargs == 2) {
+            expect(",");
+            b = expr();
+        }
+        expect(")");
+        if (failed) return -1;
+        Node n;
+        n.op = op;
+        n.a = a;
+        n.b = b;
+        return make(n);
+    }
+
+    int32_t expand(const Macro &m, const std::vector<int32_t> &args) {
+        size_t save_p = p;
+        auto save_names = env_names;
+        auto save_nodes = env_nodes;
+        int save_limit = limit;
+        p = m.body_begin;
+        env_names = &m.params;
+        env_nodes = &args;
+        limit = m.def_pos;
+        int32_t r = expr();
+        if (!failed && p != m.body_end) fail("internal: macro body length mismatch");
+        p = save_p;
+        env_names = save_names;
+        env_nodes = save_nodes;
+        limit = save_limit;
+        return r;
+    }
+
+    int32_t primary() {
+        if (failed) return -1;
+        if (accept("(")) {
+            int32_t e = expr();
+            expect(")");
+            return e;
+        }
+        if (cur().k != T_IDENT) {
+            fail("expected an expression");
+            return -1;
+        }
+        std::string id = cur().s;
+        p++;
+        Node n;
+        if (id == "true") {
+            n.op = Op::True;
+            return make(n);
+        }
+        if (id == "false") {
+            n.op = Op::False;
+            return make(n);
+        }
+        if (id == "intensity") return atom();
+        if (id == "near" || id == "N") return call(Op::Near, 1);
+        if (id == "interior") return call(Op::Interior, 1);
+        if (id == "reach") return call(Op::Reach, 2);
+        if (id == "surrounded") return call(Op::Surr, 2);
+        if (id == "grow") return call(Op::Grow, 2);
+        if (is_builtin(id)) {
+            p--;
+            fail("unexpected keyword");
+            return -1;
+        }
+        if (env_names) {
+            for (size_t i = 0; i < env_names->size(); i++)
+                if ((*env_names)[i] == id) return (*env_nodes)[i];
+        }
+        const Binding *bd = lookup(id);
+        if (!bd) {
+            p--;
+            fail("undefined name '" + id + "'");
+            return -1;
+        }
+        if (bd->macro < 0) return bd->node;
+        const Macro &m = macros[(size_t)bd->macro];
+        std::vector<int32_t> args;
+        expect("(");
+        for (size_t i = 0; i < m.params.size() && !failed; i++) {
+            if (i > 0) expect(",");
+            args.push_back(expr());
+        }
+        expect(")");
+        if (failed) return -1;
+        if (dry) return 0;
+        return expand(m, args);
+    }
+
+    int32_t unary() {
+        if (failed) return -1;
+        if (accept("!")) {
+            int32_t a = unary();
+            if (failed) return -1;
+            Node n;
+            n.op = Op::Not;
+            n.a = a;
+            return make(n);
+        }
+        return primary();
+    }
+
+    int32_t binary_chain(bool is_or) {
+        int32_t l = is_or ? binary_chain(false) : unary();
+        while (!failed && accept(is_or ? "|" : "&")) {
+            int32_t r = is_or ? binary_chain(false) : unary();
+            if (failed) return -1;
+            Node n;
+            n.op = is_or ? Op::Or : Op::And;
+            n.a = l;
+            n.b = r;
+            l = make(n);
+        }
+        return l;
+    }
+
+    int32_t expr() { return binary_chain(true); }
+
+    void program() {
+        int pos = 0;
+        while (!failed && cur().k != T_END) {
+            if (cur().k != T_IDENT || (cur().s != "let" && cur().s != "output")) {
+                fail("expected 'let' or 'output'");
+                return;
+            }
+            if (cur().s == "let") {
+                p++;
+                if (cur().k != T_IDENT) {
+                    fail("expected a name after 'let'");
+                    return;
+                }
+                std::string name = cur().s;
+                if (is_builtin(name)) {
+                    fail("cannot redefine a built-in name");
+                    return;
+                }
+                p++;
+                Macro m;
+                if (accept("(")) {
+                    do {
+                        if (m.params.size() >= 16) {
+                            fail("too many parameters");
+                            return;
+                        }
+                        if (cur().k != T_IDENT) {
+                            fail("expected a parameter name");
+                            return;
+                        }
+                        m.params.push_back(cur().s);
+                        p++;
+                    } while (accept(","));
+                    expect(")");
+                }
+                expect("=");
+                if (failed) return;
+                if (!m.params.empty()) {
+                    // check the body now (names resolve to earlier bindings);
+                    // it is expanded at each call
+                    m.body_begin = p;
+                    m.def_pos = pos;
+                    std::vector<int32_t> dummy(m.params.size(), 0);
+                    env_names = &m.params;
+                    env_nodes = &dummy;
+                    dry = true;
+                    expr();
+                    dry = false;
+                    env_names = nullptr;
+                    env_nodes = nullptr;
+                    if (failed) return;
+                    m.body_end = p;
+                    macros.push_back(m);
+                    binds[name].push_back(Binding{pos, -1, (int)macros.size() - 1});
+                } else {
+                    int32_t node = expr();
+                    if (failed) return;
+                    binds[name].push_back(Binding{pos, node, -1});
+                }
+                pos++;
+            } else {
+                p++;
+                if (cur().k != T_STR) {
+                    fail("expected a quoted output name");
+                    return;
+                }
+                std::string oname = cur().s;
+                p++;
+                int32_t node = expr();
+                if (failed) return;
+                B.dag.outputs.push_back(node);
+                B.dag.output_names.push_back(oname);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+bool parse_formula(const char *src, Dag &dag, std::string &err) {
+    std::vector<Tok> toks;
+    if (!lex(src, toks, err)) return false;
+    Builder B(dag);
+    Parser P(toks, B);
+    P.program();
+    if (P.failed) {
+        err = P.err;
+        return false;
+    }
+    return true;
+}
+
+int64_t count_op(const Dag &dag, bool reach_like) {
+    int64_t n = 0;
+    for (const Node &x : dag.nodes) {
+        if (reach_like && (x.op == Op::Reach || x.op == Op::Surr || x.op == Op::Grow)) n++;
+        if (!reach_like && x.op == Op::Atom) n++;
+    }
+    return n;
+}
+
+// ---------------------------------------------------------------- schedule
+
+namespace {
+
+struct Lower {
+    const Dag &dag;
+    Mode mode;
+    std::vector<Step> steps;   // operand/out fields hold SSA value ids
+    int32_t nssa = 0;
+    std::vector<Ref> val;      // per node
+    std::vector<char> have;
+    std::map<std::pair<int32_t, uint64_t>, int32_t> pct_memo;
+    int32_t npct = 0;
+    int64_t ccl = 0;
+
+    Lower(const Dag &d, Mode m) : dag(d), mode(m), val(d.nodes.size()), have(d.nodes.size(), 0) {}
+
+    int32_t fresh() { return nssa++; }
+
+    static Ref R(int32_t s, int inv = 0) {
+        Ref r;
+        r.slot = s;
+        r.inv = (uint8_t)(inv & 1);
+        return r;
+    }
+    static Ref Const(int v) { return R(kNone, v); }
+    static Ref Neg(Ref r) {
+        r.inv ^= 1;
+        return r;
+    }
+
+    Step &emit(SK k) {
+        steps.emplace_back();
+        steps.back().kind = k;
+        return steps.back();
+    }
+
+    int32_t pct_of(int32_t chan, double q) {
+        uint64_t qb;
+        std::memcpy(&qb, &q, sizeof q);
+        auto key = std::make_pair(chan, qb);
+        auto it = pct_memo.find(key);
+        if (it != pct_memo.end()) return it->second;
+        int32_t idx = npct++;
+        Step &s = emit(SK::Pct);
+        s.chan = chan;
+        s.q = q;
+        s.pct_out = idx;
+        pct_memo.emplace(key, idx);
+        return idx;
+    }
+
+    // materialise (x OP y) ^ inv_out
+    Ref logic(Ref x, Ref y, int op, int inv_out = 0) {
+        Step &s = emit(SK::Logic);
+        s.x = x;
+        s.y = y;
+        s.op = (uint8_t)op;
+        s.inv_out = (uint8_t)inv_out;
+        s.out = fresh();
+        return R(s.out);
+    }
+    Ref near(Ref x, int inv_out, Ref z) {
+        Step &s = emit(SK::Near);
+        s.x = x;
+        s.inv_out = (uint8_t)inv_out;
+        s.z = z;
+        s.out = fresh();
+        return R(s.out);
+    }
+    // G = seeds | (pixels of b whose component meets N(seeds)), seeds = y & z
+    Ref reach_core(Ref b, Ref y, Ref z) {
+        ccl++;
+        Step &l = emit(SK::CclLocal);
+        l.x = b;
+        l.y = y;
+        l.z = z;
+        Step &m = emit(SK::CclMerge);
+        m.x = b;
+        emit(SK::CclFlag);
+        Step &g = emit(SK::CclGather);
+        g.x = b;
+        g.y = y;
+        g.z = z;
+        g.out = fresh();
+        return R(g.out);
+    }
+
+    // per-operator schedule: every node materialised by its own kernels
+    Ref perop(int32_t id) {
+        const Node &n = dag.nodes[(size_t)id];
+        const Ref one = Const(1);
+        switch (n.op) {
+        case Op::True:
+        case Op::False:
+            return logic(Const(n.op == Op::True), one, 0);
+        case Op::Atom: {
+            int32_t pi = n.pct ? pct_of(n.pchan, n.q) : -1;
+            Step &s = emit(SK::Atoms);
+            s.chan = n.chan;
+            s.natoms = 1;
+            s.atoms[0].cmp = n.cmp;
+            s.atoms[0].use_pct = n.pct;
+            s.atoms[0].thr = n.thr;
+            s.atoms[0].pct = pi;
+            s.atoms[0].out = fresh();
+            return R(s.atoms[0].out);
+        }
+        case Op::Not:
+            return logic(Neg(val[(size_t)n.a]), one, 0);
+        case Op::And:
+        case Op::Or:
+            return logic(val[(size_t)n.a], val[(size_t)n.b], n.op == Op::Or);
+        case Op::Near:
+            return near(val[(size_t)n.a], 0, one);
+        case Op::Interior: {
+            Ref t = logic(Neg(val[(size_t)n.a]), one, 0);
+            Ref u = near(t, 0, one);
+            return logic(Neg(u), one, 0);
+        }
+        case Op::Reach: {
+            Ref g = reach_core(val[(size_t)n.b], val[(size_t)n.a], one);
+            return near(g, 0, one);
+        }
+        case Op::Grow: {
+            Ref a = val[(size_t)n.a], b = val[(size_t)n.b];
+            Ref g = reach_core(b, a, one);
+            Ref r = near(g, 0, one);
+            Ref t = logic(b, r, 0);
+            return logic(a, t, 1);
+        }
+        case Op::Surr: {
+            Ref a = val[(size_t)n.a], b = val[(size_t)n.b];
+            Ref na = logic(Neg(a), one, 0);
+            Ref nb = logic(Neg(b), one, 0);
+            Ref e = logic(na, nb, 0);
+            Ref g = reach_core(nb, e, one);
+            Ref r = near(g, 0, one);
+            Ref nr = logic(Neg(r), one, 0);
+            return logic(a, nr, 0);
+        }
+        }
+        return Const(0);
+    }
+
+    // fused schedule: negations folded into consumers, derived operators run
+    // on complemented operands without materialising them
+    Ref fused(int32_t id) {
+        const Node &n = dag.nodes[(size_t)id];
+        const Ref one = Const(1);
+        auto is_const = [](Ref r) { return r.slot == kNone; };
+        switch (n.op) {
+        case Op::True:
+            return Const(1);
+        case Op::False:
+            return Const(0);
+        case Op::Atom:
+            return val[(size_t)id];  // made by the atom groups
+        case Op::Not:
+            return Neg(val[(size_t)n.a]);
+        case Op::And:
+        case Op::Or: {
+            Ref a = val[(size_t)n.a], b = val[(size_t)n.b];
+            bool isor = n.op == Op::Or;
+            // x & 0 = 0, x & 1 = x, x | 1 = 1, x | 0 = x
+            if (is_const(a)) std::swap(a, b);
+            if (is_const(b)) return (b.inv == (isor ? 1 : 0)) ? b : a;
+            return logic(a, b, isor);
+        }
+        case Op::Near: {
+            Ref a = val[(size_t)n.a];
+            if (is_const(a)) return a;  // N 0 = 0, N 1 = 1
+            return near(a, 0, one);
+        }
+        case Op::Interior: {
+            Ref a = val[(size_t)n.a];
+            if (is_const(a)) return a;
+            return near(Neg(a), 1, one);  // !N!a
+        }
+        case Op::Reach: {
+            Ref a = val[(size_t)n.a], b = val[(size_t)n.b];
+            if (is_const(a)) return a;                   // rho 0[b] = 0, rho 1[b] = 1
+            if (is_const(b) && b.inv == 0) return near(a, 0, one);  // rho a[0] = N a
+            Ref g = reach_core(b, a, one);
+            return near(g, 0, one);
+        }
+        case Op::Grow: {
+            Ref a = val[(size_t)n.a], b = val[(size_t)n.b];
+            if (is_const(a)) return a;
+            if (is_const(b) && b.inv == 0) return a;     // grow(a, 0) = a
+            return reach_core(b, a, one);                // a | Z
+        }
+        case Op::Surr: {
+            // a & !rho(!a & !b)[!b]
+            Ref a = val[(size_t)n.a], b = val[(size_t)n.b];
+            if (is_const(a) && a.inv == 0) return a;     // surrounded(0, b) = 0
+            Ref g = reach_core(Neg(b), Neg(a), Neg(b));
+            return near(g, 1, a);
+        }
+        }
+        return Const(0);
+    }
+
+    void atom_groups(const std::vector<char> &need) {
+        // one pass per channel reads the channel once for all its atoms
+        std::map<int32_t, std::vector<int32_t>> by_chan;
+        for (size_t i = 0; i < dag.nodes.size(); i++)
+            if (need[i] && dag.nodes[i].op == Op::Atom) by_chan[dag.nodes[i].chan].push_back((int32_t)i);
+        for (auto &kv : by_chan)
+            for (int32_t id : kv.second)
+                if (dag.nodes[(size_t)id].pct) pct_of(dag.nodes[(size_t)id].pchan, dag.nodes[(size_t)id].q);
+        for (auto &kv : by_chan) {
+            const auto &ids = kv.second;
+            for (size_t i = 0; i < ids.size(); i += kMaxAtoms) {
+                Step &s = emit(SK::Atoms);
+                s.chan = kv.first;
+                for (size_t j = i; j < ids.size() && j < i + kMaxAtoms; j++) {
+                    const Node &n = dag.nodes[(size_t)ids[j]];
+                    AtomEntry &e = s.atoms[s.natoms++];
+                    e.cmp = n.cmp;
+                    e.use_pct = n.pct;
+                    e.thr = n.thr;
+                    e.pct = n.pct ? pct_of(n.pchan, n.q) : -1;
+                    e.out = fresh();
+                    val[(size_t)ids[j]] = R(e.out);
+                    have[(size_t)ids[j]] = 1;
+                }
+            }
+        }
+    }
+};
+
+void for_each_ref(Step &s, void (*fn)(Ref &, void *), void *ctx) {
+    fn(s.x, ctx);
+    fn(s.y, ctx);
+    fn(s.z, ctx);
+}
+
+}  // namespace
+
+Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
+    Lower L(dag, mode);
+    const size_t N = dag.nodes.size();
+    std::vector<char> need(N, 0);
+    for (int k : which) need[(size_t)dag.outputs[(size_t)k]] = 1;
+    for (size_t i = N; i-- > 0;) {
+        if (!need[i]) continue;
+        const Node &n = dag.nodes[i];
+        if (n.a >= 0) need[(size_t)n.a] = 1;
+        if (n.b >= 0) need[(size_t)n.b] = 1;
+    }
+    if (mode == Mode::Fused) L.atom_groups(need);
+    for (size_t i = 0; i < N; i++) {
+        if (!need[i] || L.have[i]) continue;
+        L.val[i] = mode == Mode::Fused ? L.fused((int32_t)i) : L.perop((int32_t)i);
+        L.have[i] = 1;
+    }
+
+    // route each requested output to its external slot: the first output of
+    // an SSA value takes it over directly, any other use gets a copy step
+    const Ref one = Lower::Const(1);
+    std::vector<int32_t> ext_of(L.nssa, kNone);
+    for (size_t k = 0; k < which.size(); k++) {
+        Ref r = L.val[(size_t)dag.outputs[(size_t)which[k]]];
+        if (r.slot != kNone && r.inv == 0 && ext_of[(size_t)r.slot] == kNone) {
+            ext_of[(size_t)r.slot] = ext_slot((int)k);
+        } else {
+            Step &s = L.emit(SK::Logic);
+            s.x = r;
+            s.y = one;
+            s.op = 0;
+            s.out = L.fresh();
+            ext_of.push_back(ext_slot((int)k));
+        }
+    }
+
+    // liveness over SSA values, then greedy slot reuse
+    const int32_t nv = L.nssa;
+    std::vector<int64_t> last(nv, -1);
+    for (size_t si = 0; si < L.steps.size(); si++) {
+        Step &s = L.steps[si];
+        for (Ref *r : {&s.x, &s.y, &s.z})
+            if (r->slot != kNone) last[(size_t)r->slot] = (int64_t)si;
+    }
+    std::vector<int32_t> slot_of(nv, kNone);
+    std::vector<int32_t> free_slots;
+    int32_t nslots = 0;
+    auto alloc = [&](int32_t v) {
+        if (ext_of[(size_t)v] != kNone) {
+            slot_of[(size_t)v] = ext_of[(size_t)v];
+            return;
+        }
+        if (!free_slots.empty()) {
+            slot_of[(size_t)v] = free_slots.back();
+            free_slots.pop_back();
+        } else {
+            slot_of[(size_t)v] = nslots++;
+        }
+    };
+    auto release = [&](int32_t v) {
+        int32_t s = slot_of[(size_t)v];
+        if (s >= 0) free_slots.push_back(s);
+    };
+    for (size_t si = 0; si < L.steps.size(); si++) {
+        Step &s = L.steps[si];
+        std::vector<int32_t> outs;
+        if (s.kind == SK::Atoms) {
+            for (int j = 0; j < s.natoms; j++) outs.push_back(s.atoms[j].out);
+        } else if (s.out != kNone) {
+            outs.push_back(s.out);
+        }
+        for (int32_t v : outs) alloc(v);
+        // rename operands and outputs to slots
+        std::vector<int32_t> dying;
+        for (Ref *r : {&s.x, &s.y, &s.z}) {
+            if (r->slot == kNone) continue;
+            int32_t v = r->slot;
+            if (last[(size_t)v] == (int64_t)si &&
+                std::find(dying.begin(), dying.end(), v) == dying.end())
+                dying.push_back(v);
+            r->slot = slot_of[(size_t)v];
+        }
+        if (s.kind == SK::Atoms) {
+            for (int j = 0; j < s.natoms; j++) s.atoms[j].out = slot_of[(size_t)s.atoms[j].out];
+        } else if (s.out != kNone) {
+            s.out = slot_of[(size_t)s.out];
+        }
+        for (int32_t v : dying) release(v);
+        for (int32_t v : outs)
+            if (last[(size_t)v] < 0 && !is_ext(slot_of[(size_t)v])) release(v);
+    }
+    (void)for_each_ref;
+
+    Plan P;
+    P.steps = std::move(L.steps);
+    P.nslots = nslots;
+    P.npct = L.npct;
+    P.noutputs = (int32_t)which.size();
+    P.ccl_count = L.ccl;
+    P.output_ids.assign(which.begin(), which.end());
+    return P;
+}
+
+}  // namespace vlg

@@ -1,0 +1,105 @@
+// compiler.h -- formula front end and schedule builder (host side).
+//
+// Text (ImgQL subset, paper Sect. 3 Syntax) -> hash-consed DAG of SLCS
+// operators (Sect. 2, Eq. def:syntax plus the derived interior, surrounded
+// and grow) -> a linear schedule of kernel steps over 1-bit-packed masks.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace vlg {
+
+enum class Op : uint8_t { True, False, Atom, Not, And, Or, Near, Interior, Reach, Surr, Grow };
+
+enum Cmp : uint8_t { CMP_GT = 0, CMP_LT = 1, CMP_GE = 2, CMP_LE = 3 };
+
+struct Node {
+    Op op;
+    int32_t a = -1, b = -1;  // operand node ids
+    // Atom: float32(img[chan]) CMP t; t = thr, or the percentile (pchan, q)
+    int32_t chan = 0;
+    uint8_t cmp = CMP_GT;
+    uint8_t pct = 0;
+    float thr = 0.f;
+    int32_t pchan = 0;
+    double q = 0.0;
+};
+
+struct Dag {
+    std::vector<Node> nodes;             // topologically ordered: operands first
+    std::vector<int32_t> outputs;        // node id per `output` statement
+    std::vector<std::string> output_names;
+    int64_t parsed_nodes = 0;            // operator applications before hash-consing
+};
+
+// Parse `src`; on failure returns false and sets err to "line L col C: msg".
+bool parse_formula(const char *src, Dag &dag, std::string &err);
+
+// ---------------------------------------------------------------- schedule
+
+// An operand: a mask slot with an optional complement.  slot == kNone means
+// the all-zero mask (all-one when inv is set).
+constexpr int32_t kNone = -1;
+inline constexpr int32_t ext_slot(int k) { return -2 - k; }  // caller output k
+inline constexpr bool is_ext(int32_t s) { return s <= -2; }
+inline constexpr int ext_index(int32_t s) { return -2 - s; }
+
+struct Ref {
+    int32_t slot = kNone;
+    uint8_t inv = 0;
+};
+
+enum class SK : uint8_t {
+    Pct,        // percentile of channel `chan` at q -> pct scalar `pct_out`
+    Atoms,      // up to kMaxAtoms thresholds of channel `chan` -> masks
+    Logic,      // out = ((x ^ x.inv) OP (y ^ y.inv)) ^ inv_out ; OP = and/or
+    Near,       // out = (N(x ^ x.inv) ^ inv_out) & (z ^ z.inv)
+    CclLocal,   // tile-local union-find of b = x; seeds = N(y & z) & b
+    CclMerge,   // cross-tile merge of the labelling of b = x
+    CclFlag,    // propagate seed flags to the final roots
+    CclGather,  // out = (y & z) | (pixels of b = x whose component has a seed)
+};
+
+constexpr int kMaxAtoms = 8;
+
+struct AtomEntry {
+    uint8_t cmp = CMP_GT;
+    uint8_t use_pct = 0;
+    float thr = 0.f;
+    int32_t pct = -1;    // pct scalar index if use_pct
+    int32_t out = kNone; // output slot
+};
+
+struct Step {
+    SK kind;
+    int32_t out = kNone;
+    Ref x, y, z;
+    uint8_t op = 0;       // Logic: 0 = and, 1 = or
+    uint8_t inv_out = 0;
+    int32_t chan = 0;
+    double q = 0.0;
+    int32_t pct_out = -1;
+    int natoms = 0;
+    AtomEntry atoms[kMaxAtoms];
+};
+
+enum class Mode : uint8_t { PerOp = 0, Fused = 1 };
+
+struct Plan {
+    std::vector<Step> steps;
+    int32_t nslots = 0;        // internal mask slots
+    int32_t npct = 0;          // percentile scalars
+    int32_t noutputs = 0;      // requested outputs (external slots 0..noutputs-1)
+    int64_t ccl_count = 0;     // reachability labellings per evaluation
+    std::vector<int32_t> output_ids;  // formula output index per external slot
+};
+
+// Build the schedule evaluating formula outputs `which` (indices into
+// dag.outputs); external slot k receives output which[k].
+Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode);
+
+// Number of reach/surrounded/grow nodes and of atoms.
+int64_t count_op(const Dag &dag, bool reach_like);
+
+}  // namespace vlg

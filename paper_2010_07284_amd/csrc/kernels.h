@@ -1,0 +1,70 @@
+// kernels.h -- host-side launchers of the HIP kernels (gfx950, wave64).
+//
+// All masks are 1-bit-packed: row-major uint64 words, wpr = ceil(W/64) per
+// row, pixel (y, x) = bit x%64 of word y*wpr + x/64, bits x >= W kept zero.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vlg {
+
+// Operand: a packed mask, optionally complemented.  p == nullptr stands for
+// the all-zero mask (all-one when complemented).
+struct MRef {
+    const uint64_t *p;
+    uint64_t inv;  // 0 or ~0
+};
+
+struct Geo {
+    int32_t H, W, wpr;
+    uint64_t tail;     // valid-bit mask of the last word of a row
+    int64_t nwords;    // H * wpr
+    int32_t BH, BW;    // 2x2 block grid: ceil(H/2) x ceil(W/2)
+    uint32_t wpr_mul;  // fast division by wpr (see fastdiv in kernels.hip)
+    uint32_t wpr_shift;
+};
+
+Geo make_geo(int H, int W);
+
+// Tile geometry of the reachability labelling: TBH x TBW blocks per tile.
+constexpr int kTileBH = 16;            // block rows per tile (32 pixel rows)
+constexpr int kTileWW = 2;             // words per tile row (128 pixel columns)
+constexpr int kTileBW = 32 * kTileWW;  // block columns per tile
+
+struct CclWork {
+    int32_t *glab;       // [BH*BW] parent pointers (block ids, row-major)
+    uint8_t *gflag;      // [BH*BW] bit1: tile-local root, bit0: meets the seeds
+    unsigned long long *counters; // [2] merge unions, merge retries (may be null)
+};
+
+struct AtomLaunch {
+    int n;
+    uint8_t cmp[8];
+    float thr[8];
+    const float *thr_dev[8];  // device scalar (percentile) or null
+    uint64_t *out[8];
+};
+
+hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out);
+hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, uint64_t *out);
+hipError_t launch_atoms(hipStream_t s, const Geo &g, const void *chan, int dtype, const AtomLaunch &a);
+hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w);
+hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &w);
+hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w);
+hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w,
+                             uint64_t *out);
+hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *labels);
+hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint8_t *out);
+hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v);
+
+}  // namespace vlg
+
+namespace vlg {
+// Percentile (k-th smallest value of a channel, nearest rank) by radix select
+// over order-preserving uint32 keys.  `state` is kPctStateBytes of device
+// scratch; the result is written to *result.
+constexpr size_t kPctStateBytes = 8448;
+hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, int64_t pitch,
+                             uint32_t k, void *state, float *result);
+}  // namespace vlg

@@ -1,0 +1,677 @@
+// kernels.hip -- HIP kernels for gfx950 (CDNA4, wave64) on 1-bit-packed masks.
+//
+// Operators (paper "A spatial model checker in GPU", Sect. 2): threshold
+// atoms, pixel-wise Boolean connectives, N (Moore-neighbourhood dilation) and
+// reachability rho a[b].  rho follows the decomposition of Sect. 3: label the
+// 8-connected components of b, keep the components that meet N a, and dilate
+// their union with a.  The labelling is not the paper's iterative
+// pointer-jumping scheme (Alg. CCL) but union-find over 2x2 pixel blocks
+// (every foreground pixel of a 2x2 block lies in one 8-component), run as a
+// tile-local pass in LDS followed by a global merge of tile borders with
+// atomicMin hooking, so it needs a fixed number of launches and no host-side
+// termination check.
+#include "kernels.h"
+
+namespace vlg {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t shift) {
+    return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> shift);
+}
+
+__device__ __forceinline__ uint64_t ldm(const MRef &r, int64_t i) {
+    return (r.p ? r.p[i] : 0ull) ^ r.inv;
+}
+
+__device__ __forceinline__ bool is_last_col(const Geo &g, int64_t i) {
+    uint32_t row = fdiv((uint32_t)i, g.wpr_mul, g.wpr_shift);
+    return (uint32_t)i - row * (uint32_t)g.wpr == (uint32_t)(g.wpr - 1);
+}
+
+int grid_for(int64_t n, int per_block, int cap) {
+    int64_t b = (n + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+// ------------------------------------------------------------------ Boolean
+// out = ((x ^ x.inv) OP (y ^ y.inv)) ^ inv_out, OP = and (op 0) / or (op 1).
+__global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int op, uint64_t inv_out,
+                                                    uint64_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
+        uint64_t a = ldm(x, i), b = ldm(y, i);
+        uint64_t r = (op ? (a | b) : (a & b)) ^ inv_out;
+        if (is_last_col(g, i)) r &= g.tail;
+        out[i] = r;
+    }
+}
+
+// ------------------------------------------------------------------ near
+// out = (N(x) ^ inv_out) & z.  N over the in-image 3x3 block: horizontal
+// dilation inside a word with the edge bits of the neighbouring words, then the
+// OR of three rows.  Complemented inputs have their padding bits cleared first
+// so nothing leaks in from beyond the right border.
+__global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z,
+                                                   uint64_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
+        const uint32_t y = fdiv((uint32_t)i, g.wpr_mul, g.wpr_shift);
+        const int32_t w = (int32_t)((uint32_t)i - y * (uint32_t)g.wpr);
+        const bool last = w == g.wpr - 1;
+        uint64_t acc = 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++) {
+            const int yy = (int)y + dy;
+            if (yy < 0 || yy >= g.H) continue;
+            const int64_t base = (int64_t)yy * g.wpr + w;
+            uint64_t c = ldm(x, base);
+            if (last) c &= g.tail;
+            const uint64_t l = w > 0 ? ldm(x, base - 1) : 0ull;
+            const uint64_t r = last ? 0ull : ldm(x, base + 1);
+            acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
+        }
+        uint64_t res = (acc ^ inv_out) & ldm(z, i);
+        if (last) res &= g.tail;
+        out[i] = res;
+    }
+}
+
+// ------------------------------------------------------------------ atoms
+// The image is stored with a row pitch of wpr*64 elements, so pixel word i of
+// a mask covers elements [64 i, 64 i + 64) of the channel.  A wave takes 64
+// consecutive words: lane l reads element 64 k + l (256 coalesced bytes per
+// load for float32), the wave-wide compare result is the packed word k, and
+// lane k keeps it; one coalesced 512-byte store per output at the end.
+__device__ __forceinline__ bool cmp_pix(float f, float t, int c) {
+    const bool gt = f > t, lt = f < t, eq = f == t;
+    return c == 0 ? gt : c == 1 ? lt : c == 2 ? (gt || eq) : (lt || eq);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__ img, AtomLaunch a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    float thr[N];
+    int cmp[N];
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        thr[j] = a.thr_dev[j] ? *a.thr_dev[j] : a.thr[j];
+        cmp[j] = a.cmp[j];
+    }
+    const int64_t ntasks = (g.nwords + 63) / 64;
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves) {
+        const int64_t w0 = t * 64;
+        const int nw = (int)((g.nwords - w0) < 64 ? (g.nwords - w0) : 64);
+        uint64_t mine[N];
+#pragma unroll
+        for (int j = 0; j < N; j++) mine[j] = 0;
+        const T *src = img + w0 * 64 + lane;
+        if (nw == 64) {
+#pragma unroll 16
+            for (int k = 0; k < 64; k++) {
+                const float f = (float)src[k * 64];
+#pragma unroll
+                for (int j = 0; j < N; j++) {
+                    const uint64_t m = __ballot(cmp_pix(f, thr[j], cmp[j]));
+                    mine[j] = lane == k ? m : mine[j];
+                }
+            }
+        } else {
+            for (int k = 0; k < nw; k++) {
+                const float f = (float)src[k * 64];
+#pragma unroll
+                for (int j = 0; j < N; j++) {
+                    const uint64_t m = __ballot(cmp_pix(f, thr[j], cmp[j]));
+                    mine[j] = lane == k ? m : mine[j];
+                }
+            }
+        }
+        if (lane < nw) {
+            const int64_t wi = w0 + lane;
+            const uint64_t keep = is_last_col(g, wi) ? g.tail : ~0ull;
+#pragma unroll
+            for (int j = 0; j < N; j++) a.out[j][wi] = mine[j] & keep;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ CCL
+// Blocks: block (by, bx) holds pixels rows 2by..2by+1, cols 2bx..2bx+1.  Its
+// four bits: 1 = top-left, 2 = top-right, 4 = bottom-left, 8 = bottom-right.
+// Any two foreground pixels of one block are 8-adjacent, so a block is a
+// union-find node.  Block ids are row-major, id = by*BW + bx; the root of a
+// set is its smallest id, whose block holds the component's first pixel in
+// raster order.
+//
+// 8-adjacency between a block and its earlier neighbours:
+//   left:       (tl|bl) of the block and (tr|br) of the left block
+//   up:         (tl|tr) and (bl|br) of the upper block
+//   up-left:    tl and br of the upper-left block
+//   up-right:   tr and bl of the upper-right block
+
+__device__ __forceinline__ int lds_ld(int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ int lds_find(int *L, int x) {
+    while (true) {
+        const int p = lds_ld(&L[x]);
+        if (p == x) return x;
+        const int gp = lds_ld(&L[p]);
+        if (gp == p) return p;
+        L[x] = gp;  // path halving: gp is an ancestor of x
+        x = gp;
+    }
+}
+
+__device__ void lds_unite(int *L, int a, int b) {
+    while (true) {
+        a = lds_find(L, a);
+        b = lds_find(L, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(&L[a], b);  // hook the larger root under the smaller
+        if (old == a) return;
+        a = old;  // a was hooked meanwhile: unite its new parent instead
+    }
+}
+
+// Global union-find for the cross-tile merge.  Loads and stores are
+// device-coherent atomics: the L2 of one XCD is not coherent with another's
+// within a kernel.
+__device__ __forceinline__ int g_ld(int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_st(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ int g_find(int *L, int x) {
+    while (true) {
+        const int p = g_ld(&L[x]);
+        if (p == x) return x;
+        const int gp = g_ld(&L[p]);
+        if (gp == p) return p;
+        g_st(&L[x], gp);
+        x = gp;
+    }
+}
+
+__device__ int g_unite(int *L, int a, int b) {
+    int tries = 0;
+    while (true) {
+        tries++;
+        a = g_find(L, a);
+        b = g_find(L, b);
+        if (a == b) return tries;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(&L[a], b);
+        if (old == a) return tries;
+        a = old;
+    }
+}
+
+__device__ __forceinline__ uint32_t block_bits_g(const Geo &g, const MRef &b, int by, int bx) {
+    const int w = bx >> 5, sh = (bx & 31) * 2, y0 = 2 * by;
+    const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+    const uint64_t t = ldm(b, (int64_t)y0 * g.wpr + w) & keep;
+    const uint64_t u = y0 + 1 < g.H ? (ldm(b, (int64_t)(y0 + 1) * g.wpr + w) & keep) : 0ull;
+    return (uint32_t)((t >> sh) & 3) | ((uint32_t)((u >> sh) & 3) << 2);
+}
+
+// Tile-local labelling of b (TBH x TBW blocks per workgroup), plus the seed
+// test: a block meets the seeds when one of its b-pixels lies in N(y & z).
+template <int TBH, int TWW>
+__global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
+                                                        int32_t *__restrict__ glab,
+                                                        uint8_t *__restrict__ gflag) {
+    constexpr int TR = 2 * TBH, TBW = 32 * TWW, NB = TBH * TBW;
+    __shared__ uint64_t sb[TR][TWW];
+    __shared__ uint64_t sa[TR + 2][TWW + 2];
+    __shared__ int L[NB];
+    __shared__ uint8_t sbits[NB];
+    __shared__ uint8_t sseed[NB];
+    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int r0 = ty * TR, wc0 = tx * TWW;
+
+    for (int i = threadIdx.x; i < TR * TWW; i += kThreads) {
+        const int r = i / TWW, w = i % TWW, yy = r0 + r, ww = wc0 + w;
+        uint64_t v = 0;
+        if (yy < g.H && ww < g.wpr) {
+            v = ldm(b, (int64_t)yy * g.wpr + ww);
+            if (ww == g.wpr - 1) v &= g.tail;
+        }
+        sb[r][w] = v;
+    }
+    for (int i = threadIdx.x; i < (TR + 2) * (TWW + 2); i += kThreads) {
+        const int r = i / (TWW + 2), w = i % (TWW + 2), yy = r0 + r - 1, ww = wc0 + w - 1;
+        uint64_t v = 0;
+        if (yy >= 0 && yy < g.H && ww >= 0 && ww < g.wpr) {
+            const int64_t idx = (int64_t)yy * g.wpr + ww;
+            v = ldm(y, idx) & ldm(z, idx);
+            if (ww == g.wpr - 1) v &= g.tail;
+        }
+        sa[r][w] = v;
+    }
+    __syncthreads();
+
+    for (int i = threadIdx.x; i < NB; i += kThreads) {
+        const int lby = i / TBW, lbx = i % TBW, w = lbx >> 5, sh = (lbx & 31) * 2;
+        const uint32_t bits = (uint32_t)((sb[2 * lby][w] >> sh) & 3) |
+                              ((uint32_t)((sb[2 * lby + 1][w] >> sh) & 3) << 2);
+        uint32_t seed = 0;
+        if (bits) {
+            // seed pixels within the 4x4 window around the block: rows
+            // 2lby-1 .. 2lby+2, cols 2lbx-1 .. 2lbx+2 (halo coordinates +1 row,
+            // +64 columns)
+            const int c = 64 * (w + 1) + sh - 1, q = c >> 6, s = c & 63;
+            uint32_t win[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint64_t lo = sa[2 * lby + k][q] >> s;
+                const uint64_t hi = s > 60 ? (sa[2 * lby + k][q + 1] << (64 - s)) : 0ull;
+                win[k] = (uint32_t)((lo | hi) & 0xF);
+            }
+            const uint32_t top = win[0] | win[1] | win[2], bot = win[1] | win[2] | win[3];
+            const uint32_t nmask = ((top & 0x7) ? 1u : 0u) | ((top & 0xE) ? 2u : 0u) |
+                                   ((bot & 0x7) ? 4u : 0u) | ((bot & 0xE) ? 8u : 0u);
+            seed = (bits & nmask) ? 1u : 0u;
+        }
+        sbits[i] = (uint8_t)bits;
+        sseed[i] = (uint8_t)seed;
+        L[i] = i;
+    }
+    __syncthreads();
+
+    for (int i = threadIdx.x; i < NB; i += kThreads) {
+        const uint32_t bits = sbits[i];
+        if (!bits) continue;
+        const int lby = i / TBW, lbx = i % TBW;
+        if (lbx > 0 && (bits & 5) && (sbits[i - 1] & 10)) lds_unite(L, i, i - 1);
+        if (lby > 0) {
+            if ((bits & 3) && (sbits[i - TBW] & 12)) lds_unite(L, i, i - TBW);
+            if (lbx > 0 && (bits & 1) && (sbits[i - TBW - 1] & 8)) lds_unite(L, i, i - TBW - 1);
+            if (lbx < TBW - 1 && (bits & 2) && (sbits[i - TBW + 1] & 4)) lds_unite(L, i, i - TBW + 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB; i += kThreads)
+        if (sbits[i]) L[i] = lds_find(L, i);
+    __syncthreads();
+    // seed flag on the local root (only roots are written, all with 1)
+    for (int i = threadIdx.x; i < NB; i += kThreads)
+        if (sbits[i] && sseed[i]) sseed[L[i]] = 1;
+    __syncthreads();
+
+    for (int i = threadIdx.x; i < NB; i += kThreads) {
+        const int lby = i / TBW, lbx = i % TBW;
+        const int by = ty * TBH + lby, bx = tx * TBW + lbx;
+        if (by >= g.BH || bx >= g.BW) continue;
+        const int64_t id = (int64_t)by * g.BW + bx;
+        if (sbits[i]) {
+            const int r = L[i];
+            const int gr = (ty * TBH + r / TBW) * g.BW + tx * TBW + r % TBW;
+            glab[id] = gr;
+            gflag[id] = r == i ? (uint8_t)(2 | sseed[i]) : (uint8_t)0;
+        } else {
+            glab[id] = (int32_t)id;
+            gflag[id] = 0;
+        }
+    }
+}
+
+// Cross-tile merge: blocks on a tile's top row, left column and right column
+// unite with their earlier neighbours in other tiles.
+template <int TBH, int TWW>
+__global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int ntiles,
+                                                        int32_t *glab, unsigned long long *counters) {
+    constexpr int TBW = 32 * TWW, PER = TBW + 2 * TBH;
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    int unions = 0, tries = 0;
+    if (t < (int64_t)ntiles * PER) {
+        const int tile = (int)(t / PER), k = (int)(t % PER);
+        const int tx = tile % ntx, ty = tile / ntx;
+        int lby, lbx, kind;
+        if (k < TBW) {
+            lby = 0; lbx = k; kind = 0;
+        } else if (k < TBW + TBH) {
+            lby = k - TBW; lbx = 0; kind = 1;
+        } else {
+            lby = k - TBW - TBH; lbx = TBW - 1; kind = 2;
+        }
+        const int by = ty * TBH + lby, bx = tx * TBW + lbx;
+        if (by < g.BH && bx < g.BW) {
+            const uint32_t bits = block_bits_g(g, b, by, bx);
+            const int id = by * g.BW + bx;
+            if (bits) {
+                auto link = [&](int nby, int nbx) {
+                    unions++;
+                    tries += g_unite(glab, id, nby * g.BW + nbx);
+                };
+                if (kind == 0 && by > 0) {
+                    if ((bits & 3) && (block_bits_g(g, b, by - 1, bx) & 12)) link(by - 1, bx);
+                    if (bx > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) link(by - 1, bx - 1);
+                    if (bx + 1 < g.BW && (bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4))
+                        link(by - 1, bx + 1);
+                } else if (kind == 1 && bx > 0) {
+                    if ((bits & 5) && (block_bits_g(g, b, by, bx - 1) & 10)) link(by, bx - 1);
+                    if (lby > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) link(by - 1, bx - 1);
+                } else if (kind == 2 && lby > 0 && bx + 1 < g.BW) {
+                    if ((bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) link(by - 1, bx + 1);
+                }
+            }
+        }
+    }
+    if (counters && (unions | tries)) {
+        atomicAdd(&counters[0], (unsigned long long)unions);
+        atomicAdd(&counters[1], (unsigned long long)(tries - unions));
+    }
+}
+
+// Point every tile-local root at its final root and carry its seed flag there.
+__global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride) {
+        const uint8_t f = gflag[i];
+        if (!(f & 2)) continue;
+        int x = (int)i;
+        while (true) {
+            const int p = glab[x];
+            if (p == x) break;
+            x = p;
+        }
+        if (x != (int)i) {
+            glab[i] = x;
+            if (f & 1) gflag[x] = 3;  // roots are local roots: bit1 already set
+        }
+    }
+}
+
+// out = (y & z) | Z, Z = the b-pixels whose component meets the seeds.  Every
+// foreground block points at a tile-local root, and every tile-local root at
+// its final root, so the root is two loads away.
+__global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, MRef z,
+                                                         const int32_t *__restrict__ glab,
+                                                         const uint8_t *__restrict__ gflag,
+                                                         uint64_t *__restrict__ out) {
+    const int64_t n = (int64_t)g.BH * g.wpr;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const int by = (int)(i / g.wpr), w = (int)(i % g.wpr);
+        const int y0 = 2 * by;
+        const bool two = y0 + 1 < g.H;
+        const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+        const int64_t i0 = (int64_t)y0 * g.wpr + w, i1 = i0 + g.wpr;
+        const uint64_t t = ldm(b, i0) & keep;
+        const uint64_t u = two ? (ldm(b, i1) & keep) : 0ull;
+        uint64_t zm = 0;
+        const uint64_t any = t | u;
+        if (any) {
+            const int64_t rowbase = (int64_t)by * g.BW + 32 * w;
+            for (int j = 0; j < 32; j++) {
+                if (!((any >> (2 * j)) & 3)) continue;
+                const int lr = glab[rowbase + j];
+                const int r = glab[lr];
+                if (gflag[r] & 1) zm |= 3ull << (2 * j);
+            }
+        }
+        out[i0] = ((ldm(y, i0) & ldm(z, i0)) | (t & zm)) & keep;
+        if (two) out[i1] = ((ldm(y, i1) & ldm(z, i1)) | (u & zm)) & keep;
+    }
+}
+
+// Canonical labels: smallest row-major pixel index of each component.
+__global__ __launch_bounds__(kThreads) void k_ccl_labels(Geo g, MRef b, const int32_t *__restrict__ glab,
+                                                         int32_t *__restrict__ labels) {
+    const int x = blockIdx.x * kThreads + threadIdx.x, yy = blockIdx.y;
+    if (x >= g.W) return;
+    const int w = x >> 6;
+    uint64_t word = ldm(b, (int64_t)yy * g.wpr + w);
+    if (w == g.wpr - 1) word &= g.tail;
+    int32_t lab = -1;
+    if ((word >> (x & 63)) & 1) {
+        const int lr = glab[(int64_t)(yy >> 1) * g.BW + (x >> 1)];
+        const int r = glab[lr];
+        const int rby = r / g.BW, rbx = r % g.BW;
+        const uint32_t bits = block_bits_g(g, b, rby, rbx);
+        const int k = __builtin_ctz(bits);
+        lab = (2 * rby + (k >> 1)) * g.W + 2 * rbx + (k & 1);
+    }
+    labels[(int64_t)yy * g.W + x] = lab;
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpack(Geo g, const uint64_t *__restrict__ mask,
+                                                     uint8_t *__restrict__ out) {
+    const int x = blockIdx.x * kThreads + threadIdx.x, yy = blockIdx.y;
+    if (x >= g.W) return;
+    out[(int64_t)yy * g.W + x] = (uint8_t)((mask[(int64_t)yy * g.wpr + (x >> 6)] >> (x & 63)) & 1);
+}
+
+__global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
+int ntiles_y(const Geo &g) { return (g.BH + kTileBH - 1) / kTileBH; }
+
+}  // namespace
+
+Geo make_geo(int H, int W) {
+    Geo g;
+    g.H = H;
+    g.W = W;
+    g.wpr = (W + 63) / 64;
+    g.tail = (W % 64) ? ((1ull << (W % 64)) - 1) : ~0ull;
+    g.nwords = (int64_t)H * g.wpr;
+    g.BH = (H + 1) / 2;
+    g.BW = (W + 1) / 2;
+    // n / d = (umulhi(n, mul) + n) >> shift, valid for all 32-bit n
+    uint32_t d = (uint32_t)(g.wpr > 0 ? g.wpr : 1), s = 0;
+    while ((1ull << s) < d) s++;
+    g.wpr_mul = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+    g.wpr_shift = s;
+    return g;
+}
+
+hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out) {
+    if (g.nwords == 0) return hipSuccess;
+    k_logic<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, uint64_t *out) {
+    if (g.nwords == 0) return hipSuccess;
+    k_near<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, inv_out ? ~0ull : 0ull, z, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t atoms_t(hipStream_t s, const Geo &g, const T *img, const AtomLaunch &a) {
+    const int grid = grid_for((g.nwords + 63) / 64, kThreads / 64, 8192);
+    switch (a.n) {
+    case 1: k_atoms<T, 1><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    case 2: k_atoms<T, 2><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    case 3: k_atoms<T, 3><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    case 4: k_atoms<T, 4><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    case 5: k_atoms<T, 5><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    case 6: k_atoms<T, 6><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    case 7: k_atoms<T, 7><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    case 8: k_atoms<T, 8><<<grid, kThreads, 0, s>>>(g, img, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_atoms(hipStream_t s, const Geo &g, const void *chan, int dtype, const AtomLaunch &a) {
+    if (g.nwords == 0) return hipSuccess;
+    if (dtype == 1) return atoms_t(s, g, (const uint8_t *)chan, a);
+    return atoms_t(s, g, (const float *)chan, a);
+}
+
+hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w) {
+    if (g.nwords == 0) return hipSuccess;
+    const int ntx = ntiles_x(g), nty = ntiles_y(g);
+    k_ccl_local<kTileBH, kTileWW><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &w) {
+    if (g.nwords == 0) return hipSuccess;
+    const int ntx = ntiles_x(g), nty = ntiles_y(g);
+    const int64_t n = (int64_t)ntx * nty * (kTileBW + 2 * kTileBH);
+    k_ccl_merge<kTileBH, kTileWW><<<(int)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        g, b, ntx, ntx * nty, w.glab, w.counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w) {
+    if (g.nwords == 0) return hipSuccess;
+    const int64_t nb = (int64_t)g.BH * g.BW;
+    k_ccl_flag<<<grid_for(nb, kThreads, 8192), kThreads, 0, s>>>(nb, w.glab, w.gflag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w,
+                             uint64_t *out) {
+    if (g.nwords == 0) return hipSuccess;
+    const int64_t n = (int64_t)g.BH * g.wpr;
+    k_ccl_gather<<<grid_for(n, kThreads, 8192), kThreads, 0, s>>>(g, b, y, z, w.glab, w.gflag, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *labels) {
+    if (g.nwords == 0) return hipSuccess;
+    dim3 grid((g.W + kThreads - 1) / kThreads, g.H);
+    k_ccl_labels<<<grid, kThreads, 0, s>>>(g, b, w.glab, labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint8_t *out) {
+    if (g.nwords == 0) return hipSuccess;
+    dim3 grid((g.W + kThreads - 1) / kThreads, g.H);
+    k_unpack<<<grid, kThreads, 0, s>>>(g, mask, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v) {
+    k_fill_i64<<<(n + 255) / 256, 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace vlg
+
+// ------------------------------------------------------------------ percentile
+// Radix select: keys are the float32 bit patterns made order-preserving
+// (negatives complemented, positives with the sign bit set) or the uint8
+// values.  Each pass histograms one digit of the keys that agree with the
+// digits chosen so far, then a single workgroup finds the bucket holding rank
+// k.  float32 uses digits of 11, 11 and 10 bits; uint8 one digit of 8 bits.
+namespace vlg {
+namespace {
+
+struct PctState {
+    uint32_t prefix, mask, k, pad;
+    uint32_t hist[2048];
+};
+
+__device__ __forceinline__ uint32_t f32_key(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_f32(uint32_t k) {
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__global__ void k_pct_init(PctState *st, uint32_t k) {
+    for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->hist[i] = 0;
+    if (threadIdx.x == 0) {
+        st->prefix = 0;
+        st->mask = 0;
+        st->k = k;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restrict__ img, int64_t pitch,
+                                                       PctState *st, int shift, int bins) {
+    __shared__ uint32_t h[2048];
+    for (int i = threadIdx.x; i < bins; i += kThreads) h[i] = 0;
+    __syncthreads();
+    const uint32_t prefix = st->prefix, mask = st->mask;
+    // the channel is stored with pitch wpr*64: element i is in row i / pitch
+    const int64_t n = (int64_t)g.H * pitch;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const uint32_t row = fdiv((uint32_t)(i >> 6), g.wpr_mul, g.wpr_shift);
+        if (i - (int64_t)row * pitch >= g.W) continue;
+        const T v = img[i];
+        const uint32_t key = sizeof(T) == 1 ? (uint32_t)v : f32_key((float)v);
+        if ((key & mask) == prefix) atomicAdd(&h[(key >> shift) & (uint32_t)(bins - 1)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += kThreads)
+        if (h[i]) atomicAdd(&st->hist[i], h[i]);
+}
+
+// one workgroup of 256 threads: find the bucket holding rank k
+__global__ __launch_bounds__(kThreads) void k_pct_select(PctState *st, int shift, int bins, int last,
+                                                         int is_u8, float *result) {
+    __shared__ uint32_t part[kThreads];
+    const int per = bins / kThreads;
+    uint32_t local = 0;
+    for (int j = 0; j < per; j++) local += st->hist[threadIdx.x * per + j];
+    part[threadIdx.x] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0, k = st->k;
+        int t = 0;
+        while (t < kThreads - 1 && acc + part[t] <= k) acc += part[t++];
+        int b = t * per;
+        while (b < t * per + per - 1 && acc + st->hist[b] <= k) acc += st->hist[b++];
+        st->k = k - acc;
+        st->prefix |= (uint32_t)b << shift;
+        st->mask |= (uint32_t)(bins - 1) << shift;
+        if (last) *result = is_u8 ? (float)st->prefix : key_f32(st->prefix);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2048; i += kThreads) st->hist[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, int64_t pitch,
+                             uint32_t k, void *state, float *result) {
+    PctState *st = (PctState *)state;
+    k_pct_init<<<1, kThreads, 0, s>>>(st, k);
+    const int64_t n = (int64_t)g.H * pitch;
+    if (n == 0) return hipGetLastError();
+    const int grid = grid_for(n, kThreads * 16, 2048);
+    if (dtype == 1) {
+        k_pct_hist<uint8_t><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, pitch, st, 0, 256);
+        k_pct_select<<<1, kThreads, 0, s>>>(st, 0, 256, 1, 1, result);
+        return hipGetLastError();
+    }
+    const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
+    for (int p = 0; p < 3; p++) {
+        k_pct_hist<float><<<grid, kThreads, 0, s>>>(g, (const float *)chan, pitch, st, shifts[p], bins[p]);
+        k_pct_select<<<1, kThreads, 0, s>>>(st, shifts[p], bins[p], p == 2, 0, result);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vlg

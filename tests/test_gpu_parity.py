@@ -1,0 +1,163 @@
+"""GPU path (through the C ABI) against the CPU oracle, bit for bit.
+
+Covers every operator, the three executor modes, ragged sizes around the
+64-bit word and the 128x32-pixel labelling tile, the paper-shaped grow
+specification, the maze worst case for labelling, and the full-size
+4096x4096 ellipse/maze workload."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import formulas, images
+from tests import golden_io
+from tests.gpu_util import assert_same, gpu_run
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["perop", "fused", "graph"]
+
+OPS_FORMULA = """
+let A = intensity(img, 0) >. {t0}
+let B = intensity(img, 1) <=. {t1}
+let C = intensity(img, 0) >=. {t2}
+let D = intensity(img, 1) <. {t3}
+output "not" !A
+output "and" A & B
+output "or" A | !B
+output "near" near(A)
+output "near_not" near(!B)
+output "interior" interior(A | C)
+output "reach" reach(A & !C, B | C)
+output "reach_not" reach(!B, !A)
+output "surrounded" surrounded(A | B, C)
+output "grow" grow(A, !B)
+output "const" true & near(false) | !true
+output "chain" near(interior(reach(D, A) | grow(C, B))) & !surrounded(B, D)
+"""
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2010_07284_amd as vlg
+    return vlg.create()
+
+
+def ops_src(rng):
+    t = rng.uniform(0.25, 0.75, 4)
+    return OPS_FORMULA.format(t0=t[0], t1=t[1], t2=t[2], t3=t[3])
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 70), (70, 1), (2, 64), (3, 65), (33, 63), (64, 127),
+                                 (65, 129), (31, 200), (97, 301)])
+def test_operators_ragged(ctx, mode, h, w):
+    rng = np.random.default_rng(h * 1000 + w)
+    img = rng.random((2, h, w)).astype(np.float32)
+    src = ops_src(rng)
+    assert_same(src, img, gpu_run(ctx, src, img, mode), tag=f"{h}x{w} {mode}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_operators_tiles(ctx, mode):
+    # several labelling tiles in both directions with ragged edges
+    rng = np.random.default_rng(7)
+    img = images.smoothed_noise(rng, 517, 389, sigma=2.0)[None]
+    img = np.concatenate([img, rng.random((1, 517, 389)).astype(np.float32)])
+    src = ops_src(rng)
+    assert_same(src, img, gpu_run(ctx, src, img, mode), tag=mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_plain_workload(ctx, mode):
+    img = images.plain_image(1, 256)
+    src = formulas.PLAIN_FORMULA
+    assert_same(src, img, gpu_run(ctx, src, img, mode), tag=mode)
+
+
+@pytest.mark.parametrize("fmt,host", [("u8", False), ("u8", True), ("packed", True)])
+def test_output_formats(ctx, fmt, host):
+    img = images.plain_image(5, 130)
+    src = formulas.PLAIN_FORMULA
+    assert_same(src, img, gpu_run(ctx, src, img, "graph", fmt=fmt, host=host))
+
+
+@pytest.mark.parametrize("path", golden_io.all_fixtures(), ids=lambda p: p.split("/")[-1])
+def test_golden_fixtures(ctx, path):
+    fx = golden_io.load(path)
+    B = fx["blocks"]
+    if fx["op"] == "ccl":
+        pytest.skip("labels are covered by test_ccl_labels")
+    if fx["op"] == "formula":
+        src, img = "\n".join(B["formula"]), golden_io.image(fx)
+    else:
+        a = golden_io.mask(B["a"]).astype(np.float32)
+        b = golden_io.mask(B["b"]).astype(np.float32) if "b" in B else np.zeros_like(a)
+        img = np.stack([a, b])
+        arg = "A, B" if "b" in B else "A"
+        src = ("let A = intensity(img, 0) >. 0.5\nlet B = intensity(img, 1) >. 0.5\n"
+               f'output "r" {fx["op"]}({arg})')
+    for mode in MODES:
+        got = gpu_run(ctx, src, img, mode)
+        assert np.array_equal(got[0], golden_io.mask(B["expect"])), mode
+
+
+def test_grow_specification_shape(ctx):
+    # the paper's specification (Fig. specification) on a synthetic
+    # uint16-range image: thresholds 62258 and 56360, then grow
+    rng = np.random.default_rng(3)
+    base = images.smoothed_noise(rng, 384, 512, sigma=6.0) * 65535.0
+    img = base.astype(np.float32)[None]
+    src = formulas.GROW_SPEC.format(hi=62258, lo=56360)
+    for mode in MODES:
+        assert_same(src, img, gpu_run(ctx, src, img, mode), tag=mode)
+
+
+def test_uint8_images(ctx):
+    img = images.random_mask_image(3, 300)
+    src = formulas.chain_dag(3, n_chain=300, n_reach=15)
+    want = oracle.run(src, img)
+    for mode in MODES:
+        assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=mode)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.3, 0.5, 0.86, 0.95, 1.0])
+def test_percentile_atoms(ctx, q):
+    rng = np.random.default_rng(int(q * 100))
+    img = rng.random((2, 77, 130)).astype(np.float32) - 0.25
+    img[1, :10] = 0.5  # ties
+    img[0, 5, :7] = -0.0
+    src = (f'output "a" intensity(img, 0) >. percentile(img, 0, {q})\n'
+           f'output "b" intensity(img, 1) <=. percentile(img, 1, {q})\n'
+           f'output "c" intensity(img, 1) >=. percentile(img, 0, {q})')
+    assert_same(src, img, gpu_run(ctx, src, img, "graph"))
+    u8 = rng.integers(0, 256, (1, 50, 90), dtype=np.uint8)
+    src8 = f'output "a" intensity(img) >. percentile(img, 0, {q})'
+    assert_same(src8, u8, gpu_run(ctx, src8, u8, "fused"))
+
+
+def test_segmentation_formula_small(ctx):
+    rng = np.random.default_rng(4)
+    img = images.phantom_image(rng, 190, 257)
+    src = formulas.segmentation_dag(4)
+    want = oracle.run(src, img)
+    for mode in MODES:
+        assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=mode)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_formulas(ctx, seed):
+    rng = np.random.default_rng(100 + seed)
+    h, w = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+    img = rng.random((2, h, w)).astype(np.float32)
+    src = formulas.random_dag(seed, n_nodes=60, n_reach=6, channels=2)
+    want = oracle.run(src, img)
+    for mode in MODES:
+        assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"{h}x{w} {mode}")
+
+
+def test_ellipse_maze_full_size(ctx):
+    img = images.ellipse_maze_image(2, 4096)
+    src = formulas.ellipse_dag(2)
+    want = oracle.run(src, img)
+    assert_same(src, img, gpu_run(ctx, src, img, "graph"), want, tag="graph")
+    assert_same(src, img, gpu_run(ctx, src, img, "perop"), want, tag="perop")
