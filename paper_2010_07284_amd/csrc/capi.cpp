@@ -571,18 +571,19 @@ int vlg_ccl_labels(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, 
     const Geo g = make_geo(height, width);
     if (g.nwords == 0) return VLG_OK;
     const size_t nb = (size_t)g.BH * g.BW;
-    int rc = ensure_ws(c, align256(nb * 4) + align256(nb) + 256);
+    int rc = ensure_ws(c, 2 * align256(nb * 4) + align256(nb) + 256);
     if (rc != VLG_OK) return rc;
     CclWork w;
     w.glab = (int32_t *)c->ws;
     w.gflag = (uint8_t *)c->ws + align256(nb * 4);
+    int32_t *canon = (int32_t *)((char *)c->ws + align256(nb * 4) + align256(nb));
     w.counters = c->counters;
     MRef b{mask_dev, 0ull}, none{nullptr, 0ull};
     HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
     HIP_TRY(launch_ccl_local(c->stream, g, b, none, none, w));
     HIP_TRY(launch_ccl_merge(c->stream, g, b, w));
     HIP_TRY(launch_ccl_flag(c->stream, g, w));
-    HIP_TRY(launch_ccl_labels(c->stream, g, b, w, labels_dev));
+    HIP_TRY(launch_ccl_labels(c->stream, g, b, w, canon, labels_dev));
     return VLG_OK;
 }
 

@@ -54,7 +54,9 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
 hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w);
 hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w,
                              uint64_t *out);
-hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *labels);
+// canon: [BH*BW] int32 scratch
+hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *canon,
+                             int32_t *labels);
 hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint8_t *out);
 hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v);
 

@@ -144,8 +144,10 @@ __global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__
 // four bits: 1 = top-left, 2 = top-right, 4 = bottom-left, 8 = bottom-right.
 // Any two foreground pixels of one block are 8-adjacent, so a block is a
 // union-find node.  Block ids are row-major, id = by*BW + bx; the root of a
-// set is its smallest id, whose block holds the component's first pixel in
-// raster order.
+// set is its smallest id.  (That block need not hold the component's first
+// pixel in raster order: a block with only bottom-row pixels precedes a later
+// block of the same block row whose top-row pixel comes first.  Canonical
+// pixel labels therefore take a minimum over each component.)
 //
 // 8-adjacency between a block and its earlier neighbours:
 //   left:       (tl|bl) of the block and (tr|br) of the left block
@@ -432,8 +434,29 @@ __global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, 
     }
 }
 
+// Smallest row-major pixel index of each component, gathered at its root.
+__global__ __launch_bounds__(kThreads) void k_ccl_canon(Geo g, MRef b, const int32_t *__restrict__ glab,
+                                                        int32_t *canon) {
+    const int64_t nb = (int64_t)g.BH * g.BW;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nb; i += stride) {
+        const int by = (int)(i / g.BW), bx = (int)(i - (int64_t)by * g.BW);
+        const uint32_t bits = block_bits_g(g, b, by, bx);
+        if (!bits) continue;
+        const int k = __builtin_ctz(bits);  // top-left, top-right, bottom-left, bottom-right
+        const int p = (2 * by + (k >> 1)) * g.W + 2 * bx + (k & 1);
+        atomicMin(&canon[glab[glab[i]]], p);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
 // Canonical labels: smallest row-major pixel index of each component.
 __global__ __launch_bounds__(kThreads) void k_ccl_labels(Geo g, MRef b, const int32_t *__restrict__ glab,
+                                                         const int32_t *__restrict__ canon,
                                                          int32_t *__restrict__ labels) {
     const int x = blockIdx.x * kThreads + threadIdx.x, yy = blockIdx.y;
     if (x >= g.W) return;
@@ -443,11 +466,7 @@ __global__ __launch_bounds__(kThreads) void k_ccl_labels(Geo g, MRef b, const in
     int32_t lab = -1;
     if ((word >> (x & 63)) & 1) {
         const int lr = glab[(int64_t)(yy >> 1) * g.BW + (x >> 1)];
-        const int r = glab[lr];
-        const int rby = r / g.BW, rbx = r % g.BW;
-        const uint32_t bits = block_bits_g(g, b, rby, rbx);
-        const int k = __builtin_ctz(bits);
-        lab = (2 * rby + (k >> 1)) * g.W + 2 * rbx + (k & 1);
+        lab = canon[glab[lr]];
     }
     labels[(int64_t)yy * g.W + x] = lab;
 }
@@ -552,10 +571,14 @@ hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z
     return hipGetLastError();
 }
 
-hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *labels) {
+hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *canon,
+                             int32_t *labels) {
     if (g.nwords == 0) return hipSuccess;
+    const int64_t nb = (int64_t)g.BH * g.BW;
+    k_fill_i32<<<grid_for(nb, kThreads, 8192), kThreads, 0, s>>>(canon, nb, 0x7fffffff);
+    k_ccl_canon<<<grid_for(nb, kThreads, 8192), kThreads, 0, s>>>(g, b, w.glab, canon);
     dim3 grid((g.W + kThreads - 1) / kThreads, g.H);
-    k_ccl_labels<<<grid, kThreads, 0, s>>>(g, b, w.glab, labels);
+    k_ccl_labels<<<grid, kThreads, 0, s>>>(g, b, w.glab, canon, labels);
     return hipGetLastError();
 }
 
