@@ -52,7 +52,7 @@ struct Ref {
 
 enum class SK : uint8_t {
     Pct,        // percentile of channel `chan` at q -> pct scalar `pct_out`
-    Atoms,      // up to kMaxAtoms thresholds of channel `chan` -> masks
+    Atoms,      // up to kMaxAtoms thresholds of channel `chan` -> masks (one read)
     Logic,      // out = ((x ^ x.inv) OP (y ^ y.inv)) ^ inv_out ; OP = and/or
     Near,       // out = (N(x ^ x.inv) ^ inv_out) & (z ^ z.inv)
     CclLocal,   // tile-local union-find of b = x; seeds = N(y & z) & b
@@ -61,7 +61,7 @@ enum class SK : uint8_t {
     CclGather,  // out = (y & z) | (pixels of b = x whose component has a seed)
 };
 
-constexpr int kMaxAtoms = 8;
+constexpr int kMaxAtoms = 32;
 
 struct AtomEntry {
     uint8_t cmp = CMP_GT;

@@ -38,12 +38,14 @@ struct CclWork {
     unsigned long long *counters; // [2] merge unions, merge retries (may be null)
 };
 
+constexpr int kMaxAtomsPerLaunch = 32;
+
 struct AtomLaunch {
     int n;
-    uint8_t cmp[8];
-    float thr[8];
-    const float *thr_dev[8];  // device scalar (percentile) or null
-    uint64_t *out[8];
+    uint8_t cmp[kMaxAtomsPerLaunch];
+    float thr[kMaxAtomsPerLaunch];
+    const float *thr_dev[kMaxAtomsPerLaunch];  // device scalar (percentile) or null
+    uint64_t *out[kMaxAtomsPerLaunch];
 };
 
 hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out);

@@ -81,60 +81,77 @@ __global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_o
 }
 
 // ------------------------------------------------------------------ atoms
-// The image is stored with a row pitch of wpr*64 elements, so pixel word i of
-// a mask covers elements [64 i, 64 i + 64) of the channel.  A wave takes 64
-// consecutive words: lane l reads element 64 k + l (256 coalesced bytes per
-// load for float32), the wave-wide compare result is the packed word k, and
-// lane k keeps it; one coalesced 512-byte store per output at the end.
-__device__ __forceinline__ bool cmp_pix(float f, float t, int c) {
-    const bool gt = f > t, lt = f < t, eq = f == t;
-    return c == 0 ? gt : c == 1 ? lt : c == 2 ? (gt || eq) : (lt || eq);
-}
+// The image is stored with a row pitch of wpr*64 elements, so mask word i
+// covers elements [64 i, 64 i + 64) of a channel.  A wave takes 64
+// consecutive words: lane l loads element 64 k + l for k = 0..63 (coalesced,
+// all loads issued before any compare), then for each atom the wave-wide
+// compare of pixel row k is the packed word k and is written into lane k's
+// register (v_writelane).  One coalesced 512-byte store per atom.  The
+// channel is read once for up to kMaxAtomsPerLaunch atoms.
+// Four pixel rows per asm block: four compares write four SGPR pairs
+// (s[84:91], reserved by the clobber list), then eight v_writelane move them
+// into lanes k..k+3.  Each SGPR is read at least three VALU instructions
+// after it was written and VCC is not involved, so the block needs no
+// wait states of its own.
+#define VLG_ATOM4(OP)                                                                               \
+    asm(OP " s[84:85], %[a], %[t]\n\t" OP " s[86:87], %[b], %[t]\n\t" OP " s[88:89], %[c], %[t]\n\t" OP \
+           " s[90:91], %[d], %[t]\n\t"                                                                 \
+           "v_writelane_b32 %[lo], s84, %[k0]\n\tv_writelane_b32 %[hi], s85, %[k0]\n\t"                \
+           "v_writelane_b32 %[lo], s86, %[k1]\n\tv_writelane_b32 %[hi], s87, %[k1]\n\t"                \
+           "v_writelane_b32 %[lo], s88, %[k2]\n\tv_writelane_b32 %[hi], s89, %[k2]\n\t"                \
+           "v_writelane_b32 %[lo], s90, %[k3]\n\tv_writelane_b32 %[hi], s91, %[k3]"                    \
+        : [lo] "+v"(lo), [hi] "+v"(hi)                                                                \
+        : [a] "v"(v[k]), [b] "v"(v[k + 1]), [c] "v"(v[k + 2]), [d] "v"(v[k + 3]), [t] "v"(t),       \
+          [k0] "i"(k), [k1] "i"(k + 1), [k2] "i"(k + 2), [k3] "i"(k + 3)                             \
+        : "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91")
 
-template <typename T, int N>
+template <int CMP>
+__device__ __forceinline__ uint64_t atom_words(const float (&v)[64], float t) {
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < 64; k += 4) {
+        if (CMP == 0) VLG_ATOM4("v_cmp_gt_f32_e64");
+        else if (CMP == 1) VLG_ATOM4("v_cmp_lt_f32_e64");
+        else if (CMP == 2) VLG_ATOM4("v_cmp_ge_f32_e64");
+        else VLG_ATOM4("v_cmp_le_f32_e64");
+    }
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+#undef VLG_ATOM4
+
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__ img, AtomLaunch a) {
+    __shared__ float sthr[kMaxAtomsPerLaunch];
+    if (threadIdx.x < a.n)
+        sthr[threadIdx.x] = a.thr_dev[threadIdx.x] ? *a.thr_dev[threadIdx.x] : a.thr[threadIdx.x];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
-    float thr[N];
-    int cmp[N];
-#pragma unroll
-    for (int j = 0; j < N; j++) {
-        thr[j] = a.thr_dev[j] ? *a.thr_dev[j] : a.thr[j];
-        cmp[j] = a.cmp[j];
-    }
     const int64_t ntasks = (g.nwords + 63) / 64;
     for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves) {
         const int64_t w0 = t * 64;
         const int nw = (int)((g.nwords - w0) < 64 ? (g.nwords - w0) : 64);
-        uint64_t mine[N];
-#pragma unroll
-        for (int j = 0; j < N; j++) mine[j] = 0;
         const T *src = img + w0 * 64 + lane;
+        float v[64];
         if (nw == 64) {
-#pragma unroll 16
-            for (int k = 0; k < 64; k++) {
-                const float f = (float)src[k * 64];
 #pragma unroll
-                for (int j = 0; j < N; j++) {
-                    const uint64_t m = __ballot(cmp_pix(f, thr[j], cmp[j]));
-                    mine[j] = lane == k ? m : mine[j];
-                }
-            }
+            for (int k = 0; k < 64; k++) v[k] = (float)src[k * 64];
         } else {
-            for (int k = 0; k < nw; k++) {
-                const float f = (float)src[k * 64];
 #pragma unroll
-                for (int j = 0; j < N; j++) {
-                    const uint64_t m = __ballot(cmp_pix(f, thr[j], cmp[j]));
-                    mine[j] = lane == k ? m : mine[j];
-                }
-            }
+            for (int k = 0; k < 64; k++) v[k] = k < nw ? (float)src[k * 64] : 0.f;
         }
-        if (lane < nw) {
-            const int64_t wi = w0 + lane;
-            const uint64_t keep = is_last_col(g, wi) ? g.tail : ~0ull;
-#pragma unroll
-            for (int j = 0; j < N; j++) a.out[j][wi] = mine[j] & keep;
+        const int64_t wi = w0 + lane;
+        const uint64_t keep = (lane < nw && is_last_col(g, wi)) ? g.tail : ~0ull;
+        for (int j = 0; j < a.n; j++) {
+            const float th = sthr[j];
+            uint64_t w;
+            switch (a.cmp[j]) {
+            case 0: w = atom_words<0>(v, th); break;
+            case 1: w = atom_words<1>(v, th); break;
+            case 2: w = atom_words<2>(v, th); break;
+            default: w = atom_words<3>(v, th); break;
+            }
+            if (lane < nw) a.out[j][wi] = w & keep;
         }
     }
 }
@@ -186,23 +203,18 @@ __device__ void lds_unite(int *L, int a, int b) {
     }
 }
 
-// Global union-find for the cross-tile merge.  Loads and stores are
-// device-coherent atomics: the L2 of one XCD is not coherent with another's
-// within a kernel.
-__device__ __forceinline__ int g_ld(int *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void g_st(int *p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// Global union-find for the cross-tile merge.  Plain loads and stores may
+// see stale values (the L2 of one XCD is not coherent with another's within a
+// kernel); that costs retries, never correctness: every value ever stored in
+// L[x] is an ancestor of x (L[x] <= x), sets only grow, and a failed
+// atomicMin hands back the current parent, which is then united in turn.
 __device__ int g_find(int *L, int x) {
     while (true) {
-        const int p = g_ld(&L[x]);
+        const int p = L[x];
         if (p == x) return x;
-        const int gp = g_ld(&L[p]);
+        const int gp = L[p];
         if (gp == p) return p;
-        g_st(&L[x], gp);
+        L[x] = gp;  // path halving
         x = gp;
     }
 }
@@ -233,20 +245,35 @@ __device__ __forceinline__ uint32_t block_bits_g(const Geo &g, const MRef &b, in
     return (uint32_t)((t >> sh) & 3) | ((uint32_t)((u >> sh) & 3) << 2);
 }
 
-// Tile-local labelling of b (TBH x TBW blocks per workgroup), plus the seed
-// test: a block meets the seeds when one of its b-pixels lies in N(y & z).
-template <int TBH, int TWW>
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Tile-local labelling of b: TBH block rows x 64 block columns (32*TBH x 128
+// pixels) per workgroup of four waves.  A wave takes one block row at a time,
+// one lane per block: horizontally connected blocks form runs, found with a
+// ballot and labelled by their first block without any atomics.  Runs of
+// consecutive rows are then united once per touching pair (a block skips the
+// upper runs its connected left neighbour already touches).  Also computes
+// the seed test: a block meets the seeds when one of its b-pixels lies in
+// N(y & z).
+//
+// Output: glab[id] = global id of the block's tile-local root; gflag[id] bit0
+// = the local root's component meets the seeds, bit1 = the block is a local
+// root whose component touches the tile border (only those can be joined to
+// other tiles).
+template <int TBH>
 __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
                                                         int32_t *__restrict__ glab,
                                                         uint8_t *__restrict__ gflag) {
-    constexpr int TR = 2 * TBH, TBW = 32 * TWW, NB = TBH * TBW;
+    constexpr int TWW = 2, TR = 2 * TBH, TBW = 64, NB = TBH * TBW, NWAVES = kThreads / 64;
     __shared__ uint64_t sb[TR][TWW];
     __shared__ uint64_t sa[TR + 2][TWW + 2];
     __shared__ int L[NB];
     __shared__ uint8_t sbits[NB];
-    __shared__ uint8_t sseed[NB];
+    __shared__ uint8_t srun[NB];
+    __shared__ uint8_t sflag[NB];  // bit0 seed, bit1 touches the tile border
     const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const int r0 = ty * TR, wc0 = tx * TWW;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
 
     for (int i = threadIdx.x; i < TR * TWW; i += kThreads) {
         const int r = i / TWW, w = i % TWW, yy = r0 + r, ww = wc0 + w;
@@ -269,15 +296,20 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
     }
     __syncthreads();
 
-    for (int i = threadIdx.x; i < NB; i += kThreads) {
-        const int lby = i / TBW, lbx = i % TBW, w = lbx >> 5, sh = (lbx & 31) * 2;
+    // rows: block bits, runs, seeds
+    for (int lby = wave; lby < TBH; lby += NWAVES) {
+        const int i = lby * TBW + lane, w = lane >> 5, sh = (lane & 31) * 2;
         const uint32_t bits = (uint32_t)((sb[2 * lby][w] >> sh) & 3) |
                               ((uint32_t)((sb[2 * lby + 1][w] >> sh) & 3) << 2);
+        const uint32_t left = (uint32_t)__shfl_up((int)bits, 1);
+        const bool conn_l = lane > 0 && (bits & 5) && (left & 10);
+        const uint64_t starts = __ballot(bits != 0 && !conn_l);
+        const uint64_t upto = starts & (~0ull >> (63 - lane));
+        const int run = upto ? 63 - __builtin_clzll(upto) : lane;
         uint32_t seed = 0;
         if (bits) {
-            // seed pixels within the 4x4 window around the block: rows
-            // 2lby-1 .. 2lby+2, cols 2lbx-1 .. 2lbx+2 (halo coordinates +1 row,
-            // +64 columns)
+            // seed pixels in the 4x4 window around the block: rows 2lby-1 ..
+            // 2lby+2, cols 2lbx-1 .. 2lbx+2 (halo coordinates: +1 row, +64 cols)
             const int c = 64 * (w + 1) + sh - 1, q = c >> 6, s = c & 63;
             uint32_t win[4];
 #pragma unroll
@@ -292,29 +324,53 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
             seed = (bits & nmask) ? 1u : 0u;
         }
         sbits[i] = (uint8_t)bits;
-        sseed[i] = (uint8_t)seed;
-        L[i] = i;
+        srun[i] = (uint8_t)run;
+        sflag[i] = (uint8_t)seed;
+        L[i] = bits ? lby * TBW + run : i;
     }
     __syncthreads();
 
-    for (int i = threadIdx.x; i < NB; i += kThreads) {
+    // unite runs of row lby with the runs they touch in row lby-1
+    for (int lby = 1 + wave; lby < TBH; lby += NWAVES) {
+        const int i = lby * TBW + lane, up = i - TBW;
         const uint32_t bits = sbits[i];
-        if (!bits) continue;
-        const int lby = i / TBW, lbx = i % TBW;
-        if (lbx > 0 && (bits & 5) && (sbits[i - 1] & 10)) lds_unite(L, i, i - 1);
-        if (lby > 0) {
-            if ((bits & 3) && (sbits[i - TBW] & 12)) lds_unite(L, i, i - TBW);
-            if (lbx > 0 && (bits & 1) && (sbits[i - TBW - 1] & 8)) lds_unite(L, i, i - TBW - 1);
-            if (lbx < TBW - 1 && (bits & 2) && (sbits[i - TBW + 1] & 4)) lds_unite(L, i, i - TBW + 1);
+        int c0 = -1, c1 = -1, c2 = -1;
+        if (bits) {
+            if (lane > 0 && (bits & 1) && (sbits[up - 1] & 8)) c0 = srun[up - 1];
+            if ((bits & 3) && (sbits[up] & 12)) c1 = srun[up];
+            if (lane < 63 && (bits & 2) && (sbits[up + 1] & 4)) c2 = srun[up + 1];
+        }
+        if (c1 == c0) c1 = -1;
+        if (c2 == c0 || c2 == c1) c2 = -1;
+        const int l0 = __shfl_up(c0, 1), l1 = __shfl_up(c1, 1), l2 = __shfl_up(c2, 1);
+        const uint32_t left = lane > 0 ? sbits[i - 1] : 0u;
+        if (lane > 0 && (bits & 5) && (left & 10)) {
+            // the left block is in this run and already joins its upper runs
+            if (c0 >= 0 && (c0 == l0 || c0 == l1 || c0 == l2)) c0 = -1;
+            if (c1 >= 0 && (c1 == l0 || c1 == l1 || c1 == l2)) c1 = -1;
+            if (c2 >= 0 && (c2 == l0 || c2 == l1 || c2 == l2)) c2 = -1;
+        }
+        if (bits) {
+            const int me = lby * TBW + srun[i], ub = (lby - 1) * TBW;
+            if (c0 >= 0) lds_unite(L, me, ub + c0);
+            if (c1 >= 0) lds_unite(L, me, ub + c1);
+            if (c2 >= 0) lds_unite(L, me, ub + c2);
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < NB; i += kThreads)
         if (sbits[i]) L[i] = lds_find(L, i);
     __syncthreads();
-    // seed flag on the local root (only roots are written, all with 1)
+    // carry seed and border-contact flags to the local roots (only roots are
+    // written, each with the same bits)
     for (int i = threadIdx.x; i < NB; i += kThreads)
-        if (sbits[i] && sseed[i]) sseed[L[i]] = 1;
+        if (sbits[i] && (sflag[i] & 1)) sflag[L[i]] |= 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB; i += kThreads) {
+        if (!sbits[i]) continue;
+        const int lby = i / TBW, lbx = i % TBW;
+        if (lby == 0 || lby == TBH - 1 || lbx == 0 || lbx == TBW - 1) sflag[L[i]] |= 2;
+    }
     __syncthreads();
 
     for (int i = threadIdx.x; i < NB; i += kThreads) {
@@ -324,9 +380,8 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
         const int64_t id = (int64_t)by * g.BW + bx;
         if (sbits[i]) {
             const int r = L[i];
-            const int gr = (ty * TBH + r / TBW) * g.BW + tx * TBW + r % TBW;
-            glab[id] = gr;
-            gflag[id] = r == i ? (uint8_t)(2 | sseed[i]) : (uint8_t)0;
+            glab[id] = (ty * TBH + r / TBW) * g.BW + tx * TBW + r % TBW;
+            gflag[id] = r == i ? sflag[i] : (uint8_t)0;
         } else {
             glab[id] = (int32_t)id;
             gflag[id] = 0;
@@ -335,11 +390,14 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
 }
 
 // Cross-tile merge: blocks on a tile's top row, left column and right column
-// unite with their earlier neighbours in other tiles.
-template <int TBH, int TWW>
-__global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int ntiles,
-                                                        int32_t *glab, unsigned long long *counters) {
-    constexpr int TBW = 32 * TWW, PER = TBW + 2 * TBH;
+// unite with their earlier neighbours in other tiles.  A block skips a union
+// that its connected predecessor along the same border (left neighbour on the
+// top row, upper neighbour on a side column) already makes with the same
+// tile-local component.
+template <int TBH>
+__global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int ntiles, int32_t *glab,
+                                                        unsigned long long *counters) {
+    constexpr int TBW = 64, PER = TBW + 2 * TBH;
     const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     int unions = 0, tries = 0;
     if (t < (int64_t)ntiles * PER) {
@@ -354,25 +412,72 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, 
             lby = k - TBW - TBH; lbx = TBW - 1; kind = 2;
         }
         const int by = ty * TBH + lby, bx = tx * TBW + lbx;
-        if (by < g.BH && bx < g.BW) {
-            const uint32_t bits = block_bits_g(g, b, by, bx);
-            const int id = by * g.BW + bx;
-            if (bits) {
-                auto link = [&](int nby, int nbx) {
-                    unions++;
-                    tries += g_unite(glab, id, nby * g.BW + nbx);
-                };
-                if (kind == 0 && by > 0) {
-                    if ((bits & 3) && (block_bits_g(g, b, by - 1, bx) & 12)) link(by - 1, bx);
-                    if (bx > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) link(by - 1, bx - 1);
-                    if (bx + 1 < g.BW && (bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4))
-                        link(by - 1, bx + 1);
-                } else if (kind == 1 && bx > 0) {
-                    if ((bits & 5) && (block_bits_g(g, b, by, bx - 1) & 10)) link(by, bx - 1);
-                    if (lby > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) link(by - 1, bx - 1);
-                } else if (kind == 2 && lby > 0 && bx + 1 < g.BW) {
-                    if ((bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) link(by - 1, bx + 1);
+        const uint32_t bits = (by < g.BH && bx < g.BW) ? block_bits_g(g, b, by, bx) : 0u;
+        const int id = by * g.BW + bx;
+        auto link = [&](int nid) {
+            unions++;
+            tries += g_unite(glab, id, nid);
+        };
+        if (bits && kind == 0 && by > 0) {
+            // contacts in the row above (other tile): UL, U, UR
+            int c[3] = {-1, -1, -1};
+            if (bx > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[0] = id - g.BW - 1;
+            if ((bits & 3) && (block_bits_g(g, b, by - 1, bx) & 12)) c[1] = id - g.BW;
+            if (bx + 1 < g.BW && (bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) c[2] = id - g.BW + 1;
+            // predecessor on this border row: the left block, if connected
+            int p[3] = {-1, -1, -1};
+            if (lbx > 0) {
+                const uint32_t lb = block_bits_g(g, b, by, bx - 1);
+                if ((bits & 5) && (lb & 10)) {
+                    if (bx - 1 > 0 && (lb & 1) && (block_bits_g(g, b, by - 1, bx - 2) & 8)) p[0] = id - g.BW - 2;
+                    if ((lb & 3) && (block_bits_g(g, b, by - 1, bx - 1) & 12)) p[1] = id - g.BW - 1;
+                    if ((lb & 2) && (block_bits_g(g, b, by - 1, bx) & 4)) p[2] = id - g.BW;
                 }
+            }
+            int pl[3];
+#pragma unroll
+            for (int j = 0; j < 3; j++) pl[j] = p[j] >= 0 ? glab[p[j]] : -2;
+            int done[3] = {-3, -3, -3};
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                if (c[j] < 0) continue;
+                const int lc = glab[c[j]];
+                if (lc == pl[0] || lc == pl[1] || lc == pl[2] || lc == done[0] || lc == done[1]) continue;
+                done[j < 2 ? j : 1] = lc;
+                link(c[j]);
+            }
+        } else if (bits && kind == 1 && bx > 0) {
+            // contacts in the column to the left (other tile): L, and UL below the top row
+            int c[2] = {-1, -1};
+            if ((bits & 5) && (block_bits_g(g, b, by, bx - 1) & 10)) c[0] = id - 1;
+            if (lby > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[1] = id - g.BW - 1;
+            // predecessor on this border column: the upper block, if connected
+            int p[2] = {-1, -1};
+            if (lby > 0) {
+                const uint32_t ub = block_bits_g(g, b, by - 1, bx);
+                if ((bits & 3) && (ub & 12)) {
+                    if ((ub & 5) && (block_bits_g(g, b, by - 1, bx - 1) & 10)) p[0] = id - g.BW - 1;
+                    if (lby > 1 && (ub & 1) && (block_bits_g(g, b, by - 2, bx - 1) & 8)) p[1] = id - 2 * g.BW - 1;
+                }
+            }
+            const int pl0 = p[0] >= 0 ? glab[p[0]] : -2, pl1 = p[1] >= 0 ? glab[p[1]] : -2;
+            int first = -3;
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                if (c[j] < 0) continue;
+                const int lc = glab[c[j]];
+                if (lc == pl0 || lc == pl1 || lc == first) continue;
+                first = lc;
+                link(c[j]);
+            }
+        } else if (bits && kind == 2 && lby > 0 && bx + 1 < g.BW) {
+            // contact UR (tile to the right); redundant when the upper block is
+            // connected to this block and to that same block (its right neighbour)
+            if ((bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) {
+                const uint32_t ub = block_bits_g(g, b, by - 1, bx);
+                const uint32_t ur = block_bits_g(g, b, by - 1, bx + 1);
+                const bool covered = (bits & 3) && (ub & 12) && (ur & 5) && (ub & 10);
+                if (!covered) link(id - g.BW + 1);
             }
         }
     }
@@ -382,7 +487,8 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, 
     }
 }
 
-// Point every tile-local root at its final root and carry its seed flag there.
+// Point every border-touching tile-local root at its final root and carry its
+// seed flag there.  Other local roots are final roots already.
 __global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride) {
@@ -396,41 +502,56 @@ __global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t 
         }
         if (x != (int)i) {
             glab[i] = x;
-            if (f & 1) gflag[x] = 3;  // roots are local roots: bit1 already set
+            if (f & 1) gflag[x] = 3;
         }
     }
 }
 
-// out = (y & z) | Z, Z = the b-pixels whose component meets the seeds.  Every
-// foreground block points at a tile-local root, and every tile-local root at
-// its final root, so the root is two loads away.
+// out = (y & z) | Z, Z = the b-pixels whose component meets the seeds.  One
+// lane per block (64 blocks = 128 pixels = two words of two rows per wave);
+// every foreground block points at a local root and every local root at its
+// final root, so the root is two loads away.  The per-block results are
+// gathered with a ballot and spread to pixel pairs.
+__device__ __forceinline__ uint64_t spread_pairs(uint32_t m) {
+    // bit j of m -> bits 2j and 2j+1
+    uint64_t x = m;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x | (x << 1);
+}
+
 __global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, MRef z,
                                                          const int32_t *__restrict__ glab,
                                                          const uint8_t *__restrict__ gflag,
                                                          uint64_t *__restrict__ out) {
-    const int64_t n = (int64_t)g.BH * g.wpr;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
-        const int by = (int)(i / g.wpr), w = (int)(i % g.wpr);
-        const int y0 = 2 * by;
-        const bool two = y0 + 1 < g.H;
-        const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
-        const int64_t i0 = (int64_t)y0 * g.wpr + w, i1 = i0 + g.wpr;
-        const uint64_t t = ldm(b, i0) & keep;
-        const uint64_t u = two ? (ldm(b, i1) & keep) : 0ull;
-        uint64_t zm = 0;
-        const uint64_t any = t | u;
-        if (any) {
-            const int64_t rowbase = (int64_t)by * g.BW + 32 * w;
-            for (int j = 0; j < 32; j++) {
-                if (!((any >> (2 * j)) & 3)) continue;
-                const int lr = glab[rowbase + j];
-                const int r = glab[lr];
-                if (gflag[r] & 1) zm |= 3ull << (2 * j);
+    const int lane = lane_id();
+    const int nq = (g.wpr + 1) / 2;                 // 128-pixel chunks per row
+    const int64_t ntasks = (int64_t)g.BH * nq;      // (block row, chunk) pairs
+    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves) {
+        const int by = (int)(t / nq), q = (int)(t - (int64_t)by * nq);
+        const int bx = 64 * q + lane;
+        bool zf = false;
+        if (bx < g.BW) {
+            const uint32_t bits = block_bits_g(g, b, by, bx);
+            if (bits) {
+                const int64_t id = (int64_t)by * g.BW + bx;
+                zf = (gflag[glab[glab[id]]] & 1) != 0;
             }
         }
-        out[i0] = ((ldm(y, i0) & ldm(z, i0)) | (t & zm)) & keep;
-        if (two) out[i1] = ((ldm(y, i1) & ldm(z, i1)) | (u & zm)) & keep;
+        const uint64_t m = __ballot(zf);
+        if (lane < 4) {
+            const int yy = 2 * by + (lane >> 1), w = 2 * q + (lane & 1);
+            if (yy < g.H && w < g.wpr) {
+                const int64_t i = (int64_t)yy * g.wpr + w;
+                const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+                const uint64_t zm = spread_pairs((uint32_t)(m >> (32 * (lane & 1))));
+                out[i] = ((ldm(y, i) & ldm(z, i)) | (ldm(b, i) & zm)) & keep;
+            }
+        }
     }
 }
 
@@ -519,18 +640,9 @@ hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z,
 
 template <typename T>
 static hipError_t atoms_t(hipStream_t s, const Geo &g, const T *img, const AtomLaunch &a) {
+    if (a.n < 1 || a.n > kMaxAtomsPerLaunch) return hipErrorInvalidValue;
     const int grid = grid_for((g.nwords + 63) / 64, kThreads / 64, 8192);
-    switch (a.n) {
-    case 1: k_atoms<T, 1><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    case 2: k_atoms<T, 2><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    case 3: k_atoms<T, 3><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    case 4: k_atoms<T, 4><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    case 5: k_atoms<T, 5><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    case 6: k_atoms<T, 6><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    case 7: k_atoms<T, 7><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    case 8: k_atoms<T, 8><<<grid, kThreads, 0, s>>>(g, img, a); break;
-    default: return hipErrorInvalidValue;
-    }
+    k_atoms<T><<<grid, kThreads, 0, s>>>(g, img, a);
     return hipGetLastError();
 }
 
@@ -543,7 +655,7 @@ hipError_t launch_atoms(hipStream_t s, const Geo &g, const void *chan, int dtype
 hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w) {
     if (g.nwords == 0) return hipSuccess;
     const int ntx = ntiles_x(g), nty = ntiles_y(g);
-    k_ccl_local<kTileBH, kTileWW><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag);
+    k_ccl_local<kTileBH><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag);
     return hipGetLastError();
 }
 
@@ -551,7 +663,7 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
     if (g.nwords == 0) return hipSuccess;
     const int ntx = ntiles_x(g), nty = ntiles_y(g);
     const int64_t n = (int64_t)ntx * nty * (kTileBW + 2 * kTileBH);
-    k_ccl_merge<kTileBH, kTileWW><<<(int)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+    k_ccl_merge<kTileBH><<<(int)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
         g, b, ntx, ntx * nty, w.glab, w.counters);
     return hipGetLastError();
 }
@@ -566,8 +678,8 @@ hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w) {
 hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w,
                              uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    const int64_t n = (int64_t)g.BH * g.wpr;
-    k_ccl_gather<<<grid_for(n, kThreads, 8192), kThreads, 0, s>>>(g, b, y, z, w.glab, w.gflag, out);
+    const int64_t tasks = (int64_t)g.BH * ((g.wpr + 1) / 2);
+    k_ccl_gather<<<grid_for(tasks, kThreads / 64, 8192), kThreads, 0, s>>>(g, b, y, z, w.glab, w.gflag, out);
     return hipGetLastError();
 }
 

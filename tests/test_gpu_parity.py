@@ -161,3 +161,19 @@ def test_ellipse_maze_full_size(ctx):
     want = oracle.run(src, img)
     assert_same(src, img, gpu_run(ctx, src, img, "graph"), want, tag="graph")
     assert_same(src, img, gpu_run(ctx, src, img, "perop"), want, tag="perop")
+
+
+@pytest.mark.parametrize("h,w", [(1, 70), (3, 130), (65, 200), (2, 4097)])
+def test_many_atoms_one_channel(ctx, h, w):
+    # 40 thresholds of all four comparisons on one channel: two atom launches
+    # (32 + 8), every mask compared
+    rng = np.random.default_rng(h + w)
+    img = rng.random((1, h, w)).astype(np.float32)
+    img[0, 0, : min(w, 8)] = np.float32(0.5)  # ties with one threshold
+    ops = [">.", "<.", ">=.", "<=."]
+    lines = [f'output "a{i}" intensity(img) {ops[i % 4]} {0.5 if i == 7 else rng.uniform(0.02, 0.98):.6f}'
+             for i in range(40)]
+    src = "\n".join(lines)
+    want = oracle.run(src, img)
+    for mode in ("perop", "fused"):
+        assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"{h}x{w} {mode}")
