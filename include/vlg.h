@@ -84,6 +84,11 @@ typedef struct vlg_formula_stats {
     int64_t steps_perop;    /* kernel steps of the per-operator schedule */
     int64_t steps_fused;    /* kernel steps of the fused schedule */
     int64_t peak_masks;     /* peak live intermediate masks (fused schedule) */
+    int64_t launches_fused; /* kernel launches of the fused schedule (batched
+                               Boolean and near steps count once) */
+    int64_t labellings;     /* connected-component labellings (fused schedule) */
+    int64_t labelling_reuse;/* reach-type nodes served by an earlier labelling of
+                               the same passable mask */
 } vlg_formula_stats;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to

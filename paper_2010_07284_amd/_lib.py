@@ -26,7 +26,7 @@ class VlgError(RuntimeError):
 class FormulaStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("parsed_nodes", "nodes", "reach_nodes", "atoms", "outputs", "steps_perop", "steps_fused",
-                 "peak_masks")]
+                 "peak_masks", "launches_fused", "labellings", "labelling_reuse")]
 
 
 class KernelTime(ctypes.Structure):

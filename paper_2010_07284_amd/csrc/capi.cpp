@@ -172,6 +172,7 @@ const char *kind_name(SK k) {
     case SK::CclMerge: return "ccl_merge";
     case SK::CclFlag: return "ccl_flag";
     case SK::CclGather: return "ccl_gather";
+    case SK::CclReseed: return "ccl_reseed";
     }
     return "?";
 }
@@ -198,6 +199,7 @@ double algorithmic_bytes(const Step &s, const Geo &g, int dtype) {
     }
     case SK::CclFlag: return nb;                                      // flags read
     case SK::CclGather: return ins({s.x, s.y, s.z}) + nb * 4.0 + mb;  // labels read
+    case SK::CclReseed: return ins({s.x});                            // seed mask read
     }
     return 0.0;
 }
@@ -231,6 +233,37 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         const Step &s = P.steps[si];
         if (hook) hook(hook_ctx, si, true);
         hipError_t e = hipSuccess;
+        if (s.group >= 0) {
+            // a batched group: consecutive Logic (or Near) steps, one launch
+            size_t sj = si;
+            while (sj + 1 < P.steps.size() && P.steps[sj + 1].group == s.group) sj++;
+            if (s.kind == SK::Logic) {
+                LogicBatch b;
+                b.n = (int)(sj - si + 1);
+                for (size_t k = si; k <= sj; k++) {
+                    const Step &t = P.steps[k];
+                    b.ops[k - si] = LogicOp{mref(t.x), mref(t.y), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out), t.op};
+                }
+                e = launch_logic_batch(c->stream, g, b);
+            } else {
+                NearBatch b;
+                b.n = (int)(sj - si + 1);
+                for (size_t k = si; k <= sj; k++) {
+                    const Step &t = P.steps[k];
+                    b.ops[k - si] = NearOp{mref(t.x), mref(t.z), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out)};
+                }
+                e = launch_near_batch(c->stream, g, b);
+            }
+            if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+            for (size_t k = si; k < sj; k++) {
+                // the group is timed as a whole: attribute it to its last step
+                if (hook) hook(hook_ctx, k, false);
+                if (hook) hook(hook_ctx, k + 1, true);
+            }
+            if (hook) hook(hook_ctx, sj, false);
+            si = sj;
+            continue;
+        }
         switch (s.kind) {
         case SK::Pct:
             e = launch_percentile(c->stream, g, img->chan(s.chan), img->dtype, img->pitch, pct_rank(s.q, npix),
@@ -265,7 +298,10 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
             e = launch_ccl_flag(c->stream, g, w);
             break;
         case SK::CclGather:
-            e = launch_ccl_gather(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w, slot_ptr(s.out));
+            e = launch_ccl_gather(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w, s.user, slot_ptr(s.out));
+            break;
+        case SK::CclReseed:
+            e = launch_ccl_reseed(c->stream, g, mref(s.x), w, s.user);
             break;
         }
         if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -507,6 +543,14 @@ int vlg_formula_info(const vlg_formula *cf, vlg_formula_stats *st) {
     st->steps_perop = (int64_t)pp.steps.size();
     st->steps_fused = (int64_t)pf.steps.size();
     st->peak_masks = pf.nslots;
+    int64_t launches = 0;
+    for (size_t i = 0; i < pf.steps.size(); i++) {
+        if (pf.steps[i].group >= 0 && i > 0 && pf.steps[i - 1].group == pf.steps[i].group) continue;
+        launches += pf.steps[i].kind == SK::Pct ? 7 : 1;
+    }
+    st->launches_fused = launches;
+    st->labellings = pf.ccl_count;
+    st->labelling_reuse = pf.ccl_reuse;
     return VLG_OK;
 }
 

@@ -546,7 +546,6 @@ struct Lower {
     std::vector<char> have;
     std::map<std::pair<int32_t, uint64_t>, int32_t> pct_memo;
     int32_t npct = 0;
-    int64_t ccl = 0;
 
     Lower(const Dag &d, Mode m) : dag(d), mode(m), val(d.nodes.size()), have(d.nodes.size(), 0) {}
 
@@ -605,7 +604,6 @@ struct Lower {
     }
     // G = seeds | (pixels of b whose component meets N(seeds)), seeds = y & z
     Ref reach_core(Ref b, Ref y, Ref z) {
-        ccl++;
         Step &l = emit(SK::CclLocal);
         l.x = b;
         l.y = y;
@@ -765,10 +763,157 @@ struct Lower {
     }
 };
 
-void for_each_ref(Step &s, void (*fn)(Ref &, void *), void *ctx) {
-    fn(s.x, ctx);
-    fn(s.y, ctx);
-    fn(s.z, ctx);
+
+
+// Reorder the fused schedule level by level: every ready Logic (resp. Near)
+// step joins one batched launch, and a reach labelling whose passable mask is
+// the one of the labelling emitted last is reused (reseed + gather) instead of
+// being recomputed.  Works on SSA ids, before slot allocation.
+constexpr int64_t kPctBase = int64_t(1) << 40;
+
+void schedule_fused(Lower &L) {
+    struct Unit {
+        int first = 0, count = 1;
+        bool ccl = false;
+        std::vector<int64_t> reads, writes;
+    };
+    auto refs_of = [](const Step &st, std::vector<int64_t> &rd, std::vector<int64_t> &wr) {
+        for (const Ref *r : {&st.x, &st.y, &st.z})
+            if (r->slot != kNone) rd.push_back(r->slot);
+        if (st.kind == SK::Atoms) {
+            for (int j = 0; j < st.natoms; j++) {
+                wr.push_back(st.atoms[j].out);
+                if (st.atoms[j].use_pct) rd.push_back(kPctBase + st.atoms[j].pct);
+            }
+        } else if (st.kind == SK::Pct) {
+            wr.push_back(kPctBase + st.pct_out);
+        } else if (st.out != kNone) {
+            wr.push_back(st.out);
+        }
+    };
+    std::vector<Unit> units;
+    for (size_t i = 0; i < L.steps.size();) {
+        Unit u;
+        u.first = (int)i;
+        if (L.steps[i].kind == SK::CclLocal) {
+            u.count = 4;
+            u.ccl = true;
+        }
+        for (int k = 0; k < u.count; k++) refs_of(L.steps[i + (size_t)k], u.reads, u.writes);
+        i += (size_t)u.count;
+        units.push_back(std::move(u));
+    }
+    const int n = (int)units.size();
+    std::unordered_map<int64_t, int> producer;
+    for (int u = 0; u < n; u++)
+        for (int64_t w : units[(size_t)u].writes) producer[w] = u;
+    std::vector<std::vector<int>> users((size_t)n);
+    std::vector<int> indeg((size_t)n, 0);
+    for (int u = 0; u < n; u++) {
+        std::vector<int> deps;
+        for (int64_t r : units[(size_t)u].reads) {
+            auto it = producer.find(r);
+            if (it != producer.end() && it->second != u) deps.push_back(it->second);
+        }
+        std::sort(deps.begin(), deps.end());
+        deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+        for (int d : deps) users[(size_t)d].push_back(u);
+        indeg[(size_t)u] = (int)deps.size();
+    }
+    std::vector<char> done((size_t)n, 0);
+    std::vector<Step> out;
+    int emitted = 0, group = 0;
+    bool have_last = false;
+    Ref last_b;
+    int last_users = 0;
+    auto finish = [&](int u) {
+        done[(size_t)u] = 1;
+        emitted++;
+        for (int v : users[(size_t)u]) indeg[(size_t)v]--;
+    };
+    auto ready = [&](auto pred) {
+        std::vector<int> r;
+        for (int u = 0; u < n; u++)
+            if (!done[(size_t)u] && indeg[(size_t)u] == 0 && pred(units[(size_t)u])) r.push_back(u);
+        return r;
+    };
+    auto kind_of = [&](const Unit &u) { return L.steps[(size_t)u.first].kind; };
+    auto same = [](const Ref &a, const Ref &b) { return a.slot == b.slot && a.inv == b.inv; };
+    while (emitted < n) {
+        int before = emitted;
+        for (int u : ready([&](const Unit &x) { return !x.ccl && (kind_of(x) == SK::Pct || kind_of(x) == SK::Atoms); })) {
+            out.push_back(L.steps[(size_t)units[(size_t)u].first]);
+            finish(u);
+        }
+        for (SK k : {SK::Logic, SK::Near}) {
+            std::vector<int> r = ready([&](const Unit &x) { return !x.ccl && kind_of(x) == k; });
+            for (size_t i = 0; i < r.size(); i++) {
+                if (i % kMaxBatch == 0) group++;
+                Step st = L.steps[(size_t)units[(size_t)r[i]].first];
+                st.group = r.size() > 1 ? group : -1;
+                out.push_back(st);
+            }
+            for (int u : r) finish(u);
+        }
+        std::vector<int> rc = ready([&](const Unit &x) { return x.ccl; });
+        if (!rc.empty()) {
+            int pick = rc[0];
+            if (have_last && last_users < kMaxCclUsers)
+                for (int u : rc)
+                    if (same(L.steps[(size_t)units[(size_t)u].first].x, last_b)) {
+                        pick = u;
+                        break;
+                    }
+            const Step loc = L.steps[(size_t)units[(size_t)pick].first];
+            Step gat = L.steps[(size_t)units[(size_t)pick].first + 3];
+            if (have_last && last_users < kMaxCclUsers && same(loc.x, last_b)) {
+                // reuse: seed mask N(y & z) & b, mark, gather
+                const Ref y = loc.y, z = loc.z;
+                const bool yone = y.slot == kNone && y.inv, zone = z.slot == kNone && z.inv;
+                Ref t = zone ? y : y;
+                if (!zone) {
+                    if (yone) {
+                        t = z;
+                    } else {
+                        Step lg;
+                        lg.kind = SK::Logic;
+                        lg.x = y;
+                        lg.y = z;
+                        lg.op = 0;
+                        lg.out = L.fresh();
+                        out.push_back(lg);
+                        t = Lower::R(lg.out);
+                    }
+                }
+                Step nr;
+                nr.kind = SK::Near;
+                nr.x = t;
+                nr.z = loc.x;
+                nr.out = L.fresh();
+                out.push_back(nr);
+                Step rs;
+                rs.kind = SK::CclReseed;
+                rs.x = Lower::R(nr.out);
+                rs.user = last_users;
+                out.push_back(rs);
+                gat.user = last_users;
+                out.push_back(gat);
+                last_users++;
+            } else {
+                for (int k = 0; k < 4; k++) {
+                    Step st = L.steps[(size_t)units[(size_t)pick].first + (size_t)k];
+                    st.user = 0;
+                    out.push_back(st);
+                }
+                have_last = true;
+                last_b = loc.x;
+                last_users = 1;
+            }
+            finish(pick);
+        }
+        if (emitted == before) break;  // cannot happen for a DAG
+    }
+    L.steps = std::move(out);
 }
 
 }  // namespace
@@ -809,7 +954,13 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
         }
     }
 
-    // liveness over SSA values, then greedy slot reuse
+    if (mode == Mode::Fused) {
+        schedule_fused(L);
+        ext_of.resize((size_t)L.nssa, kNone);
+    }
+
+    // liveness over SSA values, then greedy slot reuse; a batched group is
+    // allocated as one step so that no member writes a slot another reads
     const int32_t nv = L.nssa;
     std::vector<int64_t> last(nv, -1);
     for (size_t si = 0; si < L.steps.size(); si++) {
@@ -836,42 +987,54 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
         int32_t s = slot_of[(size_t)v];
         if (s >= 0) free_slots.push_back(s);
     };
-    for (size_t si = 0; si < L.steps.size(); si++) {
-        Step &s = L.steps[si];
+    for (size_t s0 = 0; s0 < L.steps.size();) {
+        size_t s1 = s0 + 1;
+        if (L.steps[s0].group >= 0)
+            while (s1 < L.steps.size() && L.steps[s1].group == L.steps[s0].group) s1++;
         std::vector<int32_t> outs;
-        if (s.kind == SK::Atoms) {
-            for (int j = 0; j < s.natoms; j++) outs.push_back(s.atoms[j].out);
-        } else if (s.out != kNone) {
-            outs.push_back(s.out);
+        for (size_t si = s0; si < s1; si++) {
+            Step &s = L.steps[si];
+            if (s.kind == SK::Atoms) {
+                for (int j = 0; j < s.natoms; j++) outs.push_back(s.atoms[j].out);
+            } else if (s.out != kNone) {
+                outs.push_back(s.out);
+            }
         }
         for (int32_t v : outs) alloc(v);
-        // rename operands and outputs to slots
         std::vector<int32_t> dying;
-        for (Ref *r : {&s.x, &s.y, &s.z}) {
-            if (r->slot == kNone) continue;
-            int32_t v = r->slot;
-            if (last[(size_t)v] == (int64_t)si &&
-                std::find(dying.begin(), dying.end(), v) == dying.end())
-                dying.push_back(v);
-            r->slot = slot_of[(size_t)v];
-        }
-        if (s.kind == SK::Atoms) {
-            for (int j = 0; j < s.natoms; j++) s.atoms[j].out = slot_of[(size_t)s.atoms[j].out];
-        } else if (s.out != kNone) {
-            s.out = slot_of[(size_t)s.out];
+        for (size_t si = s0; si < s1; si++) {
+            Step &s = L.steps[si];
+            for (Ref *r : {&s.x, &s.y, &s.z}) {
+                if (r->slot == kNone) continue;
+                int32_t v = r->slot;
+                if (last[(size_t)v] >= (int64_t)s0 && last[(size_t)v] < (int64_t)s1 &&
+                    std::find(dying.begin(), dying.end(), v) == dying.end())
+                    dying.push_back(v);
+                r->slot = slot_of[(size_t)v];
+            }
+            if (s.kind == SK::Atoms) {
+                for (int j = 0; j < s.natoms; j++) s.atoms[j].out = slot_of[(size_t)s.atoms[j].out];
+            } else if (s.out != kNone) {
+                s.out = slot_of[(size_t)s.out];
+            }
         }
         for (int32_t v : dying) release(v);
         for (int32_t v : outs)
             if (last[(size_t)v] < 0 && !is_ext(slot_of[(size_t)v])) release(v);
+        s0 = s1;
     }
-    (void)for_each_ref;
 
     Plan P;
     P.steps = std::move(L.steps);
     P.nslots = nslots;
     P.npct = L.npct;
     P.noutputs = (int32_t)which.size();
-    P.ccl_count = L.ccl;
+    P.ccl_count = 0;
+    P.ccl_reuse = 0;
+    for (const Step &st : P.steps) {
+        if (st.kind == SK::CclLocal) P.ccl_count++;
+        if (st.kind == SK::CclReseed) P.ccl_reuse++;
+    }
     P.output_ids.assign(which.begin(), which.end());
     return P;
 }

@@ -59,6 +59,8 @@ enum class SK : uint8_t {
     CclMerge,   // cross-tile merge of the labelling of b = x
     CclFlag,    // propagate seed flags to the final roots
     CclGather,  // out = (y & z) | (pixels of b = x whose component has a seed)
+    CclReseed,  // mark the components of the current labelling that meet the
+                // seed mask x (= N(seeds) & b) for labelling user `user`
 };
 
 constexpr int kMaxAtoms = 32;
@@ -82,7 +84,15 @@ struct Step {
     int32_t pct_out = -1;
     int natoms = 0;
     AtomEntry atoms[kMaxAtoms];
+    int32_t user = 0;     // CclGather / CclReseed: which seed set of the labelling
+    int32_t group = -1;   // consecutive Logic (or Near) steps of one group run
+                          // as one batched launch; they never read each other
 };
+
+// A labelling serves at most this many reach-type nodes with the same
+// passable mask (one seed bit each in the per-block flag byte).
+constexpr int kMaxCclUsers = 7;
+constexpr int kMaxBatch = 16;
 
 enum class Mode : uint8_t { PerOp = 0, Fused = 1 };
 
@@ -92,6 +102,7 @@ struct Plan {
     int32_t npct = 0;          // percentile scalars
     int32_t noutputs = 0;      // requested outputs (external slots 0..noutputs-1)
     int64_t ccl_count = 0;     // reachability labellings per evaluation
+    int64_t ccl_reuse = 0;     // reach-type nodes served by an earlier labelling
     std::vector<int32_t> output_ids;  // formula output index per external slot
 };
 

@@ -34,7 +34,8 @@ constexpr int kTileBW = 32 * kTileWW;  // block columns per tile
 
 struct CclWork {
     int32_t *glab;       // [BH*BW] parent pointers (block ids, row-major)
-    uint8_t *gflag;      // [BH*BW] bit1: tile-local root, bit0: meets the seeds
+    uint8_t *gflag;      // [BH*BW] local roots: bit0 touches the tile border,
+                         // bit 1+u meets the seeds of labelling user u
     unsigned long long *counters; // [2] merge unions, merge retries (may be null)
 };
 
@@ -55,7 +56,31 @@ hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z,
 hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &w);
 hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w);
 hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w,
-                             uint64_t *out);
+                             int user, uint64_t *out);
+hipError_t launch_ccl_reseed(hipStream_t s, const Geo &g, MRef sm, const CclWork &w, int user);
+
+constexpr int kBatchMax = 16;
+struct LogicOp {
+    MRef x, y;
+    uint64_t inv_out;
+    uint64_t *out;
+    int op;
+};
+struct LogicBatch {
+    int n;
+    LogicOp ops[kBatchMax];
+};
+struct NearOp {
+    MRef x, z;
+    uint64_t inv_out;
+    uint64_t *out;
+};
+struct NearBatch {
+    int n;
+    NearOp ops[kBatchMax];
+};
+hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b);
+hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b);
 // canon: [BH*BW] int32 scratch
 hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *canon,
                              int32_t *labels);

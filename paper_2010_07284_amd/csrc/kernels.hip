@@ -256,10 +256,10 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 // the seed test: a block meets the seeds when one of its b-pixels lies in
 // N(y & z).
 //
-// Output: glab[id] = global id of the block's tile-local root; gflag[id] bit0
-// = the local root's component meets the seeds, bit1 = the block is a local
-// root whose component touches the tile border (only those can be joined to
-// other tiles).
+// Output: glab[id] = global id of the block's tile-local root; gflag[id] of
+// a local root: bit0 = its component touches the tile border (only those can
+// be joined to other tiles), bit1 = it meets the seeds (seed set of labelling
+// user 0; bits 2..7 serve later users, see k_ccl_reseed).
 template <int TBH>
 __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
                                                         int32_t *__restrict__ glab,
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
     __shared__ int L[NB];
     __shared__ uint8_t sbits[NB];
     __shared__ uint8_t srun[NB];
-    __shared__ uint8_t sflag[NB];  // bit0 seed, bit1 touches the tile border
+    __shared__ uint8_t sflag[NB];  // bit0 touches the tile border, bit1 seed
     const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const int r0 = ty * TR, wc0 = tx * TWW;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
         }
         sbits[i] = (uint8_t)bits;
         srun[i] = (uint8_t)run;
-        sflag[i] = (uint8_t)seed;
+        sflag[i] = (uint8_t)(seed << 1);
         L[i] = bits ? lby * TBW + run : i;
     }
     __syncthreads();
@@ -358,18 +358,22 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
         }
     }
     __syncthreads();
+    // resolve each run start, then let the rest of the run copy its root
     for (int i = threadIdx.x; i < NB; i += kThreads)
-        if (sbits[i]) L[i] = lds_find(L, i);
+        if (sbits[i] && srun[i] == (i & (TBW - 1))) L[i] = lds_find(L, i);
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB; i += kThreads)
+        if (sbits[i] && srun[i] != (i & (TBW - 1))) L[i] = L[(i & ~(TBW - 1)) + srun[i]];
     __syncthreads();
     // carry seed and border-contact flags to the local roots (only roots are
     // written, each with the same bits)
     for (int i = threadIdx.x; i < NB; i += kThreads)
-        if (sbits[i] && (sflag[i] & 1)) sflag[L[i]] |= 1;
+        if (sbits[i] && (sflag[i] & 2)) sflag[L[i]] |= 2;
     __syncthreads();
     for (int i = threadIdx.x; i < NB; i += kThreads) {
         if (!sbits[i]) continue;
         const int lby = i / TBW, lbx = i % TBW;
-        if (lby == 0 || lby == TBH - 1 || lbx == 0 || lbx == TBW - 1) sflag[L[i]] |= 2;
+        if (lby == 0 || lby == TBH - 1 || lbx == 0 || lbx == TBW - 1) sflag[L[i]] |= 1;
     }
     __syncthreads();
 
@@ -488,12 +492,13 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, 
 }
 
 // Point every border-touching tile-local root at its final root and carry its
-// seed flag there.  Other local roots are final roots already.
+// seed flag there.  Other local roots are final roots already.  A walker
+// writes only its own entry, so concurrent walkers never undo each other.
 __global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride) {
         const uint8_t f = gflag[i];
-        if (!(f & 2)) continue;
+        if (!(f & 1)) continue;
         int x = (int)i;
         while (true) {
             const int p = glab[x];
@@ -502,56 +507,111 @@ __global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t 
         }
         if (x != (int)i) {
             glab[i] = x;
-            if (f & 1) gflag[x] = 3;
+            if (f & 2) gflag[x] = 3;  // final roots are border-touching local roots
         }
     }
 }
 
-// out = (y & z) | Z, Z = the b-pixels whose component meets the seeds.  One
-// lane per block (64 blocks = 128 pixels = two words of two rows per wave);
-// every foreground block points at a local root and every local root at its
-// final root, so the root is two loads away.  The per-block results are
-// gathered with a ballot and spread to pixel pairs.
-__device__ __forceinline__ uint64_t spread_pairs(uint32_t m) {
-    // bit j of m -> bits 2j and 2j+1
-    uint64_t x = m;
-    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
-    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
-    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
-    x = (x | (x << 2)) & 0x3333333333333333ull;
-    x = (x | (x << 1)) & 0x5555555555555555ull;
-    return x | (x << 1);
-}
-
+// out = (y & z) | Z, Z = the b-pixels whose component meets the seeds.  Every
+// foreground block points at a local root and every local root at its final
+// root, so the root is two loads away.
 __global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, MRef z,
                                                          const int32_t *__restrict__ glab,
-                                                         const uint8_t *__restrict__ gflag,
+                                                         const uint8_t *__restrict__ gflag, int user,
                                                          uint64_t *__restrict__ out) {
-    const int lane = lane_id();
-    const int nq = (g.wpr + 1) / 2;                 // 128-pixel chunks per row
-    const int64_t ntasks = (int64_t)g.BH * nq;      // (block row, chunk) pairs
+    // a wave takes 256 blocks of one block row (512 pixels = 8 words of two
+    // rows); lane l owns blocks 4l .. 4l+3, i.e. byte l of those 8 words
+    __shared__ uint64_t zw[kThreads / 64][8];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int nq = (g.wpr + 7) / 8;
+    const int64_t ntasks = (int64_t)g.BH * nq;
     const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves) {
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wv; t < ntasks; t += nwaves) {
         const int by = (int)(t / nq), q = (int)(t - (int64_t)by * nq);
-        const int bx = 64 * q + lane;
-        bool zf = false;
-        if (bx < g.BW) {
-            const uint32_t bits = block_bits_g(g, b, by, bx);
-            if (bits) {
-                const int64_t id = (int64_t)by * g.BW + bx;
-                zf = (gflag[glab[glab[id]]] & 1) != 0;
+        const int y0 = 2 * by;
+        const int w = 8 * q + (lane >> 3), sh = (lane & 7) * 8;  // word and bit offset of my byte
+        uint32_t top = 0, bot = 0;
+        if (w < g.wpr) {
+            const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+            top = (uint32_t)(((ldm(b, (int64_t)y0 * g.wpr + w) & keep) >> sh) & 0xFF);
+            if (y0 + 1 < g.H) bot = (uint32_t)(((ldm(b, (int64_t)(y0 + 1) * g.wpr + w) & keep) >> sh) & 0xFF);
+        }
+        const uint32_t any = top | bot;
+        uint32_t zbyte = 0;
+        if (any) {
+            const int bx0 = 256 * q + 4 * lane;
+            const int64_t id0 = (int64_t)by * g.BW + bx0;
+            int lr[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) lr[j] = ((any >> (2 * j)) & 3) ? glab[id0 + j] : -1;
+            int r[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) r[j] = lr[j] >= 0 ? glab[lr[j]] : -1;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (r[j] >= 0 && ((gflag[r[j]] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
+        }
+        ((uint8_t *)zw[wv])[lane] = (uint8_t)zbyte;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < 16) {
+            const int yy = y0 + (lane >> 3), ww = 8 * q + (lane & 7);
+            if (yy < g.H && ww < g.wpr) {
+                const int64_t i = (int64_t)yy * g.wpr + ww;
+                const uint64_t keep = ww == g.wpr - 1 ? g.tail : ~0ull;
+                out[i] = ((ldm(y, i) & ldm(z, i)) | (ldm(b, i) & zw[wv][lane & 7])) & keep;
             }
         }
-        const uint64_t m = __ballot(zf);
-        if (lane < 4) {
-            const int yy = 2 * by + (lane >> 1), w = 2 * q + (lane & 1);
-            if (yy < g.H && w < g.wpr) {
-                const int64_t i = (int64_t)yy * g.wpr + w;
-                const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
-                const uint64_t zm = spread_pairs((uint32_t)(m >> (32 * (lane & 1))));
-                out[i] = ((ldm(y, i) & ldm(z, i)) | (ldm(b, i) & zm)) & keep;
-            }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Mark, for labelling user `user`, the components of the current labelling
+// that meet the seed mask sm (= N(seeds) & b): bit 1+user of the root's flag
+// byte.  Runs after k_ccl_flag, so every block's root is two loads away.
+__global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const int32_t *__restrict__ glab,
+                                                         uint8_t *gflag, int user) {
+    const int bx = blockIdx.x * kThreads + threadIdx.x, by = blockIdx.y;
+    if (bx >= g.BW) return;
+    if (!block_bits_g(g, sm, by, bx)) return;
+    const int r = glab[glab[(int64_t)by * g.BW + bx]];
+    atomicOr((unsigned int *)(gflag + (r & ~3)), (1u << (1 + user)) << (8 * (r & 3)));
+}
+
+// Up to kMaxBatch independent Boolean steps (or near steps) in one launch:
+// blockIdx.y selects the step.
+__global__ __launch_bounds__(kThreads) void k_logic_batch(Geo g, LogicBatch bt) {
+    const LogicOp &o = bt.ops[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
+        const uint64_t a = ldm(o.x, i), b = ldm(o.y, i);
+        uint64_t r = (o.op ? (a | b) : (a & b)) ^ o.inv_out;
+        if (is_last_col(g, i)) r &= g.tail;
+        o.out[i] = r;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt) {
+    const NearOp &o = bt.ops[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
+        const uint32_t y = fdiv((uint32_t)i, g.wpr_mul, g.wpr_shift);
+        const int32_t w = (int32_t)((uint32_t)i - y * (uint32_t)g.wpr);
+        const bool last = w == g.wpr - 1;
+        uint64_t acc = 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++) {
+            const int yy = (int)y + dy;
+            if (yy < 0 || yy >= g.H) continue;
+            const int64_t base = (int64_t)yy * g.wpr + w;
+            uint64_t c = ldm(o.x, base);
+            if (last) c &= g.tail;
+            const uint64_t l = w > 0 ? ldm(o.x, base - 1) : 0ull;
+            const uint64_t r = last ? 0ull : ldm(o.x, base + 1);
+            acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
         }
+        uint64_t res = (acc ^ o.inv_out) & ldm(o.z, i);
+        if (last) res &= g.tail;
+        o.out[i] = res;
     }
 }
 
@@ -676,10 +736,32 @@ hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w) {
 }
 
 hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w,
-                             uint64_t *out) {
+                             int user, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    const int64_t tasks = (int64_t)g.BH * ((g.wpr + 1) / 2);
-    k_ccl_gather<<<grid_for(tasks, kThreads / 64, 8192), kThreads, 0, s>>>(g, b, y, z, w.glab, w.gflag, out);
+    const int64_t tasks = (int64_t)g.BH * ((g.wpr + 7) / 8);
+    k_ccl_gather<<<grid_for(tasks, kThreads / 64, 8192), kThreads, 0, s>>>(g, b, y, z, w.glab, w.gflag, user,
+                                                                            out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_reseed(hipStream_t s, const Geo &g, MRef sm, const CclWork &w, int user) {
+    if (g.nwords == 0) return hipSuccess;
+    dim3 grid((g.BW + kThreads - 1) / kThreads, g.BH);
+    k_ccl_reseed<<<grid, kThreads, 0, s>>>(g, sm, w.glab, w.gflag, user);
+    return hipGetLastError();
+}
+
+hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b) {
+    if (g.nwords == 0 || b.n == 0) return hipSuccess;
+    dim3 grid(grid_for(g.nwords, kThreads, 4096), b.n);
+    k_logic_batch<<<grid, kThreads, 0, s>>>(g, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b) {
+    if (g.nwords == 0 || b.n == 0) return hipSuccess;
+    dim3 grid(grid_for(g.nwords, kThreads, 4096), b.n);
+    k_near_batch<<<grid, kThreads, 0, s>>>(g, b);
     return hipGetLastError();
 }
 

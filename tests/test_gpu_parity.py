@@ -177,3 +177,24 @@ def test_many_atoms_one_channel(ctx, h, w):
     want = oracle.run(src, img)
     for mode in ("perop", "fused"):
         assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"{h}x{w} {mode}")
+
+
+def test_labelling_reuse(ctx):
+    # ten reach-type nodes over the same passable masks B and !B: the fused
+    # schedule labels B once per run of users (at most 7 seed sets each)
+    rng = np.random.default_rng(11)
+    img = rng.random((3, 301, 257)).astype(np.float32)
+    lines = ["let B = intensity(img, 0) >. 0.45", "let C = intensity(img, 1) >. 0.5"]
+    outs = []
+    for i in range(10):
+        t = 0.97 + 0.002 * i
+        lines.append(f"let S{i} = intensity(img, 2) >. {t:.4f}")
+        op = ["reach(S{i}, B)", "grow(S{i}, B)", "surrounded(S{i} | C, B)", "reach(S{i}, !B)"][i % 4]
+        outs.append(op.format(i=i))
+    src = "\n".join(lines) + "\n" + "\n".join(f'output "o{i}" {o}' for i, o in enumerate(outs))
+    import paper_2010_07284_amd as vlg
+    st = vlg.formula_info(vlg.compile_formula(None, src))
+    assert st["labelling_reuse"] >= 3
+    want = oracle.run(src, img)
+    for mode in MODES:
+        assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=mode)
