@@ -104,6 +104,10 @@ def main():
                                      f"{int((got != want[k]).sum())} pixels differ")
         log("[bench] parity: all outputs bit-exact in perop, fused and graph modes")
 
+    tune = vlg.autotune(ctx, f, im, iters=3)
+    tile_rows, tile_ms = tune["ccl_tile_rows"]
+    log(f"[bench] autotune: labelling tile rows {tile_rows} "
+        f"({', '.join(f'{k}: {v:.3f} ms' for k, v in sorted(tile_ms.items()))})")
     ms = {}
     for mode in ("perop", "fused", "graph"):
         ms[mode] = time_mode(vlg, lib, ctx, f, im, arr, mode, args.steps, args.warmup)
@@ -136,7 +140,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"ellipse_maze_{S}: {S}x{S} f32 x3 channels, {nodes}-node formula "
                                f"({n_ccl} reach-type), {nout} outputs",
-                   "image": [3, S, S], "nodes": nodes, "outputs": nout, "executor": "graph"},
+                   "image": [3, S, S], "nodes": nodes, "outputs": nout, "executor": "graph",
+                   "ccl_tile_rows": tile_rows, "labellings": info["labellings"],
+                   "launches": info["launches_fused"]},
         "perop_ms": round(ms["perop"], 4),
         "fused_ms": round(ms["fused"], 4),
         "speedup_graph_vs_perop": round(ms["perop"] / t, 3),

@@ -182,6 +182,37 @@ typedef struct vlg_kernel_time {
 int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_kernel_time *out,
                 int max_out, int *n_out);
 
+/* Tunables of the executor.  Each has a default, may be forced for a
+ * context, and is otherwise looked up per image shape class (ceil(log2 H),
+ * ceil(log2 W)) in the context's table, which vlg_autotune fills.
+ *   VLG_TUNE_CCL_TILE_ROWS: block rows (2x2 pixels each) per labelling tile:
+ *     8, 16 or 32; tiles are 128 pixels wide.  Taller tiles do more work in
+ *     LDS and leave fewer tile borders to merge globally. */
+#define VLG_TUNE_CCL_TILE_ROWS 0
+/* Force `value` for every image (value 0 returns to table/default). */
+int vlg_set_tunable(vlg_ctx *ctx, int which, int value);
+/* The value used for an image of height x width on this context. */
+int vlg_get_tunable(vlg_ctx *ctx, int which, int height, int width, int *value);
+
+typedef struct vlg_tune_report {
+    int which;          /* VLG_TUNE_* */
+    int best;           /* chosen value, stored for the image's shape class */
+    int n;              /* candidates tried */
+    int candidates[8];
+    double ms[8];       /* mean time of one evaluation of f on img per candidate */
+} vlg_tune_report;
+/* Autotuner: evaluate every output of f on img `iters` times per candidate
+ * value of each tunable (fused schedule, HIP events on the context's stream)
+ * and store the fastest value for img's shape class.  Writes one report per
+ * tunable to out[0 .. max_out-1]; *n_out receives the number of tunables. */
+int vlg_autotune(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_tune_report *out,
+                 int max_out, int *n_out);
+/* Save / load the context's tuning table as JSON lines
+ * {"arch": "gfx950", "tunable": ..., "h_class": ..., "w_class": ..., "value": ...};
+ * loading keeps only the entries of the context's device architecture. */
+int vlg_tune_save(vlg_ctx *ctx, const char *path);
+int vlg_tune_load(vlg_ctx *ctx, const char *path);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *vlg_last_error(void);
 

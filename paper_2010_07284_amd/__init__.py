@@ -186,6 +186,38 @@ def profile(ctx, f, img, iters=5):
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
 
 
+TUNABLES = {"ccl_tile_rows": 0}
+
+
+def set_tunable(ctx, name, value):
+    """vlg_set_tunable: force a tunable (0 = back to the tuning table)."""
+    _lib.call("vlg_set_tunable", ctx.handle, TUNABLES[name], int(value))
+
+
+def get_tunable(ctx, name, height, width):
+    v = ctypes.c_int()
+    _lib.call("vlg_get_tunable", ctx.handle, TUNABLES[name], height, width, ctypes.byref(v))
+    return v.value
+
+
+def autotune(ctx, f, img, iters=5):
+    """vlg_autotune: {tunable: (best, {candidate: ms})} for img's shape class."""
+    arr = (_lib.TuneReport * 4)()
+    n = ctypes.c_int()
+    _lib.call("vlg_autotune", ctx.handle, f.handle, img.handle, iters, arr, 4, ctypes.byref(n))
+    names = {v: k for k, v in TUNABLES.items()}
+    return {names[arr[i].which]: (arr[i].best, {arr[i].candidates[j]: arr[i].ms[j] for j in range(arr[i].n)})
+            for i in range(n.value)}
+
+
+def tune_save(ctx, path):
+    _lib.call("vlg_tune_save", ctx.handle, path.encode())
+
+
+def tune_load(ctx, path):
+    _lib.call("vlg_tune_load", ctx.handle, path.encode())
+
+
 def unpack(words, height, width):
     """Packed int64 words (torch or numpy, [H, ceil(W/64)]) -> numpy uint8 [H, W]."""
     import numpy as np
@@ -205,5 +237,6 @@ def pack(mask):
 
 
 __all__ = ["create", "sync", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
-           "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "unpack", "pack", "VlgError",
+           "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
+           "tune_load", "unpack", "pack", "VlgError",
            "LIB_PATH"]

@@ -10,7 +10,8 @@ EXPORTS = [
     "vlg_create", "vlg_destroy", "vlg_sync", "vlg_set_mode", "vlg_load_image", "vlg_image_free",
     "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name",
     "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels",
-    "vlg_ccl_read_counters", "vlg_profile", "vlg_last_error",
+    "vlg_ccl_read_counters", "vlg_profile", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune",
+    "vlg_tune_save", "vlg_tune_load", "vlg_last_error",
 ]
 
 ERRORS = {-1: "VLG_EINVAL", -2: "VLG_EPARSE", -3: "VLG_ESHAPE", -4: "VLG_ENOMEM", -5: "VLG_EHIP",
@@ -32,6 +33,11 @@ class FormulaStats(ctypes.Structure):
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("which", ctypes.c_int), ("best", ctypes.c_int), ("n", ctypes.c_int),
+                ("candidates", ctypes.c_int * 8), ("ms", ctypes.c_double * 8)]
 
 
 class CclCounters(ctypes.Structure):
@@ -71,6 +77,11 @@ def lib():
             "vlg_ccl_labels": ([P, P, I, I, P], I),
             "vlg_ccl_read_counters": ([P, P], I),
             "vlg_profile": ([P, P, P, I, P, I, P], I),
+            "vlg_set_tunable": ([P, I, I], I),
+            "vlg_get_tunable": ([P, I, I, I, P], I),
+            "vlg_autotune": ([P, P, P, I, P, I, P], I),
+            "vlg_tune_save": ([P, ctypes.c_char_p], I),
+            "vlg_tune_load": ([P, ctypes.c_char_p], I),
             "vlg_last_error": ([], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():

@@ -88,8 +88,15 @@ struct GraphKey {
     bool operator<(const GraphKey &o) const { return v < o.v; }
 };
 
+struct Tuning {
+    int ccl_tbh = kTileBHDefault;
+};
+
 struct vlg_ctx {
     int device = 0;
+    std::string arch;
+    int forced_tbh = 0;                             // 0: not forced
+    std::map<std::pair<int, int>, Tuning> tuned;    // shape class -> tuning
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int mode = VLG_MODE_GRAPH;
@@ -154,6 +161,20 @@ int ensure_ws(vlg_ctx *c, size_t need) {
     return VLG_OK;
 }
 
+int log2_class(int n) {
+    int c = 0;
+    while ((1ll << c) < (long long)n) c++;
+    return c;
+}
+
+Tuning tuning_for(const vlg_ctx *c, int H, int W) {
+    Tuning t;
+    auto it = c->tuned.find({log2_class(H), log2_class(W)});
+    if (it != c->tuned.end()) t = it->second;
+    if (c->forced_tbh) t.ccl_tbh = c->forced_tbh;
+    return t;
+}
+
 uint32_t pct_rank(double q, int64_t n) {
     // k = clamp(ceil(q * n) - 1, 0, n - 1)
     double kk = std::ceil(q * (double)n) - 1.0;
@@ -179,7 +200,7 @@ const char *kind_name(SK k) {
 
 // Bytes a step must move at the least: its image channel or input masks
 // read once, its outputs written once (and the labelling arrays it owns).
-double algorithmic_bytes(const Step &s, const Geo &g, int dtype) {
+double algorithmic_bytes(const Step &s, const Geo &g, int dtype, int tbh) {
     const double mb = (double)g.nwords * 8.0, npix = (double)g.H * g.W;
     const double nb = (double)g.BH * g.BW;
     auto ins = [&](std::initializer_list<Ref> rs) {
@@ -194,8 +215,8 @@ double algorithmic_bytes(const Step &s, const Geo &g, int dtype) {
     case SK::Near: return ins({s.x, s.z}) + mb;
     case SK::CclLocal: return ins({s.x, s.y, s.z}) + nb * 5.0;      // labels + flags written
     case SK::CclMerge: {
-        const double ntiles = std::ceil(g.BH / (double)kTileBH) * std::ceil(g.BW / (double)kTileBW);
-        return ntiles * (kTileBW + 2 * kTileBH) * 16.0;               // border words read
+        const double ntiles = std::ceil(g.BH / (double)tbh) * std::ceil(g.BW / (double)kTileBW);
+        return ntiles * (kTileBW + 2 * tbh) * 16.0;                   // border words read
     }
     case SK::CclFlag: return nb;                                      // flags read
     case SK::CclGather: return ins({s.x, s.y, s.z}) + nb * 4.0 + mb;  // labels read
@@ -228,6 +249,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
     w.glab = (int32_t *)(base + L.off_glab);
     w.gflag = (uint8_t *)(base + L.off_gflag);
     w.counters = c->count_ccl ? c->counters : nullptr;
+    w.tbh = tuning_for(c, img->H, img->W).ccl_tbh;
     const int64_t npix = (int64_t)img->H * img->W;
     for (size_t si = 0; si < P.steps.size(); si++) {
         const Step &s = P.steps[si];
@@ -353,7 +375,8 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
     if (c->mode == VLG_MODE_GRAPH) {
         GraphKey key;
         key.v = {(uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)img->dev, (uintptr_t)img->H, (uintptr_t)img->W,
-                 (uintptr_t)img->dtype, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)c->ws};
+                 (uintptr_t)img->dtype, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)c->ws,
+                 (uintptr_t)tuning_for(c, img->H, img->W).ccl_tbh};
         for (size_t k = 0; k < which.size(); k++) key.v.push_back((uintptr_t)outs[k]);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -410,6 +433,12 @@ int vlg_create(vlg_ctx **out, int device, void *hip_stream) {
     DeviceGuard dg(device);
     auto c = std::make_unique<vlg_ctx>();
     c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->arch = prop.gcnArchName;
+        const size_t colon = c->arch.find(':');
+        if (colon != std::string::npos) c->arch.resize(colon);
+    }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
@@ -622,6 +651,7 @@ int vlg_ccl_labels(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, 
     w.gflag = (uint8_t *)c->ws + align256(nb * 4);
     int32_t *canon = (int32_t *)((char *)c->ws + align256(nb * 4) + align256(nb));
     w.counters = c->counters;
+    w.tbh = tuning_for(c, height, width).ccl_tbh;
     MRef b{mask_dev, 0ull}, none{nullptr, 0ull};
     HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
     HIP_TRY(launch_ccl_local(c->stream, g, b, none, none, w));
@@ -690,10 +720,113 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
         }
         it->launches += iters;
         it->ms += ms[si];
-        it->bytes += iters * algorithmic_bytes(P.steps[si], g, img->dtype);
+        it->bytes += iters * algorithmic_bytes(P.steps[si], g, img->dtype, tuning_for(c, img->H, img->W).ccl_tbh);
     }
     for (size_t i = 0; i < kinds.size() && (int)i < max_out; i++) out[i] = kinds[i];
     *n_out = (int)kinds.size();
+    return VLG_OK;
+}
+
+int vlg_set_tunable(vlg_ctx *c, int which, int value) {
+    if (!c) return fail(VLG_EINVAL, "null context");
+    if (which != VLG_TUNE_CCL_TILE_ROWS) return fail(VLG_EINVAL, "unknown tunable");
+    if (value != 0 && !valid_tile_bh(value)) return fail(VLG_EINVAL, "tile rows must be 8, 16 or 32");
+    c->forced_tbh = value;
+    return VLG_OK;
+}
+
+int vlg_get_tunable(vlg_ctx *c, int which, int height, int width, int *value) {
+    if (!c || !value) return fail(VLG_EINVAL, "null argument");
+    if (which != VLG_TUNE_CCL_TILE_ROWS) return fail(VLG_EINVAL, "unknown tunable");
+    *value = tuning_for(c, height, width).ccl_tbh;
+    return VLG_OK;
+}
+
+int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int iters, vlg_tune_report *out,
+                 int max_out, int *n_out) {
+    if (!c || !cf || !img || iters < 1 || !n_out) return fail(VLG_EINVAL, "bad argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    if (f->max_chan >= img->C) return fail(VLG_ESHAPE, "formula uses a channel the image lacks");
+    DeviceGuard dg(c->device);
+    *n_out = 1;
+    vlg_tune_report rep;
+    std::memset(&rep, 0, sizeof rep);
+    rep.which = VLG_TUNE_CCL_TILE_ROWS;
+    const int cands[3] = {8, 16, 32};
+    std::vector<int> which(f->dag.outputs.size());
+    for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
+    const Plan &P = f->plan(which, Mode::Fused);
+    const Geo g = make_geo(img->H, img->W);
+    const int saved_forced = c->forced_tbh;
+    rep.best = tuning_for(c, img->H, img->W).ccl_tbh;
+    if (g.nwords > 0 && P.ccl_count > 0) {
+        Layout L = layout_for(P, g, true, false);
+        int rc = ensure_ws(c, L.total);
+        if (rc != VLG_OK) return rc;
+        std::vector<uint64_t *> ext(which.size());
+        for (size_t k = 0; k < which.size(); k++)
+            ext[k] = (uint64_t *)((char *)c->ws + L.off_stage + k * L.mask_bytes);
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        double best_ms = 1e30;
+        for (int ci = 0; ci < 3; ci++) {
+            c->forced_tbh = cands[ci];
+            rc = enqueue_plan(c, P, img, L, ext);  // warm-up
+            if (rc == VLG_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
+            for (int it = 0; it < iters && rc == VLG_OK; it++) rc = enqueue_plan(c, P, img, L, ext);
+            float ms = 0.f;
+            if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(VLG_EHIP, "event timing");
+            if (rc != VLG_OK) break;
+            rep.candidates[rep.n] = cands[ci];
+            rep.ms[rep.n] = ms / iters;
+            if (rep.ms[rep.n] < best_ms) {
+                best_ms = rep.ms[rep.n];
+                rep.best = cands[ci];
+            }
+            rep.n++;
+        }
+        c->forced_tbh = saved_forced;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != VLG_OK) return rc;
+        c->tuned[{log2_class(img->H), log2_class(img->W)}].ccl_tbh = rep.best;
+    }
+    if (out && max_out > 0) out[0] = rep;
+    return VLG_OK;
+}
+
+int vlg_tune_save(vlg_ctx *c, const char *path) {
+    if (!c || !path) return fail(VLG_EINVAL, "null argument");
+    FILE *fp = std::fopen(path, "w");
+    if (!fp) return fail(VLG_EINVAL, std::string("cannot write ") + path);
+    for (const auto &kv : c->tuned)
+        std::fprintf(fp,
+                     "{\"arch\": \"%s\", \"tunable\": \"ccl_tile_rows\", \"h_class\": %d, \"w_class\": %d, "
+                     "\"value\": %d}\n",
+                     c->arch.c_str(), kv.first.first, kv.first.second, kv.second.ccl_tbh);
+    std::fclose(fp);
+    return VLG_OK;
+}
+
+int vlg_tune_load(vlg_ctx *c, const char *path) {
+    if (!c || !path) return fail(VLG_EINVAL, "null argument");
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return fail(VLG_EINVAL, std::string("cannot read ") + path);
+    char line[512];
+    while (std::fgets(line, sizeof line, fp)) {
+        char arch[64] = {0}, tun[64] = {0};
+        int hc = 0, wc = 0, v = 0;
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"tunable\": \"%63[^\"]\", \"h_class\": %d, \"w_class\": %d, "
+                              "\"value\": %d}",
+                        arch, tun, &hc, &wc, &v) != 5)
+            continue;
+        if (c->arch != arch || std::string(tun) != "ccl_tile_rows" || !valid_tile_bh(v)) continue;
+        c->tuned[{hc, wc}].ccl_tbh = v;
+    }
+    std::fclose(fp);
     return VLG_OK;
 }
 

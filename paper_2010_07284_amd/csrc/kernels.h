@@ -27,16 +27,18 @@ struct Geo {
 
 Geo make_geo(int H, int W);
 
-// Tile geometry of the reachability labelling: TBH x TBW blocks per tile.
-constexpr int kTileBH = 16;            // block rows per tile (32 pixel rows)
-constexpr int kTileWW = 2;             // words per tile row (128 pixel columns)
-constexpr int kTileBW = 32 * kTileWW;  // block columns per tile
+// Tile geometry of the reachability labelling: TBH x 64 blocks per tile
+// (2*TBH pixel rows x 128 pixel columns); TBH is tunable (8, 16 or 32).
+constexpr int kTileBW = 64;
+constexpr int kTileBHDefault = 16;
+inline bool valid_tile_bh(int t) { return t == 8 || t == 16 || t == 32; }
 
 struct CclWork {
     int32_t *glab;       // [BH*BW] parent pointers (block ids, row-major)
     uint8_t *gflag;      // [BH*BW] local roots: bit0 touches the tile border,
                          // bit 1+u meets the seeds of labelling user u
     unsigned long long *counters; // [2] merge unions, merge retries (may be null)
+    int tbh = kTileBHDefault;     // block rows per labelling tile
 };
 
 constexpr int kMaxAtomsPerLaunch = 32;

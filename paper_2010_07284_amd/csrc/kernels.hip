@@ -665,7 +665,7 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 }
 
 int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
-int ntiles_y(const Geo &g) { return (g.BH + kTileBH - 1) / kTileBH; }
+int ntiles_y(const Geo &g, int tbh) { return (g.BH + tbh - 1) / tbh; }
 
 }  // namespace
 
@@ -714,17 +714,27 @@ hipError_t launch_atoms(hipStream_t s, const Geo &g, const void *chan, int dtype
 
 hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w) {
     if (g.nwords == 0) return hipSuccess;
-    const int ntx = ntiles_x(g), nty = ntiles_y(g);
-    k_ccl_local<kTileBH><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag);
+    if (!valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
+    const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh);
+    switch (w.tbh) {
+    case 8: k_ccl_local<8><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
+    case 16: k_ccl_local<16><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
+    default: k_ccl_local<32><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &w) {
     if (g.nwords == 0) return hipSuccess;
-    const int ntx = ntiles_x(g), nty = ntiles_y(g);
-    const int64_t n = (int64_t)ntx * nty * (kTileBW + 2 * kTileBH);
-    k_ccl_merge<kTileBH><<<(int)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-        g, b, ntx, ntx * nty, w.glab, w.counters);
+    if (!valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
+    const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh);
+    const int64_t n = (int64_t)ntx * nty * (kTileBW + 2 * w.tbh);
+    const int grid = (int)((n + kThreads - 1) / kThreads);
+    switch (w.tbh) {
+    case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, ntx * nty, w.glab, w.counters); break;
+    case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, ntx * nty, w.glab, w.counters); break;
+    default: k_ccl_merge<32><<<grid, kThreads, 0, s>>>(g, b, ntx, ntx * nty, w.glab, w.counters); break;
+    }
     return hipGetLastError();
 }
 

@@ -16,8 +16,9 @@ def ctx():
     return vlg.create()
 
 
-def gpu_labels(ctx, mask):
+def gpu_labels(ctx, mask, tbh=0):
     import torch
+    vlg.set_tunable(ctx, "ccl_tile_rows", tbh)
     H, W = mask.shape
     words = torch.from_numpy(vlg.pack(mask)).cuda()
     lab = vlg.ccl_labels(ctx, words, H, W)
@@ -34,11 +35,21 @@ def test_random_masks(ctx, h, w, p):
     assert np.array_equal(gpu_labels(ctx, m), oracle.ccl(m))
 
 
+@pytest.mark.parametrize("tbh", [8, 16, 32])
 @pytest.mark.parametrize("shape", [(101, 77), (1024, 1024), (2048, 4096)])
-def test_serpentine_maze(ctx, shape):
+def test_serpentine_maze(ctx, shape, tbh):
     m = images.serpentine_maze(*shape).astype(np.uint8)
-    lab = gpu_labels(ctx, m)
+    lab = gpu_labels(ctx, m, tbh)
     assert np.all(lab[m > 0] == 0) and np.all(lab[m == 0] == -1)
+
+
+@pytest.mark.parametrize("tbh", [8, 32])
+@pytest.mark.parametrize("h,w", [(17, 129), (65, 257), (333, 1029)])
+def test_tile_heights(ctx, h, w, tbh):
+    rng = np.random.default_rng(h + w + tbh)
+    for p in (0.35, 0.55):
+        m = (rng.random((h, w)) < p).astype(np.uint8)
+        assert np.array_equal(gpu_labels(ctx, m, tbh), oracle.ccl(m))
 
 
 def test_checkerboard_and_stripes(ctx):

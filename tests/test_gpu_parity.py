@@ -198,3 +198,36 @@ def test_labelling_reuse(ctx):
     want = oracle.run(src, img)
     for mode in MODES:
         assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=mode)
+
+
+@pytest.mark.parametrize("tbh", [8, 16, 32])
+def test_tile_heights_all_operators(ctx, tbh):
+    import paper_2010_07284_amd as vlg
+    rng = np.random.default_rng(tbh)
+    img = images.smoothed_noise(rng, 389, 517, sigma=2.0)[None]
+    img = np.concatenate([img, rng.random((1, 389, 517)).astype(np.float32)])
+    src = ops_src(rng)
+    vlg.set_tunable(ctx, "ccl_tile_rows", tbh)
+    try:
+        assert_same(src, img, gpu_run(ctx, src, img, "graph"), tag=f"tbh={tbh}")
+    finally:
+        vlg.set_tunable(ctx, "ccl_tile_rows", 0)
+
+
+def test_autotune_picks_and_persists(ctx, tmp_path):
+    import paper_2010_07284_amd as vlg
+    img = images.ellipse_maze_image(2, 512)
+    src = formulas.ellipse_dag(2)
+    im = vlg.load_image(ctx, img)
+    f = vlg.compile_formula(ctx, src)
+    rep = vlg.autotune(ctx, f, im, iters=2)
+    best, times = rep["ccl_tile_rows"]
+    assert set(times) == {8, 16, 32} and best == min(times, key=times.get)
+    assert vlg.get_tunable(ctx, "ccl_tile_rows", 512, 512) == best
+    path = str(tmp_path / "tune.jsonl")
+    vlg.tune_save(ctx, path)
+    ctx2 = vlg.create()
+    vlg.tune_load(ctx2, path)
+    assert vlg.get_tunable(ctx2, "ccl_tile_rows", 512, 512) == best
+    # results do not depend on the choice
+    assert_same(src, img, gpu_run(ctx, src, img, "graph"))
