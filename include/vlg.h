@@ -213,6 +213,36 @@ int vlg_autotune(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int i
 int vlg_tune_save(vlg_ctx *ctx, const char *path);
 int vlg_tune_load(vlg_ctx *ctx, const char *path);
 
+/* Serving loop: continuous batching of evaluation requests on one device.
+ * nslots worker slots each own a context (its own stream); a request
+ * (formula, resident image, device output buffers, packed format) is admitted
+ * to a free slot in arrival order once its HBM footprint (live masks,
+ * labelling and percentile workspace) fits in what remains of
+ * hbm_budget_bytes, reserved from one device pool.  Requests admitted to
+ * different slots run concurrently on the device.  A request whose footprint
+ * exceeds the whole budget completes at once with VLG_ENOMEM.  Functions are
+ * thread-safe; submit never blocks on device work. */
+typedef struct vlg_server vlg_server;
+typedef struct vlg_server_stats {
+    int64_t submitted, completed, rejected;
+    int64_t max_inflight;        /* most requests running at once */
+    int64_t max_queued;          /* most requests waiting for admission */
+    int64_t peak_reserved_bytes; /* most pool bytes reserved at once */
+    int64_t budget_bytes;
+} vlg_server_stats;
+int vlg_server_create(vlg_server **out, int device, int nslots, int64_t hbm_budget_bytes);
+/* outs[k]: packed device buffer of output k (NULL skips it); valid until the
+ * request completes.  *request_id identifies the request for vlg_server_wait. */
+int vlg_server_submit(vlg_server *s, const vlg_formula *f, const vlg_image *img, void *const *outs,
+                      int64_t *request_id);
+/* Block until the request completes; returns its status.  queue_ms: submit to
+ * admission; run_ms: admission to completion (outputs written).  Each id can
+ * be waited for once. */
+int vlg_server_wait(vlg_server *s, int64_t request_id, double *queue_ms, double *run_ms);
+int vlg_server_read_stats(vlg_server *s, vlg_server_stats *out);
+/* Finish every submitted request, stop the slots, release the pool. */
+int vlg_server_destroy(vlg_server *s);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *vlg_last_error(void);
 

@@ -218,6 +218,48 @@ def tune_load(ctx, path):
     _lib.call("vlg_tune_load", ctx.handle, path.encode())
 
 
+class Server:
+    """Serving loop (vlg_server_*): continuous batching with HBM-footprint
+    admission.  submit() returns at once; wait() blocks for one request and
+    returns (queue_ms, run_ms)."""
+
+    def __init__(self, device=0, slots=4, budget_bytes=8 << 30):
+        h = ctypes.c_void_p()
+        _lib.call("vlg_server_create", ctypes.byref(h), device, slots, int(budget_bytes))
+        self.handle = h
+        self.device = device
+        self._keep = {}
+
+    def submit(self, f, img, outs):
+        arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() if o is not None else None for o in outs])
+        rid = ctypes.c_int64()
+        _lib.call("vlg_server_submit", self.handle, f.handle, img.handle, arr, ctypes.byref(rid))
+        self._keep[rid.value] = (f, img, outs)  # keep buffers alive until waited
+        return rid.value
+
+    def wait(self, rid):
+        q, r = ctypes.c_double(), ctypes.c_double()
+        try:
+            _lib.call("vlg_server_wait", self.handle, rid, ctypes.byref(q), ctypes.byref(r))
+        finally:
+            self._keep.pop(rid, None)
+        return q.value, r.value
+
+    def stats(self):
+        st = _lib.ServerStats()
+        _lib.call("vlg_server_read_stats", self.handle, ctypes.byref(st))
+        return {n: getattr(st, n) for n, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h:
+            _lib.call("vlg_server_destroy", h)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib.loaded():
+            self.close()
+
+
 def unpack(words, height, width):
     """Packed int64 words (torch or numpy, [H, ceil(W/64)]) -> numpy uint8 [H, W]."""
     import numpy as np
@@ -238,5 +280,5 @@ def pack(mask):
 
 __all__ = ["create", "sync", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
            "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
-           "tune_load", "unpack", "pack", "VlgError",
+           "tune_load", "Server", "unpack", "pack", "VlgError",
            "LIB_PATH"]

@@ -11,7 +11,8 @@ EXPORTS = [
     "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name",
     "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels",
     "vlg_ccl_read_counters", "vlg_profile", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune",
-    "vlg_tune_save", "vlg_tune_load", "vlg_last_error",
+    "vlg_tune_save", "vlg_tune_load", "vlg_server_create", "vlg_server_submit", "vlg_server_wait",
+    "vlg_server_read_stats", "vlg_server_destroy", "vlg_last_error",
 ]
 
 ERRORS = {-1: "VLG_EINVAL", -2: "VLG_EPARSE", -3: "VLG_ESHAPE", -4: "VLG_ENOMEM", -5: "VLG_EHIP",
@@ -38,6 +39,11 @@ class KernelTime(ctypes.Structure):
 class TuneReport(ctypes.Structure):
     _fields_ = [("which", ctypes.c_int), ("best", ctypes.c_int), ("n", ctypes.c_int),
                 ("candidates", ctypes.c_int * 8), ("ms", ctypes.c_double * 8)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "max_inflight", "max_queued",
+                                              "peak_reserved_bytes", "budget_bytes")]
 
 
 class CclCounters(ctypes.Structure):
@@ -82,6 +88,11 @@ def lib():
             "vlg_autotune": ([P, P, P, I, P, I, P], I),
             "vlg_tune_save": ([P, ctypes.c_char_p], I),
             "vlg_tune_load": ([P, ctypes.c_char_p], I),
+            "vlg_server_create": ([P, I, I, I64], I),
+            "vlg_server_submit": ([P, P, P, P, P], I),
+            "vlg_server_wait": ([P, I64, P, P], I),
+            "vlg_server_read_stats": ([P, P], I),
+            "vlg_server_destroy": ([P], I),
             "vlg_last_error": ([], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():

@@ -102,6 +102,7 @@ struct vlg_ctx {
     int mode = VLG_MODE_GRAPH;
     void *ws = nullptr;
     size_t ws_size = 0;
+    bool ws_external = false;       // workspace lent by a server slot
     unsigned long long *counters = nullptr;  // device [2]
     bool count_ccl = false;         // collect merge counters (VLG_CCL_COUNTERS=1)
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -146,12 +147,13 @@ Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8)
 
 int ensure_ws(vlg_ctx *c, size_t need) {
     if (c->ws_size >= need) return VLG_OK;
+    if (c->ws_external) return fail(VLG_ENOMEM, "admitted workspace smaller than the evaluation needs");
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->drop_graphs();
+    const size_t sz = std::max(need, c->ws_size + c->ws_size / 4);
     if (c->ws) HIP_TRY(hipFree(c->ws));
     c->ws = nullptr;
     c->ws_size = 0;
-    size_t sz = std::max(need, c->ws_size + c->ws_size / 4);
     if (hipMalloc(&c->ws, sz) != hipSuccess) {
         (void)hipGetLastError();
         c->ws = nullptr;
@@ -418,6 +420,34 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
 
 }  // namespace
 
+namespace vlg {
+// Used by the serving loop (server.cpp).
+size_t evaluation_footprint(vlg_formula *f, const vlg_image *img) {
+    std::vector<int> all(f->dag.outputs.size());
+    for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
+    const Plan &P = f->plan(all, Mode::Fused);
+    return layout_for(P, make_geo(img->H, img->W), false, false).total;
+}
+int evaluate_all_on(vlg_ctx *c, vlg_formula *f, const vlg_image *img, void *const *outs, void *ws, size_t ws_size) {
+    c->ws = ws;
+    c->ws_size = ws_size;
+    c->ws_external = true;
+    std::vector<int> which;
+    std::vector<void *> o;
+    for (size_t i = 0; i < f->dag.outputs.size(); i++) {
+        if (!outs[i]) continue;
+        which.push_back((int)i);
+        o.push_back(outs[i]);
+    }
+    int rc = run(c, f, img, which, o, VLG_PACKED64, VLG_DEVICE);
+    if (rc == VLG_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(VLG_EHIP, "stream synchronize failed");
+    return rc;
+}
+const char *last_error_text() { return g_err.c_str(); }
+int set_last_error(int code, const std::string &msg) { return fail(code, msg); }
+size_t formula_outputs(const vlg_formula *f) { return f->dag.outputs.size(); }
+}  // namespace vlg
+
 extern "C" {
 
 const char *vlg_last_error(void) { return g_err.c_str(); }
@@ -459,7 +489,7 @@ void vlg_destroy(vlg_ctx *c) {
     DeviceGuard dg(c->device);
     (void)hipStreamSynchronize(c->stream);
     c->drop_graphs();
-    if (c->ws) (void)hipFree(c->ws);
+    if (c->ws && !c->ws_external) (void)hipFree(c->ws);
     if (c->counters) (void)hipFree(c->counters);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
