@@ -231,6 +231,9 @@ typedef struct vlg_server_stats {
     int64_t budget_bytes;
 } vlg_server_stats;
 int vlg_server_create(vlg_server **out, int device, int nslots, int64_t hbm_budget_bytes);
+/* Device workspace one evaluation of every output of f on img needs (the
+ * footprint the server reserves at admission), in bytes. */
+int vlg_evaluation_bytes(const vlg_formula *f, const vlg_image *img, int64_t *bytes);
 /* outs[k]: packed device buffer of output k (NULL skips it); valid until the
  * request completes.  *request_id identifies the request for vlg_server_wait. */
 int vlg_server_submit(vlg_server *s, const vlg_formula *f, const vlg_image *img, void *const *outs,

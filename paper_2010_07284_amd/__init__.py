@@ -218,6 +218,13 @@ def tune_load(ctx, path):
     _lib.call("vlg_tune_load", ctx.handle, path.encode())
 
 
+def evaluation_bytes(f, img):
+    """vlg_evaluation_bytes: device workspace of one evaluation of f on img."""
+    b = ctypes.c_int64()
+    _lib.call("vlg_evaluation_bytes", f.handle, img.handle, ctypes.byref(b))
+    return b.value
+
+
 class Server:
     """Serving loop (vlg_server_*): continuous batching with HBM-footprint
     admission.  submit() returns at once; wait() blocks for one request and
@@ -280,5 +287,5 @@ def pack(mask):
 
 __all__ = ["create", "sync", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
            "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
-           "tune_load", "Server", "unpack", "pack", "VlgError",
+           "tune_load", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

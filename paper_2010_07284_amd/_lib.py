@@ -12,7 +12,7 @@ EXPORTS = [
     "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels",
     "vlg_ccl_read_counters", "vlg_profile", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune",
     "vlg_tune_save", "vlg_tune_load", "vlg_server_create", "vlg_server_submit", "vlg_server_wait",
-    "vlg_server_read_stats", "vlg_server_destroy", "vlg_last_error",
+    "vlg_server_read_stats", "vlg_server_destroy", "vlg_evaluation_bytes", "vlg_last_error",
 ]
 
 ERRORS = {-1: "VLG_EINVAL", -2: "VLG_EPARSE", -3: "VLG_ESHAPE", -4: "VLG_ENOMEM", -5: "VLG_EHIP",
@@ -93,6 +93,7 @@ def lib():
             "vlg_server_wait": ([P, I64, P, P], I),
             "vlg_server_read_stats": ([P, P], I),
             "vlg_server_destroy": ([P], I),
+            "vlg_evaluation_bytes": ([P, P, P], I),
             "vlg_last_error": ([], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():

@@ -183,6 +183,12 @@ int vlg_server_create(vlg_server **out, int device, int nslots, int64_t hbm_budg
     return VLG_OK;
 }
 
+int vlg_evaluation_bytes(const vlg_formula *f, const vlg_image *img, int64_t *bytes) {
+    if (!f || !img || !bytes) return sfail(VLG_EINVAL, "null argument");
+    *bytes = (int64_t)vlg::evaluation_footprint(const_cast<vlg_formula *>(f), img);
+    return VLG_OK;
+}
+
 int vlg_server_submit(vlg_server *s, const vlg_formula *cf, const vlg_image *img, void *const *outs,
                       int64_t *request_id) {
     if (!s || !cf || !img || !outs || !request_id) return sfail(VLG_EINVAL, "null argument");

@@ -73,8 +73,11 @@ def test_budget_admission_and_rejection():
     im_small = vlg.load_image(ctx, torch.from_numpy(images.plain_image(1, 256)).cuda())
     im_big = vlg.load_image(ctx, torch.from_numpy(images.plain_image(2, 2048)).cuda())
     f = vlg.compile_formula(ctx, formulas.PLAIN_FORMULA)
-    # budget for about one small request at a time
-    srv = vlg.Server(slots=4, budget_bytes=600_000)
+    # budget for one small request at a time
+    fp = vlg.evaluation_bytes(f, im_small)
+    budget = fp * 3 // 2
+    assert vlg.evaluation_bytes(f, im_big) > budget
+    srv = vlg.Server(slots=4, budget_bytes=budget)
     rids = [(srv.submit(f, im_small, o), o) for o in [alloc(im_small, f) for _ in range(12)]]
     big_out = alloc(im_big, f)
     big = srv.submit(f, im_big, big_out)
@@ -85,7 +88,7 @@ def test_budget_admission_and_rejection():
     assert e.value.code == -4
     st = srv.stats()
     assert st["rejected"] == 1 and st["completed"] == 13
-    assert st["peak_reserved_bytes"] <= 600_000
+    assert st["peak_reserved_bytes"] <= budget
     assert st["max_inflight"] == 1  # the budget admits one request at a time
     first = rids[0][1]
     for _, outs in rids[1:]:
