@@ -47,6 +47,106 @@ def time_mode(vlg, lib, ctx, f, im, arr, mode, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+def bench_chain(vlg, lib, steps):
+    """Sequential large formula: 1024x1024 uint8 random mask (density 0.5),
+    10,000 rotating near/and/not elements plus 500 reach elements; per-op
+    launches against the fused schedule and its hipGraph."""
+    import torch
+    from synth import formulas, images
+    img = images.random_mask_image(3, 1024)
+    src = formulas.chain_dag(3)
+    ctx = vlg.create(0)
+    im = vlg.load_image(ctx, torch.from_numpy(img).to("cuda:0"))
+    f = vlg.compile_formula(ctx, src)
+    info = vlg.formula_info(f)
+    nout = info["outputs"]
+    outs = [torch.empty((1024, 16), dtype=torch.int64, device="cuda:0") for _ in range(nout)]
+    arr = (ctypes.c_void_p * nout)(*[o.data_ptr() for o in outs])
+    ms = {m: time_mode(vlg, lib, ctx, f, im, arr, m, steps, 1) for m in ("perop", "fused", "graph")}
+    for m, t in ms.items():
+        log(f"[bench] chain_1024 {m}: {t:.3f} ms/evaluation")
+    return {"workload": f"chain_1024: 1024x1024 u8 random mask, {info['nodes']}-node chain "
+                        f"({info['reach_nodes']} reach), {nout} outputs",
+            "nodes": info["nodes"], "launches_perop": info["steps_perop"], "launches_fused": info["launches_fused"],
+            "perop_ms": round(ms["perop"], 3), "fused_ms": round(ms["fused"], 3), "graph_ms": round(ms["graph"], 3),
+            "speedup_graph_vs_perop": round(ms["perop"] / ms["graph"], 3),
+            "gpixel_node_per_s": round(1024 * 1024 * info["nodes"] / (ms["graph"] / 1e3) / 1e9, 3)}
+
+
+def bench_serve(vlg, n_req, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
+    """Serving loop: Poisson arrivals over a pool of resident images (sides
+    log-uniform in [256, 8192], float32) and formulas (20-2000 nodes, up to 50
+    reach-type); saturation throughput first, then p50/p99 latency
+    (submission to outputs written) at fractions of it."""
+    import numpy as np
+    import torch
+    from synth import formulas, images
+    rng = np.random.default_rng(seed)
+    ctx = vlg.create(0)
+    sides = [256, 512, 1024, 2048, 4096, 8192]
+    imgs = []
+    for i, sd in enumerate(sides):
+        im = images.ellipse_maze_image(50 + i, sd, n_ellipses=60)[:1]
+        imgs.append(vlg.load_image(ctx, torch.from_numpy(np.ascontiguousarray(im)).to("cuda:0")))
+    fs = []
+    for k in range(6):
+        n = int(round(np.exp(rng.uniform(np.log(20), np.log(2000)))))
+        fs.append(vlg.compile_formula(ctx, formulas.random_dag(500 + k, n_nodes=n,
+                                                               n_reach=int(rng.integers(0, min(50, n // 10) + 1)))))
+    nouts = [vlg.formula_info(f)["outputs"] for f in fs]
+    ring = 8
+    bufs = {}
+
+    def outs_for(i, k, r):
+        key = (i, k, r % ring)
+        if key not in bufs:
+            C, H, W = imgs[i].shape
+            bufs[key] = [torch.empty((H, (W + 63) // 64), dtype=torch.int64, device="cuda:0")
+                         for _ in range(nouts[k])]
+        return bufs[key]
+
+    reqs = [(int(rng.integers(0, len(imgs))), int(rng.integers(0, len(fs)))) for _ in range(n_req)]
+    for i, k in set(reqs):  # warm plans and buffers
+        vlg.check_all(ctx, fs[k], imgs[i], outs=outs_for(i, k, 0))
+    vlg.sync(ctx)
+    srv = vlg.Server(slots=slots, budget_bytes=budget)
+    t0 = time.perf_counter()
+    ids = [srv.submit(fs[k], imgs[i], outs_for(i, k, r)) for r, (i, k) in enumerate(reqs)]
+    for rid in ids:
+        srv.wait(rid)
+    sat = n_req / (time.perf_counter() - t0)
+    log(f"[bench] serve: saturation {sat:.1f} req/s over {n_req} requests")
+    out = {"workload": f"serve: {len(imgs)} resident images (sides {sides}), {len(fs)} formulas "
+                       f"({[vlg.formula_info(f)['nodes'] for f in fs]} nodes), {slots} slots",
+           "saturation_req_per_s": round(sat, 2), "levels": []}
+    for frac in fracs:
+        rate = frac * sat
+        gaps = rng.exponential(1.0 / rate, n_req)
+        t_start = time.perf_counter()
+        ids, t_next = [], t_start
+        for r, (i, k) in enumerate(reqs):
+            t_next += gaps[r]
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ids.append(srv.submit(fs[k], imgs[i], outs_for(i, k, r)))
+        lat = []
+        for rid in ids:
+            q, rr = srv.wait(rid)
+            lat.append(q + rr)
+        wall = time.perf_counter() - t_start
+        lat = np.array(lat)
+        lvl = {"offered_req_per_s": round(rate, 2), "achieved_req_per_s": round(n_req / wall, 2),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        log(f"[bench] serve at {frac:.0%}: {lvl}")
+        out["levels"].append(lvl)
+    st = srv.stats()
+    out["max_inflight"] = st["max_inflight"]
+    out["peak_reserved_gib"] = round(st["peak_reserved_bytes"] / 2**30, 3)
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +155,9 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--skip-oracle", action="store_true", help="no parity gate, no CPU baseline")
+    ap.add_argument("--no-chain", action="store_true", help="skip the 10,500-node chain measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serve-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the formula path has no multi-GPU mode (images or "
@@ -153,6 +256,10 @@ def main():
                      "bytes_per_launch": round(dom_bytes / dom_n), "traffic": None},
         "cpu_baseline": cpu,
     }
+    if not args.no_chain:
+        line["chain"] = bench_chain(vlg, lib, steps=3)
+    if not args.no_serve:
+        line["serve"] = bench_serve(vlg, args.serve_requests)
     print(json.dumps(line), flush=True)
 
 

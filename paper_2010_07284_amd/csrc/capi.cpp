@@ -274,7 +274,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                 b.n = (int)(sj - si + 1);
                 for (size_t k = si; k <= sj; k++) {
                     const Step &t = P.steps[k];
-                    b.ops[k - si] = NearOp{mref(t.x), mref(t.z), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out)};
+                    b.ops[k - si] = NearOp{mref(t.x), mref(t.z), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out), t.op};
                 }
                 e = launch_near_batch(c->stream, g, b);
             }
@@ -310,7 +310,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
             e = launch_logic(c->stream, g, mref(s.x), mref(s.y), s.op, s.inv_out, slot_ptr(s.out));
             break;
         case SK::Near:
-            e = launch_near(c->stream, g, mref(s.x), s.inv_out, mref(s.z), slot_ptr(s.out));
+            e = launch_near(c->stream, g, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out));
             break;
         case SK::CclLocal:
             e = launch_ccl_local(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w);

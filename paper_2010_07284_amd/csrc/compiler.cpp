@@ -546,8 +546,29 @@ struct Lower {
     std::vector<char> have;
     std::map<std::pair<int32_t, uint64_t>, int32_t> pct_memo;
     int32_t npct = 0;
+    // epilogue fusion: a near/interior node whose only consumer is & or | is
+    // not emitted on its own; the consumer runs it with itself as epilogue
+    std::vector<int32_t> uses, consumer;
+    std::vector<char> deferred;
+    std::vector<Ref> dx;
+    std::vector<uint8_t> dinv;
 
-    Lower(const Dag &d, Mode m) : dag(d), mode(m), val(d.nodes.size()), have(d.nodes.size(), 0) {}
+    Lower(const Dag &d, Mode m)
+        : dag(d), mode(m), val(d.nodes.size()), have(d.nodes.size(), 0), uses(d.nodes.size(), 0),
+          consumer(d.nodes.size(), -1), deferred(d.nodes.size(), 0), dx(d.nodes.size()), dinv(d.nodes.size(), 0) {}
+
+    bool can_defer(int32_t id) const {
+        const int32_t c = consumer[(size_t)id];
+        return mode == Mode::Fused && uses[(size_t)id] == 1 && c >= 0 &&
+               (dag.nodes[(size_t)c].op == Op::And || dag.nodes[(size_t)c].op == Op::Or);
+    }
+    Ref materialize(int32_t id) {
+        if (deferred[(size_t)id]) {
+            val[(size_t)id] = near(dx[(size_t)id], dinv[(size_t)id], Const(1));
+            deferred[(size_t)id] = 0;
+        }
+        return val[(size_t)id];
+    }
 
     int32_t fresh() { return nssa++; }
 
@@ -594,11 +615,12 @@ struct Lower {
         s.out = fresh();
         return R(s.out);
     }
-    Ref near(Ref x, int inv_out, Ref z) {
+    Ref near(Ref x, int inv_out, Ref z, int zop = 0) {
         Step &s = emit(SK::Near);
         s.x = x;
         s.inv_out = (uint8_t)inv_out;
         s.z = z;
+        s.op = (uint8_t)zop;
         s.out = fresh();
         return R(s.out);
     }
@@ -693,8 +715,17 @@ struct Lower {
             return Neg(val[(size_t)n.a]);
         case Op::And:
         case Op::Or: {
+            const bool isor = n.op == Op::Or;
+            if (deferred[(size_t)n.a] || deferred[(size_t)n.b]) {
+                const int32_t d = deferred[(size_t)n.a] ? n.a : n.b, o = d == n.a ? n.b : n.a;
+                const Ref other = materialize(o);
+                if (!is_const(other)) {
+                    deferred[(size_t)d] = 0;
+                    return near(dx[(size_t)d], dinv[(size_t)d], other, isor);
+                }
+                materialize(d);
+            }
             Ref a = val[(size_t)n.a], b = val[(size_t)n.b];
-            bool isor = n.op == Op::Or;
             // x & 0 = 0, x & 1 = x, x | 1 = 1, x | 0 = x
             if (is_const(a)) std::swap(a, b);
             if (is_const(b)) return (b.inv == (isor ? 1 : 0)) ? b : a;
@@ -703,11 +734,23 @@ struct Lower {
         case Op::Near: {
             Ref a = val[(size_t)n.a];
             if (is_const(a)) return a;  // N 0 = 0, N 1 = 1
+            if (can_defer(id)) {
+                deferred[(size_t)id] = 1;
+                dx[(size_t)id] = a;
+                dinv[(size_t)id] = 0;
+                return Ref();
+            }
             return near(a, 0, one);
         }
         case Op::Interior: {
             Ref a = val[(size_t)n.a];
             if (is_const(a)) return a;
+            if (can_defer(id)) {
+                deferred[(size_t)id] = 1;
+                dx[(size_t)id] = Neg(a);
+                dinv[(size_t)id] = 1;
+                return Ref();
+            }
             return near(Neg(a), 1, one);  // !N!a
         }
         case Op::Reach: {
@@ -928,6 +971,18 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
         const Node &n = dag.nodes[i];
         if (n.a >= 0) need[(size_t)n.a] = 1;
         if (n.b >= 0) need[(size_t)n.b] = 1;
+    }
+    for (size_t i = 0; i < N; i++) {
+        if (!need[i]) continue;
+        for (int32_t o : {dag.nodes[i].a, dag.nodes[i].b}) {
+            if (o < 0) continue;
+            L.uses[(size_t)o]++;
+            L.consumer[(size_t)o] = (int32_t)i;
+        }
+    }
+    for (int k : which) {
+        L.uses[(size_t)dag.outputs[(size_t)k]]++;
+        L.consumer[(size_t)dag.outputs[(size_t)k]] = -1;
     }
     if (mode == Mode::Fused) L.atom_groups(need);
     for (size_t i = 0; i < N; i++) {

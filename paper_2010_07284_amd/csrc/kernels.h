@@ -52,7 +52,8 @@ struct AtomLaunch {
 };
 
 hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out);
-hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, uint64_t *out);
+// out = (N(x) ^ inv_out) OP z with OP = and (zop 0) or or (zop 1)
+hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, int zop, uint64_t *out);
 hipError_t launch_atoms(hipStream_t s, const Geo &g, const void *chan, int dtype, const AtomLaunch &a);
 hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w);
 hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &w);
@@ -76,6 +77,7 @@ struct NearOp {
     MRef x, z;
     uint64_t inv_out;
     uint64_t *out;
+    int zop;
 };
 struct NearBatch {
     int n;

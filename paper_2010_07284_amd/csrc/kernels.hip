@@ -51,11 +51,11 @@ __global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int o
 }
 
 // ------------------------------------------------------------------ near
-// out = (N(x) ^ inv_out) & z.  N over the in-image 3x3 block: horizontal
+// out = (N(x) ^ inv_out) OP z, OP = and (zop 0) / or (zop 1).  N over the in-image 3x3 block: horizontal
 // dilation inside a word with the edge bits of the neighbouring words, then the
 // OR of three rows.  Complemented inputs have their padding bits cleared first
 // so nothing leaks in from beyond the right border.
-__global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z,
+__global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z, int zop,
                                                    uint64_t *__restrict__ out) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
@@ -74,7 +74,8 @@ __global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_o
             const uint64_t r = last ? 0ull : ldm(x, base + 1);
             acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
         }
-        uint64_t res = (acc ^ inv_out) & ldm(z, i);
+        const uint64_t zz = ldm(z, i);
+        uint64_t res = zop ? ((acc ^ inv_out) | zz) : ((acc ^ inv_out) & zz);
         if (last) res &= g.tail;
         out[i] = res;
     }
@@ -570,11 +571,20 @@ __global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, 
 // byte.  Runs after k_ccl_flag, so every block's root is two loads away.
 __global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const int32_t *__restrict__ glab,
                                                          uint8_t *gflag, int user) {
-    const int bx = blockIdx.x * kThreads + threadIdx.x, by = blockIdx.y;
-    if (bx >= g.BW) return;
-    if (!block_bits_g(g, sm, by, bx)) return;
-    const int r = glab[glab[(int64_t)by * g.BW + bx]];
-    atomicOr((unsigned int *)(gflag + (r & ~3)), (1u << (1 + user)) << (8 * (r & 3)));
+    const int bx = blockIdx.x * kThreads + threadIdx.x, by = blockIdx.y, lane = lane_id();
+    int r = -1;
+    if (bx < g.BW && block_bits_g(g, sm, by, bx)) r = glab[glab[(int64_t)by * g.BW + bx]];
+    // neighbouring blocks mostly share a root: one atomic per distinct root
+    // per wave (a giant component would otherwise serialise on one address)
+    const uint32_t bit = 1u << (1 + user);
+    uint64_t pending = __ballot(r >= 0);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int r0 = __shfl(r, leader);
+        pending &= ~__ballot(r == r0);
+        if (lane == leader && !(gflag[r0] & bit))
+            atomicOr((unsigned int *)(gflag + (r0 & ~3)), bit << (8 * (r0 & 3)));
+    }
 }
 
 // Up to kMaxBatch independent Boolean steps (or near steps) in one launch:
@@ -609,7 +619,8 @@ __global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt) {
             const uint64_t r = last ? 0ull : ldm(o.x, base + 1);
             acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
         }
-        uint64_t res = (acc ^ o.inv_out) & ldm(o.z, i);
+        const uint64_t zz = ldm(o.z, i);
+        uint64_t res = o.zop ? ((acc ^ o.inv_out) | zz) : ((acc ^ o.inv_out) & zz);
         if (last) res &= g.tail;
         o.out[i] = res;
     }
@@ -618,15 +629,27 @@ __global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt) {
 // Smallest row-major pixel index of each component, gathered at its root.
 __global__ __launch_bounds__(kThreads) void k_ccl_canon(Geo g, MRef b, const int32_t *__restrict__ glab,
                                                         int32_t *canon) {
-    const int64_t nb = (int64_t)g.BH * g.BW;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nb; i += stride) {
-        const int by = (int)(i / g.BW), bx = (int)(i - (int64_t)by * g.BW);
+    const int bx = blockIdx.x * kThreads + threadIdx.x, by = blockIdx.y, lane = lane_id();
+    int r = -1, p = 0x7fffffff;
+    if (bx < g.BW) {
         const uint32_t bits = block_bits_g(g, b, by, bx);
-        if (!bits) continue;
-        const int k = __builtin_ctz(bits);  // top-left, top-right, bottom-left, bottom-right
-        const int p = (2 * by + (k >> 1)) * g.W + 2 * bx + (k & 1);
-        atomicMin(&canon[glab[glab[i]]], p);
+        if (bits) {
+            const int k = __builtin_ctz(bits);  // top-left, top-right, bottom-left, bottom-right
+            p = (2 * by + (k >> 1)) * g.W + 2 * bx + (k & 1);
+            r = glab[glab[(int64_t)by * g.BW + bx]];
+        }
+    }
+    // one atomicMin per distinct root per wave, with the group's minimum
+    uint64_t pending = __ballot(r >= 0);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int r0 = __shfl(r, leader);
+        const bool mine = r == r0;
+        pending &= ~__ballot(mine);
+        int m = mine ? p : 0x7fffffff;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off));
+        if (lane == leader) atomicMin(&canon[r0], m);
     }
 }
 
@@ -692,9 +715,9 @@ hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int
     return hipGetLastError();
 }
 
-hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, uint64_t *out) {
+hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, int zop, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    k_near<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, inv_out ? ~0ull : 0ull, z, out);
+    k_near<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, inv_out ? ~0ull : 0ull, z, zop, out);
     return hipGetLastError();
 }
 
@@ -780,7 +803,8 @@ hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork 
     if (g.nwords == 0) return hipSuccess;
     const int64_t nb = (int64_t)g.BH * g.BW;
     k_fill_i32<<<grid_for(nb, kThreads, 8192), kThreads, 0, s>>>(canon, nb, 0x7fffffff);
-    k_ccl_canon<<<grid_for(nb, kThreads, 8192), kThreads, 0, s>>>(g, b, w.glab, canon);
+    dim3 bgrid((g.BW + kThreads - 1) / kThreads, g.BH);
+    k_ccl_canon<<<bgrid, kThreads, 0, s>>>(g, b, w.glab, canon);
     dim3 grid((g.W + kThreads - 1) / kThreads, g.H);
     k_ccl_labels<<<grid, kThreads, 0, s>>>(g, b, w.glab, canon, labels);
     return hipGetLastError();

@@ -231,3 +231,24 @@ def test_autotune_picks_and_persists(ctx, tmp_path):
     assert vlg.get_tunable(ctx2, "ccl_tile_rows", 512, 512) == best
     # results do not depend on the choice
     assert_same(src, img, gpu_run(ctx, src, img, "graph"))
+
+
+@pytest.mark.parametrize("h,w", [(1, 65), (37, 200), (128, 128)])
+def test_epilogue_fusion_patterns(ctx, h, w):
+    rng = np.random.default_rng(h * w)
+    img = rng.random((2, h, w)).astype(np.float32)
+    src = """
+    let A = intensity(img, 0) >. 0.6
+    let B = intensity(img, 1) <. 0.5
+    output "o1" near(A) & B
+    output "o2" B | interior(A)
+    output "o3" near(A) & near(B)
+    output "o4" near(!A) & true
+    output "o5" near(B) | false
+    output "o6" !(interior(!B) & !A)
+    output "o7" near(A | B) & !near(B)
+    output "o8" near(near(A) & B) | interior(B)
+    """
+    want = oracle.run(src, img)
+    for mode in MODES:
+        assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"{h}x{w} {mode}")
