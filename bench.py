@@ -73,6 +73,118 @@ def bench_chain(vlg, lib, steps):
             "gpixel_node_per_s": round(1024 * 1024 * info["nodes"] / (ms["graph"] / 1e3) / 1e9, 3)}
 
 
+def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512):
+    """Uneven batch: `n` phantom images (sides uniform in [128, 2048], four
+    float32 channels, generated in device memory) and the shared 60-node
+    segmentation formula.  One vlg_check_batch call per step: per-image
+    per-op launches (the baseline) against the batched fused schedule and its
+    hipGraph.  Sampled images are checked against the oracle first."""
+    import numpy as np
+    import torch
+    from synth import formulas, images
+    sizes = images.batch_sizes(seed, n, 128, 2048)
+    src = formulas.segmentation_dag(seed)
+    ctx = vlg.create(0)
+    f = vlg.compile_formula(ctx, src)
+    info = vlg.formula_info(f)
+    nodes, nout = info["nodes"], info["outputs"]
+    log(f"[bench] batch: generating {n} phantom images on the device")
+    order = sorted(range(n), key=lambda i: sizes[i][0] * sizes[i][1])
+    sample = sorted({order[0], order[n // 2], order[-1]})
+    ims, host = [], {}
+    for i, (h, w) in enumerate(sizes):
+        t = images.phantom_image_device(seed, i, h, w, device="cuda:0")
+        ims.append(vlg.load_image(ctx, t))
+        if i in sample:
+            host[i] = t.cpu().numpy()
+        del t
+    torch.cuda.empty_cache()
+    outs = [[torch.empty((h, (w + 63) // 64), dtype=torch.int64, device="cuda:0") for _ in range(nout)]
+            for h, w in sizes]
+    flat = (ctypes.c_void_p * (n * nout))(*[o.data_ptr() for row in outs for o in row])
+    harr = (ctypes.c_void_p * n)(*[im.handle.value for im in ims])
+    # autotune the labelling tile on the largest image of the batch
+    big = order[-1]
+    tune = vlg.autotune(ctx, f, ims[big], iters=2)
+    log(f"[bench] batch: autotuned tile rows {tune['ccl_tile_rows'][0]} on image {big} {sizes[big]}")
+
+    def step():
+        rc = lib.vlg_check_batch(ctx.handle, f.handle, harr, n, flat, 0, 1)
+        if rc:
+            raise RuntimeError(lib.vlg_last_error().decode())
+
+    if check_oracle:
+        import oracle
+        for mode in ("perop", "graph"):
+            vlg.set_mode(ctx, mode)
+            step()
+            vlg.sync(ctx)
+            for i in sample:
+                want = oracle.run(src, host[i])
+                h, w = sizes[i]
+                for k in range(nout):
+                    if not np.array_equal(vlg.unpack(outs[i][k], h, w), want[k]):
+                        raise SystemExit(f"[bench] PARITY FAILURE: batch {mode} image {i} output {k}")
+        log(f"[bench] batch parity: images {sample} bit-exact (perop and graph)")
+    ms = {}
+    for mode in ("perop", "fused", "graph"):
+        vlg.set_mode(ctx, mode)
+        step()
+        vlg.sync(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        vlg.sync(ctx)
+        torch.cuda.synchronize()
+        ms[mode] = (time.perf_counter() - t0) * 1e3 / steps
+        log(f"[bench] batch {mode}: {ms[mode]:.3f} ms per batch")
+    px = sum(h * w for h, w in sizes)
+    res = {"workload": f"uneven_batch_{n}: {n} phantom images, sides U[128,2048], f32 x4 channels, "
+                       f"{nodes}-node segmentation formula, {nout} outputs",
+           "images": n, "gpixels": round(px / 1e9, 4), "nodes": nodes,
+           "ccl_tile_rows": tune["ccl_tile_rows"][0],
+           "perop_ms": round(ms["perop"], 3), "fused_ms": round(ms["fused"], 3), "graph_ms": round(ms["graph"], 3),
+           "speedup_graph_vs_perop": round(ms["perop"] / ms["graph"], 3),
+           "gpixel_node_per_s": round(px * nodes / (ms["graph"] / 1e3) / 1e9, 3),
+           "images_per_s": round(n / (ms["graph"] / 1e3), 1)}
+    del outs, ims
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_pixelwise(vlg, iters, side=46080):
+    """Streaming roofline of the pixel-wise kernels on one side x side float32
+    channel (side 46080: 2^31 - 24M pixels, the largest square image; 8.5 GB
+    channel, 265 MB per mask, far above the 256 MB last-level cache): the
+    threshold atom, N and a Boolean connective, timed per launch with HIP
+    events, against algorithmic bytes (channel read once, masks read/written
+    once)."""
+    import torch
+    src = ('let A = intensity(img) >. 0.5\n'
+           'let D = near(A)\n'
+           'output "atom" A\noutput "near" D\noutput "and" A & !D\n')
+    ctx = vlg.create(0)
+    t = torch.rand((1, side, side), device="cuda:0", dtype=torch.float32)
+    im = vlg.load_image(ctx, t)
+    del t
+    torch.cuda.empty_cache()
+    f = vlg.compile_formula(ctx, src)
+    vlg.profile(ctx, f, im, iters=1)
+    prof = vlg.profile(ctx, f, im, iters=iters)
+    res = {"workload": f"pixelwise_{side}: {side}x{side} f32 channel, one atom, N, and-not",
+           "peak_gbs": HBM_PEAK_GBS}
+    for k, (n, ms, b) in prof.items():
+        gbs = b / (ms / 1e3) / 1e9
+        res[k] = {"avg_launch_us": round(ms / n * 1e3, 2), "bytes_per_launch": round(b / n),
+                  "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"[bench] pixelwise {k:8s} {ms / n * 1e3:9.1f} us/launch  {gbs:7.1f} GB/s  "
+            f"({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+    del im, f, ctx
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serve(vlg, n_req, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
     """Serving loop: Poisson arrivals over a pool of resident images (sides
     log-uniform in [256, 8192], float32) and formulas (20-2000 nodes, up to 50
@@ -158,6 +270,9 @@ def main():
     ap.add_argument("--no-chain", action="store_true", help="skip the 10,500-node chain measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-image uneven batch measurement")
+    ap.add_argument("--batch-images", type=int, default=512)
+    ap.add_argument("--no-pixelwise", action="store_true", help="skip the streaming roofline of the pixel-wise kernels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the formula path has no multi-GPU mode (images or "
@@ -258,6 +373,10 @@ def main():
     }
     if not args.no_chain:
         line["chain"] = bench_chain(vlg, lib, steps=3)
+    if not args.no_pixelwise:
+        line["pixelwise"] = bench_pixelwise(vlg, 5)
+    if not args.no_batch:
+        line["batch"] = bench_batch(vlg, lib, 3, not args.skip_oracle, n=args.batch_images)
     if not args.no_serve:
         line["serve"] = bench_serve(vlg, args.serve_requests)
     print(json.dumps(line), flush=True)

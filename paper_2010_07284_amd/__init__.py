@@ -91,6 +91,9 @@ def load_image(ctx, t):
     C, H, W = t.shape
     dtype = 0 if t.dtype == torch.float32 else 1
     where = 1 if t.is_cuda else 0
+    if where == 1:
+        # the library copies on its own stream: torch's pending writes first
+        torch.cuda.current_stream(t.device).synchronize()
     h = ctypes.c_void_p()
     _lib.call("vlg_load_image", ctx.handle, ctypes.c_void_p(t.data_ptr()), dtype, C, H, W, W, where,
               ctypes.byref(h))
@@ -152,7 +155,8 @@ def check_batch(ctx, f, imgs, outs=None, fmt="packed"):
     n = formula_info(f)["outputs"]
     if outs is None:
         outs = [[_alloc_out(im, fmt, f"cuda:{ctx.device}") for _ in range(n)] for im in imgs]
-    where = 1 if outs[0][0].is_cuda else 0
+    present = [o for row in outs for o in row if o is not None]
+    where = 1 if not present or present[0].is_cuda else 0
     flat = [o.data_ptr() if o is not None else None for row in outs for o in row]
     arr = (ctypes.c_void_p * len(flat))(*flat)
     harr = (ctypes.c_void_p * len(imgs))(*[im.handle.value for im in imgs])
@@ -271,6 +275,8 @@ def unpack(words, height, width):
     """Packed int64 words (torch or numpy, [H, ceil(W/64)]) -> numpy uint8 [H, W]."""
     import numpy as np
     a = words.cpu().numpy() if hasattr(words, "cpu") else np.asarray(words)
+    if height == 0 or width == 0:
+        return np.zeros((height, width), np.uint8)
     bits = np.unpackbits(a.astype("<i8").view(np.uint8).reshape(height, -1), axis=1, bitorder="little")
     return bits[:, :width].copy()
 

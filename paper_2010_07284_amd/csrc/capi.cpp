@@ -106,6 +106,11 @@ struct vlg_ctx {
     unsigned long long *counters = nullptr;  // device [2]
     bool count_ccl = false;         // collect merge counters (VLG_CCL_COUNTERS=1)
     std::map<GraphKey, hipGraphExec_t> graphs;
+    // pinned host staging of batch descriptors; `desc_done` marks the end of
+    // the last upload from it
+    void *desc_host = nullptr;
+    size_t desc_host_size = 0;
+    hipEvent_t desc_done = nullptr;
 
     void drop_graphs() {
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -418,6 +423,272 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
     return VLG_OK;
 }
 
+// ------------------------------------------------------------------ batches
+// Evaluate every output of f on n images of one pixel type with one launch
+// per schedule step: each image gets its own workspace region (mask slots,
+// labelling arrays, percentile state) and a descriptor; the batch kernels
+// walk the concatenated units of all images.  Descriptors, output tables,
+// percentile ranks and unit prefix sums are uploaded before the steps run.
+int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const std::vector<int> &idx,
+              void *const *outs, int fmt, int where) {
+    const size_t nout = f->dag.outputs.size();
+    std::vector<int> all(nout);
+    for (size_t i = 0; i < nout; i++) all[i] = (int)i;
+    const Plan &P = f->plan(all, Mode::Fused);
+    const int n = (int)idx.size();
+    if (n == 0 || nout == 0) return VLG_OK;
+    const int dtype = imgs[idx[0]]->dtype;
+    const bool direct = fmt == VLG_PACKED64 && where == VLG_DEVICE;
+    const bool stage_u8 = fmt == VLG_U8MASK && where == VLG_HOST;
+
+    // one labelling tile height for the batch: the largest image's
+    int64_t big = -1;
+    int tbh = kTileBHDefault;
+    for (int i : idx) {
+        const int64_t px = (int64_t)imgs[i]->H * imgs[i]->W;
+        if (px > big) {
+            big = px;
+            tbh = tuning_for(c, imgs[i]->H, imgs[i]->W).ccl_tbh;
+        }
+    }
+
+    // workspace: per-image layouts, then the descriptor block
+    std::vector<Geo> geo(n);
+    std::vector<Layout> lay(n);
+    std::vector<size_t> off(n);
+    size_t total = 0;
+    for (int k = 0; k < n; k++) {
+        geo[k] = make_geo(imgs[idx[k]]->H, imgs[idx[k]]->W);
+        lay[k] = layout_for(P, geo[k], true, stage_u8);
+        off[k] = total;
+        total += align256(lay[k].total);
+    }
+    const size_t npct = (size_t)P.npct;
+    const size_t d_imgs = total;
+    const size_t d_outs = d_imgs + align256((size_t)n * sizeof(BImg));
+    const size_t d_ranks = d_outs + align256((size_t)n * nout * sizeof(uint64_t *));
+    const size_t d_prefix = d_ranks + align256((size_t)n * std::max<size_t>(npct, 1) * 4);
+    const size_t d_end = d_prefix + align256((size_t)BK_COUNT * (n + 1) * 8);
+    int rc = ensure_ws(c, d_end);
+    if (rc != VLG_OK) return rc;
+    char *base = (char *)c->ws;
+
+    // descriptors in pinned host memory, reused once the previous upload is done
+    const size_t dbytes = d_end - d_imgs;
+    if (c->desc_done) HIP_TRY(hipEventSynchronize(c->desc_done));
+    if (c->desc_host_size < dbytes) {
+        if (c->desc_host) HIP_TRY(hipHostFree(c->desc_host));
+        c->desc_host = nullptr;
+        c->desc_host_size = 0;
+        HIP_TRY(hipHostMalloc(&c->desc_host, dbytes, hipHostMallocDefault));
+        c->desc_host_size = dbytes;
+    }
+    if (!c->desc_done) HIP_TRY(hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming));
+    char *h = (char *)c->desc_host;
+    std::memset(h, 0, dbytes);
+    BImg *hi = (BImg *)h;
+    uint64_t **ho = (uint64_t **)(h + (d_outs - d_imgs));
+    uint32_t *hr = (uint32_t *)(h + (d_ranks - d_imgs));
+    int64_t *hp = (int64_t *)(h + (d_prefix - d_imgs));
+    std::vector<const Step *> pct_step(npct, nullptr);
+    for (const Step &s : P.steps)
+        if (s.kind == SK::Pct) pct_step[(size_t)s.pct_out] = &s;
+    std::vector<uint64_t *> ext((size_t)n * nout);
+    for (int k = 0; k < n; k++) {
+        const vlg_image *im = imgs[idx[k]];
+        const Layout &L = lay[k];
+        char *wb = base + off[k];
+        BImg &d = hi[k];
+        d.g = geo[k];
+        d.img = (const char *)im->dev;
+        d.chan_bytes = (int64_t)im->H * im->pitch * (int64_t)im->esize();
+        d.ws = wb + L.off_slots;
+        d.mask_bytes = L.mask_bytes;
+        d.off_glab = L.off_glab - L.off_slots;
+        d.off_gflag = L.off_gflag - L.off_slots;
+        d.off_pct = L.off_pct - L.off_slots;
+        d.off_pctst = L.off_pctst - L.off_slots;
+        d.outs = (uint64_t *const *)(base + d_outs) + (size_t)k * nout;
+        d.ranks = (const uint32_t *)(base + d_ranks) + (size_t)k * std::max<size_t>(npct, 1);
+        const int64_t npix = (int64_t)im->H * im->W;
+        for (size_t p = 0; p < npct; p++)
+            hr[(size_t)k * std::max<size_t>(npct, 1) + p] = pct_step[p] ? pct_rank(pct_step[p]->q, npix) : 0u;
+        for (size_t o = 0; o < nout; o++) {
+            void *user = outs[(size_t)idx[k] * nout + o];
+            uint64_t *e = direct && user ? (uint64_t *)user : (uint64_t *)(wb + L.off_stage + o * L.mask_bytes);
+            ext[(size_t)k * nout + o] = e;
+            ho[(size_t)k * nout + o] = e;
+        }
+        for (int kind = 0; kind < BK_COUNT; kind++)
+            hp[(size_t)kind * (n + 1) + k + 1] = hp[(size_t)kind * (n + 1) + k] + batch_units(geo[k], kind, tbh);
+    }
+    HIP_TRY(hipMemcpyAsync(base + d_imgs, h, dbytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipEventRecord(c->desc_done, c->stream));
+
+    auto args = [&](int kind) {
+        BatchArgs a;
+        a.n = n;
+        a.dtype = dtype;
+        a.imgs = (const BImg *)(base + d_imgs);
+        a.prefix = (const int64_t *)(base + d_prefix) + (size_t)kind * (n + 1);
+        return a;
+    };
+    auto units = [&](int kind) { return hp[(size_t)kind * (n + 1) + n]; };
+    auto bref = [](const Ref &r) { return BRef{r.slot, (uint32_t)(r.inv ? 1 : 0)}; };
+
+    auto enqueue_steps = [&]() -> int {
+        for (size_t si = 0; si < P.steps.size(); si++) {
+            const Step &s = P.steps[si];
+            hipError_t e = hipSuccess;
+            if (s.group >= 0) {
+                size_t sj = si;
+                while (sj + 1 < P.steps.size() && P.steps[sj + 1].group == s.group) sj++;
+                if (s.kind == SK::Logic) {
+                    BLogic b;
+                    std::memset(&b, 0, sizeof b);
+                    b.n = (int)(sj - si + 1);
+                    for (size_t k = si; k <= sj; k++) {
+                        const Step &t = P.steps[k];
+                        b.ops[k - si] = BLogicOp{bref(t.x), bref(t.y), t.op, t.inv_out, t.out};
+                    }
+                    e = launch_b_logic(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                } else {
+                    BNear b;
+                    std::memset(&b, 0, sizeof b);
+                    b.n = (int)(sj - si + 1);
+                    for (size_t k = si; k <= sj; k++) {
+                        const Step &t = P.steps[k];
+                        b.ops[k - si] = BNearOp{bref(t.x), bref(t.z), t.inv_out, t.op, t.out};
+                    }
+                    e = launch_b_near(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                }
+                if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+                si = sj;
+                continue;
+            }
+            switch (s.kind) {
+            case SK::Pct:
+                e = launch_b_percentile(c->stream, args(BK_ONE), units(BK_ONE), args(BK_PCTH), units(BK_PCTH), s.chan,
+                                        s.pct_out);
+                break;
+            case SK::Atoms: {
+                BAtoms a;
+                std::memset(&a, 0, sizeof a);
+                a.chan = s.chan;
+                a.n = s.natoms;
+                for (int j = 0; j < s.natoms; j++) {
+                    a.cmp[j] = s.atoms[j].cmp;
+                    a.thr[j] = s.atoms[j].thr;
+                    a.pct[j] = s.atoms[j].use_pct ? s.atoms[j].pct : -1;
+                    a.out[j] = s.atoms[j].out;
+                }
+                e = launch_b_atoms(c->stream, args(BK_WORDS), units(BK_WORDS), a);
+                break;
+            }
+            case SK::Logic: {
+                BLogic b;
+                std::memset(&b, 0, sizeof b);
+                b.n = 1;
+                b.ops[0] = BLogicOp{bref(s.x), bref(s.y), s.op, s.inv_out, s.out};
+                e = launch_b_logic(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                break;
+            }
+            case SK::Near: {
+                BNear b;
+                std::memset(&b, 0, sizeof b);
+                b.n = 1;
+                b.ops[0] = BNearOp{bref(s.x), bref(s.z), s.inv_out, s.op, s.out};
+                e = launch_b_near(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                break;
+            }
+            case SK::CclLocal:
+                e = launch_b_ccl_local(c->stream, args(BK_TILES), units(BK_TILES), tbh, bref(s.x), bref(s.y),
+                                       bref(s.z));
+                break;
+            case SK::CclMerge:
+                e = launch_b_ccl_merge(c->stream, args(BK_MERGE), units(BK_MERGE), tbh, bref(s.x));
+                break;
+            case SK::CclFlag:
+                e = launch_b_ccl_flag(c->stream, args(BK_BLOCKS), units(BK_BLOCKS));
+                break;
+            case SK::CclGather:
+                e = launch_b_ccl_gather(c->stream, args(BK_GATHER), units(BK_GATHER), bref(s.x), bref(s.y),
+                                        bref(s.z), s.user, s.out);
+                break;
+            case SK::CclReseed:
+                e = launch_b_ccl_reseed(c->stream, args(BK_BLOCKS), units(BK_BLOCKS), bref(s.x), s.user);
+                break;
+            }
+            if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        }
+        if (fmt == VLG_U8MASK) {
+            for (int k = 0; k < n; k++)
+                for (size_t o = 0; o < nout; o++) {
+                    void *user = outs[(size_t)idx[k] * nout + o];
+                    if (!user) continue;
+                    uint8_t *dst = where == VLG_DEVICE
+                                       ? (uint8_t *)user
+                                       : (uint8_t *)(base + off[k] + lay[k].off_u8 +
+                                                     o * align256((size_t)geo[k].H * geo[k].W));
+                    hipError_t e = launch_unpack(c->stream, geo[k], ext[(size_t)k * nout + o], dst);
+                    if (e != hipSuccess) return fail(VLG_EHIP, hipGetErrorString(e));
+                }
+        }
+        return VLG_OK;
+    };
+
+    if (c->mode == VLG_MODE_GRAPH) {
+        GraphKey key;
+        key.v = {(uintptr_t)0xBA7C, (uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)c->ws, (uintptr_t)tbh,
+                 (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)n};
+        for (int k = 0; k < n; k++) {
+            const vlg_image *im = imgs[idx[k]];
+            key.v.insert(key.v.end(), {(uintptr_t)im->dev, (uintptr_t)im->H, (uintptr_t)im->W,
+                                       (uintptr_t)im->dtype, (uintptr_t)im->pitch});
+            for (size_t o = 0; o < nout; o++) key.v.push_back((uintptr_t)outs[(size_t)idx[k] * nout + o]);
+        }
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            int r = enqueue_steps();
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(c->stream, &graph);
+            if (r != VLG_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return r;
+            }
+            if (e != hipSuccess) return fail(VLG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(VLG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            if (c->graphs.size() >= 64) c->drop_graphs();
+            it = c->graphs.emplace(key, exec).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second, c->stream));
+    } else {
+        rc = enqueue_steps();
+        if (rc != VLG_OK) return rc;
+    }
+
+    if (where == VLG_HOST) {
+        for (int k = 0; k < n; k++)
+            for (size_t o = 0; o < nout; o++) {
+                void *user = outs[(size_t)idx[k] * nout + o];
+                if (!user) continue;
+                if (fmt == VLG_PACKED64)
+                    HIP_TRY(hipMemcpyAsync(user, ext[(size_t)k * nout + o], (size_t)geo[k].nwords * 8,
+                                           hipMemcpyDeviceToHost, c->stream));
+                else
+                    HIP_TRY(hipMemcpyAsync(user,
+                                           base + off[k] + lay[k].off_u8 + o * align256((size_t)geo[k].H * geo[k].W),
+                                           (size_t)geo[k].H * geo[k].W, hipMemcpyDeviceToHost, c->stream));
+            }
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return VLG_OK;
+}
+
 }  // namespace
 
 namespace vlg {
@@ -491,6 +762,8 @@ void vlg_destroy(vlg_ctx *c) {
     c->drop_graphs();
     if (c->ws && !c->ws_external) (void)hipFree(c->ws);
     if (c->counters) (void)hipFree(c->counters);
+    if (c->desc_host) (void)hipHostFree(c->desc_host);
+    if (c->desc_done) (void)hipEventDestroy(c->desc_done);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -657,13 +930,38 @@ int vlg_check_all(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, void 
 int vlg_check_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *imgs, int n, void *const *outs,
                     int fmt, int where) {
     if (!c || !cf || (!imgs && n > 0) || (!outs && n > 0) || n < 0) return fail(VLG_EINVAL, "null argument");
-    const size_t nout = cf->dag.outputs.size();
+    if (fmt != VLG_PACKED64 && fmt != VLG_U8MASK) return fail(VLG_EINVAL, "bad mask format");
+    if (where != VLG_HOST && where != VLG_DEVICE) return fail(VLG_EINVAL, "bad memory kind");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    const size_t nout = f->dag.outputs.size();
     for (int i = 0; i < n; i++) {
         if (!imgs[i]) return fail(VLG_EINVAL, "null image in batch");
-        int rc = vlg_check_all(c, cf, imgs[i], outs + (size_t)i * nout, fmt, where);
-        if (rc != VLG_OK) return rc;
+        if (f->max_chan >= imgs[i]->C)
+            return fail(VLG_ESHAPE, "image " + std::to_string(i) + " lacks channel " + std::to_string(f->max_chan));
+        if (imgs[i]->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
     }
-    return VLG_OK;
+    try {
+        if (c->mode == VLG_MODE_PEROP) {
+            // the per-operator baseline: one image after the other
+            for (int i = 0; i < n; i++) {
+                int rc = vlg_check_all(c, cf, imgs[i], outs + (size_t)i * nout, fmt, where);
+                if (rc != VLG_OK) return rc;
+            }
+            return VLG_OK;
+        }
+        DeviceGuard dg(c->device);
+        // one batched pass per pixel type; empty images have no units
+        for (int dt : {VLG_F32, VLG_U8}) {
+            std::vector<int> idx;
+            for (int i = 0; i < n; i++)
+                if (imgs[i]->dtype == dt) idx.push_back(i);
+            int rc = run_batch(c, f, imgs, idx, outs, fmt, where);
+            if (rc != VLG_OK) return rc;
+        }
+        return VLG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(VLG_ENOMEM, "out of host memory");
+    }
 }
 
 int vlg_ccl_labels(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, int32_t *labels_dev) {
@@ -748,7 +1046,10 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
             kinds.push_back(k);
             it = kinds.end() - 1;
         }
-        it->launches += iters;
+        // a batched group is one launch, timed as a whole on its last step
+        const bool grouped_not_last = P.steps[si].group >= 0 && si + 1 < P.steps.size() &&
+                                      P.steps[si + 1].group == P.steps[si].group;
+        if (!grouped_not_last) it->launches += iters;
         it->ms += ms[si];
         it->bytes += iters * algorithmic_bytes(P.steps[si], g, img->dtype, tuning_for(c, img->H, img->W).ccl_tbh);
     }

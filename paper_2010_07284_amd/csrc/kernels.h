@@ -91,6 +91,77 @@ hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork 
 hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint8_t *out);
 hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v);
 
+
+// ------------------------------------------------------------------ batches
+// One launch per schedule step for a whole batch of images of different
+// sizes.  Every image has a descriptor in device memory; a kernel walks a
+// global unit space (the concatenation of every image's units, by a prefix
+// array per unit kind) with a persistent grid.
+struct BImg {
+    Geo g;
+    const char *img;        // channel 0
+    int64_t chan_bytes;     // bytes per channel
+    char *ws;               // this image's workspace: mask slots, labelling, percentiles
+    uint64_t mask_bytes;    // slot stride
+    uint64_t off_glab, off_gflag, off_pct, off_pctst;
+    uint64_t *const *outs;  // packed output buffer per external slot
+    const uint32_t *ranks;  // percentile rank per percentile slot
+};
+
+// A mask operand of a batched step: slot id (>= 0 workspace slot, <= -2
+// external output, -1 none) and complement flag, resolved per image.
+struct BRef {
+    int32_t slot;
+    uint32_t inv;
+};
+
+enum BatchKind { BK_WORDS = 0, BK_TILES, BK_MERGE, BK_BLOCKS, BK_GATHER, BK_PCTH, BK_ONE, BK_COUNT };
+
+struct BatchArgs {
+    int n;
+    int dtype;                // image pixel type (all images of a batch share it)
+    const BImg *imgs;
+    const int64_t *prefix;    // [n+1] units of the launch's kind, prefix sums
+};
+
+struct BAtoms {
+    int chan, n;
+    uint8_t cmp[kMaxAtomsPerLaunch];
+    float thr[kMaxAtomsPerLaunch];
+    int32_t pct[kMaxAtomsPerLaunch];  // percentile slot or -1
+    int32_t out[kMaxAtomsPerLaunch];
+};
+struct BLogicOp {
+    BRef x, y;
+    int32_t op, inv_out, out;
+};
+struct BLogic {
+    int n;
+    BLogicOp ops[kBatchMax];
+};
+struct BNearOp {
+    BRef x, z;
+    int32_t inv_out, zop, out;
+};
+struct BNear {
+    int n;
+    BNearOp ops[kBatchMax];
+};
+
+// units of each kind for one image (host side)
+int64_t batch_units(const Geo &g, int kind, int tbh);
+
+hipError_t launch_b_atoms(hipStream_t s, const BatchArgs &a, int64_t total, const BAtoms &op);
+hipError_t launch_b_logic(hipStream_t s, const BatchArgs &a, int64_t total, const BLogic &op);
+hipError_t launch_b_near(hipStream_t s, const BatchArgs &a, int64_t total, const BNear &op);
+hipError_t launch_b_ccl_local(hipStream_t s, const BatchArgs &a, int64_t total, int tbh, BRef b, BRef y, BRef z);
+hipError_t launch_b_ccl_merge(hipStream_t s, const BatchArgs &a, int64_t total, int tbh, BRef b);
+hipError_t launch_b_ccl_flag(hipStream_t s, const BatchArgs &a, int64_t total);
+hipError_t launch_b_ccl_gather(hipStream_t s, const BatchArgs &a, int64_t total, BRef b, BRef y, BRef z, int user,
+                               int32_t out);
+hipError_t launch_b_ccl_reseed(hipStream_t s, const BatchArgs &a, int64_t total, BRef sm, int user);
+hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t total_one, const BatchArgs &hist,
+                               int64_t total_hist, int chan, int pct);
 }  // namespace vlg
 
 namespace vlg {

@@ -10,12 +10,19 @@
 // tile-local pass in LDS followed by a global merge of tile borders with
 // atomicMin hooking, so it needs a fixed number of launches and no host-side
 // termination check.
+//
+// Every operator is written once as a per-unit device function; single-image
+// kernels walk one image's units, batch kernels walk the units of many
+// images of different sizes through per-image descriptors.
 #include "kernels.h"
 
 namespace vlg {
 namespace {
 
 constexpr int kThreads = 256;
+// channel elements per batched histogram unit: large enough that flushing a
+// workgroup's LDS histogram (up to 2048 bins) stays small next to the reads
+constexpr int64_t kPctUnit = 65536;
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t shift) {
     return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> shift);
@@ -30,6 +37,8 @@ __device__ __forceinline__ bool is_last_col(const Geo &g, int64_t i) {
     return (uint32_t)i - row * (uint32_t)g.wpr == (uint32_t)(g.wpr - 1);
 }
 
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
 int grid_for(int64_t n, int per_block, int cap) {
     int64_t b = (n + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -37,48 +46,68 @@ int grid_for(int64_t n, int per_block, int cap) {
     return (int)b;
 }
 
+// ------------------------------------------------------------------ batches
+// image of global unit u: the largest i with prefix[i] <= u
+__device__ __forceinline__ int find_img(const int64_t *prefix, int n, int64_t u) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= u) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t *bptr(const BImg &d, int32_t slot) {
+    if (slot == -1) return nullptr;
+    if (slot <= -2) return d.outs[-2 - slot];
+    return (uint64_t *)(d.ws + (uint64_t)slot * d.mask_bytes);
+}
+
+__device__ __forceinline__ MRef bref(const BImg &d, const BRef &r) {
+    MRef m;
+    m.p = bptr(d, r.slot);
+    m.inv = r.inv ? ~0ull : 0ull;
+    return m;
+}
+
 // ------------------------------------------------------------------ Boolean
 // out = ((x ^ x.inv) OP (y ^ y.inv)) ^ inv_out, OP = and (op 0) / or (op 1).
-__global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int op, uint64_t inv_out,
-                                                    uint64_t *__restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
-        uint64_t a = ldm(x, i), b = ldm(y, i);
-        uint64_t r = (op ? (a | b) : (a & b)) ^ inv_out;
-        if (is_last_col(g, i)) r &= g.tail;
-        out[i] = r;
-    }
+__device__ __forceinline__ void logic_word(const Geo &g, const MRef &x, const MRef &y, int op, uint64_t inv_out,
+                                           uint64_t *out, int64_t i) {
+    const uint64_t a = ldm(x, i), b = ldm(y, i);
+    uint64_t r = (op ? (a | b) : (a & b)) ^ inv_out;
+    if (is_last_col(g, i)) r &= g.tail;
+    out[i] = r;
 }
 
 // ------------------------------------------------------------------ near
-// out = (N(x) ^ inv_out) OP z, OP = and (zop 0) / or (zop 1).  N over the in-image 3x3 block: horizontal
-// dilation inside a word with the edge bits of the neighbouring words, then the
-// OR of three rows.  Complemented inputs have their padding bits cleared first
-// so nothing leaks in from beyond the right border.
-__global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z, int zop,
-                                                   uint64_t *__restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
-        const uint32_t y = fdiv((uint32_t)i, g.wpr_mul, g.wpr_shift);
-        const int32_t w = (int32_t)((uint32_t)i - y * (uint32_t)g.wpr);
-        const bool last = w == g.wpr - 1;
-        uint64_t acc = 0;
+// out = (N(x) ^ inv_out) OP z, OP = and (zop 0) / or (zop 1).  N over the
+// in-image 3x3 block: horizontal dilation inside a word with the edge bits of
+// the neighbouring words, then the OR of three rows.  Complemented inputs have
+// their padding bits cleared first so nothing leaks in from beyond the right
+// border.
+__device__ __forceinline__ void near_word(const Geo &g, const MRef &x, uint64_t inv_out, const MRef &z, int zop,
+                                          uint64_t *out, int64_t i) {
+    const uint32_t y = fdiv((uint32_t)i, g.wpr_mul, g.wpr_shift);
+    const int32_t w = (int32_t)((uint32_t)i - y * (uint32_t)g.wpr);
+    const bool last = w == g.wpr - 1;
+    uint64_t acc = 0;
 #pragma unroll
-        for (int dy = -1; dy <= 1; dy++) {
-            const int yy = (int)y + dy;
-            if (yy < 0 || yy >= g.H) continue;
-            const int64_t base = (int64_t)yy * g.wpr + w;
-            uint64_t c = ldm(x, base);
-            if (last) c &= g.tail;
-            const uint64_t l = w > 0 ? ldm(x, base - 1) : 0ull;
-            const uint64_t r = last ? 0ull : ldm(x, base + 1);
-            acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
-        }
-        const uint64_t zz = ldm(z, i);
-        uint64_t res = zop ? ((acc ^ inv_out) | zz) : ((acc ^ inv_out) & zz);
-        if (last) res &= g.tail;
-        out[i] = res;
+    for (int dy = -1; dy <= 1; dy++) {
+        const int yy = (int)y + dy;
+        if (yy < 0 || yy >= g.H) continue;
+        const int64_t base = (int64_t)yy * g.wpr + w;
+        uint64_t c = ldm(x, base);
+        if (last) c &= g.tail;
+        const uint64_t l = w > 0 ? ldm(x, base - 1) : 0ull;
+        const uint64_t r = last ? 0ull : ldm(x, base + 1);
+        acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
     }
+    const uint64_t zz = ldm(z, i);
+    uint64_t res = zop ? ((acc ^ inv_out) | zz) : ((acc ^ inv_out) & zz);
+    if (last) res &= g.tail;
+    out[i] = res;
 }
 
 // ------------------------------------------------------------------ atoms
@@ -120,40 +149,36 @@ __device__ __forceinline__ uint64_t atom_words(const float (&v)[64], float t) {
 }
 #undef VLG_ATOM4
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__ img, AtomLaunch a) {
-    __shared__ float sthr[kMaxAtomsPerLaunch];
-    if (threadIdx.x < a.n)
-        sthr[threadIdx.x] = a.thr_dev[threadIdx.x] ? *a.thr_dev[threadIdx.x] : a.thr[threadIdx.x];
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
-    const int64_t ntasks = (g.nwords + 63) / 64;
-    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves) {
-        const int64_t w0 = t * 64;
-        const int nw = (int)((g.nwords - w0) < 64 ? (g.nwords - w0) : 64);
-        const T *src = img + w0 * 64 + lane;
-        float v[64];
-        if (nw == 64) {
+// One wave task: words [64 t, 64 t + 64) of image channel img, for atoms
+// 0..n-1 with thresholds sthr (LDS) and comparisons cmp; outf(j) is atom j's
+// output mask.
+template <typename T, typename OutF>
+__device__ __forceinline__ void atoms_task(const Geo &g, const T *__restrict__ img, int n, const uint8_t *cmp,
+                                           const float *sthr, OutF outf, int64_t t) {
+    const int lane = lane_id();
+    const int64_t w0 = t * 64;
+    const int nw = (int)((g.nwords - w0) < 64 ? (g.nwords - w0) : 64);
+    const T *src = img + w0 * 64 + lane;
+    float v[64];
+    if (nw == 64) {
 #pragma unroll
-            for (int k = 0; k < 64; k++) v[k] = (float)src[k * 64];
-        } else {
+        for (int k = 0; k < 64; k++) v[k] = (float)src[k * 64];
+    } else {
 #pragma unroll
-            for (int k = 0; k < 64; k++) v[k] = k < nw ? (float)src[k * 64] : 0.f;
+        for (int k = 0; k < 64; k++) v[k] = k < nw ? (float)src[k * 64] : 0.f;
+    }
+    const int64_t wi = w0 + lane;
+    const uint64_t keep = (lane < nw && is_last_col(g, wi)) ? g.tail : ~0ull;
+    for (int j = 0; j < n; j++) {
+        const float th = sthr[j];
+        uint64_t w;
+        switch (cmp[j]) {
+        case 0: w = atom_words<0>(v, th); break;
+        case 1: w = atom_words<1>(v, th); break;
+        case 2: w = atom_words<2>(v, th); break;
+        default: w = atom_words<3>(v, th); break;
         }
-        const int64_t wi = w0 + lane;
-        const uint64_t keep = (lane < nw && is_last_col(g, wi)) ? g.tail : ~0ull;
-        for (int j = 0; j < a.n; j++) {
-            const float th = sthr[j];
-            uint64_t w;
-            switch (a.cmp[j]) {
-            case 0: w = atom_words<0>(v, th); break;
-            case 1: w = atom_words<1>(v, th); break;
-            case 2: w = atom_words<2>(v, th); break;
-            default: w = atom_words<3>(v, th); break;
-            }
-            if (lane < nw) a.out[j][wi] = w & keep;
-        }
+        if (lane < nw) outf(j)[wi] = w & keep;
     }
 }
 
@@ -246,9 +271,7 @@ __device__ __forceinline__ uint32_t block_bits_g(const Geo &g, const MRef &b, in
     return (uint32_t)((t >> sh) & 3) | ((uint32_t)((u >> sh) & 3) << 2);
 }
 
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-
-// Tile-local labelling of b: TBH block rows x 64 block columns (32*TBH x 128
+// Tile-local labelling of b: TBH block rows x 64 block columns (2*TBH x 128
 // pixels) per workgroup of four waves.  A wave takes one block row at a time,
 // one lane per block: horizontally connected blocks form runs, found with a
 // ballot and labelled by their first block without any atomics.  Runs of
@@ -260,11 +283,10 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 // Output: glab[id] = global id of the block's tile-local root; gflag[id] of
 // a local root: bit0 = its component touches the tile border (only those can
 // be joined to other tiles), bit1 = it meets the seeds (seed set of labelling
-// user 0; bits 2..7 serve later users, see k_ccl_reseed).
+// user 0; bits 2..7 serve later users, see ccl_reseed).
 template <int TBH>
-__global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
-                                                        int32_t *__restrict__ glab,
-                                                        uint8_t *__restrict__ gflag) {
+__device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const MRef &z, int tx, int ty,
+                               int32_t *__restrict__ glab, uint8_t *__restrict__ gflag) {
     constexpr int TWW = 2, TR = 2 * TBH, TBW = 64, NB = TBH * TBW, NWAVES = kThreads / 64;
     __shared__ uint64_t sb[TR][TWW];
     __shared__ uint64_t sa[TR + 2][TWW + 2];
@@ -272,7 +294,6 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
     __shared__ uint8_t sbits[NB];
     __shared__ uint8_t srun[NB];
     __shared__ uint8_t sflag[NB];  // bit0 touches the tile border, bit1 seed
-    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const int r0 = ty * TR, wc0 = tx * TWW;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
 
@@ -392,188 +413,176 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
             gflag[id] = 0;
         }
     }
+    __syncthreads();  // the next tile of a persistent workgroup reuses the LDS
 }
 
-// Cross-tile merge: blocks on a tile's top row, left column and right column
-// unite with their earlier neighbours in other tiles.  A block skips a union
-// that its connected predecessor along the same border (left neighbour on the
-// top row, upper neighbour on a side column) already makes with the same
-// tile-local component.
+// Cross-tile merge, one border block per thread t of an image: blocks on a
+// tile's top row, left column and right column unite with their earlier
+// neighbours in other tiles.  A block skips a union that its connected
+// predecessor along the same border (left neighbour on the top row, upper
+// neighbour on a side column) already makes with the same tile-local
+// component.
 template <int TBH>
-__global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int ntiles, int32_t *glab,
-                                                        unsigned long long *counters) {
+__device__ void ccl_merge_one(const Geo &g, const MRef &b, int ntx, int64_t t, int32_t *glab, int &unions,
+                              int &tries) {
     constexpr int TBW = 64, PER = TBW + 2 * TBH;
-    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    int unions = 0, tries = 0;
-    if (t < (int64_t)ntiles * PER) {
-        const int tile = (int)(t / PER), k = (int)(t % PER);
-        const int tx = tile % ntx, ty = tile / ntx;
-        int lby, lbx, kind;
-        if (k < TBW) {
-            lby = 0; lbx = k; kind = 0;
-        } else if (k < TBW + TBH) {
-            lby = k - TBW; lbx = 0; kind = 1;
-        } else {
-            lby = k - TBW - TBH; lbx = TBW - 1; kind = 2;
-        }
-        const int by = ty * TBH + lby, bx = tx * TBW + lbx;
-        const uint32_t bits = (by < g.BH && bx < g.BW) ? block_bits_g(g, b, by, bx) : 0u;
-        const int id = by * g.BW + bx;
-        auto link = [&](int nid) {
-            unions++;
-            tries += g_unite(glab, id, nid);
-        };
-        if (bits && kind == 0 && by > 0) {
-            // contacts in the row above (other tile): UL, U, UR
-            int c[3] = {-1, -1, -1};
-            if (bx > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[0] = id - g.BW - 1;
-            if ((bits & 3) && (block_bits_g(g, b, by - 1, bx) & 12)) c[1] = id - g.BW;
-            if (bx + 1 < g.BW && (bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) c[2] = id - g.BW + 1;
-            // predecessor on this border row: the left block, if connected
-            int p[3] = {-1, -1, -1};
-            if (lbx > 0) {
-                const uint32_t lb = block_bits_g(g, b, by, bx - 1);
-                if ((bits & 5) && (lb & 10)) {
-                    if (bx - 1 > 0 && (lb & 1) && (block_bits_g(g, b, by - 1, bx - 2) & 8)) p[0] = id - g.BW - 2;
-                    if ((lb & 3) && (block_bits_g(g, b, by - 1, bx - 1) & 12)) p[1] = id - g.BW - 1;
-                    if ((lb & 2) && (block_bits_g(g, b, by - 1, bx) & 4)) p[2] = id - g.BW;
-                }
-            }
-            int pl[3];
-#pragma unroll
-            for (int j = 0; j < 3; j++) pl[j] = p[j] >= 0 ? glab[p[j]] : -2;
-            int done[3] = {-3, -3, -3};
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                if (c[j] < 0) continue;
-                const int lc = glab[c[j]];
-                if (lc == pl[0] || lc == pl[1] || lc == pl[2] || lc == done[0] || lc == done[1]) continue;
-                done[j < 2 ? j : 1] = lc;
-                link(c[j]);
-            }
-        } else if (bits && kind == 1 && bx > 0) {
-            // contacts in the column to the left (other tile): L, and UL below the top row
-            int c[2] = {-1, -1};
-            if ((bits & 5) && (block_bits_g(g, b, by, bx - 1) & 10)) c[0] = id - 1;
-            if (lby > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[1] = id - g.BW - 1;
-            // predecessor on this border column: the upper block, if connected
-            int p[2] = {-1, -1};
-            if (lby > 0) {
-                const uint32_t ub = block_bits_g(g, b, by - 1, bx);
-                if ((bits & 3) && (ub & 12)) {
-                    if ((ub & 5) && (block_bits_g(g, b, by - 1, bx - 1) & 10)) p[0] = id - g.BW - 1;
-                    if (lby > 1 && (ub & 1) && (block_bits_g(g, b, by - 2, bx - 1) & 8)) p[1] = id - 2 * g.BW - 1;
-                }
-            }
-            const int pl0 = p[0] >= 0 ? glab[p[0]] : -2, pl1 = p[1] >= 0 ? glab[p[1]] : -2;
-            int first = -3;
-#pragma unroll
-            for (int j = 0; j < 2; j++) {
-                if (c[j] < 0) continue;
-                const int lc = glab[c[j]];
-                if (lc == pl0 || lc == pl1 || lc == first) continue;
-                first = lc;
-                link(c[j]);
-            }
-        } else if (bits && kind == 2 && lby > 0 && bx + 1 < g.BW) {
-            // contact UR (tile to the right); redundant when the upper block is
-            // connected to this block and to that same block (its right neighbour)
-            if ((bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) {
-                const uint32_t ub = block_bits_g(g, b, by - 1, bx);
-                const uint32_t ur = block_bits_g(g, b, by - 1, bx + 1);
-                const bool covered = (bits & 3) && (ub & 12) && (ur & 5) && (ub & 10);
-                if (!covered) link(id - g.BW + 1);
-            }
-        }
+    const int nty = (g.BH + TBH - 1) / TBH;
+    if (t >= (int64_t)ntx * nty * PER) return;
+    const int tile = (int)(t / PER), k = (int)(t % PER);
+    const int tx = tile % ntx, ty = tile / ntx;
+    int lby, lbx, kind;
+    if (k < TBW) {
+        lby = 0; lbx = k; kind = 0;
+    } else if (k < TBW + TBH) {
+        lby = k - TBW; lbx = 0; kind = 1;
+    } else {
+        lby = k - TBW - TBH; lbx = TBW - 1; kind = 2;
     }
-    if (counters && (unions | tries)) {
-        atomicAdd(&counters[0], (unsigned long long)unions);
-        atomicAdd(&counters[1], (unsigned long long)(tries - unions));
+    const int by = ty * TBH + lby, bx = tx * TBW + lbx;
+    const uint32_t bits = (by < g.BH && bx < g.BW) ? block_bits_g(g, b, by, bx) : 0u;
+    const int id = by * g.BW + bx;
+    auto link = [&](int nid) {
+        unions++;
+        tries += g_unite(glab, id, nid);
+    };
+    if (bits && kind == 0 && by > 0) {
+        // contacts in the row above (other tile): UL, U, UR
+        int c[3] = {-1, -1, -1};
+        if (bx > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[0] = id - g.BW - 1;
+        if ((bits & 3) && (block_bits_g(g, b, by - 1, bx) & 12)) c[1] = id - g.BW;
+        if (bx + 1 < g.BW && (bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) c[2] = id - g.BW + 1;
+        // predecessor on this border row: the left block, if connected
+        int p[3] = {-1, -1, -1};
+        if (lbx > 0) {
+            const uint32_t lb = block_bits_g(g, b, by, bx - 1);
+            if ((bits & 5) && (lb & 10)) {
+                if (bx - 1 > 0 && (lb & 1) && (block_bits_g(g, b, by - 1, bx - 2) & 8)) p[0] = id - g.BW - 2;
+                if ((lb & 3) && (block_bits_g(g, b, by - 1, bx - 1) & 12)) p[1] = id - g.BW - 1;
+                if ((lb & 2) && (block_bits_g(g, b, by - 1, bx) & 4)) p[2] = id - g.BW;
+            }
+        }
+        int pl[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) pl[j] = p[j] >= 0 ? glab[p[j]] : -2;
+        int done[3] = {-3, -3, -3};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            if (c[j] < 0) continue;
+            const int lc = glab[c[j]];
+            if (lc == pl[0] || lc == pl[1] || lc == pl[2] || lc == done[0] || lc == done[1]) continue;
+            done[j < 2 ? j : 1] = lc;
+            link(c[j]);
+        }
+    } else if (bits && kind == 1 && bx > 0) {
+        // contacts in the column to the left (other tile): L, and UL below the top row
+        int c[2] = {-1, -1};
+        if ((bits & 5) && (block_bits_g(g, b, by, bx - 1) & 10)) c[0] = id - 1;
+        if (lby > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[1] = id - g.BW - 1;
+        // predecessor on this border column: the upper block, if connected
+        int p[2] = {-1, -1};
+        if (lby > 0) {
+            const uint32_t ub = block_bits_g(g, b, by - 1, bx);
+            if ((bits & 3) && (ub & 12)) {
+                if ((ub & 5) && (block_bits_g(g, b, by - 1, bx - 1) & 10)) p[0] = id - g.BW - 1;
+                if (lby > 1 && (ub & 1) && (block_bits_g(g, b, by - 2, bx - 1) & 8)) p[1] = id - 2 * g.BW - 1;
+            }
+        }
+        const int pl0 = p[0] >= 0 ? glab[p[0]] : -2, pl1 = p[1] >= 0 ? glab[p[1]] : -2;
+        int first = -3;
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            if (c[j] < 0) continue;
+            const int lc = glab[c[j]];
+            if (lc == pl0 || lc == pl1 || lc == first) continue;
+            first = lc;
+            link(c[j]);
+        }
+    } else if (bits && kind == 2 && lby > 0 && bx + 1 < g.BW) {
+        // contact UR (tile to the right); redundant when the upper block is
+        // connected to this block and to that same block (its right neighbour)
+        if ((bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) {
+            const uint32_t ub = block_bits_g(g, b, by - 1, bx);
+            const uint32_t ur = block_bits_g(g, b, by - 1, bx + 1);
+            const bool covered = (bits & 3) && (ub & 12) && (ur & 5) && (ub & 10);
+            if (!covered) link(id - g.BW + 1);
+        }
     }
 }
 
-// Point every border-touching tile-local root at its final root and carry its
+// Point a border-touching tile-local root at its final root and carry its
 // seed flag there.  Other local roots are final roots already.  A walker
 // writes only its own entry, so concurrent walkers never undo each other.
-__global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride) {
-        const uint8_t f = gflag[i];
-        if (!(f & 1)) continue;
-        int x = (int)i;
-        while (true) {
-            const int p = glab[x];
-            if (p == x) break;
-            x = p;
-        }
-        if (x != (int)i) {
-            glab[i] = x;
-            if (f & 2) gflag[x] = 3;  // final roots are border-touching local roots
-        }
+__device__ __forceinline__ void ccl_flag_one(int32_t *glab, uint8_t *gflag, int64_t i) {
+    const uint8_t f = gflag[i];
+    if (!(f & 1)) return;
+    int x = (int)i;
+    while (true) {
+        const int p = glab[x];
+        if (p == x) break;
+        x = p;
+    }
+    if (x != (int)i) {
+        glab[i] = x;
+        if (f & 2) gflag[x] = 3;  // final roots are border-touching local roots
     }
 }
 
 // out = (y & z) | Z, Z = the b-pixels whose component meets the seeds.  Every
 // foreground block points at a local root and every local root at its final
-// root, so the root is two loads away.
-__global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, MRef z,
-                                                         const int32_t *__restrict__ glab,
-                                                         const uint8_t *__restrict__ gflag, int user,
-                                                         uint64_t *__restrict__ out) {
-    // a wave takes 256 blocks of one block row (512 pixels = 8 words of two
-    // rows); lane l owns blocks 4l .. 4l+3, i.e. byte l of those 8 words
-    __shared__ uint64_t zw[kThreads / 64][8];
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
+// root, so the root is two loads away.  Wave task t: 256 blocks of one block
+// row (512 pixels = 8 words of two rows); lane l owns blocks 4l .. 4l+3, i.e.
+// byte l of those 8 words, assembled in this wave's 8 LDS words zw.
+__device__ __forceinline__ void ccl_gather_task(const Geo &g, const MRef &b, const MRef &y, const MRef &z,
+                                                const int32_t *__restrict__ glab, const uint8_t *__restrict__ gflag,
+                                                int user, uint64_t *__restrict__ out, int64_t t, uint64_t *zw) {
+    const int lane = lane_id();
     const int nq = (g.wpr + 7) / 8;
-    const int64_t ntasks = (int64_t)g.BH * nq;
-    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wv; t < ntasks; t += nwaves) {
-        const int by = (int)(t / nq), q = (int)(t - (int64_t)by * nq);
-        const int y0 = 2 * by;
-        const int w = 8 * q + (lane >> 3), sh = (lane & 7) * 8;  // word and bit offset of my byte
-        uint32_t top = 0, bot = 0;
-        if (w < g.wpr) {
-            const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
-            top = (uint32_t)(((ldm(b, (int64_t)y0 * g.wpr + w) & keep) >> sh) & 0xFF);
-            if (y0 + 1 < g.H) bot = (uint32_t)(((ldm(b, (int64_t)(y0 + 1) * g.wpr + w) & keep) >> sh) & 0xFF);
-        }
-        const uint32_t any = top | bot;
-        uint32_t zbyte = 0;
-        if (any) {
-            const int bx0 = 256 * q + 4 * lane;
-            const int64_t id0 = (int64_t)by * g.BW + bx0;
-            int lr[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) lr[j] = ((any >> (2 * j)) & 3) ? glab[id0 + j] : -1;
-            int r[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) r[j] = lr[j] >= 0 ? glab[lr[j]] : -1;
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (r[j] >= 0 && ((gflag[r[j]] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
-        }
-        ((uint8_t *)zw[wv])[lane] = (uint8_t)zbyte;
-        __builtin_amdgcn_wave_barrier();
-        if (lane < 16) {
-            const int yy = y0 + (lane >> 3), ww = 8 * q + (lane & 7);
-            if (yy < g.H && ww < g.wpr) {
-                const int64_t i = (int64_t)yy * g.wpr + ww;
-                const uint64_t keep = ww == g.wpr - 1 ? g.tail : ~0ull;
-                out[i] = ((ldm(y, i) & ldm(z, i)) | (ldm(b, i) & zw[wv][lane & 7])) & keep;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
+    const int by = (int)(t / nq), q = (int)(t - (int64_t)by * nq);
+    const int y0 = 2 * by;
+    const int w = 8 * q + (lane >> 3), sh = (lane & 7) * 8;  // word and bit offset of my byte
+    uint32_t top = 0, bot = 0;
+    if (w < g.wpr) {
+        const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+        top = (uint32_t)(((ldm(b, (int64_t)y0 * g.wpr + w) & keep) >> sh) & 0xFF);
+        if (y0 + 1 < g.H) bot = (uint32_t)(((ldm(b, (int64_t)(y0 + 1) * g.wpr + w) & keep) >> sh) & 0xFF);
     }
+    const uint32_t any = top | bot;
+    uint32_t zbyte = 0;
+    if (any) {
+        const int bx0 = 256 * q + 4 * lane;
+        const int64_t id0 = (int64_t)by * g.BW + bx0;
+        int lr[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) lr[j] = ((any >> (2 * j)) & 3) ? glab[id0 + j] : -1;
+        int r[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) r[j] = lr[j] >= 0 ? glab[lr[j]] : -1;
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (r[j] >= 0 && ((gflag[r[j]] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
+    }
+    ((uint8_t *)zw)[lane] = (uint8_t)zbyte;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 16) {
+        const int yy = y0 + (lane >> 3), ww = 8 * q + (lane & 7);
+        if (yy < g.H && ww < g.wpr) {
+            const int64_t i = (int64_t)yy * g.wpr + ww;
+            const uint64_t keep = ww == g.wpr - 1 ? g.tail : ~0ull;
+            out[i] = ((ldm(y, i) & ldm(z, i)) | (ldm(b, i) & zw[lane & 7])) & keep;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Mark, for labelling user `user`, the components of the current labelling
 // that meet the seed mask sm (= N(seeds) & b): bit 1+user of the root's flag
-// byte.  Runs after k_ccl_flag, so every block's root is two loads away.
-__global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const int32_t *__restrict__ glab,
-                                                         uint8_t *gflag, int user) {
-    const int bx = blockIdx.x * kThreads + threadIdx.x, by = blockIdx.y, lane = lane_id();
+// byte.  Runs after the flag pass, so every block's root is two loads away.
+// Called by every lane of a wave (block (by, bx), or valid = false).
+__device__ __forceinline__ void ccl_reseed_lane(const Geo &g, const MRef &sm, const int32_t *__restrict__ glab,
+                                                uint8_t *gflag, int user, bool valid, int by, int bx) {
+    const int lane = lane_id();
     int r = -1;
-    if (bx < g.BW && block_bits_g(g, sm, by, bx)) r = glab[glab[(int64_t)by * g.BW + bx]];
+    if (valid && block_bits_g(g, sm, by, bx)) r = glab[glab[(int64_t)by * g.BW + bx]];
     // neighbouring blocks mostly share a root: one atomic per distinct root
     // per wave (a giant component would otherwise serialise on one address)
     const uint32_t bit = 1u << (1 + user);
@@ -587,43 +596,91 @@ __global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const i
     }
 }
 
-// Up to kMaxBatch independent Boolean steps (or near steps) in one launch:
+// ------------------------------------------------------------------ single-image kernels
+
+__global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int op, uint64_t inv_out,
+                                                    uint64_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
+        logic_word(g, x, y, op, inv_out, out, i);
+}
+
+__global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z, int zop,
+                                                   uint64_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
+        near_word(g, x, inv_out, z, zop, out, i);
+}
+
+// Up to kBatchMax independent Boolean steps (or near steps) in one launch:
 // blockIdx.y selects the step.
 __global__ __launch_bounds__(kThreads) void k_logic_batch(Geo g, LogicBatch bt) {
     const LogicOp &o = bt.ops[blockIdx.y];
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
-        const uint64_t a = ldm(o.x, i), b = ldm(o.y, i);
-        uint64_t r = (o.op ? (a | b) : (a & b)) ^ o.inv_out;
-        if (is_last_col(g, i)) r &= g.tail;
-        o.out[i] = r;
-    }
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
+        logic_word(g, o.x, o.y, o.op, o.inv_out, o.out, i);
 }
 
 __global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt) {
     const NearOp &o = bt.ops[blockIdx.y];
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride) {
-        const uint32_t y = fdiv((uint32_t)i, g.wpr_mul, g.wpr_shift);
-        const int32_t w = (int32_t)((uint32_t)i - y * (uint32_t)g.wpr);
-        const bool last = w == g.wpr - 1;
-        uint64_t acc = 0;
-#pragma unroll
-        for (int dy = -1; dy <= 1; dy++) {
-            const int yy = (int)y + dy;
-            if (yy < 0 || yy >= g.H) continue;
-            const int64_t base = (int64_t)yy * g.wpr + w;
-            uint64_t c = ldm(o.x, base);
-            if (last) c &= g.tail;
-            const uint64_t l = w > 0 ? ldm(o.x, base - 1) : 0ull;
-            const uint64_t r = last ? 0ull : ldm(o.x, base + 1);
-            acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
-        }
-        const uint64_t zz = ldm(o.z, i);
-        uint64_t res = o.zop ? ((acc ^ o.inv_out) | zz) : ((acc ^ o.inv_out) & zz);
-        if (last) res &= g.tail;
-        o.out[i] = res;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
+        near_word(g, o.x, o.inv_out, o.z, o.zop, o.out, i);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__ img, AtomLaunch a) {
+    __shared__ float sthr[kMaxAtomsPerLaunch];
+    if (threadIdx.x < a.n)
+        sthr[threadIdx.x] = a.thr_dev[threadIdx.x] ? *a.thr_dev[threadIdx.x] : a.thr[threadIdx.x];
+    __syncthreads();
+    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    const int64_t ntasks = (g.nwords + 63) / 64;
+    auto outf = [&](int j) { return a.out[j]; };
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
+        atoms_task(g, img, a.n, a.cmp, sthr, outf, t);
+}
+
+template <int TBH>
+__global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
+                                                        int32_t *__restrict__ glab,
+                                                        uint8_t *__restrict__ gflag) {
+    ccl_local_tile<TBH>(g, b, y, z, blockIdx.x % ntx, blockIdx.x / ntx, glab, gflag);
+}
+
+template <int TBH>
+__global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int32_t *glab,
+                                                        unsigned long long *counters) {
+    int unions = 0, tries = 0;
+    ccl_merge_one<TBH>(g, b, ntx, (int64_t)blockIdx.x * kThreads + threadIdx.x, glab, unions, tries);
+    if (counters && (unions | tries)) {
+        atomicAdd(&counters[0], (unsigned long long)unions);
+        atomicAdd(&counters[1], (unsigned long long)(tries - unions));
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride)
+        ccl_flag_one(glab, gflag, i);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, MRef z,
+                                                         const int32_t *__restrict__ glab,
+                                                         const uint8_t *__restrict__ gflag, int user,
+                                                         uint64_t *__restrict__ out) {
+    __shared__ uint64_t zw[kThreads / 64][8];
+    const int wv = threadIdx.x >> 6;
+    const int64_t ntasks = (int64_t)g.BH * ((g.wpr + 7) / 8);
+    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wv; t < ntasks; t += nwaves)
+        ccl_gather_task(g, b, y, z, glab, gflag, user, out, t, zw[wv]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const int32_t *__restrict__ glab,
+                                                         uint8_t *gflag, int user) {
+    const int bx = blockIdx.x * kThreads + threadIdx.x, by = blockIdx.y;
+    ccl_reseed_lane(g, sm, glab, gflag, user, bx < g.BW, by, bx);
 }
 
 // Smallest row-major pixel index of each component, gathered at its root.
@@ -686,6 +743,118 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
+
+// ------------------------------------------------------------------ batch kernels
+// Persistent: workgroup u-loop over the launch's global units.  Units per image:
+//   BK_WORDS  256 mask words (logic, near; atoms: four 64-word wave tasks)
+//   BK_TILES  one labelling tile          BK_MERGE  256 border threads
+//   BK_BLOCKS 256 blocks                  BK_GATHER four 256-block wave tasks
+//   BK_PCTH   kPctUnit channel elements   BK_ONE    one per image
+
+#define VLG_BATCH_LOOP(A)                                                                    \
+    const int64_t total_ = (A).prefix[(A).n];                                               \
+    for (int64_t u_ = blockIdx.x; u_ < total_; u_ += gridDim.x)
+
+__global__ __launch_bounds__(kThreads) void kb_logic(BatchArgs a, BLogic ops) {
+    const BLogicOp &o = ops.ops[blockIdx.y];
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
+        if (i < d.g.nwords)
+            logic_word(d.g, bref(d, o.x), bref(d, o.y), o.op, o.inv_out ? ~0ull : 0ull, bptr(d, o.out), i);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void kb_near(BatchArgs a, BNear ops) {
+    const BNearOp &o = ops.ops[blockIdx.y];
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
+        if (i < d.g.nwords)
+            near_word(d.g, bref(d, o.x), o.inv_out ? ~0ull : 0ull, bref(d, o.z), o.zop, bptr(d, o.out), i);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
+    __shared__ float sthr[kMaxAtomsPerLaunch];
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        __syncthreads();  // the previous unit is done with sthr
+        if (threadIdx.x < op.n) {
+            const int p = op.pct[threadIdx.x];
+            sthr[threadIdx.x] = p >= 0 ? ((const float *)(d.ws + d.off_pct))[p] : op.thr[threadIdx.x];
+        }
+        __syncthreads();
+        const T *img = (const T *)(d.img + (int64_t)op.chan * d.chan_bytes);
+        const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + (threadIdx.x >> 6);
+        auto outf = [&](int j) { return bptr(d, op.out[j]); };
+        if (t * 64 < d.g.nwords) atoms_task(d.g, img, op.n, op.cmp, sthr, outf, t);
+    }
+}
+
+template <int TBH>
+__global__ __launch_bounds__(kThreads) void kb_ccl_local(BatchArgs a, BRef b, BRef y, BRef z) {
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
+        const int tile = (int)(u_ - a.prefix[ii]);
+        ccl_local_tile<TBH>(d.g, bref(d, b), bref(d, y), bref(d, z), tile % ntx, tile / ntx,
+                            (int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag));
+    }
+}
+
+template <int TBH>
+__global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
+    int unions = 0, tries = 0;
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
+        ccl_merge_one<TBH>(d.g, bref(d, b), ntx, (u_ - a.prefix[ii]) * kThreads + threadIdx.x,
+                           (int32_t *)(d.ws + d.off_glab), unions, tries);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void kb_ccl_flag(BatchArgs a) {
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
+        if (i < (int64_t)d.g.BH * d.g.BW) ccl_flag_one((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), i);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void kb_ccl_gather(BatchArgs a, BRef b, BRef y, BRef z, int user, int32_t out) {
+    __shared__ uint64_t zw[kThreads / 64][8];
+    const int wv = threadIdx.x >> 6;
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + wv;
+        if (t < (int64_t)d.g.BH * ((d.g.wpr + 7) / 8))
+            ccl_gather_task(d.g, bref(d, b), bref(d, y), bref(d, z), (const int32_t *)(d.ws + d.off_glab),
+                            (const uint8_t *)(d.ws + d.off_gflag), user, bptr(d, out), t, zw[wv]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void kb_ccl_reseed(BatchArgs a, BRef sm, int user) {
+    VLG_BATCH_LOOP(a) {
+        const int ii = find_img(a.prefix, a.n, u_);
+        const BImg &d = a.imgs[ii];
+        const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
+        const bool valid = i < (int64_t)d.g.BH * d.g.BW;
+        const int by = valid ? (int)(i / d.g.BW) : 0, bx = valid ? (int)(i - (int64_t)by * d.g.BW) : 0;
+        ccl_reseed_lane(d.g, bref(d, sm), (const int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag),
+                        user, valid, by, bx);
+    }
+}
+
+#undef VLG_BATCH_LOOP
 
 int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
 int ntiles_y(const Geo &g, int tbh) { return (g.BH + tbh - 1) / tbh; }
@@ -754,9 +923,9 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
     const int64_t n = (int64_t)ntx * nty * (kTileBW + 2 * w.tbh);
     const int grid = (int)((n + kThreads - 1) / kThreads);
     switch (w.tbh) {
-    case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, ntx * nty, w.glab, w.counters); break;
-    case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, ntx * nty, w.glab, w.counters); break;
-    default: k_ccl_merge<32><<<grid, kThreads, 0, s>>>(g, b, ntx, ntx * nty, w.glab, w.counters); break;
+    case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, w.glab, w.counters); break;
+    case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, w.glab, w.counters); break;
+    default: k_ccl_merge<32><<<grid, kThreads, 0, s>>>(g, b, ntx, w.glab, w.counters); break;
     }
     return hipGetLastError();
 }
@@ -822,6 +991,91 @@ hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ batch launchers
+
+int64_t batch_units(const Geo &g, int kind, int tbh) {
+    if (g.nwords == 0) return 0;
+    const int64_t nb = (int64_t)g.BH * g.BW;
+    const int64_t ntiles = (int64_t)ntiles_x(g) * ntiles_y(g, tbh);
+    switch (kind) {
+    case BK_WORDS: return (g.nwords + kThreads - 1) / kThreads;
+    case BK_TILES: return ntiles;
+    case BK_MERGE: return (ntiles * (kTileBW + 2 * tbh) + kThreads - 1) / kThreads;
+    case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
+    case BK_GATHER: return ((int64_t)g.BH * ((g.wpr + 7) / 8) + 3) / 4;
+    case BK_PCTH: return ((int64_t)g.H * g.wpr * 64 + kPctUnit - 1) / kPctUnit;
+    case BK_ONE: return 1;
+    }
+    return 0;
+}
+
+static int persistent_grid(int64_t total) { return grid_for(total, 1, 2048); }
+
+hipError_t launch_b_atoms(hipStream_t s, const BatchArgs &a, int64_t total, const BAtoms &op) {
+    if (total == 0) return hipSuccess;
+    if (op.n < 1 || op.n > kMaxAtomsPerLaunch) return hipErrorInvalidValue;
+    if (a.dtype == 1) kb_atoms<uint8_t><<<persistent_grid(total), kThreads, 0, s>>>(a, op);
+    else kb_atoms<float><<<persistent_grid(total), kThreads, 0, s>>>(a, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_logic(hipStream_t s, const BatchArgs &a, int64_t total, const BLogic &op) {
+    if (total == 0 || op.n == 0) return hipSuccess;
+    dim3 grid(persistent_grid(total), op.n);
+    kb_logic<<<grid, kThreads, 0, s>>>(a, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_near(hipStream_t s, const BatchArgs &a, int64_t total, const BNear &op) {
+    if (total == 0 || op.n == 0) return hipSuccess;
+    dim3 grid(persistent_grid(total), op.n);
+    kb_near<<<grid, kThreads, 0, s>>>(a, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_ccl_local(hipStream_t s, const BatchArgs &a, int64_t total, int tbh, BRef b, BRef y, BRef z) {
+    if (total == 0) return hipSuccess;
+    const int grid = persistent_grid(total);
+    switch (tbh) {
+    case 8: kb_ccl_local<8><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
+    case 16: kb_ccl_local<16><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
+    case 32: kb_ccl_local<32><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_b_ccl_merge(hipStream_t s, const BatchArgs &a, int64_t total, int tbh, BRef b) {
+    if (total == 0) return hipSuccess;
+    const int grid = persistent_grid(total);
+    switch (tbh) {
+    case 8: kb_ccl_merge<8><<<grid, kThreads, 0, s>>>(a, b); break;
+    case 16: kb_ccl_merge<16><<<grid, kThreads, 0, s>>>(a, b); break;
+    case 32: kb_ccl_merge<32><<<grid, kThreads, 0, s>>>(a, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_b_ccl_flag(hipStream_t s, const BatchArgs &a, int64_t total) {
+    if (total == 0) return hipSuccess;
+    kb_ccl_flag<<<persistent_grid(total), kThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_ccl_gather(hipStream_t s, const BatchArgs &a, int64_t total, BRef b, BRef y, BRef z, int user,
+                               int32_t out) {
+    if (total == 0) return hipSuccess;
+    kb_ccl_gather<<<persistent_grid(total), kThreads, 0, s>>>(a, b, y, z, user, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_ccl_reseed(hipStream_t s, const BatchArgs &a, int64_t total, BRef sm, int user) {
+    if (total == 0) return hipSuccess;
+    kb_ccl_reseed<<<persistent_grid(total), kThreads, 0, s>>>(a, sm, user);
+    return hipGetLastError();
+}
+
 }  // namespace vlg
 
 // ------------------------------------------------------------------ percentile
@@ -848,7 +1102,7 @@ __device__ __forceinline__ float key_f32(uint32_t k) {
     return __uint_as_float(u);
 }
 
-__global__ void k_pct_init(PctState *st, uint32_t k) {
+__device__ void pct_init_wg(PctState *st, uint32_t k) {
     for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->hist[i] = 0;
     if (threadIdx.x == 0) {
         st->prefix = 0;
@@ -857,17 +1111,16 @@ __global__ void k_pct_init(PctState *st, uint32_t k) {
     }
 }
 
+// Histogram elements [i0, i1) of a channel stored with pitch wpr*64 into the
+// workgroup's LDS histogram h, then into the state.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restrict__ img, int64_t pitch,
-                                                       PctState *st, int shift, int bins) {
-    __shared__ uint32_t h[2048];
+__device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState *st, int shift, int bins,
+                               int64_t i0, int64_t i1, int64_t step, uint32_t *h) {
     for (int i = threadIdx.x; i < bins; i += kThreads) h[i] = 0;
     __syncthreads();
     const uint32_t prefix = st->prefix, mask = st->mask;
-    // the channel is stored with pitch wpr*64: element i is in row i / pitch
-    const int64_t n = (int64_t)g.H * pitch;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+    const int64_t pitch = (int64_t)g.wpr * 64;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += step) {
         const uint32_t row = fdiv((uint32_t)(i >> 6), g.wpr_mul, g.wpr_shift);
         if (i - (int64_t)row * pitch >= g.W) continue;
         const T v = img[i];
@@ -877,12 +1130,12 @@ __global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restric
     __syncthreads();
     for (int i = threadIdx.x; i < bins; i += kThreads)
         if (h[i]) atomicAdd(&st->hist[i], h[i]);
+    __syncthreads();
 }
 
 // one workgroup of 256 threads: find the bucket holding rank k
-__global__ __launch_bounds__(kThreads) void k_pct_select(PctState *st, int shift, int bins, int last,
-                                                         int is_u8, float *result) {
-    __shared__ uint32_t part[kThreads];
+__device__ void pct_select_wg(PctState *st, int shift, int bins, int last, int is_u8, float *result,
+                              uint32_t *part) {
     const int per = bins / kThreads;
     uint32_t local = 0;
     for (int j = 0; j < per; j++) local += st->hist[threadIdx.x * per + j];
@@ -901,26 +1154,99 @@ __global__ __launch_bounds__(kThreads) void k_pct_select(PctState *st, int shift
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 2048; i += kThreads) st->hist[i] = 0;
+    __syncthreads();
+}
+
+__global__ void k_pct_init(PctState *st, uint32_t k) { pct_init_wg(st, k); }
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restrict__ img, PctState *st, int shift,
+                                                       int bins) {
+    __shared__ uint32_t h[2048];
+    const int64_t n = (int64_t)g.H * g.wpr * 64;
+    pct_hist_range(g, img, st, shift, bins, (int64_t)blockIdx.x * kThreads, n, (int64_t)gridDim.x * kThreads, h);
+}
+
+__global__ __launch_bounds__(kThreads) void k_pct_select(PctState *st, int shift, int bins, int last, int is_u8,
+                                                         float *result) {
+    __shared__ uint32_t part[kThreads];
+    pct_select_wg(st, shift, bins, last, is_u8, result, part);
+}
+
+// batch variants: state and result of percentile slot p live in each image's workspace
+__device__ __forceinline__ PctState *bstate(const BImg &d, int p) {
+    return (PctState *)(d.ws + d.off_pctst + (uint64_t)p * kPctStateBytes);
+}
+
+__global__ void kb_pct_init(BatchArgs a, int p) {
+    for (int64_t u = blockIdx.x; u < a.prefix[a.n]; u += gridDim.x) {
+        const int ii = find_img(a.prefix, a.n, u);
+        pct_init_wg(bstate(a.imgs[ii], p), a.imgs[ii].ranks[p]);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, int p, int shift, int bins) {
+    __shared__ uint32_t h[2048];
+    for (int64_t u = blockIdx.x; u < a.prefix[a.n]; u += gridDim.x) {
+        const int ii = find_img(a.prefix, a.n, u);
+        const BImg &d = a.imgs[ii];
+        const int64_t i0 = (u - a.prefix[ii]) * kPctUnit;
+        const int64_t n = (int64_t)d.g.H * d.g.wpr * 64;
+        const int64_t i1 = i0 + kPctUnit < n ? i0 + kPctUnit : n;
+        pct_hist_range(d.g, (const T *)(d.img + (int64_t)chan * d.chan_bytes), bstate(d, p), shift, bins, i0, i1,
+                       kThreads, h);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void kb_pct_select(BatchArgs a, int p, int shift, int bins, int last,
+                                                          int is_u8) {
+    __shared__ uint32_t part[kThreads];
+    for (int64_t u = blockIdx.x; u < a.prefix[a.n]; u += gridDim.x) {
+        const int ii = find_img(a.prefix, a.n, u);
+        const BImg &d = a.imgs[ii];
+        pct_select_wg(bstate(d, p), shift, bins, last, is_u8, (float *)(d.ws + d.off_pct) + p, part);
+    }
 }
 
 }  // namespace
 
 hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, int64_t pitch,
                              uint32_t k, void *state, float *result) {
+    (void)pitch;  // always wpr*64
     PctState *st = (PctState *)state;
     k_pct_init<<<1, kThreads, 0, s>>>(st, k);
-    const int64_t n = (int64_t)g.H * pitch;
+    const int64_t n = (int64_t)g.H * g.wpr * 64;
     if (n == 0) return hipGetLastError();
     const int grid = grid_for(n, kThreads * 16, 2048);
     if (dtype == 1) {
-        k_pct_hist<uint8_t><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, pitch, st, 0, 256);
+        k_pct_hist<uint8_t><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, st, 0, 256);
         k_pct_select<<<1, kThreads, 0, s>>>(st, 0, 256, 1, 1, result);
         return hipGetLastError();
     }
     const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
     for (int p = 0; p < 3; p++) {
-        k_pct_hist<float><<<grid, kThreads, 0, s>>>(g, (const float *)chan, pitch, st, shifts[p], bins[p]);
+        k_pct_hist<float><<<grid, kThreads, 0, s>>>(g, (const float *)chan, st, shifts[p], bins[p]);
         k_pct_select<<<1, kThreads, 0, s>>>(st, shifts[p], bins[p], p == 2, 0, result);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t total_one, const BatchArgs &hist,
+                               int64_t total_hist, int chan, int pct) {
+    if (total_one == 0) return hipSuccess;
+    const int g1 = persistent_grid(total_one), gh = persistent_grid(total_hist);
+    kb_pct_init<<<g1, kThreads, 0, s>>>(one, pct);
+    if (hist.dtype == 1) {
+        kb_pct_hist<uint8_t><<<gh, kThreads, 0, s>>>(hist, chan, pct, 0, 256);
+        kb_pct_select<<<g1, kThreads, 0, s>>>(one, pct, 0, 256, 1, 1);
+        return hipGetLastError();
+    }
+    const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
+    for (int p = 0; p < 3; p++) {
+        kb_pct_hist<float><<<gh, kThreads, 0, s>>>(hist, chan, pct, shifts[p], bins[p]);
+        kb_pct_select<<<g1, kThreads, 0, s>>>(one, pct, shifts[p], bins[p], p == 2, 0);
     }
     return hipGetLastError();
 }

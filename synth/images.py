@@ -132,3 +132,45 @@ def batch_image(seed, index, h, w, channels=4):
 def digest(arr):
     """SHA-256 of an array's bytes (for input manifests)."""
     return hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()
+
+
+def phantom_image_device(seed, index, h, w, channels=4, sigma_noise=0.05, device="cuda"):
+    """Same recipe as `phantom_image`, generated directly in device memory
+    with torch (for batches too large to synthesise on the host in time).
+    Ellipse parameters come from ``default_rng([seed, index])``; the noise
+    from a torch generator on the device seeded from that rng.  The values
+    differ from `phantom_image`'s; copy an image to the host to hand the
+    identical array to the oracle."""
+    import torch
+    rng = np.random.default_rng([seed, index])
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(0, 2**62)))
+    out = torch.empty((channels, h, w), dtype=torch.float32, device=device)
+    side = min(h, w)
+    lo_ax, hi_ax = max(2.0, 0.03 * side), max(3.0, 0.3 * side)
+    s = float(sigma_noise)
+    for c in range(channels):
+        n = int(rng.integers(10, 41))
+        canvas = torch.zeros((h, w), dtype=torch.float32, device=device)
+        inten = rng.uniform(0.2, 1.0, n).astype(np.float32)
+        for i in range(n):
+            cy, cx = rng.uniform(0, h), rng.uniform(0, w)
+            a, b = rng.uniform(lo_ax, hi_ax), rng.uniform(lo_ax, hi_ax)
+            th = rng.uniform(0, np.pi)
+            r = max(a, b)
+            y0, y1 = max(0, int(cy - r) - 1), min(h, int(cy + r) + 2)
+            x0, x1 = max(0, int(cx - r) - 1), min(w, int(cx + r) + 2)
+            if y0 >= y1 or x0 >= x1:
+                continue
+            dy = torch.arange(y0, y1, device=device, dtype=torch.float64)[:, None] + (0.5 - cy)
+            dx = torch.arange(x0, x1, device=device, dtype=torch.float64)[None, :] + (0.5 - cx)
+            cs, sn = np.cos(th), np.sin(th)
+            u = (dx * cs + dy * sn) / a
+            v = (-dx * sn + dy * cs) / b
+            inside = u * u + v * v <= 1.0
+            view = canvas[y0:y1, x0:x1]
+            view.masked_fill_(inside, float(inten[i]))
+        n1 = torch.randn((h, w), generator=gen, device=device, dtype=torch.float32)
+        n2 = torch.randn((h, w), generator=gen, device=device, dtype=torch.float32)
+        out[c] = torch.sqrt((canvas + s * n1) ** 2 + (s * n2) ** 2)
+    return out
