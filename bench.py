@@ -30,6 +30,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+KERNEL_OF_KIND = {"atoms": "k_atoms<{t}>", "logic": "k_logic", "near": "k_near", "ccl_local": "k_ccl_local<{tbh}>",
+                  "ccl_merge": "k_ccl_merge<{tbh}>", "ccl_flag": "k_ccl_flag", "ccl_gather": "k_ccl_gather",
+                  "ccl_reseed": "k_ccl_reseed"}
+
+
+def measured_traffic(workload, kind, tbh, dtype="float"):
+    """HBM bytes per dispatch of the kernel behind `kind`, from the committed
+    rocprofv3 counter summary of `workload` (FETCH_SIZE and WRITE_SIZE scaled
+    by a 1 GiB copy), or None when there is none or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.json")
+    if kind not in KERNEL_OF_KIND or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    with open(os.path.join(ROOT, "paper_2010_07284_amd", "csrc", "kernels.hip"), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != rec.get("kernels_source_sha256"):
+            return None
+    k = rec["per_dispatch"].get(KERNEL_OF_KIND[kind].format(tbh=tbh, t=dtype))
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
+
+
 def time_mode(vlg, lib, ctx, f, im, arr, mode, steps, warmup):
     import torch
     vlg.set_mode(ctx, mode)
@@ -273,6 +296,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-image uneven batch measurement")
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-pixelwise", action="store_true", help="skip the streaming roofline of the pixel-wise kernels")
+    ap.add_argument("--hbm-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (scale for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the formula path has no multi-GPU mode (images or "
@@ -285,6 +310,16 @@ def main():
     import paper_2010_07284_amd as vlg
     from paper_2010_07284_amd import _lib
     from synth import formulas, images
+
+    if args.hbm_calibration:
+        src_t = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        log("[bench] calibration: 3 copies of 1 GiB (1 GiB read + 1 GiB written each)")
+        del src_t, dst_t
+        torch.cuda.empty_cache()
 
     S = args.size
     log(f"[bench] generating the {S}x{S} ellipse/maze image and the 100-node formula")
@@ -368,7 +403,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                      "avg_launch_us": round(dom_avg_ms * 1e3, 2),
-                     "bytes_per_launch": round(dom_bytes / dom_n), "traffic": None},
+                     "bytes_per_launch": round(dom_bytes / dom_n),
+                     "traffic": measured_traffic(f"ellipse_maze_{S}", dom_name, tile_rows)},
         "cpu_baseline": cpu,
     }
     if not args.no_chain:
