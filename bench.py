@@ -203,7 +203,23 @@ def bench_pixelwise(vlg, iters, side=46080):
                   "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"[bench] pixelwise {k:8s} {ms / n * 1e3:9.1f} us/launch  {gbs:7.1f} GB/s  "
             f"({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
-    del im, f, ctx
+    # reference: a plain device-to-device copy of 4 GiB (what streaming
+    # reaches on this device without any kernel of this library)
+    a = torch.empty(1 << 30, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    gbs = 2 * a.numel() * 4 / (ms / 1e3) / 1e9
+    res["device_copy_4GiB"] = {"avg_launch_us": round(ms * 1e3, 1), "achieved_gbs": round(gbs, 1),
+                               "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"[bench] pixelwise reference device copy: {gbs:7.1f} GB/s ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+    del a, b, im, f, ctx
     torch.cuda.empty_cache()
     return res
 

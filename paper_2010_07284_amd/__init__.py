@@ -73,6 +73,29 @@ def sync(ctx):
     _lib.call("vlg_sync", ctx.handle)
 
 
+class _Ordered:
+    """Stream ordering around a call that reads or writes caller tensors: the
+    context's stream first waits for torch's current stream (pending writes
+    to the outputs, e.g. a fill), and torch's current stream then waits for
+    the context's stream, so torch work issued later sees the results.  Both
+    are asynchronous."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+
+    def __enter__(self):
+        torch = _torch()
+        self.cur = torch.cuda.current_stream(self.ctx.device)
+        if self.cur.cuda_stream != self.ctx.stream.cuda_stream:
+            self.ctx.stream.wait_stream(self.cur)
+        return self
+
+    def __exit__(self, *exc):
+        if exc[0] is None and self.cur.cuda_stream != self.ctx.stream.cuda_stream:
+            self.cur.wait_stream(self.ctx.stream)
+        return False
+
+
 def set_mode(ctx, mode):
     _lib.call("vlg_set_mode", ctx.handle, MODES[mode] if isinstance(mode, str) else int(mode))
 
@@ -133,8 +156,9 @@ def check(ctx, f, img, output_index=0, out=None, fmt="packed"):
     if out is None:
         out = _alloc_out(img, fmt, f"cuda:{ctx.device}")
     where = 1 if out.is_cuda else 0
-    _lib.call("vlg_check", ctx.handle, f.handle, img.handle, output_index, ctypes.c_void_p(out.data_ptr()),
-              FMTS[fmt], where)
+    with _Ordered(ctx):
+        _lib.call("vlg_check", ctx.handle, f.handle, img.handle, output_index, ctypes.c_void_p(out.data_ptr()),
+                  FMTS[fmt], where)
     return out
 
 
@@ -145,7 +169,8 @@ def check_all(ctx, f, img, outs=None, fmt="packed"):
         outs = [_alloc_out(img, fmt, f"cuda:{ctx.device}") for _ in range(n)]
     where = 1 if outs[0].is_cuda else 0
     arr = (ctypes.c_void_p * n)(*[o.data_ptr() if o is not None else None for o in outs])
-    _lib.call("vlg_check_all", ctx.handle, f.handle, img.handle, arr, FMTS[fmt], where)
+    with _Ordered(ctx):
+        _lib.call("vlg_check_all", ctx.handle, f.handle, img.handle, arr, FMTS[fmt], where)
     return outs
 
 
@@ -160,7 +185,8 @@ def check_batch(ctx, f, imgs, outs=None, fmt="packed"):
     flat = [o.data_ptr() if o is not None else None for row in outs for o in row]
     arr = (ctypes.c_void_p * len(flat))(*flat)
     harr = (ctypes.c_void_p * len(imgs))(*[im.handle.value for im in imgs])
-    _lib.call("vlg_check_batch", ctx.handle, f.handle, harr, len(imgs), arr, FMTS[fmt], where)
+    with _Ordered(ctx):
+        _lib.call("vlg_check_batch", ctx.handle, f.handle, harr, len(imgs), arr, FMTS[fmt], where)
     return outs
 
 
@@ -170,8 +196,9 @@ def ccl_labels(ctx, mask, height, width, out=None):
     torch = _torch()
     if out is None:
         out = torch.empty((height, width), dtype=torch.int32, device=mask.device)
-    _lib.call("vlg_ccl_labels", ctx.handle, ctypes.c_void_p(mask.data_ptr()), height, width,
-              ctypes.c_void_p(out.data_ptr()))
+    with _Ordered(ctx):
+        _lib.call("vlg_ccl_labels", ctx.handle, ctypes.c_void_p(mask.data_ptr()), height, width,
+                  ctypes.c_void_p(out.data_ptr()))
     return out
 
 
@@ -242,6 +269,10 @@ class Server:
         self._keep = {}
 
     def submit(self, f, img, outs):
+        # slot streams live inside the library: pending torch writes to the
+        # output buffers (e.g. a fill) must be complete before they are handed over
+        if any(o is not None and o.is_cuda for o in outs):
+            _torch().cuda.current_stream(self.device).synchronize()
         arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() if o is not None else None for o in outs])
         rid = ctypes.c_int64()
         _lib.call("vlg_server_submit", self.handle, f.handle, img.handle, arr, ctypes.byref(rid))

@@ -21,6 +21,8 @@
 
 using namespace vlg;
 
+static_assert(kMaxPctSel == kMaxPctPerStep, "percentile selections per step");
+
 namespace {
 
 thread_local std::string g_err;
@@ -295,8 +297,16 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         }
         switch (s.kind) {
         case SK::Pct:
-            e = launch_percentile(c->stream, g, img->chan(s.chan), img->dtype, img->pitch, pct_rank(s.q, npix),
-                                  base + L.off_pctst + (size_t)s.pct_out * kPctStateBytes, pct + s.pct_out);
+        {
+            PctSel sel;
+            std::memset(&sel, 0, sizeof sel);
+            sel.n = s.npq;
+            for (int j = 0; j < s.npq; j++) {
+                sel.slot[j] = s.pct_out[j];
+                sel.k[j] = pct_rank(s.q[j], npix);
+            }
+            e = launch_percentile(c->stream, g, img->chan(s.chan), img->dtype, sel, base + L.off_pctst, pct);
+        }
             break;
         case SK::Atoms: {
             AtomLaunch a;
@@ -490,9 +500,10 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
     uint64_t **ho = (uint64_t **)(h + (d_outs - d_imgs));
     uint32_t *hr = (uint32_t *)(h + (d_ranks - d_imgs));
     int64_t *hp = (int64_t *)(h + (d_prefix - d_imgs));
-    std::vector<const Step *> pct_step(npct, nullptr);
+    std::vector<double> pct_q(npct, 0.0);
     for (const Step &s : P.steps)
-        if (s.kind == SK::Pct) pct_step[(size_t)s.pct_out] = &s;
+        if (s.kind == SK::Pct)
+            for (int j = 0; j < s.npq; j++) pct_q[(size_t)s.pct_out[j]] = s.q[j];
     std::vector<uint64_t *> ext((size_t)n * nout);
     for (int k = 0; k < n; k++) {
         const vlg_image *im = imgs[idx[k]];
@@ -512,7 +523,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
         d.ranks = (const uint32_t *)(base + d_ranks) + (size_t)k * std::max<size_t>(npct, 1);
         const int64_t npix = (int64_t)im->H * im->W;
         for (size_t p = 0; p < npct; p++)
-            hr[(size_t)k * std::max<size_t>(npct, 1) + p] = pct_step[p] ? pct_rank(pct_step[p]->q, npix) : 0u;
+            hr[(size_t)k * std::max<size_t>(npct, 1) + p] = pct_rank(pct_q[p], npix);
         for (size_t o = 0; o < nout; o++) {
             void *user = outs[(size_t)idx[k] * nout + o];
             uint64_t *e = direct && user ? (uint64_t *)user : (uint64_t *)(wb + L.off_stage + o * L.mask_bytes);
@@ -551,7 +562,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                         const Step &t = P.steps[k];
                         b.ops[k - si] = BLogicOp{bref(t.x), bref(t.y), t.op, t.inv_out, t.out};
                     }
-                    e = launch_b_logic(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                    e = launch_b_logic(c->stream, args(BK_LOGIC), units(BK_LOGIC), b);
                 } else {
                     BNear b;
                     std::memset(&b, 0, sizeof b);
@@ -560,7 +571,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                         const Step &t = P.steps[k];
                         b.ops[k - si] = BNearOp{bref(t.x), bref(t.z), t.inv_out, t.op, t.out};
                     }
-                    e = launch_b_near(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                    e = launch_b_near(c->stream, args(BK_NEAR), units(BK_NEAR), b);
                 }
                 if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
                 si = sj;
@@ -568,8 +579,14 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
             }
             switch (s.kind) {
             case SK::Pct:
+            {
+                PctSel sel;
+                std::memset(&sel, 0, sizeof sel);
+                sel.n = s.npq;
+                for (int j = 0; j < s.npq; j++) sel.slot[j] = s.pct_out[j];
                 e = launch_b_percentile(c->stream, args(BK_ONE), units(BK_ONE), args(BK_PCTH), units(BK_PCTH), s.chan,
-                                        s.pct_out);
+                                        sel);
+            }
                 break;
             case SK::Atoms: {
                 BAtoms a;
@@ -590,7 +607,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                 std::memset(&b, 0, sizeof b);
                 b.n = 1;
                 b.ops[0] = BLogicOp{bref(s.x), bref(s.y), s.op, s.inv_out, s.out};
-                e = launch_b_logic(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                e = launch_b_logic(c->stream, args(BK_LOGIC), units(BK_LOGIC), b);
                 break;
             }
             case SK::Near: {
@@ -598,7 +615,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                 std::memset(&b, 0, sizeof b);
                 b.n = 1;
                 b.ops[0] = BNearOp{bref(s.x), bref(s.z), s.inv_out, s.op, s.out};
-                e = launch_b_near(c->stream, args(BK_WORDS), units(BK_WORDS), b);
+                e = launch_b_near(c->stream, args(BK_NEAR), units(BK_NEAR), b);
                 break;
             }
             case SK::CclLocal:

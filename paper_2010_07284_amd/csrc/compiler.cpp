@@ -599,8 +599,9 @@ struct Lower {
         int32_t idx = npct++;
         Step &s = emit(SK::Pct);
         s.chan = chan;
-        s.q = q;
-        s.pct_out = idx;
+        s.npq = 1;
+        s.q[0] = q;
+        s.pct_out[0] = idx;
         pct_memo.emplace(key, idx);
         return idx;
     }
@@ -829,7 +830,7 @@ void schedule_fused(Lower &L) {
                 if (st.atoms[j].use_pct) rd.push_back(kPctBase + st.atoms[j].pct);
             }
         } else if (st.kind == SK::Pct) {
-            wr.push_back(kPctBase + st.pct_out);
+            for (int j = 0; j < st.npq; j++) wr.push_back(kPctBase + st.pct_out[j]);
         } else if (st.out != kNone) {
             wr.push_back(st.out);
         }
@@ -884,8 +885,24 @@ void schedule_fused(Lower &L) {
     auto same = [](const Ref &a, const Ref &b) { return a.slot == b.slot && a.inv == b.inv; };
     while (emitted < n) {
         int before = emitted;
+        const std::ptrdiff_t pct_round_start = (std::ptrdiff_t)out.size();
         for (int u : ready([&](const Unit &x) { return !x.ccl && (kind_of(x) == SK::Pct || kind_of(x) == SK::Atoms); })) {
-            out.push_back(L.steps[(size_t)units[(size_t)u].first]);
+            const Step &st = L.steps[(size_t)units[(size_t)u].first];
+            // ready percentiles of one channel share their passes over it
+            Step *merged = nullptr;
+            if (st.kind == SK::Pct)
+                for (Step &o : out)
+                    if (&o - out.data() >= pct_round_start && o.kind == SK::Pct && o.chan == st.chan &&
+                        o.npq + st.npq <= kMaxPctPerStep)
+                        merged = &o;
+            if (merged) {
+                for (int j = 0; j < st.npq; j++) {
+                    merged->q[merged->npq] = st.q[j];
+                    merged->pct_out[merged->npq++] = st.pct_out[j];
+                }
+            } else {
+                out.push_back(st);
+            }
             finish(u);
         }
         for (SK k : {SK::Logic, SK::Near}) {

@@ -51,7 +51,7 @@ struct Ref {
 };
 
 enum class SK : uint8_t {
-    Pct,        // percentile of channel `chan` at q -> pct scalar `pct_out`
+    Pct,        // percentiles of channel `chan` at q[0..npq) -> pct scalars pct_out[]
     Atoms,      // up to kMaxAtoms thresholds of channel `chan` -> masks (one read)
     Logic,      // out = ((x ^ x.inv) OP (y ^ y.inv)) ^ inv_out ; OP = and/or
     Near,       // out = (N(x ^ x.inv) ^ inv_out) & (z ^ z.inv)
@@ -64,6 +64,10 @@ enum class SK : uint8_t {
 };
 
 constexpr int kMaxAtoms = 32;
+
+// A percentile step selects up to this many quantiles of one channel in
+// shared passes over it.
+constexpr int kMaxPctPerStep = 4;
 
 struct AtomEntry {
     uint8_t cmp = CMP_GT;
@@ -80,8 +84,9 @@ struct Step {
     uint8_t op = 0;       // Logic: 0 = and, 1 = or
     uint8_t inv_out = 0;
     int32_t chan = 0;
-    double q = 0.0;
-    int32_t pct_out = -1;
+    int npq = 0;                     // Pct: ranks of channel `chan` selected together
+    double q[kMaxPctPerStep] = {};   //      quantiles
+    int32_t pct_out[kMaxPctPerStep] = {-1, -1, -1, -1};  // their percentile scalars
     int natoms = 0;
     AtomEntry atoms[kMaxAtoms];
     int32_t user = 0;     // CclGather / CclReseed: which seed set of the labelling

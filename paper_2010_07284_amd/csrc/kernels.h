@@ -27,6 +27,19 @@ struct Geo {
 
 Geo make_geo(int H, int W);
 
+// near works on bands of rows 64 words wide: the band height grows with the
+// image (4 .. 32 rows) while at least 2048 bands remain to fill the chip
+__host__ __device__ inline int near_band_rows(const Geo &g) {
+    const int64_t rows = (int64_t)g.H * ((g.wpr + 63) / 64);
+    int R = 4;
+    while (R < 32 && rows / (2 * R) >= 2048) R *= 2;
+    return R;
+}
+__host__ __device__ inline int64_t near_tasks(const Geo &g) {
+    const int R = near_band_rows(g);
+    return (int64_t)((g.H + R - 1) / R) * ((g.wpr + 63) / 64);
+}
+
 // Tile geometry of the reachability labelling: TBH x 64 blocks per tile
 // (2*TBH pixel rows x 128 pixel columns); TBH is tunable (8, 16 or 32).
 constexpr int kTileBW = 64;
@@ -115,7 +128,7 @@ struct BRef {
     uint32_t inv;
 };
 
-enum BatchKind { BK_WORDS = 0, BK_TILES, BK_MERGE, BK_BLOCKS, BK_GATHER, BK_PCTH, BK_ONE, BK_COUNT };
+enum BatchKind { BK_WORDS = 0, BK_LOGIC, BK_NEAR, BK_TILES, BK_MERGE, BK_BLOCKS, BK_GATHER, BK_PCTH, BK_ONE, BK_COUNT };
 
 struct BatchArgs {
     int n;
@@ -160,15 +173,24 @@ hipError_t launch_b_ccl_flag(hipStream_t s, const BatchArgs &a, int64_t total);
 hipError_t launch_b_ccl_gather(hipStream_t s, const BatchArgs &a, int64_t total, BRef b, BRef y, BRef z, int user,
                                int32_t out);
 hipError_t launch_b_ccl_reseed(hipStream_t s, const BatchArgs &a, int64_t total, BRef sm, int user);
+// up to kMaxPctSel quantiles of one channel: rank k[j] (single image; a batch
+// takes each image's ranks from its descriptor) into percentile slot slot[j]
+constexpr int kMaxPctSel = 4;
+struct PctSel {
+    int n;
+    int32_t slot[kMaxPctSel];
+    uint32_t k[kMaxPctSel];
+};
 hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t total_one, const BatchArgs &hist,
-                               int64_t total_hist, int chan, int pct);
+                               int64_t total_hist, int chan, const PctSel &sel);
 }  // namespace vlg
 
 namespace vlg {
-// Percentile (k-th smallest value of a channel, nearest rank) by radix select
-// over order-preserving uint32 keys.  `state` is kPctStateBytes of device
-// scratch; the result is written to *result.
+// Percentiles (k-th smallest value of a channel, nearest rank) by radix
+// select over order-preserving uint32 keys, several ranks of one channel per
+// pass over it.  Slot p has kPctStateBytes of device state at
+// states + p * kPctStateBytes; its value is written to results[p].
 constexpr size_t kPctStateBytes = 8448;
-hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, int64_t pitch,
-                             uint32_t k, void *state, float *result);
+hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, const PctSel &sel,
+                             void *states, float *results);
 }  // namespace vlg

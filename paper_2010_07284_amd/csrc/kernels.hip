@@ -28,8 +28,22 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t shif
     return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> shift);
 }
 
+// Pointers read from descriptors in memory have no known address space and
+// would be accessed with flat instructions, which also count against the LDS
+// wait counter; every mask, label and image access therefore goes through a
+// global-qualified pointer.
+#define VLG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ VLG_GLOBAL T *glb(T *p) {
+    return (VLG_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const VLG_GLOBAL T *glb(const T *p) {
+    return (const VLG_GLOBAL T *)p;
+}
+
 __device__ __forceinline__ uint64_t ldm(const MRef &r, int64_t i) {
-    return (r.p ? r.p[i] : 0ull) ^ r.inv;
+    return (r.p ? glb(r.p)[i] : 0ull) ^ r.inv;
 }
 
 __device__ __forceinline__ bool is_last_col(const Geo &g, int64_t i) {
@@ -58,9 +72,29 @@ __device__ __forceinline__ int find_img(const int64_t *prefix, int n, int64_t u)
     return lo;
 }
 
+// A workgroup of a persistent batch kernel takes a contiguous range of the
+// launch's global units, finds the image of its first unit by binary search
+// and then only steps forward (units of one image are consecutive).
+struct UnitRange {
+    const int64_t *prefix;
+    int64_t begin, end, next;
+    int ii;
+    __device__ UnitRange(const int64_t *p, int n) : prefix(p) {
+        const int64_t total = p[n];
+        begin = total * blockIdx.x / gridDim.x;
+        end = total * (blockIdx.x + 1) / gridDim.x;
+        ii = begin < end ? find_img(p, n, begin) : 0;
+        next = begin < end ? p[ii + 1] : 0;
+    }
+    __device__ __forceinline__ int img(int64_t u) {
+        while (u >= next) next = prefix[++ii + 1];
+        return ii;
+    }
+};
+
 __device__ __forceinline__ uint64_t *bptr(const BImg &d, int32_t slot) {
     if (slot == -1) return nullptr;
-    if (slot <= -2) return d.outs[-2 - slot];
+    if (slot <= -2) return glb(d.outs)[-2 - slot];
     return (uint64_t *)(d.ws + (uint64_t)slot * d.mask_bytes);
 }
 
@@ -73,41 +107,150 @@ __device__ __forceinline__ MRef bref(const BImg &d, const BRef &r) {
 
 // ------------------------------------------------------------------ Boolean
 // out = ((x ^ x.inv) OP (y ^ y.inv)) ^ inv_out, OP = and (op 0) / or (op 1).
-__device__ __forceinline__ void logic_word(const Geo &g, const MRef &x, const MRef &y, int op, uint64_t inv_out,
-                                           uint64_t *out, int64_t i) {
-    const uint64_t a = ldm(x, i), b = ldm(y, i);
-    uint64_t r = (op ? (a | b) : (a & b)) ^ inv_out;
-    if (is_last_col(g, i)) r &= g.tail;
-    out[i] = r;
+// A null operand is a constant (its inv); the loops below are specialised on
+// that once per launch so that every load is unconditional and a thread keeps
+// kLogicUnroll words in flight.
+constexpr int kLogicUnroll = 4;
+
+template <bool HX, bool HY>
+__device__ __forceinline__ void logic_span(const Geo &g, const uint64_t *__restrict__ xg, uint64_t xinv,
+                                           const uint64_t *__restrict__ yg, uint64_t yinv, int op, uint64_t inv_out,
+                                           uint64_t *__restrict__ outg, int64_t i0, int64_t stride, int64_t iend) {
+    const VLG_GLOBAL uint64_t *xp = glb(xg), *yp = glb(yg);
+    VLG_GLOBAL uint64_t *out = glb(outg);
+    for (int64_t i = i0; i < iend; i += kLogicUnroll * stride) {
+        uint64_t a[kLogicUnroll], b[kLogicUnroll];
+#pragma unroll
+        for (int k = 0; k < kLogicUnroll; k++) {
+            const int64_t j = min(i + k * stride, iend - 1);
+            a[k] = HX ? xp[j] ^ xinv : xinv;
+            b[k] = HY ? yp[j] ^ yinv : yinv;
+        }
+#pragma unroll
+        for (int k = 0; k < kLogicUnroll; k++) {
+            const int64_t j = i + k * stride;
+            uint64_t r = (op ? (a[k] | b[k]) : (a[k] & b[k])) ^ inv_out;
+            if (is_last_col(g, j)) r &= g.tail;
+            if (j < iend) out[j] = r;
+        }
+    }
+}
+
+// words i0, i0 + stride, ... below iend
+__device__ __forceinline__ void logic_words(const Geo &g, const MRef &x, const MRef &y, int op, uint64_t inv_out,
+                                            uint64_t *out, int64_t i0, int64_t stride, int64_t iend) {
+    if (x.p && y.p) logic_span<true, true>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
+    else if (x.p) logic_span<true, false>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
+    else if (y.p) logic_span<false, true>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
+    else logic_span<false, false>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
 }
 
 // ------------------------------------------------------------------ near
 // out = (N(x) ^ inv_out) OP z, OP = and (zop 0) / or (zop 1).  N over the
-// in-image 3x3 block: horizontal dilation inside a word with the edge bits of
-// the neighbouring words, then the OR of three rows.  Complemented inputs have
-// their padding bits cleared first so nothing leaks in from beyond the right
-// border.
-__device__ __forceinline__ void near_word(const Geo &g, const MRef &x, uint64_t inv_out, const MRef &z, int zop,
-                                          uint64_t *out, int64_t i) {
-    const uint32_t y = fdiv((uint32_t)i, g.wpr_mul, g.wpr_shift);
-    const int32_t w = (int32_t)((uint32_t)i - y * (uint32_t)g.wpr);
-    const bool last = w == g.wpr - 1;
-    uint64_t acc = 0;
-#pragma unroll
-    for (int dy = -1; dy <= 1; dy++) {
-        const int yy = (int)y + dy;
-        if (yy < 0 || yy >= g.H) continue;
-        const int64_t base = (int64_t)yy * g.wpr + w;
-        uint64_t c = ldm(x, base);
-        if (last) c &= g.tail;
-        const uint64_t l = w > 0 ? ldm(x, base - 1) : 0ull;
-        const uint64_t r = last ? 0ull : ldm(x, base + 1);
-        acc |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
+// in-image 3x3 block, as a vertical sliding window: a wave owns 64
+// consecutive words of a band of rows and walks down it, loading every row
+// word once (the two edge lanes also load the word beyond the wave's edge),
+// taking the left and right neighbour words from the adjacent lanes, and
+// keeping the horizontally dilated rows y-1, y, y+1 in registers.  Each input
+// word is fetched once per band instead of three times (by the workgroups of
+// rows y-1, y, y+1, which sit on different XCDs with separate L2s).
+// Complemented inputs have their padding bits cleared first so nothing leaks
+// in from beyond the right border.
+// Loads are issued unconditionally from clamped addresses and masked
+// afterwards, so a chunk of CH rows has all its loads in flight at once.
+template <int CH, bool HZ>
+__device__ __forceinline__ void near_band(const Geo &g, const uint64_t *__restrict__ xg, uint64_t xinv,
+                                          uint64_t inv_out, const uint64_t *__restrict__ zg, uint64_t zinv, int zop,
+                                          uint64_t *__restrict__ outg, int64_t task, int R) {
+    const VLG_GLOBAL uint64_t *xp = glb(xg), *zp = glb(zg);
+    VLG_GLOBAL uint64_t *out = glb(outg);
+    const int lane = lane_id();
+    const int nstrips = (g.wpr + 63) >> 6;
+    const int64_t band = task / nstrips;
+    const int w = (int)(task - band * nstrips) * 64 + lane;
+    const bool valid = w < g.wpr, last = w == g.wpr - 1;
+    const int wc = valid ? w : g.wpr - 1;
+    const int nb = lane == 0 ? w - 1 : (lane == 63 ? w + 1 : -1);  // word beyond the wave's edge
+    const bool nbv = nb >= 0 && nb < g.wpr;
+    const int nbc = nbv ? nb : wc;
+    const uint64_t keep = last ? g.tail : ~0ull;
+    const int y0 = (int)band * R, y1 = min(y0 + R, g.H);
+    // raw loads of row y (clamped into the image) and their masking; the empty
+    // asm consumes every raw value of a chunk after all its loads are issued,
+    // which keeps the compiler from sinking a load into a conditional block
+    // (with a wait right behind it)
+    auto addr = [&](int y) { return (int64_t)min(max(y, 0), g.H - 1) * g.wpr; };
+    auto mask_c = [&](int y, int lim, uint64_t raw) {
+        return (y >= 0 && y <= lim && valid) ? ((raw ^ xinv) & keep) : 0ull;
+    };
+    auto mask_e = [&](int y, int lim, uint64_t raw) { return (y >= 0 && y <= lim && nbv) ? (raw ^ xinv) : 0ull; };
+    // horizontal dilation of one row: lanes beyond the row hold c = 0
+    auto hrow = [&](uint64_t c, uint64_t e) {
+        uint64_t l = __shfl_up(c, 1), r = __shfl_down(c, 1);
+        if (lane == 0) l = e;
+        if (lane == 63) r = e;
+        return c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
+    };
+    uint64_t hm, h0;
+    {
+        uint64_t rc0 = xp[addr(y0 - 1) + wc], re0 = xp[addr(y0 - 1) + nbc];
+        uint64_t rc1 = xp[addr(y0) + wc], re1 = xp[addr(y0) + nbc];
+        asm volatile("" : "+v"(rc0), "+v"(re0), "+v"(rc1), "+v"(re1));
+        hm = hrow(mask_c(y0 - 1, g.H - 1, rc0), mask_e(y0 - 1, g.H - 1, re0));
+        h0 = hrow(mask_c(y0, g.H - 1, rc1), mask_e(y0, g.H - 1, re1));
     }
-    const uint64_t zz = ldm(z, i);
-    uint64_t res = zop ? ((acc ^ inv_out) | zz) : ((acc ^ inv_out) & zz);
-    if (last) res &= g.tail;
-    out[i] = res;
+    const int lim = min(y1, g.H - 1);
+    for (int yb = y0; yb < y1; yb += CH) {
+        uint64_t c[CH], e[CH], zz[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const int64_t a = addr(yb + 1 + k);
+            c[k] = xp[a + wc];
+            e[k] = xp[a + nbc];
+            zz[k] = HZ ? zp[addr(yb + k) + wc] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if (HZ) asm volatile("" : "+v"(c[k]), "+v"(e[k]), "+v"(zz[k]));
+            else asm volatile("" : "+v"(c[k]), "+v"(e[k]));
+        }
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const uint64_t hp = hrow(mask_c(yb + 1 + k, lim, c[k]), mask_e(yb + 1 + k, lim, e[k]));
+            const uint64_t n = (hm | h0 | hp) ^ inv_out;
+            const uint64_t zv = HZ ? (zz[k] ^ zinv) : zinv;
+            const uint64_t res = (zop ? (n | zv) : (n & zv)) & keep;
+            if (valid && yb + k < y1) out[(int64_t)(yb + k) * g.wpr + w] = res;
+            hm = h0;
+            h0 = hp;
+        }
+    }
+}
+
+// N of a constant mask (x.p == nullptr) is that constant over the image.
+__device__ __noinline__ void near_const_band(const Geo &g, uint64_t xinv, uint64_t inv_out, const MRef &z, int zop,
+                                             uint64_t *out, int64_t task, int R) {
+    const int nstrips = (g.wpr + 63) >> 6;
+    const int64_t band = task / nstrips;
+    const int w = (int)(task - band * nstrips) * 64 + lane_id();
+    if (w >= g.wpr) return;
+    const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+    const int y0 = (int)band * R, y1 = min(y0 + R, g.H);
+    for (int y = y0; y < y1; y++) {
+        const int64_t i = (int64_t)y * g.wpr + w;
+        const uint64_t n = xinv ^ inv_out, zz = ldm(z, i);
+        out[i] = (zop ? (n | zz) : (n & zz)) & keep;
+    }
+}
+
+__device__ __forceinline__ void near_task(const Geo &g, const MRef &x, uint64_t inv_out, const MRef &z, int zop,
+                                          uint64_t *out, int64_t task) {
+    const int R = near_band_rows(g);
+    if (!x.p) near_const_band(g, x.inv, inv_out, z, zop, out, task, R);
+    else if (R == 4 && z.p) near_band<4, true>(g, x.p, x.inv, inv_out, z.p, z.inv, zop, out, task, R);
+    else if (R == 4) near_band<4, false>(g, x.p, x.inv, inv_out, z.p, z.inv, zop, out, task, R);
+    else if (z.p) near_band<8, true>(g, x.p, x.inv, inv_out, z.p, z.inv, zop, out, task, R);
+    else near_band<8, false>(g, x.p, x.inv, inv_out, z.p, z.inv, zop, out, task, R);
 }
 
 // ------------------------------------------------------------------ atoms
@@ -158,7 +301,7 @@ __device__ __forceinline__ void atoms_task(const Geo &g, const T *__restrict__ i
     const int lane = lane_id();
     const int64_t w0 = t * 64;
     const int nw = (int)((g.nwords - w0) < 64 ? (g.nwords - w0) : 64);
-    const T *src = img + w0 * 64 + lane;
+    const VLG_GLOBAL T *src = glb(img) + w0 * 64 + lane;
     float v[64];
     if (nw == 64) {
 #pragma unroll
@@ -178,7 +321,7 @@ __device__ __forceinline__ void atoms_task(const Geo &g, const T *__restrict__ i
         case 2: w = atom_words<2>(v, th); break;
         default: w = atom_words<3>(v, th); break;
         }
-        if (lane < nw) outf(j)[wi] = w & keep;
+        if (lane < nw) glb(outf(j))[wi] = w & keep;
     }
 }
 
@@ -234,7 +377,7 @@ __device__ void lds_unite(int *L, int a, int b) {
 // kernel); that costs retries, never correctness: every value ever stored in
 // L[x] is an ancestor of x (L[x] <= x), sets only grow, and a failed
 // atomicMin hands back the current parent, which is then united in turn.
-__device__ int g_find(int *L, int x) {
+__device__ int g_find(VLG_GLOBAL int *L, int x) {
     while (true) {
         const int p = L[x];
         if (p == x) return x;
@@ -245,7 +388,7 @@ __device__ int g_find(int *L, int x) {
     }
 }
 
-__device__ int g_unite(int *L, int a, int b) {
+__device__ int g_unite(VLG_GLOBAL int *L, int a, int b) {
     int tries = 0;
     while (true) {
         tries++;
@@ -257,7 +400,7 @@ __device__ int g_unite(int *L, int a, int b) {
             a = b;
             b = t;
         }
-        const int old = atomicMin(&L[a], b);
+        const int old = __hip_atomic_fetch_min(&L[a], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == a) return tries;
         a = old;
     }
@@ -286,7 +429,9 @@ __device__ __forceinline__ uint32_t block_bits_g(const Geo &g, const MRef &b, in
 // user 0; bits 2..7 serve later users, see ccl_reseed).
 template <int TBH>
 __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const MRef &z, int tx, int ty,
-                               int32_t *__restrict__ glab, uint8_t *__restrict__ gflag) {
+                               int32_t *__restrict__ glab_, uint8_t *__restrict__ gflag_) {
+    VLG_GLOBAL int32_t *glab = glb(glab_);
+    VLG_GLOBAL uint8_t *gflag = glb(gflag_);
     constexpr int TWW = 2, TR = 2 * TBH, TBW = 64, NB = TBH * TBW, NWAVES = kThreads / 64;
     __shared__ uint64_t sb[TR][TWW];
     __shared__ uint64_t sa[TR + 2][TWW + 2];
@@ -423,8 +568,9 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
 // neighbour on a side column) already makes with the same tile-local
 // component.
 template <int TBH>
-__device__ void ccl_merge_one(const Geo &g, const MRef &b, int ntx, int64_t t, int32_t *glab, int &unions,
+__device__ void ccl_merge_one(const Geo &g, const MRef &b, int ntx, int64_t t, int32_t *glab_, int &unions,
                               int &tries) {
+    VLG_GLOBAL int32_t *glab = glb(glab_);
     constexpr int TBW = 64, PER = TBW + 2 * TBH;
     const int nty = (g.BH + TBH - 1) / TBH;
     if (t >= (int64_t)ntx * nty * PER) return;
@@ -512,7 +658,9 @@ __device__ void ccl_merge_one(const Geo &g, const MRef &b, int ntx, int64_t t, i
 // Point a border-touching tile-local root at its final root and carry its
 // seed flag there.  Other local roots are final roots already.  A walker
 // writes only its own entry, so concurrent walkers never undo each other.
-__device__ __forceinline__ void ccl_flag_one(int32_t *glab, uint8_t *gflag, int64_t i) {
+__device__ __forceinline__ void ccl_flag_one(int32_t *glab_, uint8_t *gflag_, int64_t i) {
+    VLG_GLOBAL int32_t *glab = glb(glab_);
+    VLG_GLOBAL uint8_t *gflag = glb(gflag_);
     const uint8_t f = gflag[i];
     if (!(f & 1)) return;
     int x = (int)i;
@@ -533,8 +681,11 @@ __device__ __forceinline__ void ccl_flag_one(int32_t *glab, uint8_t *gflag, int6
 // row (512 pixels = 8 words of two rows); lane l owns blocks 4l .. 4l+3, i.e.
 // byte l of those 8 words, assembled in this wave's 8 LDS words zw.
 __device__ __forceinline__ void ccl_gather_task(const Geo &g, const MRef &b, const MRef &y, const MRef &z,
-                                                const int32_t *__restrict__ glab, const uint8_t *__restrict__ gflag,
-                                                int user, uint64_t *__restrict__ out, int64_t t, uint64_t *zw) {
+                                                const int32_t *__restrict__ glab_, const uint8_t *__restrict__ gflag_,
+                                                int user, uint64_t *__restrict__ out_, int64_t t, uint64_t *zw) {
+    const VLG_GLOBAL int32_t *glab = glb(glab_);
+    const VLG_GLOBAL uint8_t *gflag = glb(gflag_);
+    VLG_GLOBAL uint64_t *out = glb(out_);
     const int lane = lane_id();
     const int nq = (g.wpr + 7) / 8;
     const int by = (int)(t / nq), q = (int)(t - (int64_t)by * nq);
@@ -578,8 +729,10 @@ __device__ __forceinline__ void ccl_gather_task(const Geo &g, const MRef &b, con
 // that meet the seed mask sm (= N(seeds) & b): bit 1+user of the root's flag
 // byte.  Runs after the flag pass, so every block's root is two loads away.
 // Called by every lane of a wave (block (by, bx), or valid = false).
-__device__ __forceinline__ void ccl_reseed_lane(const Geo &g, const MRef &sm, const int32_t *__restrict__ glab,
-                                                uint8_t *gflag, int user, bool valid, int by, int bx) {
+__device__ __forceinline__ void ccl_reseed_lane(const Geo &g, const MRef &sm, const int32_t *__restrict__ glab_,
+                                                uint8_t *gflag_, int user, bool valid, int by, int bx) {
+    const VLG_GLOBAL int32_t *glab = glb(glab_);
+    VLG_GLOBAL uint8_t *gflag = glb(gflag_);
     const int lane = lane_id();
     int r = -1;
     if (valid && block_bits_g(g, sm, by, bx)) r = glab[glab[(int64_t)by * g.BW + bx]];
@@ -588,11 +741,12 @@ __device__ __forceinline__ void ccl_reseed_lane(const Geo &g, const MRef &sm, co
     const uint32_t bit = 1u << (1 + user);
     uint64_t pending = __ballot(r >= 0);
     while (pending) {
-        const int leader = __builtin_ctzll(pending);
-        const int r0 = __shfl(r, leader);
+        const int leader = __builtin_ctzll(pending);  // wave-uniform
+        const int r0 = __builtin_amdgcn_readlane(r, leader);
         pending &= ~__ballot(r == r0);
         if (lane == leader && !(gflag[r0] & bit))
-            atomicOr((unsigned int *)(gflag + (r0 & ~3)), bit << (8 * (r0 & 3)));
+            __hip_atomic_fetch_or((VLG_GLOBAL unsigned int *)(gflag + (r0 & ~3)), bit << (8 * (r0 & 3)),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -600,32 +754,30 @@ __device__ __forceinline__ void ccl_reseed_lane(const Geo &g, const MRef &sm, co
 
 __global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int op, uint64_t inv_out,
                                                     uint64_t *__restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
-        logic_word(g, x, y, op, inv_out, out, i);
+    logic_words(g, x, y, op, inv_out, out, (int64_t)blockIdx.x * kThreads + threadIdx.x,
+                (int64_t)gridDim.x * kThreads, g.nwords);
 }
 
 __global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z, int zop,
                                                    uint64_t *__restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
-        near_word(g, x, inv_out, z, zop, out, i);
+    const int64_t ntasks = near_tasks(g), nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
+        near_task(g, x, inv_out, z, zop, out, t);
 }
 
 // Up to kBatchMax independent Boolean steps (or near steps) in one launch:
 // blockIdx.y selects the step.
 __global__ __launch_bounds__(kThreads) void k_logic_batch(Geo g, LogicBatch bt) {
     const LogicOp &o = bt.ops[blockIdx.y];
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
-        logic_word(g, o.x, o.y, o.op, o.inv_out, o.out, i);
+    logic_words(g, o.x, o.y, o.op, o.inv_out, o.out, (int64_t)blockIdx.x * kThreads + threadIdx.x,
+                (int64_t)gridDim.x * kThreads, g.nwords);
 }
 
 __global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt) {
     const NearOp &o = bt.ops[blockIdx.y];
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nwords; i += stride)
-        near_word(g, o.x, o.inv_out, o.z, o.zop, o.out, i);
+    const int64_t ntasks = near_tasks(g), nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
+        near_task(g, o.x, o.inv_out, o.z, o.zop, o.out, t);
 }
 
 template <typename T>
@@ -699,8 +851,8 @@ __global__ __launch_bounds__(kThreads) void k_ccl_canon(Geo g, MRef b, const int
     // one atomicMin per distinct root per wave, with the group's minimum
     uint64_t pending = __ballot(r >= 0);
     while (pending) {
-        const int leader = __builtin_ctzll(pending);
-        const int r0 = __shfl(r, leader);
+        const int leader = __builtin_ctzll(pending);  // wave-uniform
+        const int r0 = __builtin_amdgcn_readlane(r, leader);
         const bool mine = r == r0;
         pending &= ~__ballot(mine);
         int m = mine ? p : 0x7fffffff;
@@ -746,34 +898,37 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 
 // ------------------------------------------------------------------ batch kernels
 // Persistent: workgroup u-loop over the launch's global units.  Units per image:
-//   BK_WORDS  256 mask words (logic, near; atoms: four 64-word wave tasks)
+//   BK_WORDS  256 mask words (atoms: four 64-word wave tasks)
+//   BK_LOGIC  1024 mask words (Boolean steps)
+//   BK_NEAR   four near bands (64 words wide, near_band_rows(g) rows high)
 //   BK_TILES  one labelling tile          BK_MERGE  256 border threads
 //   BK_BLOCKS 256 blocks                  BK_GATHER four 256-block wave tasks
 //   BK_PCTH   kPctUnit channel elements   BK_ONE    one per image
 
-#define VLG_BATCH_LOOP(A)                                                                    \
-    const int64_t total_ = (A).prefix[(A).n];                                               \
-    for (int64_t u_ = blockIdx.x; u_ < total_; u_ += gridDim.x)
+#define VLG_BATCH_LOOP(A)                 \
+    UnitRange ur_((A).prefix, (A).n);         \
+    for (int64_t u_ = ur_.begin; u_ < ur_.end; u_++)
 
 __global__ __launch_bounds__(kThreads) void kb_logic(BatchArgs a, BLogic ops) {
     const BLogicOp &o = ops.ops[blockIdx.y];
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
-        const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
-        if (i < d.g.nwords)
-            logic_word(d.g, bref(d, o.x), bref(d, o.y), o.op, o.inv_out ? ~0ull : 0ull, bptr(d, o.out), i);
+        const int64_t i0 = (u_ - a.prefix[ii]) * (kThreads * kLogicUnroll);
+        const int64_t iend = min(i0 + kThreads * kLogicUnroll, d.g.nwords);
+        logic_words(d.g, bref(d, o.x), bref(d, o.y), o.op, o.inv_out ? ~0ull : 0ull, bptr(d, o.out),
+                    i0 + threadIdx.x, kThreads, iend);
     }
 }
 
 __global__ __launch_bounds__(kThreads) void kb_near(BatchArgs a, BNear ops) {
     const BNearOp &o = ops.ops[blockIdx.y];
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
-        const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
-        if (i < d.g.nwords)
-            near_word(d.g, bref(d, o.x), o.inv_out ? ~0ull : 0ull, bref(d, o.z), o.zop, bptr(d, o.out), i);
+        const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + (threadIdx.x >> 6);
+        if (t < near_tasks(d.g))
+            near_task(d.g, bref(d, o.x), o.inv_out ? ~0ull : 0ull, bref(d, o.z), o.zop, bptr(d, o.out), t);
     }
 }
 
@@ -781,12 +936,12 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
     __shared__ float sthr[kMaxAtomsPerLaunch];
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
         __syncthreads();  // the previous unit is done with sthr
         if (threadIdx.x < op.n) {
             const int p = op.pct[threadIdx.x];
-            sthr[threadIdx.x] = p >= 0 ? ((const float *)(d.ws + d.off_pct))[p] : op.thr[threadIdx.x];
+            sthr[threadIdx.x] = p >= 0 ? glb((const float *)(d.ws + d.off_pct))[p] : op.thr[threadIdx.x];
         }
         __syncthreads();
         const T *img = (const T *)(d.img + (int64_t)op.chan * d.chan_bytes);
@@ -799,7 +954,7 @@ __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
 template <int TBH>
 __global__ __launch_bounds__(kThreads) void kb_ccl_local(BatchArgs a, BRef b, BRef y, BRef z) {
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
         const int tile = (int)(u_ - a.prefix[ii]);
@@ -812,7 +967,7 @@ template <int TBH>
 __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
     int unions = 0, tries = 0;
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
         ccl_merge_one<TBH>(d.g, bref(d, b), ntx, (u_ - a.prefix[ii]) * kThreads + threadIdx.x,
@@ -822,7 +977,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
 
 __global__ __launch_bounds__(kThreads) void kb_ccl_flag(BatchArgs a) {
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
         const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
         if (i < (int64_t)d.g.BH * d.g.BW) ccl_flag_one((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), i);
@@ -833,7 +988,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_gather(BatchArgs a, BRef b, B
     __shared__ uint64_t zw[kThreads / 64][8];
     const int wv = threadIdx.x >> 6;
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
         const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + wv;
         if (t < (int64_t)d.g.BH * ((d.g.wpr + 7) / 8))
@@ -844,7 +999,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_gather(BatchArgs a, BRef b, B
 
 __global__ __launch_bounds__(kThreads) void kb_ccl_reseed(BatchArgs a, BRef sm, int user) {
     VLG_BATCH_LOOP(a) {
-        const int ii = find_img(a.prefix, a.n, u_);
+        const int ii = ur_.img(u_);
         const BImg &d = a.imgs[ii];
         const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
         const bool valid = i < (int64_t)d.g.BH * d.g.BW;
@@ -880,13 +1035,14 @@ Geo make_geo(int H, int W) {
 
 hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    k_logic<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
+    k_logic<<<grid_for(g.nwords, kThreads * kLogicUnroll, 4096), kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
     return hipGetLastError();
 }
 
 hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, int zop, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    k_near<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, inv_out ? ~0ull : 0ull, z, zop, out);
+    k_near<<<grid_for(near_tasks(g), kThreads / 64, 8192), kThreads, 0, s>>>(g, x, inv_out ? ~0ull : 0ull, z, zop,
+                                                                                 out);
     return hipGetLastError();
 }
 
@@ -955,14 +1111,14 @@ hipError_t launch_ccl_reseed(hipStream_t s, const Geo &g, MRef sm, const CclWork
 
 hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b) {
     if (g.nwords == 0 || b.n == 0) return hipSuccess;
-    dim3 grid(grid_for(g.nwords, kThreads, 4096), b.n);
+    dim3 grid(grid_for(g.nwords, kThreads * kLogicUnroll, 4096), b.n);
     k_logic_batch<<<grid, kThreads, 0, s>>>(g, b);
     return hipGetLastError();
 }
 
 hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b) {
     if (g.nwords == 0 || b.n == 0) return hipSuccess;
-    dim3 grid(grid_for(g.nwords, kThreads, 4096), b.n);
+    dim3 grid(grid_for(near_tasks(g), kThreads / 64, 8192), b.n);
     k_near_batch<<<grid, kThreads, 0, s>>>(g, b);
     return hipGetLastError();
 }
@@ -999,6 +1155,8 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     const int64_t ntiles = (int64_t)ntiles_x(g) * ntiles_y(g, tbh);
     switch (kind) {
     case BK_WORDS: return (g.nwords + kThreads - 1) / kThreads;
+    case BK_LOGIC: return (g.nwords + kThreads * kLogicUnroll - 1) / (kThreads * kLogicUnroll);
+    case BK_NEAR: return (near_tasks(g) + kThreads / 64 - 1) / (kThreads / 64);
     case BK_TILES: return ntiles;
     case BK_MERGE: return (ntiles * (kTileBW + 2 * tbh) + kThreads - 1) / kThreads;
     case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
@@ -1102,7 +1260,8 @@ __device__ __forceinline__ float key_f32(uint32_t k) {
     return __uint_as_float(u);
 }
 
-__device__ void pct_init_wg(PctState *st, uint32_t k) {
+__device__ void pct_init_wg(PctState *st_, uint32_t k) {
+    VLG_GLOBAL PctState *st = glb(st_);
     for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->hist[i] = 0;
     if (threadIdx.x == 0) {
         st->prefix = 0;
@@ -1111,31 +1270,101 @@ __device__ void pct_init_wg(PctState *st, uint32_t k) {
     }
 }
 
-// Histogram elements [i0, i1) of a channel stored with pitch wpr*64 into the
-// workgroup's LDS histogram h, then into the state.
+// Add 1 at bin[lane] for the active lanes of a wave.  Lanes that share the
+// first active lane's bin are counted by one atomic (channel values cluster,
+// so most of a wave often falls into one bin, and 64 atomics on one LDS
+// address would serialise); the others add their own.
+__device__ __forceinline__ void wave_hist_add(uint32_t *h, uint32_t bin, bool act) {
+    const uint64_t am = __ballot(act);
+    if (!am) return;
+    const int leader = __builtin_ctzll(am);  // wave-uniform
+    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)bin, leader);
+    const uint64_t same = __ballot(act && bin == b0);
+    if (lane_id() == leader) atomicAdd(&h[b0], (uint32_t)__popcll(same));
+    else if (act && bin != b0) atomicAdd(&h[bin], 1u);
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec4<uint8_t> { typedef uint8_t type __attribute__((ext_vector_type(4))); };
+
+// Histogram the channel elements of the chunks [c, c + 1024) for c = i0,
+// i0 + stride, ... below i1 (a channel is stored with pitch wpr*64; i0,
+// stride and i1 are multiples of 1024 or of the pitch, so four consecutive
+// elements share a row), for the n selections st[0..n): selections whose
+// digits chosen so far agree share one LDS histogram (in the first pass all
+// of them do), then every selection's histogram is added into its state.
 template <typename T>
-__device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState *st, int shift, int bins,
-                               int64_t i0, int64_t i1, int64_t step, uint32_t *h) {
-    for (int i = threadIdx.x; i < bins; i += kThreads) h[i] = 0;
-    __syncthreads();
-    const uint32_t prefix = st->prefix, mask = st->mask;
-    const int64_t pitch = (int64_t)g.wpr * 64;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += step) {
-        const uint32_t row = fdiv((uint32_t)(i >> 6), g.wpr_mul, g.wpr_shift);
-        if (i - (int64_t)row * pitch >= g.W) continue;
-        const T v = img[i];
-        const uint32_t key = sizeof(T) == 1 ? (uint32_t)v : f32_key((float)v);
-        if ((key & mask) == prefix) atomicAdd(&h[(key >> shift) & (uint32_t)(bins - 1)], 1u);
+__device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState *const *st, int n, int shift,
+                               int bins, int64_t i0, int64_t i1, int64_t stride, uint32_t (*h)[2048]) {
+    __shared__ uint32_t gpre[kMaxPctSel], gmask[kMaxPctSel];
+    __shared__ int rep[kMaxPctSel], ngroups;
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int j = 0; j < n; j++) {
+            const uint32_t p = glb(st[j])->prefix, mk = glb(st[j])->mask;
+            int r = -1;
+            for (int q = 0; q < m; q++)
+                if (gpre[q] == p && gmask[q] == mk) r = q;
+            if (r < 0) {
+                gpre[m] = p;
+                gmask[m] = mk;
+                r = m++;
+            }
+            rep[j] = r;
+        }
+        ngroups = m;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < bins; i += kThreads)
-        if (h[i]) atomicAdd(&st->hist[i], h[i]);
+    const int m = ngroups;
+    for (int q = 0; q < m; q++)
+        for (int i = threadIdx.x; i < bins; i += kThreads) h[q][i] = 0;
+    __syncthreads();
+    const int64_t pitch = (int64_t)g.wpr * 64;
+    const uint32_t dmask = (uint32_t)(bins - 1);
+    using V = typename Vec4<T>::type;
+    constexpr int U = 4;  // chunks per iteration: U vector loads in flight per thread
+    for (int64_t c = i0; c < i1; c += U * stride) {
+        V v[U];
+        int64_t idx[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            idx[u] = c + u * stride + threadIdx.x * 4;
+            v[u] = *(const VLG_GLOBAL V *)(glb(img) + (idx[u] < i1 ? idx[u] : i0));
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = idx[u];
+            const bool in = i < i1;
+            const uint32_t row = fdiv((uint32_t)(i >> 6), g.wpr_mul, g.wpr_shift);
+            const int64_t col = i - (int64_t)row * pitch;
+            const float f[4] = {(float)v[u].x, (float)v[u].y, (float)v[u].z, (float)v[u].w};
+            uint32_t key[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) key[e] = sizeof(T) == 1 ? (uint32_t)f[e] : f32_key(f[e]);
+            for (int q = 0; q < m; q++) {
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const bool act = in && col + e < g.W && (key[e] & gmask[q]) == gpre[q];
+                    wave_hist_add(h[q], (key[e] >> shift) & dmask, act);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < n; j++)
+        for (int i = threadIdx.x; i < bins; i += kThreads) {
+            const uint32_t cnt = h[rep[j]][i];
+            if (cnt) __hip_atomic_fetch_add(&glb(st[j])->hist[i], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     __syncthreads();
 }
 
 // one workgroup of 256 threads: find the bucket holding rank k
-__device__ void pct_select_wg(PctState *st, int shift, int bins, int last, int is_u8, float *result,
+__device__ void pct_select_wg(PctState *st_, int shift, int bins, int last, int is_u8, float *result_,
                               uint32_t *part) {
+    VLG_GLOBAL PctState *st = glb(st_);
+    VLG_GLOBAL float *result = glb(result_);
     const int per = bins / kThreads;
     uint32_t local = 0;
     for (int j = 0; j < per; j++) local += st->hist[threadIdx.x * per + j];
@@ -1157,20 +1386,28 @@ __device__ void pct_select_wg(PctState *st, int shift, int bins, int last, int i
     __syncthreads();
 }
 
-__global__ void k_pct_init(PctState *st, uint32_t k) { pct_init_wg(st, k); }
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restrict__ img, PctState *st, int shift,
-                                                       int bins) {
-    __shared__ uint32_t h[2048];
-    const int64_t n = (int64_t)g.H * g.wpr * 64;
-    pct_hist_range(g, img, st, shift, bins, (int64_t)blockIdx.x * kThreads, n, (int64_t)gridDim.x * kThreads, h);
+__device__ __forceinline__ PctState *sstate(void *states, int slot) {
+    return (PctState *)((char *)states + (size_t)slot * kPctStateBytes);
 }
 
-__global__ __launch_bounds__(kThreads) void k_pct_select(PctState *st, int shift, int bins, int last, int is_u8,
-                                                         float *result) {
+__global__ void k_pct_init(PctSel sel, void *states) { pct_init_wg(sstate(states, sel.slot[blockIdx.x]), sel.k[blockIdx.x]); }
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restrict__ img, PctSel sel, void *states,
+                                                       int shift, int bins) {
+    __shared__ uint32_t h[kMaxPctSel][2048];
+    PctState *st[kMaxPctSel];
+    for (int j = 0; j < sel.n; j++) st[j] = sstate(states, sel.slot[j]);
+    const int64_t n = (int64_t)g.H * g.wpr * 64;
+    pct_hist_range(g, img, st, sel.n, shift, bins, (int64_t)blockIdx.x * (kThreads * 4), n,
+                   (int64_t)gridDim.x * (kThreads * 4), h);
+}
+
+__global__ __launch_bounds__(kThreads) void k_pct_select(PctSel sel, void *states, int shift, int bins, int last,
+                                                         int is_u8, float *results) {
     __shared__ uint32_t part[kThreads];
-    pct_select_wg(st, shift, bins, last, is_u8, result, part);
+    const int slot = sel.slot[blockIdx.x];
+    pct_select_wg(sstate(states, slot), shift, bins, last, is_u8, results + slot, part);
 }
 
 // batch variants: state and result of percentile slot p live in each image's workspace
@@ -1178,75 +1415,84 @@ __device__ __forceinline__ PctState *bstate(const BImg &d, int p) {
     return (PctState *)(d.ws + d.off_pctst + (uint64_t)p * kPctStateBytes);
 }
 
-__global__ void kb_pct_init(BatchArgs a, int p) {
-    for (int64_t u = blockIdx.x; u < a.prefix[a.n]; u += gridDim.x) {
-        const int ii = find_img(a.prefix, a.n, u);
-        pct_init_wg(bstate(a.imgs[ii], p), a.imgs[ii].ranks[p]);
-        __syncthreads();
+__global__ void kb_pct_init(BatchArgs a, PctSel sel) {
+    UnitRange ur(a.prefix, a.n);
+    for (int64_t u = ur.begin; u < ur.end; u++) {
+        const int ii = ur.img(u);
+        for (int j = 0; j < sel.n; j++) {
+            pct_init_wg(bstate(a.imgs[ii], sel.slot[j]), a.imgs[ii].ranks[sel.slot[j]]);
+            __syncthreads();
+        }
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, int p, int shift, int bins) {
-    __shared__ uint32_t h[2048];
-    for (int64_t u = blockIdx.x; u < a.prefix[a.n]; u += gridDim.x) {
-        const int ii = find_img(a.prefix, a.n, u);
+__global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, PctSel sel, int shift, int bins) {
+    __shared__ uint32_t h[kMaxPctSel][2048];
+    UnitRange ur(a.prefix, a.n);
+    for (int64_t u = ur.begin; u < ur.end; u++) {
+        const int ii = ur.img(u);
         const BImg &d = a.imgs[ii];
+        PctState *st[kMaxPctSel];
+        for (int j = 0; j < sel.n; j++) st[j] = bstate(d, sel.slot[j]);
         const int64_t i0 = (u - a.prefix[ii]) * kPctUnit;
         const int64_t n = (int64_t)d.g.H * d.g.wpr * 64;
         const int64_t i1 = i0 + kPctUnit < n ? i0 + kPctUnit : n;
-        pct_hist_range(d.g, (const T *)(d.img + (int64_t)chan * d.chan_bytes), bstate(d, p), shift, bins, i0, i1,
-                       kThreads, h);
+        pct_hist_range(d.g, (const T *)(d.img + (int64_t)chan * d.chan_bytes), st, sel.n, shift, bins, i0, i1,
+                       kThreads * 4, h);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void kb_pct_select(BatchArgs a, int p, int shift, int bins, int last,
+__global__ __launch_bounds__(kThreads) void kb_pct_select(BatchArgs a, PctSel sel, int shift, int bins, int last,
                                                           int is_u8) {
     __shared__ uint32_t part[kThreads];
-    for (int64_t u = blockIdx.x; u < a.prefix[a.n]; u += gridDim.x) {
-        const int ii = find_img(a.prefix, a.n, u);
+    const int slot = sel.slot[blockIdx.y];
+    UnitRange ur(a.prefix, a.n);
+    for (int64_t u = ur.begin; u < ur.end; u++) {
+        const int ii = ur.img(u);
         const BImg &d = a.imgs[ii];
-        pct_select_wg(bstate(d, p), shift, bins, last, is_u8, (float *)(d.ws + d.off_pct) + p, part);
+        pct_select_wg(bstate(d, slot), shift, bins, last, is_u8, (float *)(d.ws + d.off_pct) + slot, part);
     }
 }
 
 }  // namespace
 
-hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, int64_t pitch,
-                             uint32_t k, void *state, float *result) {
-    (void)pitch;  // always wpr*64
-    PctState *st = (PctState *)state;
-    k_pct_init<<<1, kThreads, 0, s>>>(st, k);
+hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, const PctSel &sel,
+                             void *states, float *results) {
+    if (sel.n < 1 || sel.n > kMaxPctSel) return hipErrorInvalidValue;
+    k_pct_init<<<sel.n, kThreads, 0, s>>>(sel, states);
     const int64_t n = (int64_t)g.H * g.wpr * 64;
     if (n == 0) return hipGetLastError();
-    const int grid = grid_for(n, kThreads * 16, 2048);
+    const int grid = grid_for(n, kThreads * 64, 2048);
     if (dtype == 1) {
-        k_pct_hist<uint8_t><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, st, 0, 256);
-        k_pct_select<<<1, kThreads, 0, s>>>(st, 0, 256, 1, 1, result);
+        k_pct_hist<uint8_t><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
+        k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, 0, 256, 1, 1, results);
         return hipGetLastError();
     }
     const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
     for (int p = 0; p < 3; p++) {
-        k_pct_hist<float><<<grid, kThreads, 0, s>>>(g, (const float *)chan, st, shifts[p], bins[p]);
-        k_pct_select<<<1, kThreads, 0, s>>>(st, shifts[p], bins[p], p == 2, 0, result);
+        k_pct_hist<float><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, shifts[p], bins[p]);
+        k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, shifts[p], bins[p], p == 2, 0, results);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t total_one, const BatchArgs &hist,
-                               int64_t total_hist, int chan, int pct) {
+                               int64_t total_hist, int chan, const PctSel &sel) {
     if (total_one == 0) return hipSuccess;
+    if (sel.n < 1 || sel.n > kMaxPctSel) return hipErrorInvalidValue;
     const int g1 = persistent_grid(total_one), gh = persistent_grid(total_hist);
-    kb_pct_init<<<g1, kThreads, 0, s>>>(one, pct);
+    kb_pct_init<<<g1, kThreads, 0, s>>>(one, sel);
+    dim3 gs(g1, sel.n);
     if (hist.dtype == 1) {
-        kb_pct_hist<uint8_t><<<gh, kThreads, 0, s>>>(hist, chan, pct, 0, 256);
-        kb_pct_select<<<g1, kThreads, 0, s>>>(one, pct, 0, 256, 1, 1);
+        kb_pct_hist<uint8_t><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
+        kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, 0, 256, 1, 1);
         return hipGetLastError();
     }
     const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
     for (int p = 0; p < 3; p++) {
-        kb_pct_hist<float><<<gh, kThreads, 0, s>>>(hist, chan, pct, shifts[p], bins[p]);
-        kb_pct_select<<<g1, kThreads, 0, s>>>(one, pct, shifts[p], bins[p], p == 2, 0);
+        kb_pct_hist<float><<<gh, kThreads, 0, s>>>(hist, chan, sel, shifts[p], bins[p]);
+        kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, shifts[p], bins[p], p == 2, 0);
     }
     return hipGetLastError();
 }
