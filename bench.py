@@ -126,10 +126,10 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512):
             for h, w in sizes]
     flat = (ctypes.c_void_p * (n * nout))(*[o.data_ptr() for row in outs for o in row])
     harr = (ctypes.c_void_p * n)(*[im.handle.value for im in ims])
-    # autotune the labelling tile on the largest image of the batch
-    big = order[-1]
-    tune = vlg.autotune(ctx, f, ims[big], iters=2)
-    log(f"[bench] batch: autotuned tile rows {tune['ccl_tile_rows'][0]} on image {big} {sizes[big]}")
+    # autotune the labelling tile on the batch itself
+    tune = vlg.autotune_batch(ctx, f, ims, iters=1)
+    log(f"[bench] batch: autotuned tile rows {tune['ccl_tile_rows'][0]} "
+        f"({', '.join(f'{k}: {v:.2f} ms' for k, v in sorted(tune['ccl_tile_rows'][1].items()))})")
 
     def step():
         rc = lib.vlg_check_batch(ctx.handle, f.handle, harr, n, flat, 0, 1)

@@ -135,8 +135,9 @@ int vlg_formula_free(vlg_formula *f);
 
 /* Evaluate output `output_index` of f on img and write the mask to `out_mask`
  * (caller-owned, format fmt, in host or device memory).  Only the DAG nodes
- * that output needs are evaluated.  Device outputs complete in stream order;
- * host outputs are complete on return. */
+ * that output needs are evaluated.  Device outputs complete in the order of
+ * the context's stream (work of other streams on the same buffers must be
+ * ordered against it by the caller); host outputs are complete on return. */
 int vlg_check(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int output_index,
               void *out_mask, int fmt, int where);
 /* Evaluate every output of f on img in one pass (shared sub-expressions are
@@ -144,7 +145,11 @@ int vlg_check(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int outp
 int vlg_check_all(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, void *const *outs,
                   int fmt, int where);
 /* Evaluate every output of f on each of n images (sizes may differ).
- * outs[i * n_outputs + k] receives output k of image i (NULL skips it). */
+ * outs[i * n_outputs + k] receives output k of image i (NULL skips it).
+ * In fused and graph mode the batch runs as one launch per schedule step for
+ * all images of a pixel type (persistent kernels over per-image descriptors,
+ * each image with its own workspace region); in per-op mode the images are
+ * evaluated one after another.  Same completion rules as vlg_check_all. */
 int vlg_check_batch(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *const *imgs, int n,
                     void *const *outs, int fmt, int where);
 
@@ -207,9 +212,19 @@ typedef struct vlg_tune_report {
  * tunable to out[0 .. max_out-1]; *n_out receives the number of tunables. */
 int vlg_autotune(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_tune_report *out,
                  int max_out, int *n_out);
+/* Autotuner for batches: evaluate every output of f on the n images with the
+ * batched schedule (as vlg_check_batch in fused mode) `iters` times per
+ * candidate and store the fastest value for the batch class (ceil(log2 n),
+ * ceil(log2 of the mean pixels per image)); vlg_check_batch then uses it for
+ * batches of that class (otherwise the value of its largest image's shape
+ * class).  Outputs go to internal buffers.  Same reports as vlg_autotune. */
+int vlg_autotune_batch(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *const *imgs, int n, int iters,
+                       vlg_tune_report *out, int max_out, int *n_out);
 /* Save / load the context's tuning table as JSON lines
- * {"arch": "gfx950", "tunable": ..., "h_class": ..., "w_class": ..., "value": ...};
- * loading keeps only the entries of the context's device architecture. */
+ * {"arch": "gfx950", "tunable": ..., "h_class": ..., "w_class": ..., "value": ...}
+ * (tunable "ccl_tile_rows_batch" for batch classes, whose two class numbers
+ * are the batch and mean-image classes); loading keeps only the entries of
+ * the context's device architecture. */
 int vlg_tune_save(vlg_ctx *ctx, const char *path);
 int vlg_tune_load(vlg_ctx *ctx, const char *path);
 
@@ -235,7 +250,9 @@ int vlg_server_create(vlg_server **out, int device, int nslots, int64_t hbm_budg
  * footprint the server reserves at admission), in bytes. */
 int vlg_evaluation_bytes(const vlg_formula *f, const vlg_image *img, int64_t *bytes);
 /* outs[k]: packed device buffer of output k (NULL skips it); valid until the
- * request completes.  *request_id identifies the request for vlg_server_wait. */
+ * request completes, and with no write pending on another stream when
+ * submitted (slot streams do not wait for other streams).  *request_id
+ * identifies the request for vlg_server_wait. */
 int vlg_server_submit(vlg_server *s, const vlg_formula *f, const vlg_image *img, void *const *outs,
                       int64_t *request_id);
 /* Block until the request completes; returns its status.  queue_ms: submit to

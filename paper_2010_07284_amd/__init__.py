@@ -241,6 +241,18 @@ def autotune(ctx, f, img, iters=5):
             for i in range(n.value)}
 
 
+def autotune_batch(ctx, f, imgs, iters=3):
+    """vlg_autotune_batch: {tunable: (best, {candidate: ms})} for the batch class
+    of `imgs` (ms per batched evaluation of every output on all images)."""
+    arr = (_lib.TuneReport * 4)()
+    n = ctypes.c_int()
+    harr = (ctypes.c_void_p * len(imgs))(*[im.handle.value for im in imgs])
+    _lib.call("vlg_autotune_batch", ctx.handle, f.handle, harr, len(imgs), iters, arr, 4, ctypes.byref(n))
+    names = {v: k for k, v in TUNABLES.items()}
+    return {names[arr[i].which]: (arr[i].best, {arr[i].candidates[j]: arr[i].ms[j] for j in range(arr[i].n)})
+            for i in range(n.value)}
+
+
 def tune_save(ctx, path):
     _lib.call("vlg_tune_save", ctx.handle, path.encode())
 
@@ -324,5 +336,5 @@ def pack(mask):
 
 __all__ = ["create", "sync", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
            "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
-           "tune_load", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
+           "tune_load", "autotune_batch", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

@@ -99,6 +99,7 @@ struct vlg_ctx {
     std::string arch;
     int forced_tbh = 0;                             // 0: not forced
     std::map<std::pair<int, int>, Tuning> tuned;    // shape class -> tuning
+    std::map<std::pair<int, int>, Tuning> tuned_batch;  // (batch class, mean image class) -> tuning
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int mode = VLG_MODE_GRAPH;
@@ -182,6 +183,11 @@ Tuning tuning_for(const vlg_ctx *c, int H, int W) {
     if (it != c->tuned.end()) t = it->second;
     if (c->forced_tbh) t.ccl_tbh = c->forced_tbh;
     return t;
+}
+
+// (ceil(log2 n), ceil(log2 mean pixels per image)) of a batch
+std::pair<int, int> batch_class(int n, int64_t pixels) {
+    return {log2_class(n), log2_class((int)std::min<int64_t>(pixels / std::max(n, 1), 1 << 30))};
 }
 
 uint32_t pct_rank(double q, int64_t n) {
@@ -451,15 +457,21 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
     const bool direct = fmt == VLG_PACKED64 && where == VLG_DEVICE;
     const bool stage_u8 = fmt == VLG_U8MASK && where == VLG_HOST;
 
-    // one labelling tile height for the batch: the largest image's
-    int64_t big = -1;
+    // one labelling tile height for the batch: forced, else the batch class's
+    // tuned value, else the largest image's
+    int64_t big = -1, pixels = 0;
     int tbh = kTileBHDefault;
     for (int i : idx) {
         const int64_t px = (int64_t)imgs[i]->H * imgs[i]->W;
+        pixels += px;
         if (px > big) {
             big = px;
             tbh = tuning_for(c, imgs[i]->H, imgs[i]->W).ccl_tbh;
         }
+    }
+    if (!c->forced_tbh) {
+        auto it = c->tuned_batch.find(batch_class(n, pixels));
+        if (it != c->tuned_batch.end()) tbh = it->second.ccl_tbh;
     }
 
     // workspace: per-image layouts, then the descriptor block
@@ -1146,6 +1158,64 @@ int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int it
     return VLG_OK;
 }
 
+int vlg_autotune_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *imgs, int n, int iters,
+                       vlg_tune_report *out, int max_out, int *n_out) {
+    if (!c || !cf || !imgs || n < 1 || iters < 1 || !n_out) return fail(VLG_EINVAL, "bad argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    const int dtype = imgs[0]->dtype;
+    int64_t pixels = 0;
+    for (int i = 0; i < n; i++) {
+        if (!imgs[i]) return fail(VLG_EINVAL, "null image in batch");
+        if (f->max_chan >= imgs[i]->C) return fail(VLG_ESHAPE, "formula uses a channel an image lacks");
+        if (imgs[i]->dtype != dtype) return fail(VLG_EINVAL, "batch autotuning needs one pixel type");
+        if (imgs[i]->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
+        pixels += (int64_t)imgs[i]->H * imgs[i]->W;
+    }
+    DeviceGuard dg(c->device);
+    *n_out = 1;
+    vlg_tune_report rep;
+    std::memset(&rep, 0, sizeof rep);
+    rep.which = VLG_TUNE_CCL_TILE_ROWS;
+    const int cands[3] = {8, 16, 32};
+    const size_t nout = f->dag.outputs.size();
+    std::vector<void *> outs((size_t)n * nout, nullptr);
+    std::vector<int> idx((size_t)n);
+    for (int i = 0; i < n; i++) idx[(size_t)i] = i;
+    const int saved_forced = c->forced_tbh, saved_mode = c->mode;
+    c->mode = VLG_MODE_FUSED;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = VLG_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(VLG_EHIP, "event create");
+    double best_ms = 1e30;
+    for (int ci = 0; ci < 3 && rc == VLG_OK; ci++) {
+        c->forced_tbh = cands[ci];
+        rc = run_batch(c, f, imgs, idx, outs.data(), VLG_PACKED64, VLG_DEVICE);  // warm-up
+        if (rc == VLG_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
+        for (int it = 0; it < iters && rc == VLG_OK; it++)
+            rc = run_batch(c, f, imgs, idx, outs.data(), VLG_PACKED64, VLG_DEVICE);
+        float ms = 0.f;
+        if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = fail(VLG_EHIP, "event timing");
+        if (rc != VLG_OK) break;
+        rep.candidates[rep.n] = cands[ci];
+        rep.ms[rep.n] = ms / iters;
+        if (rep.ms[rep.n] < best_ms) {
+            best_ms = rep.ms[rep.n];
+            rep.best = cands[ci];
+        }
+        rep.n++;
+    }
+    c->forced_tbh = saved_forced;
+    c->mode = saved_mode;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != VLG_OK) return rc;
+    c->tuned_batch[batch_class(n, pixels)].ccl_tbh = rep.best;
+    if (out && max_out > 0) out[0] = rep;
+    return VLG_OK;
+}
+
 int vlg_tune_save(vlg_ctx *c, const char *path) {
     if (!c || !path) return fail(VLG_EINVAL, "null argument");
     FILE *fp = std::fopen(path, "w");
@@ -1153,6 +1223,11 @@ int vlg_tune_save(vlg_ctx *c, const char *path) {
     for (const auto &kv : c->tuned)
         std::fprintf(fp,
                      "{\"arch\": \"%s\", \"tunable\": \"ccl_tile_rows\", \"h_class\": %d, \"w_class\": %d, "
+                     "\"value\": %d}\n",
+                     c->arch.c_str(), kv.first.first, kv.first.second, kv.second.ccl_tbh);
+    for (const auto &kv : c->tuned_batch)
+        std::fprintf(fp,
+                     "{\"arch\": \"%s\", \"tunable\": \"ccl_tile_rows_batch\", \"h_class\": %d, \"w_class\": %d, "
                      "\"value\": %d}\n",
                      c->arch.c_str(), kv.first.first, kv.first.second, kv.second.ccl_tbh);
     std::fclose(fp);
@@ -1171,8 +1246,9 @@ int vlg_tune_load(vlg_ctx *c, const char *path) {
                               "\"value\": %d}",
                         arch, tun, &hc, &wc, &v) != 5)
             continue;
-        if (c->arch != arch || std::string(tun) != "ccl_tile_rows" || !valid_tile_bh(v)) continue;
-        c->tuned[{hc, wc}].ccl_tbh = v;
+        if (c->arch != arch || !valid_tile_bh(v)) continue;
+        if (std::string(tun) == "ccl_tile_rows") c->tuned[{hc, wc}].ccl_tbh = v;
+        if (std::string(tun) == "ccl_tile_rows_batch") c->tuned_batch[{hc, wc}].ccl_tbh = v;
     }
     std::fclose(fp);
     return VLG_OK;

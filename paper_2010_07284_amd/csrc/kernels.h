@@ -27,18 +27,20 @@ struct Geo {
 
 Geo make_geo(int H, int W);
 
-// near works on bands of rows 64 words wide: the band height grows with the
-// image (4 .. 32 rows) while at least 2048 bands remain to fill the chip
+// near works on bands of rows 64 words wide.  For one image the band height
+// grows with the image (4 .. 32 rows) while at least 2048 bands remain to
+// fill the chip; a batch always has bands enough and uses kBatchNearRows.
 __host__ __device__ inline int near_band_rows(const Geo &g) {
     const int64_t rows = (int64_t)g.H * ((g.wpr + 63) / 64);
     int R = 4;
     while (R < 32 && rows / (2 * R) >= 2048) R *= 2;
     return R;
 }
-__host__ __device__ inline int64_t near_tasks(const Geo &g) {
-    const int R = near_band_rows(g);
+constexpr int kBatchNearRows = 8;
+__host__ __device__ inline int64_t near_tasks(const Geo &g, int R) {
     return (int64_t)((g.H + R - 1) / R) * ((g.wpr + 63) / 64);
 }
+__host__ __device__ inline int64_t near_tasks(const Geo &g) { return near_tasks(g, near_band_rows(g)); }
 
 // Tile geometry of the reachability labelling: TBH x 64 blocks per tile
 // (2*TBH pixel rows x 128 pixel columns); TBH is tunable (8, 16 or 32).

@@ -21,8 +21,9 @@ namespace {
 
 constexpr int kThreads = 256;
 // channel elements per batched histogram unit: large enough that flushing a
-// workgroup's LDS histogram (up to 2048 bins) stays small next to the reads
-constexpr int64_t kPctUnit = 65536;
+// workgroup's LDS histograms (2048 bins per selection, global atomics that
+// all units of an image aim at the same addresses) stays small next to the reads
+constexpr int64_t kPctUnit = 262144;
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t shift) {
     return (uint32_t)(((uint64_t)__umulhi(n, mul) + n) >> shift);
@@ -74,7 +75,10 @@ __device__ __forceinline__ int find_img(const int64_t *prefix, int n, int64_t u)
 
 // A workgroup of a persistent batch kernel takes a contiguous range of the
 // launch's global units, finds the image of its first unit by binary search
-// and then only steps forward (units of one image are consecutive).
+// and then only steps forward (units of one image are consecutive).  Kernels
+// copy the image's descriptor into registers per unit: read through a
+// reference into memory, its fields would be reloaded after every LDS store
+// or atomic (a generic pointer may alias LDS).
 struct UnitRange {
     const int64_t *prefix;
     int64_t begin, end, next;
@@ -228,8 +232,8 @@ __device__ __forceinline__ void near_band(const Geo &g, const uint64_t *__restri
 }
 
 // N of a constant mask (x.p == nullptr) is that constant over the image.
-__device__ __noinline__ void near_const_band(const Geo &g, uint64_t xinv, uint64_t inv_out, const MRef &z, int zop,
-                                             uint64_t *out, int64_t task, int R) {
+__device__ __forceinline__ void near_const_band(Geo g, uint64_t xinv, uint64_t inv_out, MRef z, int zop, uint64_t *out,
+                                             int64_t task, int R) {
     const int nstrips = (g.wpr + 63) >> 6;
     const int64_t band = task / nstrips;
     const int w = (int)(task - band * nstrips) * 64 + lane_id();
@@ -243,9 +247,9 @@ __device__ __noinline__ void near_const_band(const Geo &g, uint64_t xinv, uint64
     }
 }
 
+// band `task` of height R (4, 8, 16 or 32 rows)
 __device__ __forceinline__ void near_task(const Geo &g, const MRef &x, uint64_t inv_out, const MRef &z, int zop,
-                                          uint64_t *out, int64_t task) {
-    const int R = near_band_rows(g);
+                                          uint64_t *out, int64_t task, int R) {
     if (!x.p) near_const_band(g, x.inv, inv_out, z, zop, out, task, R);
     else if (R == 4 && z.p) near_band<4, true>(g, x.p, x.inv, inv_out, z.p, z.inv, zop, out, task, R);
     else if (R == 4) near_band<4, false>(g, x.p, x.inv, inv_out, z.p, z.inv, zop, out, task, R);
@@ -760,9 +764,10 @@ __global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int o
 
 __global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z, int zop,
                                                    uint64_t *__restrict__ out) {
-    const int64_t ntasks = near_tasks(g), nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    const int R = near_band_rows(g);
+    const int64_t ntasks = near_tasks(g, R), nwaves = (int64_t)gridDim.x * (kThreads / 64);
     for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
-        near_task(g, x, inv_out, z, zop, out, t);
+        near_task(g, x, inv_out, z, zop, out, t, R);
 }
 
 // Up to kBatchMax independent Boolean steps (or near steps) in one launch:
@@ -775,9 +780,10 @@ __global__ __launch_bounds__(kThreads) void k_logic_batch(Geo g, LogicBatch bt) 
 
 __global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt) {
     const NearOp &o = bt.ops[blockIdx.y];
-    const int64_t ntasks = near_tasks(g), nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    const int R = near_band_rows(g);
+    const int64_t ntasks = near_tasks(g, R), nwaves = (int64_t)gridDim.x * (kThreads / 64);
     for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
-        near_task(g, o.x, o.inv_out, o.z, o.zop, o.out, t);
+        near_task(g, o.x, o.inv_out, o.z, o.zop, o.out, t, R);
 }
 
 template <typename T>
@@ -900,20 +906,29 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 // Persistent: workgroup u-loop over the launch's global units.  Units per image:
 //   BK_WORDS  256 mask words (atoms: four 64-word wave tasks)
 //   BK_LOGIC  1024 mask words (Boolean steps)
-//   BK_NEAR   four near bands (64 words wide, near_band_rows(g) rows high)
+//   BK_NEAR   four near bands (64 words wide, kBatchNearRows rows high)
 //   BK_TILES  one labelling tile          BK_MERGE  256 border threads
 //   BK_BLOCKS 256 blocks                  BK_GATHER four 256-block wave tasks
 //   BK_PCTH   kPctUnit channel elements   BK_ONE    one per image
 
-#define VLG_BATCH_LOOP(A)                 \
-    UnitRange ur_((A).prefix, (A).n);         \
+// d: the descriptor of unit u_'s image, reloaded only when the image changes
+#define VLG_BATCH_LOOP(A)                          \
+    UnitRange ur_((A).prefix, (A).n);                  \
+    int cur_ = -1;                                     \
+    BImg dcur_;                                        \
     for (int64_t u_ = ur_.begin; u_ < ur_.end; u_++)
+#define VLG_BATCH_IMG(A)                           \
+    const int ii = ur_.img(u_);                        \
+    if (ii != cur_) {                                  \
+        dcur_ = (A).imgs[ii];                          \
+        cur_ = ii;                                     \
+    }                                                  \
+    const BImg &d = dcur_;
 
 __global__ __launch_bounds__(kThreads) void kb_logic(BatchArgs a, BLogic ops) {
     const BLogicOp &o = ops.ops[blockIdx.y];
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         const int64_t i0 = (u_ - a.prefix[ii]) * (kThreads * kLogicUnroll);
         const int64_t iend = min(i0 + kThreads * kLogicUnroll, d.g.nwords);
         logic_words(d.g, bref(d, o.x), bref(d, o.y), o.op, o.inv_out ? ~0ull : 0ull, bptr(d, o.out),
@@ -924,11 +939,11 @@ __global__ __launch_bounds__(kThreads) void kb_logic(BatchArgs a, BLogic ops) {
 __global__ __launch_bounds__(kThreads) void kb_near(BatchArgs a, BNear ops) {
     const BNearOp &o = ops.ops[blockIdx.y];
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + (threadIdx.x >> 6);
-        if (t < near_tasks(d.g))
-            near_task(d.g, bref(d, o.x), o.inv_out ? ~0ull : 0ull, bref(d, o.z), o.zop, bptr(d, o.out), t);
+        if (t < near_tasks(d.g, kBatchNearRows))
+            near_task(d.g, bref(d, o.x), o.inv_out ? ~0ull : 0ull, bref(d, o.z), o.zop, bptr(d, o.out), t,
+                      kBatchNearRows);
     }
 }
 
@@ -936,8 +951,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
     __shared__ float sthr[kMaxAtomsPerLaunch];
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         __syncthreads();  // the previous unit is done with sthr
         if (threadIdx.x < op.n) {
             const int p = op.pct[threadIdx.x];
@@ -954,8 +968,7 @@ __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
 template <int TBH>
 __global__ __launch_bounds__(kThreads) void kb_ccl_local(BatchArgs a, BRef b, BRef y, BRef z) {
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
         const int tile = (int)(u_ - a.prefix[ii]);
         ccl_local_tile<TBH>(d.g, bref(d, b), bref(d, y), bref(d, z), tile % ntx, tile / ntx,
@@ -967,8 +980,7 @@ template <int TBH>
 __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
     int unions = 0, tries = 0;
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
         ccl_merge_one<TBH>(d.g, bref(d, b), ntx, (u_ - a.prefix[ii]) * kThreads + threadIdx.x,
                            (int32_t *)(d.ws + d.off_glab), unions, tries);
@@ -977,8 +989,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
 
 __global__ __launch_bounds__(kThreads) void kb_ccl_flag(BatchArgs a) {
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
         if (i < (int64_t)d.g.BH * d.g.BW) ccl_flag_one((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), i);
     }
@@ -988,8 +999,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_gather(BatchArgs a, BRef b, B
     __shared__ uint64_t zw[kThreads / 64][8];
     const int wv = threadIdx.x >> 6;
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + wv;
         if (t < (int64_t)d.g.BH * ((d.g.wpr + 7) / 8))
             ccl_gather_task(d.g, bref(d, b), bref(d, y), bref(d, z), (const int32_t *)(d.ws + d.off_glab),
@@ -999,8 +1009,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_gather(BatchArgs a, BRef b, B
 
 __global__ __launch_bounds__(kThreads) void kb_ccl_reseed(BatchArgs a, BRef sm, int user) {
     VLG_BATCH_LOOP(a) {
-        const int ii = ur_.img(u_);
-        const BImg &d = a.imgs[ii];
+        VLG_BATCH_IMG(a)
         const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
         const bool valid = i < (int64_t)d.g.BH * d.g.BW;
         const int by = valid ? (int)(i / d.g.BW) : 0, bx = valid ? (int)(i - (int64_t)by * d.g.BW) : 0;
@@ -1010,6 +1019,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_reseed(BatchArgs a, BRef sm, 
 }
 
 #undef VLG_BATCH_LOOP
+#undef VLG_BATCH_IMG
 
 int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
 int ntiles_y(const Geo &g, int tbh) { return (g.BH + tbh - 1) / tbh; }
@@ -1035,7 +1045,7 @@ Geo make_geo(int H, int W) {
 
 hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    k_logic<<<grid_for(g.nwords, kThreads * kLogicUnroll, 4096), kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
+    k_logic<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
     return hipGetLastError();
 }
 
@@ -1111,7 +1121,7 @@ hipError_t launch_ccl_reseed(hipStream_t s, const Geo &g, MRef sm, const CclWork
 
 hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b) {
     if (g.nwords == 0 || b.n == 0) return hipSuccess;
-    dim3 grid(grid_for(g.nwords, kThreads * kLogicUnroll, 4096), b.n);
+    dim3 grid(grid_for(g.nwords, kThreads, 4096), b.n);
     k_logic_batch<<<grid, kThreads, 0, s>>>(g, b);
     return hipGetLastError();
 }
@@ -1156,7 +1166,7 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     switch (kind) {
     case BK_WORDS: return (g.nwords + kThreads - 1) / kThreads;
     case BK_LOGIC: return (g.nwords + kThreads * kLogicUnroll - 1) / (kThreads * kLogicUnroll);
-    case BK_NEAR: return (near_tasks(g) + kThreads / 64 - 1) / (kThreads / 64);
+    case BK_NEAR: return (near_tasks(g, kBatchNearRows) + kThreads / 64 - 1) / (kThreads / 64);
     case BK_TILES: return ntiles;
     case BK_MERGE: return (ntiles * (kTileBW + 2 * tbh) + kThreads - 1) / kThreads;
     case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
@@ -1272,7 +1282,7 @@ __device__ void pct_init_wg(PctState *st_, uint32_t k) {
 
 // Add 1 at bin[lane] for the active lanes of a wave.  Lanes that share the
 // first active lane's bin are counted by one atomic (channel values cluster,
-// so most of a wave often falls into one bin, and 64 atomics on one LDS
+// so much of a wave often falls into one bin, and 64 atomics on one LDS
 // address would serialise); the others add their own.
 __device__ __forceinline__ void wave_hist_add(uint32_t *h, uint32_t bin, bool act) {
     const uint64_t am = __ballot(act);
@@ -1316,7 +1326,15 @@ __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState
         ngroups = m;
     }
     __syncthreads();
+    // the group table in registers: the histogram atomics below write LDS, so
+    // values left in LDS would be reloaded after every one of them
     const int m = ngroups;
+    uint32_t pre[kMaxPctSel], msk[kMaxPctSel];
+#pragma unroll
+    for (int q = 0; q < kMaxPctSel; q++) {
+        pre[q] = q < m ? gpre[q] : 0u;
+        msk[q] = q < m ? gmask[q] : 0u;
+    }
     for (int q = 0; q < m; q++)
         for (int i = threadIdx.x; i < bins; i += kThreads) h[q][i] = 0;
     __syncthreads();
@@ -1342,12 +1360,16 @@ __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState
             uint32_t key[4];
 #pragma unroll
             for (int e = 0; e < 4; e++) key[e] = sizeof(T) == 1 ? (uint32_t)f[e] : f32_key(f[e]);
-            for (int q = 0; q < m; q++) {
+            // the groups of a pass share the digit mask and differ in prefix,
+            // so an element belongs to at most one of them
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const bool act = in && col + e < g.W && (key[e] & gmask[q]) == gpre[q];
-                    wave_hist_add(h[q], (key[e] >> shift) & dmask, act);
-                }
+            for (int e = 0; e < 4; e++) {
+                int grp = -1;
+#pragma unroll
+                for (int q = kMaxPctSel - 1; q >= 0; q--)
+                    if (q < m && (key[e] & msk[q]) == pre[q]) grp = q;
+                const bool act = in && col + e < g.W && grp >= 0;
+                wave_hist_add(&h[0][0], (uint32_t)max(grp, 0) * 2048u + ((key[e] >> shift) & dmask), act);
             }
         }
     }
@@ -1432,7 +1454,7 @@ __global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, P
     UnitRange ur(a.prefix, a.n);
     for (int64_t u = ur.begin; u < ur.end; u++) {
         const int ii = ur.img(u);
-        const BImg &d = a.imgs[ii];
+        const BImg d = a.imgs[ii];  // by value (see UnitRange)
         PctState *st[kMaxPctSel];
         for (int j = 0; j < sel.n; j++) st[j] = bstate(d, sel.slot[j]);
         const int64_t i0 = (u - a.prefix[ii]) * kPctUnit;
@@ -1450,7 +1472,7 @@ __global__ __launch_bounds__(kThreads) void kb_pct_select(BatchArgs a, PctSel se
     UnitRange ur(a.prefix, a.n);
     for (int64_t u = ur.begin; u < ur.end; u++) {
         const int ii = ur.img(u);
-        const BImg &d = a.imgs[ii];
+        const BImg d = a.imgs[ii];  // by value (see UnitRange)
         pct_select_wg(bstate(d, slot), shift, bins, last, is_u8, (float *)(d.ws + d.off_pct) + slot, part);
     }
 }

@@ -191,3 +191,22 @@ def test_batch_uneven_full_config_sampled(ctx):
         assert_same(src, dimgs[i], got, tag=f"image {i} {h}x{w}")
     del outs
     torch.cuda.empty_cache()
+
+
+def test_batch_autotune_picks_persists_and_keeps_results(ctx, tmp_path):
+    import paper_2010_07284_amd as vlg
+    src = formulas.segmentation_dag(4)
+    sizes = [(190, 257), (300, 77), (128, 520), (64, 64)]
+    imgs = [images.phantom_image(np.random.default_rng([41, i]), h, w) for i, (h, w) in enumerate(sizes)]
+    f = vlg.compile_formula(ctx, src)
+    ims = [vlg.load_image(ctx, im) for im in imgs]
+    best, times = vlg.autotune_batch(ctx, f, ims, iters=1)["ccl_tile_rows"]
+    assert set(times) == {8, 16, 32} and best == min(times, key=times.get)
+    path = str(tmp_path / "tune.jsonl")
+    vlg.tune_save(ctx, path)
+    assert '"ccl_tile_rows_batch"' in open(path).read()
+    ctx2 = vlg.create()
+    vlg.tune_load(ctx2, path)
+    got = run_batch(ctx2, src, imgs, "graph")
+    for (h, w), img, g in zip(sizes, imgs, got):
+        assert_same(src, img, g, tag=f"{h}x{w} tuned")
