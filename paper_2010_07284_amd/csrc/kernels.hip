@@ -427,10 +427,11 @@ __device__ __forceinline__ uint32_t block_bits_g(const Geo &g, const MRef &b, in
 // the seed test: a block meets the seeds when one of its b-pixels lies in
 // N(y & z).
 //
-// Output: glab[id] = global id of the block's tile-local root; gflag[id] of
-// a local root: bit0 = its component touches the tile border (only those can
-// be joined to other tiles), bit1 = it meets the seeds (seed set of labelling
-// user 0; bits 2..7 serve later users, see ccl_reseed).
+// Output: glab[id] = global id of the foreground block's tile-local root
+// (background entries are left as they are); gflag[id] of a local root:
+// bit0 = its component touches the tile border (only those can be joined to
+// other tiles), bit1 = it meets the seeds (seed set of labelling user 0;
+// bits 2..7 serve later users, see ccl_reseed).
 template <int TBH>
 __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const MRef &z, int tx, int ty,
                                int32_t *__restrict__ glab_, uint8_t *__restrict__ gflag_) {
@@ -553,110 +554,147 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
         const int by = ty * TBH + lby, bx = tx * TBW + lbx;
         if (by >= g.BH || bx >= g.BW) continue;
         const int64_t id = (int64_t)by * g.BW + bx;
+        // background blocks get a flag byte only: no later pass reads their
+        // parent entry (every lookup starts from a foreground block)
         if (sbits[i]) {
             const int r = L[i];
             glab[id] = (ty * TBH + r / TBW) * g.BW + tx * TBW + r % TBW;
             gflag[id] = r == i ? sflag[i] : (uint8_t)0;
         } else {
-            glab[id] = (int32_t)id;
             gflag[id] = 0;
         }
     }
     __syncthreads();  // the next tile of a persistent workgroup reuses the LDS
 }
 
-// Cross-tile merge, one border block per thread t of an image: blocks on a
-// tile's top row, left column and right column unite with their earlier
-// neighbours in other tiles.  A block skips a union that its connected
-// predecessor along the same border (left neighbour on the top row, upper
-// neighbour on a side column) already makes with the same tile-local
-// component.
+// Cross-tile merge, one wave per tile: blocks on the tile's top row, left
+// column and right column unite with their earlier neighbours in other tiles.
+// A block skips a union that its connected predecessor along the same border
+// (left neighbour on the top row, upper neighbour on a side column) already
+// makes with the same tile-local component.
+//
+// The wave first stages the mask words around the tile's border in LDS: pixel
+// rows 2*by0-4 .. 2*by0+2*TBH-1 and word columns 2*tx-1 .. 2*tx+2 (every block
+// any border block or its neighbours and predecessors touch), all loads in
+// flight at once.  Each lane then derives the block bits it needs from LDS and
+// loads the labels of its candidates and predecessors together before uniting.
 template <int TBH>
-__device__ void ccl_merge_one(const Geo &g, const MRef &b, int ntx, int64_t t, int32_t *glab_, int &unions,
-                              int &tries) {
+constexpr int merge_window_words() {
+    return (2 * TBH + 4) * 4;
+}
+
+template <int TBH>
+__device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, int32_t *glab_, uint64_t *win,
+                               int &unions, int &tries) {
+    constexpr int TBW = 64, WN = merge_window_words<TBH>(), NL = (WN + 63) / 64;
     VLG_GLOBAL int32_t *glab = glb(glab_);
-    constexpr int TBW = 64, PER = TBW + 2 * TBH;
-    const int nty = (g.BH + TBH - 1) / TBH;
-    if (t >= (int64_t)ntx * nty * PER) return;
-    const int tile = (int)(t / PER), k = (int)(t % PER);
+    const int lane = lane_id();
     const int tx = tile % ntx, ty = tile / ntx;
-    int lby, lbx, kind;
-    if (k < TBW) {
-        lby = 0; lbx = k; kind = 0;
-    } else if (k < TBW + TBH) {
-        lby = k - TBW; lbx = 0; kind = 1;
-    } else {
-        lby = k - TBW - TBH; lbx = TBW - 1; kind = 2;
+    const int by0 = ty * TBH, bx0 = tx * TBW;
+    const int r0 = 2 * by0 - 4, w0 = 2 * tx - 1;  // window origin: pixel row, word column
+    {
+        uint64_t v[NL];
+        int64_t idx[NL];
+#pragma unroll
+        for (int k = 0; k < NL; k++) {
+            const int i = lane + 64 * k, r = r0 + i / 4, w = w0 + (i & 3);
+            const bool ok = i < WN && r >= 0 && r < g.H && w >= 0 && w < g.wpr;
+            idx[k] = ok ? (int64_t)r * g.wpr + w : -1;
+            v[k] = b.p ? glb(b.p)[ok ? idx[k] : 0] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < NL; k++) {
+            const int i = lane + 64 * k, w = w0 + (i & 3);
+            if (i < WN) win[i] = idx[k] >= 0 ? ((v[k] ^ b.inv) & (w == g.wpr - 1 ? g.tail : ~0ull)) : 0ull;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    const int by = ty * TBH + lby, bx = tx * TBW + lbx;
-    const uint32_t bits = (by < g.BH && bx < g.BW) ? block_bits_g(g, b, by, bx) : 0u;
-    const int id = by * g.BW + bx;
-    auto link = [&](int nid) {
+    // bits of block (by, bx), by in [by0-2, by0+TBH), bx in [bx0-2, bx0+64]
+    auto bits = [&](int by, int bx) -> uint32_t {
+        const int r = 2 * by - r0, p = 2 * bx - 64 * w0, q = p >> 6, sh = p & 63;
+        return (uint32_t)((win[r * 4 + q] >> sh) & 3) | ((uint32_t)((win[(r + 1) * 4 + q] >> sh) & 3) << 2);
+    };
+    auto link = [&](int id, int nid) {
         unions++;
         tries += g_unite(glab, id, nid);
     };
-    if (bits && kind == 0 && by > 0) {
-        // contacts in the row above (other tile): UL, U, UR
-        int c[3] = {-1, -1, -1};
-        if (bx > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[0] = id - g.BW - 1;
-        if ((bits & 3) && (block_bits_g(g, b, by - 1, bx) & 12)) c[1] = id - g.BW;
-        if (bx + 1 < g.BW && (bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) c[2] = id - g.BW + 1;
-        // predecessor on this border row: the left block, if connected
-        int p[3] = {-1, -1, -1};
-        if (lbx > 0) {
-            const uint32_t lb = block_bits_g(g, b, by, bx - 1);
-            if ((bits & 5) && (lb & 10)) {
-                if (bx - 1 > 0 && (lb & 1) && (block_bits_g(g, b, by - 1, bx - 2) & 8)) p[0] = id - g.BW - 2;
-                if ((lb & 3) && (block_bits_g(g, b, by - 1, bx - 1) & 12)) p[1] = id - g.BW - 1;
-                if ((lb & 2) && (block_bits_g(g, b, by - 1, bx) & 4)) p[2] = id - g.BW;
+
+    // top row: contacts with the row above (other tile): UL, U, UR
+    if (by0 > 0 && by0 < g.BH) {
+        const int by = by0, bx = bx0 + lane, id = by * g.BW + bx;
+        const uint32_t bb = bx < g.BW ? bits(by, bx) : 0u;
+        int c[3] = {-1, -1, -1}, p[3] = {-1, -1, -1};
+        if (bb) {
+            if (bx > 0 && (bb & 1) && (bits(by - 1, bx - 1) & 8)) c[0] = id - g.BW - 1;
+            if ((bb & 3) && (bits(by - 1, bx) & 12)) c[1] = id - g.BW;
+            if (bx + 1 < g.BW && (bb & 2) && (bits(by - 1, bx + 1) & 4)) c[2] = id - g.BW + 1;
+            // predecessor on this border row: the left block, if connected
+            if (lane > 0) {
+                const uint32_t lb = bits(by, bx - 1);
+                if ((bb & 5) && (lb & 10)) {
+                    if (bx - 1 > 0 && (lb & 1) && (bits(by - 1, bx - 2) & 8)) p[0] = id - g.BW - 2;
+                    if ((lb & 3) && (bits(by - 1, bx - 1) & 12)) p[1] = id - g.BW - 1;
+                    if ((lb & 2) && (bits(by - 1, bx) & 4)) p[2] = id - g.BW;
+                }
             }
         }
-        int pl[3];
+        int pl[3], lc[3];
 #pragma unroll
-        for (int j = 0; j < 3; j++) pl[j] = p[j] >= 0 ? glab[p[j]] : -2;
-        int done[3] = {-3, -3, -3};
+        for (int j = 0; j < 3; j++) {
+            pl[j] = p[j] >= 0 ? glab[p[j]] : -2;
+            lc[j] = c[j] >= 0 ? glab[c[j]] : -4;
+        }
+        int done[2] = {-3, -3};
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             if (c[j] < 0) continue;
-            const int lc = glab[c[j]];
-            if (lc == pl[0] || lc == pl[1] || lc == pl[2] || lc == done[0] || lc == done[1]) continue;
-            done[j < 2 ? j : 1] = lc;
-            link(c[j]);
-        }
-    } else if (bits && kind == 1 && bx > 0) {
-        // contacts in the column to the left (other tile): L, and UL below the top row
-        int c[2] = {-1, -1};
-        if ((bits & 5) && (block_bits_g(g, b, by, bx - 1) & 10)) c[0] = id - 1;
-        if (lby > 0 && (bits & 1) && (block_bits_g(g, b, by - 1, bx - 1) & 8)) c[1] = id - g.BW - 1;
-        // predecessor on this border column: the upper block, if connected
-        int p[2] = {-1, -1};
-        if (lby > 0) {
-            const uint32_t ub = block_bits_g(g, b, by - 1, bx);
-            if ((bits & 3) && (ub & 12)) {
-                if ((ub & 5) && (block_bits_g(g, b, by - 1, bx - 1) & 10)) p[0] = id - g.BW - 1;
-                if (lby > 1 && (ub & 1) && (block_bits_g(g, b, by - 2, bx - 1) & 8)) p[1] = id - 2 * g.BW - 1;
-            }
-        }
-        const int pl0 = p[0] >= 0 ? glab[p[0]] : -2, pl1 = p[1] >= 0 ? glab[p[1]] : -2;
-        int first = -3;
-#pragma unroll
-        for (int j = 0; j < 2; j++) {
-            if (c[j] < 0) continue;
-            const int lc = glab[c[j]];
-            if (lc == pl0 || lc == pl1 || lc == first) continue;
-            first = lc;
-            link(c[j]);
-        }
-    } else if (bits && kind == 2 && lby > 0 && bx + 1 < g.BW) {
-        // contact UR (tile to the right); redundant when the upper block is
-        // connected to this block and to that same block (its right neighbour)
-        if ((bits & 2) && (block_bits_g(g, b, by - 1, bx + 1) & 4)) {
-            const uint32_t ub = block_bits_g(g, b, by - 1, bx);
-            const uint32_t ur = block_bits_g(g, b, by - 1, bx + 1);
-            const bool covered = (bits & 3) && (ub & 12) && (ur & 5) && (ub & 10);
-            if (!covered) link(id - g.BW + 1);
+            if (lc[j] == pl[0] || lc[j] == pl[1] || lc[j] == pl[2] || lc[j] == done[0] || lc[j] == done[1]) continue;
+            done[j < 2 ? j : 1] = lc[j];
+            link(id, c[j]);
         }
     }
+    // side columns: lanes 0..TBH-1 the left column, lanes 32..32+TBH-1 the right
+    const int lby = lane & 31, side = lane >> 5;
+    const int by = by0 + lby;
+    if (lby < TBH && by < g.BH) {
+        if (side == 0 && bx0 > 0 && bx0 < g.BW) {
+            // contacts in the column to the left (other tile): L, and UL below the top row
+            const int bx = bx0, id = by * g.BW + bx;
+            const uint32_t bb = bits(by, bx);
+            int c[2] = {-1, -1}, p[2] = {-1, -1};
+            if (bb) {
+                if ((bb & 5) && (bits(by, bx - 1) & 10)) c[0] = id - 1;
+                if (lby > 0 && (bb & 1) && (bits(by - 1, bx - 1) & 8)) c[1] = id - g.BW - 1;
+                // predecessor on this border column: the upper block, if connected
+                if (lby > 0) {
+                    const uint32_t ub = bits(by - 1, bx);
+                    if ((bb & 3) && (ub & 12)) {
+                        if ((ub & 5) && (bits(by - 1, bx - 1) & 10)) p[0] = id - g.BW - 1;
+                        if (lby > 1 && (ub & 1) && (bits(by - 2, bx - 1) & 8)) p[1] = id - 2 * g.BW - 1;
+                    }
+                }
+            }
+            const int pl0 = p[0] >= 0 ? glab[p[0]] : -2, pl1 = p[1] >= 0 ? glab[p[1]] : -2;
+            const int lc0 = c[0] >= 0 ? glab[c[0]] : -4, lc1 = c[1] >= 0 ? glab[c[1]] : -4;
+            int first = -3;
+            if (c[0] >= 0 && lc0 != pl0 && lc0 != pl1) {
+                first = lc0;
+                link(id, c[0]);
+            }
+            if (c[1] >= 0 && lc1 != pl0 && lc1 != pl1 && lc1 != first) link(id, c[1]);
+        } else if (side == 1 && lby > 0 && bx0 + TBW < g.BW) {
+            // contact UR (tile to the right); redundant when the upper block is
+            // connected to this block and to that same block (its right neighbour)
+            const int bx = bx0 + TBW - 1, id = by * g.BW + bx;
+            const uint32_t bb = bits(by, bx);
+            if ((bb & 2) && (bits(by - 1, bx + 1) & 4)) {
+                const uint32_t ub = bits(by - 1, bx), ur = bits(by - 1, bx + 1);
+                const bool covered = (bb & 3) && (ub & 12) && (ur & 5) && (ub & 10);
+                if (!covered) link(id, id - g.BW + 1);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // the window is rewritten by the wave's next tile
 }
 
 // Point a border-touching tile-local root at its final root and carry its
@@ -807,10 +845,12 @@ __global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, M
 }
 
 template <int TBH>
-__global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int32_t *glab,
+__global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int ntiles, int32_t *glab,
                                                         unsigned long long *counters) {
+    __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
+    const int wv = threadIdx.x >> 6, tile = blockIdx.x * (kThreads / 64) + wv;
     int unions = 0, tries = 0;
-    ccl_merge_one<TBH>(g, b, ntx, (int64_t)blockIdx.x * kThreads + threadIdx.x, glab, unions, tries);
+    if (tile < ntiles) ccl_merge_tile<TBH>(g, b, ntx, tile, glab, win[wv], unions, tries);
     if (counters && (unions | tries)) {
         atomicAdd(&counters[0], (unsigned long long)unions);
         atomicAdd(&counters[1], (unsigned long long)(tries - unions));
@@ -907,7 +947,7 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 //   BK_WORDS  256 mask words (atoms: four 64-word wave tasks)
 //   BK_LOGIC  1024 mask words (Boolean steps)
 //   BK_NEAR   four near bands (64 words wide, kBatchNearRows rows high)
-//   BK_TILES  one labelling tile          BK_MERGE  256 border threads
+//   BK_TILES  one labelling tile          BK_MERGE  four tiles (one per wave)
 //   BK_BLOCKS 256 blocks                  BK_GATHER four 256-block wave tasks
 //   BK_PCTH   kPctUnit channel elements   BK_ONE    one per image
 
@@ -978,12 +1018,15 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_local(BatchArgs a, BRef b, BR
 
 template <int TBH>
 __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
+    __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
+    const int wv = threadIdx.x >> 6;
     int unions = 0, tries = 0;
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
-        const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
-        ccl_merge_one<TBH>(d.g, bref(d, b), ntx, (u_ - a.prefix[ii]) * kThreads + threadIdx.x,
-                           (int32_t *)(d.ws + d.off_glab), unions, tries);
+        const int ntx = (d.g.BW + kTileBW - 1) / kTileBW, nty = (d.g.BH + TBH - 1) / TBH;
+        const int tile = (int)(u_ - a.prefix[ii]) * (kThreads / 64) + wv;
+        if (tile < ntx * nty)
+            ccl_merge_tile<TBH>(d.g, bref(d, b), ntx, tile, (int32_t *)(d.ws + d.off_glab), win[wv], unions, tries);
     }
 }
 
@@ -1085,13 +1128,12 @@ hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z,
 hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &w) {
     if (g.nwords == 0) return hipSuccess;
     if (!valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
-    const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh);
-    const int64_t n = (int64_t)ntx * nty * (kTileBW + 2 * w.tbh);
-    const int grid = (int)((n + kThreads - 1) / kThreads);
+    const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh), ntiles = ntx * nty;
+    const int grid = (ntiles + kThreads / 64 - 1) / (kThreads / 64);  // one wave per tile
     switch (w.tbh) {
-    case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, w.glab, w.counters); break;
-    case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, w.glab, w.counters); break;
-    default: k_ccl_merge<32><<<grid, kThreads, 0, s>>>(g, b, ntx, w.glab, w.counters); break;
+    case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters); break;
+    case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters); break;
+    default: k_ccl_merge<32><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters); break;
     }
     return hipGetLastError();
 }
@@ -1168,7 +1210,7 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     case BK_LOGIC: return (g.nwords + kThreads * kLogicUnroll - 1) / (kThreads * kLogicUnroll);
     case BK_NEAR: return (near_tasks(g, kBatchNearRows) + kThreads / 64 - 1) / (kThreads / 64);
     case BK_TILES: return ntiles;
-    case BK_MERGE: return (ntiles * (kTileBW + 2 * tbh) + kThreads - 1) / kThreads;
+    case BK_MERGE: return (ntiles + kThreads / 64 - 1) / (kThreads / 64);
     case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
     case BK_GATHER: return ((int64_t)g.BH * ((g.wpr + 7) / 8) + 3) / 4;
     case BK_PCTH: return ((int64_t)g.H * g.wpr * 64 + kPctUnit - 1) / kPctUnit;
