@@ -447,6 +447,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     const int r0 = ty * TR, wc0 = tx * TWW;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
 
+    int any = 0;
     for (int i = threadIdx.x; i < TR * TWW; i += kThreads) {
         const int r = i / TWW, w = i % TWW, yy = r0 + r, ww = wc0 + w;
         uint64_t v = 0;
@@ -455,6 +456,16 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
             if (ww == g.wpr - 1) v &= g.tail;
         }
         sb[r][w] = v;
+        any |= v != 0;
+    }
+    // a tile without passable pixels only clears its flag bytes (the flag pass
+    // reads every block's; no pass reads a background block's parent entry)
+    if (!__syncthreads_or(any)) {
+        for (int i = threadIdx.x; i < NB; i += kThreads) {
+            const int by = ty * TBH + i / TBW, bx = tx * TBW + i % TBW;
+            if (by < g.BH && bx < g.BW) gflag[(int64_t)by * g.BW + bx] = 0;
+        }
+        return;
     }
     for (int i = threadIdx.x; i < (TR + 2) * (TWW + 2); i += kThreads) {
         const int r = i / (TWW + 2), w = i % (TWW + 2), yy = r0 + r - 1, ww = wc0 + w - 1;
