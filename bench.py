@@ -15,6 +15,7 @@ Before timing, every output is compared bit for bit with the CPU oracle
 """
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -107,7 +108,7 @@ def bench_chain(vlg, lib, steps):
             "gpixel_node_per_s": round(1024 * 1024 * info["nodes"] / (ms["graph"] / 1e3) / 1e9, 3)}
 
 
-def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512):
+def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512, square=False):
     """Uneven batch: `n` phantom images (sides uniform in [128, 2048], four
     float32 channels, generated in device memory) and the shared 60-node
     segmentation formula.  One vlg_check_batch call per step: per-image
@@ -116,7 +117,7 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512):
     import numpy as np
     import torch
     from synth import formulas, images
-    sizes = images.batch_sizes(seed, n, 128, 2048)
+    sizes = images.batch_sizes(seed, n, 128, 2048, square=square)
     src = formulas.segmentation_dag(seed)
     ctx = vlg.create(0)
     f = vlg.compile_formula(ctx, src)
@@ -139,8 +140,9 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512):
     harr = (ctypes.c_void_p * n)(*[im.handle.value for im in ims])
     # autotune the labelling tile on the batch itself
     tune = vlg.autotune_batch(ctx, f, ims, iters=1)
-    log(f"[bench] batch: autotuned tile rows {tune['ccl_tile_rows'][0]} "
-        f"({', '.join(f'{k}: {v:.2f} ms' for k, v in sorted(tune['ccl_tile_rows'][1].items()))})")
+    for name, (best, times) in tune.items():
+        log(f"[bench] batch: autotuned {name} {best} "
+            f"({', '.join(f'{k}: {v:.2f} ms' for k, v in sorted(times.items()))})")
 
     def step():
         rc = lib.vlg_check_batch(ctx.handle, f.handle, harr, n, flat, 0, 1)
@@ -174,10 +176,11 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512):
         ms[mode] = (time.perf_counter() - t0) * 1e3 / steps
         log(f"[bench] batch {mode}: {ms[mode]:.3f} ms per batch")
     px = sum(h * w for h, w in sizes)
-    res = {"workload": f"uneven_batch_{n}: {n} phantom images, sides U[128,2048], f32 x4 channels, "
+    res = {"workload": f"uneven_batch_{n}{'_square' if square else ''}: {n} phantom images, "
+                       f"{'square sides' if square else 'sides H, W'} U[128,2048], f32 x4 channels, "
                        f"{nodes}-node segmentation formula, {nout} outputs",
            "images": n, "gpixels": round(px / 1e9, 4), "nodes": nodes,
-           "ccl_tile_rows": tune["ccl_tile_rows"][0],
+           "ccl_tile_rows": tune["ccl_tile_rows"][0], "batch_grid": tune["batch_grid"][0],
            "perop_ms": round(ms["perop"], 3), "fused_ms": round(ms["fused"], 3), "graph_ms": round(ms["graph"], 3),
            "speedup_graph_vs_perop": round(ms["perop"] / ms["graph"], 3),
            "gpixel_node_per_s": round(px * nodes / (ms["graph"] / 1e3) / 1e9, 3),
@@ -280,11 +283,12 @@ def bench_paper_grow(vlg, lib, steps, check_oracle, side=7680):
                              "start of computation to file saved (OpenCL, uint16 MRI slice)"}
 
 
-def bench_serve(vlg, n_req, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
+def bench_serve(vlg, n_req, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
     """Serving loop: Poisson arrivals over a pool of resident images (sides
     log-uniform in [256, 8192], float32) and formulas (20-2000 nodes, up to 50
-    reach-type); saturation throughput first, then p50/p99 latency
-    (submission to outputs written) at fractions of it."""
+    reach-type); saturation throughput first, then p50/p99 latency (scheduled
+    arrival to outputs written) and throughput at fractions of it, each level
+    over n_req requests after n_warm warm-up requests."""
     import numpy as np
     import torch
     from synth import formulas, images
@@ -301,6 +305,7 @@ def bench_serve(vlg, n_req, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0
         fs.append(vlg.compile_formula(ctx, formulas.random_dag(500 + k, n_nodes=n,
                                                                n_reach=int(rng.integers(0, min(50, n // 10) + 1)))))
     nouts = [vlg.formula_info(f)["outputs"] for f in fs]
+    nodes = [vlg.formula_info(f)["nodes"] for f in fs]
     ring = 8
     bufs = {}
 
@@ -312,7 +317,12 @@ def bench_serve(vlg, n_req, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0
                          for _ in range(nouts[k])]
         return bufs[key]
 
-    reqs = [(int(rng.integers(0, len(imgs))), int(rng.integers(0, len(fs)))) for _ in range(n_req)]
+    def work(i, k):  # pixel-node evaluations of one request
+        _, H, W = imgs[i].shape
+        return H * W * nodes[k]
+
+    total = n_warm + n_req
+    reqs = [(int(rng.integers(0, len(imgs))), int(rng.integers(0, len(fs)))) for _ in range(total)]
     for i, k in set(reqs):  # warm plans and buffers
         vlg.check_all(ctx, fs[k], imgs[i], outs=outs_for(i, k, 0))
     vlg.sync(ctx)
@@ -321,29 +331,35 @@ def bench_serve(vlg, n_req, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0
     ids = [srv.submit(fs[k], imgs[i], outs_for(i, k, r)) for r, (i, k) in enumerate(reqs)]
     for rid in ids:
         srv.wait(rid)
-    sat = n_req / (time.perf_counter() - t0)
-    log(f"[bench] serve: saturation {sat:.1f} req/s over {n_req} requests")
+    sat = total / (time.perf_counter() - t0)
+    log(f"[bench] serve: saturation {sat:.1f} req/s over {total} requests")
     out = {"workload": f"serve: {len(imgs)} resident images (sides {sides}), {len(fs)} formulas "
-                       f"({[vlg.formula_info(f)['nodes'] for f in fs]} nodes), {slots} slots",
+                       f"({nodes} nodes), {slots} slots, {budget >> 30} GiB pool, "
+                       f"{n_req} requests per level after {n_warm} warm-up",
            "saturation_req_per_s": round(sat, 2), "levels": []}
     for frac in fracs:
         rate = frac * sat
-        gaps = rng.exponential(1.0 / rate, n_req)
+        arrive = np.cumsum(rng.exponential(1.0 / rate, total))
         t_start = time.perf_counter()
-        ids, t_next = [], t_start
+        ids, late = [], []
         for r, (i, k) in enumerate(reqs):
-            t_next += gaps[r]
-            d = t_next - time.perf_counter()
+            d = t_start + arrive[r] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
+            late.append(max(0.0, -d) * 1e3)  # submitted after its scheduled arrival
             ids.append(srv.submit(fs[k], imgs[i], outs_for(i, k, r)))
         lat = []
-        for rid in ids:
+        t_first = None
+        for r, rid in enumerate(ids):
             q, rr = srv.wait(rid)
-            lat.append(q + rr)
-        wall = time.perf_counter() - t_start
-        lat = np.array(lat)
+            if r == n_warm:
+                t_first = t_start + arrive[r]
+            lat.append(late[r] + q + rr)
+        wall = time.perf_counter() - t_first
+        lat = np.array(lat[n_warm:])
+        px = sum(work(i, k) for i, k in reqs[n_warm:])
         lvl = {"offered_req_per_s": round(rate, 2), "achieved_req_per_s": round(n_req / wall, 2),
+               "gpixel_node_per_s": round(px / wall / 1e9, 2),
                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
         log(f"[bench] serve at {frac:.0%}: {lvl}")
         out["levels"].append(lvl)
@@ -364,7 +380,7 @@ def main():
     ap.add_argument("--skip-oracle", action="store_true", help="no parity gate, no CPU baseline")
     ap.add_argument("--no-chain", action="store_true", help="skip the 10,500-node chain measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load level (after 200 warm-up)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-image uneven batch measurement")
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-pixelwise", action="store_true", help="skip the streaming roofline of the pixel-wise kernels")
@@ -432,9 +448,11 @@ def main():
         log("[bench] parity: all outputs bit-exact in perop, fused and graph modes")
 
     tune = vlg.autotune(ctx, f, im, iters=3)
-    tile_rows, tile_ms = tune["ccl_tile_rows"]
-    log(f"[bench] autotune: labelling tile rows {tile_rows} "
-        f"({', '.join(f'{k}: {v:.3f} ms' for k, v in sorted(tile_ms.items()))})")
+    for name, (best, times) in tune.items():
+        log(f"[bench] autotune: {name} {best} "
+            f"({', '.join(f'{k}: {v:.3f} ms' for k, v in sorted(times.items()))})")
+    tile_rows = tune["ccl_tile_rows"][0]
+    near_rows = tune["near_band_rows"][0] if "near_band_rows" in tune else None
     ms = {}
     for mode in ("perop", "fused", "graph"):
         ms[mode] = time_mode(vlg, lib, ctx, f, im, arr, mode, args.steps, args.warmup)
@@ -468,8 +486,10 @@ def main():
         "config": {"workload": f"ellipse_maze_{S}: {S}x{S} f32 x3 channels, {nodes}-node formula "
                                f"({n_ccl} reach-type), {nout} outputs",
                    "image": [3, S, S], "nodes": nodes, "outputs": nout, "executor": "graph",
-                   "ccl_tile_rows": tile_rows, "labellings": info["labellings"],
-                   "launches": info["launches_fused"]},
+                   "ccl_tile_rows": tile_rows, "near_band_rows": near_rows, "labellings": info["labellings"],
+                   "launches": info["launches_fused"],
+                   "input_sha256": {"image": images.digest(img),
+                                    "formula": hashlib.sha256(src.encode()).hexdigest()}},
         "perop_ms": round(ms["perop"], 4),
         "fused_ms": round(ms["fused"], 4),
         "speedup_graph_vs_perop": round(ms["perop"] / t, 3),
@@ -489,6 +509,7 @@ def main():
         line["pixelwise"] = bench_pixelwise(vlg, 5)
     if not args.no_batch:
         line["batch"] = bench_batch(vlg, lib, 3, not args.skip_oracle, n=args.batch_images)
+        line["batch_square"] = bench_batch(vlg, lib, 3, not args.skip_oracle, n=args.batch_images, square=True)
     if not args.no_serve:
         line["serve"] = bench_serve(vlg, args.serve_requests)
     print(json.dumps(line), flush=True)

@@ -189,11 +189,19 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
 
 /* Tunables of the executor.  Each has a default, may be forced for a
  * context, and is otherwise looked up per image shape class (ceil(log2 H),
- * ceil(log2 W)) in the context's table, which vlg_autotune fills.
+ * ceil(log2 W)) in the context's table, which vlg_autotune fills (batches:
+ * per batch class, filled by vlg_autotune_batch).
  *   VLG_TUNE_CCL_TILE_ROWS: block rows (2x2 pixels each) per labelling tile:
  *     8, 16 or 32; tiles are 128 pixels wide.  Taller tiles do more work in
- *     LDS and leave fewer tile borders to merge globally. */
+ *     LDS and leave fewer tile borders to merge globally.
+ *   VLG_TUNE_NEAR_ROWS: rows per band of the near kernel: 4, 8, 16 or 32
+ *     (default: from the image size).  Taller bands reload fewer halo rows,
+ *     shorter ones give more parallel bands.
+ *   VLG_TUNE_BATCH_GRID: workgroups of a persistent batched launch: 1024,
+ *     2048 (default), 4096 or 8192. */
 #define VLG_TUNE_CCL_TILE_ROWS 0
+#define VLG_TUNE_NEAR_ROWS 1
+#define VLG_TUNE_BATCH_GRID 2
 /* Force `value` for every image (value 0 returns to table/default). */
 int vlg_set_tunable(vlg_ctx *ctx, int which, int value);
 /* The value used for an image of height x width on this context. */
@@ -207,24 +215,29 @@ typedef struct vlg_tune_report {
     double ms[8];       /* mean time of one evaluation of f on img per candidate */
 } vlg_tune_report;
 /* Autotuner: evaluate every output of f on img `iters` times per candidate
- * value of each tunable (fused schedule, HIP events on the context's stream)
- * and store the fastest value for img's shape class.  Writes one report per
- * tunable to out[0 .. max_out-1]; *n_out receives the number of tunables. */
+ * value of each tunable that applies (labelling tile rows when f has a
+ * reach-type node, near band rows when it has a near step; fused schedule,
+ * HIP events on the context's stream), one tunable after the other, and
+ * store the fastest value for img's shape class.  Writes one report per
+ * tunable tried to out[0 .. max_out-1]; *n_out receives their number. */
 int vlg_autotune(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_tune_report *out,
                  int max_out, int *n_out);
 /* Autotuner for batches: evaluate every output of f on the n images with the
  * batched schedule (as vlg_check_batch in fused mode) `iters` times per
- * candidate and store the fastest value for the batch class (ceil(log2 n),
- * ceil(log2 of the mean pixels per image)); vlg_check_batch then uses it for
- * batches of that class (otherwise the value of its largest image's shape
- * class).  Outputs go to internal buffers.  Same reports as vlg_autotune. */
+ * candidate of the labelling tile rows (when f has a reach-type node) and of
+ * the persistent grid size, and store the fastest values for the batch class
+ * (ceil(log2 n), ceil(log2 of the mean pixels per image)); vlg_check_batch
+ * then uses them for batches of that class (otherwise the tile rows of its
+ * largest image's shape class and the default grid).  Outputs go to internal
+ * buffers.  Same reports as vlg_autotune. */
 int vlg_autotune_batch(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *const *imgs, int n, int iters,
                        vlg_tune_report *out, int max_out, int *n_out);
 /* Save / load the context's tuning table as JSON lines
  * {"arch": "gfx950", "tunable": ..., "h_class": ..., "w_class": ..., "value": ...}
- * (tunable "ccl_tile_rows_batch" for batch classes, whose two class numbers
- * are the batch and mean-image classes); loading keeps only the entries of
- * the context's device architecture. */
+ * with tunable "ccl_tile_rows", "near_band_rows" or "batch_grid" (suffix
+ * "_batch" for batch classes, whose two class numbers are the batch and
+ * mean-image classes); loading keeps only the entries of the context's
+ * device architecture. */
 int vlg_tune_save(vlg_ctx *ctx, const char *path);
 int vlg_tune_load(vlg_ctx *ctx, const char *path);
 

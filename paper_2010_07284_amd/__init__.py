@@ -31,7 +31,7 @@ class Context:
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
-        if h and _lib.loaded():
+        if h and _lib is not None and _lib.loaded():
             _lib.lib().vlg_destroy(h)
 
 
@@ -43,7 +43,7 @@ class Image:
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
-        if h and _lib.loaded():
+        if h and _lib is not None and _lib.loaded():
             _lib.lib().vlg_image_free(h)
 
 
@@ -53,7 +53,7 @@ class Formula:
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
-        if h and _lib.loaded():
+        if h and _lib is not None and _lib.loaded():
             _lib.lib().vlg_formula_free(h)
 
 
@@ -217,7 +217,7 @@ def profile(ctx, f, img, iters=5):
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
 
 
-TUNABLES = {"ccl_tile_rows": 0}
+TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2}
 
 
 def set_tunable(ctx, name, value):
@@ -310,7 +310,7 @@ class Server:
             _lib.call("vlg_server_destroy", h)
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib.loaded():
+        if getattr(self, "handle", None) and _lib is not None and _lib.loaded():
             self.close()
 
 

@@ -90,14 +90,27 @@ struct GraphKey {
     bool operator<(const GraphKey &o) const { return v < o.v; }
 };
 
+// Tunables (VLG_TUNE_*): a value of 0 means "not set" (default rule).
+constexpr int kNumTunables = 3;
+const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid"};
+
+bool tunable_valid(int which, int v) {
+    switch (which) {
+    case VLG_TUNE_CCL_TILE_ROWS: return valid_tile_bh(v);
+    case VLG_TUNE_NEAR_ROWS: return valid_near_rows(v);
+    case VLG_TUNE_BATCH_GRID: return valid_batch_grid(v);
+    }
+    return false;
+}
+
 struct Tuning {
-    int ccl_tbh = kTileBHDefault;
+    int v[kNumTunables] = {0, 0, 0};
 };
 
 struct vlg_ctx {
     int device = 0;
     std::string arch;
-    int forced_tbh = 0;                             // 0: not forced
+    Tuning forced;                                  // 0 entries: not forced
     std::map<std::pair<int, int>, Tuning> tuned;    // shape class -> tuning
     std::map<std::pair<int, int>, Tuning> tuned_batch;  // (batch class, mean image class) -> tuning
     hipStream_t stream = nullptr;
@@ -177,17 +190,37 @@ int log2_class(int n) {
     return c;
 }
 
-Tuning tuning_for(const vlg_ctx *c, int H, int W) {
-    Tuning t;
+// The value of a tunable for an image of H x W: forced, else the shape
+// class's tuned value, else the default (0 for the near band height: chosen
+// from the image size by the launcher).
+int tuned_value(const vlg_ctx *c, int which, int H, int W) {
+    if (c->forced.v[which]) return c->forced.v[which];
     auto it = c->tuned.find({log2_class(H), log2_class(W)});
-    if (it != c->tuned.end()) t = it->second;
-    if (c->forced_tbh) t.ccl_tbh = c->forced_tbh;
-    return t;
+    if (it != c->tuned.end() && it->second.v[which]) return it->second.v[which];
+    switch (which) {
+    case VLG_TUNE_CCL_TILE_ROWS: return kTileBHDefault;
+    case VLG_TUNE_BATCH_GRID: return kBatchGridDefault;
+    }
+    return 0;
 }
+
+struct TuningShim {
+    int ccl_tbh;
+};
+TuningShim tuning_for(const vlg_ctx *c, int H, int W) { return {tuned_value(c, VLG_TUNE_CCL_TILE_ROWS, H, W)}; }
 
 // (ceil(log2 n), ceil(log2 mean pixels per image)) of a batch
 std::pair<int, int> batch_class(int n, int64_t pixels) {
     return {log2_class(n), log2_class((int)std::min<int64_t>(pixels / std::max(n, 1), 1 << 30))};
+}
+
+// The value of a tunable for a batch: forced, else the batch class's tuned
+// value, else `fallback`.
+int batch_value(const vlg_ctx *c, int which, int n, int64_t pixels, int fallback) {
+    if (c->forced.v[which]) return c->forced.v[which];
+    auto it = c->tuned_batch.find(batch_class(n, pixels));
+    if (it != c->tuned_batch.end() && it->second.v[which]) return it->second.v[which];
+    return fallback;
 }
 
 uint32_t pct_rank(double q, int64_t n) {
@@ -265,6 +298,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
     w.gflag = (uint8_t *)(base + L.off_gflag);
     w.counters = c->count_ccl ? c->counters : nullptr;
     w.tbh = tuning_for(c, img->H, img->W).ccl_tbh;
+    const int near_rows = tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W);
     const int64_t npix = (int64_t)img->H * img->W;
     for (size_t si = 0; si < P.steps.size(); si++) {
         const Step &s = P.steps[si];
@@ -289,7 +323,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                     const Step &t = P.steps[k];
                     b.ops[k - si] = NearOp{mref(t.x), mref(t.z), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out), t.op};
                 }
-                e = launch_near_batch(c->stream, g, b);
+                e = launch_near_batch(c->stream, g, b, near_rows);
             }
             if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
             for (size_t k = si; k < sj; k++) {
@@ -331,7 +365,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
             e = launch_logic(c->stream, g, mref(s.x), mref(s.y), s.op, s.inv_out, slot_ptr(s.out));
             break;
         case SK::Near:
-            e = launch_near(c->stream, g, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out));
+            e = launch_near(c->stream, g, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out), near_rows);
             break;
         case SK::CclLocal:
             e = launch_ccl_local(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w);
@@ -399,7 +433,8 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
         GraphKey key;
         key.v = {(uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)img->dev, (uintptr_t)img->H, (uintptr_t)img->W,
                  (uintptr_t)img->dtype, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)c->ws,
-                 (uintptr_t)tuning_for(c, img->H, img->W).ccl_tbh};
+                 (uintptr_t)tuning_for(c, img->H, img->W).ccl_tbh,
+                 (uintptr_t)tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W)};
         for (size_t k = 0; k < which.size(); k++) key.v.push_back((uintptr_t)outs[k]);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -469,10 +504,8 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
             tbh = tuning_for(c, imgs[i]->H, imgs[i]->W).ccl_tbh;
         }
     }
-    if (!c->forced_tbh) {
-        auto it = c->tuned_batch.find(batch_class(n, pixels));
-        if (it != c->tuned_batch.end()) tbh = it->second.ccl_tbh;
-    }
+    tbh = batch_value(c, VLG_TUNE_CCL_TILE_ROWS, n, pixels, tbh);
+    const int grid_cap = batch_value(c, VLG_TUNE_BATCH_GRID, n, pixels, kBatchGridDefault);
 
     // workspace: per-image layouts, then the descriptor block
     std::vector<Geo> geo(n);
@@ -552,6 +585,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
         BatchArgs a;
         a.n = n;
         a.dtype = dtype;
+        a.grid_cap = grid_cap;
         a.imgs = (const BImg *)(base + d_imgs);
         a.prefix = (const int64_t *)(base + d_prefix) + (size_t)kind * (n + 1);
         return a;
@@ -669,7 +703,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
     if (c->mode == VLG_MODE_GRAPH) {
         GraphKey key;
         key.v = {(uintptr_t)0xBA7C, (uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)c->ws, (uintptr_t)tbh,
-                 (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)n};
+                 (uintptr_t)grid_cap, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)n};
         for (int k = 0; k < n; k++) {
             const vlg_image *im = imgs[idx[k]];
             key.v.insert(key.v.end(), {(uintptr_t)im->dev, (uintptr_t)im->H, (uintptr_t)im->W,
@@ -747,6 +781,56 @@ const char *last_error_text() { return g_err.c_str(); }
 int set_last_error(int code, const std::string &msg) { return fail(code, msg); }
 size_t formula_outputs(const vlg_formula *f) { return f->dag.outputs.size(); }
 }  // namespace vlg
+
+namespace {
+
+// Time `run` (which enqueues one evaluation) for every candidate of each
+// tunable in turn, each forced in turn; the fastest value of a tunable is
+// kept (via `keep`) before the next tunable is tried.
+template <typename Run, typename Keep>
+int tune_loop(vlg_ctx *c, const std::vector<std::pair<int, std::vector<int>>> &space, int iters, Run run,
+              Keep keep, vlg_tune_report *out, int max_out, int *n_out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = VLG_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(VLG_EHIP, "event create");
+    const Tuning saved = c->forced;
+    *n_out = 0;
+    for (size_t t = 0; t < space.size() && rc == VLG_OK; t++) {
+        const int which = space[t].first;
+        vlg_tune_report rep;
+        std::memset(&rep, 0, sizeof rep);
+        rep.which = which;
+        double best_ms = 1e30;
+        for (int cand : space[t].second) {
+            c->forced.v[which] = cand;
+            rc = run();  // warm-up
+            if (rc == VLG_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
+            for (int it = 0; it < iters && rc == VLG_OK; it++) rc = run();
+            float ms = 0.f;
+            if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(VLG_EHIP, "event timing");
+            if (rc != VLG_OK) break;
+            rep.candidates[rep.n] = cand;
+            rep.ms[rep.n] = ms / iters;
+            if (rep.ms[rep.n] < best_ms) {
+                best_ms = rep.ms[rep.n];
+                rep.best = cand;
+            }
+            rep.n++;
+        }
+        c->forced.v[which] = saved.v[which];
+        if (rc != VLG_OK) break;
+        keep(which, rep.best);
+        if (out && *n_out < max_out) out[*n_out] = rep;
+        (*n_out)++;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1089,16 +1173,18 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
 
 int vlg_set_tunable(vlg_ctx *c, int which, int value) {
     if (!c) return fail(VLG_EINVAL, "null context");
-    if (which != VLG_TUNE_CCL_TILE_ROWS) return fail(VLG_EINVAL, "unknown tunable");
-    if (value != 0 && !valid_tile_bh(value)) return fail(VLG_EINVAL, "tile rows must be 8, 16 or 32");
-    c->forced_tbh = value;
+    if (which < 0 || which >= kNumTunables) return fail(VLG_EINVAL, "unknown tunable");
+    if (value != 0 && !tunable_valid(which, value))
+        return fail(VLG_EINVAL, std::string("bad value for ") + kTunableNames[which]);
+    c->forced.v[which] = value;
     return VLG_OK;
 }
 
 int vlg_get_tunable(vlg_ctx *c, int which, int height, int width, int *value) {
     if (!c || !value) return fail(VLG_EINVAL, "null argument");
-    if (which != VLG_TUNE_CCL_TILE_ROWS) return fail(VLG_EINVAL, "unknown tunable");
-    *value = tuning_for(c, height, width).ccl_tbh;
+    if (which < 0 || which >= kNumTunables) return fail(VLG_EINVAL, "unknown tunable");
+    *value = tuned_value(c, which, height, width);
+    if (which == VLG_TUNE_NEAR_ROWS && *value == 0) *value = near_band_rows(make_geo(height, width));
     return VLG_OK;
 }
 
@@ -1108,54 +1194,26 @@ int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int it
     vlg_formula *f = const_cast<vlg_formula *>(cf);
     if (f->max_chan >= img->C) return fail(VLG_ESHAPE, "formula uses a channel the image lacks");
     DeviceGuard dg(c->device);
-    *n_out = 1;
-    vlg_tune_report rep;
-    std::memset(&rep, 0, sizeof rep);
-    rep.which = VLG_TUNE_CCL_TILE_ROWS;
-    const int cands[3] = {8, 16, 32};
+    *n_out = 0;
     std::vector<int> which(f->dag.outputs.size());
     for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
     const Plan &P = f->plan(which, Mode::Fused);
     const Geo g = make_geo(img->H, img->W);
-    const int saved_forced = c->forced_tbh;
-    rep.best = tuning_for(c, img->H, img->W).ccl_tbh;
-    if (g.nwords > 0 && P.ccl_count > 0) {
-        Layout L = layout_for(P, g, true, false);
-        int rc = ensure_ws(c, L.total);
-        if (rc != VLG_OK) return rc;
-        std::vector<uint64_t *> ext(which.size());
-        for (size_t k = 0; k < which.size(); k++)
-            ext[k] = (uint64_t *)((char *)c->ws + L.off_stage + k * L.mask_bytes);
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        double best_ms = 1e30;
-        for (int ci = 0; ci < 3; ci++) {
-            c->forced_tbh = cands[ci];
-            rc = enqueue_plan(c, P, img, L, ext);  // warm-up
-            if (rc == VLG_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
-            for (int it = 0; it < iters && rc == VLG_OK; it++) rc = enqueue_plan(c, P, img, L, ext);
-            float ms = 0.f;
-            if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-                rc = fail(VLG_EHIP, "event timing");
-            if (rc != VLG_OK) break;
-            rep.candidates[rep.n] = cands[ci];
-            rep.ms[rep.n] = ms / iters;
-            if (rep.ms[rep.n] < best_ms) {
-                best_ms = rep.ms[rep.n];
-                rep.best = cands[ci];
-            }
-            rep.n++;
-        }
-        c->forced_tbh = saved_forced;
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (rc != VLG_OK) return rc;
-        c->tuned[{log2_class(img->H), log2_class(img->W)}].ccl_tbh = rep.best;
-    }
-    if (out && max_out > 0) out[0] = rep;
-    return VLG_OK;
+    if (g.nwords == 0) return VLG_OK;
+    bool has_near = false;
+    for (const Step &st : P.steps) has_near |= st.kind == SK::Near;
+    std::vector<std::pair<int, std::vector<int>>> space;
+    if (P.ccl_count > 0) space.push_back({VLG_TUNE_CCL_TILE_ROWS, {8, 16, 32}});
+    if (has_near) space.push_back({VLG_TUNE_NEAR_ROWS, {4, 8, 16, 32}});
+    Layout L = layout_for(P, g, true, false);
+    int rc = ensure_ws(c, L.total);
+    if (rc != VLG_OK) return rc;
+    std::vector<uint64_t *> ext(which.size());
+    for (size_t k = 0; k < which.size(); k++) ext[k] = (uint64_t *)((char *)c->ws + L.off_stage + k * L.mask_bytes);
+    const std::pair<int, int> cls{log2_class(img->H), log2_class(img->W)};
+    return tune_loop(
+        c, space, iters, [&] { return enqueue_plan(c, P, img, L, ext); },
+        [&](int w, int best) { c->tuned[cls].v[w] = best; }, out, max_out, n_out);
 }
 
 int vlg_autotune_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *imgs, int n, int iters,
@@ -1172,64 +1230,40 @@ int vlg_autotune_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const
         pixels += (int64_t)imgs[i]->H * imgs[i]->W;
     }
     DeviceGuard dg(c->device);
-    *n_out = 1;
-    vlg_tune_report rep;
-    std::memset(&rep, 0, sizeof rep);
-    rep.which = VLG_TUNE_CCL_TILE_ROWS;
-    const int cands[3] = {8, 16, 32};
+    *n_out = 0;
     const size_t nout = f->dag.outputs.size();
+    std::vector<int> all(nout);
+    for (size_t i = 0; i < nout; i++) all[i] = (int)i;
+    const Plan &P = f->plan(all, Mode::Fused);
     std::vector<void *> outs((size_t)n * nout, nullptr);
     std::vector<int> idx((size_t)n);
     for (int i = 0; i < n; i++) idx[(size_t)i] = i;
-    const int saved_forced = c->forced_tbh, saved_mode = c->mode;
+    std::vector<std::pair<int, std::vector<int>>> space;
+    if (P.ccl_count > 0) space.push_back({VLG_TUNE_CCL_TILE_ROWS, {8, 16, 32}});
+    space.push_back({VLG_TUNE_BATCH_GRID, {1024, 2048, 4096, 8192}});
+    const int saved_mode = c->mode;
     c->mode = VLG_MODE_FUSED;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int rc = VLG_OK;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(VLG_EHIP, "event create");
-    double best_ms = 1e30;
-    for (int ci = 0; ci < 3 && rc == VLG_OK; ci++) {
-        c->forced_tbh = cands[ci];
-        rc = run_batch(c, f, imgs, idx, outs.data(), VLG_PACKED64, VLG_DEVICE);  // warm-up
-        if (rc == VLG_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
-        for (int it = 0; it < iters && rc == VLG_OK; it++)
-            rc = run_batch(c, f, imgs, idx, outs.data(), VLG_PACKED64, VLG_DEVICE);
-        float ms = 0.f;
-        if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            rc = fail(VLG_EHIP, "event timing");
-        if (rc != VLG_OK) break;
-        rep.candidates[rep.n] = cands[ci];
-        rep.ms[rep.n] = ms / iters;
-        if (rep.ms[rep.n] < best_ms) {
-            best_ms = rep.ms[rep.n];
-            rep.best = cands[ci];
-        }
-        rep.n++;
-    }
-    c->forced_tbh = saved_forced;
+    const std::pair<int, int> cls = batch_class(n, pixels);
+    const int rc = tune_loop(
+        c, space, iters, [&] { return run_batch(c, f, imgs, idx, outs.data(), VLG_PACKED64, VLG_DEVICE); },
+        [&](int w, int best) { c->tuned_batch[cls].v[w] = best; }, out, max_out, n_out);
     c->mode = saved_mode;
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (rc != VLG_OK) return rc;
-    c->tuned_batch[batch_class(n, pixels)].ccl_tbh = rep.best;
-    if (out && max_out > 0) out[0] = rep;
-    return VLG_OK;
+    return rc;
 }
 
 int vlg_tune_save(vlg_ctx *c, const char *path) {
     if (!c || !path) return fail(VLG_EINVAL, "null argument");
     FILE *fp = std::fopen(path, "w");
     if (!fp) return fail(VLG_EINVAL, std::string("cannot write ") + path);
-    for (const auto &kv : c->tuned)
-        std::fprintf(fp,
-                     "{\"arch\": \"%s\", \"tunable\": \"ccl_tile_rows\", \"h_class\": %d, \"w_class\": %d, "
-                     "\"value\": %d}\n",
-                     c->arch.c_str(), kv.first.first, kv.first.second, kv.second.ccl_tbh);
-    for (const auto &kv : c->tuned_batch)
-        std::fprintf(fp,
-                     "{\"arch\": \"%s\", \"tunable\": \"ccl_tile_rows_batch\", \"h_class\": %d, \"w_class\": %d, "
-                     "\"value\": %d}\n",
-                     c->arch.c_str(), kv.first.first, kv.first.second, kv.second.ccl_tbh);
+    for (int batch = 0; batch < 2; batch++)
+        for (const auto &kv : batch ? c->tuned_batch : c->tuned)
+            for (int w = 0; w < kNumTunables; w++)
+                if (kv.second.v[w])
+                    std::fprintf(fp,
+                                 "{\"arch\": \"%s\", \"tunable\": \"%s%s\", \"h_class\": %d, \"w_class\": %d, "
+                                 "\"value\": %d}\n",
+                                 c->arch.c_str(), kTunableNames[w], batch ? "_batch" : "", kv.first.first,
+                                 kv.first.second, kv.second.v[w]);
     std::fclose(fp);
     return VLG_OK;
 }
@@ -1246,9 +1280,13 @@ int vlg_tune_load(vlg_ctx *c, const char *path) {
                               "\"value\": %d}",
                         arch, tun, &hc, &wc, &v) != 5)
             continue;
-        if (c->arch != arch || !valid_tile_bh(v)) continue;
-        if (std::string(tun) == "ccl_tile_rows") c->tuned[{hc, wc}].ccl_tbh = v;
-        if (std::string(tun) == "ccl_tile_rows_batch") c->tuned_batch[{hc, wc}].ccl_tbh = v;
+        if (c->arch != arch) continue;
+        const std::string name(tun);
+        for (int w = 0; w < kNumTunables; w++) {
+            if (!tunable_valid(w, v)) continue;
+            if (name == kTunableNames[w]) c->tuned[{hc, wc}].v[w] = v;
+            if (name == std::string(kTunableNames[w]) + "_batch") c->tuned_batch[{hc, wc}].v[w] = v;
+        }
     }
     std::fclose(fp);
     return VLG_OK;

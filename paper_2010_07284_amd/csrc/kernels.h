@@ -37,6 +37,9 @@ __host__ __device__ inline int near_band_rows(const Geo &g) {
     return R;
 }
 constexpr int kBatchNearRows = 8;
+inline bool valid_near_rows(int r) { return r == 4 || r == 8 || r == 16 || r == 32; }
+constexpr int kBatchGridDefault = 2048;
+inline bool valid_batch_grid(int n) { return n == 1024 || n == 2048 || n == 4096 || n == 8192; }
 __host__ __device__ inline int64_t near_tasks(const Geo &g, int R) {
     return (int64_t)((g.H + R - 1) / R) * ((g.wpr + 63) / 64);
 }
@@ -68,7 +71,9 @@ struct AtomLaunch {
 
 hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out);
 // out = (N(x) ^ inv_out) OP z with OP = and (zop 0) or or (zop 1)
-hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, int zop, uint64_t *out);
+// rows: band height (4, 8, 16 or 32; 0 = near_band_rows(g))
+hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, int zop, uint64_t *out,
+                       int rows = 0);
 hipError_t launch_atoms(hipStream_t s, const Geo &g, const void *chan, int dtype, const AtomLaunch &a);
 hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const CclWork &w);
 hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &w);
@@ -99,7 +104,7 @@ struct NearBatch {
     NearOp ops[kBatchMax];
 };
 hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b);
-hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b);
+hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b, int rows = 0);
 // canon: [BH*BW] int32 scratch
 hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *canon,
                              int32_t *labels);
@@ -135,6 +140,7 @@ enum BatchKind { BK_WORDS = 0, BK_LOGIC, BK_NEAR, BK_TILES, BK_MERGE, BK_BLOCKS,
 struct BatchArgs {
     int n;
     int dtype;                // image pixel type (all images of a batch share it)
+    int grid_cap;             // most workgroups of a persistent launch (host side)
     const BImg *imgs;
     const int64_t *prefix;    // [n+1] units of the launch's kind, prefix sums
 };

@@ -381,14 +381,30 @@ __device__ void lds_unite(int *L, int a, int b) {
 // kernel); that costs retries, never correctness: every value ever stored in
 // L[x] is an ancestor of x (L[x] <= x), sets only grow, and a failed
 // atomicMin hands back the current parent, which is then united in turn.
-__device__ int g_find(VLG_GLOBAL int *L, int x) {
+//
+// g_find2: the roots of a and b, walked in lockstep (path halving on both) so
+// that the loads of the two paths overlap.
+__device__ __forceinline__ void g_find2(VLG_GLOBAL int *L, int &a, int &b) {
     while (true) {
-        const int p = L[x];
-        if (p == x) return x;
-        const int gp = L[p];
-        if (gp == p) return p;
-        L[x] = gp;  // path halving
-        x = gp;
+        const int pa = L[a], pb = L[b];
+        if (pa == a && pb == b) return;
+        const int ga = L[pa], gb = L[pb];
+        if (pa != a) {
+            if (ga == pa) {
+                a = pa;
+            } else {
+                L[a] = ga;  // path halving
+                a = ga;
+            }
+        }
+        if (pb != b) {
+            if (gb == pb) {
+                b = pb;
+            } else {
+                L[b] = gb;
+                b = gb;
+            }
+        }
     }
 }
 
@@ -396,8 +412,7 @@ __device__ int g_unite(VLG_GLOBAL int *L, int a, int b) {
     int tries = 0;
     while (true) {
         tries++;
-        a = g_find(L, a);
-        b = g_find(L, b);
+        g_find2(L, a, b);
         if (a == b) return tries;
         if (a < b) {
             const int t = a;
@@ -812,8 +827,7 @@ __global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int o
 }
 
 __global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_out, MRef z, int zop,
-                                                   uint64_t *__restrict__ out) {
-    const int R = near_band_rows(g);
+                                                   uint64_t *__restrict__ out, int R) {
     const int64_t ntasks = near_tasks(g, R), nwaves = (int64_t)gridDim.x * (kThreads / 64);
     for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
         near_task(g, x, inv_out, z, zop, out, t, R);
@@ -827,9 +841,8 @@ __global__ __launch_bounds__(kThreads) void k_logic_batch(Geo g, LogicBatch bt) 
                 (int64_t)gridDim.x * kThreads, g.nwords);
 }
 
-__global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt) {
+__global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt, int R) {
     const NearOp &o = bt.ops[blockIdx.y];
-    const int R = near_band_rows(g);
     const int64_t ntasks = near_tasks(g, R), nwaves = (int64_t)gridDim.x * (kThreads / 64);
     for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
         near_task(g, o.x, o.inv_out, o.z, o.zop, o.out, t, R);
@@ -915,7 +928,10 @@ __global__ __launch_bounds__(kThreads) void k_ccl_canon(Geo g, MRef b, const int
         int m = mine ? p : 0x7fffffff;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off));
-        if (lane == leader) atomicMin(&canon[r0], m);
+        // a giant component would serialise every wave on one address: skip
+        // the atomic when the root already holds a smaller index
+        if (lane == leader && m < __hip_atomic_load(&canon[r0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMin(&canon[r0], m);
     }
 }
 
@@ -1103,10 +1119,13 @@ hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int
     return hipGetLastError();
 }
 
-hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, int zop, uint64_t *out) {
+hipError_t launch_near(hipStream_t s, const Geo &g, MRef x, int inv_out, MRef z, int zop, uint64_t *out,
+                       int rows) {
     if (g.nwords == 0) return hipSuccess;
-    k_near<<<grid_for(near_tasks(g), kThreads / 64, 8192), kThreads, 0, s>>>(g, x, inv_out ? ~0ull : 0ull, z, zop,
-                                                                                 out);
+    if (rows == 0) rows = near_band_rows(g);
+    if (!valid_near_rows(rows)) return hipErrorInvalidValue;
+    k_near<<<grid_for(near_tasks(g, rows), kThreads / 64, 8192), kThreads, 0, s>>>(g, x, inv_out ? ~0ull : 0ull, z,
+                                                                                       zop, out, rows);
     return hipGetLastError();
 }
 
@@ -1179,10 +1198,12 @@ hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b) 
     return hipGetLastError();
 }
 
-hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b) {
+hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b, int rows) {
     if (g.nwords == 0 || b.n == 0) return hipSuccess;
-    dim3 grid(grid_for(near_tasks(g), kThreads / 64, 8192), b.n);
-    k_near_batch<<<grid, kThreads, 0, s>>>(g, b);
+    if (rows == 0) rows = near_band_rows(g);
+    if (!valid_near_rows(rows)) return hipErrorInvalidValue;
+    dim3 grid(grid_for(near_tasks(g, rows), kThreads / 64, 8192), b.n);
+    k_near_batch<<<grid, kThreads, 0, s>>>(g, b, rows);
     return hipGetLastError();
 }
 
@@ -1230,33 +1251,35 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     return 0;
 }
 
-static int persistent_grid(int64_t total) { return grid_for(total, 1, 2048); }
+static int persistent_grid(const BatchArgs &a, int64_t total) {
+    return grid_for(total, 1, valid_batch_grid(a.grid_cap) ? a.grid_cap : kBatchGridDefault);
+}
 
 hipError_t launch_b_atoms(hipStream_t s, const BatchArgs &a, int64_t total, const BAtoms &op) {
     if (total == 0) return hipSuccess;
     if (op.n < 1 || op.n > kMaxAtomsPerLaunch) return hipErrorInvalidValue;
-    if (a.dtype == 1) kb_atoms<uint8_t><<<persistent_grid(total), kThreads, 0, s>>>(a, op);
-    else kb_atoms<float><<<persistent_grid(total), kThreads, 0, s>>>(a, op);
+    if (a.dtype == 1) kb_atoms<uint8_t><<<persistent_grid(a, total), kThreads, 0, s>>>(a, op);
+    else kb_atoms<float><<<persistent_grid(a, total), kThreads, 0, s>>>(a, op);
     return hipGetLastError();
 }
 
 hipError_t launch_b_logic(hipStream_t s, const BatchArgs &a, int64_t total, const BLogic &op) {
     if (total == 0 || op.n == 0) return hipSuccess;
-    dim3 grid(persistent_grid(total), op.n);
+    dim3 grid(persistent_grid(a, total), op.n);
     kb_logic<<<grid, kThreads, 0, s>>>(a, op);
     return hipGetLastError();
 }
 
 hipError_t launch_b_near(hipStream_t s, const BatchArgs &a, int64_t total, const BNear &op) {
     if (total == 0 || op.n == 0) return hipSuccess;
-    dim3 grid(persistent_grid(total), op.n);
+    dim3 grid(persistent_grid(a, total), op.n);
     kb_near<<<grid, kThreads, 0, s>>>(a, op);
     return hipGetLastError();
 }
 
 hipError_t launch_b_ccl_local(hipStream_t s, const BatchArgs &a, int64_t total, int tbh, BRef b, BRef y, BRef z) {
     if (total == 0) return hipSuccess;
-    const int grid = persistent_grid(total);
+    const int grid = persistent_grid(a, total);
     switch (tbh) {
     case 8: kb_ccl_local<8><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
     case 16: kb_ccl_local<16><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
@@ -1268,7 +1291,7 @@ hipError_t launch_b_ccl_local(hipStream_t s, const BatchArgs &a, int64_t total, 
 
 hipError_t launch_b_ccl_merge(hipStream_t s, const BatchArgs &a, int64_t total, int tbh, BRef b) {
     if (total == 0) return hipSuccess;
-    const int grid = persistent_grid(total);
+    const int grid = persistent_grid(a, total);
     switch (tbh) {
     case 8: kb_ccl_merge<8><<<grid, kThreads, 0, s>>>(a, b); break;
     case 16: kb_ccl_merge<16><<<grid, kThreads, 0, s>>>(a, b); break;
@@ -1280,20 +1303,20 @@ hipError_t launch_b_ccl_merge(hipStream_t s, const BatchArgs &a, int64_t total, 
 
 hipError_t launch_b_ccl_flag(hipStream_t s, const BatchArgs &a, int64_t total) {
     if (total == 0) return hipSuccess;
-    kb_ccl_flag<<<persistent_grid(total), kThreads, 0, s>>>(a);
+    kb_ccl_flag<<<persistent_grid(a, total), kThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_b_ccl_gather(hipStream_t s, const BatchArgs &a, int64_t total, BRef b, BRef y, BRef z, int user,
                                int32_t out) {
     if (total == 0) return hipSuccess;
-    kb_ccl_gather<<<persistent_grid(total), kThreads, 0, s>>>(a, b, y, z, user, out);
+    kb_ccl_gather<<<persistent_grid(a, total), kThreads, 0, s>>>(a, b, y, z, user, out);
     return hipGetLastError();
 }
 
 hipError_t launch_b_ccl_reseed(hipStream_t s, const BatchArgs &a, int64_t total, BRef sm, int user) {
     if (total == 0) return hipSuccess;
-    kb_ccl_reseed<<<persistent_grid(total), kThreads, 0, s>>>(a, sm, user);
+    kb_ccl_reseed<<<persistent_grid(a, total), kThreads, 0, s>>>(a, sm, user);
     return hipGetLastError();
 }
 
@@ -1556,7 +1579,7 @@ hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t tota
                                int64_t total_hist, int chan, const PctSel &sel) {
     if (total_one == 0) return hipSuccess;
     if (sel.n < 1 || sel.n > kMaxPctSel) return hipErrorInvalidValue;
-    const int g1 = persistent_grid(total_one), gh = persistent_grid(total_hist);
+    const int g1 = persistent_grid(one, total_one), gh = persistent_grid(hist, total_hist);
     kb_pct_init<<<g1, kThreads, 0, s>>>(one, sel);
     dim3 gs(g1, sel.n);
     if (hist.dtype == 1) {

@@ -200,8 +200,11 @@ def test_batch_autotune_picks_persists_and_keeps_results(ctx, tmp_path):
     imgs = [images.phantom_image(np.random.default_rng([41, i]), h, w) for i, (h, w) in enumerate(sizes)]
     f = vlg.compile_formula(ctx, src)
     ims = [vlg.load_image(ctx, im) for im in imgs]
-    best, times = vlg.autotune_batch(ctx, f, ims, iters=1)["ccl_tile_rows"]
+    rep = vlg.autotune_batch(ctx, f, ims, iters=1)
+    best, times = rep["ccl_tile_rows"]
     assert set(times) == {8, 16, 32} and best == min(times, key=times.get)
+    gbest, gtimes = rep["batch_grid"]
+    assert set(gtimes) == {1024, 2048, 4096, 8192} and gbest == min(gtimes, key=gtimes.get)
     path = str(tmp_path / "tune.jsonl")
     vlg.tune_save(ctx, path)
     assert '"ccl_tile_rows_batch"' in open(path).read()
@@ -210,3 +213,18 @@ def test_batch_autotune_picks_persists_and_keeps_results(ctx, tmp_path):
     got = run_batch(ctx2, src, imgs, "graph")
     for (h, w), img, g in zip(sizes, imgs, got):
         assert_same(src, img, g, tag=f"{h}x{w} tuned")
+
+
+@pytest.mark.parametrize("grid", [1024, 4096])
+def test_batch_grid_sizes(ctx, grid):
+    import paper_2010_07284_amd as vlg
+    src = formulas.segmentation_dag(4)
+    sizes = [(190, 257), (64, 1), (300, 301), (17, 17)]
+    imgs = [images.phantom_image(np.random.default_rng([61, i]), h, w) for i, (h, w) in enumerate(sizes)]
+    vlg.set_tunable(ctx, "batch_grid", grid)
+    try:
+        got = run_batch(ctx, src, imgs, "graph")
+    finally:
+        vlg.set_tunable(ctx, "batch_grid", 0)
+    for (h, w), img, g in zip(sizes, imgs, got):
+        assert_same(src, img, g, tag=f"{h}x{w} grid={grid}")

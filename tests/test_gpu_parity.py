@@ -252,3 +252,35 @@ def test_epilogue_fusion_patterns(ctx, h, w):
     want = oracle.run(src, img)
     for mode in MODES:
         assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"{h}x{w} {mode}")
+
+
+@pytest.mark.parametrize("rows", [4, 8, 16, 32])
+def test_near_band_rows_all_operators(ctx, rows):
+    import paper_2010_07284_amd as vlg
+    rng = np.random.default_rng(50 + rows)
+    img = rng.random((2, 301, 200)).astype(np.float32)
+    src = ops_src(rng)
+    vlg.set_tunable(ctx, "near_band_rows", rows)
+    try:
+        assert vlg.get_tunable(ctx, "near_band_rows", 301, 200) == rows
+        for mode in MODES:
+            assert_same(src, img, gpu_run(ctx, src, img, mode), tag=f"rows={rows} {mode}")
+    finally:
+        vlg.set_tunable(ctx, "near_band_rows", 0)
+
+
+def test_autotune_reports_near_rows(ctx, tmp_path):
+    import paper_2010_07284_amd as vlg
+    img = images.plain_image(7, 512)
+    src = formulas.PLAIN_FORMULA
+    f = vlg.compile_formula(ctx, src)
+    rep = vlg.autotune(ctx, f, vlg.load_image(ctx, img), iters=2)
+    best, times = rep["near_band_rows"]
+    assert set(times) == {4, 8, 16, 32} and best == min(times, key=times.get)
+    assert vlg.get_tunable(ctx, "near_band_rows", 512, 512) == best
+    path = str(tmp_path / "tune.jsonl")
+    vlg.tune_save(ctx, path)
+    ctx2 = vlg.create()
+    vlg.tune_load(ctx2, path)
+    assert vlg.get_tunable(ctx2, "near_band_rows", 512, 512) == best
+    assert_same(src, img, gpu_run(ctx2, src, img, "graph"))
