@@ -458,7 +458,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     __shared__ int L[NB];
     __shared__ uint8_t sbits[NB];
     __shared__ uint8_t srun[NB];
-    __shared__ uint8_t sflag[NB];  // bit0 touches the tile border, bit1 seed
+    __shared__ alignas(4) uint8_t sflag[NB];  // bit0 touches the tile border, bit1 seed
     const int r0 = ty * TR, wc0 = tx * TWW;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
 
@@ -556,22 +556,22 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
         }
     }
     __syncthreads();
-    // resolve each run start, then let the rest of the run copy its root
+    // resolve each run start; the other blocks of a run reach their root
+    // through their run start
     for (int i = threadIdx.x; i < NB; i += kThreads)
         if (sbits[i] && srun[i] == (i & (TBW - 1))) L[i] = lds_find(L, i);
     __syncthreads();
-    for (int i = threadIdx.x; i < NB; i += kThreads)
-        if (sbits[i] && srun[i] != (i & (TBW - 1))) L[i] = L[(i & ~(TBW - 1)) + srun[i]];
-    __syncthreads();
-    // carry seed and border-contact flags to the local roots (only roots are
-    // written, each with the same bits)
-    for (int i = threadIdx.x; i < NB; i += kThreads)
-        if (sbits[i] && (sflag[i] & 2)) sflag[L[i]] |= 2;
-    __syncthreads();
+    auto root_of = [&](int i) { return L[(i & ~(TBW - 1)) + srun[i]]; };
+    // carry seed and border-contact flags to the local roots (32-bit LDS
+    // atomics on the flag bytes)
     for (int i = threadIdx.x; i < NB; i += kThreads) {
         if (!sbits[i]) continue;
         const int lby = i / TBW, lbx = i % TBW;
-        if (lby == 0 || lby == TBH - 1 || lbx == 0 || lbx == TBW - 1) sflag[L[i]] |= 1;
+        const uint32_t f = (sflag[i] & 2u) | ((lby == 0 || lby == TBH - 1 || lbx == 0 || lbx == TBW - 1) ? 1u : 0u);
+        if (f) {
+            const int r = root_of(i);
+            atomicOr((unsigned int *)(sflag + (r & ~3)), f << (8 * (r & 3)));
+        }
     }
     __syncthreads();
 
@@ -583,7 +583,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
         // background blocks get a flag byte only: no later pass reads their
         // parent entry (every lookup starts from a foreground block)
         if (sbits[i]) {
-            const int r = L[i];
+            const int r = root_of(i);
             glab[id] = (ty * TBH + r / TBW) * g.BW + tx * TBW + r % TBW;
             gflag[id] = r == i ? sflag[i] : (uint8_t)0;
         } else {
