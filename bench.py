@@ -385,6 +385,8 @@ def main():
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-pixelwise", action="store_true", help="skip the streaming roofline of the pixel-wise kernels")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 7680^2 grow specification workload")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="also time the headline with this many concurrent labelling lanes (2 or 4; experimental)")
     ap.add_argument("--hbm-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (scale for hardware byte counters)")
     args = ap.parse_args()
@@ -458,6 +460,21 @@ def main():
         ms[mode] = time_mode(vlg, lib, ctx, f, im, arr, mode, args.steps, args.warmup)
         log(f"[bench] {mode}: {ms[mode]:.4f} ms/step")
 
+    # concurrent labelling lanes (opt-in, experimental): parity, then graph timing
+    lanes_ms = None
+    if args.lanes > 1:
+        vlg.set_tunable(ctx, "ccl_lanes", args.lanes)
+        vlg.set_mode(ctx, "graph")
+        lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr, 0, 1)
+        vlg.sync(ctx)
+        if not args.skip_oracle:
+            for k in range(nout):
+                if not np.array_equal(vlg.unpack(outs[k], S, S), want[k]):
+                    raise SystemExit(f"[bench] PARITY FAILURE: {args.lanes} labelling lanes, output {k}")
+        lanes_ms = time_mode(vlg, lib, ctx, f, im, arr, "graph", args.steps, args.warmup)
+        vlg.set_tunable(ctx, "ccl_lanes", 0)
+        log(f"[bench] graph with {args.lanes} labelling lanes: {lanes_ms:.4f} ms/step")
+
     prof = vlg.profile(ctx, f, im, iters=args.profile_iters)
     dom_name, (dom_n, dom_ms, dom_bytes) = max(prof.items(), key=lambda kv: kv[1][1])
     dom_avg_ms = dom_ms / dom_n
@@ -493,6 +510,7 @@ def main():
         "perop_ms": round(ms["perop"], 4),
         "fused_ms": round(ms["fused"], 4),
         "speedup_graph_vs_perop": round(ms["perop"] / t, 3),
+        "graph_ms_with_labelling_lanes": ({"lanes": args.lanes, "ms": round(lanes_ms, 4)} if lanes_ms else None),
         "ccl_gpixel_per_s": round(S * S / (ccl_ms / max(1, n_ccl) / 1e3) / 1e9, 3) if n_ccl else None,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),

@@ -198,10 +198,15 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
  *     (default: from the image size).  Taller bands reload fewer halo rows,
  *     shorter ones give more parallel bands.
  *   VLG_TUNE_BATCH_GRID: workgroups of a persistent batched launch: 1024,
- *     2048 (default), 4096 or 8192. */
+ *     2048 (default), 4096 or 8192.
+ *   VLG_TUNE_CCL_LANES: labelling lanes of the fused schedule: 1 (default),
+ *     2 or 4.  With more than one, independent labellings of a scheduling
+ *     round run concurrently on separate streams, each with its own
+ *     labelling workspace (experimental: never chosen by the autotuner). */
 #define VLG_TUNE_CCL_TILE_ROWS 0
 #define VLG_TUNE_NEAR_ROWS 1
 #define VLG_TUNE_BATCH_GRID 2
+#define VLG_TUNE_CCL_LANES 3
 /* Force `value` for every image (value 0 returns to table/default). */
 int vlg_set_tunable(vlg_ctx *ctx, int which, int value);
 /* The value used for an image of height x width on this context. */

@@ -217,7 +217,7 @@ def profile(ctx, f, img, iters=5):
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
 
 
-TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2}
+TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2, "ccl_lanes": 3}
 
 
 def set_tunable(ctx, name, value):

@@ -63,12 +63,13 @@ struct vlg_formula {
     std::mutex mu;
     std::map<std::pair<std::vector<int>, int>, std::unique_ptr<Plan>> plans;
 
-    const Plan &plan(const std::vector<int> &which, Mode m) {
+    // lanes: concurrent labelling lanes of the fused schedule (1: sequential)
+    const Plan &plan(const std::vector<int> &which, Mode m, int lanes = 1) {
         std::lock_guard<std::mutex> lk(mu);
-        auto key = std::make_pair(which, (int)m);
+        auto key = std::make_pair(which, (int)m * 16 + lanes);
         auto it = plans.find(key);
         if (it != plans.end()) return *it->second;
-        auto p = std::make_unique<Plan>(build_plan(dag, which, m));
+        auto p = std::make_unique<Plan>(build_plan(dag, which, m, lanes));
         const Plan &ref = *p;
         plans.emplace(key, std::move(p));
         return ref;
@@ -91,20 +92,21 @@ struct GraphKey {
 };
 
 // Tunables (VLG_TUNE_*): a value of 0 means "not set" (default rule).
-constexpr int kNumTunables = 3;
-const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid"};
+constexpr int kNumTunables = 4;
+const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid", "ccl_lanes"};
 
 bool tunable_valid(int which, int v) {
     switch (which) {
     case VLG_TUNE_CCL_TILE_ROWS: return valid_tile_bh(v);
     case VLG_TUNE_NEAR_ROWS: return valid_near_rows(v);
     case VLG_TUNE_BATCH_GRID: return valid_batch_grid(v);
+    case VLG_TUNE_CCL_LANES: return v == 1 || v == 2 || v == 4;
     }
     return false;
 }
 
 struct Tuning {
-    int v[kNumTunables] = {0, 0, 0};
+    int v[kNumTunables] = {0, 0, 0, 0};
 };
 
 struct vlg_ctx {
@@ -115,6 +117,11 @@ struct vlg_ctx {
     std::map<std::pair<int, int>, Tuning> tuned_batch;  // (batch class, mean image class) -> tuning
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // streams of labelling lanes 1.. (lane 0 runs on `stream`) and the events
+    // that fork them from and join them back into `stream`
+    hipStream_t lane_stream[kMaxCclLanes - 1] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kMaxCclLanes - 1] = {};
     int mode = VLG_MODE_GRAPH;
     void *ws = nullptr;
     size_t ws_size = 0;
@@ -128,7 +135,11 @@ struct vlg_ctx {
     size_t desc_host_size = 0;
     hipEvent_t desc_done = nullptr;
 
+    // an executable graph may still be running from an earlier launch: wait
+    // for the stream (its parallel branches join into it) before destroying
     void drop_graphs() {
+        if (graphs.empty()) return;
+        (void)hipStreamSynchronize(stream);
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
     }
@@ -141,6 +152,7 @@ struct Layout {
     size_t mask_bytes = 0;
     size_t off_slots = 0, off_stage = 0, off_u8 = 0, off_glab = 0, off_gflag = 0, off_pct = 0,
            off_pctst = 0, total = 0;
+    size_t lane_bytes = 0;  // labelling workspace of lane l at off_glab / off_gflag + l * lane_bytes
 };
 
 Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8) {
@@ -155,9 +167,9 @@ Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8)
     if (stage_u8) off += (size_t)P.noutputs * align256((size_t)g.H * g.W);
     L.off_glab = off;
     const size_t nb = (size_t)g.BH * g.BW;
-    if (P.ccl_count > 0) off += align256(nb * 4);
-    L.off_gflag = off;
-    if (P.ccl_count > 0) off += align256(nb);
+    L.lane_bytes = P.ccl_count > 0 ? align256(nb * 4) + align256(nb) : 0;
+    L.off_gflag = off + (P.ccl_count > 0 ? align256(nb * 4) : 0);
+    off += (size_t)std::max(P.ccl_lanes, 1) * L.lane_bytes;
     L.off_pct = off;
     off += align256((size_t)P.npct * 4);
     L.off_pctst = off;
@@ -200,6 +212,7 @@ int tuned_value(const vlg_ctx *c, int which, int H, int W) {
     switch (which) {
     case VLG_TUNE_CCL_TILE_ROWS: return kTileBHDefault;
     case VLG_TUNE_BATCH_GRID: return kBatchGridDefault;
+    case VLG_TUNE_CCL_LANES: return 1;
     }
     return 0;
 }
@@ -293,15 +306,47 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         return m;
     };
     float *pct = (float *)(base + L.off_pct);
-    CclWork w;
-    w.glab = (int32_t *)(base + L.off_glab);
-    w.gflag = (uint8_t *)(base + L.off_gflag);
-    w.counters = c->count_ccl ? c->counters : nullptr;
-    w.tbh = tuning_for(c, img->H, img->W).ccl_tbh;
+    CclWork w0;
+    w0.counters = c->count_ccl ? c->counters : nullptr;
+    w0.tbh = tuning_for(c, img->H, img->W).ccl_tbh;
     const int near_rows = tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W);
     const int64_t npix = (int64_t)img->H * img->W;
+    // concurrent regions: the steps of a span with lanes run on the lanes'
+    // streams, forked from the main stream at the region's start and joined
+    // back into it at its end (events; captured as graph dependencies)
+    int open_span = -1;
+    uint32_t open_lanes = 0;
+    auto join = [&]() -> int {
+        for (int l = 1; l < kMaxCclLanes; l++) {
+            if (!(open_lanes >> l & 1)) continue;
+            HIP_TRY(hipEventRecord(c->join_ev[l - 1], c->lane_stream[l - 1]));
+            HIP_TRY(hipStreamWaitEvent(c->stream, c->join_ev[l - 1], 0));
+        }
+        open_span = -1;
+        open_lanes = 0;
+        return VLG_OK;
+    };
     for (size_t si = 0; si < P.steps.size(); si++) {
         const Step &s = P.steps[si];
+        if (open_span >= 0 && (s.lane < 0 || s.span != open_span)) {
+            int rc = join();
+            if (rc != VLG_OK) return rc;
+        }
+        if (s.lane >= 0 && open_span < 0) {
+            for (size_t sj = si; sj < P.steps.size() && P.steps[sj].span == s.span && P.steps[sj].lane >= 0; sj++)
+                open_lanes |= 1u << P.steps[sj].lane;
+            if (open_lanes > 1) {
+                HIP_TRY(hipEventRecord(c->fork_ev, c->stream));
+                for (int l = 1; l < kMaxCclLanes; l++)
+                    if (open_lanes >> l & 1) HIP_TRY(hipStreamWaitEvent(c->lane_stream[l - 1], c->fork_ev, 0));
+            }
+            open_span = s.span;
+        }
+        const int lane = s.lane > 0 ? s.lane : 0;
+        hipStream_t stream = lane > 0 ? c->lane_stream[lane - 1] : c->stream;
+        CclWork w = w0;
+        w.glab = (int32_t *)(base + L.off_glab + (size_t)lane * L.lane_bytes);
+        w.gflag = (uint8_t *)(base + L.off_gflag + (size_t)lane * L.lane_bytes);
         if (hook) hook(hook_ctx, si, true);
         hipError_t e = hipSuccess;
         if (s.group >= 0) {
@@ -315,7 +360,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                     const Step &t = P.steps[k];
                     b.ops[k - si] = LogicOp{mref(t.x), mref(t.y), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out), t.op};
                 }
-                e = launch_logic_batch(c->stream, g, b);
+                e = launch_logic_batch(stream, g, b);
             } else {
                 NearBatch b;
                 b.n = (int)(sj - si + 1);
@@ -323,7 +368,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                     const Step &t = P.steps[k];
                     b.ops[k - si] = NearOp{mref(t.x), mref(t.z), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out), t.op};
                 }
-                e = launch_near_batch(c->stream, g, b, near_rows);
+                e = launch_near_batch(stream, g, b, near_rows);
             }
             if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
             for (size_t k = si; k < sj; k++) {
@@ -345,7 +390,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                 sel.slot[j] = s.pct_out[j];
                 sel.k[j] = pct_rank(s.q[j], npix);
             }
-            e = launch_percentile(c->stream, g, img->chan(s.chan), img->dtype, sel, base + L.off_pctst, pct);
+            e = launch_percentile(stream, g, img->chan(s.chan), img->dtype, sel, base + L.off_pctst, pct);
         }
             break;
         case SK::Atoms: {
@@ -358,34 +403,35 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                 a.thr_dev[j] = s.atoms[j].use_pct ? pct + s.atoms[j].pct : nullptr;
                 a.out[j] = slot_ptr(s.atoms[j].out);
             }
-            e = launch_atoms(c->stream, g, img->chan(s.chan), img->dtype, a);
+            e = launch_atoms(stream, g, img->chan(s.chan), img->dtype, a);
             break;
         }
         case SK::Logic:
-            e = launch_logic(c->stream, g, mref(s.x), mref(s.y), s.op, s.inv_out, slot_ptr(s.out));
+            e = launch_logic(stream, g, mref(s.x), mref(s.y), s.op, s.inv_out, slot_ptr(s.out));
             break;
         case SK::Near:
-            e = launch_near(c->stream, g, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out), near_rows);
+            e = launch_near(stream, g, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out), near_rows);
             break;
         case SK::CclLocal:
-            e = launch_ccl_local(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w);
+            e = launch_ccl_local(stream, g, mref(s.x), mref(s.y), mref(s.z), w);
             break;
         case SK::CclMerge:
-            e = launch_ccl_merge(c->stream, g, mref(s.x), w);
+            e = launch_ccl_merge(stream, g, mref(s.x), w);
             break;
         case SK::CclFlag:
-            e = launch_ccl_flag(c->stream, g, w);
+            e = launch_ccl_flag(stream, g, w);
             break;
         case SK::CclGather:
-            e = launch_ccl_gather(c->stream, g, mref(s.x), mref(s.y), mref(s.z), w, s.user, slot_ptr(s.out));
+            e = launch_ccl_gather(stream, g, mref(s.x), mref(s.y), mref(s.z), w, s.user, slot_ptr(s.out));
             break;
         case SK::CclReseed:
-            e = launch_ccl_reseed(c->stream, g, mref(s.x), w, s.user);
+            e = launch_ccl_reseed(stream, g, mref(s.x), w, s.user);
             break;
         }
         if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
         if (hook) hook(hook_ctx, si, false);
     }
+    if (open_span >= 0) return join();
     return VLG_OK;
 }
 
@@ -400,7 +446,7 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
     if (img->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
     DeviceGuard dg(c->device);
     const Mode m = c->mode == VLG_MODE_PEROP ? Mode::PerOp : Mode::Fused;
-    const Plan &P = f->plan(which, m);
+    const Plan &P = f->plan(which, m, m == Mode::Fused ? tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W) : 1);
     const Geo g = make_geo(img->H, img->W);
     if (g.nwords == 0 || which.empty()) return VLG_OK;
     const bool direct = fmt == VLG_PACKED64 && where == VLG_DEVICE;
@@ -759,7 +805,7 @@ namespace vlg {
 size_t evaluation_footprint(vlg_formula *f, const vlg_image *img) {
     std::vector<int> all(f->dag.outputs.size());
     for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
-    const Plan &P = f->plan(all, Mode::Fused);
+    const Plan &P = f->plan(all, Mode::Fused, 1);  // server slots run one labelling lane
     return layout_for(P, make_geo(img->H, img->W), false, false).total;
 }
 int evaluate_all_on(vlg_ctx *c, vlg_formula *f, const vlg_image *img, void *const *outs, void *ws, size_t ws_size) {
@@ -859,6 +905,11 @@ int vlg_create(vlg_ctx **out, int device, void *hip_stream) {
         HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
+    for (int l = 0; l < kMaxCclLanes - 1; l++) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->lane_stream[l], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->join_ev[l], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
     const char *cc = std::getenv("VLG_CCL_COUNTERS");
     c->count_ccl = cc && cc[0] == '1';
     HIP_TRY(hipMalloc(&c->counters, 2 * sizeof(unsigned long long)));
@@ -877,6 +928,14 @@ void vlg_destroy(vlg_ctx *c) {
     if (c->counters) (void)hipFree(c->counters);
     if (c->desc_host) (void)hipHostFree(c->desc_host);
     if (c->desc_done) (void)hipEventDestroy(c->desc_done);
+    for (int l = 0; l < kMaxCclLanes - 1; l++) {
+        if (c->lane_stream[l]) {
+            (void)hipStreamSynchronize(c->lane_stream[l]);
+            (void)hipStreamDestroy(c->lane_stream[l]);
+        }
+        if (c->join_ev[l]) (void)hipEventDestroy(c->join_ev[l]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -979,7 +1038,7 @@ int vlg_formula_info(const vlg_formula *cf, vlg_formula_stats *st) {
     std::vector<int> all(f->dag.outputs.size());
     for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
     const Plan &pp = f->plan(all, Mode::PerOp);
-    const Plan &pf = f->plan(all, Mode::Fused);
+    const Plan &pf = f->plan(all, Mode::Fused, 1);
     st->parsed_nodes = f->dag.parsed_nodes;
     st->nodes = (int64_t)f->dag.nodes.size();
     st->reach_nodes = count_op(f->dag, true);
@@ -1197,7 +1256,7 @@ int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int it
     *n_out = 0;
     std::vector<int> which(f->dag.outputs.size());
     for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
-    const Plan &P = f->plan(which, Mode::Fused);
+    const Plan &P = f->plan(which, Mode::Fused, tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W));
     const Geo g = make_geo(img->H, img->W);
     if (g.nwords == 0) return VLG_OK;
     bool has_near = false;

@@ -815,7 +815,7 @@ struct Lower {
 // being recomputed.  Works on SSA ids, before slot allocation.
 constexpr int64_t kPctBase = int64_t(1) << 40;
 
-void schedule_fused(Lower &L) {
+void schedule_fused(Lower &L, int lanes) {
     struct Unit {
         int first = 0, count = 1;
         bool ccl = false;
@@ -866,10 +866,18 @@ void schedule_fused(Lower &L) {
     }
     std::vector<char> done((size_t)n, 0);
     std::vector<Step> out;
-    int emitted = 0, group = 0;
+    int emitted = 0, group = 0, span = 0;
     bool have_last = false;
     Ref last_b;
     int last_users = 0;
+    // labelling lanes (lanes > 1): the passable mask each lane's workspace
+    // holds a labelling of, and how many seed sets it serves
+    struct LaneState {
+        bool have = false;
+        Ref b;
+        int users = 0;
+    };
+    std::vector<LaneState> lane_st((size_t)std::max(lanes, 1));
     auto finish = [&](int u) {
         done[(size_t)u] = 1;
         emitted++;
@@ -911,12 +919,65 @@ void schedule_fused(Lower &L) {
                 if (i % kMaxBatch == 0) group++;
                 Step st = L.steps[(size_t)units[(size_t)r[i]].first];
                 st.group = r.size() > 1 ? group : -1;
+                st.span = r.size() > 1 ? 1000000 + group : -1;
                 out.push_back(st);
             }
             for (int u : r) finish(u);
         }
         std::vector<int> rc = ready([&](const Unit &x) { return x.ccl; });
-        if (!rc.empty()) {
+        // reuse of an existing labelling of b: seed mask N(y & z) & b, mark, gather
+        auto emit_reuse = [&](int u, int users, int lane, int sp) {
+            const Step loc = L.steps[(size_t)units[(size_t)u].first];
+            Step gat = L.steps[(size_t)units[(size_t)u].first + 3];
+            const Ref y = loc.y, z = loc.z;
+            const bool yone = y.slot == kNone && y.inv, zone = z.slot == kNone && z.inv;
+            Ref t = y;
+            if (!zone) {
+                if (yone) {
+                    t = z;
+                } else {
+                    Step lg;
+                    lg.kind = SK::Logic;
+                    lg.x = y;
+                    lg.y = z;
+                    lg.op = 0;
+                    lg.out = L.fresh();
+                    lg.lane = lane;
+                    lg.span = sp;
+                    out.push_back(lg);
+                    t = Lower::R(lg.out);
+                }
+            }
+            Step nr;
+            nr.kind = SK::Near;
+            nr.x = t;
+            nr.z = loc.x;
+            nr.out = L.fresh();
+            nr.lane = lane;
+            nr.span = sp;
+            out.push_back(nr);
+            Step rs;
+            rs.kind = SK::CclReseed;
+            rs.x = Lower::R(nr.out);
+            rs.user = users;
+            rs.lane = lane;
+            rs.span = sp;
+            out.push_back(rs);
+            gat.user = users;
+            gat.lane = lane;
+            gat.span = sp;
+            out.push_back(gat);
+        };
+        auto emit_fresh = [&](int u, int lane, int sp) {
+            for (int k = 0; k < 4; k++) {
+                Step st = L.steps[(size_t)units[(size_t)u].first + (size_t)k];
+                st.user = 0;
+                st.lane = lane;
+                st.span = sp;
+                out.push_back(st);
+            }
+        };
+        if (!rc.empty() && lanes <= 1) {
             int pick = rc[0];
             if (have_last && last_users < kMaxCclUsers)
                 for (int u : rc)
@@ -925,51 +986,42 @@ void schedule_fused(Lower &L) {
                         break;
                     }
             const Step loc = L.steps[(size_t)units[(size_t)pick].first];
-            Step gat = L.steps[(size_t)units[(size_t)pick].first + 3];
             if (have_last && last_users < kMaxCclUsers && same(loc.x, last_b)) {
-                // reuse: seed mask N(y & z) & b, mark, gather
-                const Ref y = loc.y, z = loc.z;
-                const bool yone = y.slot == kNone && y.inv, zone = z.slot == kNone && z.inv;
-                Ref t = zone ? y : y;
-                if (!zone) {
-                    if (yone) {
-                        t = z;
-                    } else {
-                        Step lg;
-                        lg.kind = SK::Logic;
-                        lg.x = y;
-                        lg.y = z;
-                        lg.op = 0;
-                        lg.out = L.fresh();
-                        out.push_back(lg);
-                        t = Lower::R(lg.out);
-                    }
-                }
-                Step nr;
-                nr.kind = SK::Near;
-                nr.x = t;
-                nr.z = loc.x;
-                nr.out = L.fresh();
-                out.push_back(nr);
-                Step rs;
-                rs.kind = SK::CclReseed;
-                rs.x = Lower::R(nr.out);
-                rs.user = last_users;
-                out.push_back(rs);
-                gat.user = last_users;
-                out.push_back(gat);
+                emit_reuse(pick, last_users, -1, -1);
                 last_users++;
             } else {
-                for (int k = 0; k < 4; k++) {
-                    Step st = L.steps[(size_t)units[(size_t)pick].first + (size_t)k];
-                    st.user = 0;
-                    out.push_back(st);
-                }
+                emit_fresh(pick, -1, -1);
                 have_last = true;
                 last_b = loc.x;
                 last_users = 1;
             }
             finish(pick);
+        } else if (!rc.empty()) {
+            // one concurrent region: a labelling that can reuse the labelling a
+            // lane holds (or starts in this region) follows it on that lane
+            // (a lane's steps run in order); any other takes a free lane
+            const int sp = span++;
+            std::vector<char> busy((size_t)lanes, 0);
+            for (int u : rc) {
+                const Ref b = L.steps[(size_t)units[(size_t)u].first].x;
+                int l = 0;
+                while (l < lanes && !(lane_st[(size_t)l].have && lane_st[(size_t)l].users < kMaxCclUsers &&
+                                      same(lane_st[(size_t)l].b, b)))
+                    l++;
+                if (l < lanes) {
+                    emit_reuse(u, lane_st[(size_t)l].users++, l, sp);
+                    busy[(size_t)l] = 1;
+                    finish(u);
+                    continue;
+                }
+                l = 0;
+                while (l < lanes && busy[(size_t)l]) l++;
+                if (l == lanes) continue;  // next round
+                emit_fresh(u, l, sp);
+                lane_st[(size_t)l] = LaneState{true, b, 1};
+                busy[(size_t)l] = 1;
+                finish(u);
+            }
         }
         if (emitted == before) break;  // cannot happen for a DAG
     }
@@ -978,7 +1030,7 @@ void schedule_fused(Lower &L) {
 
 }  // namespace
 
-Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
+Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes) {
     Lower L(dag, mode);
     const size_t N = dag.nodes.size();
     std::vector<char> need(N, 0);
@@ -1027,12 +1079,13 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
     }
 
     if (mode == Mode::Fused) {
-        schedule_fused(L);
+        schedule_fused(L, std::min(std::max(lanes, 1), kMaxCclLanes));
         ext_of.resize((size_t)L.nssa, kNone);
     }
 
-    // liveness over SSA values, then greedy slot reuse; a batched group is
-    // allocated as one step so that no member writes a slot another reads
+    // liveness over SSA values, then greedy slot reuse; a span (a batched
+    // group, or a concurrent region of labelling lanes) is allocated as one
+    // step so that no member writes a slot another reads
     const int32_t nv = L.nssa;
     std::vector<int64_t> last(nv, -1);
     for (size_t si = 0; si < L.steps.size(); si++) {
@@ -1061,8 +1114,8 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
     };
     for (size_t s0 = 0; s0 < L.steps.size();) {
         size_t s1 = s0 + 1;
-        if (L.steps[s0].group >= 0)
-            while (s1 < L.steps.size() && L.steps[s1].group == L.steps[s0].group) s1++;
+        if (L.steps[s0].span >= 0)
+            while (s1 < L.steps.size() && L.steps[s1].span == L.steps[s0].span) s1++;
         std::vector<int32_t> outs;
         for (size_t si = s0; si < s1; si++) {
             Step &s = L.steps[si];
@@ -1106,6 +1159,7 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode) {
     for (const Step &st : P.steps) {
         if (st.kind == SK::CclLocal) P.ccl_count++;
         if (st.kind == SK::CclReseed) P.ccl_reuse++;
+        P.ccl_lanes = std::max(P.ccl_lanes, st.lane + 1);
     }
     P.output_ids.assign(which.begin(), which.end());
     return P;

@@ -92,6 +92,11 @@ struct Step {
     int32_t user = 0;     // CclGather / CclReseed: which seed set of the labelling
     int32_t group = -1;   // consecutive Logic (or Near) steps of one group run
                           // as one batched launch; they never read each other
+    int32_t lane = -1;    // labelling lane (>= 0): the steps of one concurrent
+                          // region (same span) run on their lane's stream,
+                          // lanes concurrently; -1: the main stream
+    int32_t span = -1;    // consecutive steps with one span id are allocated
+                          // mask slots as one step (batched group, region)
 };
 
 // A labelling serves at most this many reach-type nodes with the same
@@ -108,12 +113,17 @@ struct Plan {
     int32_t noutputs = 0;      // requested outputs (external slots 0..noutputs-1)
     int64_t ccl_count = 0;     // reachability labellings per evaluation
     int64_t ccl_reuse = 0;     // reach-type nodes served by an earlier labelling
+    int32_t ccl_lanes = 1;     // labelling workspaces (concurrent labelling lanes)
     std::vector<int32_t> output_ids;  // formula output index per external slot
 };
 
 // Build the schedule evaluating formula outputs `which` (indices into
-// dag.outputs); external slot k receives output which[k].
-Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode);
+// dag.outputs); external slot k receives output which[k].  With lanes > 1
+// (fused mode) up to `lanes` independent labellings of one scheduling round
+// form a concurrent region, each on its own lane with its own labelling
+// workspace.
+constexpr int kMaxCclLanes = 4;
+Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes = 1);
 
 // Number of reach/surrounded/grow nodes and of atoms.
 int64_t count_op(const Dag &dag, bool reach_like);

@@ -284,3 +284,24 @@ def test_autotune_reports_near_rows(ctx, tmp_path):
     vlg.tune_load(ctx2, path)
     assert vlg.get_tunable(ctx2, "near_band_rows", 512, 512) == best
     assert_same(src, img, gpu_run(ctx2, src, img, "graph"))
+
+
+@pytest.mark.parametrize("lanes", [2, 4])
+def test_ccl_lanes_opt_in(ctx, lanes):
+    # concurrent labelling lanes (opt-in tunable): segmentation, labelling
+    # reuse and random formulas, every executor mode against the oracle
+    import paper_2010_07284_amd as vlg
+    cases = [(formulas.segmentation_dag(4), images.phantom_image(np.random.default_rng(4), 190, 257))]
+    for seed in range(3):
+        rng = np.random.default_rng(100 + seed)
+        h, w = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        cases.append((formulas.random_dag(seed, n_nodes=60, n_reach=6, channels=2),
+                      rng.random((2, h, w)).astype(np.float32)))
+    vlg.set_tunable(ctx, "ccl_lanes", lanes)
+    try:
+        for src, img in cases:
+            want = oracle.run(src, img)
+            for mode in ("fused", "graph"):
+                assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"lanes={lanes} {mode}")
+    finally:
+        vlg.set_tunable(ctx, "ccl_lanes", 0)
