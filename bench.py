@@ -358,8 +358,8 @@ def bench_serve(vlg, n_req, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=
         wall = time.perf_counter() - t_first
         lat = np.array(lat[n_warm:])
         px = sum(work(i, k) for i, k in reqs[n_warm:])
-        lvl = {"offered_req_per_s": round(rate, 2), "achieved_req_per_s": round(n_req / wall, 2),
-               "gpixel_node_per_s": round(px / wall / 1e9, 2),
+        lvl = {"offered_req_per_s": round(float(rate), 2), "achieved_req_per_s": round(float(n_req / wall), 2),
+               "gpixel_node_per_s": round(float(px / wall / 1e9), 2),
                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
         log(f"[bench] serve at {frac:.0%}: {lvl}")
         out["levels"].append(lvl)
