@@ -42,6 +42,10 @@ template <typename T>
 __device__ __forceinline__ const VLG_GLOBAL T *glb(const T *p) {
     return (const VLG_GLOBAL T *)p;
 }
+// Constant address space: for tables that no kernel writes while it runs
+// (the per-image descriptors of a batched launch).  A wave-uniform index into
+// them becomes a scalar load whose result stays in scalar registers.
+#define VLG_CONST __attribute__((address_space(4)))
 
 __device__ __forceinline__ uint64_t ldm(const MRef &r, int64_t i) {
     return (r.p ? glb(r.p)[i] : 0ull) ^ r.inv;
@@ -349,30 +353,53 @@ __device__ __forceinline__ int lds_ld(int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ int lds_find(int *L, int x) {
+// Value of v in the previous lane of the wave (DPP wave shift right by one;
+// lane 0 receives 0).
+__device__ __forceinline__ int lane_prev(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+
+// Union of a and b on the LDS forest L (L[x] <= x, a root is the smallest
+// entry of its set).  Both walks advance together, one path-halving step per
+// round, so their LDS latencies overlap; once both reach roots the larger
+// root is hooked under the smaller with atomicMin, and if that root was
+// hooked meanwhile the returned parent is united in its place.  Halving
+// stores may race with other lanes' hooks; the hooking lane then unites the
+// old parent as well, so no connection is lost.
+__device__ __forceinline__ void lds_unite(int *L, int a, int b) {
+    while (a != b) {
+        const int pa = lds_ld(&L[a]), pb = lds_ld(&L[b]);
+        if (pa == a && pb == b) {
+            const int hi = a > b ? a : b, lo = a > b ? b : a;
+            const int old = atomicMin(&L[hi], lo);
+            if (old == hi) return;
+            a = old;
+            b = lo;
+            continue;
+        }
+        const int ga = pa != a ? lds_ld(&L[pa]) : pa, gb = pb != b ? lds_ld(&L[pb]) : pb;
+        if (pa != a) {
+            if (ga != pa) L[a] = ga;
+            a = ga;
+        }
+        if (pb != b) {
+            if (gb != pb) L[b] = gb;
+            b = gb;
+        }
+    }
+}
+
+// Root of x once all unions are done.  Path halving here goes through
+// atomicMin: the root is the smallest entry of its set, so a stale halving
+// store can never replace a root that its owner has already written.
+__device__ __forceinline__ int lds_root(int *L, int x) {
     while (true) {
         const int p = lds_ld(&L[x]);
         if (p == x) return x;
         const int gp = lds_ld(&L[p]);
         if (gp == p) return p;
-        L[x] = gp;  // path halving: gp is an ancestor of x
+        __hip_atomic_fetch_min(&L[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         x = gp;
-    }
-}
-
-__device__ void lds_unite(int *L, int a, int b) {
-    while (true) {
-        a = lds_find(L, a);
-        b = lds_find(L, b);
-        if (a == b) return;
-        if (a < b) {
-            const int t = a;
-            a = b;
-            b = t;
-        }
-        const int old = atomicMin(&L[a], b);  // hook the larger root under the smaller
-        if (old == a) return;
-        a = old;  // a was hooked meanwhile: unite its new parent instead
     }
 }
 
@@ -433,14 +460,23 @@ __device__ __forceinline__ uint32_t block_bits_g(const Geo &g, const MRef &b, in
     return (uint32_t)((t >> sh) & 3) | ((uint32_t)((u >> sh) & 3) << 2);
 }
 
+// Threads per workgroup of the tile-local pass: four block rows per wave at
+// most (TBH = 32 takes eight waves), which bounds the per-row state each
+// lane keeps in registers.
+template <int TBH>
+constexpr int ccl_local_threads() {
+    return TBH > 16 ? 512 : 256;
+}
+
 // Tile-local labelling of b: TBH block rows x 64 block columns (2*TBH x 128
-// pixels) per workgroup of four waves.  A wave takes one block row at a time,
-// one lane per block: horizontally connected blocks form runs, found with a
-// ballot and labelled by their first block without any atomics.  Runs of
-// consecutive rows are then united once per touching pair (a block skips the
-// upper runs its connected left neighbour already touches).  Also computes
-// the seed test: a block meets the seeds when one of its b-pixels lies in
-// N(y & z).
+// pixels) per workgroup of NWAVES waves.  Wave v owns block rows v,
+// v+NWAVES, ... (RPW of them), one lane per block column, and keeps each
+// row's block state in a register from the first phase to the last.  Horizontally
+// connected blocks form runs, found with a ballot and labelled by their first
+// block without any atomics.  Runs of consecutive rows are then united once
+// per touching pair (a block skips the upper runs its connected left
+// neighbour already touches).  Also computes the seed test: a block meets the
+// seeds when one of its b-pixels lies in N(y & z).
 //
 // Output: glab[id] = global id of the foreground block's tile-local root
 // (background entries are left as they are); gflag[id] of a local root:
@@ -452,60 +488,87 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
                                int32_t *__restrict__ glab_, uint8_t *__restrict__ gflag_) {
     VLG_GLOBAL int32_t *glab = glb(glab_);
     VLG_GLOBAL uint8_t *gflag = glb(gflag_);
-    constexpr int TWW = 2, TR = 2 * TBH, TBW = 64, NB = TBH * TBW, NWAVES = kThreads / 64;
+    constexpr int NT = ccl_local_threads<TBH>();
+    constexpr int TWW = 2, TR = 2 * TBH, TBW = 64, NB = TBH * TBW, NWAVES = NT / 64;
+    constexpr int RPW = TBH / NWAVES;
+    static_assert(RPW * NWAVES == TBH, "tile rows must split evenly over the waves");
+    constexpr int NSB = TR * TWW, NSA = (TR + 2) * (TWW + 2), NLD = NSB + NSA;
+    constexpr int LIT = (NLD + NT - 1) / NT;
     __shared__ uint64_t sb[TR][TWW];
     __shared__ uint64_t sa[TR + 2][TWW + 2];
     __shared__ int L[NB];
-    __shared__ uint8_t sbits[NB];
-    __shared__ uint8_t srun[NB];
+    __shared__ uint16_t sbr[NB];              // block bits | run start column << 4
     __shared__ alignas(4) uint8_t sflag[NB];  // bit0 touches the tile border, bit1 seed
+    __shared__ int sany;
+    // the thread index is made opaque per tile so that a persistent
+    // workgroup recomputes its per-row addressing in each tile instead of
+    // holding it in registers across the whole tile loop
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
     const int r0 = ty * TR, wc0 = tx * TWW;
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
 
-    int any = 0;
-    for (int i = threadIdx.x; i < TR * TWW; i += kThreads) {
-        const int r = i / TWW, w = i % TWW, yy = r0 + r, ww = wc0 + w;
-        uint64_t v = 0;
-        if (yy < g.H && ww < g.wpr) {
-            v = ldm(b, (int64_t)yy * g.wpr + ww);
-            if (ww == g.wpr - 1) v &= g.tail;
+    // b words of the tile and (y & z) words of the tile plus a one-pixel halo,
+    // all loads in flight at once; sany: bit0 = some b pixel, bit1 = some seed
+    if (tid == 0) sany = 0;
+    __syncthreads();
+    int any;
+    {
+        uint64_t v[LIT];
+#pragma unroll
+        for (int k = 0; k < LIT; k++) {
+            const int i = tid + k * NT;
+            v[k] = 0;
+            if (i < NSB) {
+                const int yy = r0 + i / TWW, ww = wc0 + i % TWW;
+                if (yy < g.H && ww < g.wpr) v[k] = ldm(b, (int64_t)yy * g.wpr + ww) & (ww == g.wpr - 1 ? g.tail : ~0ull);
+            } else if (i < NLD) {
+                const int j = i - NSB, yy = r0 + j / (TWW + 2) - 1, ww = wc0 + j % (TWW + 2) - 1;
+                if (yy >= 0 && yy < g.H && ww >= 0 && ww < g.wpr) {
+                    const int64_t idx = (int64_t)yy * g.wpr + ww;
+                    v[k] = ldm(y, idx) & ldm(z, idx) & (ww == g.wpr - 1 ? g.tail : ~0ull);
+                }
+            }
         }
-        sb[r][w] = v;
-        any |= v != 0;
+        bool has_b = false, has_s = false;
+#pragma unroll
+        for (int k = 0; k < LIT; k++) {
+            const int i = tid + k * NT;
+            if (i < NSB) {
+                sb[i / TWW][i % TWW] = v[k];
+                has_b |= v[k] != 0;
+            } else if (i < NLD) {
+                const int j = i - NSB;
+                sa[j / (TWW + 2)][j % (TWW + 2)] = v[k];
+                has_s |= v[k] != 0;
+            }
+        }
+        const int f = (__ballot(has_b) ? 1 : 0) | (__ballot(has_s) ? 2 : 0);
+        if (lane == 0 && f) atomicOr(&sany, f);
+        __syncthreads();
+        any = sany;
     }
     // a tile without passable pixels only clears its flag bytes (the flag pass
     // reads every block's; no pass reads a background block's parent entry)
-    if (!__syncthreads_or(any)) {
-        for (int i = threadIdx.x; i < NB; i += kThreads) {
+    if (!(any & 1)) {
+        for (int i = tid; i < NB; i += NT) {
             const int by = ty * TBH + i / TBW, bx = tx * TBW + i % TBW;
             if (by < g.BH && bx < g.BW) gflag[(int64_t)by * g.BW + bx] = 0;
         }
+        __syncthreads();  // sany is reset by the next tile of a persistent workgroup
         return;
     }
-    for (int i = threadIdx.x; i < (TR + 2) * (TWW + 2); i += kThreads) {
-        const int r = i / (TWW + 2), w = i % (TWW + 2), yy = r0 + r - 1, ww = wc0 + w - 1;
-        uint64_t v = 0;
-        if (yy >= 0 && yy < g.H && ww >= 0 && ww < g.wpr) {
-            const int64_t idx = (int64_t)yy * g.wpr + ww;
-            v = ldm(y, idx) & ldm(z, idx);
-            if (ww == g.wpr - 1) v &= g.tail;
-        }
-        sa[r][w] = v;
-    }
-    __syncthreads();
 
-    // rows: block bits, runs, seeds
-    for (int lby = wave; lby < TBH; lby += NWAVES) {
-        const int i = lby * TBW + lane, w = lane >> 5, sh = (lane & 31) * 2;
-        const uint32_t bits = (uint32_t)((sb[2 * lby][w] >> sh) & 3) |
-                              ((uint32_t)((sb[2 * lby + 1][w] >> sh) & 3) << 2);
-        const uint32_t left = (uint32_t)__shfl_up((int)bits, 1);
-        const bool conn_l = lane > 0 && (bits & 5) && (left & 10);
-        const uint64_t starts = __ballot(bits != 0 && !conn_l);
-        const uint64_t upto = starts & (~0ull >> (63 - lane));
-        const int run = upto ? 63 - __builtin_clzll(upto) : lane;
+    // rows: block bits, runs, seeds.  st[j] (row wave + NWAVES*j) = bits | run << 4 |
+    // seed << 10 | (connected to the left block) << 11
+    const int w = lane >> 5, sh = (lane & 31) * 2;
+    uint32_t st[RPW];
+#pragma unroll
+    for (int j = 0; j < RPW; j++) {
+        const int lby = wave + NWAVES * j, i = lby * TBW + lane;
+        const uint32_t bits = (uint32_t)((sb[2 * lby][w] >> sh) & 3) | ((uint32_t)((sb[2 * lby + 1][w] >> sh) & 3) << 2);
         uint32_t seed = 0;
-        if (bits) {
+        if (any & 2) {
             // seed pixels in the 4x4 window around the block: rows 2lby-1 ..
             // 2lby+2, cols 2lbx-1 .. 2lbx+2 (halo coordinates: +1 row, +64 cols)
             const int c = 64 * (w + 1) + sh - 1, q = c >> 6, s = c & 63;
@@ -521,69 +584,84 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
                                    ((bot & 0x7) ? 4u : 0u) | ((bot & 0xE) ? 8u : 0u);
             seed = (bits & nmask) ? 1u : 0u;
         }
-        sbits[i] = (uint8_t)bits;
-        srun[i] = (uint8_t)run;
+        const uint32_t left = (uint32_t)lane_prev((int)bits);
+        const bool conn = lane > 0 && (bits & 5) && (left & 10);
+        const uint64_t starts = __ballot(bits != 0 && !conn);
+        const uint64_t upto = starts & (~0ull >> (63 - lane));
+        const int run = upto ? 63 - __builtin_clzll(upto) : lane;
+        st[j] = bits | ((uint32_t)run << 4) | (seed << 10) | (conn ? 1u << 11 : 0u);
+        sbr[i] = (uint16_t)(bits | ((uint32_t)run << 4));
         sflag[i] = (uint8_t)(seed << 1);
         L[i] = bits ? lby * TBW + run : i;
     }
+    auto st_bits = [](uint32_t s) { return s & 15u; };
+    auto st_run = [](uint32_t s) { return (int)((s >> 4) & 63u); };
     __syncthreads();
 
-    // unite runs of row lby with the runs they touch in row lby-1
-    for (int lby = 1 + wave; lby < TBH; lby += NWAVES) {
-        const int i = lby * TBW + lane, up = i - TBW;
-        const uint32_t bits = sbits[i];
+    // unite the runs of each row with the runs they touch in the row above
+#pragma unroll
+    for (int j = 0; j < RPW; j++) {
+        const int lby = wave + NWAVES * j, up = (lby - 1) * TBW + lane;
+        const uint32_t bits = st_bits(st[j]);
         int c0 = -1, c1 = -1, c2 = -1;
-        if (bits) {
-            if (lane > 0 && (bits & 1) && (sbits[up - 1] & 8)) c0 = srun[up - 1];
-            if ((bits & 3) && (sbits[up] & 12)) c1 = srun[up];
-            if (lane < 63 && (bits & 2) && (sbits[up + 1] & 4)) c2 = srun[up + 1];
+        if (lby > 0 && bits) {
+            const uint32_t ul = lane > 0 ? sbr[up - 1] : 0u, uc = sbr[up], ur = lane < 63 ? sbr[up + 1] : 0u;
+            if ((bits & 1) && (ul & 8)) c0 = (int)(ul >> 4);
+            if ((bits & 3) && (uc & 12)) c1 = (int)(uc >> 4);
+            if ((bits & 2) && (ur & 4)) c2 = (int)(ur >> 4);
         }
         if (c1 == c0) c1 = -1;
         if (c2 == c0 || c2 == c1) c2 = -1;
-        const int l0 = __shfl_up(c0, 1), l1 = __shfl_up(c1, 1), l2 = __shfl_up(c2, 1);
-        const uint32_t left = lane > 0 ? sbits[i - 1] : 0u;
-        if (lane > 0 && (bits & 5) && (left & 10)) {
+        const int l0 = lane_prev(c0), l1 = lane_prev(c1), l2 = lane_prev(c2);
+        if (st[j] & (1u << 11)) {
             // the left block is in this run and already joins its upper runs
             if (c0 >= 0 && (c0 == l0 || c0 == l1 || c0 == l2)) c0 = -1;
             if (c1 >= 0 && (c1 == l0 || c1 == l1 || c1 == l2)) c1 = -1;
             if (c2 >= 0 && (c2 == l0 || c2 == l1 || c2 == l2)) c2 = -1;
         }
-        if (bits) {
-            const int me = lby * TBW + srun[i], ub = (lby - 1) * TBW;
-            if (c0 >= 0) lds_unite(L, me, ub + c0);
-            if (c1 >= 0) lds_unite(L, me, ub + c1);
-            if (c2 >= 0) lds_unite(L, me, ub + c2);
-        }
+        const int me = lby * TBW + st_run(st[j]), ub = (lby - 1) * TBW;
+        if (c0 >= 0) lds_unite(L, me, ub + c0);
+        if (c1 >= 0) lds_unite(L, me, ub + c1);
+        if (c2 >= 0) lds_unite(L, me, ub + c2);
     }
     __syncthreads();
+
     // resolve each run start; the other blocks of a run reach their root
     // through their run start
-    for (int i = threadIdx.x; i < NB; i += kThreads)
-        if (sbits[i] && srun[i] == (i & (TBW - 1))) L[i] = lds_find(L, i);
+#pragma unroll
+    for (int j = 0; j < RPW; j++) {
+        const int i = (wave + NWAVES * j) * TBW + lane;
+        if (st_bits(st[j]) && st_run(st[j]) == lane) L[i] = lds_root(L, i);
+    }
     __syncthreads();
-    auto root_of = [&](int i) { return L[(i & ~(TBW - 1)) + srun[i]]; };
-    // carry seed and border-contact flags to the local roots (32-bit LDS
-    // atomics on the flag bytes)
-    for (int i = threadIdx.x; i < NB; i += kThreads) {
-        if (!sbits[i]) continue;
-        const int lby = i / TBW, lbx = i % TBW;
-        const uint32_t f = (sflag[i] & 2u) | ((lby == 0 || lby == TBH - 1 || lbx == 0 || lbx == TBW - 1) ? 1u : 0u);
-        if (f) {
-            const int r = root_of(i);
+
+    // every block's root (through its run start); carry seed and
+    // border-contact flags to the local roots (32-bit LDS atomics on the flag
+    // bytes)
+    int root[RPW];
+#pragma unroll
+    for (int j = 0; j < RPW; j++) root[j] = L[(wave + NWAVES * j) * TBW + st_run(st[j])];
+#pragma unroll
+    for (int j = 0; j < RPW; j++) {
+        const int lby = wave + NWAVES * j;
+        const uint32_t f = ((st[j] >> 9) & 2u) | ((lby == 0 || lby == TBH - 1 || lane == 0 || lane == TBW - 1) ? 1u : 0u);
+        if (st_bits(st[j]) && f) {
+            const int r = root[j];
             atomicOr((unsigned int *)(sflag + (r & ~3)), f << (8 * (r & 3)));
         }
     }
     __syncthreads();
 
-    for (int i = threadIdx.x; i < NB; i += kThreads) {
-        const int lby = i / TBW, lbx = i % TBW;
-        const int by = ty * TBH + lby, bx = tx * TBW + lbx;
+#pragma unroll
+    for (int j = 0; j < RPW; j++) {
+        const int lby = wave + NWAVES * j, i = lby * TBW + lane;
+        const int by = ty * TBH + lby, bx = tx * TBW + lane;
         if (by >= g.BH || bx >= g.BW) continue;
         const int64_t id = (int64_t)by * g.BW + bx;
         // background blocks get a flag byte only: no later pass reads their
         // parent entry (every lookup starts from a foreground block)
-        if (sbits[i]) {
-            const int r = root_of(i);
+        if (st_bits(st[j])) {
+            const int r = root[j];
             glab[id] = (ty * TBH + r / TBW) * g.BW + tx * TBW + r % TBW;
             gflag[id] = r == i ? sflag[i] : (uint8_t)0;
         } else {
@@ -862,7 +940,7 @@ __global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__
 }
 
 template <int TBH>
-__global__ __launch_bounds__(kThreads) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
+__global__ __launch_bounds__(ccl_local_threads<TBH>()) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
                                                         int32_t *__restrict__ glab,
                                                         uint8_t *__restrict__ gflag) {
     ccl_local_tile<TBH>(g, b, y, z, blockIdx.x % ntx, blockIdx.x / ntx, glab, gflag);
@@ -978,6 +1056,18 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 //   BK_BLOCKS 256 blocks                  BK_GATHER four 256-block wave tasks
 //   BK_PCTH   kPctUnit channel elements   BK_ONE    one per image
 
+// The descriptor of image ii (wave-uniform) through scalar loads: the table
+// is written before the launch and only read while it runs.
+__device__ __forceinline__ BImg load_bimg(const BImg *imgs, int ii) {
+    static_assert(sizeof(BImg) % 4 == 0, "descriptor copied as 32-bit words");
+    const VLG_CONST uint32_t *p = (const VLG_CONST uint32_t *)(imgs + __builtin_amdgcn_readfirstlane(ii));
+    BImg r;
+    uint32_t *q = (uint32_t *)&r;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(BImg) / 4); k++) q[k] = p[k];
+    return r;
+}
+
 // d: the descriptor of unit u_'s image, reloaded only when the image changes
 #define VLG_BATCH_LOOP(A)                          \
     UnitRange ur_((A).prefix, (A).n);                  \
@@ -987,7 +1077,7 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 #define VLG_BATCH_IMG(A)                           \
     const int ii = ur_.img(u_);                        \
     if (ii != cur_) {                                  \
-        dcur_ = (A).imgs[ii];                          \
+        dcur_ = load_bimg((A).imgs, ii);                \
         cur_ = ii;                                     \
     }                                                  \
     const BImg &d = dcur_;
@@ -1033,7 +1123,7 @@ __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
 }
 
 template <int TBH>
-__global__ __launch_bounds__(kThreads) void kb_ccl_local(BatchArgs a, BRef b, BRef y, BRef z) {
+__global__ __launch_bounds__(ccl_local_threads<TBH>()) void kb_ccl_local(BatchArgs a, BRef b, BRef y, BRef z) {
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
@@ -1148,9 +1238,9 @@ hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z,
     if (!valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
     const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh);
     switch (w.tbh) {
-    case 8: k_ccl_local<8><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
-    case 16: k_ccl_local<16><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
-    default: k_ccl_local<32><<<ntx * nty, kThreads, 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
+    case 8: k_ccl_local<8><<<ntx * nty, ccl_local_threads<8>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
+    case 16: k_ccl_local<16><<<ntx * nty, ccl_local_threads<16>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
+    default: k_ccl_local<32><<<ntx * nty, ccl_local_threads<32>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
     }
     return hipGetLastError();
 }
@@ -1281,9 +1371,9 @@ hipError_t launch_b_ccl_local(hipStream_t s, const BatchArgs &a, int64_t total, 
     if (total == 0) return hipSuccess;
     const int grid = persistent_grid(a, total);
     switch (tbh) {
-    case 8: kb_ccl_local<8><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
-    case 16: kb_ccl_local<16><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
-    case 32: kb_ccl_local<32><<<grid, kThreads, 0, s>>>(a, b, y, z); break;
+    case 8: kb_ccl_local<8><<<grid, ccl_local_threads<8>(), 0, s>>>(a, b, y, z); break;
+    case 16: kb_ccl_local<16><<<grid, ccl_local_threads<16>(), 0, s>>>(a, b, y, z); break;
+    case 32: kb_ccl_local<32><<<grid, ccl_local_threads<32>(), 0, s>>>(a, b, y, z); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
