@@ -718,7 +718,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                 e = launch_b_ccl_merge(c->stream, args(BK_MERGE), units(BK_MERGE), tbh, bref(s.x));
                 break;
             case SK::CclFlag:
-                e = launch_b_ccl_flag(c->stream, args(BK_BLOCKS), units(BK_BLOCKS));
+                e = launch_b_ccl_flag(c->stream, args(BK_FLAG), units(BK_FLAG));
                 break;
             case SK::CclGather:
                 e = launch_b_ccl_gather(c->stream, args(BK_GATHER), units(BK_GATHER), bref(s.x), bref(s.y),

@@ -135,7 +135,7 @@ struct BRef {
     uint32_t inv;
 };
 
-enum BatchKind { BK_WORDS = 0, BK_LOGIC, BK_NEAR, BK_TILES, BK_MERGE, BK_BLOCKS, BK_GATHER, BK_PCTH, BK_ONE, BK_COUNT };
+enum BatchKind { BK_WORDS = 0, BK_LOGIC, BK_NEAR, BK_TILES, BK_MERGE, BK_BLOCKS, BK_FLAG, BK_GATHER, BK_PCTH, BK_ONE, BK_COUNT };
 
 struct BatchArgs {
     int n;

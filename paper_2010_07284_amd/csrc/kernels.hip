@@ -801,23 +801,61 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
     __builtin_amdgcn_wave_barrier();  // the window is rewritten by the wave's next tile
 }
 
-// Point a border-touching tile-local root at its final root and carry its
-// seed flag there.  Other local roots are final roots already.  A walker
-// writes only its own entry, so concurrent walkers never undo each other.
-__device__ __forceinline__ void ccl_flag_one(int32_t *glab_, uint8_t *gflag_, int64_t i) {
-    VLG_GLOBAL int32_t *glab = glb(glab_);
-    VLG_GLOBAL uint8_t *gflag = glb(gflag_);
-    const uint8_t f = gflag[i];
-    if (!(f & 1)) return;
-    int x = (int)i;
+// Point a border-touching tile-local root i (flag byte f) at its final root
+// and carry its seed flag there.  Other local roots are final roots already.
+// A walker writes only its own entry, so concurrent walkers never undo each
+// other.
+__device__ __forceinline__ void ccl_flag_walk(VLG_GLOBAL int32_t *glab, VLG_GLOBAL uint8_t *gflag, int i, uint32_t f) {
+    int x = i;
     while (true) {
         const int p = glab[x];
         if (p == x) break;
         x = p;
     }
-    if (x != (int)i) {
+    if (x != i) {
         glab[i] = x;
         if (f & 2) gflag[x] = 3;  // final roots are border-touching local roots
+    }
+}
+
+// Flag pass over blocks i0 .. i0+15 (i0 a multiple of 16): one 16-byte load
+// of their flag bytes, then a walk for each border-touching local root among
+// them (bit0 of its byte).  A byte that another walker rewrites after the
+// load is either a final root (the walk ends at once) or unchanged.
+__device__ __forceinline__ void ccl_flag16(int32_t *glab_, uint8_t *gflag_, int64_t nb, int64_t i0) {
+    VLG_GLOBAL int32_t *glab = glb(glab_);
+    VLG_GLOBAL uint8_t *gflag = glb(gflag_);
+    uint64_t lo = 0, hi = 0;
+    if (i0 + 16 <= nb && ((uintptr_t)(gflag_ + i0) & 7) == 0) {
+        const VLG_GLOBAL uint64_t *q = (const VLG_GLOBAL uint64_t *)(gflag + i0);
+        lo = q[0];
+        hi = q[1];
+    } else {
+        for (int k = 0; k < 16 && i0 + k < nb; k++) {
+            const uint64_t v = gflag[i0 + k];
+            if (k < 8)
+                lo |= v << (8 * k);
+            else
+                hi |= v << (8 * (k - 8));
+        }
+    }
+    constexpr uint64_t kBit0 = 0x0101010101010101ull;
+    uint64_t mlo = lo & kBit0, mhi = hi & kBit0;
+    while (mlo | mhi) {
+        int bit, k;
+        uint32_t f;
+        if (mlo) {
+            bit = __builtin_ctzll(mlo);
+            mlo &= mlo - 1;
+            k = bit >> 3;
+            f = (uint32_t)(lo >> bit) & 0xFF;
+        } else {
+            bit = __builtin_ctzll(mhi);
+            mhi &= mhi - 1;
+            k = 8 + (bit >> 3);
+            f = (uint32_t)(hi >> bit) & 0xFF;
+        }
+        ccl_flag_walk(glab, gflag, (int)(i0 + k), f);
     }
 }
 
@@ -960,9 +998,9 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, 
 }
 
 __global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride)
-        ccl_flag_one(glab, gflag, i);
+    const int64_t stride = (int64_t)gridDim.x * kThreads * 16;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 16; i0 < nblocks; i0 += stride)
+        ccl_flag16(glab, gflag, nblocks, i0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, MRef z,
@@ -1054,6 +1092,7 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 //   BK_NEAR   four near bands (64 words wide, kBatchNearRows rows high)
 //   BK_TILES  one labelling tile          BK_MERGE  four tiles (one per wave)
 //   BK_BLOCKS 256 blocks                  BK_GATHER four 256-block wave tasks
+//   BK_FLAG   4096 blocks (16 per thread)
 //   BK_PCTH   kPctUnit channel elements   BK_ONE    one per image
 
 // The descriptor of image ii (wave-uniform) through scalar loads: the table
@@ -1150,8 +1189,8 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
 __global__ __launch_bounds__(kThreads) void kb_ccl_flag(BatchArgs a) {
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
-        const int64_t i = (u_ - a.prefix[ii]) * kThreads + threadIdx.x;
-        if (i < (int64_t)d.g.BH * d.g.BW) ccl_flag_one((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), i);
+        const int64_t i0 = ((u_ - a.prefix[ii]) * kThreads + threadIdx.x) * 16, nb = (int64_t)d.g.BH * d.g.BW;
+        if (i0 < nb) ccl_flag16((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), nb, i0);
     }
 }
 
@@ -1261,7 +1300,7 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
 hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w) {
     if (g.nwords == 0) return hipSuccess;
     const int64_t nb = (int64_t)g.BH * g.BW;
-    k_ccl_flag<<<grid_for(nb, kThreads, 8192), kThreads, 0, s>>>(nb, w.glab, w.gflag);
+    k_ccl_flag<<<grid_for((nb + 15) / 16, kThreads, 65536), kThreads, 0, s>>>(nb, w.glab, w.gflag);
     return hipGetLastError();
 }
 
@@ -1334,6 +1373,7 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     case BK_TILES: return ntiles;
     case BK_MERGE: return (ntiles + kThreads / 64 - 1) / (kThreads / 64);
     case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
+    case BK_FLAG: return (nb + 16 * kThreads - 1) / (16 * kThreads);
     case BK_GATHER: return ((int64_t)g.BH * ((g.wpr + 7) / 8) + 3) / 4;
     case BK_PCTH: return ((int64_t)g.H * g.wpr * 64 + kPctUnit - 1) / kPctUnit;
     case BK_ONE: return 1;
