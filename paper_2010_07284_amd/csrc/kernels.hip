@@ -861,9 +861,12 @@ __device__ __forceinline__ void ccl_flag16(int32_t *glab_, uint8_t *gflag_, int6
 
 // out = (y & z) | Z, Z = the b-pixels whose component meets the seeds.  Every
 // foreground block points at a local root and every local root at its final
-// root, so the root is two loads away.  Wave task t: 256 blocks of one block
-// row (512 pixels = 8 words of two rows); lane l owns blocks 4l .. 4l+3, i.e.
-// byte l of those 8 words, assembled in this wave's 8 LDS words zw.
+// root, so the root is two loads away; the flag byte of the local root is
+// loaded beside its parent entry and is the final one when the local root is
+// a final root.  Wave task t: 256 blocks of one block row (512 pixels = 8
+// words of two rows); lane l owns blocks 4l .. 4l+3, i.e. byte l of those 8
+// words, assembled in this wave's 8 LDS words zw.  Lanes 0..15 load the
+// output words' operands up front.
 __device__ __forceinline__ void ccl_gather_task(const Geo &g, const MRef &b, const MRef &y, const MRef &z,
                                                 const int32_t *__restrict__ glab_, const uint8_t *__restrict__ gflag_,
                                                 int user, uint64_t *__restrict__ out_, int64_t t, uint64_t *zw) {
@@ -874,6 +877,15 @@ __device__ __forceinline__ void ccl_gather_task(const Geo &g, const MRef &b, con
     const int nq = (g.wpr + 7) / 8;
     const int by = (int)(t / nq), q = (int)(t - (int64_t)by * nq);
     const int y0 = 2 * by;
+    // output word of lanes 0..15: row y0 + lane/8, word 8q + lane%8
+    const int oy = y0 + (lane >> 3), ow = 8 * q + (lane & 7);
+    const bool ovalid = lane < 16 && oy < g.H && ow < g.wpr;
+    const int64_t oi = ovalid ? (int64_t)oy * g.wpr + ow : 0;
+    uint64_t oyz = 0, ob = 0;
+    if (ovalid) {
+        oyz = ldm(y, oi) & ldm(z, oi);
+        ob = ldm(b, oi);
+    }
     const int w = 8 * q + (lane >> 3), sh = (lane & 7) * 8;  // word and bit offset of my byte
     uint32_t top = 0, bot = 0;
     if (w < g.wpr) {
@@ -890,21 +902,24 @@ __device__ __forceinline__ void ccl_gather_task(const Geo &g, const MRef &b, con
 #pragma unroll
         for (int j = 0; j < 4; j++) lr[j] = ((any >> (2 * j)) & 3) ? glab[id0 + j] : -1;
         int r[4];
+        uint32_t f[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) r[j] = lr[j] >= 0 ? glab[lr[j]] : -1;
+        for (int j = 0; j < 4; j++) {
+            r[j] = lr[j] >= 0 ? glab[lr[j]] : -1;
+            f[j] = lr[j] >= 0 ? gflag[lr[j]] : 0u;
+        }
 #pragma unroll
         for (int j = 0; j < 4; j++)
-            if (r[j] >= 0 && ((gflag[r[j]] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
+            if (r[j] >= 0 && r[j] != lr[j]) f[j] = gflag[r[j]];
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (r[j] >= 0 && ((f[j] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
     }
     ((uint8_t *)zw)[lane] = (uint8_t)zbyte;
     __builtin_amdgcn_wave_barrier();
-    if (lane < 16) {
-        const int yy = y0 + (lane >> 3), ww = 8 * q + (lane & 7);
-        if (yy < g.H && ww < g.wpr) {
-            const int64_t i = (int64_t)yy * g.wpr + ww;
-            const uint64_t keep = ww == g.wpr - 1 ? g.tail : ~0ull;
-            out[i] = ((ldm(y, i) & ldm(z, i)) | (ldm(b, i) & zw[lane & 7])) & keep;
-        }
+    if (ovalid) {
+        const uint64_t keep = ow == g.wpr - 1 ? g.tail : ~0ull;
+        out[oi] = (oyz | (ob & zw[lane & 7])) & keep;
     }
     __builtin_amdgcn_wave_barrier();
 }
