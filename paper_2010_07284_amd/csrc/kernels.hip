@@ -337,11 +337,10 @@ __device__ __forceinline__ void atoms_task(const Geo &g, const T *__restrict__ i
 // Blocks: block (by, bx) holds pixels rows 2by..2by+1, cols 2bx..2bx+1.  Its
 // four bits: 1 = top-left, 2 = top-right, 4 = bottom-left, 8 = bottom-right.
 // Any two foreground pixels of one block are 8-adjacent, so a block is a
-// union-find node.  Block ids are row-major, id = by*BW + bx; the root of a
-// set is its smallest id.  (That block need not hold the component's first
-// pixel in raster order: a block with only bottom-row pixels precedes a later
-// block of the same block row whose top-row pixel comes first.  Canonical
-// pixel labels therefore take a minimum over each component.)
+// union-find node.  Block ids are row-major, id = by*BW + bx.  Inside a tile
+// the root of a set is its smallest id; across tiles roots are linked by a
+// pseudo-random priority of their ids (see g_unite).  Canonical pixel labels
+// therefore take a minimum over each component.
 //
 // 8-adjacency between a block and its earlier neighbours:
 //   left:       (tl|bl) of the block and (tr|br) of the left block
@@ -403,11 +402,18 @@ __device__ __forceinline__ int lds_root(int *L, int x) {
     }
 }
 
-// Global union-find for the cross-tile merge.  Plain loads and stores may
-// see stale values (the L2 of one XCD is not coherent with another's within a
-// kernel); that costs retries, never correctness: every value ever stored in
-// L[x] is an ancestor of x (L[x] <= x), sets only grow, and a failed
-// atomicMin hands back the current parent, which is then united in turn.
+// Global union-find for the cross-tile merge.  A root is hooked under the
+// root of smaller priority uf_prio(id), a bijective mix of the id, so the
+// priority strictly falls along every parent path.  Linking by id instead
+// turns a row of tiles whose components join left to right (a corridor
+// crossing the image) into a chain as long as the row, because every tile
+// hooks under its left neighbour at the same time; pseudo-random priorities
+// keep the expected depth logarithmic.  Plain loads and stores may see stale
+// values (the L2 of one XCD is not coherent with another's within a kernel);
+// that costs retries, never correctness: every value ever stored in L[x] is
+// an ancestor of x, sets only grow, and a hook is a compare-and-swap that
+// succeeds only on a current root and otherwise hands back the current
+// parent, which is then united in turn.
 //
 // g_find2: the roots of a and b, walked in lockstep (path halving on both) so
 // that the loads of the two paths overlap.
@@ -435,18 +441,25 @@ __device__ __forceinline__ void g_find2(VLG_GLOBAL int *L, int &a, int &b) {
     }
 }
 
+__device__ __forceinline__ uint32_t uf_prio(int x) {
+    uint32_t h = (uint32_t)x * 0x9E3779B1u;  // odd multiplier: a bijection
+    return h ^ (h >> 16);                     // invertible xor-shift
+}
+
 __device__ int g_unite(VLG_GLOBAL int *L, int a, int b) {
     int tries = 0;
     while (true) {
         tries++;
         g_find2(L, a, b);
         if (a == b) return tries;
-        if (a < b) {
+        if (uf_prio(a) < uf_prio(b)) {
             const int t = a;
             a = b;
             b = t;
         }
-        const int old = __hip_atomic_fetch_min(&L[a], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int old = a;  // hook a (larger priority) under b if a is still a root
+        __hip_atomic_compare_exchange_strong(&L[a], &old, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
         if (old == a) return tries;
         a = old;
     }
