@@ -513,6 +513,8 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     __shared__ uint16_t sbr[NB];              // block bits | run start column << 4
     __shared__ alignas(4) uint8_t sflag[NB];  // bit0 touches the tile border, bit1 seed
     __shared__ int sany;
+    constexpr int kPairQueue = 192;              // union pairs per wave: me | other << 16
+    __shared__ int spair[NWAVES][kPairQueue];
     // the thread index is made opaque per tile so that a persistent
     // workgroup recomputes its per-row addressing in each tile instead of
     // holding it in registers across the whole tile loop
@@ -611,7 +613,14 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     auto st_run = [](uint32_t s) { return (int)((s >> 4) & 63u); };
     __syncthreads();
 
-    // unite the runs of each row with the runs they touch in the row above
+    // unite the runs of each row with the runs they touch in the row above.
+    // The wave first lists the pairs of all its rows (at most three per lane
+    // and row) in its LDS queue, then every lane takes pairs from the queue:
+    // a row's unions are usually held by a few lanes (the run starts), and
+    // taking them row by row in those lanes would chain the rows' union walks
+    // one after another.  Pairs beyond the queue's capacity are united by
+    // their own lane at once.
+    int npairs = 0;  // wave-uniform
 #pragma unroll
     for (int j = 0; j < RPW; j++) {
         const int lby = wave + NWAVES * j, up = (lby - 1) * TBW + lane;
@@ -633,9 +642,25 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
             if (c2 >= 0 && (c2 == l0 || c2 == l1 || c2 == l2)) c2 = -1;
         }
         const int me = lby * TBW + st_run(st[j]), ub = (lby - 1) * TBW;
-        if (c0 >= 0) lds_unite(L, me, ub + c0);
-        if (c1 >= 0) lds_unite(L, me, ub + c1);
-        if (c2 >= 0) lds_unite(L, me, ub + c2);
+        const int cs[3] = {c0, c1, c2};
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint64_t has = __ballot(cs[k] >= 0);
+            if (cs[k] >= 0) {
+                const int q = npairs + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(has >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)has, 0u));
+                if (q < kPairQueue)
+                    spair[wave][q] = me | ((ub + cs[k]) << 16);
+                else
+                    lds_unite(L, me, ub + cs[k]);
+            }
+            npairs += __popcll(has);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < (npairs < kPairQueue ? npairs : kPairQueue); q += 64) {
+        const int pr = spair[wave][q];
+        lds_unite(L, pr & 0xFFFF, pr >> 16);
     }
     __syncthreads();
 
