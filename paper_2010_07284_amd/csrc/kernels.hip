@@ -513,8 +513,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     __shared__ uint16_t sbr[NB];              // block bits | run start column << 4
     __shared__ alignas(4) uint8_t sflag[NB];  // bit0 touches the tile border, bit1 seed
     __shared__ int sany;
-    constexpr int kPairQueue = 256;              // union pairs per wave: me | other << 16
-    static_assert(64 * RPW <= kPairQueue, "the queue holds every run start of a wave's rows");
+    constexpr int kPairQueue = 192;              // union pairs per wave: me | other << 16
     __shared__ int spair[NWAVES][kPairQueue];
     // the thread index is made opaque per tile so that a persistent
     // workgroup recomputes its per-row addressing in each tile instead of
@@ -666,25 +665,11 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     __syncthreads();
 
     // resolve each run start; the other blocks of a run reach their root
-    // through their run start.  The run starts of the wave's rows (at most 64
-    // per row) are spread over its lanes through the same queue.
-    {
-        int nstart = 0;  // wave-uniform
+    // through their run start
 #pragma unroll
-        for (int j = 0; j < RPW; j++) {
-            const bool is_start = st_bits(st[j]) && st_run(st[j]) == lane;
-            const uint64_t has = __ballot(is_start);
-            if (is_start)
-                spair[wave][nstart + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(has >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)has, 0u))] =
-                    (wave + NWAVES * j) * TBW + lane;
-            nstart += __popcll(has);
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int q = lane; q < nstart; q += 64) {
-            const int i = spair[wave][q];
-            L[i] = lds_root(L, i);
-        }
+    for (int j = 0; j < RPW; j++) {
+        const int i = (wave + NWAVES * j) * TBW + lane;
+        if (st_bits(st[j]) && st_run(st[j]) == lane) L[i] = lds_root(L, i);
     }
     __syncthreads();
 
