@@ -1539,19 +1539,6 @@ __device__ void pct_init_wg(PctState *st_, uint32_t k) {
     }
 }
 
-// Add 1 at bin[lane] for the active lanes of a wave.  Lanes that share the
-// first active lane's bin are counted by one atomic (channel values cluster,
-// so much of a wave often falls into one bin, and 64 atomics on one LDS
-// address would serialise); the others add their own.
-__device__ __forceinline__ void wave_hist_add(uint32_t *h, uint32_t bin, bool act) {
-    const uint64_t am = __ballot(act);
-    if (!am) return;
-    const int leader = __builtin_ctzll(am);  // wave-uniform
-    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)bin, leader);
-    const uint64_t same = __ballot(act && bin == b0);
-    if (lane_id() == leader) atomicAdd(&h[b0], (uint32_t)__popcll(same));
-    else if (act && bin != b0) atomicAdd(&h[bin], 1u);
-}
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
@@ -1563,6 +1550,61 @@ template <> struct Vec4<uint8_t> { typedef uint8_t type __attribute__((ext_vecto
 // elements share a row), for the n selections st[0..n): selections whose
 // digits chosen so far agree share one LDS histogram (in the first pass all
 // of them do), then every selection's histogram is added into its state.
+// The streaming part of a histogram pass over elements [i0, i1): MG is the
+// number of groups the group test has to try (one in every first pass).
+template <typename T, int MG>
+__device__ __forceinline__ void pct_hist_stream(const Geo &g, const T *__restrict__ img, int m, const uint32_t *pre,
+                                                const uint32_t *msk, int shift, int bins, int64_t i0, int64_t i1,
+                                                int64_t stride, uint32_t (*h)[2048]) {
+    const int64_t pitch = (int64_t)g.wpr * 64;
+    const uint32_t dmask = (uint32_t)(bins - 1);
+    using V = typename Vec4<T>::type;
+    constexpr int U = 4;  // chunks per iteration: U vector loads in flight per thread
+    for (int64_t c = i0; c < i1; c += U * stride) {
+        V v[U];
+        int64_t idx[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            idx[u] = c + u * stride + threadIdx.x * 4;
+            v[u] = *(const VLG_GLOBAL V *)(glb(img) + (idx[u] < i1 ? idx[u] : i0));
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = idx[u];
+            const bool in = i < i1;
+            const uint32_t row = fdiv((uint32_t)(i >> 6), g.wpr_mul, g.wpr_shift);
+            const int64_t col = i - (int64_t)row * pitch;
+            const float f[4] = {(float)v[u].x, (float)v[u].y, (float)v[u].z, (float)v[u].w};
+            uint32_t key[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) key[e] = sizeof(T) == 1 ? (uint32_t)f[e] : f32_key(f[e]);
+            // the groups of a pass share the digit mask and differ in prefix,
+            // so an element belongs to at most one of them
+            uint32_t bin[4];
+            bool act[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int grp = -1;
+#pragma unroll
+                for (int q = MG - 1; q >= 0; q--)
+                    if (q < m && (key[e] & msk[q]) == pre[q]) grp = q;
+                act[e] = in && col + e < g.W && grp >= 0;
+                bin[e] = (uint32_t)max(grp, 0) * 2048u + ((key[e] >> shift) & dmask);
+            }
+            // four neighbouring elements in one bin (channel values cluster)
+            // take one atomic; otherwise each active element adds its own
+            uint32_t *hh = &h[0][0];
+            if (act[0] && act[1] && act[2] && act[3] && bin[0] == bin[1] && bin[1] == bin[2] && bin[2] == bin[3]) {
+                atomicAdd(&hh[bin[0]], 4u);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    if (act[e]) atomicAdd(&hh[bin[e]], 1u);
+            }
+        }
+    }
+}
+
 template <typename T>
 __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState *const *st, int n, int shift,
                                int bins, int64_t i0, int64_t i1, int64_t stride, uint32_t (*h)[2048]) {
@@ -1597,41 +1639,10 @@ __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState
     for (int q = 0; q < m; q++)
         for (int i = threadIdx.x; i < bins; i += kThreads) h[q][i] = 0;
     __syncthreads();
-    const int64_t pitch = (int64_t)g.wpr * 64;
-    const uint32_t dmask = (uint32_t)(bins - 1);
-    using V = typename Vec4<T>::type;
-    constexpr int U = 4;  // chunks per iteration: U vector loads in flight per thread
-    for (int64_t c = i0; c < i1; c += U * stride) {
-        V v[U];
-        int64_t idx[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            idx[u] = c + u * stride + threadIdx.x * 4;
-            v[u] = *(const VLG_GLOBAL V *)(glb(img) + (idx[u] < i1 ? idx[u] : i0));
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i = idx[u];
-            const bool in = i < i1;
-            const uint32_t row = fdiv((uint32_t)(i >> 6), g.wpr_mul, g.wpr_shift);
-            const int64_t col = i - (int64_t)row * pitch;
-            const float f[4] = {(float)v[u].x, (float)v[u].y, (float)v[u].z, (float)v[u].w};
-            uint32_t key[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) key[e] = sizeof(T) == 1 ? (uint32_t)f[e] : f32_key(f[e]);
-            // the groups of a pass share the digit mask and differ in prefix,
-            // so an element belongs to at most one of them
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                int grp = -1;
-#pragma unroll
-                for (int q = kMaxPctSel - 1; q >= 0; q--)
-                    if (q < m && (key[e] & msk[q]) == pre[q]) grp = q;
-                const bool act = in && col + e < g.W && grp >= 0;
-                wave_hist_add(&h[0][0], (uint32_t)max(grp, 0) * 2048u + ((key[e] >> shift) & dmask), act);
-            }
-        }
-    }
+    if (m == 1)
+        pct_hist_stream<T, 1>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
+    else
+        pct_hist_stream<T, kMaxPctSel>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
     __syncthreads();
     for (int j = 0; j < n; j++)
         for (int i = threadIdx.x; i < bins; i += kThreads) {
