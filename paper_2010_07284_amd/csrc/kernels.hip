@@ -901,66 +901,94 @@ __device__ __forceinline__ void ccl_flag16(int32_t *glab_, uint8_t *gflag_, int6
 // foreground block points at a local root and every local root at its final
 // root, so the root is two loads away; the flag byte of the local root is
 // loaded beside its parent entry and is the final one when the local root is
-// a final root.  Wave task t: 256 blocks of one block row (512 pixels = 8
-// words of two rows); lane l owns blocks 4l .. 4l+3, i.e. byte l of those 8
-// words, assembled in this wave's 8 LDS words zw.  Lanes 0..15 load the
-// output words' operands up front.
-__device__ __forceinline__ void ccl_gather_task(const Geo &g, const MRef &b, const MRef &y, const MRef &z,
-                                                const int32_t *__restrict__ glab_, const uint8_t *__restrict__ gflag_,
-                                                int user, uint64_t *__restrict__ out_, int64_t t, uint64_t *zw) {
+// a final root.  A task is 256 blocks of one block row (512 pixels = 8 words
+// of two rows); lane l owns blocks 4l .. 4l+3, i.e. byte l of those 8 words,
+// assembled in LDS (zw: 8 words per task).  A wave takes NT consecutive tasks
+// t0 .. t0+NT-1 (those below ntasks) and walks them together, so their
+// dependent loads overlap.  Lanes 0..15 load the output words' operands up
+// front.
+template <int NT>
+__device__ __forceinline__ void ccl_gather_tasks(const Geo &g, const MRef &b, const MRef &y, const MRef &z,
+                                                 const int32_t *__restrict__ glab_, const uint8_t *__restrict__ gflag_,
+                                                 int user, uint64_t *__restrict__ out_, int64_t t0, int64_t ntasks,
+                                                 uint64_t *zw) {
     const VLG_GLOBAL int32_t *glab = glb(glab_);
     const VLG_GLOBAL uint8_t *gflag = glb(gflag_);
     VLG_GLOBAL uint64_t *out = glb(out_);
     const int lane = lane_id();
     const int nq = (g.wpr + 7) / 8;
-    const int by = (int)(t / nq), q = (int)(t - (int64_t)by * nq);
-    const int y0 = 2 * by;
-    // output word of lanes 0..15: row y0 + lane/8, word 8q + lane%8
-    const int oy = y0 + (lane >> 3), ow = 8 * q + (lane & 7);
-    const bool ovalid = lane < 16 && oy < g.H && ow < g.wpr;
-    const int64_t oi = ovalid ? (int64_t)oy * g.wpr + ow : 0;
-    uint64_t oyz = 0, ob = 0;
-    if (ovalid) {
-        oyz = ldm(y, oi) & ldm(z, oi);
-        ob = ldm(b, oi);
-    }
-    const int w = 8 * q + (lane >> 3), sh = (lane & 7) * 8;  // word and bit offset of my byte
-    uint32_t top = 0, bot = 0;
-    if (w < g.wpr) {
-        const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
-        top = (uint32_t)(((ldm(b, (int64_t)y0 * g.wpr + w) & keep) >> sh) & 0xFF);
-        if (y0 + 1 < g.H) bot = (uint32_t)(((ldm(b, (int64_t)(y0 + 1) * g.wpr + w) & keep) >> sh) & 0xFF);
-    }
-    const uint32_t any = top | bot;
-    uint32_t zbyte = 0;
-    if (any) {
-        const int bx0 = 256 * q + 4 * lane;
-        const int64_t id0 = (int64_t)by * g.BW + bx0;
-        int lr[4];
+    bool ovalid[NT];
+    int64_t oi[NT];
+    uint64_t oyz[NT], ob[NT];
+    uint32_t any[NT];
+    int by[NT], q[NT];
 #pragma unroll
-        for (int j = 0; j < 4; j++) lr[j] = ((any >> (2 * j)) & 3) ? glab[id0 + j] : -1;
-        int r[4];
-        uint32_t f[4];
+    for (int k = 0; k < NT; k++) {
+        const int64_t t = t0 + k;
+        const bool valid = t < ntasks;
+        by[k] = valid ? (int)(t / nq) : 0;
+        q[k] = valid ? (int)(t - (int64_t)by[k] * nq) : 0;
+        const int y0 = 2 * by[k];
+        // output word of lanes 0..15: row y0 + lane/8, word 8q + lane%8
+        const int oy = y0 + (lane >> 3), ow = 8 * q[k] + (lane & 7);
+        ovalid[k] = valid && lane < 16 && oy < g.H && ow < g.wpr;
+        oi[k] = ovalid[k] ? (int64_t)oy * g.wpr + ow : 0;
+        oyz[k] = 0;
+        ob[k] = 0;
+        if (ovalid[k]) {
+            oyz[k] = ldm(y, oi[k]) & ldm(z, oi[k]);
+            ob[k] = ldm(b, oi[k]);
+        }
+        const int w = 8 * q[k] + (lane >> 3), sh = (lane & 7) * 8;  // word and bit offset of my byte
+        uint32_t top = 0, bot = 0;
+        if (valid && w < g.wpr) {
+            const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+            top = (uint32_t)(((ldm(b, (int64_t)y0 * g.wpr + w) & keep) >> sh) & 0xFF);
+            if (y0 + 1 < g.H) bot = (uint32_t)(((ldm(b, (int64_t)(y0 + 1) * g.wpr + w) & keep) >> sh) & 0xFF);
+        }
+        any[k] = top | bot;
+    }
+    int lr[NT][4];
+#pragma unroll
+    for (int k = 0; k < NT; k++) {
+        const int64_t id0 = (int64_t)by[k] * g.BW + 256 * q[k] + 4 * lane;
+#pragma unroll
+        for (int j = 0; j < 4; j++) lr[k][j] = ((any[k] >> (2 * j)) & 3) ? glab[id0 + j] : -1;
+    }
+    int r[NT][4];
+    uint32_t f[NT][4];
+#pragma unroll
+    for (int k = 0; k < NT; k++)
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            r[j] = lr[j] >= 0 ? glab[lr[j]] : -1;
-            f[j] = lr[j] >= 0 ? gflag[lr[j]] : 0u;
+            r[k][j] = lr[k][j] >= 0 ? glab[lr[k][j]] : -1;
+            f[k][j] = lr[k][j] >= 0 ? gflag[lr[k][j]] : 0u;
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++)
-            if (r[j] >= 0 && r[j] != lr[j]) f[j] = gflag[r[j]];
+    for (int k = 0; k < NT; k++)
 #pragma unroll
         for (int j = 0; j < 4; j++)
-            if (r[j] >= 0 && ((f[j] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
+            if (r[k][j] >= 0 && r[k][j] != lr[k][j]) f[k][j] = gflag[r[k][j]];
+#pragma unroll
+    for (int k = 0; k < NT; k++) {
+        uint32_t zbyte = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (r[k][j] >= 0 && ((f[k][j] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
+        ((uint8_t *)zw)[64 * k + lane] = (uint8_t)zbyte;
     }
-    ((uint8_t *)zw)[lane] = (uint8_t)zbyte;
     __builtin_amdgcn_wave_barrier();
-    if (ovalid) {
-        const uint64_t keep = ow == g.wpr - 1 ? g.tail : ~0ull;
-        out[oi] = (oyz | (ob & zw[lane & 7])) & keep;
-    }
+#pragma unroll
+    for (int k = 0; k < NT; k++)
+        if (ovalid[k]) {
+            const int ow = 8 * q[k] + (lane & 7);
+            const uint64_t keep = ow == g.wpr - 1 ? g.tail : ~0ull;
+            out[oi[k]] = (oyz[k] | (ob[k] & zw[8 * k + (lane & 7)])) & keep;
+        }
     __builtin_amdgcn_wave_barrier();
 }
+
+constexpr int kGatherTasksPerWave = 2;
 
 // Mark, for labelling user `user`, the components of the current labelling
 // that meet the seed mask sm (= N(seeds) & b): bit 1+user of the root's flag
@@ -1060,12 +1088,13 @@ __global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, 
                                                          const int32_t *__restrict__ glab,
                                                          const uint8_t *__restrict__ gflag, int user,
                                                          uint64_t *__restrict__ out) {
-    __shared__ uint64_t zw[kThreads / 64][8];
+    constexpr int NT = kGatherTasksPerWave;
+    __shared__ uint64_t zw[kThreads / 64][8 * NT];
     const int wv = threadIdx.x >> 6;
     const int64_t ntasks = (int64_t)g.BH * ((g.wpr + 7) / 8);
     const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wv; t < ntasks; t += nwaves)
-        ccl_gather_task(g, b, y, z, glab, gflag, user, out, t, zw[wv]);
+    for (int64_t t = ((int64_t)blockIdx.x * (kThreads / 64) + wv) * NT; t < ntasks; t += nwaves * NT)
+        ccl_gather_tasks<NT>(g, b, y, z, glab, gflag, user, out, t, ntasks, zw[wv]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const int32_t *__restrict__ glab,
@@ -1144,7 +1173,7 @@ __global__ void k_fill_i64(unsigned long long *p, int n, unsigned long long v) {
 //   BK_LOGIC  1024 mask words (Boolean steps)
 //   BK_NEAR   four near bands (64 words wide, kBatchNearRows rows high)
 //   BK_TILES  one labelling tile          BK_MERGE  four tiles (one per wave)
-//   BK_BLOCKS 256 blocks                  BK_GATHER four 256-block wave tasks
+//   BK_BLOCKS 256 blocks                  BK_GATHER eight 256-block tasks (two per wave)
 //   BK_FLAG   4096 blocks (16 per thread)
 //   BK_PCTH   kPctUnit channel elements   BK_ONE    one per image
 
@@ -1248,14 +1277,16 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_flag(BatchArgs a) {
 }
 
 __global__ __launch_bounds__(kThreads) void kb_ccl_gather(BatchArgs a, BRef b, BRef y, BRef z, int user, int32_t out) {
-    __shared__ uint64_t zw[kThreads / 64][8];
+    constexpr int NT = kGatherTasksPerWave;
+    __shared__ uint64_t zw[kThreads / 64][8 * NT];
     const int wv = threadIdx.x >> 6;
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
-        const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + wv;
-        if (t < (int64_t)d.g.BH * ((d.g.wpr + 7) / 8))
-            ccl_gather_task(d.g, bref(d, b), bref(d, y), bref(d, z), (const int32_t *)(d.ws + d.off_glab),
-                            (const uint8_t *)(d.ws + d.off_gflag), user, bptr(d, out), t, zw[wv]);
+        const int64_t t = ((u_ - a.prefix[ii]) * (kThreads / 64) + wv) * NT;
+        const int64_t ntasks = (int64_t)d.g.BH * ((d.g.wpr + 7) / 8);
+        if (t < ntasks)
+            ccl_gather_tasks<NT>(d.g, bref(d, b), bref(d, y), bref(d, z), (const int32_t *)(d.ws + d.off_glab),
+                                 (const uint8_t *)(d.ws + d.off_gflag), user, bptr(d, out), t, ntasks, zw[wv]);
     }
 }
 
@@ -1361,8 +1392,8 @@ hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z
                              int user, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
     const int64_t tasks = (int64_t)g.BH * ((g.wpr + 7) / 8);
-    k_ccl_gather<<<grid_for(tasks, kThreads / 64, 8192), kThreads, 0, s>>>(g, b, y, z, w.glab, w.gflag, user,
-                                                                            out);
+    const int grid = grid_for((tasks + kGatherTasksPerWave - 1) / kGatherTasksPerWave, kThreads / 64, 8192);
+    k_ccl_gather<<<grid, kThreads, 0, s>>>(g, b, y, z, w.glab, w.gflag, user, out);
     return hipGetLastError();
 }
 
@@ -1427,7 +1458,10 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     case BK_MERGE: return (ntiles + kThreads / 64 - 1) / (kThreads / 64);
     case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
     case BK_FLAG: return (nb + 16 * kThreads - 1) / (16 * kThreads);
-    case BK_GATHER: return ((int64_t)g.BH * ((g.wpr + 7) / 8) + 3) / 4;
+    case BK_GATHER: {
+        const int64_t per = (int64_t)kGatherTasksPerWave * (kThreads / 64);  // tasks per unit
+        return ((int64_t)g.BH * ((g.wpr + 7) / 8) + per - 1) / per;
+    }
     case BK_PCTH: return ((int64_t)g.H * g.wpr * 64 + kPctUnit - 1) / kPctUnit;
     case BK_ONE: return 1;
     }
