@@ -1048,7 +1048,7 @@ __global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt, in
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__ img, AtomLaunch a) {
     __shared__ float sthr[kMaxAtomsPerLaunch];
-    if (threadIdx.x < a.n)
+    if ((int)threadIdx.x < a.n)
         sthr[threadIdx.x] = a.thr_dev[threadIdx.x] ? *a.thr_dev[threadIdx.x] : a.thr[threadIdx.x];
     __syncthreads();
     const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
         __syncthreads();  // the previous unit is done with sthr
-        if (threadIdx.x < op.n) {
+        if ((int)threadIdx.x < op.n) {
             const int p = op.pct[threadIdx.x];
             sthr[threadIdx.x] = p >= 0 ? glb((const float *)(d.ws + d.off_pct))[p] : op.thr[threadIdx.x];
         }
