@@ -198,7 +198,7 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
  *     (default: from the image size).  Taller bands reload fewer halo rows,
  *     shorter ones give more parallel bands.
  *   VLG_TUNE_BATCH_GRID: workgroups of a persistent batched launch: 1024,
- *     2048 (default), 4096 or 8192.
+ *     2048, 4096 or 8192 (default).
  *   VLG_TUNE_CCL_LANES: labelling lanes of the fused schedule: 1 (default),
  *     2 or 4.  With more than one, independent labellings of a scheduling
  *     round run concurrently on separate streams, each with its own

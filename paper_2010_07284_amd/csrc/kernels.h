@@ -38,7 +38,7 @@ __host__ __device__ inline int near_band_rows(const Geo &g) {
 }
 constexpr int kBatchNearRows = 8;
 inline bool valid_near_rows(int r) { return r == 4 || r == 8 || r == 16 || r == 32; }
-constexpr int kBatchGridDefault = 2048;
+constexpr int kBatchGridDefault = 8192;
 inline bool valid_batch_grid(int n) { return n == 1024 || n == 2048 || n == 4096 || n == 8192; }
 __host__ __device__ inline int64_t near_tasks(const Geo &g, int R) {
     return (int64_t)((g.H + R - 1) / R) * ((g.wpr + 63) / 64);
