@@ -193,7 +193,9 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
  * per batch class, filled by vlg_autotune_batch).
  *   VLG_TUNE_CCL_TILE_ROWS: block rows (2x2 pixels each) per labelling tile:
  *     8, 16 or 32; tiles are 128 pixels wide.  Taller tiles do more work in
- *     LDS and leave fewer tile borders to merge globally.
+ *     LDS and leave fewer tile borders to merge globally.  Default: the
+ *     tallest height that leaves at least 1024 tiles (counted over the whole
+ *     batch for vlg_check_batch), else 8.
  *   VLG_TUNE_NEAR_ROWS: rows per band of the near kernel: 4, 8, 16 or 32
  *     (default: from the image size).  Taller bands reload fewer halo rows,
  *     shorter ones give more parallel bands.

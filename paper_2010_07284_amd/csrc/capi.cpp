@@ -210,7 +210,7 @@ int tuned_value(const vlg_ctx *c, int which, int H, int W) {
     auto it = c->tuned.find({log2_class(H), log2_class(W)});
     if (it != c->tuned.end() && it->second.v[which]) return it->second.v[which];
     switch (which) {
-    case VLG_TUNE_CCL_TILE_ROWS: return kTileBHDefault;
+    case VLG_TUNE_CCL_TILE_ROWS: return default_tile_bh([&](int t) { return tile_count(H, W, t); });
     case VLG_TUNE_BATCH_GRID: return kBatchGridDefault;
     case VLG_TUNE_CCL_LANES: return 1;
     }
@@ -539,18 +539,16 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
     const bool stage_u8 = fmt == VLG_U8MASK && where == VLG_HOST;
 
     // one labelling tile height for the batch: forced, else the batch class's
-    // tuned value, else the largest image's
-    int64_t big = -1, pixels = 0;
-    int tbh = kTileBHDefault;
-    for (int i : idx) {
-        const int64_t px = (int64_t)imgs[i]->H * imgs[i]->W;
-        pixels += px;
-        if (px > big) {
-            big = px;
-            tbh = tuning_for(c, imgs[i]->H, imgs[i]->W).ccl_tbh;
-        }
-    }
-    tbh = batch_value(c, VLG_TUNE_CCL_TILE_ROWS, n, pixels, tbh);
+    // tuned value, else the tallest tile that leaves enough tiles over the
+    // whole batch
+    int64_t pixels = 0;
+    for (int i : idx) pixels += (int64_t)imgs[i]->H * imgs[i]->W;
+    const int tbh_untuned = default_tile_bh([&](int t) {
+        int64_t sum = 0;
+        for (int i : idx) sum += tile_count(imgs[i]->H, imgs[i]->W, t);
+        return sum;
+    });
+    const int tbh = batch_value(c, VLG_TUNE_CCL_TILE_ROWS, n, pixels, tbh_untuned);
     const int grid_cap = batch_value(c, VLG_TUNE_BATCH_GRID, n, pixels, kBatchGridDefault);
 
     // workspace: per-image layouts, then the descriptor block

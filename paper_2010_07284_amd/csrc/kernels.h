@@ -50,6 +50,20 @@ __host__ __device__ inline int64_t near_tasks(const Geo &g) { return near_tasks(
 constexpr int kTileBW = 64;
 constexpr int kTileBHDefault = 16;
 inline bool valid_tile_bh(int t) { return t == 8 || t == 16 || t == 32; }
+inline int64_t tile_count(int H, int W, int tbh) {
+    const int64_t bh = (H + 1) / 2, bw = (W + 1) / 2;
+    return ((bh + tbh - 1) / tbh) * ((bw + kTileBW - 1) / kTileBW);
+}
+// Untuned tile height for a labelling of `tiles(t)` tiles at height t: the
+// tallest that still leaves kMinTiles tiles (about four per compute unit;
+// taller tiles leave fewer borders to merge), else the shortest.
+constexpr int64_t kMinTiles = 1024;
+template <typename Tiles>
+inline int default_tile_bh(Tiles tiles) {
+    for (int t : {32, 16})
+        if (tiles(t) >= kMinTiles) return t;
+    return 8;
+}
 
 struct CclWork {
     int32_t *glab;       // [BH*BW] parent pointers (block ids, row-major)
