@@ -217,6 +217,16 @@ def bench_pixelwise(vlg, iters, side=46080):
                   "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"[bench] pixelwise {k:8s} {ms / n * 1e3:9.1f} us/launch  {gbs:7.1f} GB/s  "
             f"({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+    # the whole pass (atom, N, connective): a launch that streams past the
+    # last-level cache leaves the write-back of its output to the next one,
+    # so the per-kernel rates shift cost between neighbours; the sum does not
+    tb = sum(b for _, _, b in prof.values())
+    tms = sum(ms for _, ms, _ in prof.values())
+    gbs = tb / (tms / 1e3) / 1e9
+    res["pass"] = {"us_per_pass": round(tms / iters * 1e3, 1), "bytes_per_pass": round(tb / iters),
+                   "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"[bench] pixelwise pass     {tms / iters * 1e3:9.1f} us/pass    {gbs:7.1f} GB/s  "
+        f"({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
     # reference: a plain device-to-device copy of 4 GiB (what streaming
     # reaches on this device without any kernel of this library)
     a = torch.empty(1 << 30, dtype=torch.float32, device="cuda:0").fill_(1.0)

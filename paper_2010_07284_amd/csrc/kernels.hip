@@ -120,7 +120,19 @@ __device__ __forceinline__ MRef bref(const BImg &d, const BRef &r) {
 // kLogicUnroll words in flight.
 constexpr int kLogicUnroll = 4;
 
-template <bool HX, bool HY>
+// A launch whose operands add up to more than the last-level cache (256 MB
+// Infinity Cache) cannot leave them cached for the next launch, so it reads
+// them with the non-temporal hint, which keeps streaming reads from evicting
+// what is still reused; smaller launches read normally, since the next step
+// of a schedule usually reads their operands again.
+constexpr int64_t kStreamBytes = 256ll << 20;
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_hint(const VLG_GLOBAL T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool HX, bool HY, bool NT>
 __device__ __forceinline__ void logic_span(const Geo &g, const uint64_t *__restrict__ xg, uint64_t xinv,
                                            const uint64_t *__restrict__ yg, uint64_t yinv, int op, uint64_t inv_out,
                                            uint64_t *__restrict__ outg, int64_t i0, int64_t stride, int64_t iend) {
@@ -131,8 +143,8 @@ __device__ __forceinline__ void logic_span(const Geo &g, const uint64_t *__restr
 #pragma unroll
         for (int k = 0; k < kLogicUnroll; k++) {
             const int64_t j = min(i + k * stride, iend - 1);
-            a[k] = HX ? xp[j] ^ xinv : xinv;
-            b[k] = HY ? yp[j] ^ yinv : yinv;
+            a[k] = HX ? ld_hint<NT>(&xp[j]) ^ xinv : xinv;
+            b[k] = HY ? ld_hint<NT>(&yp[j]) ^ yinv : yinv;
         }
 #pragma unroll
         for (int k = 0; k < kLogicUnroll; k++) {
@@ -145,12 +157,13 @@ __device__ __forceinline__ void logic_span(const Geo &g, const uint64_t *__restr
 }
 
 // words i0, i0 + stride, ... below iend
+template <bool NT = false>
 __device__ __forceinline__ void logic_words(const Geo &g, const MRef &x, const MRef &y, int op, uint64_t inv_out,
                                             uint64_t *out, int64_t i0, int64_t stride, int64_t iend) {
-    if (x.p && y.p) logic_span<true, true>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
-    else if (x.p) logic_span<true, false>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
-    else if (y.p) logic_span<false, true>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
-    else logic_span<false, false>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
+    if (x.p && y.p) logic_span<true, true, NT>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
+    else if (x.p) logic_span<true, false, NT>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
+    else if (y.p) logic_span<false, true, NT>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
+    else logic_span<false, false, NT>(g, x.p, x.inv, y.p, y.inv, op, inv_out, out, i0, stride, iend);
 }
 
 // ------------------------------------------------------------------ near
@@ -303,7 +316,7 @@ __device__ __forceinline__ uint64_t atom_words(const float (&v)[64], float t) {
 // One wave task: words [64 t, 64 t + 64) of image channel img, for atoms
 // 0..n-1 with thresholds sthr (LDS) and comparisons cmp; outf(j) is atom j's
 // output mask.
-template <typename T, typename OutF>
+template <typename T, bool NT = false, typename OutF>
 __device__ __forceinline__ void atoms_task(const Geo &g, const T *__restrict__ img, int n, const uint8_t *cmp,
                                            const float *sthr, OutF outf, int64_t t) {
     const int lane = lane_id();
@@ -313,10 +326,10 @@ __device__ __forceinline__ void atoms_task(const Geo &g, const T *__restrict__ i
     float v[64];
     if (nw == 64) {
 #pragma unroll
-        for (int k = 0; k < 64; k++) v[k] = (float)src[k * 64];
+        for (int k = 0; k < 64; k++) v[k] = (float)ld_hint<NT>(&src[k * 64]);
     } else {
 #pragma unroll
-        for (int k = 0; k < 64; k++) v[k] = k < nw ? (float)src[k * 64] : 0.f;
+        for (int k = 0; k < 64; k++) v[k] = k < nw ? (float)ld_hint<NT>(&src[k * 64]) : 0.f;
     }
     const int64_t wi = w0 + lane;
     const uint64_t keep = (lane < nw && is_last_col(g, wi)) ? g.tail : ~0ull;
@@ -1017,9 +1030,10 @@ __device__ __forceinline__ void ccl_reseed_lane(const Geo &g, const MRef &sm, co
 
 // ------------------------------------------------------------------ single-image kernels
 
+template <bool NT>
 __global__ __launch_bounds__(kThreads) void k_logic(Geo g, MRef x, MRef y, int op, uint64_t inv_out,
                                                     uint64_t *__restrict__ out) {
-    logic_words(g, x, y, op, inv_out, out, (int64_t)blockIdx.x * kThreads + threadIdx.x,
+    logic_words<NT>(g, x, y, op, inv_out, out, (int64_t)blockIdx.x * kThreads + threadIdx.x,
                 (int64_t)gridDim.x * kThreads, g.nwords);
 }
 
@@ -1032,9 +1046,10 @@ __global__ __launch_bounds__(kThreads) void k_near(Geo g, MRef x, uint64_t inv_o
 
 // Up to kBatchMax independent Boolean steps (or near steps) in one launch:
 // blockIdx.y selects the step.
+template <bool NT>
 __global__ __launch_bounds__(kThreads) void k_logic_batch(Geo g, LogicBatch bt) {
     const LogicOp &o = bt.ops[blockIdx.y];
-    logic_words(g, o.x, o.y, o.op, o.inv_out, o.out, (int64_t)blockIdx.x * kThreads + threadIdx.x,
+    logic_words<NT>(g, o.x, o.y, o.op, o.inv_out, o.out, (int64_t)blockIdx.x * kThreads + threadIdx.x,
                 (int64_t)gridDim.x * kThreads, g.nwords);
 }
 
@@ -1045,7 +1060,7 @@ __global__ __launch_bounds__(kThreads) void k_near_batch(Geo g, NearBatch bt, in
         near_task(g, o.x, o.inv_out, o.z, o.zop, o.out, t, R);
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__ img, AtomLaunch a) {
     __shared__ float sthr[kMaxAtomsPerLaunch];
     if ((int)threadIdx.x < a.n)
@@ -1055,7 +1070,7 @@ __global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__
     const int64_t ntasks = (g.nwords + 63) / 64;
     auto outf = [&](int j) { return a.out[j]; };
     for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < ntasks; t += nwaves)
-        atoms_task(g, img, a.n, a.cmp, sthr, outf, t);
+        atoms_task<T, NT>(g, img, a.n, a.cmp, sthr, outf, t);
 }
 
 template <int TBH>
@@ -1328,7 +1343,11 @@ Geo make_geo(int H, int W) {
 
 hipError_t launch_logic(hipStream_t s, const Geo &g, MRef x, MRef y, int op, int inv_out, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    k_logic<<<grid_for(g.nwords, kThreads, 4096), kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
+    const int grid = grid_for(g.nwords, kThreads, 4096);
+    if (3 * g.nwords * 8 > kStreamBytes)
+        k_logic<true><<<grid, kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
+    else
+        k_logic<false><<<grid, kThreads, 0, s>>>(g, x, y, op, inv_out ? ~0ull : 0ull, out);
     return hipGetLastError();
 }
 
@@ -1346,7 +1365,10 @@ template <typename T>
 static hipError_t atoms_t(hipStream_t s, const Geo &g, const T *img, const AtomLaunch &a) {
     if (a.n < 1 || a.n > kMaxAtomsPerLaunch) return hipErrorInvalidValue;
     const int grid = grid_for((g.nwords + 63) / 64, kThreads / 64, 8192);
-    k_atoms<T><<<grid, kThreads, 0, s>>>(g, img, a);
+    if (g.nwords * 64 * (int64_t)sizeof(T) + a.n * g.nwords * 8 > kStreamBytes)
+        k_atoms<T, true><<<grid, kThreads, 0, s>>>(g, img, a);
+    else
+        k_atoms<T, false><<<grid, kThreads, 0, s>>>(g, img, a);
     return hipGetLastError();
 }
 
@@ -1407,7 +1429,8 @@ hipError_t launch_ccl_reseed(hipStream_t s, const Geo &g, MRef sm, const CclWork
 hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b) {
     if (g.nwords == 0 || b.n == 0) return hipSuccess;
     dim3 grid(grid_for(g.nwords, kThreads, 4096), b.n);
-    k_logic_batch<<<grid, kThreads, 0, s>>>(g, b);
+    if (3 * b.n * g.nwords * 8 > kStreamBytes) k_logic_batch<true><<<grid, kThreads, 0, s>>>(g, b);
+    else k_logic_batch<false><<<grid, kThreads, 0, s>>>(g, b);
     return hipGetLastError();
 }
 
