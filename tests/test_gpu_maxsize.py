@@ -1,7 +1,10 @@
 """The largest image the boundary accepts (H*W < 2^31): 46080 x 46080 pixels,
 three float32 channels generated in device memory.  Sampled rows are checked
 against the oracle on 3-row strips (N of row y depends on rows y-1..y+1
-only); whole-image properties are checked on the device."""
+only); whole-image properties are checked on the device.  At this size every
+atom and Boolean launch streams more than the last-level cache holds, so
+these are the launches that read with the non-temporal hint (the connectives
+both batched, in graph mode, and one per launch, in per-op mode)."""
 import numpy as np
 import pytest
 
@@ -19,6 +22,17 @@ let S = intensity(img, 2) >. 0.5
 output "atom" A
 output "near" near(A)
 output "reach" reach(S, M)
+output "andnot" M & !A
+output "or" A | S
+"""
+PIXELWISE = """
+let A = intensity(img, 0) >. 0.5
+let M = intensity(img, 1) >. 0.5
+let S = intensity(img, 2) >. 0.5
+output "atom" A
+output "near" near(A)
+output "andnot" M & !A
+output "or" A | S
 """
 
 
@@ -42,7 +56,13 @@ def test_max_size_sampled_rows_and_properties():
     im = vlg.load_image(ctx, img)
     f = vlg.compile_formula(ctx, SRC)
     vlg.set_mode(ctx, "graph")
-    atom, near, reach = vlg.check_all(ctx, f, im)
+    atom, near, reach, andnot, orr = vlg.check_all(ctx, f, im)
+    vlg.sync(ctx)
+    torch.cuda.synchronize()
+    # the pixel-wise outputs once more, one launch per operator
+    vlg.set_mode(ctx, "perop")
+    fp = vlg.compile_formula(ctx, PIXELWISE)
+    per_op = vlg.check_all(ctx, fp, im)
     vlg.sync(ctx)
     torch.cuda.synchronize()
 
@@ -56,11 +76,13 @@ def test_max_size_sampled_rows_and_properties():
     rows = sorted({0, 1, SIDE // 2, SIDE - 2, SIDE - 1, *rng.integers(2, SIDE - 2, 8).tolist()})
     for r in rows:
         lo, hi = max(0, r - 1), min(SIDE, r + 2)
-        strip = img[0:1, lo:hi].cpu().numpy()
-        want = oracle.run('let A = intensity(img, 0) >. 0.5\noutput "atom" A\noutput "near" near(A)\n', strip)
+        strip = img[:, lo:hi].cpu().numpy()
+        want = oracle.run(PIXELWISE, strip)
         k = r - lo
-        got_atom = vlg.unpack(atom[r:r + 1], 1, SIDE)
-        got_near = vlg.unpack(near[r:r + 1], 1, SIDE)
-        assert_same("", None, [got_atom, got_near], want=[want[0][k:k + 1], want[1][k:k + 1]], tag=f"row {r}")
-    del img, im, atom, near, reach
+        want = [w[k:k + 1] for w in want]
+        got = [vlg.unpack(o[r:r + 1], 1, SIDE) for o in (atom, near, andnot, orr)]
+        assert_same("", None, got, want=want, tag=f"row {r}, graph")
+        got = [vlg.unpack(o[r:r + 1], 1, SIDE) for o in per_op]
+        assert_same("", None, got, want=want, tag=f"row {r}, per-op")
+    del img, im, atom, near, reach, andnot, orr, per_op
     torch.cuda.empty_cache()
