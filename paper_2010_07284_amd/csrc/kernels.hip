@@ -1240,7 +1240,7 @@ __global__ __launch_bounds__(kThreads) void kb_near(BatchArgs a, BNear ops) {
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
     __shared__ float sthr[kMaxAtomsPerLaunch];
     VLG_BATCH_LOOP(a) {
@@ -1254,7 +1254,7 @@ __global__ __launch_bounds__(kThreads) void kb_atoms(BatchArgs a, BAtoms op) {
         const T *img = (const T *)(d.img + (int64_t)op.chan * d.chan_bytes);
         const int64_t t = (u_ - a.prefix[ii]) * (kThreads / 64) + (threadIdx.x >> 6);
         auto outf = [&](int j) { return bptr(d, op.out[j]); };
-        if (t * 64 < d.g.nwords) atoms_task(d.g, img, op.n, op.cmp, sthr, outf, t);
+        if (t * 64 < d.g.nwords) atoms_task<T, NT>(d.g, img, op.n, op.cmp, sthr, outf, t);
     }
 }
 
@@ -1498,8 +1498,16 @@ static int persistent_grid(const BatchArgs &a, int64_t total) {
 hipError_t launch_b_atoms(hipStream_t s, const BatchArgs &a, int64_t total, const BAtoms &op) {
     if (total == 0) return hipSuccess;
     if (op.n < 1 || op.n > kMaxAtomsPerLaunch) return hipErrorInvalidValue;
-    if (a.dtype == 1) kb_atoms<uint8_t><<<persistent_grid(a, total), kThreads, 0, s>>>(a, op);
-    else kb_atoms<float><<<persistent_grid(a, total), kThreads, 0, s>>>(a, op);
+    // a unit is 256 words: 16384 channel elements in, 256 words out per atom
+    const int64_t bytes = total * (16384 * (a.dtype == 1 ? 1 : 4) + op.n * 256 * 8);
+    const int grid = persistent_grid(a, total);
+    if (a.dtype == 1) {
+        if (bytes > kStreamBytes) kb_atoms<uint8_t, true><<<grid, kThreads, 0, s>>>(a, op);
+        else kb_atoms<uint8_t, false><<<grid, kThreads, 0, s>>>(a, op);
+    } else {
+        if (bytes > kStreamBytes) kb_atoms<float, true><<<grid, kThreads, 0, s>>>(a, op);
+        else kb_atoms<float, false><<<grid, kThreads, 0, s>>>(a, op);
+    }
     return hipGetLastError();
 }
 
