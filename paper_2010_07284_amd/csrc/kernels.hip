@@ -1617,21 +1617,21 @@ template <> struct Vec4<uint8_t> { typedef uint8_t type __attribute__((ext_vecto
 // of them do), then every selection's histogram is added into its state.
 // The streaming part of a histogram pass over elements [i0, i1): MG is the
 // number of groups the group test has to try (one in every first pass).
-template <typename T, int MG>
+template <typename T, int MG, bool NT>
 __device__ __forceinline__ void pct_hist_stream(const Geo &g, const T *__restrict__ img, int m, const uint32_t *pre,
                                                 const uint32_t *msk, int shift, int bins, int64_t i0, int64_t i1,
                                                 int64_t stride, uint32_t (*h)[2048]) {
     const int64_t pitch = (int64_t)g.wpr * 64;
     const uint32_t dmask = (uint32_t)(bins - 1);
     using V = typename Vec4<T>::type;
-    constexpr int U = 4;  // chunks per iteration: U vector loads in flight per thread
+    constexpr int U = 8;  // chunks per iteration: U vector loads in flight per thread
     for (int64_t c = i0; c < i1; c += U * stride) {
         V v[U];
         int64_t idx[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             idx[u] = c + u * stride + threadIdx.x * 4;
-            v[u] = *(const VLG_GLOBAL V *)(glb(img) + (idx[u] < i1 ? idx[u] : i0));
+            v[u] = ld_hint<NT>((const VLG_GLOBAL V *)(glb(img) + (idx[u] < i1 ? idx[u] : i0)));
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -1670,7 +1670,7 @@ __device__ __forceinline__ void pct_hist_stream(const Geo &g, const T *__restric
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState *const *st, int n, int shift,
                                int bins, int64_t i0, int64_t i1, int64_t stride, uint32_t (*h)[2048]) {
     __shared__ uint32_t gpre[kMaxPctSel], gmask[kMaxPctSel];
@@ -1705,9 +1705,9 @@ __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState
         for (int i = threadIdx.x; i < bins; i += kThreads) h[q][i] = 0;
     __syncthreads();
     if (m == 1)
-        pct_hist_stream<T, 1>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
+        pct_hist_stream<T, 1, NT>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
     else
-        pct_hist_stream<T, kMaxPctSel>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
+        pct_hist_stream<T, kMaxPctSel, NT>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
     __syncthreads();
     for (int j = 0; j < n; j++)
         for (int i = threadIdx.x; i < bins; i += kThreads) {
@@ -1749,14 +1749,14 @@ __device__ __forceinline__ PctState *sstate(void *states, int slot) {
 
 __global__ void k_pct_init(PctSel sel, void *states) { pct_init_wg(sstate(states, sel.slot[blockIdx.x]), sel.k[blockIdx.x]); }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restrict__ img, PctSel sel, void *states,
                                                        int shift, int bins) {
     __shared__ uint32_t h[kMaxPctSel][2048];
     PctState *st[kMaxPctSel];
     for (int j = 0; j < sel.n; j++) st[j] = sstate(states, sel.slot[j]);
     const int64_t n = (int64_t)g.H * g.wpr * 64;
-    pct_hist_range(g, img, st, sel.n, shift, bins, (int64_t)blockIdx.x * (kThreads * 4), n,
+    pct_hist_range<T, NT>(g, img, st, sel.n, shift, bins, (int64_t)blockIdx.x * (kThreads * 4), n,
                    (int64_t)gridDim.x * (kThreads * 4), h);
 }
 
@@ -1783,7 +1783,7 @@ __global__ void kb_pct_init(BatchArgs a, PctSel sel) {
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, PctSel sel, int shift, int bins) {
     __shared__ uint32_t h[kMaxPctSel][2048];
     UnitRange ur(a.prefix, a.n);
@@ -1795,7 +1795,7 @@ __global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, P
         const int64_t i0 = (u - a.prefix[ii]) * kPctUnit;
         const int64_t n = (int64_t)d.g.H * d.g.wpr * 64;
         const int64_t i1 = i0 + kPctUnit < n ? i0 + kPctUnit : n;
-        pct_hist_range(d.g, (const T *)(d.img + (int64_t)chan * d.chan_bytes), st, sel.n, shift, bins, i0, i1,
+        pct_hist_range<T, NT>(d.g, (const T *)(d.img + (int64_t)chan * d.chan_bytes), st, sel.n, shift, bins, i0, i1,
                        kThreads * 4, h);
     }
 }
@@ -1822,13 +1822,17 @@ hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int 
     if (n == 0) return hipGetLastError();
     const int grid = grid_for(n, kThreads * 64, 2048);
     if (dtype == 1) {
-        k_pct_hist<uint8_t><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
+        if (n > kStreamBytes) k_pct_hist<uint8_t, true><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
+        else k_pct_hist<uint8_t, false><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
         k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, 0, 256, 1, 1, results);
         return hipGetLastError();
     }
     const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
     for (int p = 0; p < 3; p++) {
-        k_pct_hist<float><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, shifts[p], bins[p]);
+        if (4 * n > kStreamBytes)
+            k_pct_hist<float, true><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, shifts[p], bins[p]);
+        else
+            k_pct_hist<float, false><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, shifts[p], bins[p]);
         k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, shifts[p], bins[p], p == 2, 0, results);
     }
     return hipGetLastError();
@@ -1841,14 +1845,18 @@ hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t tota
     const int g1 = persistent_grid(one, total_one), gh = persistent_grid(hist, total_hist);
     kb_pct_init<<<g1, kThreads, 0, s>>>(one, sel);
     dim3 gs(g1, sel.n);
+    // a histogram unit is kPctUnit channel elements
+    const bool nt = total_hist * kPctUnit * (hist.dtype == 1 ? 1 : 4) > kStreamBytes;
     if (hist.dtype == 1) {
-        kb_pct_hist<uint8_t><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
+        if (nt) kb_pct_hist<uint8_t, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
+        else kb_pct_hist<uint8_t, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
         kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, 0, 256, 1, 1);
         return hipGetLastError();
     }
     const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
     for (int p = 0; p < 3; p++) {
-        kb_pct_hist<float><<<gh, kThreads, 0, s>>>(hist, chan, sel, shifts[p], bins[p]);
+        if (nt) kb_pct_hist<float, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, shifts[p], bins[p]);
+        else kb_pct_hist<float, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, shifts[p], bins[p]);
         kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, shifts[p], bins[p], p == 2, 0);
     }
     return hipGetLastError();
