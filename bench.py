@@ -82,27 +82,68 @@ def time_mode(vlg, lib, ctx, f, im, arr, mode, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def bench_chain(vlg, lib, steps):
+def load_digests():
+    """Expected-mask digests of the full-size workloads, written by
+    tests/golden/make_digests.py from the CPU oracle."""
+    with open(os.path.join(ROOT, "tests", "golden", "digests.json")) as fh:
+        return json.load(fh)["cases"]
+
+
+def packed_digest(t):
+    return hashlib.sha256(t.cpu().numpy().astype("<i8").tobytes()).hexdigest()
+
+
+def check_digests(key, outs, digests, tag):
+    want = digests[key]["outputs"]
+    bad = [k for k, (o, w) in enumerate(zip(outs, want)) if packed_digest(o) != w]
+    if len(outs) != len(want) or bad:
+        raise SystemExit(f"[bench] PARITY FAILURE: {key} {tag}: outputs {bad} differ from the oracle")
+
+
+def bench_chain(vlg, lib, steps, check_oracle):
     """Sequential large formula: 1024x1024 uint8 random mask (density 0.5),
     10,000 rotating near/and/not elements plus 500 reach elements; per-op
-    launches against the fused schedule and its hipGraph."""
+    launches against the fused schedule and its hipGraph.  Every output of
+    every executor is first compared with the oracle's digests; compile time
+    (parse, hash-consing, both schedules) and graph build time (capture and
+    instantiation) are reported beside the evaluation time."""
     import torch
     from synth import formulas, images
     img = images.random_mask_image(3, 1024)
     src = formulas.chain_dag(3)
     ctx = vlg.create(0)
     im = vlg.load_image(ctx, torch.from_numpy(img).to("cuda:0"))
+    t0 = time.perf_counter()
     f = vlg.compile_formula(ctx, src)
-    info = vlg.formula_info(f)
+    info = vlg.formula_info(f)  # builds the per-op and fused schedules
+    compile_ms = (time.perf_counter() - t0) * 1e3
     nout = info["outputs"]
     outs = [torch.empty((1024, 16), dtype=torch.int64, device="cuda:0") for _ in range(nout)]
     arr = (ctypes.c_void_p * nout)(*[o.data_ptr() for o in outs])
+    digests = load_digests() if check_oracle else None
+    first_ms = {}
+    for m in ("perop", "fused", "graph"):
+        vlg.set_mode(ctx, m)
+        vlg.sync(ctx)
+        t0 = time.perf_counter()
+        rc = lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr, 0, 1)
+        if rc:
+            raise RuntimeError(lib.vlg_last_error().decode())
+        vlg.sync(ctx)
+        first_ms[m] = (time.perf_counter() - t0) * 1e3
+        if check_oracle:
+            check_digests("chain_1024", outs, digests, m)
+    if check_oracle:
+        log("[bench] chain_1024 parity: every output bit-exact (oracle digests) in perop, fused and graph")
     ms = {m: time_mode(vlg, lib, ctx, f, im, arr, m, steps, 1) for m in ("perop", "fused", "graph")}
     for m, t in ms.items():
         log(f"[bench] chain_1024 {m}: {t:.3f} ms/evaluation")
     return {"workload": f"chain_1024: 1024x1024 u8 random mask, {info['nodes']}-node chain "
                         f"({info['reach_nodes']} reach), {nout} outputs",
             "nodes": info["nodes"], "launches_perop": info["steps_perop"], "launches_fused": info["launches_fused"],
+            "parity": "oracle digests, every output, every executor" if check_oracle else None,
+            "compile_ms": round(compile_ms, 2),
+            "graph_build_ms": round(first_ms["graph"] - ms["graph"], 2),
             "perop_ms": round(ms["perop"], 3), "fused_ms": round(ms["fused"], 3), "graph_ms": round(ms["graph"], 3),
             "speedup_graph_vs_perop": round(ms["perop"] / ms["graph"], 3),
             "gpixel_node_per_s": round(1024 * 1024 * info["nodes"] / (ms["graph"] / 1e3) / 1e9, 3)}
@@ -293,38 +334,37 @@ def bench_paper_grow(vlg, lib, steps, check_oracle, side=7680):
                              "start of computation to file saved (OpenCL, uint16 MRI slice)"}
 
 
-def bench_serve(vlg, n_req, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
+def bench_serve(vlg, n_req, check_oracle, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
     """Serving loop: Poisson arrivals over a pool of resident images (sides
-    log-uniform in [256, 8192], float32) and formulas (20-2000 nodes, up to 50
-    reach-type); saturation throughput first, then p50/p99 latency (scheduled
-    arrival to outputs written) and throughput at fractions of it, each level
-    over n_req requests after n_warm warm-up requests."""
+    256 .. 8192, float32) and formulas (node counts log-uniform in [20, 2000]
+    with up to 50 reach-type nodes, plus one 2000-node formula with 50);
+    saturation throughput first, then p50/p99 latency (scheduled arrival to
+    outputs written) and throughput at fractions of it, each level over n_req
+    requests after n_warm warm-up requests.  One request per level writes to
+    buffers of its own and is compared with the oracle's digests."""
     import numpy as np
     import torch
     from synth import formulas, images
     rng = np.random.default_rng(seed)
     ctx = vlg.create(0)
-    sides = [256, 512, 1024, 2048, 4096, 8192]
-    imgs = []
-    for i, sd in enumerate(sides):
-        im = images.ellipse_maze_image(50 + i, sd, n_ellipses=60)[:1]
-        imgs.append(vlg.load_image(ctx, torch.from_numpy(np.ascontiguousarray(im)).to("cuda:0")))
-    fs = []
-    for k in range(6):
-        n = int(round(np.exp(rng.uniform(np.log(20), np.log(2000)))))
-        fs.append(vlg.compile_formula(ctx, formulas.random_dag(500 + k, n_nodes=n,
-                                                               n_reach=int(rng.integers(0, min(50, n // 10) + 1)))))
+    sides = list(formulas.SERVE_SIDES)
+    imgs = [vlg.load_image(ctx, torch.from_numpy(images.serve_image(i, sd)).to("cuda:0"))
+            for i, sd in enumerate(sides)]
+    fs = [vlg.compile_formula(ctx, src) for src, _, _ in formulas.serve_formulas(seed)]
     nouts = [vlg.formula_info(f)["outputs"] for f in fs]
     nodes = [vlg.formula_info(f)["nodes"] for f in fs]
+    digests = load_digests() if check_oracle else None
     ring = 8
     bufs = {}
+
+    def fresh(i, k):
+        C, H, W = imgs[i].shape
+        return [torch.empty((H, (W + 63) // 64), dtype=torch.int64, device="cuda:0") for _ in range(nouts[k])]
 
     def outs_for(i, k, r):
         key = (i, k, r % ring)
         if key not in bufs:
-            C, H, W = imgs[i].shape
-            bufs[key] = [torch.empty((H, (W + 63) // 64), dtype=torch.int64, device="cuda:0")
-                         for _ in range(nouts[k])]
+            bufs[key] = fresh(i, k)
         return bufs[key]
 
     def work(i, k):  # pixel-node evaluations of one request
@@ -350,6 +390,8 @@ def bench_serve(vlg, n_req, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=
     for frac in fracs:
         rate = frac * sat
         arrive = np.cumsum(rng.exponential(1.0 / rate, total))
+        gate = n_warm + int(rng.integers(0, n_req))  # the request checked against the oracle
+        gate_outs = fresh(*reqs[gate])
         t_start = time.perf_counter()
         ids, late = [], []
         for r, (i, k) in enumerate(reqs):
@@ -357,7 +399,7 @@ def bench_serve(vlg, n_req, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=
             if d > 0:
                 time.sleep(d)
             late.append(max(0.0, -d) * 1e3)  # submitted after its scheduled arrival
-            ids.append(srv.submit(fs[k], imgs[i], outs_for(i, k, r)))
+            ids.append(srv.submit(fs[k], imgs[i], gate_outs if r == gate else outs_for(i, k, r)))
         lat = []
         t_first = None
         for r, rid in enumerate(ids):
@@ -366,11 +408,15 @@ def bench_serve(vlg, n_req, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=
                 t_first = t_start + arrive[r]
             lat.append(late[r] + q + rr)
         wall = time.perf_counter() - t_first
+        i, k = reqs[gate]
+        if check_oracle:
+            check_digests(f"serve_f{k}_s{sides[i]}", gate_outs, digests, f"serve request {gate}")
         lat = np.array(lat[n_warm:])
         px = sum(work(i, k) for i, k in reqs[n_warm:])
         lvl = {"offered_req_per_s": round(float(rate), 2), "achieved_req_per_s": round(float(n_req / wall), 2),
                "gpixel_node_per_s": round(float(px / wall / 1e9), 2),
-               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "oracle_checked_request": {"formula": k, "side": sides[i], "nodes": nodes[k]} if check_oracle else None}
         log(f"[bench] serve at {frac:.0%}: {lvl}")
         out["levels"].append(lvl)
     st = srv.stats()
@@ -396,10 +442,14 @@ def main():
     ap.add_argument("--no-pixelwise", action="store_true", help="skip the streaming roofline of the pixel-wise kernels")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 7680^2 grow specification workload")
     ap.add_argument("--lanes", type=int, default=1,
-                    help="also time the headline with this many concurrent labelling lanes (2 or 4; experimental)")
+                    help="concurrent labelling lanes: switched off, only 1 is accepted")
     ap.add_argument("--hbm-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (scale for hardware byte counters)")
     args = ap.parse_args()
+    if args.lanes != 1:
+        print("--lanes: concurrent labelling lanes are switched off (a host-side crash seen with four lanes is "
+              "not explained); only 1 is accepted", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the formula path has no multi-GPU mode (images or "
               "requests shard across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
@@ -530,7 +580,7 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.no_chain:
-        line["chain"] = bench_chain(vlg, lib, steps=3)
+        line["chain"] = bench_chain(vlg, lib, 3, not args.skip_oracle)
     if not args.no_paper:
         line["paper_grow"] = bench_paper_grow(vlg, lib, 10, not args.skip_oracle)
     if not args.no_pixelwise:
@@ -539,7 +589,7 @@ def main():
         line["batch"] = bench_batch(vlg, lib, 3, not args.skip_oracle, n=args.batch_images)
         line["batch_square"] = bench_batch(vlg, lib, 3, not args.skip_oracle, n=args.batch_images, square=True)
     if not args.no_serve:
-        line["serve"] = bench_serve(vlg, args.serve_requests)
+        line["serve"] = bench_serve(vlg, args.serve_requests, not args.skip_oracle)
     print(json.dumps(line), flush=True)
 
 

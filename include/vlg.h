@@ -43,7 +43,9 @@ extern "C" {
 #define VLG_ESHAPE (-3)  /* image shape/channel mismatch or size beyond limits */
 #define VLG_ENOMEM (-4)  /* device or host allocation failed */
 #define VLG_EHIP (-5)    /* a HIP runtime call failed */
-#define VLG_ENOCONV (-6) /* a bounded device loop hit its iteration cap */
+#define VLG_ENOCONV (-6) /* a labelling loop stopped at its iteration cap (see
+                            vlg_set_loop_cap); reported by the next call that
+                            synchronises the context's stream */
 
 /* ---- enums ---- */
 #define VLG_F32 0        /* image pixel types */
@@ -96,8 +98,22 @@ typedef struct vlg_formula_stats {
  * take ownership of a caller stream. */
 int vlg_create(vlg_ctx **out, int device, void *hip_stream);
 void vlg_destroy(vlg_ctx *ctx);
-/* Block until all work enqueued by this context has finished. */
+/* Block until all work enqueued by this context has finished.  Returns
+ * VLG_ENOCONV (and clears the condition) when a labelling loop of that work
+ * stopped at its iteration cap: the outputs of the work enqueued since the
+ * previous synchronisation are then not valid. */
 int vlg_sync(vlg_ctx *ctx);
+/* Iteration cap of every loop of the labelling kernels (union-find walks,
+ * hooks and their retries, the root walks of the flag pass), per walk.  The
+ * paper's labelling ends by a termination check after each iteration (Sect. 3,
+ * Connected components labelling); here every device loop is bounded instead,
+ * so that a labelling fault ends in an error code, never in a hang.  When a
+ * walk reaches the cap it stops, the kernel exits normally with every array
+ * still readable, and a flag is raised that the next synchronising call
+ * (vlg_sync, a call with host outputs, a server request) turns into
+ * VLG_ENOCONV.  cap >= 1; 0 restores the default (2^20, far above any walk of
+ * a correct labelling). */
+int vlg_set_loop_cap(vlg_ctx *ctx, int cap);
 /* Select the executor mode (VLG_MODE_*); see above. */
 int vlg_set_mode(vlg_ctx *ctx, int mode);
 
@@ -133,23 +149,35 @@ int vlg_formula_info(const vlg_formula *f, vlg_formula_stats *stats);
 const char *vlg_formula_output_name(const vlg_formula *f, int index);
 int vlg_formula_free(vlg_formula *f);
 
-/* Evaluate output `output_index` of f on img and write the mask to `out_mask`
+/* Model checking of one formula on one image (paper Sect. 2: the satisfaction
+ * relation of Eq. def:syntax, pixel by pixel; Sect. 3: one kernel per
+ * operator over whole images, with reachability through connected components;
+ * Sect. 4.2, Fig. specification: the saved result is the mask of the pixels
+ * that satisfy a formula).
+ * Evaluate output `output_index` of f on img and write the mask to `out_mask`
  * (caller-owned, format fmt, in host or device memory).  Only the DAG nodes
  * that output needs are evaluated.  Device outputs complete in the order of
  * the context's stream (work of other streams on the same buffers must be
- * ordered against it by the caller); host outputs are complete on return. */
+ * ordered against it by the caller); host outputs are complete on return.
+ * Errors: VLG_EINVAL (null handle, bad index, format or memory kind),
+ * VLG_ESHAPE (the formula reads a channel the image lacks), VLG_ENOMEM,
+ * VLG_EHIP; with host outputs also VLG_ENOCONV (see vlg_sync). */
 int vlg_check(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int output_index,
               void *out_mask, int fmt, int where);
 /* Evaluate every output of f on img in one pass (shared sub-expressions are
- * evaluated once).  outs[i] receives output i; a NULL entry skips it. */
+ * evaluated once, as the paper's memoised task DAG does, Sect. 3,
+ * Implementation details).  outs[i] receives output i; a NULL entry skips it.
+ * Same formats, completion rules and errors as vlg_check. */
 int vlg_check_all(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, void *const *outs,
                   int fmt, int where);
-/* Evaluate every output of f on each of n images (sizes may differ).
+/* Evaluate every output of f on each of n images (sizes may differ): the
+ * satisfaction relation of Sect. 2 per image, as vlg_check_all.
  * outs[i * n_outputs + k] receives output k of image i (NULL skips it).
  * In fused and graph mode the batch runs as one launch per schedule step for
  * all images of a pixel type (persistent kernels over per-image descriptors,
  * each image with its own workspace region); in per-op mode the images are
- * evaluated one after another.  Same completion rules as vlg_check_all. */
+ * evaluated one after another.  Same completion rules and errors as
+ * vlg_check_all. */
 int vlg_check_batch(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *const *imgs, int n,
                     void *const *outs, int fmt, int where);
 
@@ -201,10 +229,10 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
  *     shorter ones give more parallel bands.
  *   VLG_TUNE_BATCH_GRID: workgroups of a persistent batched launch: 1024,
  *     2048, 4096 or 8192 (default).
- *   VLG_TUNE_CCL_LANES: labelling lanes of the fused schedule: 1 (default),
- *     2 or 4.  With more than one, independent labellings of a scheduling
- *     round run concurrently on separate streams, each with its own
- *     labelling workspace (experimental: never chosen by the autotuner). */
+ *   VLG_TUNE_CCL_LANES: labelling lanes of the fused schedule.  Only 1 is
+ *     accepted: concurrent lanes (2 or 4, independent labellings on separate
+ *     streams) are switched off while a host-side crash seen with four lanes
+ *     is unexplained; other values return VLG_EINVAL. */
 #define VLG_TUNE_CCL_TILE_ROWS 0
 #define VLG_TUNE_NEAR_ROWS 1
 #define VLG_TUNE_BATCH_GRID 2

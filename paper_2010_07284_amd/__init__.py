@@ -70,7 +70,14 @@ def create(device=0, stream=None):
 
 
 def sync(ctx):
+    """vlg_sync: raises VlgError (code -6, VLG_ENOCONV) when a labelling loop
+    of the work since the last synchronisation stopped at its iteration cap."""
     _lib.call("vlg_sync", ctx.handle)
+
+
+def set_loop_cap(ctx, cap):
+    """vlg_set_loop_cap: iteration cap of the labelling loops (0 = default)."""
+    _lib.call("vlg_set_loop_cap", ctx.handle, int(cap))
 
 
 class _Ordered:
@@ -334,7 +341,7 @@ def pack(mask):
     return np.packbits(padded, axis=1, bitorder="little").view("<i8").reshape(H, wpr).copy()
 
 
-__all__ = ["create", "sync", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
+__all__ = ["create", "sync", "set_loop_cap", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
            "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
            "tune_load", "autotune_batch", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

@@ -7,7 +7,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvlg.so")
 
 # every symbol declared in include/vlg.h
 EXPORTS = [
-    "vlg_create", "vlg_destroy", "vlg_sync", "vlg_set_mode", "vlg_load_image", "vlg_image_free",
+    "vlg_create", "vlg_destroy", "vlg_sync", "vlg_set_loop_cap", "vlg_set_mode", "vlg_load_image", "vlg_image_free",
     "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name",
     "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels",
     "vlg_ccl_read_counters", "vlg_profile", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune", "vlg_autotune_batch",
@@ -69,6 +69,7 @@ def lib():
             "vlg_create": ([P, I, P], I),
             "vlg_destroy": ([P], None),
             "vlg_sync": ([P], I),
+            "vlg_set_loop_cap": ([P, I], I),
             "vlg_set_mode": ([P, I], I),
             "vlg_load_image": ([P, P, I, I, I, I, I64, I, P], I),
             "vlg_image_free": ([P], I),

@@ -80,11 +80,42 @@ struct vlg_image {
     int device;
     int dtype, C, H, W;
     int64_t pitch;  // elements per row (wpr * 64)
-    void *dev;
+    void *dev;      // from the device's stream-ordered pool (hipMallocAsync)
     size_t bytes;
     size_t esize() const { return dtype == VLG_U8 ? 1 : 4; }
     const char *chan(int c) const { return (const char *)dev + (size_t)c * H * pitch * esize(); }
+    // the last enqueued use of the image on each stream that read it: its
+    // release waits for these events instead of for the whole device
+    mutable std::mutex mu;
+    mutable std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+    int note_use(hipStream_t s) const {
+        std::lock_guard<std::mutex> lk(mu);
+        hipEvent_t ev = nullptr;
+        for (auto &u : uses)
+            if (u.first == s) ev = u.second;
+        if (!ev) {
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return VLG_EHIP;
+            uses.emplace_back(s, ev);
+        }
+        return hipEventRecord(ev, s) == hipSuccess ? VLG_OK : VLG_EHIP;
+    }
 };
+
+namespace {
+// One stream per device (created on first use, kept until the process ends)
+// on which images are released once every stream that read them is done.
+std::mutex g_release_mu;
+std::map<int, hipStream_t> g_release_stream;
+hipStream_t release_stream(int device) {
+    std::lock_guard<std::mutex> lk(g_release_mu);
+    auto it = g_release_stream.find(device);
+    if (it != g_release_stream.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    g_release_stream[device] = s;
+    return s;
+}
+}  // namespace
 
 struct GraphKey {
     std::vector<uintptr_t> v;
@@ -100,7 +131,11 @@ bool tunable_valid(int which, int v) {
     case VLG_TUNE_CCL_TILE_ROWS: return valid_tile_bh(v);
     case VLG_TUNE_NEAR_ROWS: return valid_near_rows(v);
     case VLG_TUNE_BATCH_GRID: return valid_batch_grid(v);
-    case VLG_TUNE_CCL_LANES: return v == 1 || v == 2 || v == 4;
+    // Concurrent labelling lanes are switched off: with four lanes a
+    // vlg_check_all call ended twice in a host-side segmentation fault whose
+    // cause is not found, so only the sequential schedule (one lane) is
+    // accepted until it is.
+    case VLG_TUNE_CCL_LANES: return v == 1;
     }
     return false;
 }
@@ -119,14 +154,21 @@ struct vlg_ctx {
     bool own_stream = false;
     // streams of labelling lanes 1.. (lane 0 runs on `stream`) and the events
     // that fork them from and join them back into `stream`
+    // (created on first use)
     hipStream_t lane_stream[kMaxCclLanes - 1] = {};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kMaxCclLanes - 1] = {};
     int mode = VLG_MODE_GRAPH;
+    int loop_cap = kLoopCapDefault;  // iterations per labelling walk (vlg_set_loop_cap)
     void *ws = nullptr;
     size_t ws_size = 0;
     bool ws_external = false;       // workspace lent by a server slot
-    unsigned long long *counters = nullptr;  // device [2]
+    // device [4]: merge unions, merge retries, then the 32-bit give-up flag of
+    // the labelling loops (status) and padding
+    unsigned long long *counters = nullptr;
+    unsigned int *status_host = nullptr;     // pinned staging of the flag
+    unsigned int *status() const { return (unsigned int *)(counters + 2); }
+    LoopGuard guard() const { return LoopGuard{status(), loop_cap}; }
     bool count_ccl = false;         // collect merge counters (VLG_CCL_COUNTERS=1)
     std::map<GraphKey, hipGraphExec_t> graphs;
     // pinned host staging of batch descriptors; `desc_done` marks the end of
@@ -146,6 +188,32 @@ struct vlg_ctx {
 };
 
 namespace {
+
+// Read and clear the give-up flag of the labelling loops; waits for the
+// context's stream.  VLG_ENOCONV when a loop stopped at its iteration cap in
+// work enqueued since the last check.
+int check_status(vlg_ctx *c) {
+    HIP_TRY(hipMemcpyAsync(c->status_host, c->status(), sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (*c->status_host) {
+        *c->status_host = 0;
+        HIP_TRY(launch_fill_i64(c->stream, c->counters + 2, 1, 0));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return fail(VLG_ENOCONV, "a labelling loop stopped at its iteration cap (" + std::to_string(c->loop_cap) +
+                                     "): the results of the work since the last synchronisation are not valid");
+    }
+    return VLG_OK;
+}
+
+// Streams and events of labelling lanes 1.., created on first use.
+int ensure_lane_streams(vlg_ctx *c) {
+    for (int l = 0; l < kMaxCclLanes - 1; l++) {
+        if (!c->lane_stream[l]) HIP_TRY(hipStreamCreateWithFlags(&c->lane_stream[l], hipStreamNonBlocking));
+        if (!c->join_ev[l]) HIP_TRY(hipEventCreateWithFlags(&c->join_ev[l], hipEventDisableTiming));
+    }
+    if (!c->fork_ev) HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    return VLG_OK;
+}
 
 // Workspace layout of one evaluation.
 struct Layout {
@@ -290,10 +358,12 @@ using StepHook = void (*)(void *, size_t, bool);
 
 // Enqueue every step of P on the stream.  ext[k] is the packed device buffer
 // of external slot k.  hook (optional) runs before and after each step.
+// base_ (optional) is the workspace to use instead of the context's.
 int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &L,
-                 const std::vector<uint64_t *> &ext, StepHook hook = nullptr, void *hook_ctx = nullptr) {
+                 const std::vector<uint64_t *> &ext, StepHook hook = nullptr, void *hook_ctx = nullptr,
+                 char *base_ = nullptr) {
     const Geo g = make_geo(img->H, img->W);
-    char *base = (char *)c->ws;
+    char *base = base_ ? base_ : (char *)c->ws;
     auto slot_ptr = [&](int32_t s) -> uint64_t * {
         if (s == kNone) return nullptr;
         if (is_ext(s)) return ext[(size_t)ext_index(s)];
@@ -308,6 +378,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
     float *pct = (float *)(base + L.off_pct);
     CclWork w0;
     w0.counters = c->count_ccl ? c->counters : nullptr;
+    w0.guard = c->guard();
     w0.tbh = tuning_for(c, img->H, img->W).ccl_tbh;
     const int near_rows = tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W);
     const int64_t npix = (int64_t)img->H * img->W;
@@ -336,6 +407,8 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
             for (size_t sj = si; sj < P.steps.size() && P.steps[sj].span == s.span && P.steps[sj].lane >= 0; sj++)
                 open_lanes |= 1u << P.steps[sj].lane;
             if (open_lanes > 1) {
+                const int rl = ensure_lane_streams(c);
+                if (rl != VLG_OK) return rl;
                 HIP_TRY(hipEventRecord(c->fork_ev, c->stream));
                 for (int l = 1; l < kMaxCclLanes; l++)
                     if (open_lanes >> l & 1) HIP_TRY(hipStreamWaitEvent(c->lane_stream[l - 1], c->fork_ev, 0));
@@ -480,7 +553,7 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
         key.v = {(uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)img->dev, (uintptr_t)img->H, (uintptr_t)img->W,
                  (uintptr_t)img->dtype, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)c->ws,
                  (uintptr_t)tuning_for(c, img->H, img->W).ccl_tbh,
-                 (uintptr_t)tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W)};
+                 (uintptr_t)tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W), (uintptr_t)c->loop_cap};
         for (size_t k = 0; k < which.size(); k++) key.v.push_back((uintptr_t)outs[k]);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -505,6 +578,7 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
         rc = enqueue_all();
         if (rc != VLG_OK) return rc;
     }
+    if (img->note_use(c->stream) != VLG_OK) return fail(VLG_EHIP, "event record failed");
 
     if (where == VLG_HOST) {
         for (size_t k = 0; k < which.size(); k++) {
@@ -515,7 +589,7 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
                 HIP_TRY(hipMemcpyAsync(outs[k], base + L.off_u8 + k * u8_bytes, (size_t)g.H * g.W,
                                        hipMemcpyDeviceToHost, c->stream));
         }
-        HIP_TRY(hipStreamSynchronize(c->stream));
+        return check_status(c);
     }
     return VLG_OK;
 }
@@ -632,6 +706,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
         a.grid_cap = grid_cap;
         a.imgs = (const BImg *)(base + d_imgs);
         a.prefix = (const int64_t *)(base + d_prefix) + (size_t)kind * (n + 1);
+        a.guard = c->guard();
         return a;
     };
     auto units = [&](int kind) { return hp[(size_t)kind * (n + 1) + n]; };
@@ -747,7 +822,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
     if (c->mode == VLG_MODE_GRAPH) {
         GraphKey key;
         key.v = {(uintptr_t)0xBA7C, (uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)c->ws, (uintptr_t)tbh,
-                 (uintptr_t)grid_cap, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)n};
+                 (uintptr_t)grid_cap, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)n, (uintptr_t)c->loop_cap};
         for (int k = 0; k < n; k++) {
             const vlg_image *im = imgs[idx[k]];
             key.v.insert(key.v.end(), {(uintptr_t)im->dev, (uintptr_t)im->H, (uintptr_t)im->W,
@@ -777,6 +852,8 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
         rc = enqueue_steps();
         if (rc != VLG_OK) return rc;
     }
+    for (int k = 0; k < n; k++)
+        if (imgs[idx[k]]->note_use(c->stream) != VLG_OK) return fail(VLG_EHIP, "event record failed");
 
     if (where == VLG_HOST) {
         for (int k = 0; k < n; k++)
@@ -791,7 +868,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                                            base + off[k] + lay[k].off_u8 + o * align256((size_t)geo[k].H * geo[k].W),
                                            (size_t)geo[k].H * geo[k].W, hipMemcpyDeviceToHost, c->stream));
             }
-        HIP_TRY(hipStreamSynchronize(c->stream));
+        return check_status(c);
     }
     return VLG_OK;
 }
@@ -818,7 +895,7 @@ int evaluate_all_on(vlg_ctx *c, vlg_formula *f, const vlg_image *img, void *cons
         o.push_back(outs[i]);
     }
     int rc = run(c, f, img, which, o, VLG_PACKED64, VLG_DEVICE);
-    if (rc == VLG_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(VLG_EHIP, "stream synchronize failed");
+    if (rc == VLG_OK) rc = check_status(c);
     return rc;
 }
 const char *last_error_text() { return g_err.c_str(); }
@@ -903,15 +980,12 @@ int vlg_create(vlg_ctx **out, int device, void *hip_stream) {
         HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
-    for (int l = 0; l < kMaxCclLanes - 1; l++) {
-        HIP_TRY(hipStreamCreateWithFlags(&c->lane_stream[l], hipStreamNonBlocking));
-        HIP_TRY(hipEventCreateWithFlags(&c->join_ev[l], hipEventDisableTiming));
-    }
-    HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
     const char *cc = std::getenv("VLG_CCL_COUNTERS");
     c->count_ccl = cc && cc[0] == '1';
-    HIP_TRY(hipMalloc(&c->counters, 2 * sizeof(unsigned long long)));
-    HIP_TRY(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), c->stream));
+    HIP_TRY(hipMalloc(&c->counters, 4 * sizeof(unsigned long long)));
+    HIP_TRY(hipHostMalloc((void **)&c->status_host, 256, hipHostMallocDefault));
+    *c->status_host = 0;
+    HIP_TRY(launch_fill_i64(c->stream, c->counters, 4, 0));
     HIP_TRY(hipStreamSynchronize(c->stream));
     *out = c.release();
     return VLG_OK;
@@ -924,6 +998,7 @@ void vlg_destroy(vlg_ctx *c) {
     c->drop_graphs();
     if (c->ws && !c->ws_external) (void)hipFree(c->ws);
     if (c->counters) (void)hipFree(c->counters);
+    if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->desc_host) (void)hipHostFree(c->desc_host);
     if (c->desc_done) (void)hipEventDestroy(c->desc_done);
     for (int l = 0; l < kMaxCclLanes - 1; l++) {
@@ -941,7 +1016,12 @@ void vlg_destroy(vlg_ctx *c) {
 int vlg_sync(vlg_ctx *c) {
     if (!c) return fail(VLG_EINVAL, "null context");
     DeviceGuard dg(c->device);
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    return check_status(c);
+}
+
+int vlg_set_loop_cap(vlg_ctx *c, int cap) {
+    if (!c || cap < 0) return fail(VLG_EINVAL, "bad loop cap");
+    c->loop_cap = cap == 0 ? kLoopCapDefault : cap;
     return VLG_OK;
 }
 
@@ -972,7 +1052,7 @@ int vlg_load_image(vlg_ctx *c, const void *data, int dtype, int channels, int he
     im->pitch = (int64_t)((width + 63) / 64) * 64;
     const size_t es = im->esize();
     im->bytes = std::max<size_t>(256, (size_t)channels * height * im->pitch * es);
-    if (hipMalloc(&im->dev, im->bytes) != hipSuccess) {
+    if (hipMallocAsync(&im->dev, im->bytes, c->stream) != hipSuccess) {
         (void)hipGetLastError();
         return fail(VLG_ENOMEM, "image allocation failed");
     }
@@ -987,6 +1067,8 @@ int vlg_load_image(vlg_ctx *c, const void *data, int dtype, int channels, int he
         }
     }
     if (where == VLG_HOST) HIP_TRY(hipStreamSynchronize(c->stream));
+    const int ru = im->note_use(c->stream);  // the upload is the first use
+    if (ru != VLG_OK) return fail(ru, "event record failed");
     *out = im.release();
     return VLG_OK;
 }
@@ -994,10 +1076,21 @@ int vlg_load_image(vlg_ctx *c, const void *data, int dtype, int channels, int he
 int vlg_image_free(vlg_image *img) {
     if (!img) return VLG_OK;
     DeviceGuard dg(img->device);
-    (void)hipDeviceSynchronize();
-    hipError_t e = hipFree(img->dev);
+    hipStream_t rel = release_stream(img->device);
+    hipError_t e = rel ? hipSuccess : hipErrorOutOfMemory;
+    {
+        std::lock_guard<std::mutex> lk(img->mu);
+        for (auto &u : img->uses) {
+            if (e == hipSuccess) e = hipStreamWaitEvent(rel, u.second, 0);
+            (void)hipEventDestroy(u.second);
+        }
+        img->uses.clear();
+    }
+    // stream-ordered release: after every enqueued use, without waiting for
+    // the rest of the device (other contexts and server slots keep running)
+    if (e == hipSuccess) e = hipFreeAsync(img->dev, rel);
     delete img;
-    if (e != hipSuccess) return fail(VLG_EHIP, hipGetErrorString(e));
+    if (e != hipSuccess) return fail(VLG_EHIP, std::string("image release: ") + hipGetErrorString(e));
     return VLG_OK;
 }
 
@@ -1150,6 +1243,7 @@ int vlg_ccl_labels(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, 
     int32_t *canon = (int32_t *)((char *)c->ws + align256(nb * 4) + align256(nb));
     w.counters = c->counters;
     w.tbh = tuning_for(c, height, width).ccl_tbh;
+    w.guard = c->guard();
     MRef b{mask_dev, 0ull}, none{nullptr, 0ull};
     HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
     HIP_TRY(launch_ccl_local(c->stream, g, b, none, none, w));
@@ -1231,6 +1325,9 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
 int vlg_set_tunable(vlg_ctx *c, int which, int value) {
     if (!c) return fail(VLG_EINVAL, "null context");
     if (which < 0 || which >= kNumTunables) return fail(VLG_EINVAL, "unknown tunable");
+    if (which == VLG_TUNE_CCL_LANES && value > 1)
+        return fail(VLG_EINVAL, "ccl_lanes: concurrent labelling lanes are switched off (a host-side crash seen "
+                                "with four lanes is not explained); only 1 is accepted");
     if (value != 0 && !tunable_valid(which, value))
         return fail(VLG_EINVAL, std::string("bad value for ") + kTunableNames[which]);
     c->forced.v[which] = value;

@@ -65,12 +65,24 @@ inline int default_tile_bh(Tiles tiles) {
     return 8;
 }
 
+// Every loop of the labelling kernels (union-find walks, hooks, retries) runs
+// at most `cap` iterations per walk.  A walk that reaches the cap stops, leaves
+// the arrays in a state every later pass can still read (all stored values are
+// valid block ids), and sets *status to a non-zero value; the host turns that
+// into VLG_ENOCONV.  A correct labelling never comes near the default cap.
+constexpr int kLoopCapDefault = 1 << 20;
+struct LoopGuard {
+    unsigned int *status;  // device word, set to 1 when a loop gives up
+    int cap;               // iterations per walk (>= 1)
+};
+
 struct CclWork {
     int32_t *glab;       // [BH*BW] parent pointers (block ids, row-major)
     uint8_t *gflag;      // [BH*BW] local roots: bit0 touches the tile border,
                          // bit 1+u meets the seeds of labelling user u
     unsigned long long *counters; // [2] merge unions, merge retries (may be null)
     int tbh = kTileBHDefault;     // block rows per labelling tile
+    LoopGuard guard{nullptr, kLoopCapDefault};
 };
 
 constexpr int kMaxAtomsPerLaunch = 32;
@@ -157,6 +169,7 @@ struct BatchArgs {
     int grid_cap;             // most workgroups of a persistent launch (host side)
     const BImg *imgs;
     const int64_t *prefix;    // [n+1] units of the launch's kind, prefix sums
+    LoopGuard guard;          // loop cap and give-up flag of the labelling kernels
 };
 
 struct BAtoms {

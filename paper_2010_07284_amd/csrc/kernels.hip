@@ -377,14 +377,16 @@ __device__ __forceinline__ int lane_prev(int v) {
 // root is hooked under the smaller with atomicMin, and if that root was
 // hooked meanwhile the returned parent is united in its place.  Halving
 // stores may race with other lanes' hooks; the hooking lane then unites the
-// old parent as well, so no connection is lost.
-__device__ __forceinline__ void lds_unite(int *L, int a, int b) {
-    while (a != b) {
+// old parent as well, so no connection is lost.  At most `cap` rounds:
+// returns false when the cap stops the walk (the union may be missing).
+__device__ __forceinline__ bool lds_unite(int *L, int a, int b, int cap) {
+    for (int it = 0; a != b; it++) {
+        if (it >= cap) return false;
         const int pa = lds_ld(&L[a]), pb = lds_ld(&L[b]);
         if (pa == a && pb == b) {
             const int hi = a > b ? a : b, lo = a > b ? b : a;
             const int old = atomicMin(&L[hi], lo);
-            if (old == hi) return;
+            if (old == hi) return true;
             a = old;
             b = lo;
             continue;
@@ -399,13 +401,16 @@ __device__ __forceinline__ void lds_unite(int *L, int a, int b) {
             b = gb;
         }
     }
+    return true;
 }
 
 // Root of x once all unions are done.  Path halving here goes through
 // atomicMin: the root is the smallest entry of its set, so a stale halving
-// store can never replace a root that its owner has already written.
-__device__ __forceinline__ int lds_root(int *L, int x) {
-    while (true) {
+// store can never replace a root that its owner has already written.  At
+// most `cap` rounds; when the cap stops the walk, ok is cleared and the
+// ancestor reached so far (a block of the same tile) is returned.
+__device__ __forceinline__ int lds_root(int *L, int x, int cap, bool &ok) {
+    for (int it = 0; it < cap; it++) {
         const int p = lds_ld(&L[x]);
         if (p == x) return x;
         const int gp = lds_ld(&L[p]);
@@ -413,6 +418,27 @@ __device__ __forceinline__ int lds_root(int *L, int x) {
         __hip_atomic_fetch_min(&L[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         x = gp;
     }
+    ok = false;
+    return x;
+}
+
+// Raise the give-up flag of a launch (one vector atomic per wave).
+// Called by every lane of the wave.
+__device__ __forceinline__ void guard_report(const LoopGuard &gd, bool ok) {
+    const uint64_t bad = __ballot(!ok);
+    if (bad && lane_id() == __builtin_ctzll(bad) && gd.status)
+        __hip_atomic_fetch_or(glb(gd.status), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Cross-lane handoff through LDS inside one wave: every lane's LDS writes
+// before this point are complete (and visible to the other lanes) before any
+// lane's LDS reads after it.  The workgroup-scope fences order the accesses
+// for the compiler and wait for the outstanding LDS operations; the wave
+// barrier keeps the lanes together.
+__device__ __forceinline__ void wave_lds_handoff() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // Global union-find for the cross-tile merge.  A root is hooked under the
@@ -429,11 +455,13 @@ __device__ __forceinline__ int lds_root(int *L, int x) {
 // parent, which is then united in turn.
 //
 // g_find2: the roots of a and b, walked in lockstep (path halving on both) so
-// that the loads of the two paths overlap.
-__device__ __forceinline__ void g_find2(VLG_GLOBAL int *L, int &a, int &b) {
+// that the loads of the two paths overlap.  `budget` counts the rounds left
+// to the caller's walk; returns false when it runs out.
+__device__ __forceinline__ bool g_find2(VLG_GLOBAL int *L, int &a, int &b, int &budget) {
     while (true) {
+        if (--budget < 0) return false;
         const int pa = L[a], pb = L[b];
-        if (pa == a && pb == b) return;
+        if (pa == a && pb == b) return true;
         const int ga = L[pa], gb = L[pb];
         if (pa != a) {
             if (ga == pa) {
@@ -459,11 +487,16 @@ __device__ __forceinline__ uint32_t uf_prio(int x) {
     return h ^ (h >> 16);                     // invertible xor-shift
 }
 
-__device__ int g_unite(VLG_GLOBAL int *L, int a, int b) {
-    int tries = 0;
+// Unite a and b; returns the number of hook attempts, and clears ok when the
+// walk used up `cap` rounds (finds and hooks together) before it finished.
+__device__ int g_unite(VLG_GLOBAL int *L, int a, int b, int cap, bool &ok) {
+    int tries = 0, budget = cap;
     while (true) {
         tries++;
-        g_find2(L, a, b);
+        if (!g_find2(L, a, b, budget)) {
+            ok = false;
+            return tries;
+        }
         if (a == b) return tries;
         if (uf_prio(a) < uf_prio(b)) {
             const int t = a;
@@ -511,7 +544,7 @@ constexpr int ccl_local_threads() {
 // bits 2..7 serve later users, see ccl_reseed).
 template <int TBH>
 __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const MRef &z, int tx, int ty,
-                               int32_t *__restrict__ glab_, uint8_t *__restrict__ gflag_) {
+                               int32_t *__restrict__ glab_, uint8_t *__restrict__ gflag_, const LoopGuard &gd) {
     VLG_GLOBAL int32_t *glab = glb(glab_);
     VLG_GLOBAL uint8_t *gflag = glb(gflag_);
     constexpr int NT = ccl_local_threads<TBH>();
@@ -634,6 +667,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     // one after another.  Pairs beyond the queue's capacity are united by
     // their own lane at once.
     int npairs = 0;  // wave-uniform
+    bool ok = true;  // no walk of this lane hit the loop cap
 #pragma unroll
     for (int j = 0; j < RPW; j++) {
         const int lby = wave + NWAVES * j, up = (lby - 1) * TBW + lane;
@@ -665,15 +699,15 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
                 if (q < kPairQueue)
                     spair[wave][q] = me | ((ub + cs[k]) << 16);
                 else
-                    lds_unite(L, me, ub + cs[k]);
+                    ok &= lds_unite(L, me, ub + cs[k], gd.cap);
             }
             npairs += __popcll(has);
         }
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_handoff();  // the queue entries of every lane, then the reads
     for (int q = lane; q < (npairs < kPairQueue ? npairs : kPairQueue); q += 64) {
         const int pr = spair[wave][q];
-        lds_unite(L, pr & 0xFFFF, pr >> 16);
+        ok &= lds_unite(L, pr & 0xFFFF, pr >> 16, gd.cap);
     }
     __syncthreads();
 
@@ -682,7 +716,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
 #pragma unroll
     for (int j = 0; j < RPW; j++) {
         const int i = (wave + NWAVES * j) * TBW + lane;
-        if (st_bits(st[j]) && st_run(st[j]) == lane) L[i] = lds_root(L, i);
+        if (st_bits(st[j]) && st_run(st[j]) == lane) L[i] = lds_root(L, i, gd.cap, ok);
     }
     __syncthreads();
 
@@ -719,6 +753,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
             gflag[id] = 0;
         }
     }
+    guard_report(gd, ok);
     __syncthreads();  // the next tile of a persistent workgroup reuses the LDS
 }
 
@@ -740,7 +775,7 @@ constexpr int merge_window_words() {
 
 template <int TBH>
 __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, int32_t *glab_, uint64_t *win,
-                               int &unions, int &tries) {
+                               int &unions, int &tries, const LoopGuard &gd) {
     constexpr int TBW = 64, WN = merge_window_words<TBH>(), NL = (WN + 63) / 64;
     VLG_GLOBAL int32_t *glab = glb(glab_);
     const int lane = lane_id();
@@ -762,16 +797,17 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
             const int i = lane + 64 * k, w = w0 + (i & 3);
             if (i < WN) win[i] = idx[k] >= 0 ? ((v[k] ^ b.inv) & (w == g.wpr - 1 ? g.tail : ~0ull)) : 0ull;
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_handoff();  // every lane's window words, then the reads
     }
     // bits of block (by, bx), by in [by0-2, by0+TBH), bx in [bx0-2, bx0+64]
     auto bits = [&](int by, int bx) -> uint32_t {
         const int r = 2 * by - r0, p = 2 * bx - 64 * w0, q = p >> 6, sh = p & 63;
         return (uint32_t)((win[r * 4 + q] >> sh) & 3) | ((uint32_t)((win[(r + 1) * 4 + q] >> sh) & 3) << 2);
     };
+    bool ok = true;  // no walk of this lane hit the loop cap
     auto link = [&](int id, int nid) {
         unions++;
-        tries += g_unite(glab, id, nid);
+        tries += g_unite(glab, id, nid, gd.cap, ok);
     };
 
     // top row: contacts with the row above (other tile): UL, U, UR
@@ -849,16 +885,23 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
             }
         }
     }
-    __builtin_amdgcn_wave_barrier();  // the window is rewritten by the wave's next tile
+    guard_report(gd, ok);
+    wave_lds_handoff();  // the window is rewritten by the wave's next tile
 }
 
 // Point a border-touching tile-local root i (flag byte f) at its final root
 // and carry its seed flag there.  Other local roots are final roots already.
 // A walker writes only its own entry, so concurrent walkers never undo each
-// other.
-__device__ __forceinline__ void ccl_flag_walk(VLG_GLOBAL int32_t *glab, VLG_GLOBAL uint8_t *gflag, int i, uint32_t f) {
+// other.  At most `cap` steps; a walk the cap stops writes nothing and clears
+// ok.
+__device__ __forceinline__ void ccl_flag_walk(VLG_GLOBAL int32_t *glab, VLG_GLOBAL uint8_t *gflag, int i, uint32_t f,
+                                              int cap, bool &ok) {
     int x = i;
-    while (true) {
+    for (int it = 0;; it++) {
+        if (it >= cap) {
+            ok = false;
+            return;
+        }
         const int p = glab[x];
         if (p == x) break;
         x = p;
@@ -873,7 +916,8 @@ __device__ __forceinline__ void ccl_flag_walk(VLG_GLOBAL int32_t *glab, VLG_GLOB
 // of their flag bytes, then a walk for each border-touching local root among
 // them (bit0 of its byte).  A byte that another walker rewrites after the
 // load is either a final root (the walk ends at once) or unchanged.
-__device__ __forceinline__ void ccl_flag16(int32_t *glab_, uint8_t *gflag_, int64_t nb, int64_t i0) {
+__device__ __forceinline__ void ccl_flag16(int32_t *glab_, uint8_t *gflag_, int64_t nb, int64_t i0, int cap,
+                                           bool &ok) {
     VLG_GLOBAL int32_t *glab = glb(glab_);
     VLG_GLOBAL uint8_t *gflag = glb(gflag_);
     uint64_t lo = 0, hi = 0;
@@ -906,7 +950,7 @@ __device__ __forceinline__ void ccl_flag16(int32_t *glab_, uint8_t *gflag_, int6
             k = 8 + (bit >> 3);
             f = (uint32_t)(hi >> bit) & 0xFF;
         }
-        ccl_flag_walk(glab, gflag, (int)(i0 + k), f);
+        ccl_flag_walk(glab, gflag, (int)(i0 + k), f, cap, ok);
     }
 }
 
@@ -990,7 +1034,7 @@ __device__ __forceinline__ void ccl_gather_tasks(const Geo &g, const MRef &b, co
             if (r[k][j] >= 0 && ((f[k][j] >> (1 + user)) & 1)) zbyte |= 3u << (2 * j);
         ((uint8_t *)zw)[64 * k + lane] = (uint8_t)zbyte;
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_handoff();  // every lane's Z byte, then the word reads
 #pragma unroll
     for (int k = 0; k < NT; k++)
         if (ovalid[k]) {
@@ -998,7 +1042,7 @@ __device__ __forceinline__ void ccl_gather_tasks(const Geo &g, const MRef &b, co
             const uint64_t keep = ow == g.wpr - 1 ? g.tail : ~0ull;
             out[oi[k]] = (oyz[k] | (ob[k] & zw[8 * k + (lane & 7)])) & keep;
         }
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_handoff();  // zw is rewritten by the wave's next tasks
 }
 
 constexpr int kGatherTasksPerWave = 2;
@@ -1076,27 +1120,29 @@ __global__ __launch_bounds__(kThreads) void k_atoms(Geo g, const T *__restrict__
 template <int TBH>
 __global__ __launch_bounds__(ccl_local_threads<TBH>()) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
                                                         int32_t *__restrict__ glab,
-                                                        uint8_t *__restrict__ gflag) {
-    ccl_local_tile<TBH>(g, b, y, z, blockIdx.x % ntx, blockIdx.x / ntx, glab, gflag);
+                                                        uint8_t *__restrict__ gflag, LoopGuard gd) {
+    ccl_local_tile<TBH>(g, b, y, z, blockIdx.x % ntx, blockIdx.x / ntx, glab, gflag, gd);
 }
 
 template <int TBH>
 __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int ntiles, int32_t *glab,
-                                                        unsigned long long *counters) {
+                                                        unsigned long long *counters, LoopGuard gd) {
     __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
     const int wv = threadIdx.x >> 6, tile = blockIdx.x * (kThreads / 64) + wv;
     int unions = 0, tries = 0;
-    if (tile < ntiles) ccl_merge_tile<TBH>(g, b, ntx, tile, glab, win[wv], unions, tries);
+    if (tile < ntiles) ccl_merge_tile<TBH>(g, b, ntx, tile, glab, win[wv], unions, tries, gd);
     if (counters && (unions | tries)) {
         atomicAdd(&counters[0], (unsigned long long)unions);
         atomicAdd(&counters[1], (unsigned long long)(tries - unions));
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag) {
+__global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag, LoopGuard gd) {
     const int64_t stride = (int64_t)gridDim.x * kThreads * 16;
+    bool ok = true;
     for (int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 16; i0 < nblocks; i0 += stride)
-        ccl_flag16(glab, gflag, nblocks, i0);
+        ccl_flag16(glab, gflag, nblocks, i0, gd.cap, ok);
+    guard_report(gd, ok);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ccl_gather(Geo g, MRef b, MRef y, MRef z,
@@ -1265,7 +1311,7 @@ __global__ __launch_bounds__(ccl_local_threads<TBH>()) void kb_ccl_local(BatchAr
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW;
         const int tile = (int)(u_ - a.prefix[ii]);
         ccl_local_tile<TBH>(d.g, bref(d, b), bref(d, y), bref(d, z), tile % ntx, tile / ntx,
-                            (int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag));
+                            (int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), a.guard);
     }
 }
 
@@ -1279,16 +1325,19 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW, nty = (d.g.BH + TBH - 1) / TBH;
         const int tile = (int)(u_ - a.prefix[ii]) * (kThreads / 64) + wv;
         if (tile < ntx * nty)
-            ccl_merge_tile<TBH>(d.g, bref(d, b), ntx, tile, (int32_t *)(d.ws + d.off_glab), win[wv], unions, tries);
+            ccl_merge_tile<TBH>(d.g, bref(d, b), ntx, tile, (int32_t *)(d.ws + d.off_glab), win[wv], unions, tries,
+                                a.guard);
     }
 }
 
 __global__ __launch_bounds__(kThreads) void kb_ccl_flag(BatchArgs a) {
+    bool ok = true;
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
         const int64_t i0 = ((u_ - a.prefix[ii]) * kThreads + threadIdx.x) * 16, nb = (int64_t)d.g.BH * d.g.BW;
-        if (i0 < nb) ccl_flag16((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), nb, i0);
+        if (i0 < nb) ccl_flag16((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), nb, i0, a.guard.cap, ok);
     }
+    guard_report(a.guard, ok);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_ccl_gather(BatchArgs a, BRef b, BRef y, BRef z, int user, int32_t out) {
@@ -1383,9 +1432,9 @@ hipError_t launch_ccl_local(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z,
     if (!valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
     const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh);
     switch (w.tbh) {
-    case 8: k_ccl_local<8><<<ntx * nty, ccl_local_threads<8>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
-    case 16: k_ccl_local<16><<<ntx * nty, ccl_local_threads<16>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
-    default: k_ccl_local<32><<<ntx * nty, ccl_local_threads<32>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag); break;
+    case 8: k_ccl_local<8><<<ntx * nty, ccl_local_threads<8>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag, w.guard); break;
+    case 16: k_ccl_local<16><<<ntx * nty, ccl_local_threads<16>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag, w.guard); break;
+    default: k_ccl_local<32><<<ntx * nty, ccl_local_threads<32>(), 0, s>>>(g, b, y, z, ntx, w.glab, w.gflag, w.guard); break;
     }
     return hipGetLastError();
 }
@@ -1396,9 +1445,9 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
     const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh), ntiles = ntx * nty;
     const int grid = (ntiles + kThreads / 64 - 1) / (kThreads / 64);  // one wave per tile
     switch (w.tbh) {
-    case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters); break;
-    case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters); break;
-    default: k_ccl_merge<32><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters); break;
+    case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters, w.guard); break;
+    case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters, w.guard); break;
+    default: k_ccl_merge<32><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters, w.guard); break;
     }
     return hipGetLastError();
 }
@@ -1406,7 +1455,7 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
 hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w) {
     if (g.nwords == 0) return hipSuccess;
     const int64_t nb = (int64_t)g.BH * g.BW;
-    k_ccl_flag<<<grid_for((nb + 15) / 16, kThreads, 65536), kThreads, 0, s>>>(nb, w.glab, w.gflag);
+    k_ccl_flag<<<grid_for((nb + 15) / 16, kThreads, 65536), kThreads, 0, s>>>(nb, w.glab, w.gflag, w.guard);
     return hipGetLastError();
 }
 

@@ -250,3 +250,20 @@ def random_dag(seed, n_nodes, n_reach, channels=1, max_outputs=8):
              .tolist() if n_reach > 0 else [])
     _grow_ops(d, n_nodes, slots, extra)
     return d.text(max_outputs=max_outputs)
+
+
+SERVE_SIDES = (256, 512, 1024, 2048, 4096, 8192)
+
+
+def serve_formulas(seed=5, n_random=5, n_max=2000, reach_max=50):
+    """Formula texts of the serving mix: `n_random` formulas with node counts
+    log-uniform in [20, n_max] and U{0 .. min(reach_max, n/10)} reach-type
+    nodes, plus one formula at the top of both ranges (n_max nodes, reach_max
+    reach-type nodes).  Returns [(text, n_nodes, n_reach)]."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for _ in range(n_random):
+        n = int(round(np.exp(rng.uniform(np.log(20), np.log(n_max)))))
+        specs.append((n, int(rng.integers(0, min(reach_max, n // 10) + 1))))
+    specs.append((n_max, reach_max))
+    return [(random_dag(500 + k, n_nodes=n, n_reach=r), n, r) for k, (n, r) in enumerate(specs)]

@@ -174,3 +174,9 @@ def phantom_image_device(seed, index, h, w, channels=4, sigma_noise=0.05, device
         n2 = torch.randn((h, w), generator=gen, device=device, dtype=torch.float32)
         out[c] = torch.sqrt((canvas + s * n1) ** 2 + (s * n2) ** 2)
     return out
+
+
+def serve_image(index, side):
+    """Image `index` of the serving mix: one float32 channel, the ellipse
+    recipe (60 ellipses on smoothed noise) at `side` x `side`."""
+    return np.ascontiguousarray(ellipse_maze_image(50 + index, side, n_ellipses=60)[:1])
