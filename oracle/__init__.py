@@ -5,7 +5,8 @@ CPU-baseline leg may import this package.  It shares no code with the GPU
 library and never calls it.
 
 Masks are numpy uint8 arrays of 0/1, shape (H, W).  Images are numpy arrays
-of shape (C, H, W) (or (H, W) for one channel), dtype float32 or uint8.
+of shape (C, H, W) (or (H, W) for one channel), dtype float32, uint8 or
+uint16.
 """
 import ctypes
 import os
@@ -15,7 +16,7 @@ import numpy as np
 from .build import LIB_PATH, build
 
 CMP = {">": 0, "<": 1, ">=": 2, "<=": 3}
-_DT = {np.dtype(np.float32): 0, np.dtype(np.uint8): 1}
+_DT = {np.dtype(np.float32): 0, np.dtype(np.uint8): 1, np.dtype(np.uint16): 2}
 _lib = None
 
 
@@ -57,7 +58,7 @@ def _img3(img):
     if img.ndim == 2:
         img = img[None]
     if img.ndim != 3 or img.dtype not in _DT:
-        raise ValueError("image must be (C,H,W) float32 or uint8")
+        raise ValueError("image must be (C,H,W) float32, uint8 or uint16")
     return img
 
 

@@ -56,6 +56,7 @@
 
 #define DT_F32 0
 #define DT_U8 1
+#define DT_U16 2 /* the paper's pixel type (Sect. 3 restricts its tool to 2-D uint16 images) */
 
 /* ------------------------------------------------------------------ */
 /* Primitive operators on byte masks                                   */
@@ -244,6 +245,8 @@ static float pixel_value(const void *img, int dtype, int64_t idx)
 {
     if (dtype == DT_U8)
         return (float)((const uint8_t *)img)[idx];
+    if (dtype == DT_U16)
+        return (float)((const uint16_t *)img)[idx]; /* exact: 16 bits fit the float32 mantissa */
     return ((const float *)img)[idx];
 }
 
@@ -1053,7 +1056,7 @@ int oracle_run(const char *src, const void *img, int dtype, int C, int H, int W,
 {
     if (err && errlen > 0)
         err[0] = 0;
-    if ((dtype != DT_F32 && dtype != DT_U8) || C < 1 || H < 0 || W < 0) {
+    if ((dtype != DT_F32 && dtype != DT_U8 && dtype != DT_U16) || C < 1 || H < 0 || W < 0) {
         if (err && errlen > 0)
             snprintf(err, (size_t)errlen, "bad image description");
         return ORC_EINVAL;

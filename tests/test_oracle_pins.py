@@ -89,6 +89,30 @@ def test_percentile_u8_and_threshold_use():
     assert np.array_equal(m, (img[0] > t).astype(np.uint8))
 
 
+def test_threshold_u16_exact():
+    # uint16 pixels (the paper's type) convert exactly to float32; the
+    # specification's thresholds are uint16 values (Fig. specification)
+    img = np.array([[0, 1, 56359, 56360, 56361, 62257, 62258, 62259, 65534, 65535]], np.uint16)[None]
+    for op, t, ref in [(">", 62258, np.greater), (">", 56360, np.greater), (">=", 56360, np.greater_equal),
+                       ("<", 1, np.less), ("<=", 65534.5, np.less_equal), (">", 62257.5, np.greater)]:
+        got = oracle.threshold(img, 0, op, t)
+        assert np.array_equal(got, ref(img[0].astype(np.float64), np.float32(t)).astype(np.uint8)), (op, t)
+
+
+def test_percentile_u16_and_threshold_use():
+    rng = np.random.default_rng(9)
+    img = rng.integers(0, 65536, (2, 23, 37), dtype=np.uint16)
+    img[1, :5] = 40000  # ties
+    for c in (0, 1):
+        for q in (0.0, 0.3, 0.86, 0.95, 1.0):
+            v = np.sort(img[c].reshape(-1))
+            k = min(max(int(np.ceil(q * v.size)) - 1, 0), v.size - 1)
+            assert oracle.percentile(img, c, q) == np.float32(v[k])
+    t = np.sort(img[0].reshape(-1))[int(np.ceil(0.95 * img[0].size)) - 1]
+    (m,) = oracle.run('output "m" intensity(img) >. percentile(img, 0, 0.95)', img)
+    assert np.array_equal(m, (img[0] > t).astype(np.uint8))
+
+
 # ---------------------------------------------------------------- Boolean operators
 
 def test_boolean_truth_tables():
