@@ -50,6 +50,7 @@ extern "C" {
 /* ---- enums ---- */
 #define VLG_F32 0        /* image pixel types */
 #define VLG_U8 1
+#define VLG_U16 2        /* the paper's pixel type (Sect. 3: 2-D uint16 images) */
 #define VLG_HOST 0       /* where a caller buffer lives */
 #define VLG_DEVICE 1
 #define VLG_PACKED64 0   /* mask formats, see above */
@@ -91,6 +92,8 @@ typedef struct vlg_formula_stats {
     int64_t labellings;     /* connected-component labellings (fused schedule) */
     int64_t labelling_reuse;/* reach-type nodes served by an earlier labelling of
                                the same passable mask */
+    int64_t segments;       /* fused segments (runs of Boolean and near steps
+                               run by one tile kernel) at the default halo cap */
 } vlg_formula_stats;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
@@ -122,7 +125,8 @@ int vlg_set_mode(vlg_ctx *ctx, int mode);
  *   data: pixels, channel-planar [channels][height][pitch], in host memory
  *     (where = VLG_HOST) or device memory (VLG_DEVICE, e.g. a torch tensor's
  *     data pointer); pitch_elems >= width is the row stride in elements (0
- *     means width).  dtype is VLG_F32 or VLG_U8.
+ *     means width).  dtype is VLG_F32, VLG_U8 or VLG_U16; every pixel type
+ *     converts exactly to float32, the type atoms compare in.
  *   channels >= 1, height >= 0, width >= 0; height*width < 2^31.
  * The copy is complete when the call returns (host source) or in stream order
  * (device source): the caller may free a host source at once and a device
@@ -145,6 +149,17 @@ int vlg_image_shape(const vlg_image *img, int *channels, int *height, int *width
  * error returns VLG_EPARSE with "line L col C: ..." in vlg_last_error(). */
 int vlg_compile_formula(vlg_ctx *ctx, const char *src, vlg_formula **out);
 int vlg_formula_info(const vlg_formula *f, vlg_formula_stats *stats);
+/* The kernel schedule of every output of f as JSON text (an "explain" of the
+ * plan; no device work): mode VLG_MODE_PEROP or VLG_MODE_FUSED, fuse_halo
+ * the segment halo cap of the fused schedule (see VLG_TUNE_FUSE_HALO).
+ * {"nslots", "npct", "noutputs", "steps": [{"kind", "x"/"y"/"z": [slot, inv],
+ * "out", "op", "inv_out", "chan", "user", "group", "seg", "q": [[q, scalar]],
+ * "atoms": [[cmp, use_pct, thr, scalar, out]]}], "segments": [{"halo",
+ * "nregs", "inputs", "outputs", "ins": [[op, dst, a, b, inv]]}]}; mask slot
+ * -1 is the zero mask, slots <= -2 are outputs -2-k.  Writes at most len bytes
+ * (NUL included) to buf; *needed (if not NULL) receives the size needed; with
+ * len = 0 only the size is reported. */
+int vlg_formula_plan(const vlg_formula *f, int mode, int fuse_halo, char *buf, int64_t len, int64_t *needed);
 /* Name of output `index` (pointer valid while f lives), or NULL. */
 const char *vlg_formula_output_name(const vlg_formula *f, int index);
 int vlg_formula_free(vlg_formula *f);
@@ -232,11 +247,17 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
  *   VLG_TUNE_CCL_LANES: labelling lanes of the fused schedule.  Only 1 is
  *     accepted: concurrent lanes (2 or 4, independent labellings on separate
  *     streams) are switched off while a host-side crash seen with four lanes
- *     is unexplained; other values return VLG_EINVAL. */
+ *     is unexplained; other values return VLG_EINVAL.
+ *   VLG_TUNE_FUSE_HALO: fused segments of the fused schedule: runs of
+ *     consecutive Boolean and near steps that one tile kernel evaluates with
+ *     every intermediate mask in LDS, the tile extended by a halo as deep as
+ *     the segment's longest chain of near steps.  The value is the largest
+ *     halo allowed (2, 4, 8 or 16 rows; default 8); 1 forms no segments. */
 #define VLG_TUNE_CCL_TILE_ROWS 0
 #define VLG_TUNE_NEAR_ROWS 1
 #define VLG_TUNE_BATCH_GRID 2
 #define VLG_TUNE_CCL_LANES 3
+#define VLG_TUNE_FUSE_HALO 4
 /* Force `value` for every image (value 0 returns to table/default). */
 int vlg_set_tunable(vlg_ctx *ctx, int which, int value);
 /* The value used for an image of height x width on this context. */

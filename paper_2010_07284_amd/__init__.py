@@ -109,17 +109,18 @@ def set_mode(ctx, mode):
 
 def load_image(ctx, t):
     """vlg_load_image from a torch tensor or numpy array, (C,H,W) or (H,W),
-    float32 or uint8, host or device."""
+    float32, uint8 or uint16, host or device."""
     torch = _torch()
     if not isinstance(t, torch.Tensor):
         t = torch.from_numpy(t)
     if t.dim() == 2:
         t = t.unsqueeze(0)
-    if t.dim() != 3 or t.dtype not in (torch.float32, torch.uint8):
-        raise ValueError("image must be (C,H,W) float32 or uint8")
+    codes = {torch.float32: 0, torch.uint8: 1, torch.uint16: 2}
+    if t.dim() != 3 or t.dtype not in codes:
+        raise ValueError("image must be (C,H,W) float32, uint8 or uint16")
     t = t.contiguous()
     C, H, W = t.shape
-    dtype = 0 if t.dtype == torch.float32 else 1
+    dtype = codes[t.dtype]
     where = 1 if t.is_cuda else 0
     if where == 1:
         # the library copies on its own stream: torch's pending writes first
@@ -142,6 +143,17 @@ def formula_info(f):
     st = _lib.FormulaStats()
     _lib.call("vlg_formula_info", f.handle, ctypes.byref(st))
     return {name: getattr(st, name) for name, _ in _lib.FormulaStats._fields_}
+
+
+def formula_plan(f, mode="fused", fuse_halo=8):
+    """vlg_formula_plan: the kernel schedule of every output as a dict."""
+    import json
+    need = ctypes.c_int64()
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _lib.call("vlg_formula_plan", f.handle, m, fuse_halo, None, 0, ctypes.byref(need))
+    buf = ctypes.create_string_buffer(need.value)
+    _lib.call("vlg_formula_plan", f.handle, m, fuse_halo, buf, need.value, ctypes.byref(need))
+    return json.loads(buf.value.decode())
 
 
 def output_names(f):
@@ -224,7 +236,7 @@ def profile(ctx, f, img, iters=5):
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
 
 
-TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2, "ccl_lanes": 3}
+TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2, "ccl_lanes": 3, "fuse_halo": 4}
 
 
 def set_tunable(ctx, name, value):
@@ -240,9 +252,9 @@ def get_tunable(ctx, name, height, width):
 
 def autotune(ctx, f, img, iters=5):
     """vlg_autotune: {tunable: (best, {candidate: ms})} for img's shape class."""
-    arr = (_lib.TuneReport * 4)()
+    arr = (_lib.TuneReport * 8)()
     n = ctypes.c_int()
-    _lib.call("vlg_autotune", ctx.handle, f.handle, img.handle, iters, arr, 4, ctypes.byref(n))
+    _lib.call("vlg_autotune", ctx.handle, f.handle, img.handle, iters, arr, 8, ctypes.byref(n))
     names = {v: k for k, v in TUNABLES.items()}
     return {names[arr[i].which]: (arr[i].best, {arr[i].candidates[j]: arr[i].ms[j] for j in range(arr[i].n)})
             for i in range(n.value)}
@@ -341,7 +353,7 @@ def pack(mask):
     return np.packbits(padded, axis=1, bitorder="little").view("<i8").reshape(H, wpr).copy()
 
 
-__all__ = ["create", "sync", "set_loop_cap", "set_mode", "load_image", "compile_formula", "formula_info", "output_names",
+__all__ = ["create", "sync", "set_loop_cap", "set_mode", "load_image", "compile_formula", "formula_info", "formula_plan", "output_names",
            "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
            "tune_load", "autotune_batch", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

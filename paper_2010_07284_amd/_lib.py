@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvlg.so")
 # every symbol declared in include/vlg.h
 EXPORTS = [
     "vlg_create", "vlg_destroy", "vlg_sync", "vlg_set_loop_cap", "vlg_set_mode", "vlg_load_image", "vlg_image_free",
-    "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name",
+    "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name", "vlg_formula_plan",
     "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels",
     "vlg_ccl_read_counters", "vlg_profile", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune", "vlg_autotune_batch",
     "vlg_tune_save", "vlg_tune_load", "vlg_server_create", "vlg_server_submit", "vlg_server_wait",
@@ -28,7 +28,7 @@ class VlgError(RuntimeError):
 class FormulaStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("parsed_nodes", "nodes", "reach_nodes", "atoms", "outputs", "steps_perop", "steps_fused",
-                 "peak_masks", "launches_fused", "labellings", "labelling_reuse")]
+                 "peak_masks", "launches_fused", "labellings", "labelling_reuse", "segments")]
 
 
 class KernelTime(ctypes.Structure):
@@ -77,6 +77,7 @@ def lib():
             "vlg_compile_formula": ([P, ctypes.c_char_p, P], I),
             "vlg_formula_info": ([P, P], I),
             "vlg_formula_output_name": ([P, I], ctypes.c_char_p),
+            "vlg_formula_plan": ([P, I, I, P, I64, P], I),
             "vlg_formula_free": ([P], I),
             "vlg_check": ([P, P, P, I, P, I, I], I),
             "vlg_check_all": ([P, P, P, P, I, I], I),

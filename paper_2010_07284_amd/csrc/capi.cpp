@@ -63,13 +63,14 @@ struct vlg_formula {
     std::mutex mu;
     std::map<std::pair<std::vector<int>, int>, std::unique_ptr<Plan>> plans;
 
-    // lanes: concurrent labelling lanes of the fused schedule (1: sequential)
-    const Plan &plan(const std::vector<int> &which, Mode m, int lanes = 1) {
+    // lanes: concurrent labelling lanes of the fused schedule (1: sequential);
+    // fuse: segment halo cap of the fused schedule (1: no segments)
+    const Plan &plan(const std::vector<int> &which, Mode m, int lanes = 1, int fuse = 1) {
         std::lock_guard<std::mutex> lk(mu);
-        auto key = std::make_pair(which, (int)m * 16 + lanes);
+        auto key = std::make_pair(which, ((int)m * 16 + lanes) * 64 + fuse);
         auto it = plans.find(key);
         if (it != plans.end()) return *it->second;
-        auto p = std::make_unique<Plan>(build_plan(dag, which, m, lanes));
+        auto p = std::make_unique<Plan>(build_plan(dag, which, m, lanes, m == Mode::Fused ? fuse : 1));
         const Plan &ref = *p;
         plans.emplace(key, std::move(p));
         return ref;
@@ -82,7 +83,7 @@ struct vlg_image {
     int64_t pitch;  // elements per row (wpr * 64)
     void *dev;      // from the device's stream-ordered pool (hipMallocAsync)
     size_t bytes;
-    size_t esize() const { return dtype == VLG_U8 ? 1 : 4; }
+    size_t esize() const { return dtype == VLG_U8 ? 1 : dtype == VLG_U16 ? 2 : 4; }
     const char *chan(int c) const { return (const char *)dev + (size_t)c * H * pitch * esize(); }
     // the last enqueued use of the image on each stream that read it: its
     // release waits for these events instead of for the whole device
@@ -123,8 +124,9 @@ struct GraphKey {
 };
 
 // Tunables (VLG_TUNE_*): a value of 0 means "not set" (default rule).
-constexpr int kNumTunables = 4;
-const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid", "ccl_lanes"};
+constexpr int kNumTunables = 5;
+const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid", "ccl_lanes",
+                                                 "fuse_halo"};
 
 bool tunable_valid(int which, int v) {
     switch (which) {
@@ -136,12 +138,13 @@ bool tunable_valid(int which, int v) {
     // cause is not found, so only the sequential schedule (one lane) is
     // accepted until it is.
     case VLG_TUNE_CCL_LANES: return v == 1;
+    case VLG_TUNE_FUSE_HALO: return valid_fuse_halo(v);
     }
     return false;
 }
 
 struct Tuning {
-    int v[kNumTunables] = {0, 0, 0, 0};
+    int v[kNumTunables] = {0, 0, 0, 0, 0};
 };
 
 struct vlg_ctx {
@@ -281,6 +284,7 @@ int tuned_value(const vlg_ctx *c, int which, int H, int W) {
     case VLG_TUNE_CCL_TILE_ROWS: return default_tile_bh([&](int t) { return tile_count(H, W, t); });
     case VLG_TUNE_BATCH_GRID: return kBatchGridDefault;
     case VLG_TUNE_CCL_LANES: return 1;
+    case VLG_TUNE_FUSE_HALO: return kFuseHaloDefault;
     }
     return 0;
 }
@@ -323,13 +327,14 @@ const char *kind_name(SK k) {
     case SK::CclFlag: return "ccl_flag";
     case SK::CclGather: return "ccl_gather";
     case SK::CclReseed: return "ccl_reseed";
+    case SK::Segment: return "segment";
     }
     return "?";
 }
 
 // Bytes a step must move at the least: its image channel or input masks
 // read once, its outputs written once (and the labelling arrays it owns).
-double algorithmic_bytes(const Step &s, const Geo &g, int dtype, int tbh) {
+double algorithmic_bytes(const Plan &P, const Step &s, const Geo &g, int dtype, int tbh) {
     const double mb = (double)g.nwords * 8.0, npix = (double)g.H * g.W;
     const double nb = (double)g.BH * g.BW;
     auto ins = [&](std::initializer_list<Ref> rs) {
@@ -338,8 +343,8 @@ double algorithmic_bytes(const Step &s, const Geo &g, int dtype, int tbh) {
         return n;
     };
     switch (s.kind) {
-    case SK::Pct: return npix * (dtype == VLG_U8 ? 1.0 : 3.0 * 4.0);
-    case SK::Atoms: return npix * (dtype == VLG_U8 ? 1.0 : 4.0) + s.natoms * mb;
+    case SK::Pct: return npix * (dtype == VLG_U8 ? 1.0 : dtype == VLG_U16 ? 2.0 * 2.0 : 3.0 * 4.0);  // per pass
+    case SK::Atoms: return npix * (dtype == VLG_U8 ? 1.0 : dtype == VLG_U16 ? 2.0 : 4.0) + s.natoms * mb;
     case SK::Logic: return ins({s.x, s.y}) + mb;
     case SK::Near: return ins({s.x, s.z}) + mb;
     case SK::CclLocal: return ins({s.x, s.y, s.z}) + nb * 5.0;      // labels + flags written
@@ -350,6 +355,10 @@ double algorithmic_bytes(const Step &s, const Geo &g, int dtype, int tbh) {
     case SK::CclFlag: return nb;                                      // flags read
     case SK::CclGather: return ins({s.x, s.y, s.z}) + nb * 4.0 + mb;  // labels read
     case SK::CclReseed: return ins({s.x});                            // seed mask read
+    case SK::Segment: {                                               // loads + stores
+        const Segment &S = P.segments[(size_t)s.seg];
+        return (double)(S.inputs.size() + S.outputs.size()) * mb;
+    }
     }
     return 0.0;
 }
@@ -500,6 +509,27 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         case SK::CclReseed:
             e = launch_ccl_reseed(stream, g, mref(s.x), w, s.user);
             break;
+        case SK::Segment: {
+            const Segment &S = P.segments[(size_t)s.seg];
+            SegProg sp;
+            std::memset(&sp, 0, sizeof sp);
+            const size_t ni = S.inputs.size();
+            if (S.ins.size() > (size_t)kSegMaxIns || ni + S.outputs.size() > (size_t)kSegMaxPtrs ||
+                S.nregs > kSegMaxRegs)
+                return fail(VLG_EINVAL, "internal: segment exceeds the kernel's program limits");
+            sp.nins = (int32_t)S.ins.size();
+            sp.nregs = S.nregs;
+            sp.halo = S.halo;
+            for (size_t k = 0; k < S.ins.size(); k++) {
+                const SegInstr &q = S.ins[k];
+                sp.ins[k] = SegIns{q.op, q.dst, q.a, q.b, q.inv};
+                if (q.op == SOP_STORE) sp.ins[k].dst = (uint8_t)(ni + q.dst);
+            }
+            for (size_t k = 0; k < ni; k++) sp.ptr[k] = slot_ptr(S.inputs[k]);
+            for (size_t k = 0; k < S.outputs.size(); k++) sp.ptr[ni + k] = slot_ptr(S.outputs[k]);
+            e = launch_segment(stream, g, sp);
+            break;
+        }
         }
         if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
         if (hook) hook(hook_ctx, si, false);
@@ -519,7 +549,8 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
     if (img->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
     DeviceGuard dg(c->device);
     const Mode m = c->mode == VLG_MODE_PEROP ? Mode::PerOp : Mode::Fused;
-    const Plan &P = f->plan(which, m, m == Mode::Fused ? tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W) : 1);
+    const Plan &P = f->plan(which, m, m == Mode::Fused ? tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W) : 1,
+                            tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
     const Geo g = make_geo(img->H, img->W);
     if (g.nwords == 0 || which.empty()) return VLG_OK;
     const bool direct = fmt == VLG_PACKED64 && where == VLG_DEVICE;
@@ -800,6 +831,8 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
             case SK::CclReseed:
                 e = launch_b_ccl_reseed(c->stream, args(BK_BLOCKS), units(BK_BLOCKS), bref(s.x), s.user);
                 break;
+            case SK::Segment:
+                return fail(VLG_EINVAL, "internal: the batched schedule has no segments");
             }
             if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
         }
@@ -880,7 +913,8 @@ namespace vlg {
 size_t evaluation_footprint(vlg_formula *f, const vlg_image *img) {
     std::vector<int> all(f->dag.outputs.size());
     for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
-    const Plan &P = f->plan(all, Mode::Fused, 1);  // server slots run one labelling lane
+    // server slots run one labelling lane and the default segment halo cap
+    const Plan &P = f->plan(all, Mode::Fused, 1, kFuseHaloDefault);
     return layout_for(P, make_geo(img->H, img->W), false, false).total;
 }
 int evaluate_all_on(vlg_ctx *c, vlg_formula *f, const vlg_image *img, void *const *outs, void *ws, size_t ws_size) {
@@ -1035,7 +1069,8 @@ int vlg_load_image(vlg_ctx *c, const void *data, int dtype, int channels, int he
                    int64_t pitch_elems, int where, vlg_image **out) {
     if (!c || !out) return fail(VLG_EINVAL, "null handle");
     *out = nullptr;
-    if (dtype != VLG_F32 && dtype != VLG_U8) return fail(VLG_EINVAL, "dtype must be VLG_F32 or VLG_U8");
+    if (dtype != VLG_F32 && dtype != VLG_U8 && dtype != VLG_U16)
+        return fail(VLG_EINVAL, "dtype must be VLG_F32, VLG_U8 or VLG_U16");
     if (where != VLG_HOST && where != VLG_DEVICE) return fail(VLG_EINVAL, "bad memory kind");
     if (channels < 1 || height < 0 || width < 0) return fail(VLG_ESHAPE, "bad image shape");
     if ((int64_t)height * width >= (1ll << 31)) return fail(VLG_ESHAPE, "image too large (H*W >= 2^31)");
@@ -1123,13 +1158,80 @@ int vlg_compile_formula(vlg_ctx *c, const char *src, vlg_formula **out) {
     return VLG_OK;
 }
 
+int vlg_formula_plan(const vlg_formula *cf, int mode, int fuse_halo, char *buf, int64_t len, int64_t *needed) {
+    if (!cf || (!buf && len > 0) || len < 0) return fail(VLG_EINVAL, "null argument");
+    if (mode != VLG_MODE_PEROP && mode != VLG_MODE_FUSED) return fail(VLG_EINVAL, "mode must be per-op or fused");
+    if (mode == VLG_MODE_FUSED && !valid_fuse_halo(fuse_halo)) return fail(VLG_EINVAL, "bad segment halo cap");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    std::vector<int> all(f->dag.outputs.size());
+    for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
+    std::string t;
+    try {
+        const Plan &P = f->plan(all, mode == VLG_MODE_PEROP ? Mode::PerOp : Mode::Fused, 1, fuse_halo);
+        char tmp[256];
+        auto ref = [&](const Ref &r) {
+            std::snprintf(tmp, sizeof tmp, "[%d, %d]", r.slot, (int)r.inv);
+            return std::string(tmp);
+        };
+        std::snprintf(tmp, sizeof tmp, "{\"nslots\": %d, \"npct\": %d, \"noutputs\": %d, \"steps\": [", P.nslots,
+                      P.npct, P.noutputs);
+        t += tmp;
+        for (size_t si = 0; si < P.steps.size(); si++) {
+            const Step &st = P.steps[si];
+            std::snprintf(tmp, sizeof tmp, "%s{\"kind\": \"%s\", \"out\": %d, \"op\": %d, \"inv_out\": %d, "
+                                           "\"chan\": %d, \"user\": %d, \"group\": %d, \"seg\": %d, ",
+                          si ? ", " : "", kind_name(st.kind), st.out, (int)st.op, (int)st.inv_out, st.chan, st.user,
+                          st.group, st.seg);
+            t += tmp;
+            t += "\"x\": " + ref(st.x) + ", \"y\": " + ref(st.y) + ", \"z\": " + ref(st.z) + ", \"q\": [";
+            for (int j = 0; j < st.npq; j++) {
+                std::snprintf(tmp, sizeof tmp, "%s[%.17g, %d]", j ? ", " : "", st.q[j], st.pct_out[j]);
+                t += tmp;
+            }
+            t += "], \"atoms\": [";
+            for (int j = 0; j < st.natoms; j++) {
+                const AtomEntry &e = st.atoms[j];
+                std::snprintf(tmp, sizeof tmp, "%s[%d, %d, %.9g, %d, %d]", j ? ", " : "", (int)e.cmp, (int)e.use_pct,
+                              (double)e.thr, e.pct, e.out);
+                t += tmp;
+            }
+            t += "]}";
+        }
+        t += "], \"segments\": [";
+        for (size_t k = 0; k < P.segments.size(); k++) {
+            const Segment &S = P.segments[k];
+            std::snprintf(tmp, sizeof tmp, "%s{\"halo\": %d, \"nregs\": %d, \"inputs\": [", k ? ", " : "", S.halo,
+                          S.nregs);
+            t += tmp;
+            for (size_t q = 0; q < S.inputs.size(); q++) t += (q ? ", " : "") + std::to_string(S.inputs[q]);
+            t += "], \"outputs\": [";
+            for (size_t q = 0; q < S.outputs.size(); q++) t += (q ? ", " : "") + std::to_string(S.outputs[q]);
+            t += "], \"ins\": [";
+            for (size_t q = 0; q < S.ins.size(); q++) {
+                const SegInstr &in = S.ins[q];
+                std::snprintf(tmp, sizeof tmp, "%s[%d, %d, %d, %d, %d]", q ? ", " : "", in.op, in.dst, in.a, in.b,
+                              in.inv);
+                t += tmp;
+            }
+            t += "]}";
+        }
+        t += "]}";
+    } catch (const std::bad_alloc &) {
+        return fail(VLG_ENOMEM, "out of host memory");
+    }
+    if (needed) *needed = (int64_t)t.size() + 1;
+    if (len < (int64_t)t.size() + 1) return len == 0 ? VLG_OK : fail(VLG_EINVAL, "buffer too small");
+    std::memcpy(buf, t.c_str(), t.size() + 1);
+    return VLG_OK;
+}
+
 int vlg_formula_info(const vlg_formula *cf, vlg_formula_stats *st) {
     if (!cf || !st) return fail(VLG_EINVAL, "null argument");
     vlg_formula *f = const_cast<vlg_formula *>(cf);
     std::vector<int> all(f->dag.outputs.size());
     for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
     const Plan &pp = f->plan(all, Mode::PerOp);
-    const Plan &pf = f->plan(all, Mode::Fused, 1);
+    const Plan &pf = f->plan(all, Mode::Fused, 1, kFuseHaloDefault);
     st->parsed_nodes = f->dag.parsed_nodes;
     st->nodes = (int64_t)f->dag.nodes.size();
     st->reach_nodes = count_op(f->dag, true);
@@ -1146,6 +1248,7 @@ int vlg_formula_info(const vlg_formula *cf, vlg_formula_stats *st) {
     st->launches_fused = launches;
     st->labellings = pf.ccl_count;
     st->labelling_reuse = pf.ccl_reuse;
+    st->segments = (int64_t)pf.segments.size();
     return VLG_OK;
 }
 
@@ -1214,7 +1317,7 @@ int vlg_check_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *i
         }
         DeviceGuard dg(c->device);
         // one batched pass per pixel type; empty images have no units
-        for (int dt : {VLG_F32, VLG_U8}) {
+        for (int dt : {VLG_F32, VLG_U8, VLG_U16}) {
             std::vector<int> idx;
             for (int i = 0; i < n; i++)
                 if (imgs[i]->dtype == dt) idx.push_back(i);
@@ -1261,7 +1364,7 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
     DeviceGuard dg(c->device);
     std::vector<int> which(f->dag.outputs.size());
     for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
-    const Plan &P = f->plan(which, Mode::Fused);
+    const Plan &P = f->plan(which, Mode::Fused, 1, tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
     const Geo g = make_geo(img->H, img->W);
     *n_out = 0;
     if (g.nwords == 0 || which.empty()) return VLG_OK;
@@ -1315,7 +1418,7 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
                                       P.steps[si + 1].group == P.steps[si].group;
         if (!grouped_not_last) it->launches += iters;
         it->ms += ms[si];
-        it->bytes += iters * algorithmic_bytes(P.steps[si], g, img->dtype, tuning_for(c, img->H, img->W).ccl_tbh);
+        it->bytes += iters * algorithmic_bytes(P, P.steps[si], g, img->dtype, tuning_for(c, img->H, img->W).ccl_tbh);
     }
     for (size_t i = 0; i < kinds.size() && (int)i < max_out; i++) out[i] = kinds[i];
     *n_out = (int)kinds.size();
@@ -1351,23 +1454,37 @@ int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int it
     *n_out = 0;
     std::vector<int> which(f->dag.outputs.size());
     for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
-    const Plan &P = f->plan(which, Mode::Fused, tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W));
+    const int lanes = tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W);
     const Geo g = make_geo(img->H, img->W);
     if (g.nwords == 0) return VLG_OK;
+    // the step kinds of the schedule without segments, and a workspace that
+    // fits the plan of every segment halo cap the tuner may try
+    const std::vector<int> fuse_cands = {1, 4, 8, 16};
+    const Plan &P1 = f->plan(which, Mode::Fused, lanes, 1);
     bool has_near = false;
-    for (const Step &st : P.steps) has_near |= st.kind == SK::Near;
+    int local_steps = 0;
+    for (const Step &st : P1.steps) {
+        has_near |= st.kind == SK::Near;
+        local_steps += st.kind == SK::Near || st.kind == SK::Logic;
+    }
+    size_t need = 0;
+    for (int fz : fuse_cands) need = std::max(need, layout_for(f->plan(which, Mode::Fused, lanes, fz), g, true, false).total);
     std::vector<std::pair<int, std::vector<int>>> space;
-    if (P.ccl_count > 0) space.push_back({VLG_TUNE_CCL_TILE_ROWS, {8, 16, 32}});
+    if (P1.ccl_count > 0) space.push_back({VLG_TUNE_CCL_TILE_ROWS, {8, 16, 32}});
+    if (local_steps >= 2) space.push_back({VLG_TUNE_FUSE_HALO, fuse_cands});
     if (has_near) space.push_back({VLG_TUNE_NEAR_ROWS, {4, 8, 16, 32}});
-    Layout L = layout_for(P, g, true, false);
-    int rc = ensure_ws(c, L.total);
+    int rc = ensure_ws(c, need);
     if (rc != VLG_OK) return rc;
-    std::vector<uint64_t *> ext(which.size());
-    for (size_t k = 0; k < which.size(); k++) ext[k] = (uint64_t *)((char *)c->ws + L.off_stage + k * L.mask_bytes);
     const std::pair<int, int> cls{log2_class(img->H), log2_class(img->W)};
+    auto run_once = [&]() {
+        const Plan &P = f->plan(which, Mode::Fused, lanes, tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
+        const Layout L = layout_for(P, g, true, false);
+        std::vector<uint64_t *> ext(which.size());
+        for (size_t k = 0; k < which.size(); k++) ext[k] = (uint64_t *)((char *)c->ws + L.off_stage + k * L.mask_bytes);
+        return enqueue_plan(c, P, img, L, ext);
+    };
     return tune_loop(
-        c, space, iters, [&] { return enqueue_plan(c, P, img, L, ext); },
-        [&](int w, int best) { c->tuned[cls].v[w] = best; }, out, max_out, n_out);
+        c, space, iters, run_once, [&](int w, int best) { c->tuned[cls].v[w] = best; }, out, max_out, n_out);
 }
 
 int vlg_autotune_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *imgs, int n, int iters,

@@ -1028,9 +1028,145 @@ void schedule_fused(Lower &L, int lanes) {
     L.steps = std::move(out);
 }
 
+// Turn runs of consecutive Logic/Near steps of the (SSA) schedule into
+// segments: a run grows while its deepest chain of near steps stays within
+// `cap` and its program fits the kernel (registers, instructions, pointers);
+// a run of one step stays a plain step.  ext_of marks the SSA values that are
+// requested outputs (they are always stored).
+struct SegBuild {
+    Segment seg;
+    bool ok = false;
+};
+
+SegBuild build_segment(const std::vector<Step> &steps, size_t i, size_t j, const std::vector<int64_t> &last_read,
+                       const std::vector<int32_t> &ext_of, int cap) {
+    SegBuild r;
+    Segment &S = r.seg;
+    std::unordered_map<int32_t, int> depth, last_in;  // SSA -> near depth; -> last member reading it
+    std::unordered_map<int32_t, int> input_idx;
+    auto operands = [](const Step &st) {
+        std::vector<Ref> v;
+        if (st.kind == SK::Logic) v = {st.x, st.y};
+        else v = {st.x, st.z};
+        return v;
+    };
+    for (size_t k = i; k < j; k++) {
+        const Step &st = steps[k];
+        int d = 0;
+        for (const Ref &o : operands(st)) {
+            if (o.slot == kNone) continue;
+            auto it = depth.find(o.slot);
+            if (it == depth.end() && !input_idx.count(o.slot)) {
+                input_idx[o.slot] = (int)S.inputs.size();
+                S.inputs.push_back(o.slot);
+            }
+            last_in[o.slot] = (int)(k - i);
+        }
+        if (st.kind == SK::Near) {
+            const int dx = st.x.slot != kNone && depth.count(st.x.slot) ? depth[st.x.slot] : 0;
+            const int dz = st.z.slot != kNone && depth.count(st.z.slot) ? depth[st.z.slot] : 0;
+            d = std::max(dx + 1, dz);
+        } else {
+            for (const Ref &o : operands(st))
+                if (o.slot != kNone && depth.count(o.slot)) d = std::max(d, depth[o.slot]);
+        }
+        if (d > cap) return r;
+        depth[st.out] = d;
+        S.halo = std::max(S.halo, d);
+    }
+    // registers: inputs first, then members in order; a register is freed
+    // after the last member that reads it (results are stored right away)
+    std::vector<int> free_regs;
+    int nregs = 0;
+    auto alloc = [&]() {
+        if (!free_regs.empty()) {
+            const int x = free_regs.back();
+            free_regs.pop_back();
+            return x;
+        }
+        return nregs++;
+    };
+    std::unordered_map<int32_t, int> reg;
+    for (size_t q = 0; q < S.inputs.size(); q++) {
+        const int x = alloc();
+        reg[S.inputs[q]] = x;
+        S.ins.push_back(SegInstr{SOP_LOAD, (uint8_t)x, (uint8_t)q, kSegNoReg, 0});
+    }
+    auto reg_of = [&](const Ref &o) -> uint8_t { return o.slot == kNone ? kSegNoReg : (uint8_t)reg[o.slot]; };
+    for (size_t k = i; k < j; k++) {
+        const Step &st = steps[k];
+        const std::vector<Ref> ops = operands(st);
+        const int x = alloc();
+        SegInstr in;
+        if (st.kind == SK::Logic) in.op = st.op ? SOP_OR : SOP_AND;
+        else in.op = st.op ? SOP_NEAR_OR : SOP_NEAR_AND;
+        in.dst = (uint8_t)x;
+        in.a = reg_of(ops[0]);
+        in.b = reg_of(ops[1]);
+        in.inv = (uint8_t)((ops[0].inv ? 1 : 0) | (ops[1].inv ? 2 : 0) | (st.inv_out ? 4 : 0));
+        S.ins.push_back(in);
+        reg[st.out] = x;
+        const bool stored = last_read[(size_t)st.out] >= (int64_t)j || ext_of[(size_t)st.out] != kNone;
+        if (stored) {
+            S.ins.push_back(SegInstr{SOP_STORE, (uint8_t)S.outputs.size(), (uint8_t)x, kSegNoReg, 0});
+            S.outputs.push_back(st.out);
+        }
+        for (const Ref &o : ops) {
+            if (o.slot == kNone) continue;
+            auto it = last_in.find(o.slot);
+            if (it != last_in.end() && it->second == (int)(k - i) && reg.count(o.slot)) {
+                free_regs.push_back(reg[o.slot]);
+                last_in.erase(it);
+            }
+        }
+        if (!last_in.count(st.out)) free_regs.push_back(x);  // never read inside the segment
+    }
+    S.nregs = nregs;
+    r.ok = nregs <= kSegRegs && (int)S.ins.size() <= kSegInstrs &&
+           (int)(S.inputs.size() + S.outputs.size()) <= kSegPtrs;
+    return r;
+}
+
+void form_segments(Lower &L, const std::vector<int32_t> &ext_of, int cap, std::vector<Segment> &segs) {
+    const std::vector<Step> &steps = L.steps;
+    const size_t n = steps.size();
+    std::vector<int64_t> last_read((size_t)L.nssa, -1);
+    for (size_t si = 0; si < n; si++)
+        for (const Ref *r : {&steps[si].x, &steps[si].y, &steps[si].z})
+            if (r->slot != kNone) last_read[(size_t)r->slot] = (int64_t)si;
+    auto local = [](const Step &st) { return (st.kind == SK::Logic || st.kind == SK::Near) && st.lane < 0; };
+    std::vector<Step> out;
+    for (size_t i = 0; i < n;) {
+        if (!local(steps[i])) {
+            out.push_back(steps[i++]);
+            continue;
+        }
+        // the longest run from i that builds
+        size_t j = i + 1;
+        SegBuild best;
+        while (j < n && local(steps[j])) {
+            SegBuild b = build_segment(steps, i, j + 1, last_read, ext_of, cap);
+            if (!b.ok) break;
+            best = std::move(b);
+            j++;
+        }
+        if (!best.ok) {
+            out.push_back(steps[i++]);
+            continue;
+        }
+        Step sg;
+        sg.kind = SK::Segment;
+        sg.seg = (int32_t)segs.size();
+        segs.push_back(std::move(best.seg));
+        out.push_back(sg);
+        i = j;
+    }
+    L.steps = std::move(out);
+}
+
 }  // namespace
 
-Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes) {
+Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes, int fuse_halo) {
     Lower L(dag, mode);
     const size_t N = dag.nodes.size();
     std::vector<char> need(N, 0);
@@ -1078,21 +1214,42 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int la
         }
     }
 
+    std::vector<Segment> segs;
     if (mode == Mode::Fused) {
         schedule_fused(L, std::min(std::max(lanes, 1), kMaxCclLanes));
         ext_of.resize((size_t)L.nssa, kNone);
+        if (fuse_halo >= 2) form_segments(L, ext_of, fuse_halo, segs);
     }
+    // SSA values a step reads and writes (pointers, rewritten to slots below)
+    auto reads_of = [&](Step &s) {
+        std::vector<int32_t *> v;
+        if (s.kind == SK::Segment) {
+            for (int32_t &x : segs[(size_t)s.seg].inputs) v.push_back(&x);
+        } else {
+            for (Ref *r : {&s.x, &s.y, &s.z})
+                if (r->slot != kNone) v.push_back(&r->slot);
+        }
+        return v;
+    };
+    auto writes_of = [&](Step &s) {
+        std::vector<int32_t *> v;
+        if (s.kind == SK::Segment) {
+            for (int32_t &x : segs[(size_t)s.seg].outputs) v.push_back(&x);
+        } else if (s.kind == SK::Atoms) {
+            for (int j = 0; j < s.natoms; j++) v.push_back(&s.atoms[j].out);
+        } else if (s.out != kNone) {
+            v.push_back(&s.out);
+        }
+        return v;
+    };
 
     // liveness over SSA values, then greedy slot reuse; a span (a batched
     // group, or a concurrent region of labelling lanes) is allocated as one
     // step so that no member writes a slot another reads
     const int32_t nv = L.nssa;
     std::vector<int64_t> last(nv, -1);
-    for (size_t si = 0; si < L.steps.size(); si++) {
-        Step &s = L.steps[si];
-        for (Ref *r : {&s.x, &s.y, &s.z})
-            if (r->slot != kNone) last[(size_t)r->slot] = (int64_t)si;
-    }
+    for (size_t si = 0; si < L.steps.size(); si++)
+        for (int32_t *r : reads_of(L.steps[si])) last[(size_t)*r] = (int64_t)si;
     std::vector<int32_t> slot_of(nv, kNone);
     std::vector<int32_t> free_slots;
     int32_t nslots = 0;
@@ -1117,31 +1274,20 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int la
         if (L.steps[s0].span >= 0)
             while (s1 < L.steps.size() && L.steps[s1].span == L.steps[s0].span) s1++;
         std::vector<int32_t> outs;
-        for (size_t si = s0; si < s1; si++) {
-            Step &s = L.steps[si];
-            if (s.kind == SK::Atoms) {
-                for (int j = 0; j < s.natoms; j++) outs.push_back(s.atoms[j].out);
-            } else if (s.out != kNone) {
-                outs.push_back(s.out);
-            }
-        }
+        for (size_t si = s0; si < s1; si++)
+            for (int32_t *w : writes_of(L.steps[si])) outs.push_back(*w);
         for (int32_t v : outs) alloc(v);
         std::vector<int32_t> dying;
         for (size_t si = s0; si < s1; si++) {
             Step &s = L.steps[si];
-            for (Ref *r : {&s.x, &s.y, &s.z}) {
-                if (r->slot == kNone) continue;
-                int32_t v = r->slot;
+            for (int32_t *r : reads_of(s)) {
+                int32_t v = *r;
                 if (last[(size_t)v] >= (int64_t)s0 && last[(size_t)v] < (int64_t)s1 &&
                     std::find(dying.begin(), dying.end(), v) == dying.end())
                     dying.push_back(v);
-                r->slot = slot_of[(size_t)v];
+                *r = slot_of[(size_t)v];
             }
-            if (s.kind == SK::Atoms) {
-                for (int j = 0; j < s.natoms; j++) s.atoms[j].out = slot_of[(size_t)s.atoms[j].out];
-            } else if (s.out != kNone) {
-                s.out = slot_of[(size_t)s.out];
-            }
+            for (int32_t *w : writes_of(s)) *w = slot_of[(size_t)*w];
         }
         for (int32_t v : dying) release(v);
         for (int32_t v : outs)
@@ -1162,6 +1308,7 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int la
         P.ccl_lanes = std::max(P.ccl_lanes, st.lane + 1);
     }
     P.output_ids.assign(which.begin(), which.end());
+    P.segments = std::move(segs);
     return P;
 }
 

@@ -61,6 +61,25 @@ enum class SK : uint8_t {
     CclGather,  // out = (y & z) | (pixels of b = x whose component has a seed)
     CclReseed,  // mark the components of the current labelling that meet the
                 // seed mask x (= N(seeds) & b) for labelling user `user`
+    Segment,    // consecutive Logic/Near steps run by one tile kernel with a
+                // halo: Plan::segments[seg]
+};
+
+// A fused segment (see SegProg in kernels.h; same opcodes and operand rules):
+// inputs are loaded into registers first, members run in schedule order,
+// each result read after the segment (or requested as an output) is stored
+// right after it is computed.  Before slot allocation inputs/outputs hold SSA
+// values, afterwards mask slots.
+enum SegOpc : uint8_t { SOP_LOAD = 0, SOP_AND, SOP_OR, SOP_NEAR_AND, SOP_NEAR_OR, SOP_STORE };
+constexpr uint8_t kSegNoReg = 255;
+constexpr int kSegRegs = 16, kSegInstrs = 64, kSegPtrs = 32;
+struct SegInstr {
+    uint8_t op, dst, a, b, inv;  // LOAD: a = input index; STORE: dst = output index
+};
+struct Segment {
+    std::vector<int32_t> inputs, outputs;
+    std::vector<SegInstr> ins;
+    int32_t nregs = 0, halo = 0;
 };
 
 constexpr int kMaxAtoms = 32;
@@ -97,6 +116,7 @@ struct Step {
                           // lanes concurrently; -1: the main stream
     int32_t span = -1;    // consecutive steps with one span id are allocated
                           // mask slots as one step (batched group, region)
+    int32_t seg = -1;     // Segment: index into Plan::segments
 };
 
 // A labelling serves at most this many reach-type nodes with the same
@@ -115,6 +135,7 @@ struct Plan {
     int64_t ccl_reuse = 0;     // reach-type nodes served by an earlier labelling
     int32_t ccl_lanes = 1;     // labelling workspaces (concurrent labelling lanes)
     std::vector<int32_t> output_ids;  // formula output index per external slot
+    std::vector<Segment> segments;
 };
 
 // Build the schedule evaluating formula outputs `which` (indices into
@@ -122,8 +143,13 @@ struct Plan {
 // (fused mode) up to `lanes` independent labellings of one scheduling round
 // form a concurrent region, each on its own lane with its own labelling
 // workspace.
+// With fuse_halo >= 2 (fused mode) runs of consecutive Logic/Near steps
+// become segments whose deepest chain of near steps is at most fuse_halo;
+// fuse_halo <= 1 forms no segments.
 constexpr int kMaxCclLanes = 4;
-Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes = 1);
+constexpr int kFuseHaloDefault = 8;
+inline bool valid_fuse_halo(int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == 16; }
+Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes = 1, int fuse_halo = 1);
 
 // Number of reach/surrounded/grow nodes and of atoms.
 int64_t count_op(const Dag &dag, bool reach_like);

@@ -135,6 +135,47 @@ hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b, in
 hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *canon,
                              int32_t *labels);
 hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint8_t *out);
+
+// ------------------------------------------------------------------ segments
+// A segment: consecutive Boolean and near steps of the fused schedule run by
+// one kernel.  A workgroup takes a tile of TR rows x TW words of the image,
+// extended by `halo` rows above and below and one word left and right, and
+// keeps every mask of the segment for that extended tile in LDS registers:
+// operands from outside the segment are loaded once, results that are read
+// later are stored once, and everything else never leaves LDS.  After d near
+// steps along a path a register is exact except in its d outermost rows (and
+// the outermost d bits of the two halo words), so with halo >= the deepest
+// near chain the tile itself is exact.
+constexpr int kSegMaxIns = 64;
+constexpr int kSegMaxRegs = 16;
+constexpr int kSegMaxPtrs = 32;
+constexpr uint8_t kSegNone = 255;  // operand "no register": the all-zero mask
+enum SegOpcode : uint8_t { SEG_LOAD = 0, SEG_AND, SEG_OR, SEG_NEAR_AND, SEG_NEAR_OR, SEG_STORE };
+struct SegIns {
+    uint8_t op;
+    uint8_t dst;  // register; SEG_STORE: pointer index
+    uint8_t a;    // register (kSegNone: zero mask); SEG_LOAD: pointer index
+    uint8_t b;    // register or kSegNone
+    uint8_t inv;  // bit0 complements a, bit1 complements b, bit2 complements the
+                  // Boolean result (logic) or N(a) (near, before its epilogue)
+};
+// LOAD    dst = ptr[a]
+// AND/OR  dst = ((a ^ ia) OP (b ^ ib)) ^ io
+// NEAR_*  dst = (N(a ^ ia) ^ io) OP (b ^ ib)     (OP = and / or)
+// STORE   ptr[dst] = a ^ ia over the tile (padding bits cleared)
+// The leading LOADs of a program are issued together.
+struct SegProg {
+    int32_t nins, nregs, halo;
+    SegIns ins[kSegMaxIns];
+    uint64_t *ptr[kSegMaxPtrs];
+};
+// Tile shape of a segment on an image: TR rows x TW words.
+struct SegTile {
+    int tr, tw;
+    size_t lds_bytes;
+};
+SegTile seg_tile(const Geo &g, int halo, int nregs);
+hipError_t launch_segment(hipStream_t s, const Geo &g, const SegProg &p);
 hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v);
 
 

@@ -16,6 +16,8 @@
 // images of different sizes through per-image descriptors.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace vlg {
 namespace {
 
@@ -1368,6 +1370,85 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_reseed(BatchArgs a, BRef sm, 
 #undef VLG_BATCH_LOOP
 #undef VLG_BATCH_IMG
 
+// ------------------------------------------------------------------ segments
+// Register r of the extended tile is sreg[r * NI + i], i = row * RW + col,
+// with image row r0 + row and image word w0 + col.
+__global__ __launch_bounds__(kThreads) void k_segment(Geo g, SegProg p, int TR, int TW, int ntx) {
+    extern __shared__ uint64_t sreg[];
+    const int RR = TR + 2 * p.halo, RW = TW + 2, NI = RR * RW;
+    const int tx = (int)(blockIdx.x % ntx), ty = (int)(blockIdx.x / ntx);
+    const int r0 = ty * TR - p.halo, w0 = tx * TW - 1;
+    const int tid = (int)threadIdx.x;
+    // the leading loads, all in flight together
+    int nl = 0;
+    while (nl < p.nins && p.ins[nl].op == SEG_LOAD) nl++;
+    for (int i = tid; i < NI; i += kThreads) {
+        const int row = r0 + i / RW, w = w0 + i % RW;
+        const bool in = row >= 0 && row < g.H && w >= 0 && w < g.wpr;
+        const int64_t idx = in ? (int64_t)row * g.wpr + w : 0;
+        uint64_t v[kSegMaxRegs];
+#pragma unroll
+        for (int j = 0; j < kSegMaxRegs; j++)
+            if (j < nl) v[j] = in ? glb(p.ptr[p.ins[j].a])[idx] : 0ull;
+#pragma unroll
+        for (int j = 0; j < kSegMaxRegs; j++)
+            if (j < nl) sreg[p.ins[j].dst * NI + i] = v[j];
+    }
+    __syncthreads();
+    for (int k = nl; k < p.nins; k++) {
+        const SegIns in = p.ins[k];
+        const uint64_t ia = (in.inv & 1) ? ~0ull : 0ull, ib = (in.inv & 2) ? ~0ull : 0ull,
+                       io = (in.inv & 4) ? ~0ull : 0ull;
+        const uint64_t *A = in.a != kSegNone ? sreg + in.a * NI : nullptr;
+        const uint64_t *B = in.b != kSegNone ? sreg + in.b * NI : nullptr;
+        if (in.op == SEG_STORE) {
+            // every thread stores the register entries it owns (the same
+            // entries it writes in every other instruction), so a later
+            // instruction that reuses the register needs no barrier first
+            VLG_GLOBAL uint64_t *out = glb(p.ptr[in.dst]);
+            for (int i = tid; i < NI; i += kThreads) {
+                const int rr = i / RW, cc = i - rr * RW;
+                if (rr < p.halo || rr >= p.halo + TR || cc < 1 || cc > TW) continue;
+                const int row = r0 + rr, w = w0 + cc;
+                if (row >= g.H || w >= g.wpr) continue;
+                const uint64_t v = (A ? A[i] : 0ull) ^ ia;
+                out[(int64_t)row * g.wpr + w] = w == g.wpr - 1 ? (v & g.tail) : v;
+            }
+            continue;
+        }
+        uint64_t *D = sreg + in.dst * NI;
+        if (in.op == SEG_AND || in.op == SEG_OR) {
+            for (int i = tid; i < NI; i += kThreads) {
+                const uint64_t x = (A ? A[i] : 0ull) ^ ia, y = (B ? B[i] : 0ull) ^ ib;
+                D[i] = (in.op == SEG_OR ? (x | y) : (x & y)) ^ io;
+            }
+        } else {
+            // N over the image's pixels only: operand words outside the image
+            // and padding bits count as background
+            for (int i = tid; i < NI; i += kThreads) {
+                const int rr = i / RW, cc = i - rr * RW;
+                auto val = [&](int r, int c) -> uint64_t {
+                    const int row = r0 + r, w = w0 + c;
+                    if (r < 0 || r >= RR || c < 0 || c >= RW || row < 0 || row >= g.H || w < 0 || w >= g.wpr)
+                        return 0ull;
+                    const uint64_t v = (A ? A[r * RW + c] : 0ull) ^ ia;
+                    return w == g.wpr - 1 ? (v & g.tail) : v;
+                };
+                uint64_t n = 0;
+#pragma unroll
+                for (int dr = -1; dr <= 1; dr++) {
+                    const uint64_t c = val(rr + dr, cc), l = val(rr + dr, cc - 1), r = val(rr + dr, cc + 1);
+                    n |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
+                }
+                n ^= io;
+                const uint64_t z = (B ? B[i] : 0ull) ^ ib;
+                D[i] = in.op == SEG_NEAR_OR ? (n | z) : (n & z);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
 int ntiles_y(const Geo &g, int tbh) { return (g.BH + tbh - 1) / tbh; }
 
@@ -1424,6 +1505,7 @@ static hipError_t atoms_t(hipStream_t s, const Geo &g, const T *img, const AtomL
 hipError_t launch_atoms(hipStream_t s, const Geo &g, const void *chan, int dtype, const AtomLaunch &a) {
     if (g.nwords == 0) return hipSuccess;
     if (dtype == 1) return atoms_t(s, g, (const uint8_t *)chan, a);
+    if (dtype == 2) return atoms_t(s, g, (const uint16_t *)chan, a);
     return atoms_t(s, g, (const float *)chan, a);
 }
 
@@ -1511,6 +1593,43 @@ hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint
     return hipGetLastError();
 }
 
+// Tile of a segment: the shape with the least halo overhead among those that
+// fit the LDS budget and leave at least kMinSegTiles tiles (or the most tiles
+// when no shape leaves that many).
+constexpr size_t kSegLdsBudget = 48 * 1024;
+constexpr int64_t kMinSegTiles = 1024;
+SegTile seg_tile(const Geo &g, int halo, int nregs) {
+    SegTile best{4, 1, 0};
+    double best_score = -1.0;
+    for (int tw : {1, 2, 4, 8, 16}) {
+        if (tw > 1 && tw / 2 >= g.wpr) break;
+        for (int tr : {4, 8, 16, 32}) {
+            const size_t lds = (size_t)nregs * (tr + 2 * halo) * (tw + 2) * 8;
+            if (lds > kSegLdsBudget) continue;
+            const int64_t tiles = (int64_t)((g.H + tr - 1) / tr) * ((g.wpr + tw - 1) / tw);
+            const double eff = (double)tr * tw / ((double)(tr + 2 * halo) * (tw + 2));
+            const double score = eff * std::min(1.0, (double)tiles / kMinSegTiles);
+            if (score > best_score) {
+                best_score = score;
+                best = SegTile{tr, tw, lds};
+            }
+        }
+    }
+    if (best.lds_bytes == 0) best.lds_bytes = (size_t)nregs * (best.tr + 2 * halo) * (best.tw + 2) * 8;
+    return best;
+}
+
+hipError_t launch_segment(hipStream_t s, const Geo &g, const SegProg &p) {
+    if (g.nwords == 0) return hipSuccess;
+    if (p.nins < 1 || p.nins > kSegMaxIns || p.nregs < 1 || p.nregs > kSegMaxRegs || p.halo < 0 || p.halo > 32)
+        return hipErrorInvalidValue;
+    const SegTile t = seg_tile(g, p.halo, p.nregs);
+    if (t.lds_bytes > kSegLdsBudget) return hipErrorInvalidValue;
+    const int ntx = (g.wpr + t.tw - 1) / t.tw, nty = (g.H + t.tr - 1) / t.tr;
+    k_segment<<<ntx * nty, kThreads, t.lds_bytes, s>>>(g, p, t.tr, t.tw, ntx);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v) {
     k_fill_i64<<<(n + 255) / 256, 256, 0, s>>>(p, n, v);
     return hipGetLastError();
@@ -1548,11 +1667,14 @@ hipError_t launch_b_atoms(hipStream_t s, const BatchArgs &a, int64_t total, cons
     if (total == 0) return hipSuccess;
     if (op.n < 1 || op.n > kMaxAtomsPerLaunch) return hipErrorInvalidValue;
     // a unit is 256 words: 16384 channel elements in, 256 words out per atom
-    const int64_t bytes = total * (16384 * (a.dtype == 1 ? 1 : 4) + op.n * 256 * 8);
+    const int64_t bytes = total * (16384 * (a.dtype == 1 ? 1 : a.dtype == 2 ? 2 : 4) + op.n * 256 * 8);
     const int grid = persistent_grid(a, total);
     if (a.dtype == 1) {
         if (bytes > kStreamBytes) kb_atoms<uint8_t, true><<<grid, kThreads, 0, s>>>(a, op);
         else kb_atoms<uint8_t, false><<<grid, kThreads, 0, s>>>(a, op);
+    } else if (a.dtype == 2) {
+        if (bytes > kStreamBytes) kb_atoms<uint16_t, true><<<grid, kThreads, 0, s>>>(a, op);
+        else kb_atoms<uint16_t, false><<<grid, kThreads, 0, s>>>(a, op);
     } else {
         if (bytes > kStreamBytes) kb_atoms<float, true><<<grid, kThreads, 0, s>>>(a, op);
         else kb_atoms<float, false><<<grid, kThreads, 0, s>>>(a, op);
@@ -1657,6 +1779,7 @@ __device__ void pct_init_wg(PctState *st_, uint32_t k) {
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct Vec4<uint8_t> { typedef uint8_t type __attribute__((ext_vector_type(4))); };
+template <> struct Vec4<uint16_t> { typedef uint16_t type __attribute__((ext_vector_type(4))); };
 
 // Histogram the channel elements of the chunks [c, c + 1024) for c = i0,
 // i0 + stride, ... below i1 (a channel is stored with pitch wpr*64; i0,
@@ -1691,7 +1814,7 @@ __device__ __forceinline__ void pct_hist_stream(const Geo &g, const T *__restric
             const float f[4] = {(float)v[u].x, (float)v[u].y, (float)v[u].z, (float)v[u].w};
             uint32_t key[4];
 #pragma unroll
-            for (int e = 0; e < 4; e++) key[e] = sizeof(T) == 1 ? (uint32_t)f[e] : f32_key(f[e]);
+            for (int e = 0; e < 4; e++) key[e] = sizeof(T) < 4 ? (uint32_t)f[e] : f32_key(f[e]);
             // the groups of a pass share the digit mask and differ in prefix,
             // so an element belongs to at most one of them
             uint32_t bin[4];
@@ -1767,7 +1890,7 @@ __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState
 }
 
 // one workgroup of 256 threads: find the bucket holding rank k
-__device__ void pct_select_wg(PctState *st_, int shift, int bins, int last, int is_u8, float *result_,
+__device__ void pct_select_wg(PctState *st_, int shift, int bins, int last, int is_int, float *result_,
                               uint32_t *part) {
     VLG_GLOBAL PctState *st = glb(st_);
     VLG_GLOBAL float *result = glb(result_);
@@ -1785,7 +1908,7 @@ __device__ void pct_select_wg(PctState *st_, int shift, int bins, int last, int 
         st->k = k - acc;
         st->prefix |= (uint32_t)b << shift;
         st->mask |= (uint32_t)(bins - 1) << shift;
-        if (last) *result = is_u8 ? (float)st->prefix : key_f32(st->prefix);
+        if (last) *result = is_int ? (float)st->prefix : key_f32(st->prefix);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 2048; i += kThreads) st->hist[i] = 0;
@@ -1810,10 +1933,10 @@ __global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restric
 }
 
 __global__ __launch_bounds__(kThreads) void k_pct_select(PctSel sel, void *states, int shift, int bins, int last,
-                                                         int is_u8, float *results) {
+                                                         int is_int, float *results) {
     __shared__ uint32_t part[kThreads];
     const int slot = sel.slot[blockIdx.x];
-    pct_select_wg(sstate(states, slot), shift, bins, last, is_u8, results + slot, part);
+    pct_select_wg(sstate(states, slot), shift, bins, last, is_int, results + slot, part);
 }
 
 // batch variants: state and result of percentile slot p live in each image's workspace
@@ -1850,14 +1973,14 @@ __global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, P
 }
 
 __global__ __launch_bounds__(kThreads) void kb_pct_select(BatchArgs a, PctSel sel, int shift, int bins, int last,
-                                                          int is_u8) {
+                                                          int is_int) {
     __shared__ uint32_t part[kThreads];
     const int slot = sel.slot[blockIdx.y];
     UnitRange ur(a.prefix, a.n);
     for (int64_t u = ur.begin; u < ur.end; u++) {
         const int ii = ur.img(u);
         const BImg d = a.imgs[ii];  // by value (see UnitRange)
-        pct_select_wg(bstate(d, slot), shift, bins, last, is_u8, (float *)(d.ws + d.off_pct) + slot, part);
+        pct_select_wg(bstate(d, slot), shift, bins, last, is_int, (float *)(d.ws + d.off_pct) + slot, part);
     }
 }
 
@@ -1874,6 +1997,16 @@ hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int 
         if (n > kStreamBytes) k_pct_hist<uint8_t, true><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
         else k_pct_hist<uint8_t, false><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
         k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, 0, 256, 1, 1, results);
+        return hipGetLastError();
+    }
+    if (dtype == 2) {  // uint16: two 8-bit digits
+        for (int p = 0; p < 2; p++) {
+            if (2 * n > kStreamBytes)
+                k_pct_hist<uint16_t, true><<<grid, kThreads, 0, s>>>(g, (const uint16_t *)chan, sel, states, 8 - 8 * p, 256);
+            else
+                k_pct_hist<uint16_t, false><<<grid, kThreads, 0, s>>>(g, (const uint16_t *)chan, sel, states, 8 - 8 * p, 256);
+            k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, 8 - 8 * p, 256, p == 1, 1, results);
+        }
         return hipGetLastError();
     }
     const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
@@ -1895,11 +2028,19 @@ hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t tota
     kb_pct_init<<<g1, kThreads, 0, s>>>(one, sel);
     dim3 gs(g1, sel.n);
     // a histogram unit is kPctUnit channel elements
-    const bool nt = total_hist * kPctUnit * (hist.dtype == 1 ? 1 : 4) > kStreamBytes;
+    const bool nt = total_hist * kPctUnit * (hist.dtype == 1 ? 1 : hist.dtype == 2 ? 2 : 4) > kStreamBytes;
     if (hist.dtype == 1) {
         if (nt) kb_pct_hist<uint8_t, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
         else kb_pct_hist<uint8_t, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
         kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, 0, 256, 1, 1);
+        return hipGetLastError();
+    }
+    if (hist.dtype == 2) {  // uint16: two 8-bit digits
+        for (int p = 0; p < 2; p++) {
+            if (nt) kb_pct_hist<uint16_t, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, 8 - 8 * p, 256);
+            else kb_pct_hist<uint16_t, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, 8 - 8 * p, 256);
+            kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, 8 - 8 * p, 256, p == 1, 1);
+        }
         return hipGetLastError();
     }
     const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};

@@ -307,3 +307,64 @@ def test_ccl_lanes_opt_in(ctx, lanes):
                 assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"lanes={lanes} {mode}")
     finally:
         vlg.set_tunable(ctx, "ccl_lanes", 0)
+
+
+@pytest.mark.parametrize("halo", [1, 2, 4, 8, 16])
+def test_fused_segments_every_halo_cap(ctx, halo):
+    # fused segments (runs of Boolean and near steps in one tile kernel) at
+    # every halo cap: deep near chains, complements, ragged sizes around the
+    # word and the tile, and the small chain workload
+    import paper_2010_07284_amd as vlg
+    rng = np.random.default_rng(halo)
+    deep = ops_src(rng) + 'output "deep" near(near(near(near(near(A) & B) | C) & !D) | interior(interior(B)))\n'
+    cases = [(deep, rng.random((2, 97, 301)).astype(np.float32)),
+             (deep, rng.random((2, 3, 65)).astype(np.float32)),
+             (formulas.chain_dag(3, n_chain=300, n_reach=15), images.random_mask_image(3, 300)),
+             (formulas.random_dag(7, n_nodes=120, n_reach=4, channels=2),
+              rng.random((2, 517, 389)).astype(np.float32))]
+    vlg.set_tunable(ctx, "fuse_halo", halo)
+    try:
+        for src, img in cases:
+            want = oracle.run(src, img)
+            for mode in ("fused", "graph"):
+                assert_same(src, img, gpu_run(ctx, src, img, mode), want, tag=f"halo={halo} {mode} {img.shape}")
+    finally:
+        vlg.set_tunable(ctx, "fuse_halo", 0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("h,w", [(1, 70), (37, 129), (300, 257)])
+def test_uint16_images(ctx, mode, h, w):
+    # the paper's pixel type: atoms of every comparison at uint16 thresholds
+    # and between them, two-pass percentiles, the grow specification
+    rng = np.random.default_rng(h + 3 * w)
+    img = rng.integers(0, 65536, (2, h, w), dtype=np.uint16)
+    img[0, 0, : min(w, 5)] = 62258  # ties with the threshold
+    img[1, -1, :3] = 56360
+    src = ("let hI = intensity(img) >. 62258\n"
+           "let vI = intensity(img) >. 56360\n"
+           'output "grow" grow(hI, vI)\n'
+           'output "ge" intensity(img, 1) >=. 56360\n'
+           'output "le" intensity(img, 1) <=. 1000.5\n'
+           'output "pct" intensity(img, 0) >. percentile(img, 0, 0.95)\n'
+           'output "pct1" intensity(img, 1) <. percentile(img, 1, 0.86)\n'
+           'output "mix" near(intensity(img, 0) <. percentile(img, 1, 0.3)) & !vI\n')
+    assert_same(src, img, gpu_run(ctx, src, img, mode), tag=f"u16 {h}x{w} {mode}")
+
+
+def test_uint16_batch(ctx):
+    import paper_2010_07284_amd as vlg
+    rng = np.random.default_rng(16)
+    imgs = [rng.integers(0, 65536, (1, h, w), dtype=np.uint16) for h, w in [(64, 64), (130, 77), (300, 513)]]
+    src = formulas.GROW_SPEC.format(hi=62258, lo=56360) + 'output "p" intensity(img) >. percentile(img, 0, 0.86)\n'
+    f = vlg.compile_formula(ctx, src)
+    ims = [vlg.load_image(ctx, im) for im in imgs]
+    for mode in ("fused", "graph"):
+        vlg.set_mode(ctx, mode)
+        outs = vlg.check_batch(ctx, f, ims)
+        vlg.sync(ctx)
+        for im, row in zip(imgs, outs):
+            want = oracle.run(src, im)
+            H, W = im.shape[1:]
+            for k, (o, wm) in enumerate(zip(row, want)):
+                assert np.array_equal(vlg.unpack(o, H, W), wm), (im.shape, k, mode)
