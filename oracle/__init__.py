@@ -41,6 +41,8 @@ def _load(path=None):
         fn.argtypes = [P, P, I, I, P]
     L.oracle_interior.argtypes = [P, I, I, P]
     L.oracle_ccl.argtypes = [P, I, I, P]
+    L.oracle_ccl_max.argtypes = [P, I, I, P]
+    L.oracle_ccl_pj.argtypes = [P, I, I, I, I, P, ctypes.POINTER(I64)]
     L.oracle_percentile.argtypes = [P, I, I, I, I, I, D, ctypes.POINTER(F)]
     L.oracle_threshold.argtypes = [P, I, I, I, I, I, I, F, P]
     return L
@@ -164,6 +166,30 @@ def ccl(a):
     if rc < 0:
         raise OracleError(f"oracle error {rc}")
     return lab
+
+
+def ccl_max(a):
+    """8-connected labels of the paper's labelling once terminated: label =
+    largest row-major index in the component, -1 = background."""
+    a = _mask(a)
+    lab = np.zeros(a.shape, np.int32)
+    rc = lib().oracle_ccl_max(_ptr(a), a.shape[0], a.shape[1], _ptr(lab))
+    if rc < 0:
+        raise OracleError(f"oracle error {rc}")
+    return lab
+
+
+def ccl_pj(a, k=16, max_rounds=100000):
+    """The paper's labelling algorithm (Alg. CCL) run step by step: returns
+    (labels as in ccl_max, number of main iterations).  Raises OracleError
+    when the termination check still fails after max_rounds rounds."""
+    a = _mask(a)
+    lab = np.zeros(a.shape, np.int32)
+    it = ctypes.c_int64()
+    rc = lib().oracle_ccl_pj(_ptr(a), a.shape[0], a.shape[1], k, max_rounds, _ptr(lab), ctypes.byref(it))
+    if rc < 0:
+        raise OracleError(f"oracle error {rc} after {it.value} main iterations")
+    return lab, it.value
 
 
 def percentile(img, c, q):

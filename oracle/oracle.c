@@ -241,6 +241,191 @@ int oracle_ccl(const uint8_t *a, int H, int W, int32_t *lab)
     return ORC_OK;
 }
 
+/* Labels of the paper's own labelling algorithm once it has terminated
+ * (Sect. 3, Alg. CCL): every pixel of a component carries the largest
+ * coordinate pair of the component in lexicographic order, null elsewhere.
+ * Coordinates are read as (row, column), so the order is the row-major
+ * linear order and the label is written as the linear index y*W+x of the
+ * component's last pixel in raster order; background pixels get -1.
+ * Plain definition: a flood from each unlabelled pixel in reverse raster
+ * order, so the flood's first pixel is the component's largest. */
+int oracle_ccl_max(const uint8_t *a, int H, int W, int32_t *lab)
+{
+    int64_t n = (int64_t)H * W;
+    if (n == 0)
+        return ORC_OK;
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!queue)
+        return ORC_ENOMEM;
+    for (int64_t p = 0; p < n; p++)
+        lab[p] = -1;
+    for (int64_t s = n - 1; s >= 0; s--) {
+        if (!a[s] || lab[s] >= 0)
+            continue;
+        int64_t head = 0, tail = 0;
+        lab[s] = (int32_t)s;
+        queue[tail++] = s;
+        while (head < tail) {
+            int64_t p = queue[head++];
+            int y = (int)(p / W), x = (int)(p % W);
+            for (int dy = -1; dy <= 1; dy++) {
+                for (int dx = -1; dx <= 1; dx++) {
+                    int yy = y + dy, xx = x + dx;
+                    if (yy < 0 || yy >= H || xx < 0 || xx >= W)
+                        continue;
+                    int64_t q = (int64_t)yy * W + xx;
+                    if (a[q] && lab[q] < 0) {
+                        lab[q] = lab[s]; /* the flood's first pixel */
+                        queue[tail++] = q;
+                    }
+                }
+            }
+        }
+    }
+    free(queue);
+    return ORC_OK;
+}
+
+/* ---- The paper's labelling algorithm, step by step (Sect. 3, Alg. CCL) ----
+ *
+ * Labels are coordinate pairs (i, j) = (row, column), compared
+ * lexicographically; null (a background pixel) is below every pair.
+ *   initialization: a pixel of `start` is labelled with its own coordinates.
+ *   mainIteration:  a pixel of `start` holding (i', j') takes the largest
+ *                   label in the Moore neighbourhood of (i', j') (that pixel
+ *                   included) of the input labels; pointer jumping.
+ *   reconnect:      a pixel of `start` at (i, j) holding (i', j') compares
+ *                   the largest label (a, b) around (i, j) with the label
+ *                   (c, d) stored at (i', j'); if (a, b) is larger it is
+ *                   written at (i', j').  The paper asks for an atomic write
+ *                   there without saying which of several writers wins;
+ *                   read as an atomic maximum over the writers, into a copy
+ *                   of the input labels (so the step reads only its input).
+ *   termination:    done when no pixel of `start` has a neighbour of
+ *                   `start` with a different label.
+ * Schedule: after initialization, rounds of k main iterations, one
+ * reconnect, then the termination check, until it reports done (Fig.
+ * cc-movie: reconnect every 8 main iterations, termination after 24).
+ * *iterations receives the number of main iterations.  At most max_rounds
+ * rounds; if the check still fails, returns -6. */
+typedef struct {
+    int32_t i, j; /* i = -1: null */
+} PjLabel;
+
+static int pj_greater(PjLabel x, PjLabel y)
+{
+    return x.i > y.i || (x.i == y.i && x.j > y.j);
+}
+
+static PjLabel pj_max_neighbour(const PjLabel *in, int H, int W, int i, int j)
+{
+    PjLabel m = {-1, -1};
+    for (int di = -1; di <= 1; di++) {
+        for (int dj = -1; dj <= 1; dj++) {
+            int ii = i + di, jj = j + dj;
+            if (ii < 0 || ii >= H || jj < 0 || jj >= W)
+                continue;
+            PjLabel v = in[(int64_t)ii * W + jj];
+            if (pj_greater(v, m))
+                m = v;
+        }
+    }
+    return m;
+}
+
+int oracle_ccl_pj(const uint8_t *start, int H, int W, int k, int max_rounds, int32_t *lab,
+                  int64_t *iterations)
+{
+    int64_t n = (int64_t)H * W;
+    *iterations = 0;
+    if (k < 1 || max_rounds < 1)
+        return ORC_EINVAL;
+    if (n == 0)
+        return ORC_OK;
+    PjLabel *A = (PjLabel *)malloc((size_t)n * sizeof(PjLabel));
+    PjLabel *B = (PjLabel *)malloc((size_t)n * sizeof(PjLabel));
+    if (!A || !B) {
+        free(A);
+        free(B);
+        return ORC_ENOMEM;
+    }
+    /* initialization */
+    for (int i = 0; i < H; i++) {
+        for (int j = 0; j < W; j++) {
+            PjLabel v = {-1, -1};
+            if (start[(int64_t)i * W + j]) {
+                v.i = i;
+                v.j = j;
+            }
+            A[(int64_t)i * W + j] = v;
+            B[(int64_t)i * W + j] = v;
+        }
+    }
+    int done = 0;
+    for (int round = 0; round < max_rounds && !done; round++) {
+        /* k main iterations, input A -> output B, then swap */
+        for (int it = 0; it < k; it++) {
+            for (int i = 0; i < H; i++) {
+                for (int j = 0; j < W; j++) {
+                    int64_t p = (int64_t)i * W + j;
+                    if (!start[p])
+                        continue;
+                    PjLabel ij = A[p];
+                    B[p] = pj_max_neighbour(A, H, W, ij.i, ij.j);
+                }
+            }
+            PjLabel *t = A;
+            A = B;
+            B = t;
+            (*iterations)++;
+        }
+        /* reconnect: input A, output B = copy of A raised by atomic maxima */
+        memcpy(B, A, (size_t)n * sizeof(PjLabel));
+        for (int i = 0; i < H; i++) {
+            for (int j = 0; j < W; j++) {
+                int64_t p = (int64_t)i * W + j;
+                if (!start[p])
+                    continue;
+                PjLabel ij = A[p];
+                PjLabel ab = pj_max_neighbour(A, H, W, i, j);
+                int64_t q = (int64_t)ij.i * W + ij.j;
+                PjLabel cd = A[q];
+                if (pj_greater(ab, cd) && pj_greater(ab, B[q]))
+                    B[q] = ab;
+            }
+        }
+        PjLabel *t = A;
+        A = B;
+        B = t;
+        /* termination check on the labels after the reconnect */
+        done = 1;
+        for (int i = 0; i < H && done; i++) {
+            for (int j = 0; j < W && done; j++) {
+                int64_t p = (int64_t)i * W + j;
+                if (!start[p])
+                    continue;
+                for (int di = -1; di <= 1 && done; di++) {
+                    for (int dj = -1; dj <= 1; dj++) {
+                        int ii = i + di, jj = j + dj;
+                        if (ii < 0 || ii >= H || jj < 0 || jj >= W)
+                            continue;
+                        int64_t q = (int64_t)ii * W + jj;
+                        if (start[q] && (A[q].i != A[p].i || A[q].j != A[p].j)) {
+                            done = 0;
+                            break;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t p = 0; p < n; p++)
+        lab[p] = A[p].i < 0 ? -1 : (int32_t)((int64_t)A[p].i * W + A[p].j);
+    free(A);
+    free(B);
+    return done ? ORC_OK : -6;
+}
+
 static float pixel_value(const void *img, int dtype, int64_t idx)
 {
     if (dtype == DT_U8)

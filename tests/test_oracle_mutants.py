@@ -37,6 +37,13 @@ MUTANTS = {
                            'while (!P->failed && accept(P, "|")) {'),
     "threshold_constant_rounded_down": ("n->thr = (float)(neg ? -v : v);",
                                         "n->thr = nextafterf((float)(neg ? -v : v), 0.0f);"),
+    "ccl_max_scans_forward": ("for (int64_t s = n - 1; s >= 0; s--) {\n        if (!a[s] || lab[s] >= 0)",
+                              "for (int64_t s = 0; s < n; s++) {\n        if (!a[s] || lab[s] >= 0)"),
+    "pj_main_looks_around_the_pixel": ("B[p] = pj_max_neighbour(A, H, W, ij.i, ij.j);",
+                                       "B[p] = pj_max_neighbour(A, H, W, i, j);"),
+    "pj_reconnect_writes_the_pixel": ("                    B[q] = ab;", "                    B[p] = ab;"),
+    "pj_lexicographic_order_swapped": ("return x.i > y.i || (x.i == y.i && x.j > y.j);",
+                                       "return x.j > y.j || (x.j == y.j && x.i > y.i);"),
 }
 
 

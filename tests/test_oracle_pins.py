@@ -322,6 +322,101 @@ def test_ccl_concave_corner_is_one_component():
     assert set(lab[a > 0].tolist()) == {1 * 4 + 1}
 
 
+# ------------------------------------- the paper's labelling (Sect. 3, Alg. CCL)
+
+def scipy_max_labels(a):
+    """Largest row-major index of each 8-component (scipy's partition)."""
+    h, w = a.shape
+    ref, n = ndimage.label(a, structure=K3)
+    idx = np.arange(h * w).reshape(h, w)
+    out = np.full((h, w), -1, np.int32)
+    if n:
+        mx = ndimage.maximum(idx, labels=ref, index=np.arange(1, n + 1))
+        for c in range(1, n + 1):
+            out[ref == c] = int(mx[c - 1])
+    return out
+
+
+def test_ccl_max_is_the_largest_index_of_the_component():
+    rng = np.random.default_rng(21)
+    for h, w in [(1, 1), (1, 40), (40, 1), (7, 9), (64, 64), (33, 129)]:
+        for p in (0.2, 0.45, 0.6):
+            a = rand_mask(rng, h, w, p)
+            assert np.array_equal(oracle.ccl_max(a), scipy_max_labels(a))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 16])
+def test_ccl_pj_terminates_with_the_largest_label(k):
+    # the paper: the algorithm exits only when every component is labelled
+    # uniformly, and a label always lies in the pixel's own component, so
+    # the final label of a component is its largest coordinate pair
+    rng = np.random.default_rng(22 + k)
+    cases = [rand_mask(rng, h, w, p) for h, w in [(1, 1), (5, 5), (17, 23), (48, 40)] for p in (0.3, 0.5, 0.7)]
+    from synth import images
+    cases.append(images.serpentine_maze(21, 14).astype(np.uint8))
+    cases.append(np.ones((9, 11), np.uint8))
+    for a in cases:
+        lab, iters = oracle.ccl_pj(a, k=k)
+        assert np.array_equal(lab, scipy_max_labels(a))
+        assert iters % k == 0 and iters >= k
+
+
+def test_ccl_pj_line_doubles_per_iteration():
+    # on a straight line of n pixels, max-neighbour pointer jumping gives the
+    # pixel at offset x the label min(x + 2^t - 1, n - 1) after t main
+    # iterations, and reconnect never fires (the largest label around x is
+    # never above the label stored at x's target); so the check first passes
+    # at the end of the round in which t reaches ceil(log2 n)
+    for n in range(1, 70):
+        t = int(np.ceil(np.log2(n))) if n > 1 else 0
+        for k in (1, 2, 3, 5, 8):
+            want = k * max(1, -(-t // k))
+            for a in (np.ones((1, n), np.uint8), np.ones((n, 1), np.uint8), np.eye(n, dtype=np.uint8)):
+                lab, iters = oracle.ccl_pj(a, k=k)
+                assert iters == want, (n, k, a.shape)
+                assert np.all(lab[a > 0] == np.flatnonzero(a.reshape(-1))[-1])
+
+
+def test_ccl_pj_hand_traced_turn():
+    # rows 1111 / 0001 / 1111, one reconnect per main iteration (k = 1);
+    # traced by hand: after iteration 1 the top row holds (0,1) (0,2) (1,3)
+    # (1,3); after iteration 2 it holds (1,3) (2,3) (2,3) (2,3) and every
+    # other pixel (2,3); reconnect changes nothing on the way and iteration 3
+    # labels everything (2,3), so the check passes after 3 main iterations
+    a = np.array([[1, 1, 1, 1], [0, 0, 0, 1], [1, 1, 1, 1]], np.uint8)
+    lab, iters = oracle.ccl_pj(a, k=1)
+    assert iters == 3
+    assert np.all(lab[a > 0] == 2 * 4 + 3)
+
+
+def test_ccl_pj_hand_traced_reconnect_target():
+    # rows 111 / 101 / 001, k = 1, traced by hand.  Iteration 1 labels
+    # (0,0)->(1,0), (0,1)->(1,2), (0,2)->(1,2), (1,0)->(1,0), (1,2)->(2,2),
+    # (2,2)->(2,2).  Reconnect: pixel (0,0) points at (1,0) and sees (1,2)
+    # around itself, larger than the (1,0) stored at (1,0), so (1,2) is
+    # written at (1,0) -- the pointed-at pixel, not (0,0).  Iteration 2 then
+    # leaves (0,0) at (1,2) and everything else at (2,2); iteration 3 ends it
+    a = np.array([[1, 1, 1], [1, 0, 1], [0, 0, 1]], np.uint8)
+    lab, iters = oracle.ccl_pj(a, k=1)
+    assert iters == 3
+    assert np.all(lab[a > 0] == 2 * 3 + 2)
+
+
+def test_ccl_pj_needs_reconnect():
+    # rows 1111 / 0001 / 1111 / 1000 / 1111: row 2 runs into row 4 at its
+    # left end.  Pixels (1,3), (2,2), (2,3) and the top row point at (2,3),
+    # whose neighbourhood never holds a larger label, so main iterations
+    # alone settle with two labels; the first reconnect writes (4,3) at
+    # (2,3) (from pixel (2,2), whose neighbour (2,1) already holds (4,3)),
+    # which the check right after it still sees unpropagated; the second
+    # round finishes
+    a = np.array([[1, 1, 1, 1], [0, 0, 0, 1], [1, 1, 1, 1], [1, 0, 0, 0], [1, 1, 1, 1]], np.uint8)
+    with pytest.raises(oracle.OracleError):
+        oracle.ccl_pj(a, k=64, max_rounds=1)
+    lab, iters = oracle.ccl_pj(a, k=64, max_rounds=2)
+    assert iters == 128 and np.all(lab[a > 0] == 4 * 4 + 3)
+
+
 # ---------------------------------------------------------------- language
 
 def test_macros_let_and_sharing():
