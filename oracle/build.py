@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 def build(out=LIB_PATH, src=SRC, extra=()):
     """Compile `src` to the shared library `out` (always recompiles)."""
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
+    # float arithmetic exactly as written: one rounding per operation
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra", "-fPIC", "-shared",
            *extra, "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)

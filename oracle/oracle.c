@@ -504,12 +504,24 @@ int oracle_threshold(const void *img, int dtype, int C, int H, int W, int c, int
 /*   CMP := '>.' | '<.' | '>=.' | '<=.'                                */
 /*   scalar := ['-'] NUMBER | 'percentile' '(' 'img' ',' INT ',' NUMBER ')' */
 /*   built-ins: near(e) N(e) interior(e) reach(a,b) surrounded(a,b)    */
-/*              grow(a,b); comments run from '//' to end of line.      */
+/*              grow(a,b) touch(a,b); comments run from '//' to end of */
+/*              line.                                                  */
+/*   Arithmetic atoms (Sect. 3: the tool's built-in arithmetic):       */
+/*   prim := num CMP num    (any atom that is not the form above)      */
+/*   num := term { ('+' | '-') term }   term := fac { ('*' | '/') fac } */
+/*   fac := '-' fac | NUMBER | 'intensity' '(' 'img' [',' INT] ')'      */
+/*        | 'percentile' '(' 'img' ',' INT ',' NUMBER ')'               */
+/*        | 'abs' '(' num ')' | ('min' | 'max') '(' num ',' num ')'     */
+/*        | '(' num ')'                                                 */
 /* ------------------------------------------------------------------ */
 
 enum {
     K_TRUE, K_FALSE, K_ATOM, K_NOT, K_AND, K_OR, K_NEAR, K_INTERIOR,
-    K_REACH, K_SURR, K_GROW, K_GLOBAL, K_PARAM, K_CALL
+    K_REACH, K_SURR, K_GROW, K_GLOBAL, K_PARAM, K_CALL, K_TOUCH,
+    K_ARITH, /* atom a CMP b over numeric expressions a, b */
+    /* numeric expression nodes (values per pixel, float32) */
+    K_N_CONST, K_N_CHAN, K_N_PCT, K_N_NEG, K_N_ABS, K_N_ADD, K_N_SUB, K_N_MUL, K_N_DIV,
+    K_N_MIN, K_N_MAX
 };
 
 typedef struct Node {
@@ -645,18 +657,6 @@ static int read_ident(Parser *P, char *out, size_t outlen)
     return 1;
 }
 
-/* peek an identifier without consuming it */
-static int peek_ident(Parser *P, char *out, size_t outlen)
-{
-    size_t pos = P->pos;
-    int line = P->line, col = P->col;
-    int ok = read_ident(P, out, outlen);
-    P->pos = pos;
-    P->line = line;
-    P->col = col;
-    return ok;
-}
-
 static int read_number(Parser *P, double *v)
 {
     skip_ws(P);
@@ -716,7 +716,7 @@ static int is_builtin(const char *s)
 {
     static const char *names[] = {"let", "output", "true", "false", "intensity", "percentile",
                                   "img", "near", "N", "interior", "reach", "surrounded",
-                                  "grow", NULL};
+                                  "grow", "touch", "abs", "min", "max", NULL};
     for (int i = 0; names[i]; i++)
         if (strcmp(s, names[i]) == 0)
             return 1;
@@ -741,48 +741,183 @@ static void parse_img_channel(Parser *P, int *chan, int allow_default)
     }
 }
 
-static Node *parse_atom(Parser *P)
+/* ---- arithmetic atoms ----
+ * Numeric expressions are parsed speculatively: where the text at this point
+ * is a numeric expression followed by a comparison, it is an arithmetic
+ * atom; otherwise the parser backs up and reads a Boolean expression.  A
+ * numeric parse fails quietly (NULL) on anything that is not numeric. */
+static int peek_cmp(Parser *P)
 {
-    Node *n = new_node(P, K_ATOM);
-    if (!n)
+    skip_ws(P);
+    const char *t = P->src + P->pos;
+    return strncmp(t, ">=.", 3) == 0 || strncmp(t, "<=.", 3) == 0 || strncmp(t, ">.", 2) == 0 ||
+           strncmp(t, "<.", 2) == 0;
+}
+
+static Node *parse_num(Parser *P);
+
+static Node *num_node(Parser *P, int kind, Node *a, Node *b)
+{
+    Node *n = new_node(P, kind);
+    if (n) {
+        n->a = a;
+        n->b = b;
+    }
+    return n;
+}
+
+static Node *parse_num_factor(Parser *P)
+{
+    if (P->failed)
         return NULL;
-    expect(P, "(");
-    parse_img_channel(P, &n->chan, 1);
-    expect(P, ")");
-    if (accept(P, ">=."))
-        n->cmp = CMP_GE;
-    else if (accept(P, "<=."))
-        n->cmp = CMP_LE;
-    else if (accept(P, ">."))
-        n->cmp = CMP_GT;
-    else if (accept(P, "<."))
-        n->cmp = CMP_LT;
-    else {
-        perr(P, "expected a comparison '>.', '<.', '>=.' or '<=.'");
+    if (accept(P, "-")) {
+        Node *a = parse_num_factor(P);
+        return a ? num_node(P, K_N_NEG, a, NULL) : NULL;
+    }
+    if (accept(P, "(")) {
+        Node *a = parse_num(P);
+        if (!a || !accept(P, ")"))
+            return NULL;
+        return a;
+    }
+    double v;
+    if (read_number(P, &v)) {
+        Node *n = new_node(P, K_N_CONST);
+        if (n)
+            n->thr = (float)v; /* read as double, rounded once to float32 */
         return n;
     }
     char id[64];
-    if (peek_ident(P, id, sizeof id)) {
-        if (strcmp(id, "percentile") != 0) {
-            perr(P, "expected a number or percentile(...)");
-            return n;
-        }
-        read_ident(P, id, sizeof id);
-        expect(P, "(");
+    if (!read_ident(P, id, sizeof id))
+        return NULL;
+    if (strcmp(id, "intensity") == 0) {
+        Node *n = new_node(P, K_N_CHAN);
+        if (!n || !accept(P, "("))
+            return NULL;
+        parse_img_channel(P, &n->chan, 1);
+        return (!P->failed && accept(P, ")")) ? n : NULL;
+    }
+    if (strcmp(id, "percentile") == 0) {
+        Node *n = new_node(P, K_N_PCT);
+        if (!n || !accept(P, "("))
+            return NULL;
         parse_img_channel(P, &n->pchan, 0);
-        expect(P, ",");
-        if (!read_number(P, &n->pq))
-            perr(P, "expected a percentile fraction");
-        expect(P, ")");
-        n->use_pct = 1;
-    } else {
-        int neg = accept(P, "-");
-        double v;
-        if (!read_number(P, &v)) {
-            perr(P, "expected a number");
-            return n;
+        if (P->failed || !accept(P, ",") || !read_number(P, &n->pq) || !accept(P, ")"))
+            return NULL;
+        return n;
+    }
+    if (strcmp(id, "abs") == 0) {
+        if (!accept(P, "("))
+            return NULL;
+        Node *a = parse_num(P);
+        if (!a || !accept(P, ")"))
+            return NULL;
+        return num_node(P, K_N_ABS, a, NULL);
+    }
+    if (strcmp(id, "min") == 0 || strcmp(id, "max") == 0) {
+        int kind = id[1] == 'i' ? K_N_MIN : K_N_MAX;
+        if (!accept(P, "("))
+            return NULL;
+        Node *a = parse_num(P);
+        if (!a || !accept(P, ","))
+            return NULL;
+        Node *b = parse_num(P);
+        if (!b || !accept(P, ")"))
+            return NULL;
+        return num_node(P, kind, a, b);
+    }
+    return NULL;
+}
+
+static Node *parse_num_term(Parser *P)
+{
+    Node *l = parse_num_factor(P);
+    while (l) {
+        int kind;
+        if (accept(P, "*"))
+            kind = K_N_MUL;
+        else if (accept(P, "/"))
+            kind = K_N_DIV;
+        else
+            break;
+        Node *r = parse_num_factor(P);
+        l = r ? num_node(P, kind, l, r) : NULL;
+    }
+    return l;
+}
+
+static Node *parse_num(Parser *P)
+{
+    Node *l = parse_num_term(P);
+    while (l) {
+        int kind;
+        if (accept(P, "+"))
+            kind = K_N_ADD;
+        else if (accept(P, "-"))
+            kind = K_N_SUB;
+        else
+            break;
+        Node *r = parse_num_term(P);
+        l = r ? num_node(P, kind, l, r) : NULL;
+    }
+    return l;
+}
+
+/* An arithmetic atom at the current position, or NULL (position unchanged)
+ * when the text there is not a numeric expression followed by a comparison.
+ * The paper's plain atom, intensity(img[, c]) CMP constant-or-percentile, is
+ * returned as K_ATOM; every other comparison as K_ARITH. */
+static Node *try_parse_arith_atom(Parser *P)
+{
+    size_t pos = P->pos;
+    int line = P->line, col = P->col;
+    Node *lhs = parse_num(P);
+    if (P->failed)
+        return NULL;
+    if (!lhs || !peek_cmp(P)) {
+        P->pos = pos;
+        P->line = line;
+        P->col = col;
+        return NULL;
+    }
+    int cmp;
+    if (accept(P, ">=."))
+        cmp = CMP_GE;
+    else if (accept(P, "<=."))
+        cmp = CMP_LE;
+    else if (accept(P, ">."))
+        cmp = CMP_GT;
+    else {
+        accept(P, "<.");
+        cmp = CMP_LT;
+    }
+    Node *rhs = parse_num(P);
+    if (!rhs) {
+        perr(P, "expected a numeric expression after the comparison");
+        return NULL;
+    }
+    int rconst = rhs->kind == K_N_CONST ||
+                 (rhs->kind == K_N_NEG && rhs->a->kind == K_N_CONST);
+    if (lhs->kind == K_N_CHAN && (rconst || rhs->kind == K_N_PCT)) {
+        Node *n = new_node(P, K_ATOM);
+        if (!n)
+            return NULL;
+        n->chan = lhs->chan;
+        n->cmp = cmp;
+        if (rhs->kind == K_N_PCT) {
+            n->use_pct = 1;
+            n->pchan = rhs->pchan;
+            n->pq = rhs->pq;
+        } else {
+            n->thr = rhs->kind == K_N_CONST ? rhs->thr : -rhs->a->thr;
         }
-        n->thr = (float)(neg ? -v : v);
+        return n;
+    }
+    Node *n = new_node(P, K_ARITH);
+    if (n) {
+        n->a = lhs;
+        n->b = rhs;
+        n->cmp = cmp;
     }
     return n;
 }
@@ -803,6 +938,9 @@ static Node *parse_prim(Parser *P)
 {
     if (P->failed)
         return NULL;
+    Node *at = try_parse_arith_atom(P);
+    if (at || P->failed)
+        return at;
     if (accept(P, "(")) {
         Node *e = parse_expr(P);
         expect(P, ")");
@@ -817,8 +955,11 @@ static Node *parse_prim(Parser *P)
         return new_node(P, K_TRUE);
     if (strcmp(id, "false") == 0)
         return new_node(P, K_FALSE);
-    if (strcmp(id, "intensity") == 0)
-        return parse_atom(P);
+    if (strcmp(id, "intensity") == 0 || strcmp(id, "percentile") == 0 || strcmp(id, "abs") == 0 ||
+        strcmp(id, "min") == 0 || strcmp(id, "max") == 0) {
+        perr(P, "expected a comparison '>.', '<.', '>=.' or '<=.' after a numeric expression");
+        return NULL;
+    }
     if (strcmp(id, "near") == 0 || strcmp(id, "N") == 0)
         return parse_call_args(P, new_node(P, K_NEAR), 1);
     if (strcmp(id, "interior") == 0)
@@ -829,6 +970,8 @@ static Node *parse_prim(Parser *P)
         return parse_call_args(P, new_node(P, K_SURR), 2);
     if (strcmp(id, "grow") == 0)
         return parse_call_args(P, new_node(P, K_GROW), 2);
+    if (strcmp(id, "touch") == 0)
+        return parse_call_args(P, new_node(P, K_TOUCH), 2);
     if (is_builtin(id)) {
         perr(P, "unexpected keyword");
         return NULL;
@@ -1080,6 +1223,65 @@ static uint8_t *alloc_mask(Ctx *X)
     return m;
 }
 
+/* Numeric expressions, pixel by pixel in float32: every operation rounds
+ * once (IEEE single, round to nearest even; no fused multiply-add), min and
+ * max keep the first operand unless the second compares below (above) it,
+ * abs and unary minus act on the sign.  Percentile leaves are computed once
+ * per evaluation of their atom (num_prepare). */
+static int num_prepare(Ctx *X, Node *e)
+{
+    if (!e)
+        return ORC_OK;
+    if (e->kind == K_N_CHAN && (e->chan < 0 || e->chan >= X->C)) {
+        X->rc = ORC_EINVAL;
+        if (X->err && X->errlen > 0)
+            snprintf(X->err, (size_t)X->errlen, "channel index out of range");
+        return X->rc;
+    }
+    if (e->kind == K_N_PCT) {
+        if (e->pchan < 0 || e->pchan >= X->C) {
+            X->rc = ORC_EINVAL;
+            if (X->err && X->errlen > 0)
+                snprintf(X->err, (size_t)X->errlen, "channel index out of range");
+            return X->rc;
+        }
+        int rc = oracle_percentile(X->img, X->dtype, X->C, X->H, X->W, e->pchan, e->pq, &e->thr);
+        if (rc != ORC_OK)
+            X->rc = rc;
+        return rc;
+    }
+    int rc = num_prepare(X, e->a);
+    return rc == ORC_OK ? num_prepare(X, e->b) : rc;
+}
+
+static float num_eval(Ctx *X, Node *e, int64_t i)
+{
+    float a, b;
+    switch (e->kind) {
+    case K_N_CONST:
+    case K_N_PCT:
+        return e->thr;
+    case K_N_CHAN:
+        return pixel_value(X->img, X->dtype, (int64_t)e->chan * X->n + i);
+    case K_N_NEG:
+        return -num_eval(X, e->a, i);
+    case K_N_ABS:
+        return fabsf(num_eval(X, e->a, i));
+    default:
+        break;
+    }
+    a = num_eval(X, e->a, i);
+    b = num_eval(X, e->b, i);
+    switch (e->kind) {
+    case K_N_ADD: return a + b;
+    case K_N_SUB: return a - b;
+    case K_N_MUL: return a * b;
+    case K_N_DIV: return a / b;
+    case K_N_MIN: return b < a ? b : a;
+    default: return b > a ? b : a; /* K_N_MAX */
+    }
+}
+
 /* Evaluate e; params (may be NULL) are the masks bound to the parameters of the
  * macro whose body is being evaluated.  Returns a fresh mask owned by the
  * caller, or NULL on error. */
@@ -1117,6 +1319,35 @@ static uint8_t *eval(Ctx *X, Node *e, uint8_t **params)
         oracle_threshold(X->img, X->dtype, X->C, X->H, X->W, e->chan, e->cmp, t, out);
         return out;
     }
+    case K_ARITH: {
+        if (num_prepare(X, e->a) != ORC_OK || num_prepare(X, e->b) != ORC_OK)
+            return NULL;
+        out = alloc_mask(X);
+        if (!out)
+            return NULL;
+        for (int64_t i = 0; i < n; i++) {
+            float v = num_eval(X, e->a, i), t = num_eval(X, e->b, i);
+            out[i] = (uint8_t)(e->cmp == CMP_GT ? v > t : e->cmp == CMP_LT ? v < t : e->cmp == CMP_GE ? v >= t : v <= t);
+        }
+        return out;
+    }
+    case K_TOUCH: /* touch(a, b) = a & rho b[a] */
+        a = eval(X, e->a, params);
+        b = eval(X, e->b, params);
+        out = (a && b) ? alloc_mask(X) : NULL;
+        if (out) {
+            int rc = oracle_reach(b, a, X->H, X->W, out);
+            if (rc == ORC_OK) {
+                oracle_and(a, out, n, out);
+            } else {
+                X->rc = rc;
+                free(out);
+                out = NULL;
+            }
+        }
+        free(a);
+        free(b);
+        return out;
     case K_NOT:
         a = eval(X, e->a, params);
         if (!a)

@@ -35,13 +35,18 @@ MUTANTS = {
                              "    oracle_near(t, H, W, out);"),
     "precedence_swapped": ('while (!P->failed && accept(P, "&")) {',
                            'while (!P->failed && accept(P, "|")) {'),
-    "threshold_constant_rounded_down": ("n->thr = (float)(neg ? -v : v);",
-                                        "n->thr = nextafterf((float)(neg ? -v : v), 0.0f);"),
+    "threshold_constant_rounded_down": ("n->thr = (float)v; /* read as double",
+                                        "n->thr = nextafterf((float)v, 0.0f); /* read as double"),
     "ccl_max_scans_forward": ("for (int64_t s = n - 1; s >= 0; s--) {\n        if (!a[s] || lab[s] >= 0)",
                               "for (int64_t s = 0; s < n; s++) {\n        if (!a[s] || lab[s] >= 0)"),
     "pj_main_looks_around_the_pixel": ("B[p] = pj_max_neighbour(A, H, W, ij.i, ij.j);",
                                        "B[p] = pj_max_neighbour(A, H, W, i, j);"),
     "pj_reconnect_writes_the_pixel": ("                    B[q] = ab;", "                    B[p] = ab;"),
+    "arith_sub_swapped": ("case K_N_SUB: return a - b;", "case K_N_SUB: return b - a;"),
+    "arith_min_as_max": ("case K_N_MIN: return b < a ? b : a;", "case K_N_MIN: return b > a ? b : a;"),
+    "arith_mul_left_assoc_lost": ("        l = r ? num_node(P, kind, l, r) : NULL;\n    }\n    return l;\n}\n\nstatic Node *parse_num(",
+                                  "        l = r ? num_node(P, kind, r, l) : NULL;\n    }\n    return l;\n}\n\nstatic Node *parse_num("),
+    "touch_reach_reversed": ("int rc = oracle_reach(b, a, X->H, X->W, out);", "int rc = oracle_reach(a, b, X->H, X->W, out);"),
     "pj_lexicographic_order_swapped": ("return x.i > y.i || (x.i == y.i && x.j > y.j);",
                                        "return x.j > y.j || (x.j == y.j && x.i > y.i);"),
 }

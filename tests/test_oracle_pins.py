@@ -417,6 +417,78 @@ def test_ccl_pj_needs_reconnect():
     assert iters == 128 and np.all(lab[a > 0] == 4 * 4 + 3)
 
 
+# ------------------------------- arithmetic atoms and touch (Sect. 2, Sect. 3)
+
+F32 = np.float32
+
+
+def test_arithmetic_atoms_follow_float32_arithmetic():
+    # each operation rounds once to float32, as numpy's float32 arithmetic does
+    rng = np.random.default_rng(31)
+    img = rng.uniform(-2, 2, (3, 17, 23)).astype(F32)
+    a, b, c = img[0], img[1], img[2]
+    cases = [
+        ("intensity(img, 0) + intensity(img, 1) >. 0.25", (a + b) > F32(0.25)),
+        ("intensity(img, 0) - intensity(img, 1) - intensity(img, 2) <. 0", ((a - b) - c) < F32(0)),
+        ("intensity(img, 0) - intensity(img, 1) * intensity(img, 2) >=. 0.1", (a - b * c) >= F32(0.1)),
+        ("(intensity(img, 0) - intensity(img, 1)) * intensity(img, 2) <=. -0.3", ((a - b) * c) <= F32(-0.3)),
+        ("intensity(img, 0) / intensity(img, 1) >. 1.5", (a / b) > F32(1.5)),
+        ("-intensity(img, 2) >. abs(intensity(img, 0))", (-c) > np.abs(a)),
+        ("min(intensity(img, 0), intensity(img, 1)) >. max(intensity(img, 2), 0.5)",
+         np.where(b < a, b, a) > np.where(F32(0.5) > c, F32(0.5), c)),
+        ("2 * intensity(img, 1) + 0.1 <. intensity(img, 0) * 3", (F32(2) * b + F32(0.1)) < (a * F32(3))),
+        ("intensity(img) >. intensity(img, 1)", a > b),
+        ("0.5 <. intensity(img, 2)", F32(0.5) < c),
+    ]
+    for src, want in cases:
+        got = oracle.run(f'output "o" {src}', img)[0]
+        assert np.array_equal(got, want.astype(np.uint8)), src
+
+
+def test_arithmetic_on_integer_pixels_and_percentiles():
+    rng = np.random.default_rng(32)
+    for dt in (np.uint8, np.uint16):
+        img = rng.integers(0, np.iinfo(dt).max + 1, (2, 20, 30)).astype(dt)
+        a, b = img[0].astype(F32), img[1].astype(F32)
+        p = np.sort(img[1].reshape(-1))[int(np.ceil(0.7 * img[1].size)) - 1].astype(F32)
+        src = 'output "o" intensity(img, 0) - percentile(img, 1, 0.7) >. intensity(img, 1) / 4'
+        want = (a - p) > (b / F32(4))
+        assert np.array_equal(oracle.run(src, img)[0], want.astype(np.uint8))
+
+
+def test_division_by_zero_and_nan_compare_false():
+    img = np.array([[[0.0, 1.0, -1.0, 0.0]], [[0.0, 0.0, 0.0, 2.0]]], F32)
+    # 0/0 = nan (every comparison false), 1/0 = inf, -1/0 = -inf
+    got = oracle.run('output "a" intensity(img, 0) / intensity(img, 1) >. 0\n'
+                     'output "b" intensity(img, 0) / intensity(img, 1) <=. 0', img)
+    assert got[0].tolist() == [[0, 1, 0, 0]] and got[1].tolist() == [[0, 0, 1, 1]]
+
+
+def test_touch_keeps_the_regions_of_a_in_contact_with_b():
+    # touch(a, b) = a & rho b[a]: a pixel of a whose 8-component in a meets
+    # N b (by the path definition, the intermediate pixels lie in a)
+    rng = np.random.default_rng(33)
+    for h, w in [(1, 1), (6, 7), (30, 41)]:
+        for _ in range(10):
+            img = rng.random((2, h, w)).astype(F32)
+            a = (img[0] > F32(0.45)).astype(np.uint8)
+            b = (img[1] > F32(0.93)).astype(np.uint8)
+            lab, n = ndimage.label(a, structure=K3)
+            nb = ndimage.binary_dilation(b, structure=K3, border_value=0)
+            keep = np.unique(lab[nb & (lab > 0)])
+            want = np.isin(lab, keep[keep > 0]).astype(np.uint8)
+            got = oracle.run('output "t" touch(intensity(img, 0) >. 0.45, intensity(img, 1) >. 0.93)', img)[0]
+            assert np.array_equal(got, want)
+
+
+def test_numeric_parse_errors():
+    for src in ['output "x" intensity(img) + >. 1', 'output "x" intensity(img) * 2',
+                'output "x" (intensity(img) >. 1', 'output "x" abs(intensity(img)) >. ',
+                'let min = true']:
+        with pytest.raises(oracle.OracleError):
+            oracle.run(src, np.zeros((1, 2, 2), F32))
+
+
 # ---------------------------------------------------------------- language
 
 def test_macros_let_and_sharing():
@@ -445,7 +517,7 @@ def test_macros_let_and_sharing():
 
 @pytest.mark.parametrize("src,where", [
     ('output "x" foo', "undefined name"),
-    ('let a = intensity(img) >. \noutput "x" a', "expected a number"),
+    ('let a = intensity(img) >. \noutput "x" a', "expected a numeric expression"),
     ('output "x" near(true', "expected ')'"),
     ('let near = true', "built-in"),
     ('output x true', "quoted"),
