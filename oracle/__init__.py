@@ -32,6 +32,10 @@ def _load(path=None):
     L = ctypes.CDLL(path)
     P, I, I64, D, F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_float
     L.oracle_run.argtypes = [ctypes.c_char_p, P, I, I, I, I, P, I, ctypes.c_char_p, I]
+    L.oracle_run3.argtypes = [ctypes.c_char_p, P, I, I, I, I, I, P, I, ctypes.c_char_p, I]
+    L.oracle_near3.argtypes = [P, I, I, I, P]
+    L.oracle_reach3.argtypes = [P, P, I, I, I, P]
+    L.oracle_ccl3.argtypes = [P, I, I, I, P]
     L.oracle_count_outputs.argtypes = [ctypes.c_char_p, ctypes.c_char_p, I]
     L.oracle_not.argtypes = [P, I64, P]
     L.oracle_and.argtypes = [P, P, I64, P]
@@ -95,6 +99,57 @@ def run(src, img):
     if rc < 0:
         raise OracleError(f"oracle error {rc}: {err.value.decode()}")
     return [out[i] for i in range(nout)]
+
+
+def run3(src, vol):
+    """Evaluate every `output` of `src` on a volume (C, D, H, W) or (D, H, W):
+    26-neighbourhood N and 26-connected paths."""
+    vol = np.ascontiguousarray(vol)
+    if vol.ndim == 3:
+        vol = vol[None]
+    if vol.ndim != 4 or vol.dtype not in _DT:
+        raise ValueError("volume must be (C,D,H,W) float32, uint8 or uint16")
+    C, D, H, W = vol.shape
+    nout = count_outputs(src)
+    out = np.zeros((max(nout, 1), D, H, W), np.uint8)
+    err = ctypes.create_string_buffer(512)
+    rc = lib().oracle_run3(src.encode(), _ptr(vol), _DT[vol.dtype], C, D, H, W, _ptr(out), nout, err, 512)
+    if rc < 0:
+        raise OracleError(f"oracle error {rc}: {err.value.decode()}")
+    return [out[i] for i in range(nout)]
+
+
+def _vol(a):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    if a.ndim != 3:
+        raise ValueError("volume mask must be 3-D")
+    return a
+
+
+def near3(a):
+    a = _vol(a)
+    out = np.zeros_like(a)
+    lib().oracle_near3(_ptr(a), *a.shape, _ptr(out))
+    return out
+
+
+def reach3(a, b):
+    a, b = _vol(a), _vol(b)
+    out = np.zeros_like(a)
+    rc = lib().oracle_reach3(_ptr(a), _ptr(b), *a.shape, _ptr(out))
+    if rc < 0:
+        raise OracleError(f"oracle error {rc}")
+    return out
+
+
+def ccl3(a):
+    """26-connected labels; label = smallest linear index in the component, -1 = background."""
+    a = _vol(a)
+    lab = np.zeros(a.shape, np.int32)
+    rc = lib().oracle_ccl3(_ptr(a), *a.shape, _ptr(lab))
+    if rc < 0:
+        raise OracleError(f"oracle error {rc}")
+    return lab
 
 
 def _unary(fn, a):

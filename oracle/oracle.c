@@ -426,6 +426,133 @@ int oracle_ccl_pj(const uint8_t *start, int H, int W, int k, int max_rounds, int
     return done ? ORC_OK : -6;
 }
 
+/* ---- Volumes (D x H x W, slice-major) ----
+ * The logic on 3-D images (the paper's tool is restricted to 2-D; its
+ * limitation named in Sect. 1, Sect. 3 and Sect. 5): the Moore neighbourhood
+ * becomes the 26 voxels sharing a face, an edge or a vertex, the voxel
+ * itself included; paths step between such neighbours.  With D = 1 every
+ * function equals its 2-D counterpart. */
+
+/* N a over voxels: (z,y,x) is set iff a voxel of a lies in the 3x3x3 block
+ * centred on it, counting only voxels inside the volume. */
+void oracle_near3(const uint8_t *a, int D, int H, int W, uint8_t *out)
+{
+    for (int z = 0; z < D; z++) {
+        for (int y = 0; y < H; y++) {
+            for (int x = 0; x < W; x++) {
+                int v = 0;
+                for (int dz = -1; !v && dz <= 1; dz++) {
+                    for (int dy = -1; !v && dy <= 1; dy++) {
+                        for (int dx = -1; dx <= 1; dx++) {
+                            int zz = z + dz, yy = y + dy, xx = x + dx;
+                            if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W)
+                                continue;
+                            if (a[((int64_t)zz * H + yy) * W + xx]) {
+                                v = 1;
+                                break;
+                            }
+                        }
+                    }
+                }
+                out[((int64_t)z * H + y) * W + x] = (uint8_t)v;
+            }
+        }
+    }
+}
+
+/* Flood from every voxel of a through 26-neighbours that satisfy b; marks
+ * every flooded voxel in mark (caller-zeroed). */
+static int flood3(const uint8_t *a, const uint8_t *b, int D, int H, int W, uint8_t *mark)
+{
+    int64_t n = (int64_t)D * H * W;
+    int64_t *queue = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    if (!queue)
+        return ORC_ENOMEM;
+    int64_t head = 0, tail = 0;
+    for (int64_t p = 0; p < n; p++) {
+        if (!a[p])
+            continue;
+        mark[p] = 1;
+        queue[tail++] = p;
+    }
+    while (head < tail) {
+        int64_t p = queue[head++];
+        int z = (int)(p / ((int64_t)H * W)), y = (int)(p / W % H), x = (int)(p % W);
+        for (int dz = -1; dz <= 1; dz++) {
+            for (int dy = -1; dy <= 1; dy++) {
+                for (int dx = -1; dx <= 1; dx++) {
+                    int zz = z + dz, yy = y + dy, xx = x + dx;
+                    if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W)
+                        continue;
+                    int64_t q = ((int64_t)zz * H + yy) * W + xx;
+                    if (!mark[q] && b[q]) {
+                        mark[q] = 1;
+                        queue[tail++] = q;
+                    }
+                }
+            }
+        }
+    }
+    free(queue);
+    return ORC_OK;
+}
+
+/* rho a[b] over voxels: flood from a through b, then one dilation. */
+int oracle_reach3(const uint8_t *a, const uint8_t *b, int D, int H, int W, uint8_t *out)
+{
+    int64_t n = (int64_t)D * H * W;
+    uint8_t *mark = (uint8_t *)calloc((size_t)(n ? n : 1), 1);
+    if (!mark)
+        return ORC_ENOMEM;
+    int rc = flood3(a, b, D, H, W, mark);
+    if (rc == ORC_OK)
+        oracle_near3(mark, D, H, W, out);
+    free(mark);
+    return rc;
+}
+
+/* 26-connected labels of a volume: a flood from each unlabelled voxel in
+ * raster order; label = the flood's first voxel = the smallest linear index
+ * (z*H + y)*W + x of the component; -1 for background. */
+int oracle_ccl3(const uint8_t *a, int D, int H, int W, int32_t *lab)
+{
+    int64_t n = (int64_t)D * H * W;
+    if (n == 0)
+        return ORC_OK;
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!queue)
+        return ORC_ENOMEM;
+    for (int64_t p = 0; p < n; p++)
+        lab[p] = -1;
+    for (int64_t s = 0; s < n; s++) {
+        if (!a[s] || lab[s] >= 0)
+            continue;
+        int64_t head = 0, tail = 0;
+        lab[s] = (int32_t)s;
+        queue[tail++] = s;
+        while (head < tail) {
+            int64_t p = queue[head++];
+            int z = (int)(p / ((int64_t)H * W)), y = (int)(p / W % H), x = (int)(p % W);
+            for (int dz = -1; dz <= 1; dz++) {
+                for (int dy = -1; dy <= 1; dy++) {
+                    for (int dx = -1; dx <= 1; dx++) {
+                        int zz = z + dz, yy = y + dy, xx = x + dx;
+                        if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W)
+                            continue;
+                        int64_t q = ((int64_t)zz * H + yy) * W + xx;
+                        if (a[q] && lab[q] < 0) {
+                            lab[q] = lab[s]; /* the flood's first voxel */
+                            queue[tail++] = q;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    free(queue);
+    return ORC_OK;
+}
+
 static float pixel_value(const void *img, int dtype, int64_t idx)
 {
     if (dtype == DT_U8)
@@ -1208,7 +1335,7 @@ static int parse_program(const char *src, Prog *G, char *err, int errlen)
 typedef struct Ctx {
     Prog *G;
     const void *img;
-    int dtype, C, H, W;
+    int dtype, C, D, H, W; /* D slices of H x W (D = 1: a 2-D image) */
     int64_t n;
     char *err;
     int errlen;
@@ -1245,7 +1372,7 @@ static int num_prepare(Ctx *X, Node *e)
                 snprintf(X->err, (size_t)X->errlen, "channel index out of range");
             return X->rc;
         }
-        int rc = oracle_percentile(X->img, X->dtype, X->C, X->H, X->W, e->pchan, e->pq, &e->thr);
+        int rc = oracle_percentile(X->img, X->dtype, X->C, X->D * X->H, X->W, e->pchan, e->pq, &e->thr);
         if (rc != ORC_OK)
             X->rc = rc;
         return rc;
@@ -1282,6 +1409,38 @@ static float num_eval(Ctx *X, Node *e, int64_t i)
     }
 }
 
+/* reach, surrounded and grow on a volume, by the same definitions as in 2-D:
+ * surrounded(a,b) = a & !rho(!a & !b)[!b], grow(a,b) = a | (b & rho a[b]). */
+static int reach_like3(Ctx *X, int kind, const uint8_t *a, const uint8_t *b, uint8_t *out)
+{
+    int64_t n = X->n;
+    if (kind == K_REACH)
+        return oracle_reach3(a, b, X->D, X->H, X->W, out);
+    uint8_t *t = (uint8_t *)malloc((size_t)(n ? n : 1)), *u = (uint8_t *)malloc((size_t)(n ? n : 1));
+    int rc = ORC_ENOMEM;
+    if (t && u) {
+        if (kind == K_GROW) {
+            rc = oracle_reach3(a, b, X->D, X->H, X->W, t);
+            if (rc == ORC_OK) {
+                oracle_and(b, t, n, t);
+                oracle_or(a, t, n, out);
+            }
+        } else {
+            oracle_not(a, n, t);
+            oracle_not(b, n, u);
+            oracle_and(t, u, n, t); /* !a & !b */
+            rc = oracle_reach3(t, u, X->D, X->H, X->W, out);
+            if (rc == ORC_OK) {
+                oracle_not(out, n, out);
+                oracle_and(a, out, n, out);
+            }
+        }
+    }
+    free(t);
+    free(u);
+    return rc;
+}
+
 /* Evaluate e; params (may be NULL) are the masks bound to the parameters of the
  * macro whose body is being evaluated.  Returns a fresh mask owned by the
  * caller, or NULL on error. */
@@ -1307,7 +1466,7 @@ static uint8_t *eval(Ctx *X, Node *e, uint8_t **params)
             return NULL;
         }
         if (e->use_pct) {
-            int rc = oracle_percentile(X->img, X->dtype, X->C, X->H, X->W, e->pchan, e->pq, &t);
+            int rc = oracle_percentile(X->img, X->dtype, X->C, X->D * X->H, X->W, e->pchan, e->pq, &t);
             if (rc != ORC_OK) {
                 X->rc = rc;
                 return NULL;
@@ -1316,7 +1475,7 @@ static uint8_t *eval(Ctx *X, Node *e, uint8_t **params)
         out = alloc_mask(X);
         if (!out)
             return NULL;
-        oracle_threshold(X->img, X->dtype, X->C, X->H, X->W, e->chan, e->cmp, t, out);
+        oracle_threshold(X->img, X->dtype, X->C, X->D * X->H, X->W, e->chan, e->cmp, t, out);
         return out;
     }
     case K_ARITH: {
@@ -1336,7 +1495,7 @@ static uint8_t *eval(Ctx *X, Node *e, uint8_t **params)
         b = eval(X, e->b, params);
         out = (a && b) ? alloc_mask(X) : NULL;
         if (out) {
-            int rc = oracle_reach(b, a, X->H, X->W, out);
+            int rc = X->D == 1 ? oracle_reach(b, a, X->H, X->W, out) : oracle_reach3(b, a, X->D, X->H, X->W, out);
             if (rc == ORC_OK) {
                 oracle_and(a, out, n, out);
             } else {
@@ -1375,7 +1534,13 @@ static uint8_t *eval(Ctx *X, Node *e, uint8_t **params)
         if (!a)
             return NULL;
         out = alloc_mask(X);
-        if (out) {
+        if (out && X->D > 1) { /* volumes: N over 26 neighbours, interior = !N! */
+            if (e->kind == K_INTERIOR)
+                oracle_not(a, n, a);
+            oracle_near3(a, X->D, X->H, X->W, out);
+            if (e->kind == K_INTERIOR)
+                oracle_not(out, n, out);
+        } else if (out) {
             if (e->kind == K_NEAR)
                 oracle_near(a, X->H, X->W, out);
             else if (oracle_interior(a, X->H, X->W, out) != ORC_OK) {
@@ -1389,10 +1554,18 @@ static uint8_t *eval(Ctx *X, Node *e, uint8_t **params)
     case K_REACH:
     case K_SURR:
     case K_GROW: {
+        int rc3;
         a = eval(X, e->a, params);
         b = eval(X, e->b, params);
         out = (a && b) ? alloc_mask(X) : NULL;
-        if (out) {
+        if (out && X->D > 1) {
+            rc3 = reach_like3(X, e->kind, a, b, out);
+            if (rc3 != ORC_OK) {
+                X->rc = rc3;
+                free(out);
+                out = NULL;
+            }
+        } else if (out) {
             int rc;
             if (e->kind == K_REACH)
                 rc = oracle_reach(a, b, X->H, X->W, out);
@@ -1464,15 +1637,15 @@ int oracle_count_outputs(const char *src, char *err, int errlen)
     return rc == ORC_OK ? nout : rc;
 }
 
-/* Evaluate every output of src on img.  Output i is written to
- * out + i*H*W (one byte per pixel) for i < max_out.  Returns the number of
- * outputs, or a negative error code (message in err). */
-int oracle_run(const char *src, const void *img, int dtype, int C, int H, int W, uint8_t *out,
-               int max_out, char *err, int errlen)
+/* Evaluate every output of src on img ([C][D][H][W]).  Output i is written
+ * to out + i*D*H*W (one byte per voxel) for i < max_out.  Returns the number
+ * of outputs, or a negative error code (message in err). */
+int oracle_run3(const char *src, const void *img, int dtype, int C, int D, int H, int W, uint8_t *out,
+                int max_out, char *err, int errlen)
 {
     if (err && errlen > 0)
         err[0] = 0;
-    if ((dtype != DT_F32 && dtype != DT_U8 && dtype != DT_U16) || C < 1 || H < 0 || W < 0) {
+    if ((dtype != DT_F32 && dtype != DT_U8 && dtype != DT_U16) || C < 1 || D < 1 || H < 0 || W < 0) {
         if (err && errlen > 0)
             snprintf(err, (size_t)errlen, "bad image description");
         return ORC_EINVAL;
@@ -1490,9 +1663,10 @@ int oracle_run(const char *src, const void *img, int dtype, int C, int H, int W,
     X.img = img;
     X.dtype = dtype;
     X.C = C;
+    X.D = D;
     X.H = H;
     X.W = W;
-    X.n = (int64_t)H * W;
+    X.n = (int64_t)D * H * W;
     X.err = err;
     X.errlen = errlen;
     X.rc = ORC_OK;
@@ -1520,4 +1694,11 @@ int oracle_run(const char *src, const void *img, int dtype, int C, int H, int W,
     rc = X.rc;
     free_prog(&G);
     return rc == ORC_OK ? oi : rc;
+}
+
+/* A 2-D image: one slice. */
+int oracle_run(const char *src, const void *img, int dtype, int C, int H, int W, uint8_t *out,
+               int max_out, char *err, int errlen)
+{
+    return oracle_run3(src, img, dtype, C, 1, H, W, out, max_out, err, errlen);
 }

@@ -115,3 +115,33 @@ def components(a):
                             stack.append(q)
                 comps.append(comp)
     return comps
+
+
+def neighbours3(z, y, x, d, h, w):
+    """26-neighbours of voxel (z, y, x) inside a d x h x w volume, excluding it."""
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if (dz or dy or dx) and 0 <= z + dz < d and 0 <= y + dy < h and 0 <= x + dx < w:
+                    yield z + dz, y + dy, x + dx
+
+
+def reach_walks3(a, b):
+    """rho a[b] on a volume by the same unrolled walk existential as
+    reach_walks, over the 26-neighbour adjacency matrix."""
+    d, h, w = a.shape
+    n = d * h * w
+    adj = np.zeros((n, n), np.int64)
+    for z in range(d):
+        for y in range(h):
+            for x in range(w):
+                for q in neighbours3(z, y, x, d, h, w):
+                    adj[(z * h + y) * w + x, (q[0] * h + q[1]) * w + q[2]] = 1
+    av = a.reshape(-1).astype(np.int64)
+    bv = b.reshape(-1).astype(np.int64)
+    res = av > 0
+    t = (adj @ av) > 0
+    for _ in range(n + 1):
+        res = res | t
+        t = (adj @ (bv * t)) > 0
+    return res.reshape(d, h, w).astype(np.uint8)

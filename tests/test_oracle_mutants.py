@@ -46,7 +46,11 @@ MUTANTS = {
     "arith_min_as_max": ("case K_N_MIN: return b < a ? b : a;", "case K_N_MIN: return b > a ? b : a;"),
     "arith_mul_left_assoc_lost": ("        l = r ? num_node(P, kind, l, r) : NULL;\n    }\n    return l;\n}\n\nstatic Node *parse_num(",
                                   "        l = r ? num_node(P, kind, r, l) : NULL;\n    }\n    return l;\n}\n\nstatic Node *parse_num("),
-    "touch_reach_reversed": ("int rc = oracle_reach(b, a, X->H, X->W, out);", "int rc = oracle_reach(a, b, X->H, X->W, out);"),
+    "touch_reach_reversed": ("int rc = X->D == 1 ? oracle_reach(b, a, X->H, X->W, out)",
+                             "int rc = X->D == 1 ? oracle_reach(a, b, X->H, X->W, out)"),
+    "near3_drops_next_slice": ("for (int dz = -1; !v && dz <= 1; dz++)", "for (int dz = -1; !v && dz <= 0; dz++)"),
+    "flood3_steps_onto_a": ("if (!mark[q] && b[q]) {", "if (!mark[q] && a[q]) {"),
+    "volume_surrounded_or_for_and": ("oracle_and(t, u, n, t); /* !a & !b */", "oracle_or(t, u, n, t); /* !a & !b */"),
     "pj_lexicographic_order_swapped": ("return x.i > y.i || (x.i == y.i && x.j > y.j);",
                                        "return x.j > y.j || (x.j == y.j && x.i > y.i);"),
 }
@@ -62,7 +66,7 @@ def _run_mutant(name, tmpdir):
     lib = build(os.path.join(tmpdir, f"lib_{name}.so"), src)
     env = dict(os.environ, ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py", "tests/test_golden.py"],
+                        "tests/test_oracle_pins.py", "tests/test_oracle_pins3.py", "tests/test_golden.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
