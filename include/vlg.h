@@ -204,6 +204,23 @@ int vlg_check_batch(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *const *
 int vlg_ccl_labels(vlg_ctx *ctx, const uint64_t *mask_dev, int height, int width,
                    int32_t *labels_dev);
 
+/* For callers that cannot allocate device memory during a call (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same labelling as vlg_ccl_labels, with the same arguments, result and
+ * errors, but its labelling arrays live in a fixed device array of
+ * VLG_NOALLOC_SCRATCH_BYTES that each GPU holds from the library's load until
+ * the process ends; the call allocates nothing.  The array needs
+ * 9 * ceil(height/2) * ceil(width/2) bytes plus alignment (4096 x 4096 fits);
+ * a larger image fails with VLG_ESHAPE and a message, before any work is
+ * enqueued.  Every call on one GPU, from any context or thread, shares that
+ * GPU's array and leaves its contents behind (the next call rewrites what it
+ * reads): calls that overlap on one GPU race, so the caller orders them (for
+ * example on one stream).  The result completes in the order of the
+ * context's stream, as with vlg_ccl_labels. */
+#define VLG_NOALLOC_SCRATCH_BYTES (40ll << 20)
+int vlg_ccl_labels_noalloc(vlg_ctx *ctx, const uint64_t *mask_dev, int height, int width,
+                           int32_t *labels_dev);
+
 /* Counters of the last reachability labelling run on ctx (for measurement):
  * union attempts and retry iterations of the cross-tile merge, and the
  * number of kernel launches per labelling. */

@@ -221,6 +221,19 @@ def ccl_labels(ctx, mask, height, width, out=None):
     return out
 
 
+def ccl_labels_noalloc(ctx, mask, height, width, out):
+    """vlg_ccl_labels_noalloc: the labelling of ccl_labels into the caller's
+    int32 [H, W] device tensor `out`, with the library allocating nothing
+    (its arrays live in a fixed per-GPU device array; VLG_ESHAPE beyond it)."""
+    with _Ordered(ctx):
+        _lib.call("vlg_ccl_labels_noalloc", ctx.handle, ctypes.c_void_p(mask.data_ptr()), height, width,
+                  ctypes.c_void_p(out.data_ptr()))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 40 << 20
+
+
 def ccl_counters(ctx):
     c = _lib.CclCounters()
     _lib.call("vlg_ccl_read_counters", ctx.handle, ctypes.byref(c))
@@ -354,6 +367,6 @@ def pack(mask):
 
 
 __all__ = ["create", "sync", "set_loop_cap", "set_mode", "load_image", "compile_formula", "formula_info", "formula_plan", "output_names",
-           "check", "check_all", "check_batch", "ccl_labels", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
+           "check", "check_all", "check_batch", "ccl_labels", "ccl_labels_noalloc", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
            "tune_load", "autotune_batch", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

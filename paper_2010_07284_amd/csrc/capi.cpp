@@ -52,6 +52,38 @@ struct DeviceGuard {
     }
 };
 
+// The fixed device array behind vlg_ccl_labels_noalloc: labelling scratch for
+// callers that cannot allocate.  Each GPU holds its own copy from the moment
+// the library's code object is loaded on it until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device memory: kernels
+// and copies get the device address that hipGetSymbolAddress returns for the
+// current device (noalloc_scratch).
+constexpr size_t kNoallocScratchBytes = 40ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_dev;  // device -> address of its `scratch`
+
+// Device address of `scratch` on `device`, which must be current.  Looked up
+// once per device (vlg_create does it at set-up) and cached.
+int noalloc_scratch(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_dev.find(device);
+    if (it != g_scratch_dev.end()) {
+        *out = it->second;
+        return VLG_OK;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(VLG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_dev[device] = p;
+    *out = p;
+    return VLG_OK;
+}
+
 }  // namespace
 
 std::atomic<uint64_t> g_serial{1};
@@ -987,6 +1019,40 @@ int tune_loop(vlg_ctx *c, const std::vector<std::pair<int, std::vector<int>>> &s
 
 }  // namespace
 
+namespace {
+
+// Labelling scratch of vlg_ccl_labels: parent pointers (4 B per 2x2 block),
+// flag bytes (1 B per block) and the canonical-label table (4 B per block).
+size_t ccl_labels_scratch_bytes(const Geo &g) {
+    const size_t nb = (size_t)g.BH * g.BW;
+    return 2 * align256(nb * 4) + align256(nb) + 256;
+}
+
+// Labels of the mask into labels_dev, with the labelling arrays in `scratch`
+// (at least ccl_labels_scratch_bytes(g) bytes of device memory).  Every array
+// the kernels read is written first in the same call (the local pass writes
+// every block's parent and flag byte, the table is filled before use), so the
+// scratch needs no clearing between calls.
+int ccl_labels_on(vlg_ctx *c, const Geo &g, const uint64_t *mask_dev, int32_t *labels_dev, void *scratch) {
+    const size_t nb = (size_t)g.BH * g.BW;
+    CclWork w;
+    w.glab = (int32_t *)scratch;
+    w.gflag = (uint8_t *)scratch + align256(nb * 4);
+    int32_t *canon = (int32_t *)((char *)scratch + align256(nb * 4) + align256(nb));
+    w.counters = c->counters;
+    w.tbh = tuning_for(c, g.H, g.W).ccl_tbh;
+    w.guard = c->guard();
+    MRef b{mask_dev, 0ull}, none{nullptr, 0ull};
+    HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
+    HIP_TRY(launch_ccl_local(c->stream, g, b, none, none, w));
+    HIP_TRY(launch_ccl_merge(c->stream, g, b, w));
+    HIP_TRY(launch_ccl_flag(c->stream, g, w));
+    HIP_TRY(launch_ccl_labels(c->stream, g, b, w, canon, labels_dev));
+    return VLG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *vlg_last_error(void) { return g_err.c_str(); }
@@ -1021,6 +1087,9 @@ int vlg_create(vlg_ctx **out, int device, void *hip_stream) {
     *c->status_host = 0;
     HIP_TRY(launch_fill_i64(c->stream, c->counters, 4, 0));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    void *scratch_dev = nullptr;  // set-up of vlg_ccl_labels_noalloc on this device
+    const int rc = noalloc_scratch(device, &scratch_dev);
+    if (rc != VLG_OK) return rc;
     *out = c.release();
     return VLG_OK;
 }
@@ -1337,23 +1406,27 @@ int vlg_ccl_labels(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, 
     DeviceGuard dg(c->device);
     const Geo g = make_geo(height, width);
     if (g.nwords == 0) return VLG_OK;
-    const size_t nb = (size_t)g.BH * g.BW;
-    int rc = ensure_ws(c, 2 * align256(nb * 4) + align256(nb) + 256);
+    int rc = ensure_ws(c, ccl_labels_scratch_bytes(g));
     if (rc != VLG_OK) return rc;
-    CclWork w;
-    w.glab = (int32_t *)c->ws;
-    w.gflag = (uint8_t *)c->ws + align256(nb * 4);
-    int32_t *canon = (int32_t *)((char *)c->ws + align256(nb * 4) + align256(nb));
-    w.counters = c->counters;
-    w.tbh = tuning_for(c, height, width).ccl_tbh;
-    w.guard = c->guard();
-    MRef b{mask_dev, 0ull}, none{nullptr, 0ull};
-    HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
-    HIP_TRY(launch_ccl_local(c->stream, g, b, none, none, w));
-    HIP_TRY(launch_ccl_merge(c->stream, g, b, w));
-    HIP_TRY(launch_ccl_flag(c->stream, g, w));
-    HIP_TRY(launch_ccl_labels(c->stream, g, b, w, canon, labels_dev));
-    return VLG_OK;
+    return ccl_labels_on(c, g, mask_dev, labels_dev, c->ws);
+}
+
+int vlg_ccl_labels_noalloc(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, int32_t *labels_dev) {
+    if (!c || (!mask_dev && (int64_t)height * width > 0) || (!labels_dev && (int64_t)height * width > 0))
+        return fail(VLG_EINVAL, "null argument");
+    if (height < 0 || width < 0 || (int64_t)height * width >= (1ll << 31)) return fail(VLG_ESHAPE, "bad shape");
+    const Geo g = make_geo(height, width);
+    if (g.nwords == 0) return VLG_OK;
+    const size_t need = ccl_labels_scratch_bytes(g);
+    if (need > kNoallocScratchBytes)
+        return fail(VLG_ESHAPE, "vlg_ccl_labels_noalloc: a " + std::to_string(height) + " x " + std::to_string(width) +
+                                    " image needs " + std::to_string(need) + " bytes of labelling scratch, more than the " +
+                                    std::to_string(kNoallocScratchBytes) + " of the fixed device array");
+    DeviceGuard dg(c->device);
+    void *scratch_dev = nullptr;
+    int rc = noalloc_scratch(c->device, &scratch_dev);
+    if (rc != VLG_OK) return rc;
+    return ccl_labels_on(c, g, mask_dev, labels_dev, scratch_dev);
 }
 
 int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int iters, vlg_kernel_time *out,
