@@ -149,6 +149,12 @@ def bench_chain(vlg, lib, steps, check_oracle):
             "gpixel_node_per_s": round(1024 * 1024 * info["nodes"] / (ms["graph"] / 1e3) / 1e9, 3)}
 
 
+def _oracle_run_one(src, img):
+    import oracle
+    oracle.run(src, img)
+    return 0
+
+
 def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512, square=False):
     """Uneven batch: `n` phantom images (sides uniform in [128, 2048], four
     float32 channels, generated in device memory) and the shared 60-node
@@ -167,11 +173,13 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512, square=False):
     log(f"[bench] batch: generating {n} phantom images on the device")
     order = sorted(range(n), key=lambda i: sizes[i][0] * sizes[i][1])
     sample = sorted({order[0], order[n // 2], order[-1]})
+    # images timed with the oracle on the host cores: every 16th image
+    cpu_sample = list(range(0, n, 16)) if check_oracle and not square else []
     ims, host = [], {}
     for i, (h, w) in enumerate(sizes):
         t = images.phantom_image_device(seed, i, h, w, device="cuda:0")
         ims.append(vlg.load_image(ctx, t))
-        if i in sample:
+        if i in sample or i in cpu_sample:
             host[i] = t.cpu().numpy()
         del t
     torch.cuda.empty_cache()
@@ -203,6 +211,22 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512, square=False):
                     if not np.array_equal(vlg.unpack(outs[i][k], h, w), want[k]):
                         raise SystemExit(f"[bench] PARITY FAILURE: batch {mode} image {i} output {k}")
         log(f"[bench] batch parity: images {sample} bit-exact (perop and graph)")
+    cpu = None
+    if cpu_sample:
+        # the oracle on all host cores, one image per worker process
+        import multiprocessing as mp
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+        imgs = [host[i] for i in cpu_sample]
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            pool.starmap(_oracle_run_one, [(src, x) for x in imgs])
+        t_cpu = time.perf_counter() - t0
+        px_s = sum(x.shape[1] * x.shape[2] for x in imgs)
+        cpu = {"value": round(px_s * nodes / t_cpu / 1e9, 4), "unit": "Gpixel-node evals/s", "cores": cores,
+               "kind": "oracle", "images_per_s": round(len(imgs) / t_cpu, 2),
+               "sample": f"every 16th image of the batch ({len(imgs)} images, {px_s / 1e6:.1f} Mpx) on {cores} "
+                         f"worker processes of {cpu_model()}, one image per process, {t_cpu:.1f} s"}
+        log(f"[bench] batch oracle on {cores} host cores: {cpu}")
     ms = {}
     for mode in ("perop", "fused", "graph"):
         vlg.set_mode(ctx, mode)
@@ -225,7 +249,7 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512, square=False):
            "perop_ms": round(ms["perop"], 3), "fused_ms": round(ms["fused"], 3), "graph_ms": round(ms["graph"], 3),
            "speedup_graph_vs_perop": round(ms["perop"] / ms["graph"], 3),
            "gpixel_node_per_s": round(px * nodes / (ms["graph"] / 1e3) / 1e9, 3),
-           "images_per_s": round(n / (ms["graph"] / 1e3), 1)}
+           "images_per_s": round(n / (ms["graph"] / 1e3), 1), "cpu_baseline_all_cores": cpu}
     del outs, ims
     torch.cuda.empty_cache()
     return res
@@ -290,23 +314,22 @@ def bench_pixelwise(vlg, iters, side=46080):
 
 
 def bench_paper_grow(vlg, lib, steps, check_oracle, side=7680):
-    """The paper's specification workload (Fig. specification): one 7680x7680
-    image in the uint16 range, hI = >.62258, vI = >.56360, grow(hI, vI).  The
+    """The paper's specification workload (Sect. 4.2, Fig. specification): one
+    7680x7680 uint16 image, hI = >.62258, vI = >.56360, grow(hI, vI).  The
     MRI slice is not available: a phantom (ellipses of intensities 0.2-1 with
-    Rician-like noise) scaled to 65535 stands in for it.  Reports the
-    device-resident evaluation and, as in the paper's protocol, the evaluation
-    with the mask copied to host memory."""
+    Rician-like noise) scaled to the uint16 range stands in for it.  Reports
+    the device-resident evaluation, the evaluation with the byte mask copied
+    to host memory, and, as in the paper's protocol (start of computation to
+    result saved), upload of the uint16 slice from host memory + evaluation
+    + readback."""
     import numpy as np
     import torch
     from synth import formulas, images
-    t = images.phantom_image_device(6, 0, side, side, channels=1, device="cuda:0") * 65535.0
+    host = images.paper_slice_u16(side)
     ctx = vlg.create(0)
-    im = vlg.load_image(ctx, t)
+    im = vlg.load_image(ctx, host)
     src = formulas.GROW_SPEC.format(hi=62258, lo=56360)
     f = vlg.compile_formula(ctx, src)
-    host = t.cpu().numpy() if check_oracle else None
-    del t
-    torch.cuda.empty_cache()
     dev = torch.empty((side, (side + 63) // 64), dtype=torch.int64, device="cuda:0")
     hst = torch.empty((side, side), dtype=torch.uint8).pin_memory()
     arr_d = (ctypes.c_void_p * 1)(dev.data_ptr())
@@ -318,7 +341,7 @@ def bench_paper_grow(vlg, lib, steps, check_oracle, side=7680):
         lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr_h, 1, 0)
         if not np.array_equal(hst.numpy(), want):
             raise SystemExit("[bench] PARITY FAILURE: paper grow workload")
-        log("[bench] paper grow: bit-exact against the oracle")
+        log("[bench] paper grow (uint16): bit-exact against the oracle")
     ms_dev = time_mode(vlg, lib, ctx, f, im, arr_d, "graph", steps, 2)
     for _ in range(2):
         lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr_h, 1, 0)
@@ -326,12 +349,167 @@ def bench_paper_grow(vlg, lib, steps, check_oracle, side=7680):
     for _ in range(steps):
         lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr_h, 1, 0)
     ms_host = (time.perf_counter() - t0) * 1e3 / steps
-    log(f"[bench] paper grow {side}^2: {ms_dev:.3f} ms resident, {ms_host:.3f} ms with the byte mask copied to host")
-    return {"workload": f"paper_grow_{side}: {side}x{side} f32 (uint16 range) phantom, grow(>.62258, >.56360)",
+    # the paper's protocol: the slice starts in host memory (pinned here)
+    pinned = torch.from_numpy(host.view(np.int16)).pin_memory()
+    src_ptr = ctypes.c_void_p(pinned.data_ptr())
+    h = ctypes.c_void_p()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc = lib.vlg_load_image(ctx.handle, src_ptr, 2, 1, side, side, side, 0, ctypes.byref(h))
+        if rc != 0:
+            raise SystemExit(f"[bench] vlg_load_image failed: {rc}")
+        lib.vlg_check_all(ctx.handle, f.handle, h, arr_h, 1, 0)
+        lib.vlg_image_free(h)
+    ms_e2e = (time.perf_counter() - t0) * 1e3 / steps
+    log(f"[bench] paper grow {side}^2 uint16: {ms_dev:.3f} ms resident, {ms_host:.3f} ms with the byte mask "
+        f"copied to host, {ms_e2e:.3f} ms host slice in to host mask out")
+    return {"workload": f"paper_grow_{side}: {side}x{side} uint16 phantom, grow(>.62258, >.56360)",
             "device_ms": round(ms_dev, 3), "with_host_readback_ms": round(ms_host, 3),
+            "host_to_host_ms": round(ms_e2e, 3),
             "mpixel_per_s": round(side * side / (ms_dev / 1e3) / 1e6, 1),
             "paper_context": "about 600 ms on a TITAN Xp and 3 s on an HD Graphics 630 for the same shape, "
                              "start of computation to file saved (OpenCL, uint16 MRI slice)"}
+
+
+def bench_pj(vlg, lib, check_oracle, side=2048):
+    """The paper's own labelling (Sect. 3, Alg. CCL) against the union-find
+    labelling on the same masks: a 2048x2048 mask (the size of Fig.
+    cc-movie, whose test image is not available: thresholded smooth noise)
+    with reconnect every 8 main iterations as in the figure and every 16 as
+    in the text, and the 4096^2 serpentine corridor of the headline.  Main
+    iterations, rounds (each ends with the host waiting for the termination
+    check, as in the paper's tool), launches and wall time per labelling."""
+    import numpy as np
+    import torch
+    from synth import images
+    ctx = vlg.create(0)
+    out = {}
+    masks = {f"noise_{side}": (images.plain_image(7, side)[0] > np.float32(0.5)).astype(np.uint8),
+             "maze_4096": images.serpentine_maze(4096, 4096).astype(np.uint8)}
+    for name, m in masks.items():
+        H, W = m.shape
+        words = torch.from_numpy(vlg.pack(m)).to("cuda:0")
+        lab = torch.empty((H, W), dtype=torch.int32, device="cuda:0")
+        row = {}
+        for k in (8, 16):
+            vlg.ccl_labels_pj(ctx, words, H, W, k, out=lab)  # warm-up
+            vlg.sync(ctx)
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                _, st = vlg.ccl_labels_pj(ctx, words, H, W, k, out=lab)
+            vlg.sync(ctx)
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            row[f"reconnect_every_{k}"] = {"main_iterations": st["main_iterations"], "rounds": st["rounds"],
+                                           "launches": st["launches"], "ms": round(ms, 3)}
+            if check_oracle and name.startswith("noise"):
+                import oracle
+                want, iters = oracle.ccl_pj(m, k=k)
+                if iters != st["main_iterations"] or not np.array_equal(lab.cpu().numpy(), want):
+                    raise SystemExit(f"[bench] PARITY FAILURE: pointer-jumping labelling {name} k={k}")
+                row[f"reconnect_every_{k}"]["parity"] = "labels and iteration count equal the oracle's run"
+        uf = torch.empty((H, W), dtype=torch.int32, device="cuda:0")
+        vlg.ccl_labels(ctx, words, H, W, out=uf)
+        vlg.sync(ctx)
+        t0 = time.perf_counter()
+        for _ in range(20):
+            vlg.ccl_labels(ctx, words, H, W, out=uf)
+        vlg.sync(ctx)
+        row["union_find_ms"] = round((time.perf_counter() - t0) * 1e3 / 20, 3)
+        log(f"[bench] paper labelling {name}: {row}")
+        out[name] = row
+    out["paper_context"] = "Fig. cc-movie: 24 iterations (reconnect every 8) on the paper's 2048x2048 test image"
+    return out
+
+
+def bench_volume(vlg, lib, steps, check_oracle, side=256, check_side=96):
+    """The logic on volumes: a two-channel ellipsoid phantom of side^3 voxels
+    and an 18-node segmentation-shaped formula (percentile thresholds,
+    arithmetic, N and interior over 26 neighbours, grow, surrounded, touch,
+    reach through 26-connected components).  Parity against the oracle on a
+    check_side^3 volume of the same recipe first (the oracle on side^3 takes
+    minutes)."""
+    import numpy as np
+    from synth import formulas, images
+    src = formulas.VOLUME_FORMULA
+    ctx = vlg.create(0)
+    f = vlg.compile_formula(ctx, src)
+    info = vlg.formula_info(f)
+    nout = info["outputs"]
+    if check_oracle:
+        import oracle
+        v = images.volume_phantom_device(8, check_side, check_side, check_side).cpu().numpy()
+        want = oracle.run3(src, v)
+        im = vlg.load_volume(ctx, v)
+        for mode in ("perop", "graph"):
+            vlg.set_mode(ctx, mode)
+            got = vlg.check_all(ctx, f, im)
+            vlg.sync(ctx)
+            for k in range(nout):
+                g = vlg.unpack(got[k], check_side * check_side, check_side).reshape(v.shape[1:])
+                if not np.array_equal(g, want[k]):
+                    raise SystemExit(f"[bench] PARITY FAILURE: volume {check_side}^3 {mode} output {k}")
+        log(f"[bench] volume {check_side}^3: bit-exact against the oracle (perop, graph)")
+    vol = images.volume_phantom_device(8, side, side, side)
+    im = vlg.load_volume(ctx, vol)
+    del vol
+    outs = [torch_empty_mask(side * side, side) for _ in range(nout)]
+    arr = (ctypes.c_void_p * nout)(*[o.data_ptr() for o in outs])
+    res = {"workload": f"volume_{side}: {side}^3 f32 x2 ellipsoid phantom, {info['nodes']}-node formula "
+                       f"({info['reach_nodes']} reach-type), {nout} outputs",
+           "nodes": info["nodes"]}
+    for mode in ("perop", "graph"):
+        res[f"{mode}_ms"] = round(time_mode(vlg, lib, ctx, f, im, arr, mode, steps, 2), 3)
+    res["gvoxel_node_per_s"] = round(side ** 3 * info["nodes"] / (res["graph_ms"] / 1e3) / 1e9, 2)
+    prof = vlg.profile(ctx, f, im, iters=3)
+    res["kernels"] = {k: {"launches": n // 3, "avg_us": round(t / n * 1e3, 2),
+                          "gbs": round(b / (t / 1e3) / 1e9, 1) if t else None} for k, (n, t, b) in prof.items()}
+    log(f"[bench] volume {side}^3: {res}")
+    return res
+
+
+def torch_empty_mask(rows, width):
+    import torch
+    return torch.empty((rows, (width + 63) // 64), dtype=torch.int64, device="cuda:0")
+
+
+def bench_arith(vlg, lib, steps, check_oracle, side=4096):
+    """Arithmetic atoms and touch on a two-channel 4096^2 float32 image
+    (smoothed noise and the ellipse channel of the headline workload)."""
+    import numpy as np
+    from synth import formulas, images
+    img = images.ellipse_maze_image(2, side)[[0]]
+    img = np.concatenate([img, images.plain_image(9, side)]).astype(np.float32)
+    src = formulas.ARITH_FORMULA.format(t0=0.55, t1=-0.2, t2=0.35, t3=0.4)
+    ctx = vlg.create(0)
+    f = vlg.compile_formula(ctx, src)
+    info = vlg.formula_info(f)
+    nout = info["outputs"]
+    im = vlg.load_image(ctx, img)
+    outs = [torch_empty_mask(side, side) for _ in range(nout)]
+    arr = (ctypes.c_void_p * nout)(*[o.data_ptr() for o in outs])
+    if check_oracle:
+        import oracle
+        want = oracle.run(src, img)
+        vlg.set_mode(ctx, "graph")
+        lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr, 0, 1)
+        vlg.sync(ctx)
+        for k in range(nout):
+            if not np.array_equal(vlg.unpack(outs[k], side, side), want[k]):
+                raise SystemExit(f"[bench] PARITY FAILURE: arithmetic workload output {k}")
+        log("[bench] arithmetic workload: bit-exact against the oracle")
+    res = {"workload": f"arith_{side}: {side}x{side} f32 x2, {info['nodes']}-node formula with arithmetic atoms "
+                       f"and touch, {nout} outputs", "nodes": info["nodes"]}
+    for mode in ("perop", "graph"):
+        res[f"{mode}_ms"] = round(time_mode(vlg, lib, ctx, f, im, arr, mode, steps, 2), 4)
+    res["gpixel_node_per_s"] = round(side * side * info["nodes"] / (res["graph_ms"] / 1e3) / 1e9, 1)
+    prof = vlg.profile(ctx, f, im, iters=3)
+    if "arith" in prof:
+        n, t, b = prof["arith"]
+        res["arith_kernel"] = {"launches": n // 3, "avg_us": round(t / n * 1e3, 2),
+                               "gbs": round(b / (t / 1e3) / 1e9, 1)}
+    log(f"[bench] arithmetic {side}^2: {res}")
+    return res
 
 
 def bench_serve(vlg, n_req, check_oracle, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
@@ -441,15 +619,14 @@ def main():
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-pixelwise", action="store_true", help="skip the streaming roofline of the pixel-wise kernels")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 7680^2 grow specification workload")
-    ap.add_argument("--lanes", type=int, default=1,
-                    help="concurrent labelling lanes: switched off, only 1 is accepted")
+    ap.add_argument("--no-pj", action="store_true", help="skip the paper's own labelling algorithm")
+    ap.add_argument("--no-volume", action="store_true", help="skip the 256^3 volume workload")
+    ap.add_argument("--no-arith", action="store_true", help="skip the arithmetic-atom workload")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="labellings run together (1, 2, 4, 8); default: what the autotuner picks")
     ap.add_argument("--hbm-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (scale for hardware byte counters)")
     args = ap.parse_args()
-    if args.lanes != 1:
-        print("--lanes: concurrent labelling lanes are switched off (a host-side crash seen with four lanes is "
-              "not explained); only 1 is accepted", file=sys.stderr)
-        sys.exit(2)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the formula path has no multi-GPU mode (images or "
               "requests shard across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
@@ -520,25 +697,27 @@ def main():
         ms[mode] = time_mode(vlg, lib, ctx, f, im, arr, mode, args.steps, args.warmup)
         log(f"[bench] {mode}: {ms[mode]:.4f} ms/step")
 
-    # concurrent labelling lanes (opt-in, experimental): parity, then graph timing
-    lanes_ms = None
-    if args.lanes > 1:
+    if args.lanes:
         vlg.set_tunable(ctx, "ccl_lanes", args.lanes)
-        vlg.set_mode(ctx, "graph")
-        lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr, 0, 1)
-        vlg.sync(ctx)
-        if not args.skip_oracle:
-            for k in range(nout):
-                if not np.array_equal(vlg.unpack(outs[k], S, S), want[k]):
-                    raise SystemExit(f"[bench] PARITY FAILURE: {args.lanes} labelling lanes, output {k}")
-        lanes_ms = time_mode(vlg, lib, ctx, f, im, arr, "graph", args.steps, args.warmup)
-        vlg.set_tunable(ctx, "ccl_lanes", 0)
-        log(f"[bench] graph with {args.lanes} labelling lanes: {lanes_ms:.4f} ms/step")
+    lanes_used = vlg.get_tunable(ctx, "ccl_lanes", S, S)
+    # the same step with one labelling at a time, for comparison
+    vlg.set_tunable(ctx, "ccl_lanes", 1)
+    lanes1_ms = time_mode(vlg, lib, ctx, f, im, arr, "graph", args.steps, args.warmup)
+    vlg.set_tunable(ctx, "ccl_lanes", args.lanes)
+    log(f"[bench] graph with one labelling at a time: {lanes1_ms:.4f} ms/step "
+        f"(headline: {lanes_used} labellings together)")
 
     prof = vlg.profile(ctx, f, im, iters=args.profile_iters)
     dom_name, (dom_n, dom_ms, dom_bytes) = max(prof.items(), key=lambda kv: kv[1][1])
-    dom_avg_ms = dom_ms / dom_n
-    dom_gbs = dom_bytes / (dom_ms / 1e3) / 1e9
+    # the dominant kernel's launch time without per-launch events: its step
+    # launched 50 times back to back between two events (HIP events on the
+    # context's stream, the stream it runs on); the per-launch event average
+    # of vlg_profile is kept beside it
+    dom_event_avg_ms = dom_ms / dom_n
+    dom_avg_ms, dom_step_bytes = vlg.profile_step(ctx, f, im, dom_name, reps=50)
+    dom_gbs = dom_step_bytes / (dom_avg_ms / 1e3) / 1e9
+    log(f"[bench] dominant kernel {dom_name}: {dom_avg_ms * 1e3:.2f} us per launch back to back "
+        f"({dom_event_avg_ms * 1e3:.2f} us with per-launch events), {dom_step_bytes / 1e6:.2f} MB algorithmic")
     ccl_ms = sum(v[1] for k, v in prof.items() if k.startswith("ccl_")) / args.profile_iters
     n_ccl = info["reach_nodes"]
     for k, (n, t, b) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
@@ -563,19 +742,22 @@ def main():
         "config": {"workload": f"ellipse_maze_{S}: {S}x{S} f32 x3 channels, {nodes}-node formula "
                                f"({n_ccl} reach-type), {nout} outputs",
                    "image": [3, S, S], "nodes": nodes, "outputs": nout, "executor": "graph",
-                   "ccl_tile_rows": tile_rows, "near_band_rows": near_rows, "labellings": info["labellings"],
+                   "ccl_tile_rows": tile_rows, "near_band_rows": near_rows, "ccl_lanes": lanes_used,
+                   "labellings": info["labellings"],
                    "launches": info["launches_fused"],
                    "input_sha256": {"image": images.digest(img),
                                     "formula": hashlib.sha256(src.encode()).hexdigest()}},
         "perop_ms": round(ms["perop"], 4),
         "fused_ms": round(ms["fused"], 4),
         "speedup_graph_vs_perop": round(ms["perop"] / t, 3),
-        "graph_ms_with_labelling_lanes": ({"lanes": args.lanes, "ms": round(lanes_ms, 4)} if lanes_ms else None),
+        "ccl_lanes": lanes_used,
+        "graph_ms_one_labelling_at_a_time": round(lanes1_ms, 4),
         "ccl_gpixel_per_s": round(S * S / (ccl_ms / max(1, n_ccl) / 1e3) / 1e9, 3) if n_ccl else None,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                      "avg_launch_us": round(dom_avg_ms * 1e3, 2),
-                     "bytes_per_launch": round(dom_bytes / dom_n),
+                     "avg_launch_us_with_per_launch_events": round(dom_event_avg_ms * 1e3, 2),
+                     "bytes_per_launch": round(dom_step_bytes),
                      "traffic": measured_traffic(f"ellipse_maze_{S}", dom_name, tile_rows)},
         "cpu_baseline": cpu,
     }
@@ -583,6 +765,12 @@ def main():
         line["chain"] = bench_chain(vlg, lib, 3, not args.skip_oracle)
     if not args.no_paper:
         line["paper_grow"] = bench_paper_grow(vlg, lib, 10, not args.skip_oracle)
+    if not args.no_pj:
+        line["paper_labelling"] = bench_pj(vlg, lib, not args.skip_oracle)
+    if not args.no_arith:
+        line["arith"] = bench_arith(vlg, lib, 10, not args.skip_oracle)
+    if not args.no_volume:
+        line["volume"] = bench_volume(vlg, lib, 5, not args.skip_oracle)
     if not args.no_pixelwise:
         line["pixelwise"] = bench_pixelwise(vlg, 5)
     if not args.no_batch:

@@ -134,7 +134,24 @@ int vlg_set_mode(vlg_ctx *ctx, int mode);
 int vlg_load_image(vlg_ctx *ctx, const void *data, int dtype, int channels, int height, int width,
                    int64_t pitch_elems, int where, vlg_image **out);
 int vlg_image_free(vlg_image *img);
+/* Load a volume (a 3-D image: the logic on volumes, the extension the paper
+ * names as its main limitation, Sect. 1, Sect. 3, Sect. 5): data is
+ * [channels][depth][height][width], rows of width elements, dtype and
+ * `where` as for vlg_load_image.  Formulas evaluate with N over the 26
+ * voxels sharing a face, an edge or a vertex (the voxel included) and
+ * 26-connected paths; atoms, percentiles and Boolean operators are voxel by
+ * voxel.  Output masks of a volume are depth*height rows of packed words
+ * (slice after slice), or depth*height*width bytes.  Volumes are evaluated
+ * one at a time (vlg_check_batch rejects them), never with fused segments,
+ * and label with the voxel union-find whatever VLG_TUNE_CCL_ALGO says.
+ * Errors: as vlg_load_image; VLG_ESHAPE when depth*height*width >= 2^31. */
+int vlg_load_volume(vlg_ctx *ctx, const void *data, int dtype, int channels, int depth, int height, int width,
+                    int where, vlg_image **out);
 int vlg_image_shape(const vlg_image *img, int *channels, int *height, int *width);
+/* Shape of an image or volume: depth 1 and the image's height for images,
+ * slices and rows per slice for volumes (vlg_image_shape reports a volume's
+ * height as depth*height). */
+int vlg_image_shape3(const vlg_image *img, int *channels, int *depth, int *height, int *width);
 
 /* Parse and compile formula text (ImgQL subset, paper Sect. 3 Syntax):
  *   let NAME = expr | let NAME(p1, ..., pk) = expr | output "name" expr
@@ -221,6 +238,16 @@ int vlg_ccl_labels(vlg_ctx *ctx, const uint64_t *mask_dev, int height, int width
 int vlg_ccl_labels_noalloc(vlg_ctx *ctx, const uint64_t *mask_dev, int height, int width,
                            int32_t *labels_dev);
 
+/* Connected-component labelling of a packed device volume mask of depth
+ * slices of height x width (26-connectivity, the labelling behind
+ * reachability on volumes).  labels_dev is a device int32
+ * [depth][height][width] array; each voxel of the mask receives the
+ * smallest linear index (z*height + y)*width + x of its component,
+ * background -1.  Runs on the context's stream; VLG_ENOCONV (at vlg_sync)
+ * when a union-find walk stopped at the loop cap. */
+int vlg_ccl_labels3(vlg_ctx *ctx, const uint64_t *mask_dev, int depth, int height, int width,
+                    int32_t *labels_dev);
+
 /* Counters of the last reachability labelling run on ctx (for measurement):
  * union attempts and retry iterations of the cross-tile merge, and the
  * number of kernel launches per labelling. */
@@ -228,8 +255,41 @@ typedef struct vlg_ccl_counters {
     int64_t merge_unions;
     int64_t merge_retries;
     int64_t launches_per_ccl;
+    /* pointer-jumping labellings (VLG_CCL_POINTER_JUMPING) since the last
+     * read: labellings, main iterations, rounds (reconnect + termination
+     * check), kernel launches */
+    int64_t pj_labellings;
+    int64_t pj_main_iterations;
+    int64_t pj_rounds;
+    int64_t pj_launches;
 } vlg_ccl_counters;
 int vlg_ccl_read_counters(vlg_ctx *ctx, vlg_ccl_counters *out);
+
+/* The paper's own labelling algorithm (Sect. 3, Alg. CCL, Fig. cc-movie) on
+ * a packed device mask: labels are coordinate pairs (row, column) ordered
+ * lexicographically; initialization labels each pixel of the mask with its
+ * coordinates; a main iteration gives each pixel holding (i', j') the
+ * largest label in the Moore neighbourhood of (i', j') (pointer jumping,
+ * from one label array into the other); every `reconnect_every` main
+ * iterations (1..64; 0 = the context's VLG_TUNE_PJ_RECONNECT, default 16 as
+ * in the paper's text; its figure uses 8) a reconnect writes, at the pixel a
+ * pixel points to, the largest label around that pixel when it is larger
+ * (atomic maximum over the writers), and the termination check looks for
+ * two neighbouring pixels of the mask with different labels.  The host
+ * waits for the check after every round, as the paper's tool does.
+ * labels_dev (device int32 [height][width]) receives, for each pixel of the
+ * mask, the row-major index y*width+x of its component's largest pixel, -1
+ * for background.  stats (optional) receives the main iterations, rounds
+ * and launches.  height and width must be below 65535 (VLG_ESHAPE);
+ * VLG_ENOCONV when the check still fails after the context's loop cap of
+ * rounds (vlg_set_loop_cap). */
+typedef struct vlg_pj_stats {
+    int64_t main_iterations;
+    int64_t rounds;
+    int64_t launches;
+} vlg_pj_stats;
+int vlg_ccl_labels_pj(vlg_ctx *ctx, const uint64_t *mask_dev, int height, int width, int reconnect_every,
+                      int32_t *labels_dev, vlg_pj_stats *stats);
 
 /* Measurement.  Runs the fused schedule of every output of f on img `iters`
  * times, one launch at a time, with a HIP event recorded on the context's
@@ -246,6 +306,17 @@ typedef struct vlg_kernel_time {
 } vlg_kernel_time;
 int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_kernel_time *out,
                 int max_out, int *n_out);
+/* Measurement of one kernel without per-launch events: enqueues the fused
+ * schedule of every output of f on img up to and including its first
+ * single (ungrouped) step of `kind` ("atoms", "logic", "near", "ccl_local",
+ * "ccl_gather", "segment" or "arith": kinds whose repeated launch redoes
+ * the same work on the same inputs), then that step `reps` times back to
+ * back between two HIP events on the context's stream.  *avg_ms receives
+ * the mean time of one launch of the step, *bytes its algorithmic bytes (as
+ * in vlg_profile).  Synchronises the stream.  VLG_EINVAL when the schedule
+ * has no such step or labels with the pointer-jumping schedule. */
+int vlg_profile_step(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, const char *kind, int reps,
+                     double *avg_ms, double *bytes);
 
 /* Tunables of the executor.  Each has a default, may be forced for a
  * context, and is otherwise looked up per image shape class (ceil(log2 H),
@@ -261,20 +332,36 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
  *     shorter ones give more parallel bands.
  *   VLG_TUNE_BATCH_GRID: workgroups of a persistent batched launch: 1024,
  *     2048, 4096 or 8192 (default).
- *   VLG_TUNE_CCL_LANES: labelling lanes of the fused schedule.  Only 1 is
- *     accepted: concurrent lanes (2 or 4, independent labellings on separate
- *     streams) are switched off while a host-side crash seen with four lanes
- *     is unexplained; other values return VLG_EINVAL.
+ *   VLG_TUNE_CCL_LANES: labellings run together, 1, 2, 4 or 8 (default 1).
+ *     With L > 1 the fused schedule groups up to L independent labellings
+ *     that are ready together into one region, each with its own labelling
+ *     workspace, and each phase of the union-find labelling (tile-local
+ *     pass, merge, flag, gather) runs for all of them in one launch on the
+ *     context's stream.  Needs L labelling workspaces.
  *   VLG_TUNE_FUSE_HALO: fused segments of the fused schedule: runs of
  *     consecutive Boolean and near steps that one tile kernel evaluates with
  *     every intermediate mask in LDS, the tile extended by a halo as deep as
  *     the segment's longest chain of near steps.  The value is the largest
- *     halo allowed (2, 4, 8 or 16 rows; default 8); 1 forms no segments. */
+ *     halo allowed (2, 4, 8 or 16 rows; default 8); 1 forms no segments.
+ *   VLG_TUNE_CCL_ALGO: the labelling behind reach-type nodes (Sect. 3:
+ *     reachability through connected components).  VLG_CCL_UNION_FIND
+ *     (default): union-find over 2x2 blocks in fixed launches, no host wait.
+ *     VLG_CCL_POINTER_JUMPING: the paper's Alg. CCL as vlg_ccl_labels_pj
+ *     runs it, with the host waiting for the termination check after every
+ *     round; an evaluation that labels with it is therefore never captured
+ *     as a graph (graph mode runs it launch by launch), and images need
+ *     rows and columns below 65535.  vlg_check_batch always uses union-find.
+ *   VLG_TUNE_PJ_RECONNECT: main iterations between reconnects of the
+ *     pointer-jumping labelling, 1..64 (default 16). */
 #define VLG_TUNE_CCL_TILE_ROWS 0
 #define VLG_TUNE_NEAR_ROWS 1
 #define VLG_TUNE_BATCH_GRID 2
 #define VLG_TUNE_CCL_LANES 3
 #define VLG_TUNE_FUSE_HALO 4
+#define VLG_TUNE_CCL_ALGO 5
+#define VLG_TUNE_PJ_RECONNECT 6
+#define VLG_CCL_UNION_FIND 1      /* values of VLG_TUNE_CCL_ALGO */
+#define VLG_CCL_POINTER_JUMPING 2
 /* Force `value` for every image (value 0 returns to table/default). */
 int vlg_set_tunable(vlg_ctx *ctx, int which, int value);
 /* The value used for an image of height x width on this context. */

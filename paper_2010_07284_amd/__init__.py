@@ -133,6 +133,45 @@ def load_image(ctx, t):
     return Image(h, (C, H, W), t.dtype)
 
 
+def load_volume(ctx, t):
+    """vlg_load_volume from a torch tensor or numpy array, (C,D,H,W) or
+    (D,H,W), float32, uint8 or uint16, host or device.  The returned image's
+    shape is (C, D*H, W) for mask allocation; image.depth holds D."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.from_numpy(t)
+    if t.dim() == 3:
+        t = t.unsqueeze(0)
+    codes = {torch.float32: 0, torch.uint8: 1, torch.uint16: 2}
+    if t.dim() != 4 or t.dtype not in codes:
+        raise ValueError("volume must be (C,D,H,W) float32, uint8 or uint16")
+    t = t.contiguous()
+    C, D, H, W = t.shape
+    where = 1 if t.is_cuda else 0
+    if where == 1:
+        torch.cuda.current_stream(t.device).synchronize()
+    h = ctypes.c_void_p()
+    _lib.call("vlg_load_volume", ctx.handle, ctypes.c_void_p(t.data_ptr()), codes[t.dtype], C, D, H, W, where,
+              ctypes.byref(h))
+    if where == 1:
+        sync(ctx)
+    im = Image(h, (C, D * H, W), t.dtype)
+    im.depth = D
+    return im
+
+
+def ccl_labels3(ctx, mask, depth, height, width, out=None):
+    """vlg_ccl_labels3 of a packed device volume mask -> int32 [D, H, W] labels
+    (smallest linear index of each 26-component, -1 for background)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((depth, height, width), dtype=torch.int32, device=mask.device)
+    with _Ordered(ctx):
+        _lib.call("vlg_ccl_labels3", ctx.handle, ctypes.c_void_p(mask.data_ptr()), depth, height, width,
+                  ctypes.c_void_p(out.data_ptr()))
+    return out
+
+
 def compile_formula(ctx, src):
     h = ctypes.c_void_p()
     _lib.call("vlg_compile_formula", ctx.handle if ctx else None, src.encode(), ctypes.byref(h))
@@ -234,6 +273,29 @@ def ccl_labels_noalloc(ctx, mask, height, width, out):
 NOALLOC_SCRATCH_BYTES = 40 << 20
 
 
+def ccl_labels_pj(ctx, mask, height, width, reconnect_every=0, out=None):
+    """vlg_ccl_labels_pj: the paper's pointer-jumping labelling of a packed
+    device mask -> (int32 [H, W] labels = largest row-major index of each
+    component, -1 background; {"main_iterations", "rounds", "launches"})."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((height, width), dtype=torch.int32, device=mask.device)
+    st = _lib.PjStats()
+    with _Ordered(ctx):
+        _lib.call("vlg_ccl_labels_pj", ctx.handle, ctypes.c_void_p(mask.data_ptr()), height, width,
+                  int(reconnect_every), ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
+    return out, {name: getattr(st, name) for name, _ in _lib.PjStats._fields_}
+
+
+def profile_step(ctx, f, img, kind, reps=20):
+    """vlg_profile_step: (mean ms of one launch of the first `kind` step,
+    repeated back to back without per-launch events; its algorithmic bytes)."""
+    ms, b = ctypes.c_double(), ctypes.c_double()
+    _lib.call("vlg_profile_step", ctx.handle, f.handle, img.handle, kind.encode(), int(reps), ctypes.byref(ms),
+              ctypes.byref(b))
+    return ms.value, b.value
+
+
 def ccl_counters(ctx):
     c = _lib.CclCounters()
     _lib.call("vlg_ccl_read_counters", ctx.handle, ctypes.byref(c))
@@ -249,7 +311,9 @@ def profile(ctx, f, img, iters=5):
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
 
 
-TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2, "ccl_lanes": 3, "fuse_halo": 4}
+TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2, "ccl_lanes": 3, "fuse_halo": 4,
+            "ccl_algo": 5, "pj_reconnect": 6}
+CCL_UNION_FIND, CCL_POINTER_JUMPING = 1, 2
 
 
 def set_tunable(ctx, name, value):
@@ -367,6 +431,6 @@ def pack(mask):
 
 
 __all__ = ["create", "sync", "set_loop_cap", "set_mode", "load_image", "compile_formula", "formula_info", "formula_plan", "output_names",
-           "check", "check_all", "check_batch", "ccl_labels", "ccl_labels_noalloc", "ccl_counters", "profile", "set_tunable", "get_tunable", "autotune", "tune_save",
+           "check", "check_all", "check_batch", "ccl_labels", "ccl_labels_noalloc", "ccl_labels_pj", "ccl_labels3", "load_volume", "ccl_counters", "profile", "profile_step", "set_tunable", "get_tunable", "autotune", "tune_save",
            "tune_load", "autotune_batch", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

@@ -9,7 +9,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvlg.so")
 EXPORTS = [
     "vlg_create", "vlg_destroy", "vlg_sync", "vlg_set_loop_cap", "vlg_set_mode", "vlg_load_image", "vlg_image_free",
     "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name", "vlg_formula_plan",
-    "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels", "vlg_ccl_labels_noalloc",
+    "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels", "vlg_ccl_labels_noalloc", "vlg_ccl_labels_pj",
+    "vlg_load_volume", "vlg_image_shape3", "vlg_ccl_labels3", "vlg_profile_step",
     "vlg_ccl_read_counters", "vlg_profile", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune", "vlg_autotune_batch",
     "vlg_tune_save", "vlg_tune_load", "vlg_server_create", "vlg_server_submit", "vlg_server_wait",
     "vlg_server_read_stats", "vlg_server_destroy", "vlg_evaluation_bytes", "vlg_last_error",
@@ -47,7 +48,12 @@ class ServerStats(ctypes.Structure):
 
 
 class CclCounters(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int64) for n in ("merge_unions", "merge_retries", "launches_per_ccl")]
+    _fields_ = [(n, ctypes.c_int64) for n in ("merge_unions", "merge_retries", "launches_per_ccl", "pj_labellings",
+                                              "pj_main_iterations", "pj_rounds", "pj_launches")]
+
+
+class PjStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("main_iterations", "rounds", "launches")]
 
 
 _lib = None
@@ -84,6 +90,11 @@ def lib():
             "vlg_check_batch": ([P, P, P, I, P, I, I], I),
             "vlg_ccl_labels": ([P, P, I, I, P], I),
             "vlg_ccl_labels_noalloc": ([P, P, I, I, P], I),
+            "vlg_ccl_labels_pj": ([P, P, I, I, I, P, P], I),
+            "vlg_load_volume": ([P, P, I, I, I, I, I, I, P], I),
+            "vlg_image_shape3": ([P, P, P, P, P], I),
+            "vlg_ccl_labels3": ([P, P, I, I, I, P], I),
+            "vlg_profile_step": ([P, P, P, ctypes.c_char_p, I, P, P], I),
             "vlg_ccl_read_counters": ([P, P], I),
             "vlg_profile": ([P, P, P, I, P, I, P], I),
             "vlg_set_tunable": ([P, I, I], I),

@@ -22,6 +22,7 @@
 using namespace vlg;
 
 static_assert(kMaxPctSel == kMaxPctPerStep, "percentile selections per step");
+static_assert(kMaxCclLanes <= kMaxMulti, "a region's labellings fit one multi-launch");
 
 namespace {
 
@@ -111,7 +112,8 @@ struct vlg_formula {
 
 struct vlg_image {
     int device;
-    int dtype, C, H, W;
+    int dtype, C, H, W;   // H: rows of all slices together
+    int D = 1, S = 0;     // a volume: D slices of S rows (S = H / D); an image: D = 1
     int64_t pitch;  // elements per row (wpr * 64)
     void *dev;      // from the device's stream-ordered pool (hipMallocAsync)
     size_t bytes;
@@ -156,27 +158,26 @@ struct GraphKey {
 };
 
 // Tunables (VLG_TUNE_*): a value of 0 means "not set" (default rule).
-constexpr int kNumTunables = 5;
+constexpr int kNumTunables = 7;
 const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid", "ccl_lanes",
-                                                 "fuse_halo"};
+                                                 "fuse_halo",     "ccl_algo",       "pj_reconnect"};
+constexpr int kPjReconnectDefault = 16;
 
 bool tunable_valid(int which, int v) {
     switch (which) {
     case VLG_TUNE_CCL_TILE_ROWS: return valid_tile_bh(v);
     case VLG_TUNE_NEAR_ROWS: return valid_near_rows(v);
     case VLG_TUNE_BATCH_GRID: return valid_batch_grid(v);
-    // Concurrent labelling lanes are switched off: with four lanes a
-    // vlg_check_all call ended twice in a host-side segmentation fault whose
-    // cause is not found, so only the sequential schedule (one lane) is
-    // accepted until it is.
-    case VLG_TUNE_CCL_LANES: return v == 1;
+    case VLG_TUNE_CCL_LANES: return v == 1 || v == 2 || v == 4 || v == 8;
     case VLG_TUNE_FUSE_HALO: return valid_fuse_halo(v);
+    case VLG_TUNE_CCL_ALGO: return v == VLG_CCL_UNION_FIND || v == VLG_CCL_POINTER_JUMPING;
+    case VLG_TUNE_PJ_RECONNECT: return v >= 1 && v <= 64;
     }
     return false;
 }
 
 struct Tuning {
-    int v[kNumTunables] = {0, 0, 0, 0, 0};
+    int v[kNumTunables] = {};
 };
 
 struct vlg_ctx {
@@ -187,12 +188,6 @@ struct vlg_ctx {
     std::map<std::pair<int, int>, Tuning> tuned_batch;  // (batch class, mean image class) -> tuning
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // streams of labelling lanes 1.. (lane 0 runs on `stream`) and the events
-    // that fork them from and join them back into `stream`
-    // (created on first use)
-    hipStream_t lane_stream[kMaxCclLanes - 1] = {};
-    hipEvent_t fork_ev = nullptr;
-    hipEvent_t join_ev[kMaxCclLanes - 1] = {};
     int mode = VLG_MODE_GRAPH;
     int loop_cap = kLoopCapDefault;  // iterations per labelling walk (vlg_set_loop_cap)
     void *ws = nullptr;
@@ -205,6 +200,9 @@ struct vlg_ctx {
     unsigned int *status() const { return (unsigned int *)(counters + 2); }
     LoopGuard guard() const { return LoopGuard{status(), loop_cap}; }
     bool count_ccl = false;         // collect merge counters (VLG_CCL_COUNTERS=1)
+    // pointer-jumping labellings since the counters were last read: main
+    // iterations, rounds (reconnect + termination check), kernel launches
+    int64_t pj_iters = 0, pj_rounds = 0, pj_launches = 0, pj_labellings = 0;
     std::map<GraphKey, hipGraphExec_t> graphs;
     // pinned host staging of batch descriptors; `desc_done` marks the end of
     // the last upload from it
@@ -240,15 +238,6 @@ int check_status(vlg_ctx *c) {
     return VLG_OK;
 }
 
-// Streams and events of labelling lanes 1.., created on first use.
-int ensure_lane_streams(vlg_ctx *c) {
-    for (int l = 0; l < kMaxCclLanes - 1; l++) {
-        if (!c->lane_stream[l]) HIP_TRY(hipStreamCreateWithFlags(&c->lane_stream[l], hipStreamNonBlocking));
-        if (!c->join_ev[l]) HIP_TRY(hipEventCreateWithFlags(&c->join_ev[l], hipEventDisableTiming));
-    }
-    if (!c->fork_ev) HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-    return VLG_OK;
-}
 
 // Workspace layout of one evaluation.
 struct Layout {
@@ -256,9 +245,14 @@ struct Layout {
     size_t off_slots = 0, off_stage = 0, off_u8 = 0, off_glab = 0, off_gflag = 0, off_pct = 0,
            off_pctst = 0, total = 0;
     size_t lane_bytes = 0;  // labelling workspace of lane l at off_glab / off_gflag + l * lane_bytes
+    bool pj = false;        // pointer-jumping labelling: its arrays (pj_work) start at off_glab
+    bool vol = false;       // volume labelling: voxel parents (4 B) then flag bytes at off_glab
 };
 
-Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8) {
+size_t vol_label_bytes(const Geo &g) { return align256((size_t)g.H * g.W * 4); }
+
+Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8, bool pj = false,
+                  bool vol = false) {
     Layout L;
     L.mask_bytes = align256((size_t)g.nwords * 8);
     size_t off = 0;
@@ -270,7 +264,12 @@ Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8)
     if (stage_u8) off += (size_t)P.noutputs * align256((size_t)g.H * g.W);
     L.off_glab = off;
     const size_t nb = (size_t)g.BH * g.BW;
-    L.lane_bytes = P.ccl_count > 0 ? align256(nb * 4) + align256(nb) : 0;
+    L.pj = pj && !vol;
+    L.vol = vol;
+    L.lane_bytes = P.ccl_count == 0 ? 0
+                   : vol          ? vol_label_bytes(g) + align256((size_t)g.H * g.W)
+                   : L.pj         ? align256(pj_bytes(g))
+                                  : align256(nb * 4) + align256(nb);
     L.off_gflag = off + (P.ccl_count > 0 ? align256(nb * 4) : 0);
     off += (size_t)std::max(P.ccl_lanes, 1) * L.lane_bytes;
     L.off_pct = off;
@@ -360,6 +359,7 @@ const char *kind_name(SK k) {
     case SK::CclGather: return "ccl_gather";
     case SK::CclReseed: return "ccl_reseed";
     case SK::Segment: return "segment";
+    case SK::Arith: return "arith";
     }
     return "?";
 }
@@ -387,6 +387,12 @@ double algorithmic_bytes(const Plan &P, const Step &s, const Geo &g, int dtype, 
     case SK::CclFlag: return nb;                                      // flags read
     case SK::CclGather: return ins({s.x, s.y, s.z}) + nb * 4.0 + mb;  // labels read
     case SK::CclReseed: return ins({s.x});                            // seed mask read
+    case SK::Arith: {  // every channel the program reads, once, and the mask
+        std::vector<int32_t> ch;
+        for (const ArInstr &in : P.ariths[(size_t)s.arith].ins)
+            if (in.op == AR_CHAN && std::find(ch.begin(), ch.end(), in.chan) == ch.end()) ch.push_back(in.chan);
+        return npix * (dtype == VLG_U8 ? 1.0 : dtype == VLG_U16 ? 2.0 : 4.0) * (double)ch.size() + mb;
+    }
     case SK::Segment: {                                               // loads + stores
         const Segment &S = P.segments[(size_t)s.seg];
         return (double)(S.inputs.size() + S.outputs.size()) * mb;
@@ -395,14 +401,75 @@ double algorithmic_bytes(const Plan &P, const Step &s, const Geo &g, int dtype, 
     return 0.0;
 }
 
+// The labelling schedule of reach-type nodes for an image of H x W
+// (VLG_TUNE_CCL_ALGO; default union-find).
+int ccl_algo(const vlg_ctx *c, int H, int W) {
+    const int v = tuned_value(c, VLG_TUNE_CCL_ALGO, H, W);
+    return v == VLG_CCL_POINTER_JUMPING ? v : VLG_CCL_UNION_FIND;
+}
+
+int pj_reconnect_every(const vlg_ctx *c, int H, int W) {
+    const int v = tuned_value(c, VLG_TUNE_PJ_RECONNECT, H, W);
+    return v >= 1 ? v : kPjReconnectDefault;
+}
+
+// The paper's labelling of b (Sect. 3, Alg. CCL): initialization, then
+// rounds of k main iterations, one reconnect and the termination check, the
+// host waiting for the check's word after every round as the paper's tool
+// does.  On return the labels are in w.lab[at].  VLG_ENOCONV when the check
+// still fails after the context's loop cap of rounds.
+int pj_label(vlg_ctx *c, hipStream_t s, const Geo &g, MRef b, const PjWork &w, int k, int &at) {
+    HIP_TRY(launch_pj_init(s, g, b, w));
+    at = 0;
+    int64_t launches = 1;
+    for (int64_t round = 0;; round++) {
+        if (round >= c->loop_cap)
+            return fail(VLG_ENOCONV, "pointer-jumping labelling: the termination check still fails after " +
+                                         std::to_string(round) + " rounds (the loop cap)");
+        for (int it = 0; it < k; it++) {
+            HIP_TRY(launch_pj_main(s, g, b, w, at));
+            at ^= 1;
+        }
+        HIP_TRY(launch_pj_reconnect(s, g, b, w, at));
+        at ^= 1;
+        HIP_TRY(launch_pj_check(s, g, b, w, at));
+        launches += k + 4;
+        c->pj_iters += k;
+        c->pj_rounds++;
+        HIP_TRY(hipMemcpyAsync(c->status_host + 1, w.term, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c->status_host[1] == 0) break;
+    }
+    c->pj_launches += launches;
+    c->pj_labellings++;
+    return VLG_OK;
+}
+
+// The kernel form of an Arith step's program.
+ArithLaunch arith_launch(const Plan &P, const Step &s) {
+    const ArProgram &pr = P.ariths[(size_t)s.arith];
+    ArithLaunch a;
+    std::memset(&a, 0, sizeof a);
+    a.n = (int32_t)pr.ins.size();
+    a.lhs_len = pr.lhs_len;
+    a.cmp = s.op;
+    for (size_t k = 0; k < pr.ins.size() && k < (size_t)kArithMax; k++) {
+        a.ins[k].op = pr.ins[k].op;
+        a.ins[k].idx = pr.ins[k].op == AR_PCT ? pr.ins[k].pct : pr.ins[k].chan;
+        a.ins[k].c = pr.ins[k].c;
+    }
+    return a;
+}
+
 using StepHook = void (*)(void *, size_t, bool);
 
 // Enqueue every step of P on the stream.  ext[k] is the packed device buffer
 // of external slot k.  hook (optional) runs before and after each step.
 // base_ (optional) is the workspace to use instead of the context's.
+// [first, last) (optional) restricts the steps enqueued.
 int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &L,
                  const std::vector<uint64_t *> &ext, StepHook hook = nullptr, void *hook_ctx = nullptr,
-                 char *base_ = nullptr) {
+                 char *base_ = nullptr, size_t first = 0, size_t last = SIZE_MAX) {
     const Geo g = make_geo(img->H, img->W);
     char *base = base_ ? base_ : (char *)c->ws;
     auto slot_ptr = [&](int32_t s) -> uint64_t * {
@@ -423,50 +490,102 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
     w0.tbh = tuning_for(c, img->H, img->W).ccl_tbh;
     const int near_rows = tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W);
     const int64_t npix = (int64_t)img->H * img->W;
-    // concurrent regions: the steps of a span with lanes run on the lanes'
-    // streams, forked from the main stream at the region's start and joined
-    // back into it at its end (events; captured as graph dependencies)
-    int open_span = -1;
-    uint32_t open_lanes = 0;
-    auto join = [&]() -> int {
-        for (int l = 1; l < kMaxCclLanes; l++) {
-            if (!(open_lanes >> l & 1)) continue;
-            HIP_TRY(hipEventRecord(c->join_ev[l - 1], c->lane_stream[l - 1]));
-            HIP_TRY(hipStreamWaitEvent(c->stream, c->join_ev[l - 1], 0));
-        }
-        open_span = -1;
-        open_lanes = 0;
-        return VLG_OK;
-    };
-    for (size_t si = 0; si < P.steps.size(); si++) {
-        const Step &s = P.steps[si];
-        if (open_span >= 0 && (s.lane < 0 || s.span != open_span)) {
-            int rc = join();
-            if (rc != VLG_OK) return rc;
-        }
-        if (s.lane >= 0 && open_span < 0) {
-            for (size_t sj = si; sj < P.steps.size() && P.steps[sj].span == s.span && P.steps[sj].lane >= 0; sj++)
-                open_lanes |= 1u << P.steps[sj].lane;
-            if (open_lanes > 1) {
-                const int rl = ensure_lane_streams(c);
-                if (rl != VLG_OK) return rl;
-                HIP_TRY(hipEventRecord(c->fork_ev, c->stream));
-                for (int l = 1; l < kMaxCclLanes; l++)
-                    if (open_lanes >> l & 1) HIP_TRY(hipStreamWaitEvent(c->lane_stream[l - 1], c->fork_ev, 0));
-            }
-            open_span = s.span;
-        }
-        const int lane = s.lane > 0 ? s.lane : 0;
-        hipStream_t stream = lane > 0 ? c->lane_stream[lane - 1] : c->stream;
+    // pointer-jumping labellings (L.pj): the label array the current
+    // labelling's steps read
+    const int pj_k = pj_reconnect_every(c, img->H, img->W);
+    int pj_at = 0;
+    // volumes: N over 26 neighbours, voxel labelling (L.vol)
+    const bool vol = img->D > 1;
+    const int vS = img->S, vD = img->D;
+    // The labellings of a concurrent region (steps of one span with lanes,
+    // each lane with its own labelling workspace) run on the context's
+    // stream: the union-find phases of all lanes go into one launch each
+    // (blockIdx.y = lane), the other steps launch one by one, every lane's
+    // steps in their order.  Pointer-jumping and volume labellings run the
+    // region's steps in plan order.
+    auto lane_work = [&](int lane) {
         CclWork w = w0;
         w.glab = (int32_t *)(base + L.off_glab + (size_t)lane * L.lane_bytes);
         w.gflag = (uint8_t *)(base + L.off_gflag + (size_t)lane * L.lane_bytes);
+        return w;
+    };
+    auto run_region = [&](size_t r0, size_t r1) -> int {
+        std::vector<std::vector<size_t>> q((size_t)kMaxCclLanes);
+        for (size_t k = r0; k < r1; k++) q[(size_t)P.steps[k].lane].push_back(k);
+        std::vector<size_t> head(q.size(), 0);
+        // one level per iteration: each lane's next step as it stood at the
+        // iteration's start, so the lanes' phases line up
+        for (;;) {
+            bool any = false;
+            const std::vector<size_t> at = head;
+            for (SK kind : {SK::CclLocal, SK::CclMerge, SK::CclFlag, SK::CclGather}) {
+                CclMulti m;
+                std::memset(&m, 0, sizeof m);
+                for (size_t l = 0; l < q.size(); l++) {
+                    if (at[l] >= q[l].size() || head[l] != at[l] || P.steps[q[l][at[l]]].kind != kind) continue;
+                    const Step &t = P.steps[q[l][head[l]++]];
+                    const CclWork lw = lane_work((int)l);
+                    m.b[m.n] = mref(t.x);
+                    m.y[m.n] = mref(t.y);
+                    m.z[m.n] = mref(t.z);
+                    m.glab[m.n] = lw.glab;
+                    m.gflag[m.n] = lw.gflag;
+                    m.user[m.n] = t.user;
+                    m.out[m.n] = slot_ptr(t.out);
+                    m.n++;
+                }
+                if (m.n == 0) continue;
+                any = true;
+                hipError_t e = kind == SK::CclLocal   ? launch_ccl_local_multi(c->stream, g, m, w0)
+                               : kind == SK::CclMerge ? launch_ccl_merge_multi(c->stream, g, m, w0)
+                               : kind == SK::CclFlag  ? launch_ccl_flag_multi(c->stream, g, m, w0)
+                                                      : launch_ccl_gather_multi(c->stream, g, m);
+                if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+            }
+            for (size_t l = 0; l < q.size(); l++) {
+                if (at[l] >= q[l].size() || head[l] != at[l]) continue;
+                const Step &t = P.steps[q[l][head[l]]];
+                hipError_t e = hipSuccess;
+                if (t.kind == SK::Logic)
+                    e = launch_logic(c->stream, g, mref(t.x), mref(t.y), t.op, t.inv_out, slot_ptr(t.out));
+                else if (t.kind == SK::Near)
+                    e = launch_near(c->stream, g, mref(t.x), t.inv_out, mref(t.z), t.op, slot_ptr(t.out), near_rows);
+                else if (t.kind == SK::CclReseed)
+                    e = launch_ccl_reseed(c->stream, g, mref(t.x), lane_work((int)l), t.user);
+                else
+                    continue;  // a labelling phase: next round
+                head[l]++;
+                any = true;
+                if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+            }
+            if (!any) break;
+        }
+        for (size_t l = 0; l < q.size(); l++)
+            if (head[l] < q[l].size()) return fail(VLG_EINVAL, "internal: a region step of an unexpected kind");
+        return VLG_OK;
+    };
+    for (size_t si = first; si < P.steps.size() && si < last; si++) {
+        const Step &s = P.steps[si];
+        if (s.lane >= 0 && !L.pj && !vol && !hook) {
+            size_t sj = si;
+            while (sj < P.steps.size() && sj < last && P.steps[sj].span == s.span && P.steps[sj].lane >= 0) sj++;
+            const int rc = run_region(si, sj);
+            if (rc != VLG_OK) return rc;
+            si = sj - 1;
+            continue;
+        }
+        const int lane = s.lane > 0 ? s.lane : 0;
+        hipStream_t stream = c->stream;
+        CclWork w = lane_work(lane);
+        const PjWork pw = pj_work(base + L.off_glab + (size_t)lane * L.lane_bytes, g);
+        int *vP = (int *)(base + L.off_glab + (size_t)lane * L.lane_bytes);
+        uint8_t *vflag = (uint8_t *)vP + vol_label_bytes(g);
         if (hook) hook(hook_ctx, si, true);
         hipError_t e = hipSuccess;
         if (s.group >= 0) {
             // a batched group: consecutive Logic (or Near) steps, one launch
             size_t sj = si;
-            while (sj + 1 < P.steps.size() && P.steps[sj + 1].group == s.group) sj++;
+            while (sj + 1 < P.steps.size() && sj + 1 < last && P.steps[sj + 1].group == s.group) sj++;
             if (s.kind == SK::Logic) {
                 LogicBatch b;
                 b.n = (int)(sj - si + 1);
@@ -475,6 +594,11 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                     b.ops[k - si] = LogicOp{mref(t.x), mref(t.y), t.inv_out ? ~0ull : 0ull, slot_ptr(t.out), t.op};
                 }
                 e = launch_logic_batch(stream, g, b);
+            } else if (vol) {
+                for (size_t k = si; k <= sj && e == hipSuccess; k++) {
+                    const Step &t = P.steps[k];
+                    e = launch_near3(stream, g, vS, vD, mref(t.x), t.inv_out, mref(t.z), t.op, slot_ptr(t.out));
+                }
             } else {
                 NearBatch b;
                 b.n = (int)(sj - si + 1);
@@ -523,25 +647,57 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         case SK::Logic:
             e = launch_logic(stream, g, mref(s.x), mref(s.y), s.op, s.inv_out, slot_ptr(s.out));
             break;
+        case SK::Arith:
+            e = launch_arith(stream, g, img->dev, (int64_t)img->H * img->pitch, img->dtype, arith_launch(P, s), pct,
+                             slot_ptr(s.out));
+            break;
         case SK::Near:
-            e = launch_near(stream, g, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out), near_rows);
+            if (vol)
+                e = launch_near3(stream, g, vS, vD, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out));
+            else
+                e = launch_near(stream, g, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out), near_rows);
             break;
         case SK::CclLocal:
-            e = launch_ccl_local(stream, g, mref(s.x), mref(s.y), mref(s.z), w);
+            if (L.vol) {
+                // the whole voxel labelling, then the seeds
+                e = launch_vl_label(stream, g, vS, vD, mref(s.x), vP, w.guard);
+                if (e == hipSuccess) e = launch_vl_clear_flags(stream, g, vflag);
+                if (e == hipSuccess) e = launch_vl_seed(stream, g, vS, vD, mref(s.x), mref(s.y), mref(s.z), vP, vflag, 0);
+            } else if (L.pj) {
+                // the whole labelling (host-waited rounds), then the seeds
+                const int rc = pj_label(c, stream, g, mref(s.x), pw, pj_k, pj_at);
+                if (rc != VLG_OK) return rc;
+                e = launch_pj_clear_flags(stream, g, pw);
+                if (e == hipSuccess) e = launch_pj_seed(stream, g, mref(s.x), mref(s.y), mref(s.z), pw, pj_at, 0);
+            } else {
+                e = launch_ccl_local(stream, g, mref(s.x), mref(s.y), mref(s.z), w);
+            }
             break;
-        case SK::CclMerge:
-            e = launch_ccl_merge(stream, g, mref(s.x), w);
+        case SK::CclMerge:  // the pointer-jumping and voxel labellings have no merge or flag pass
+            if (!L.pj && !L.vol) e = launch_ccl_merge(stream, g, mref(s.x), w);
             break;
         case SK::CclFlag:
-            e = launch_ccl_flag(stream, g, w);
+            if (!L.pj && !L.vol) e = launch_ccl_flag(stream, g, w);
             break;
         case SK::CclGather:
-            e = launch_ccl_gather(stream, g, mref(s.x), mref(s.y), mref(s.z), w, s.user, slot_ptr(s.out));
+            if (L.vol)
+                e = launch_vl_gather(stream, g, vS, vD, mref(s.x), mref(s.y), mref(s.z), vP, vflag, s.user,
+                                     slot_ptr(s.out));
+            else if (L.pj)
+                e = launch_pj_gather(stream, g, mref(s.x), mref(s.y), mref(s.z), pw, pj_at, s.user, slot_ptr(s.out));
+            else
+                e = launch_ccl_gather(stream, g, mref(s.x), mref(s.y), mref(s.z), w, s.user, slot_ptr(s.out));
             break;
         case SK::CclReseed:
-            e = launch_ccl_reseed(stream, g, mref(s.x), w, s.user);
+            if (L.vol)
+                e = launch_vl_reseed(stream, g, vS, vD, mref(s.x), vP, vflag, s.user);
+            else if (L.pj)
+                e = launch_pj_reseed(stream, g, mref(s.x), pw, pj_at, s.user);
+            else
+                e = launch_ccl_reseed(stream, g, mref(s.x), w, s.user);
             break;
         case SK::Segment: {
+            if (vol) return fail(VLG_EINVAL, "internal: no fused segments on volumes");
             const Segment &S = P.segments[(size_t)s.seg];
             SegProg sp;
             std::memset(&sp, 0, sizeof sp);
@@ -566,7 +722,6 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
         if (hook) hook(hook_ctx, si, false);
     }
-    if (open_span >= 0) return join();
     return VLG_OK;
 }
 
@@ -581,13 +736,19 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
     if (img->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
     DeviceGuard dg(c->device);
     const Mode m = c->mode == VLG_MODE_PEROP ? Mode::PerOp : Mode::Fused;
+    const bool vol = img->D > 1;  // volumes: no fused segments, voxel labelling
     const Plan &P = f->plan(which, m, m == Mode::Fused ? tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W) : 1,
-                            tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
+                            vol ? 1 : tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
     const Geo g = make_geo(img->H, img->W);
     if (g.nwords == 0 || which.empty()) return VLG_OK;
     const bool direct = fmt == VLG_PACKED64 && where == VLG_DEVICE;
     const bool stage_u8 = fmt == VLG_U8MASK && where == VLG_HOST;
-    Layout L = layout_for(P, g, !direct, stage_u8);
+    // the pointer-jumping labelling waits on the host between its rounds, so
+    // a formula that labels with it is never captured as a graph
+    const bool pj = !vol && P.ccl_count > 0 && ccl_algo(c, img->H, img->W) == VLG_CCL_POINTER_JUMPING;
+    if (pj && !pj_shape_ok(img->H, img->W))
+        return fail(VLG_ESHAPE, "pointer-jumping labelling: rows and columns must stay below 65535");
+    Layout L = layout_for(P, g, !direct, stage_u8, pj, vol);
     int rc = ensure_ws(c, L.total);
     if (rc != VLG_OK) return rc;
     char *base = (char *)c->ws;
@@ -611,12 +772,13 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
         return VLG_OK;
     };
 
-    if (c->mode == VLG_MODE_GRAPH) {
+    if (c->mode == VLG_MODE_GRAPH && !pj) {
         GraphKey key;
         key.v = {(uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)img->dev, (uintptr_t)img->H, (uintptr_t)img->W,
                  (uintptr_t)img->dtype, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)c->ws,
                  (uintptr_t)tuning_for(c, img->H, img->W).ccl_tbh,
-                 (uintptr_t)tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W), (uintptr_t)c->loop_cap};
+                 (uintptr_t)tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W), (uintptr_t)c->loop_cap,
+                 (uintptr_t)img->D};
         for (size_t k = 0; k < which.size(); k++) key.v.push_back((uintptr_t)outs[k]);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -865,6 +1027,19 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                 break;
             case SK::Segment:
                 return fail(VLG_EINVAL, "internal: the batched schedule has no segments");
+            case SK::Arith: {
+                // one launch per image: the arithmetic kernel has no batched form
+                const ArithLaunch al = arith_launch(P, s);
+                for (int k = 0; k < n && e == hipSuccess; k++) {
+                    const vlg_image *im = imgs[idx[k]];
+                    char *wb = base + off[k];
+                    uint64_t *o = is_ext(s.out) ? ext[(size_t)k * nout + (size_t)ext_index(s.out)]
+                                                : (uint64_t *)(wb + lay[k].off_slots + (size_t)s.out * lay[k].mask_bytes);
+                    e = launch_arith(c->stream, geo[k], im->dev, (int64_t)im->H * im->pitch, im->dtype, al,
+                                     (const float *)(wb + lay[k].off_pct), o);
+                }
+                break;
+            }
             }
             if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
         }
@@ -946,8 +1121,9 @@ size_t evaluation_footprint(vlg_formula *f, const vlg_image *img) {
     std::vector<int> all(f->dag.outputs.size());
     for (size_t i = 0; i < all.size(); i++) all[i] = (int)i;
     // server slots run one labelling lane and the default segment halo cap
-    const Plan &P = f->plan(all, Mode::Fused, 1, kFuseHaloDefault);
-    return layout_for(P, make_geo(img->H, img->W), false, false).total;
+    const bool vol = img->D > 1;
+    const Plan &P = f->plan(all, Mode::Fused, 1, vol ? 1 : kFuseHaloDefault);
+    return layout_for(P, make_geo(img->H, img->W), false, false, false, vol).total;
 }
 int evaluate_all_on(vlg_ctx *c, vlg_formula *f, const vlg_image *img, void *const *outs, void *ws, size_t ws_size) {
     c->ws = ws;
@@ -990,16 +1166,32 @@ int tune_loop(vlg_ctx *c, const std::vector<std::pair<int, std::vector<int>>> &s
         double best_ms = 1e30;
         for (int cand : space[t].second) {
             c->forced.v[which] = cand;
-            rc = run();  // warm-up
-            if (rc == VLG_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
-            for (int it = 0; it < iters && rc == VLG_OK; it++) rc = run();
+            // the warm-up is timed too: a candidate more than 8x slower than
+            // the best so far is not timed again
             float ms = 0.f;
+            if (hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
+            if (rc == VLG_OK) rc = run();  // warm-up
             if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                 rc = fail(VLG_EHIP, "event timing");
+            int timed = 1;
+            if (rc == VLG_OK && ms < 8.0 * best_ms) {
+                if (hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
+                for (int it = 0; it < iters && rc == VLG_OK; it++) rc = run();
+                if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess ||
+                                     hipEventSynchronize(e1) != hipSuccess ||
+                                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = fail(VLG_EHIP, "event timing");
+                timed = iters;
+            }
+            if (rc == VLG_ENOCONV && which == VLG_TUNE_CCL_ALGO) {
+                rc = VLG_OK;  // a labelling that did not terminate within the cap is not a candidate
+                (void)hipStreamSynchronize(c->stream);
+                continue;
+            }
             if (rc != VLG_OK) break;
             rep.candidates[rep.n] = cand;
-            rep.ms[rep.n] = ms / iters;
+            rep.ms[rep.n] = ms / timed;
             if (rep.ms[rep.n] < best_ms) {
                 best_ms = rep.ms[rep.n];
                 rep.best = cand;
@@ -1104,14 +1296,6 @@ void vlg_destroy(vlg_ctx *c) {
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->desc_host) (void)hipHostFree(c->desc_host);
     if (c->desc_done) (void)hipEventDestroy(c->desc_done);
-    for (int l = 0; l < kMaxCclLanes - 1; l++) {
-        if (c->lane_stream[l]) {
-            (void)hipStreamSynchronize(c->lane_stream[l]);
-            (void)hipStreamDestroy(c->lane_stream[l]);
-        }
-        if (c->join_ev[l]) (void)hipEventDestroy(c->join_ev[l]);
-    }
-    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1206,6 +1390,41 @@ int vlg_image_shape(const vlg_image *img, int *channels, int *height, int *width
     return VLG_OK;
 }
 
+int vlg_load_volume(vlg_ctx *c, const void *data, int dtype, int channels, int depth, int height, int width,
+                    int where, vlg_image **out) {
+    if (out) *out = nullptr;
+    if (depth < 1 || height < 0 || width < 0) return fail(VLG_ESHAPE, "bad volume shape");
+    if ((int64_t)depth * height * width >= (1ll << 31) || (int64_t)depth * height >= (1ll << 31))
+        return fail(VLG_ESHAPE, "volume too large (D*H*W >= 2^31)");
+    // [C][D][H][W] with rows of W elements is [C][D*H][W]: loaded as D*H rows
+    const int rc = vlg_load_image(c, data, dtype, channels, depth * height, width, width, where, out);
+    if (rc != VLG_OK) return rc;
+    (*out)->D = depth;
+    (*out)->S = height;
+    return VLG_OK;
+}
+
+int vlg_image_shape3(const vlg_image *img, int *channels, int *depth, int *height, int *width) {
+    if (!img) return fail(VLG_EINVAL, "null image");
+    if (channels) *channels = img->C;
+    if (depth) *depth = img->D;
+    if (height) *height = img->D > 1 ? img->S : img->H;
+    if (width) *width = img->W;
+    return VLG_OK;
+}
+
+int vlg_ccl_labels3(vlg_ctx *c, const uint64_t *mask_dev, int depth, int height, int width, int32_t *labels_dev) {
+    const int64_t n = (int64_t)depth * height * width;
+    if (!c || (!mask_dev && n > 0) || (!labels_dev && n > 0)) return fail(VLG_EINVAL, "null argument");
+    if (depth < 1 || height < 0 || width < 0 || n >= (1ll << 31)) return fail(VLG_ESHAPE, "bad volume shape");
+    DeviceGuard dg(c->device);
+    const Geo g = make_geo(depth * height, width);
+    if (g.nwords == 0) return VLG_OK;
+    // the caller's label array is the parent array of the labelling
+    HIP_TRY(launch_vl_label(c->stream, g, height, depth, MRef{mask_dev, 0ull}, (int *)labels_dev, c->guard()));
+    return VLG_OK;
+}
+
 int vlg_compile_formula(vlg_ctx *c, const char *src, vlg_formula **out) {
     (void)c;
     if (!src || !out) return fail(VLG_EINVAL, "null argument");
@@ -1223,6 +1442,9 @@ int vlg_compile_formula(vlg_ctx *c, const char *src, vlg_formula **out) {
             if (n.pct) f->max_chan = std::max(f->max_chan, n.pchan);
         }
     }
+    for (const ArProgram &pr : f->dag.ariths)
+        for (const ArInstr &in : pr.ins)
+            if (in.op == AR_CHAN || in.op == AR_PCT) f->max_chan = std::max(f->max_chan, in.chan);
     *out = f.release();
     return VLG_OK;
 }
@@ -1264,7 +1486,21 @@ int vlg_formula_plan(const vlg_formula *cf, int mode, int fuse_halo, char *buf, 
                               (double)e.thr, e.pct, e.out);
                 t += tmp;
             }
-            t += "]}";
+            t += "]";
+            if (st.kind == SK::Arith) {
+                // [op, channel or percentile scalar, constant]; the left side first
+                const ArProgram &pr = P.ariths[(size_t)st.arith];
+                std::snprintf(tmp, sizeof tmp, ", \"lhs_len\": %d, \"arith\": [", pr.lhs_len);
+                t += tmp;
+                for (size_t q = 0; q < pr.ins.size(); q++) {
+                    const ArInstr &in = pr.ins[q];
+                    std::snprintf(tmp, sizeof tmp, "%s[%d, %d, %.9g]", q ? ", " : "", (int)in.op,
+                                  in.op == AR_PCT ? in.pct : in.chan, (double)in.c);
+                    t += tmp;
+                }
+                t += "]";
+            }
+            t += "}";
         }
         t += "], \"segments\": [";
         for (size_t k = 0; k < P.segments.size(); k++) {
@@ -1371,6 +1607,8 @@ int vlg_check_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *i
     const size_t nout = f->dag.outputs.size();
     for (int i = 0; i < n; i++) {
         if (!imgs[i]) return fail(VLG_EINVAL, "null image in batch");
+        if (imgs[i]->D > 1)
+            return fail(VLG_EINVAL, "image " + std::to_string(i) + " is a volume: volumes are evaluated one at a time");
         if (f->max_chan >= imgs[i]->C)
             return fail(VLG_ESHAPE, "image " + std::to_string(i) + " lacks channel " + std::to_string(f->max_chan));
         if (imgs[i]->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
@@ -1437,11 +1675,15 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
     DeviceGuard dg(c->device);
     std::vector<int> which(f->dag.outputs.size());
     for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
-    const Plan &P = f->plan(which, Mode::Fused, 1, tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
+    const Plan &P = f->plan(which, Mode::Fused, 1, img->D > 1 ? 1 : tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
     const Geo g = make_geo(img->H, img->W);
     *n_out = 0;
     if (g.nwords == 0 || which.empty()) return VLG_OK;
-    Layout L = layout_for(P, g, true, false);
+    const bool vol = img->D > 1;
+    const bool pj = !vol && P.ccl_count > 0 && ccl_algo(c, img->H, img->W) == VLG_CCL_POINTER_JUMPING;
+    if (pj && !pj_shape_ok(img->H, img->W))
+        return fail(VLG_ESHAPE, "pointer-jumping labelling: rows and columns must stay below 65535");
+    Layout L = layout_for(P, g, true, false, pj, vol);
     int rc = ensure_ws(c, L.total);
     if (rc != VLG_OK) return rc;
     std::vector<uint64_t *> ext(which.size());
@@ -1476,7 +1718,16 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
     if (rc != VLG_OK) return rc;
     std::vector<vlg_kernel_time> kinds;
     for (size_t si = 0; si < P.steps.size(); si++) {
-        const char *nm = kind_name(P.steps[si].kind);
+        const SK kind = P.steps[si].kind;
+        if ((pj || vol) && (kind == SK::CclMerge || kind == SK::CclFlag)) continue;  // not run
+        const char *nm = vol && kind == SK::CclLocal    ? "vol_label"
+                         : vol && kind == SK::CclGather ? "vol_gather"
+                         : vol && kind == SK::CclReseed ? "vol_reseed"
+                         : vol && kind == SK::Near      ? "near3"
+                         : pj && kind == SK::CclLocal    ? "pj_label"
+                         : pj && kind == SK::CclGather ? "pj_gather"
+                         : pj && kind == SK::CclReseed ? "pj_reseed"
+                                                       : kind_name(kind);
         auto it = std::find_if(kinds.begin(), kinds.end(),
                                [&](const vlg_kernel_time &k) { return std::strcmp(k.name, nm) == 0; });
         if (it == kinds.end()) {
@@ -1491,19 +1742,80 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
                                       P.steps[si + 1].group == P.steps[si].group;
         if (!grouped_not_last) it->launches += iters;
         it->ms += ms[si];
-        it->bytes += iters * algorithmic_bytes(P, P.steps[si], g, img->dtype, tuning_for(c, img->H, img->W).ccl_tbh);
+        if ((pj || vol) && kind == SK::CclLocal)  // labels written once, mask read once
+            it->bytes += iters * ((double)g.H * g.W * 4.0 + (double)g.nwords * 8.0);
+        else if ((pj || vol) && (kind == SK::CclGather || kind == SK::CclReseed))  // labels read once
+            it->bytes += iters * ((double)g.H * g.W * 4.0 + (double)g.nwords * 8.0 * 2.0);
+        else
+            it->bytes += iters * algorithmic_bytes(P, P.steps[si], g, img->dtype, tuning_for(c, img->H, img->W).ccl_tbh);
     }
     for (size_t i = 0; i < kinds.size() && (int)i < max_out; i++) out[i] = kinds[i];
     *n_out = (int)kinds.size();
     return VLG_OK;
 }
 
+int vlg_profile_step(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, const char *kind, int reps,
+                     double *avg_ms, double *bytes) {
+    if (!c || !cf || !img || !kind || reps < 1 || !avg_ms || !bytes) return fail(VLG_EINVAL, "bad argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    if (f->max_chan >= img->C) return fail(VLG_ESHAPE, "formula uses a channel the image lacks");
+    const std::string k(kind);
+    SK sk;
+    if (k == "atoms") sk = SK::Atoms;
+    else if (k == "logic") sk = SK::Logic;
+    else if (k == "near") sk = SK::Near;
+    else if (k == "ccl_local") sk = SK::CclLocal;
+    else if (k == "ccl_gather") sk = SK::CclGather;
+    else if (k == "segment") sk = SK::Segment;
+    else if (k == "arith") sk = SK::Arith;
+    else return fail(VLG_EINVAL, "kind must be one whose repeated launch redoes the same work: atoms, logic, near, "
+                                 "ccl_local, ccl_gather, segment or arith");
+    DeviceGuard dg(c->device);
+    std::vector<int> which(f->dag.outputs.size());
+    for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
+    const bool vol = img->D > 1;
+    const Plan &P = f->plan(which, Mode::Fused, 1, vol ? 1 : tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
+    const Geo g = make_geo(img->H, img->W);
+    *avg_ms = 0.0;
+    *bytes = 0.0;
+    if (g.nwords == 0) return VLG_OK;
+    size_t at = SIZE_MAX;
+    for (size_t si = 0; si < P.steps.size() && at == SIZE_MAX; si++)
+        if (P.steps[si].kind == sk && P.steps[si].group < 0) at = si;
+    if (at == SIZE_MAX) return fail(VLG_EINVAL, "the fused schedule has no single (ungrouped) step of kind " + k);
+    const bool pj = !vol && P.ccl_count > 0 && ccl_algo(c, img->H, img->W) == VLG_CCL_POINTER_JUMPING;
+    if (pj) return fail(VLG_EINVAL, "not with the pointer-jumping labelling (its rounds wait on the host)");
+    const Layout L = layout_for(P, g, true, false, false, vol);
+    int rc = ensure_ws(c, L.total);
+    if (rc != VLG_OK) return rc;
+    std::vector<uint64_t *> ext(which.size());
+    for (size_t q = 0; q < which.size(); q++) ext[q] = (uint64_t *)((char *)c->ws + L.off_stage + q * L.mask_bytes);
+    // the steps before it make its inputs; then the step alone, back to back
+    rc = enqueue_plan(c, P, img, L, ext, nullptr, nullptr, nullptr, 0, at + 1);
+    if (rc != VLG_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(VLG_EHIP, "event create");
+    }
+    rc = hipEventRecord(e0, c->stream) == hipSuccess ? VLG_OK : fail(VLG_EHIP, "event record");
+    for (int r = 0; r < reps && rc == VLG_OK; r++) rc = enqueue_plan(c, P, img, L, ext, nullptr, nullptr, nullptr, at, at + 1);
+    float ms = 0.f;
+    if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(VLG_EHIP, "event timing");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != VLG_OK) return rc;
+    *avg_ms = ms / reps;
+    *bytes = algorithmic_bytes(P, P.steps[at], g, img->dtype, tuning_for(c, img->H, img->W).ccl_tbh);
+    return check_status(c);
+}
+
 int vlg_set_tunable(vlg_ctx *c, int which, int value) {
     if (!c) return fail(VLG_EINVAL, "null context");
     if (which < 0 || which >= kNumTunables) return fail(VLG_EINVAL, "unknown tunable");
-    if (which == VLG_TUNE_CCL_LANES && value > 1)
-        return fail(VLG_EINVAL, "ccl_lanes: concurrent labelling lanes are switched off (a host-side crash seen "
-                                "with four lanes is not explained); only 1 is accepted");
     if (value != 0 && !tunable_valid(which, value))
         return fail(VLG_EINVAL, std::string("bad value for ") + kTunableNames[which]);
     c->forced.v[which] = value;
@@ -1527,31 +1839,43 @@ int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int it
     *n_out = 0;
     std::vector<int> which(f->dag.outputs.size());
     for (size_t i = 0; i < which.size(); i++) which[i] = (int)i;
-    const int lanes = tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W);
     const Geo g = make_geo(img->H, img->W);
-    if (g.nwords == 0) return VLG_OK;
+    // volumes run the 3-D kernels, which have none of these tunables
+    if (g.nwords == 0 || img->D > 1) return VLG_OK;
     // the step kinds of the schedule without segments, and a workspace that
-    // fits the plan of every segment halo cap the tuner may try
-    const std::vector<int> fuse_cands = {1, 4, 8, 16};
-    const Plan &P1 = f->plan(which, Mode::Fused, lanes, 1);
+    // fits the plan of every candidate the tuner may try
+    const std::vector<int> fuse_cands = {1, 4, 8, 16}, lane_cands = {1, 2, 4, 8};
+    const Plan &P1 = f->plan(which, Mode::Fused, 1, 1);
     bool has_near = false;
     int local_steps = 0;
     for (const Step &st : P1.steps) {
         has_near |= st.kind == SK::Near;
         local_steps += st.kind == SK::Near || st.kind == SK::Logic;
     }
+    const bool try_pj = P1.ccl_count > 0 && pj_shape_ok(img->H, img->W);
+    const bool try_lanes = P1.ccl_count > 1;
     size_t need = 0;
-    for (int fz : fuse_cands) need = std::max(need, layout_for(f->plan(which, Mode::Fused, lanes, fz), g, true, false).total);
+    for (int fz : fuse_cands)
+        for (int pj = 0; pj <= (int)try_pj; pj++)
+            for (int ln : lane_cands)
+                if (ln == 1 || try_lanes)
+                    need = std::max(need, layout_for(f->plan(which, Mode::Fused, ln, fz), g, true, false, pj).total);
     std::vector<std::pair<int, std::vector<int>>> space;
+    // the labelling schedule first (union-find, then the paper's pointer
+    // jumping), then its tile height, then how many labellings run together
+    if (try_pj) space.push_back({VLG_TUNE_CCL_ALGO, {VLG_CCL_UNION_FIND, VLG_CCL_POINTER_JUMPING}});
     if (P1.ccl_count > 0) space.push_back({VLG_TUNE_CCL_TILE_ROWS, {8, 16, 32}});
+    if (try_lanes) space.push_back({VLG_TUNE_CCL_LANES, lane_cands});
     if (local_steps >= 2) space.push_back({VLG_TUNE_FUSE_HALO, fuse_cands});
     if (has_near) space.push_back({VLG_TUNE_NEAR_ROWS, {4, 8, 16, 32}});
     int rc = ensure_ws(c, need);
     if (rc != VLG_OK) return rc;
     const std::pair<int, int> cls{log2_class(img->H), log2_class(img->W)};
     auto run_once = [&]() {
-        const Plan &P = f->plan(which, Mode::Fused, lanes, tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
-        const Layout L = layout_for(P, g, true, false);
+        const Plan &P = f->plan(which, Mode::Fused, tuned_value(c, VLG_TUNE_CCL_LANES, img->H, img->W),
+                                tuned_value(c, VLG_TUNE_FUSE_HALO, img->H, img->W));
+        const bool pj = P.ccl_count > 0 && ccl_algo(c, img->H, img->W) == VLG_CCL_POINTER_JUMPING;
+        const Layout L = layout_for(P, g, true, false, pj);
         std::vector<uint64_t *> ext(which.size());
         for (size_t k = 0; k < which.size(); k++) ext[k] = (uint64_t *)((char *)c->ws + L.off_stage + k * L.mask_bytes);
         return enqueue_plan(c, P, img, L, ext);
@@ -1568,6 +1892,7 @@ int vlg_autotune_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const
     int64_t pixels = 0;
     for (int i = 0; i < n; i++) {
         if (!imgs[i]) return fail(VLG_EINVAL, "null image in batch");
+        if (imgs[i]->D > 1) return fail(VLG_EINVAL, "volumes are not batched");
         if (f->max_chan >= imgs[i]->C) return fail(VLG_ESHAPE, "formula uses a channel an image lacks");
         if (imgs[i]->dtype != dtype) return fail(VLG_EINVAL, "batch autotuning needs one pixel type");
         if (imgs[i]->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
@@ -1646,6 +1971,39 @@ int vlg_ccl_read_counters(vlg_ctx *c, vlg_ccl_counters *out) {
     out->merge_retries = h[1];
     HIP_TRY(launch_fill_i64(c->stream, c->counters, 2, 0));
     out->launches_per_ccl = 4;
+    out->pj_labellings = c->pj_labellings;
+    out->pj_main_iterations = c->pj_iters;
+    out->pj_rounds = c->pj_rounds;
+    out->pj_launches = c->pj_launches;
+    c->pj_labellings = c->pj_iters = c->pj_rounds = c->pj_launches = 0;
+    return VLG_OK;
+}
+
+int vlg_ccl_labels_pj(vlg_ctx *c, const uint64_t *mask_dev, int height, int width, int reconnect_every,
+                      int32_t *labels_dev, vlg_pj_stats *stats) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (!c || (!mask_dev && (int64_t)height * width > 0) || (!labels_dev && (int64_t)height * width > 0))
+        return fail(VLG_EINVAL, "null argument");
+    if (reconnect_every < 0 || reconnect_every > 64) return fail(VLG_EINVAL, "reconnect period must be 0..64");
+    if (height < 0 || width < 0 || !pj_shape_ok(height, width))
+        return fail(VLG_ESHAPE, "pointer-jumping labelling: rows and columns must stay below 65535");
+    DeviceGuard dg(c->device);
+    const Geo g = make_geo(height, width);
+    if (g.nwords == 0) return VLG_OK;
+    int rc = ensure_ws(c, pj_bytes(g));
+    if (rc != VLG_OK) return rc;
+    const PjWork w = pj_work(c->ws, g);
+    const int k = reconnect_every ? reconnect_every : pj_reconnect_every(c, height, width);
+    const int64_t it0 = c->pj_iters, r0 = c->pj_rounds, l0 = c->pj_launches;
+    int at = 0;
+    rc = pj_label(c, c->stream, g, MRef{mask_dev, 0ull}, w, k, at);
+    if (stats) {
+        stats->main_iterations = c->pj_iters - it0;
+        stats->rounds = c->pj_rounds - r0;
+        stats->launches = rc == VLG_OK ? c->pj_launches - l0 + 1 : 0;
+    }
+    if (rc != VLG_OK) return rc;
+    HIP_TRY(launch_pj_labels(c->stream, g, w, at, labels_dev));
     return VLG_OK;
 }
 

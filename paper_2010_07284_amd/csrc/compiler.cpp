@@ -36,7 +36,7 @@ std::string at(int line, int col, const std::string &msg) {
 }
 
 bool lex(const char *src, std::vector<Tok> &out, std::string &err) {
-    static const char *puncts[] = {">=.", "<=.", ">.", "<.", "(", ")", ",", "=", "!", "&", "|", "-"};
+    static const char *puncts[] = {">=.", "<=.", ">.", "<.", "(", ")", ",", "=", "!", "&", "|", "-", "+", "*", "/"};
     int line = 1, col = 1;
     size_t i = 0;
     auto step = [&](size_t n) {
@@ -152,6 +152,10 @@ struct Builder {
         k.op = (uint8_t)n.op;
         k.a = n.a;
         k.b = n.b;
+        if (n.op == Op::Arith) {
+            k.cmp = n.cmp;
+            k.chan = n.arith;  // interned: equal programs share one index
+        }
         if (n.op == Op::Atom) {
             k.cmp = n.cmp;
             k.pct = n.pct;
@@ -170,13 +174,32 @@ struct Builder {
         memo.emplace(k, id);
         return id;
     }
+
+    // index of an arithmetic program, equal programs sharing one
+    std::map<std::string, int32_t> arith_ids;
+    int32_t intern(const ArProgram &pr) {
+        std::string key((const char *)&pr.lhs_len, sizeof pr.lhs_len);
+        for (const ArInstr &in : pr.ins) {
+            key.append((const char *)&in.op, sizeof in.op);
+            key.append((const char *)&in.chan, sizeof in.chan);
+            key.append((const char *)&in.c, sizeof in.c);
+            key.append((const char *)&in.q, sizeof in.q);
+        }
+        auto it = arith_ids.find(key);
+        if (it != arith_ids.end()) return it->second;
+        const int32_t id = (int32_t)dag.ariths.size();
+        dag.ariths.push_back(pr);
+        arith_ids.emplace(key, id);
+        return id;
+    }
 };
 
 // ---------------------------------------------------------------- parser
 
 bool is_builtin(const std::string &s) {
-    static const char *names[] = {"let", "output", "true", "false", "intensity", "percentile",
-                                  "img", "near", "N", "interior", "reach", "surrounded", "grow"};
+    static const char *names[] = {"let",  "output",     "true", "false", "intensity", "percentile", "img",
+                                  "near", "N",          "interior", "reach", "surrounded", "grow", "touch",
+                                  "abs",  "min",        "max"};
     for (const char *n : names)
         if (s == n) return true;
     return false;
@@ -260,55 +283,150 @@ struct Parser {
         }
     }
 
-    int32_t atom() {
-        Node n;
-        n.op = Op::Atom;
-        expect("(");
-        if (failed) return -1;
-        img_channel(n.chan, true);
-        if (failed) return -1;
-        expect(")");
-        if (failed) return -1;
-        if (accept(">=.")) n.cmp = CMP_GE;
-        else if (accept("<=.")) n.cmp = CMP_LE;
-        else if (accept(">.")) n.cmp = CMP_GT;
-        else if (accept("<.")) n.cmp = CMP_LT;
-        else {
-            fail("expected a comparison '>.', '<.', '>=.' or '<=.'");
+    // ---- arithmetic atoms: a numeric expression (postfix into `out`)
+    // followed by a comparison and another numeric expression.  The parse is
+    // speculative: false (the caller backs up) when the tokens here are not
+    // a numeric expression.
+    bool num_factor(std::vector<ArInstr> &out) {
+        if (failed) return false;
+        if (accept("-")) {
+            if (!num_factor(out)) return false;
+            ArInstr in;
+            in.op = AR_NEG;
+            out.push_back(in);
+            return true;
+        }
+        if (accept("(")) return num_expr(out) && accept(")");
+        if (cur().k == T_NUM) {
+            ArInstr in;
+            in.op = AR_CONST;
+            in.c = (float)cur().num;  // read as double, rounded once to float32
+            p++;
+            out.push_back(in);
+            return true;
+        }
+        if (cur().k != T_IDENT) return false;
+        const std::string id = cur().s;
+        ArInstr in;
+        if (id == "intensity") {
+            p++;
+            if (!accept("(")) return false;
+            in.op = AR_CHAN;
+            img_channel(in.chan, true);
+            if (failed || !accept(")")) return false;
+            out.push_back(in);
+            return true;
+        }
+        if (id == "percentile") {
+            p++;
+            if (!accept("(")) return false;
+            in.op = AR_PCT;
+            img_channel(in.chan, false);
+            if (failed || !accept(",") || cur().k != T_NUM) return false;
+            in.q = cur().num;
+            p++;
+            if (!accept(")")) return false;
+            out.push_back(in);
+            return true;
+        }
+        if (id == "abs" || id == "min" || id == "max") {
+            p++;
+            if (!accept("(") || !num_expr(out)) return false;
+            if (id != "abs" && !(accept(",") && num_expr(out))) return false;
+            if (!accept(")")) return false;
+            in.op = id == "abs" ? AR_ABS : id == "min" ? AR_MIN : AR_MAX;
+            out.push_back(in);
+            return true;
+        }
+        return false;
+    }
+    bool num_term(std::vector<ArInstr> &out) {
+        if (!num_factor(out)) return false;
+        for (;;) {
+            uint8_t op;
+            if (accept("*")) op = AR_MUL;
+            else if (accept("/")) op = AR_DIV;
+            else return true;
+            if (!num_factor(out)) return false;
+            ArInstr in;
+            in.op = op;
+            out.push_back(in);
+        }
+    }
+    bool num_expr(std::vector<ArInstr> &out) {
+        if (!num_term(out)) return false;
+        for (;;) {
+            uint8_t op;
+            if (accept("+")) op = AR_ADD;
+            else if (accept("-")) op = AR_SUB;
+            else return true;
+            if (!num_term(out)) return false;
+            ArInstr in;
+            in.op = op;
+            out.push_back(in);
+        }
+    }
+    static int stack_depth(const std::vector<ArInstr> &v) {
+        int d = 0, m = 0;
+        for (const ArInstr &in : v) {
+            if (in.op == AR_CONST || in.op == AR_CHAN || in.op == AR_PCT) d++;
+            else if (in.op != AR_NEG && in.op != AR_ABS) d--;
+            m = std::max(m, d);
+        }
+        return m;
+    }
+    bool at_cmp() const {
+        return cur().k == T_PUNCT && (cur().s == ">." || cur().s == "<." || cur().s == ">=." || cur().s == "<=.");
+    }
+    // An atom at the current position (matched = true), or nothing consumed.
+    // The paper's plain atom, intensity(img[, c]) CMP constant-or-percentile,
+    // stays an Atom node; any other comparison becomes an Arith node.
+    int32_t arith_atom(bool &matched) {
+        matched = false;
+        const size_t save = p;
+        std::vector<ArInstr> lhs;
+        if (!num_expr(lhs) || !at_cmp()) {
+            if (!failed) p = save;
             return -1;
         }
-        if (cur().k == T_IDENT) {
-            if (cur().s != "percentile") {
-                fail("expected a number or percentile(...)");
-                return -1;
-            }
-            p++;
-            expect("(");
-            if (failed) return -1;
-            img_channel(n.pchan, false);
-            if (failed) return -1;
-            expect(",");
-            if (failed) return -1;
-            if (cur().k != T_NUM) {
-                fail("expected a percentile fraction");
-                return -1;
-            }
-            n.q = cur().num;
-            p++;
-            expect(")");
-            n.pct = 1;
-        } else {
-            bool neg = accept("-");
-            if (cur().k != T_NUM) {
-                fail("expected a number");
-                return -1;
-            }
-            double v = cur().num;
-            p++;
-            // the constant is read as double and rounded once to float32
-            n.thr = (float)(neg ? -v : v);
+        matched = true;
+        const std::string c = cur().s;
+        p++;
+        const uint8_t cmp = c == ">=." ? CMP_GE : c == "<=." ? CMP_LE : c == ">." ? CMP_GT : CMP_LT;
+        std::vector<ArInstr> rhs;
+        if (!num_expr(rhs)) {
+            fail("expected a numeric expression after the comparison");
+            return -1;
         }
-        if (failed) return -1;
+        Node n;
+        n.cmp = cmp;
+        if (lhs.size() == 1 && lhs[0].op == AR_CHAN) {
+            const bool konst = rhs.size() == 1 && rhs[0].op == AR_CONST;
+            const bool neg = rhs.size() == 2 && rhs[0].op == AR_CONST && rhs[1].op == AR_NEG;
+            if (konst || neg || (rhs.size() == 1 && rhs[0].op == AR_PCT)) {
+                n.op = Op::Atom;
+                n.chan = lhs[0].chan;
+                if (rhs[0].op == AR_PCT) {
+                    n.pct = 1;
+                    n.pchan = rhs[0].chan;
+                    n.q = rhs[0].q;
+                } else {
+                    n.thr = neg ? -rhs[0].c : rhs[0].c;
+                }
+                return make(n);
+            }
+        }
+        if (lhs.size() + rhs.size() > (size_t)kArMaxInstrs || stack_depth(lhs) > kArMaxDepth ||
+            stack_depth(rhs) > kArMaxDepth) {
+            fail("arithmetic expression too large (at most 32 terms and operators, nesting depth 8 per side)");
+            return -1;
+        }
+        ArProgram pr;
+        pr.ins = lhs;
+        pr.ins.insert(pr.ins.end(), rhs.begin(), rhs.end());
+        pr.lhs_len = (int32_t)lhs.size();
+        n.op = Op::Arith;
+        n.arith = dry ? 0 : B.intern(pr);
         return make(n);
     }
 
@@ -348,6 +466,9 @@ struct Parser {
 
     int32_t primary() {
         if (failed) return -1;
+        bool matched = false;
+        const int32_t at = arith_atom(matched);
+        if (matched || failed) return at;
         if (accept("(")) {
             int32_t e = expr();
             expect(")");
@@ -368,7 +489,29 @@ struct Parser {
             n.op = Op::False;
             return make(n);
         }
-        if (id == "intensity") return atom();
+        if (id == "intensity" || id == "percentile" || id == "abs" || id == "min" || id == "max") {
+            p--;
+            fail("expected a comparison '>.', '<.', '>=.' or '<=.' after a numeric expression");
+            return -1;
+        }
+        if (id == "touch") {
+            // touch(a, b) = a & reach(b, a): the regions of a in contact with b
+            expect("(");
+            const int32_t a = expr();
+            expect(",");
+            const int32_t b = expr();
+            expect(")");
+            if (failed) return -1;
+            Node r;
+            r.op = Op::Reach;
+            r.a = b;  // seeds
+            r.b = a;  // passable
+            Node n;
+            n.op = Op::And;
+            n.a = a;
+            n.b = make(r);
+            return make(n);
+        }
         if (id == "near" || id == "N") return call(Op::Near, 1);
         if (id == "interior") return call(Op::Interior, 1);
         if (id == "reach") return call(Op::Reach, 2);
@@ -528,7 +671,7 @@ int64_t count_op(const Dag &dag, bool reach_like) {
     int64_t n = 0;
     for (const Node &x : dag.nodes) {
         if (reach_like && (x.op == Op::Reach || x.op == Op::Surr || x.op == Op::Grow)) n++;
-        if (!reach_like && x.op == Op::Atom) n++;
+        if (!reach_like && (x.op == Op::Atom || x.op == Op::Arith)) n++;
     }
     return n;
 }
@@ -552,6 +695,7 @@ struct Lower {
     std::vector<char> deferred;
     std::vector<Ref> dx;
     std::vector<uint8_t> dinv;
+    std::vector<ArProgram> ariths;  // programs of the Arith steps, percentile leaves resolved
 
     Lower(const Dag &d, Mode m)
         : dag(d), mode(m), val(d.nodes.size()), have(d.nodes.size(), 0), uses(d.nodes.size(), 0),
@@ -604,6 +748,20 @@ struct Lower {
         s.pct_out[0] = idx;
         pct_memo.emplace(key, idx);
         return idx;
+    }
+
+    // an arithmetic atom: its percentile leaves first, then one Arith step
+    Ref arith(int32_t id) {
+        const Node &n = dag.nodes[(size_t)id];
+        ArProgram pr = dag.ariths[(size_t)n.arith];
+        for (ArInstr &in : pr.ins)
+            if (in.op == AR_PCT) in.pct = pct_of(in.chan, in.q);
+        Step &s = emit(SK::Arith);
+        s.op = n.cmp;
+        s.arith = (int32_t)ariths.size();
+        ariths.push_back(std::move(pr));
+        s.out = fresh();
+        return R(s.out);
     }
 
     // materialise (x OP y) ^ inv_out
@@ -662,6 +820,8 @@ struct Lower {
             s.atoms[0].out = fresh();
             return R(s.atoms[0].out);
         }
+        case Op::Arith:
+            return arith(id);
         case Op::Not:
             return logic(Neg(val[(size_t)n.a]), one, 0);
         case Op::And:
@@ -712,6 +872,8 @@ struct Lower {
             return Const(0);
         case Op::Atom:
             return val[(size_t)id];  // made by the atom groups
+        case Op::Arith:
+            return arith(id);
         case Op::Not:
             return Neg(val[(size_t)n.a]);
         case Op::And:
@@ -821,7 +983,7 @@ void schedule_fused(Lower &L, int lanes) {
         bool ccl = false;
         std::vector<int64_t> reads, writes;
     };
-    auto refs_of = [](const Step &st, std::vector<int64_t> &rd, std::vector<int64_t> &wr) {
+    auto refs_of = [&L](const Step &st, std::vector<int64_t> &rd, std::vector<int64_t> &wr) {
         for (const Ref *r : {&st.x, &st.y, &st.z})
             if (r->slot != kNone) rd.push_back(r->slot);
         if (st.kind == SK::Atoms) {
@@ -831,6 +993,10 @@ void schedule_fused(Lower &L, int lanes) {
             }
         } else if (st.kind == SK::Pct) {
             for (int j = 0; j < st.npq; j++) wr.push_back(kPctBase + st.pct_out[j]);
+        } else if (st.kind == SK::Arith) {
+            wr.push_back(st.out);
+            for (const ArInstr &in : L.ariths[(size_t)st.arith].ins)
+                if (in.op == AR_PCT) rd.push_back(kPctBase + in.pct);
         } else if (st.out != kNone) {
             wr.push_back(st.out);
         }
@@ -894,7 +1060,9 @@ void schedule_fused(Lower &L, int lanes) {
     while (emitted < n) {
         int before = emitted;
         const std::ptrdiff_t pct_round_start = (std::ptrdiff_t)out.size();
-        for (int u : ready([&](const Unit &x) { return !x.ccl && (kind_of(x) == SK::Pct || kind_of(x) == SK::Atoms); })) {
+        for (int u : ready([&](const Unit &x) {
+                 return !x.ccl && (kind_of(x) == SK::Pct || kind_of(x) == SK::Atoms || kind_of(x) == SK::Arith);
+             })) {
             const Step &st = L.steps[(size_t)units[(size_t)u].first];
             // ready percentiles of one channel share their passes over it
             Step *merged = nullptr;
@@ -1309,6 +1477,7 @@ Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int la
     }
     P.output_ids.assign(which.begin(), which.end());
     P.segments = std::move(segs);
+    P.ariths = std::move(L.ariths);
     return P;
 }
 

@@ -10,9 +10,27 @@
 
 namespace vlg {
 
-enum class Op : uint8_t { True, False, Atom, Not, And, Or, Near, Interior, Reach, Surr, Grow };
+enum class Op : uint8_t { True, False, Atom, Not, And, Or, Near, Interior, Reach, Surr, Grow, Arith };
 
 enum Cmp : uint8_t { CMP_GT = 0, CMP_LT = 1, CMP_GE = 2, CMP_LE = 3 };
+
+// Arithmetic atoms (the tool's built-in arithmetic, Sect. 3): a comparison
+// of two numeric expressions evaluated pixel by pixel in float32, kept as one
+// postfix program (the left side, then the right side).
+enum ArOp : uint8_t { AR_CONST = 0, AR_CHAN, AR_PCT, AR_NEG, AR_ABS, AR_ADD, AR_SUB, AR_MUL, AR_DIV, AR_MIN, AR_MAX };
+struct ArInstr {
+    uint8_t op = AR_CONST;
+    int32_t chan = 0;    // AR_CHAN: channel; AR_PCT: percentile channel
+    float c = 0.f;       // AR_CONST
+    double q = 0.0;      // AR_PCT: quantile
+    int32_t pct = -1;    // AR_PCT in a plan: its percentile scalar
+};
+struct ArProgram {
+    std::vector<ArInstr> ins;
+    int32_t lhs_len = 0;
+};
+constexpr int kArMaxInstrs = 32;  // per program (both sides)
+constexpr int kArMaxDepth = 8;    // evaluation stack per side
 
 struct Node {
     Op op;
@@ -24,12 +42,14 @@ struct Node {
     float thr = 0.f;
     int32_t pchan = 0;
     double q = 0.0;
+    int32_t arith = -1;  // Arith: program index in Dag::ariths (cmp holds the comparison)
 };
 
 struct Dag {
     std::vector<Node> nodes;             // topologically ordered: operands first
     std::vector<int32_t> outputs;        // node id per `output` statement
     std::vector<std::string> output_names;
+    std::vector<ArProgram> ariths;       // programs of Arith nodes (shared by equal ones)
     int64_t parsed_nodes = 0;            // operator applications before hash-consing
 };
 
@@ -63,6 +83,7 @@ enum class SK : uint8_t {
                 // seed mask x (= N(seeds) & b) for labelling user `user`
     Segment,    // consecutive Logic/Near steps run by one tile kernel with a
                 // halo: Plan::segments[seg]
+    Arith,      // out = lhs(pixel) CMP rhs(pixel): Plan::ariths[arith], CMP = op
 };
 
 // A fused segment (see SegProg in kernels.h; same opcodes and operand rules):
@@ -117,6 +138,7 @@ struct Step {
     int32_t span = -1;    // consecutive steps with one span id are allocated
                           // mask slots as one step (batched group, region)
     int32_t seg = -1;     // Segment: index into Plan::segments
+    int32_t arith = -1;   // Arith: index into Plan::ariths
 };
 
 // A labelling serves at most this many reach-type nodes with the same
@@ -136,6 +158,7 @@ struct Plan {
     int32_t ccl_lanes = 1;     // labelling workspaces (concurrent labelling lanes)
     std::vector<int32_t> output_ids;  // formula output index per external slot
     std::vector<Segment> segments;
+    std::vector<ArProgram> ariths;    // percentile leaves resolved to scalars
 };
 
 // Build the schedule evaluating formula outputs `which` (indices into
@@ -146,7 +169,7 @@ struct Plan {
 // With fuse_halo >= 2 (fused mode) runs of consecutive Logic/Near steps
 // become segments whose deepest chain of near steps is at most fuse_halo;
 // fuse_halo <= 1 forms no segments.
-constexpr int kMaxCclLanes = 4;
+constexpr int kMaxCclLanes = 8;
 constexpr int kFuseHaloDefault = 8;
 inline bool valid_fuse_halo(int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == 16; }
 Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes = 1, int fuse_halo = 1);

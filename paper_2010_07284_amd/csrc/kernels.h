@@ -108,6 +108,24 @@ hipError_t launch_ccl_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z
                              int user, uint64_t *out);
 hipError_t launch_ccl_reseed(hipStream_t s, const Geo &g, MRef sm, const CclWork &w, int user);
 
+// Several independent labellings of one image in each launch (blockIdx.y =
+// labelling): each with its own passable mask b, seeds y & z, workspace
+// (glab, gflag) and, for the gather, its user bit and output.
+constexpr int kMaxMulti = 8;
+struct CclMulti {
+    int n;
+    MRef b[kMaxMulti], y[kMaxMulti], z[kMaxMulti];
+    int32_t *glab[kMaxMulti];
+    uint8_t *gflag[kMaxMulti];
+    int user[kMaxMulti];
+    uint64_t *out[kMaxMulti];
+};
+// w supplies the tile height, loop guard and counters (its arrays are unused)
+hipError_t launch_ccl_local_multi(hipStream_t s, const Geo &g, const CclMulti &m, const CclWork &w);
+hipError_t launch_ccl_merge_multi(hipStream_t s, const Geo &g, const CclMulti &m, const CclWork &w);
+hipError_t launch_ccl_flag_multi(hipStream_t s, const Geo &g, const CclMulti &m, const CclWork &w);
+hipError_t launch_ccl_gather_multi(hipStream_t s, const Geo &g, const CclMulti &m);
+
 constexpr int kBatchMax = 16;
 struct LogicOp {
     MRef x, y;
@@ -135,6 +153,77 @@ hipError_t launch_near_batch(hipStream_t s, const Geo &g, const NearBatch &b, in
 hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork &w, int32_t *canon,
                              int32_t *labels);
 hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint8_t *out);
+
+// Arithmetic atom: a postfix program over channel values, constants and
+// percentile scalars, evaluated per pixel in float32 (one rounding per
+// operation), ins[0, lhs_len) the left side, the rest the right side;
+// out = lhs CMP rhs (CMP 0 >, 1 <, 2 >=, 3 <=).  Op codes as ArOp in
+// compiler.h.  Stack depth at most 8 per side.
+constexpr int kArithMax = 32;
+struct ArithIns {
+    uint8_t op;
+    uint8_t pad[3];
+    int32_t idx;  // channel (AR_CHAN) or percentile scalar (AR_PCT)
+    float c;      // AR_CONST
+};
+struct ArithLaunch {
+    int32_t n, lhs_len, cmp, pad;
+    ArithIns ins[kArithMax];
+};
+// img: channel 0 of the image; chan_elems: elements per channel (H * pitch)
+hipError_t launch_arith(hipStream_t s, const Geo &g, const void *img, int64_t chan_elems, int dtype,
+                        const ArithLaunch &a, const float *pct, uint64_t *out);
+
+// Volumes (vol.hip): D slices of S rows; the Geo is that of the D*S-row mask.
+// N over the 26-neighbourhood: out = (N(x) ^ inv_out) OP z (zop 0 and, 1 or).
+hipError_t launch_near3(hipStream_t s, const Geo &g, int S, int D, MRef x, int inv_out, MRef z, int zop,
+                        uint64_t *out);
+// 26-connected labelling of b: P[v] = the smallest voxel of v's component
+// (voxel index (z*S + y)*W + x), -1 for background; P has g.H * g.W entries.
+hipError_t launch_vl_label(hipStream_t s, const Geo &g, int S, int D, MRef b, int *P, const LoopGuard &gd);
+hipError_t launch_vl_clear_flags(hipStream_t s, const Geo &g, uint8_t *flag);
+hipError_t launch_vl_seed(hipStream_t s, const Geo &g, int S, int D, MRef b, MRef y, MRef z, const int *P,
+                          uint8_t *flag, int user);
+hipError_t launch_vl_reseed(hipStream_t s, const Geo &g, int S, int D, MRef sm, const int *P, uint8_t *flag,
+                            int user);
+hipError_t launch_vl_gather(hipStream_t s, const Geo &g, int S, int D, MRef b, MRef y, MRef z, const int *P,
+                            const uint8_t *flag, int user, uint64_t *out);
+
+// The paper's labelling (Sect. 3, Alg. CCL), pj.hip.  lab[0], lab[1]: the
+// ping-pong label arrays [H][W] (keys ((row << 16) | column) + 1, 0 = null);
+// flag: [H][W] seed bytes indexed by a label's pixel (bit 1+u: the seeds of
+// labelling user u); term: the termination check's word (non-zero: some
+// pixel has a neighbour with another label).  `from` / `at` select the
+// label array a step reads.
+struct PjWork {
+    uint32_t *lab[2];
+    uint8_t *flag;
+    uint32_t *term;
+};
+bool pj_shape_ok(int H, int W);  // rows and columns below 65535
+inline size_t pj_bytes(const Geo &g) {
+    const size_t n = (size_t)g.H * g.W;
+    return 2 * ((n * 4 + 255) & ~(size_t)255) + ((n + 255) & ~(size_t)255) + 256;
+}
+inline PjWork pj_work(void *base, const Geo &g) {
+    const size_t n = (size_t)g.H * g.W, l = (n * 4 + 255) & ~(size_t)255;
+    PjWork w;
+    w.lab[0] = (uint32_t *)base;
+    w.lab[1] = (uint32_t *)((char *)base + l);
+    w.flag = (uint8_t *)((char *)base + 2 * l);
+    w.term = (uint32_t *)((char *)base + 2 * l + ((n + 255) & ~(size_t)255));
+    return w;
+}
+hipError_t launch_pj_init(hipStream_t s, const Geo &g, MRef b, const PjWork &w);
+hipError_t launch_pj_main(hipStream_t s, const Geo &g, MRef b, const PjWork &w, int from);
+hipError_t launch_pj_reconnect(hipStream_t s, const Geo &g, MRef b, const PjWork &w, int from);
+hipError_t launch_pj_check(hipStream_t s, const Geo &g, MRef b, const PjWork &w, int at);
+hipError_t launch_pj_clear_flags(hipStream_t s, const Geo &g, const PjWork &w);
+hipError_t launch_pj_seed(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const PjWork &w, int at, int user);
+hipError_t launch_pj_reseed(hipStream_t s, const Geo &g, MRef sm, const PjWork &w, int at, int user);
+hipError_t launch_pj_gather(hipStream_t s, const Geo &g, MRef b, MRef y, MRef z, const PjWork &w, int at, int user,
+                            uint64_t *out);
+hipError_t launch_pj_labels(hipStream_t s, const Geo &g, const PjWork &w, int at, int32_t *labels);
 
 // ------------------------------------------------------------------ segments
 // A segment: consecutive Boolean and near steps of the fused schedule run by

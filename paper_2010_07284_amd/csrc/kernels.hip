@@ -1166,6 +1166,49 @@ __global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const i
     ccl_reseed_lane(g, sm, glab, gflag, user, bx < g.BW, by, bx);
 }
 
+// ---- several labellings per launch (blockIdx.y selects the labelling)
+template <int TBH>
+__global__ __launch_bounds__(ccl_local_threads<TBH>()) void k_ccl_local_multi(Geo g, CclMulti m, int ntx,
+                                                                              LoopGuard gd) {
+    const int l = (int)blockIdx.y;
+    ccl_local_tile<TBH>(g, m.b[l], m.y[l], m.z[l], blockIdx.x % ntx, blockIdx.x / ntx, m.glab[l], m.gflag[l], gd);
+}
+
+template <int TBH>
+__global__ __launch_bounds__(kThreads) void k_ccl_merge_multi(Geo g, CclMulti m, int ntx, int ntiles,
+                                                              unsigned long long *counters, LoopGuard gd) {
+    __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
+    const int l = (int)blockIdx.y;
+    const int wv = threadIdx.x >> 6, tile = blockIdx.x * (kThreads / 64) + wv;
+    int unions = 0, tries = 0;
+    if (tile < ntiles) ccl_merge_tile<TBH>(g, m.b[l], ntx, tile, m.glab[l], win[wv], unions, tries, gd);
+    if (counters && (unions | tries)) {
+        atomicAdd(&counters[0], (unsigned long long)unions);
+        atomicAdd(&counters[1], (unsigned long long)(tries - unions));
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ccl_flag_multi(int64_t nblocks, CclMulti m, LoopGuard gd) {
+    const int l = (int)blockIdx.y;
+    const int64_t stride = (int64_t)gridDim.x * kThreads * 16;
+    bool ok = true;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 16; i0 < nblocks; i0 += stride)
+        ccl_flag16(m.glab[l], m.gflag[l], nblocks, i0, gd.cap, ok);
+    guard_report(gd, ok);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ccl_gather_multi(Geo g, CclMulti m) {
+    constexpr int NT = kGatherTasksPerWave;
+    __shared__ uint64_t zw[kThreads / 64][8 * NT];
+    const int l = (int)blockIdx.y;
+    const int wv = threadIdx.x >> 6;
+    const int64_t ntasks = (int64_t)g.BH * ((g.wpr + 7) / 8);
+    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = ((int64_t)blockIdx.x * (kThreads / 64) + wv) * NT; t < ntasks; t += nwaves * NT)
+        ccl_gather_tasks<NT>(g, m.b[l], m.y[l], m.z[l], m.glab[l], m.gflag[l], m.user[l], m.out[l], t, ntasks,
+                             zw[wv]);
+}
+
 // Smallest row-major pixel index of each component, gathered at its root.
 __global__ __launch_bounds__(kThreads) void k_ccl_canon(Geo g, MRef b, const int32_t *__restrict__ glab,
                                                         int32_t *canon) {
@@ -1449,6 +1492,151 @@ __global__ __launch_bounds__(kThreads) void k_segment(Geo g, SegProg p, int TR, 
     }
 }
 
+// Wide tiles: an LDS row is 64 words (62 interior words and one halo word on
+// each side), so lane l of every wave owns column l of the rows it is given
+// (rows wave, wave + 8, ...); left and right neighbour words come from the
+// adjacent lanes, the rows above and below from LDS.  Row r of register x is
+// sreg[x * NI + r * 64 + lane].  Same instruction semantics as k_segment.
+constexpr int kSegWideThreads = 512;
+constexpr int kSegWideWaves = kSegWideThreads / 64;
+constexpr int kSegWideTW = 62;
+__global__ __launch_bounds__(kSegWideThreads) void k_segment_wide(Geo g, SegProg p, int TR, int ntx) {
+    extern __shared__ uint64_t sreg[];
+    const int RR = TR + 2 * p.halo, NI = RR * 64;
+    const int tx = (int)(blockIdx.x % ntx), ty = (int)(blockIdx.x / ntx);
+    const int r0 = ty * TR - p.halo, w0 = tx * kSegWideTW - 1;
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int w = w0 + lane;
+    const bool win = w >= 0 && w < g.wpr;
+    const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
+    int nl = 0;
+    while (nl < p.nins && p.ins[nl].op == SEG_LOAD) nl++;
+    // the leading loads: for each input, all of this thread's rows in flight
+    for (int j = 0; j < nl; j++) {
+        const VLG_GLOBAL uint64_t *src = glb((const uint64_t *)p.ptr[p.ins[j].a]);
+        uint64_t *dst = sreg + p.ins[j].dst * NI;
+        for (int rb = wave; rb < RR; rb += kSegWideWaves * 8) {
+            uint64_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int rr = rb + kSegWideWaves * u, row = r0 + rr;
+                const bool in = win && rr < RR && row >= 0 && row < g.H;
+                v[u] = in ? src[(int64_t)row * g.wpr + w] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int rr = rb + kSegWideWaves * u;
+                if (rr < RR) dst[rr * 64 + lane] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = nl; k < p.nins; k++) {
+        const SegIns in = p.ins[k];
+        const uint64_t ia = (in.inv & 1) ? ~0ull : 0ull, ib = (in.inv & 2) ? ~0ull : 0ull,
+                       io = (in.inv & 4) ? ~0ull : 0ull;
+        const uint64_t *A = in.a != kSegNone ? sreg + in.a * NI : nullptr;
+        const uint64_t *B = in.b != kSegNone ? sreg + in.b * NI : nullptr;
+        if (in.op == SEG_STORE) {
+            // each thread stores the entries it owns (the same it writes in
+            // every other instruction): no barrier needed before reuse
+            VLG_GLOBAL uint64_t *out = glb(p.ptr[in.dst]);
+            const bool col_ok = lane >= 1 && lane <= kSegWideTW && win;
+            for (int rr = p.halo + wave; rr < p.halo + TR; rr += kSegWideWaves) {
+                const int row = r0 + rr;
+                if (!col_ok || row >= g.H) continue;
+                out[(int64_t)row * g.wpr + w] = ((A ? A[rr * 64 + lane] : 0ull) ^ ia) & keep;
+            }
+            continue;
+        }
+        uint64_t *D = sreg + in.dst * NI;
+        if (in.op == SEG_AND || in.op == SEG_OR) {
+            for (int rr = wave; rr < RR; rr += kSegWideWaves) {
+                const int i = rr * 64 + lane;
+                const uint64_t x = (A ? A[i] : 0ull) ^ ia, y = (B ? B[i] : 0ull) ^ ib;
+                D[i] = (in.op == SEG_OR ? (x | y) : (x & y)) ^ io;
+            }
+        } else {
+            // N over the image's pixels only: rows and words outside the image
+            // and padding bits count as background; rows outside the tile too
+            // (they only reach the halo, which is inexact by design)
+            auto hrow = [&](int r) -> uint64_t {
+                const int row = r0 + r;
+                const bool ok = win && r >= 0 && r < RR && row >= 0 && row < g.H;
+                const uint64_t v = ok ? (((A ? A[r * 64 + lane] : 0ull) ^ ia) & keep) : 0ull;
+                uint64_t l = __shfl_up(v, 1), h = __shfl_down(v, 1);
+                if (lane == 0) l = 0ull;
+                if (lane == 63) h = 0ull;
+                return v | (v << 1) | (v >> 1) | (l >> 63) | (h << 63);
+            };
+            for (int rr = wave; rr < RR; rr += kSegWideWaves) {
+                const uint64_t n = (hrow(rr - 1) | hrow(rr) | hrow(rr + 1)) ^ io;
+                const int i = rr * 64 + lane;
+                const uint64_t z = (B ? B[i] : 0ull) ^ ib;
+                D[i] = in.op == SEG_NEAR_OR ? (n | z) : (n & z);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ arithmetic
+// One wave per mask word: lane l evaluates pixel 64*w + l.  The program is
+// the same for every lane (kernel argument), so each instruction is a
+// uniform branch; the evaluation stack is eight registers shifted on push
+// and pop (no indexed private memory).  No contraction into fused
+// multiply-adds: each operation rounds once, as the oracle's float32 does.
+enum : uint8_t { KA_CONST = 0, KA_CHAN, KA_PCT, KA_NEG, KA_ABS, KA_ADD, KA_SUB, KA_MUL, KA_DIV, KA_MIN, KA_MAX };
+
+template <typename T>
+__device__ __forceinline__ float arith_side(const ArithLaunch &a, int k0, int k1, const T *__restrict__ img,
+                                            int64_t chan_elems, int64_t e, const float *__restrict__ pct) {
+#pragma clang fp contract(off)
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f;
+    auto push = [&](float v) {
+        s7 = s6; s6 = s5; s5 = s4; s4 = s3; s3 = s2; s2 = s1; s1 = s0; s0 = v;
+    };
+    for (int k = k0; k < k1; k++) {
+        const ArithIns in = a.ins[k];
+        switch (in.op) {
+        case KA_CONST: push(in.c); break;
+        case KA_CHAN: push((float)glb(img)[(int64_t)in.idx * chan_elems + e]); break;
+        case KA_PCT: push(glb(pct)[in.idx]); break;
+        case KA_NEG: s0 = -s0; break;
+        case KA_ABS: s0 = fabsf(s0); break;
+        default: {
+            const float x = s1, y = s0;
+            float r;
+            switch (in.op) {
+            case KA_ADD: r = x + y; break;
+            case KA_SUB: r = x - y; break;
+            case KA_MUL: r = x * y; break;
+            case KA_DIV: r = x / y; break;
+            case KA_MIN: r = y < x ? y : x; break;
+            default: r = y > x ? y : x; break;  // KA_MAX
+            }
+            s0 = r; s1 = s2; s2 = s3; s3 = s4; s4 = s5; s5 = s6; s6 = s7;
+        }
+        }
+    }
+    return s0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_arith(Geo g, const T *__restrict__ img, int64_t chan_elems, ArithLaunch a,
+                                                   const float *__restrict__ pct, uint64_t *__restrict__ out) {
+    const int64_t wi = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (wi >= g.nwords) return;
+    const int lane = lane_id();
+    const uint32_t row = fdiv((uint32_t)wi, g.wpr_mul, g.wpr_shift), w = (uint32_t)wi - row * (uint32_t)g.wpr;
+    const int64_t e = (int64_t)row * g.wpr * 64 + (int64_t)w * 64 + lane;
+    const float l = arith_side<T>(a, 0, a.lhs_len, img, chan_elems, e, pct);
+    const float r = arith_side<T>(a, a.lhs_len, a.n, img, chan_elems, e, pct);
+    const bool v = a.cmp == 0 ? l > r : a.cmp == 1 ? l < r : a.cmp == 2 ? l >= r : l <= r;
+    const uint64_t word = __ballot(v);
+    if (lane == 0) glb(out)[wi] = word & (w == (uint32_t)g.wpr - 1 ? g.tail : ~0ull);
+}
+
 int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
 int ntiles_y(const Geo &g, int tbh) { return (g.BH + tbh - 1) / tbh; }
 
@@ -1557,6 +1745,51 @@ hipError_t launch_ccl_reseed(hipStream_t s, const Geo &g, MRef sm, const CclWork
     return hipGetLastError();
 }
 
+hipError_t launch_ccl_local_multi(hipStream_t s, const Geo &g, const CclMulti &m, const CclWork &w) {
+    if (g.nwords == 0 || m.n == 0) return hipSuccess;
+    if (m.n < 0 || m.n > kMaxMulti || !valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
+    const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh);
+    const dim3 grid((unsigned)(ntx * nty), (unsigned)m.n);
+    switch (w.tbh) {
+    case 8: k_ccl_local_multi<8><<<grid, ccl_local_threads<8>(), 0, s>>>(g, m, ntx, w.guard); break;
+    case 16: k_ccl_local_multi<16><<<grid, ccl_local_threads<16>(), 0, s>>>(g, m, ntx, w.guard); break;
+    default: k_ccl_local_multi<32><<<grid, ccl_local_threads<32>(), 0, s>>>(g, m, ntx, w.guard); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_merge_multi(hipStream_t s, const Geo &g, const CclMulti &m, const CclWork &w) {
+    if (g.nwords == 0 || m.n == 0) return hipSuccess;
+    if (m.n < 0 || m.n > kMaxMulti || !valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
+    const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh), ntiles = ntx * nty;
+    const dim3 grid((unsigned)((ntiles + kThreads / 64 - 1) / (kThreads / 64)), (unsigned)m.n);
+    switch (w.tbh) {
+    case 8: k_ccl_merge_multi<8><<<grid, kThreads, 0, s>>>(g, m, ntx, ntiles, w.counters, w.guard); break;
+    case 16: k_ccl_merge_multi<16><<<grid, kThreads, 0, s>>>(g, m, ntx, ntiles, w.counters, w.guard); break;
+    default: k_ccl_merge_multi<32><<<grid, kThreads, 0, s>>>(g, m, ntx, ntiles, w.counters, w.guard); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_flag_multi(hipStream_t s, const Geo &g, const CclMulti &m, const CclWork &w) {
+    if (g.nwords == 0 || m.n == 0) return hipSuccess;
+    if (m.n < 0 || m.n > kMaxMulti) return hipErrorInvalidValue;
+    const int64_t nb = (int64_t)g.BH * g.BW;
+    const dim3 grid((unsigned)grid_for((nb + 15) / 16, kThreads, 65536), (unsigned)m.n);
+    k_ccl_flag_multi<<<grid, kThreads, 0, s>>>(nb, m, w.guard);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccl_gather_multi(hipStream_t s, const Geo &g, const CclMulti &m) {
+    if (g.nwords == 0 || m.n == 0) return hipSuccess;
+    if (m.n < 0 || m.n > kMaxMulti) return hipErrorInvalidValue;
+    const int64_t tasks = (int64_t)g.BH * ((g.wpr + 7) / 8);
+    const dim3 grid((unsigned)grid_for((tasks + kGatherTasksPerWave - 1) / kGatherTasksPerWave, kThreads / 64, 8192),
+                    (unsigned)m.n);
+    k_ccl_gather_multi<<<grid, kThreads, 0, s>>>(g, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_logic_batch(hipStream_t s, const Geo &g, const LogicBatch &b) {
     if (g.nwords == 0 || b.n == 0) return hipSuccess;
     dim3 grid(grid_for(g.nwords, kThreads, 4096), b.n);
@@ -1595,24 +1828,32 @@ hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint
 
 // Tile of a segment: the shape with the least halo overhead among those that
 // fit the LDS budget and leave at least kMinSegTiles tiles (or the most tiles
-// when no shape leaves that many).
+// when no shape leaves that many).  Wide tiles (62 words, k_segment_wide)
+// count only the words of the image they cover.
 constexpr size_t kSegLdsBudget = 48 * 1024;
+constexpr size_t kSegWideLdsBudget = 64 * 1024;
 constexpr int64_t kMinSegTiles = 1024;
 SegTile seg_tile(const Geo &g, int halo, int nregs) {
     SegTile best{4, 1, 0};
     double best_score = -1.0;
+    auto consider = [&](int tr, int tw, size_t lds, double useful_w, int rw) {
+        const int64_t tiles = (int64_t)((g.H + tr - 1) / tr) * ((g.wpr + tw - 1) / tw);
+        const double eff = (double)tr * useful_w / ((double)(tr + 2 * halo) * rw);
+        const double score = eff * std::min(1.0, (double)tiles / kMinSegTiles);
+        if (score > best_score) {
+            best_score = score;
+            best = SegTile{tr, tw, lds};
+        }
+    };
+    for (int tr : {4, 8, 16, 32, 64}) {
+        const size_t lds = (size_t)nregs * (tr + 2 * halo) * 64 * 8;
+        if (lds <= kSegWideLdsBudget) consider(tr, kSegWideTW, lds, std::min(kSegWideTW, g.wpr), 64);
+    }
     for (int tw : {1, 2, 4, 8, 16}) {
         if (tw > 1 && tw / 2 >= g.wpr) break;
         for (int tr : {4, 8, 16, 32}) {
             const size_t lds = (size_t)nregs * (tr + 2 * halo) * (tw + 2) * 8;
-            if (lds > kSegLdsBudget) continue;
-            const int64_t tiles = (int64_t)((g.H + tr - 1) / tr) * ((g.wpr + tw - 1) / tw);
-            const double eff = (double)tr * tw / ((double)(tr + 2 * halo) * (tw + 2));
-            const double score = eff * std::min(1.0, (double)tiles / kMinSegTiles);
-            if (score > best_score) {
-                best_score = score;
-                best = SegTile{tr, tw, lds};
-            }
+            if (lds <= kSegLdsBudget) consider(tr, tw, lds, tw, tw + 2);
         }
     }
     if (best.lds_bytes == 0) best.lds_bytes = (size_t)nregs * (best.tr + 2 * halo) * (best.tw + 2) * 8;
@@ -1624,9 +1865,29 @@ hipError_t launch_segment(hipStream_t s, const Geo &g, const SegProg &p) {
     if (p.nins < 1 || p.nins > kSegMaxIns || p.nregs < 1 || p.nregs > kSegMaxRegs || p.halo < 0 || p.halo > 32)
         return hipErrorInvalidValue;
     const SegTile t = seg_tile(g, p.halo, p.nregs);
-    if (t.lds_bytes > kSegLdsBudget) return hipErrorInvalidValue;
     const int ntx = (g.wpr + t.tw - 1) / t.tw, nty = (g.H + t.tr - 1) / t.tr;
-    k_segment<<<ntx * nty, kThreads, t.lds_bytes, s>>>(g, p, t.tr, t.tw, ntx);
+    if (t.tw == kSegWideTW) {
+        if (t.lds_bytes > kSegWideLdsBudget) return hipErrorInvalidValue;
+        k_segment_wide<<<ntx * nty, kSegWideThreads, t.lds_bytes, s>>>(g, p, t.tr, ntx);
+    } else {
+        if (t.lds_bytes > kSegLdsBudget) return hipErrorInvalidValue;
+        k_segment<<<ntx * nty, kThreads, t.lds_bytes, s>>>(g, p, t.tr, t.tw, ntx);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_arith(hipStream_t s, const Geo &g, const void *img, int64_t chan_elems, int dtype,
+                        const ArithLaunch &a, const float *pct, uint64_t *out) {
+    if (g.nwords == 0) return hipSuccess;
+    if (a.n < 1 || a.n > kArithMax || a.lhs_len < 1 || a.lhs_len >= a.n || a.cmp < 0 || a.cmp > 3)
+        return hipErrorInvalidValue;
+    const int64_t blocks = (g.nwords + kThreads / 64 - 1) / (kThreads / 64);
+    if (dtype == 1)
+        k_arith<uint8_t><<<(unsigned)blocks, kThreads, 0, s>>>(g, (const uint8_t *)img, chan_elems, a, pct, out);
+    else if (dtype == 2)
+        k_arith<uint16_t><<<(unsigned)blocks, kThreads, 0, s>>>(g, (const uint16_t *)img, chan_elems, a, pct, out);
+    else
+        k_arith<float><<<(unsigned)blocks, kThreads, 0, s>>>(g, (const float *)img, chan_elems, a, pct, out);
     return hipGetLastError();
 }
 

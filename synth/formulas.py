@@ -40,6 +40,41 @@ let gtv = grow(hI, vI)
 output "segmentation" gtv
 """
 
+# Arithmetic atoms (the tool's built-in arithmetic) and touch on two
+# channels, thresholds as fractions of a [0, 1) range.
+ARITH_FORMULA = """\
+let A = (intensity(img, 0) + intensity(img, 1)) * 0.5 >. {t0}
+let B = intensity(img, 0) - intensity(img, 1) <. {t1}
+let C = abs(intensity(img, 1) - 0.5) * 2 <=. {t2}
+let D = intensity(img, 0) / (intensity(img, 1) + 0.25) >=. 1
+let E = min(intensity(img, 0), intensity(img, 1)) >. max(0.2, percentile(img, 1, 0.4) - 0.1)
+let F = intensity(img, 0) >. percentile(img, 0, 0.6)
+output "a" A
+output "b" B & !C
+output "d" D | E
+output "touch" touch(A, C)
+output "touch2" touch(!B, F & D)
+output "mix" grow(E, A | B) & near(touch(C, D))
+output "neg" -intensity(img, 1) <. -{t3}
+"""
+
+# A segmentation-shaped formula for volumes (two channels in [0, ~1.2]):
+# thresholds, percentiles, arithmetic, N, interior and every reach-type
+# operator.
+VOLUME_FORMULA = """\
+let A = intensity(img, 0) >. percentile(img, 0, 0.95)
+let B = intensity(img, 0) >. percentile(img, 0, 0.86)
+let C = intensity(img, 1) >. 0.5
+let M = (intensity(img, 0) + intensity(img, 1)) * 0.5 >. 0.45
+let core = grow(A, B)
+output "core" core
+output "edema" grow(core, B | (C & M)) & !core
+output "shell" near(core) & !interior(core)
+output "enclosed" surrounded(C, near(core))
+output "contact" touch(C, core)
+output "reach" reach(A, M)
+"""
+
 REACH_OPS = ("reach", "surrounded", "grow")
 
 

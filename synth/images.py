@@ -4,7 +4,8 @@ Input generation only: nothing here evaluates a formula or any operator of
 the logic.  Both the GPU path and the oracle receive these arrays unchanged.
 All randomness comes from ``numpy.random.default_rng(seed)`` (PCG64).
 
-Layout of every image: numpy array (C, H, W), float32 or uint8.
+Layout of every image: numpy array (C, H, W), float32, uint8 or uint16;
+volumes (C, D, H, W).
 """
 import hashlib
 
@@ -173,6 +174,55 @@ def phantom_image_device(seed, index, h, w, channels=4, sigma_noise=0.05, device
         n1 = torch.randn((h, w), generator=gen, device=device, dtype=torch.float32)
         n2 = torch.randn((h, w), generator=gen, device=device, dtype=torch.float32)
         out[c] = torch.sqrt((canvas + s * n1) ** 2 + (s * n2) ** 2)
+    return out
+
+
+def paper_slice_u16(side=7680, seed=6, device="cuda"):
+    """A uint16 stand-in for the paper's MRI slice (Sect. 4.2, Fig.
+    specification: a 2-D uint16 image thresholded at 62258 and 56360): the
+    device phantom (one channel) scaled by 65535, rounded and clamped to the
+    uint16 range.  Returns the (1, side, side) numpy uint16 array."""
+    import torch
+    t = phantom_image_device(seed, 0, side, side, channels=1, device=device)
+    t = torch.round(t * 65535.0).clamp_(0.0, 65535.0).to(torch.int32)
+    out = t.cpu().numpy().astype(np.uint16)
+    del t
+    return out
+
+
+def volume_phantom_device(seed, d, h, w, channels=2, sigma_noise=0.05, device="cuda"):
+    """A volume (channels, d, h, w) float32 in device memory: per channel
+    10-40 filled ellipsoids (semi-axes 3-30% of the smallest side, random
+    orientation about the slice axis) with intensities in [0.2, 1], plus the
+    Rician-like noise of `phantom_image`.  Parameters from
+    ``default_rng([seed, 7])``, noise from a device generator seeded from it."""
+    import torch
+    rng = np.random.default_rng([seed, 7])
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(0, 2**62)))
+    out = torch.empty((channels, d, h, w), dtype=torch.float32, device=device)
+    side = min(d, h, w)
+    lo_ax, hi_ax = max(1.5, 0.03 * side), max(2.0, 0.3 * side)
+    zz = torch.arange(d, device=device, dtype=torch.float32)[:, None, None] + 0.5
+    yy = torch.arange(h, device=device, dtype=torch.float32)[None, :, None] + 0.5
+    xx = torch.arange(w, device=device, dtype=torch.float32)[None, None, :] + 0.5
+    for c in range(channels):
+        canvas = torch.zeros((d, h, w), dtype=torch.float32, device=device)
+        n = int(rng.integers(10, 41))
+        inten = rng.uniform(0.2, 1.0, n).astype(np.float32)
+        for i in range(n):
+            cz, cy, cx = rng.uniform(0, d), rng.uniform(0, h), rng.uniform(0, w)
+            a, b, e = rng.uniform(lo_ax, hi_ax, 3)
+            th = rng.uniform(0, np.pi)
+            cs, sn = float(np.cos(th)), float(np.sin(th))
+            dy, dx = yy - cy, xx - cx
+            u = (dx * cs + dy * sn) / a
+            v = (-dx * sn + dy * cs) / b
+            t = (zz - cz) / e
+            canvas.masked_fill_(u * u + v * v + t * t <= 1.0, float(inten[i]))
+        n1 = torch.randn((d, h, w), generator=gen, device=device, dtype=torch.float32)
+        n2 = torch.randn((d, h, w), generator=gen, device=device, dtype=torch.float32)
+        out[c] = torch.sqrt((canvas + sigma_noise * n1) ** 2 + (sigma_noise * n2) ** 2)
     return out
 
 

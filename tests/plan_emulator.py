@@ -6,6 +6,8 @@ cleared), so that the schedule builder, the slot allocator and the fused
 segment programs can be checked against the oracle on the CPU:
 
   atoms, percentile     float32 comparisons, nearest-rank order statistic
+  arith                 the postfix program in numpy float32 (one rounding
+                        per operation), then the comparison
   logic                 ((x ^ ix) OP (y ^ iy)) ^ io
   near                  (N(x ^ ix) ^ io) OP (z ^ iz) over the image's pixels
   ccl_local/gather/...  labelling of the passable mask with 8-connectivity
@@ -118,6 +120,34 @@ class Emulator:
             m = [ch > t, ch < t, ch >= t, ch <= t][cmp]
             self.put(out, pack(m.astype(np.uint8), self.g))
 
+    def arith(self, st):
+        F = np.float32
+        prog, k = st["arith"], st["lhs_len"]
+
+        def side(ins):
+            stack = []
+            for op, idx, c in ins:
+                if op == 0:
+                    stack.append(np.full((self.g.H, self.g.W), F(c), F))
+                elif op == 1:
+                    stack.append(self.img[idx].astype(F))
+                elif op == 2:
+                    stack.append(np.full((self.g.H, self.g.W), self.pct[idx], F))
+                elif op == 3:
+                    stack.append(-stack.pop())
+                elif op == 4:
+                    stack.append(np.abs(stack.pop()))
+                else:
+                    y, x = stack.pop(), stack.pop()
+                    with np.errstate(all="ignore"):
+                        stack.append([x + y, x - y, x * y, x / y, np.where(y < x, y, x),
+                                      np.where(y > x, y, x)][op - 5])
+            return stack[0]
+
+        lhs, rhs = side(prog[:k]), side(prog[k:])
+        m = [lhs > rhs, lhs < rhs, lhs >= rhs, lhs <= rhs][st["op"]]
+        self.put(st["out"], pack(m.astype(np.uint8), self.g))
+
     def logic(self, st):
         x, y = self.ref(st["x"]), self.ref(st["y"])
         r = (x | y) if st["op"] else (x & y)
@@ -221,24 +251,32 @@ class Emulator:
             if k in ("ccl_merge", "ccl_flag"):
                 continue
             getattr(self, {"percentile": "percentile", "atoms": "atoms", "logic": "logic", "near": "near",
+                           "arith": "arith",
                            "ccl_local": "ccl_local", "ccl_gather": "ccl_gather", "ccl_reseed": "ccl_reseed",
                            "segment": "segment"}[k])(st)
         return [unpack(self.slots[-2 - k], self.g) for k in range(self.P["noutputs"])]
 
 
-def seg_tile(g, halo, nregs, budget=48 * 1024, min_tiles=1024):
-    """The launcher's tile choice for a segment (same rule, restated)."""
+def seg_tile(g, halo, nregs, budget=48 * 1024, wide_budget=64 * 1024, min_tiles=1024):
+    """The launcher's tile choice for a segment (same rule, restated): wide
+    tiles of 62 words in 64-word LDS rows, or narrow tiles of 1-16 words."""
     best, best_score = (4, 1), -1.0
+
+    def consider(tr, tw, useful_w, rw):
+        nonlocal best, best_score
+        tiles = ((g.H + tr - 1) // tr) * ((g.wpr + tw - 1) // tw)
+        eff = tr * useful_w / ((tr + 2 * halo) * rw)
+        score = eff * min(1.0, tiles / min_tiles)
+        if score > best_score:
+            best_score, best = score, (tr, tw)
+
+    for tr in (4, 8, 16, 32, 64):
+        if nregs * (tr + 2 * halo) * 64 * 8 <= wide_budget:
+            consider(tr, 62, min(62, g.wpr), 64)
     for tw in (1, 2, 4, 8, 16):
         if tw > 1 and tw // 2 >= g.wpr:
             break
         for tr in (4, 8, 16, 32):
-            lds = nregs * (tr + 2 * halo) * (tw + 2) * 8
-            if lds > budget:
-                continue
-            tiles = ((g.H + tr - 1) // tr) * ((g.wpr + tw - 1) // tw)
-            eff = tr * tw / ((tr + 2 * halo) * (tw + 2))
-            score = eff * min(1.0, tiles / min_tiles)
-            if score > best_score:
-                best_score, best = score, (tr, tw)
+            if nregs * (tr + 2 * halo) * (tw + 2) * 8 <= budget:
+                consider(tr, tw, tw, tw + 2)
     return best

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared():
     text = open(os.path.join(ROOT, "include", "vlg.h")).read()
-    return sorted(set(re.findall(r"\b(vlg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(vlg_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_exports_every_declared_symbol():

@@ -45,6 +45,12 @@ def cases():
         t = rng.uniform(0.25, 0.75, 4)
         out.append((f"ops{h}x{w}", OPS.format(t0=t[0], t1=t[1], t2=t[2], t3=t[3]),
                     rng.random((2, h, w)).astype(np.float32)))
+    for h, w in [(5, 70), (61, 130)]:
+        rng = np.random.default_rng(h + w)
+        t = rng.uniform(0.25, 0.75, 4)
+        src = formulas.ARITH_FORMULA.format(t0=t[0], t1=t[1], t2=t[2], t3=t[3])
+        out.append((f"arith{h}x{w}", src, rng.random((2, h, w)).astype(np.float32)))
+        out.append((f"arith_u16_{h}x{w}", src, rng.integers(0, 3, (2, h, w)).astype(np.uint16)))
     out.append(("plain", formulas.PLAIN_FORMULA, images.plain_image(1, 256)))
     out.append(("chain", formulas.chain_dag(3, n_chain=240, n_reach=12), images.random_mask_image(3, 190)))
     rng = np.random.default_rng(4)
