@@ -121,6 +121,10 @@ def bench_chain(vlg, lib, steps, check_oracle):
     outs = [torch.empty((1024, 16), dtype=torch.int64, device="cuda:0") for _ in range(nout)]
     arr = (ctypes.c_void_p * nout)(*[o.data_ptr() for o in outs])
     digests = load_digests() if check_oracle else None
+    tune = vlg.autotune(ctx, f, im, iters=2)
+    for name, (best, times) in tune.items():
+        log(f"[bench] chain_1024 autotune: {name} {best} "
+            f"({', '.join(f'{k}: {v:.2f} ms' for k, v in sorted(times.items()))})")
     first_ms = {}
     for m in ("perop", "fused", "graph"):
         vlg.set_mode(ctx, m)
@@ -138,9 +142,24 @@ def bench_chain(vlg, lib, steps, check_oracle):
     ms = {m: time_mode(vlg, lib, ctx, f, im, arr, m, steps, 1) for m in ("perop", "fused", "graph")}
     for m, t in ms.items():
         log(f"[bench] chain_1024 {m}: {t:.3f} ms/evaluation")
+    halo = vlg.get_tunable(ctx, "fuse_halo", 1024, 1024)
+    launches_tuned = len(vlg.formula_plan(f, "fused", halo)["steps"])
+    # fused segments with halo cap 8, whether or not the tuner picked them
+    vlg.set_tunable(ctx, "fuse_halo", 8)
+    if check_oracle:
+        vlg.set_mode(ctx, "graph")
+        lib.vlg_check_all(ctx.handle, f.handle, im.handle, arr, 0, 1)
+        vlg.sync(ctx)
+        check_digests("chain_1024", outs, digests, "graph, segments")
+    seg_ms = time_mode(vlg, lib, ctx, f, im, arr, "graph", steps, 1)
+    seg_launches = len(vlg.formula_plan(f, "fused", 8)["steps"])
+    vlg.set_tunable(ctx, "fuse_halo", 0)
+    log(f"[bench] chain_1024 graph with segments (halo cap 8): {seg_ms:.3f} ms, {seg_launches} steps")
     return {"workload": f"chain_1024: 1024x1024 u8 random mask, {info['nodes']}-node chain "
                         f"({info['reach_nodes']} reach), {nout} outputs",
-            "nodes": info["nodes"], "launches_perop": info["steps_perop"], "launches_fused": info["launches_fused"],
+            "nodes": info["nodes"], "launches_perop": info["steps_perop"], "launches_fused": launches_tuned,
+            "tuned": {k: v[0] for k, v in tune.items()},
+            "graph_ms_with_segments": round(seg_ms, 3), "steps_with_segments": seg_launches,
             "parity": "oracle digests, every output, every executor" if check_oracle else None,
             "compile_ms": round(compile_ms, 2),
             "graph_build_ms": round(first_ms["graph"] - ms["graph"], 2),

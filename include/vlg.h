@@ -342,7 +342,9 @@ int vlg_profile_step(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, c
  *     consecutive Boolean and near steps that one tile kernel evaluates with
  *     every intermediate mask in LDS, the tile extended by a halo as deep as
  *     the segment's longest chain of near steps.  The value is the largest
- *     halo allowed (2, 4, 8 or 16 rows; default 8); 1 forms no segments.
+ *     halo allowed (2, 4, 8 or 16 rows); 1 (the default) forms no segments:
+ *     on the measured workloads segments only paid off where the autotuner
+ *     picks them.
  *   VLG_TUNE_CCL_ALGO: the labelling behind reach-type nodes (Sect. 3:
  *     reachability through connected components).  VLG_CCL_UNION_FIND
  *     (default): union-find over 2x2 blocks in fixed launches, no host wait.

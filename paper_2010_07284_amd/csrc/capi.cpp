@@ -455,8 +455,17 @@ ArithLaunch arith_launch(const Plan &P, const Step &s) {
     a.cmp = s.op;
     for (size_t k = 0; k < pr.ins.size() && k < (size_t)kArithMax; k++) {
         a.ins[k].op = pr.ins[k].op;
-        a.ins[k].idx = pr.ins[k].op == AR_PCT ? pr.ins[k].pct : pr.ins[k].chan;
         a.ins[k].c = pr.ins[k].c;
+        if (pr.ins[k].op == AR_PCT) {
+            a.ins[k].idx = pr.ins[k].pct;
+        } else if (pr.ins[k].op == AR_CHAN) {
+            // position of the channel among the distinct channels read
+            int c = 0;
+            while (c < a.nch && a.ch[c] != pr.ins[k].chan) c++;
+            if (c == a.nch && a.nch < kArithChans) a.ch[a.nch++] = pr.ins[k].chan;
+            a.ins[k].idx = c;  // kArithChans (invalid) past the limit: the launcher rejects it
+            if (c >= kArithChans) a.nch = kArithChans + 1;
+        }
     }
     return a;
 }

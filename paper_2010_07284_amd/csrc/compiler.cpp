@@ -421,6 +421,17 @@ struct Parser {
             fail("arithmetic expression too large (at most 32 terms and operators, nesting depth 8 per side)");
             return -1;
         }
+        {
+            std::vector<int32_t> chans;
+            for (const std::vector<ArInstr> *side : {&lhs, &rhs})
+                for (const ArInstr &in : *side)
+                    if (in.op == AR_CHAN && std::find(chans.begin(), chans.end(), in.chan) == chans.end())
+                        chans.push_back(in.chan);
+            if (chans.size() > 8) {
+                fail("an arithmetic atom reads at most 8 distinct channels");
+                return -1;
+            }
+        }
         ArProgram pr;
         pr.ins = lhs;
         pr.ins.insert(pr.ins.end(), rhs.begin(), rhs.end());

@@ -170,7 +170,7 @@ struct Plan {
 // become segments whose deepest chain of near steps is at most fuse_halo;
 // fuse_halo <= 1 forms no segments.
 constexpr int kMaxCclLanes = 8;
-constexpr int kFuseHaloDefault = 8;
+constexpr int kFuseHaloDefault = 1;  // no segments unless tuned or forced
 inline bool valid_fuse_halo(int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == 16; }
 Plan build_plan(const Dag &dag, const std::vector<int> &which, Mode mode, int lanes = 1, int fuse_halo = 1);
 

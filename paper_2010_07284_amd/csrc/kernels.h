@@ -163,11 +163,13 @@ constexpr int kArithMax = 32;
 struct ArithIns {
     uint8_t op;
     uint8_t pad[3];
-    int32_t idx;  // channel (AR_CHAN) or percentile scalar (AR_PCT)
+    int32_t idx;  // position in ArithLaunch::ch (AR_CHAN) or percentile scalar (AR_PCT)
     float c;      // AR_CONST
 };
+constexpr int kArithChans = 8;  // distinct channels a program may read
 struct ArithLaunch {
-    int32_t n, lhs_len, cmp, pad;
+    int32_t n, lhs_len, cmp, nch;
+    int32_t ch[kArithChans];  // the distinct channels read (AR_CHAN idx = position here)
     ArithIns ins[kArithMax];
 };
 // img: channel 0 of the image; chan_elems: elements per channel (H * pitch)

@@ -1581,26 +1581,35 @@ __global__ __launch_bounds__(kSegWideThreads) void k_segment_wide(Geo g, SegProg
 }
 
 // ------------------------------------------------------------------ arithmetic
-// One wave per mask word: lane l evaluates pixel 64*w + l.  The program is
-// the same for every lane (kernel argument), so each instruction is a
-// uniform branch; the evaluation stack is eight registers shifted on push
-// and pop (no indexed private memory).  No contraction into fused
-// multiply-adds: each operation rounds once, as the oracle's float32 does.
+// A wave evaluates four consecutive mask words: lane l takes pixel 64*w + l
+// of each.  Every channel the program reads is loaded for all four words
+// before any arithmetic (up to 32 loads in flight per lane).  The program is
+// the same for every lane (kernel argument), so each instruction is a uniform
+// branch; the evaluation stack is eight registers shifted on push and pop (no
+// indexed private memory).  No contraction into fused multiply-adds: each
+// operation rounds once, as the oracle's float32 does.
 enum : uint8_t { KA_CONST = 0, KA_CHAN, KA_PCT, KA_NEG, KA_ABS, KA_ADD, KA_SUB, KA_MUL, KA_DIV, KA_MIN, KA_MAX };
+constexpr int kArithWords = 4;  // mask words per wave
 
-template <typename T>
-__device__ __forceinline__ float arith_side(const ArithLaunch &a, int k0, int k1, const T *__restrict__ img,
-                                            int64_t chan_elems, int64_t e, const float *__restrict__ pct) {
+__device__ __forceinline__ float arith_side(const ArithLaunch &a, int k0, int k1, const float (&v)[kArithChans],
+                                            const float *__restrict__ pct) {
 #pragma clang fp contract(off)
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f;
-    auto push = [&](float v) {
-        s7 = s6; s6 = s5; s5 = s4; s4 = s3; s3 = s2; s2 = s1; s1 = s0; s0 = v;
+    auto push = [&](float x) {
+        s7 = s6; s6 = s5; s5 = s4; s4 = s3; s3 = s2; s2 = s1; s1 = s0; s0 = x;
     };
     for (int k = k0; k < k1; k++) {
         const ArithIns in = a.ins[k];
         switch (in.op) {
         case KA_CONST: push(in.c); break;
-        case KA_CHAN: push((float)glb(img)[(int64_t)in.idx * chan_elems + e]); break;
+        case KA_CHAN: {
+            float x = v[0];
+#pragma unroll
+            for (int c = 1; c < kArithChans; c++)
+                if (in.idx == c) x = v[c];
+            push(x);
+            break;
+        }
         case KA_PCT: push(glb(pct)[in.idx]); break;
         case KA_NEG: s0 = -s0; break;
         case KA_ABS: s0 = fabsf(s0); break;
@@ -1625,16 +1634,33 @@ __device__ __forceinline__ float arith_side(const ArithLaunch &a, int k0, int k1
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_arith(Geo g, const T *__restrict__ img, int64_t chan_elems, ArithLaunch a,
                                                    const float *__restrict__ pct, uint64_t *__restrict__ out) {
-    const int64_t wi = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    if (wi >= g.nwords) return;
+    const int64_t w0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * kArithWords;
+    if (w0 >= g.nwords) return;
     const int lane = lane_id();
-    const uint32_t row = fdiv((uint32_t)wi, g.wpr_mul, g.wpr_shift), w = (uint32_t)wi - row * (uint32_t)g.wpr;
-    const int64_t e = (int64_t)row * g.wpr * 64 + (int64_t)w * 64 + lane;
-    const float l = arith_side<T>(a, 0, a.lhs_len, img, chan_elems, e, pct);
-    const float r = arith_side<T>(a, a.lhs_len, a.n, img, chan_elems, e, pct);
-    const bool v = a.cmp == 0 ? l > r : a.cmp == 1 ? l < r : a.cmp == 2 ? l >= r : l <= r;
-    const uint64_t word = __ballot(v);
-    if (lane == 0) glb(out)[wi] = word & (w == (uint32_t)g.wpr - 1 ? g.tail : ~0ull);
+    int64_t e[kArithWords];
+#pragma unroll
+    for (int j = 0; j < kArithWords; j++) {
+        const int64_t wi = w0 + j < g.nwords ? w0 + j : w0;
+        const uint32_t row = fdiv((uint32_t)wi, g.wpr_mul, g.wpr_shift), w = (uint32_t)wi - row * (uint32_t)g.wpr;
+        e[j] = (int64_t)row * g.wpr * 64 + (int64_t)w * 64 + lane;
+    }
+    float v[kArithWords][kArithChans];
+#pragma unroll
+    for (int c = 0; c < kArithChans; c++)
+#pragma unroll
+        for (int j = 0; j < kArithWords; j++)
+            v[j][c] = c < a.nch ? (float)glb(img)[(int64_t)a.ch[c] * chan_elems + e[j]] : 0.f;
+#pragma unroll
+    for (int j = 0; j < kArithWords; j++) {
+        const int64_t wi = w0 + j;
+        const float l = arith_side(a, 0, a.lhs_len, v[j], pct), r = arith_side(a, a.lhs_len, a.n, v[j], pct);
+        const bool b = a.cmp == 0 ? l > r : a.cmp == 1 ? l < r : a.cmp == 2 ? l >= r : l <= r;
+        const uint64_t word = __ballot(b);
+        if (lane == j && wi < g.nwords) {
+            const uint32_t row = fdiv((uint32_t)wi, g.wpr_mul, g.wpr_shift), w = (uint32_t)wi - row * (uint32_t)g.wpr;
+            glb(out)[wi] = word & (w == (uint32_t)g.wpr - 1 ? g.tail : ~0ull);
+        }
+    }
 }
 
 int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
@@ -1879,9 +1905,11 @@ hipError_t launch_segment(hipStream_t s, const Geo &g, const SegProg &p) {
 hipError_t launch_arith(hipStream_t s, const Geo &g, const void *img, int64_t chan_elems, int dtype,
                         const ArithLaunch &a, const float *pct, uint64_t *out) {
     if (g.nwords == 0) return hipSuccess;
-    if (a.n < 1 || a.n > kArithMax || a.lhs_len < 1 || a.lhs_len >= a.n || a.cmp < 0 || a.cmp > 3)
+    if (a.n < 1 || a.n > kArithMax || a.lhs_len < 1 || a.lhs_len >= a.n || a.cmp < 0 || a.cmp > 3 || a.nch < 0 ||
+        a.nch > kArithChans)
         return hipErrorInvalidValue;
-    const int64_t blocks = (g.nwords + kThreads / 64 - 1) / (kThreads / 64);
+    const int64_t per_block = (int64_t)(kThreads / 64) * kArithWords;
+    const int64_t blocks = (g.nwords + per_block - 1) / per_block;
     if (dtype == 1)
         k_arith<uint8_t><<<(unsigned)blocks, kThreads, 0, s>>>(g, (const uint8_t *)img, chan_elems, a, pct, out);
     else if (dtype == 2)

@@ -142,30 +142,51 @@ __device__ __forceinline__ void vl_report(const LoopGuard &gd, bool ok) {
         __hip_atomic_fetch_or(gv(gd.status), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Initial parents: each voxel of b points at the first voxel of its run
+// (consecutive voxels of b in its row) within its mask word; the run start
+// is a root.  Runs that continue across a word boundary are joined by the
+// union pass.
 __global__ __launch_bounds__(kVlThreads) void k_vl_init(Geo g, int S, int D, MRef b, int *P) {
     VlPos q;
     if (!vl_pos(g, S, D, b, q) || q.x >= g.W) return;
-    gv(P)[q.v] = q.mine ? (int)q.v : -1;
+    int r = -1;
+    if (q.mine) {
+        const uint64_t gaps = ~q.bw & ((1ull << q.lane) - 1ull);  // background voxels before this one
+        const int start = gaps ? 64 - __builtin_clzll(gaps) : 0;
+        r = (int)(q.v - (q.lane - start));
+    }
+    gv(P)[q.v] = r;
 }
 
-// Every voxel of b is united with those of its 26 neighbours that come
-// before it in linear order (the 9 of the slice before, the 3 of the row
-// before, the one to its left).
+// Unions with the voxels before each voxel of b in linear order: the
+// neighbours in the row above and in the three rows of the slice before
+// (rows R), and the left neighbour across a word boundary (inside a word
+// the run's parents already join it).  Connections that are already made
+// are skipped: a voxel whose left neighbour is in b leaves the neighbours
+// at x-1 and x of each row R to that neighbour and unites only with x+1,
+// and only when x is not in b (otherwise x+1 is in the run of x); a run's
+// first voxel unites with x if it is in b, else with x-1 and x+1.
 __global__ __launch_bounds__(kVlThreads) void k_vl_union(Geo g, int S, int D, MRef b, int *P, LoopGuard gd) {
     VlPos q;
     if (!vl_pos(g, S, D, b, q)) return;
     bool ok = true;
     if (q.mine) {
-        const int64_t rowstep = g.W, slicestep = (int64_t)S * g.W;
-        for (int dz = -1; dz <= 0; dz++) {
-            for (int dy = -1; dy <= 1; dy++) {
-                if (dz == 0 && dy > 0) break;
-                for (int dx = -1; dx <= 1; dx++) {
-                    if (dz == 0 && dy == 0 && dx >= 0) break;
-                    if (!vl_bit(g, S, D, b, q.z + dz, q.y + dy, q.x + dx)) continue;
-                    const int u = (int)(q.v + dz * slicestep + dy * rowstep + dx);
-                    ok &= vl_unite(P, (int)q.v, u, gd.cap);
-                }
+        const bool left = vl_bit(g, S, D, b, q.z, q.y, q.x - 1);
+        if (left && q.lane == 0) ok &= vl_unite(P, (int)q.v, (int)q.v - 1, gd.cap);
+        const int rz[4] = {q.z - 1, q.z - 1, q.z - 1, q.z}, ry[4] = {q.y - 1, q.y, q.y + 1, q.y - 1};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int z = rz[k], y = ry[k];
+            if (z < 0 || y < 0 || y >= S) continue;
+            const int64_t base = ((int64_t)z * S + y) * g.W;
+            const bool c = vl_bit(g, S, D, b, z, y, q.x), r = vl_bit(g, S, D, b, z, y, q.x + 1);
+            if (left) {
+                if (!c && r) ok &= vl_unite(P, (int)q.v, (int)(base + q.x + 1), gd.cap);
+            } else if (c) {
+                ok &= vl_unite(P, (int)q.v, (int)(base + q.x), gd.cap);
+            } else {
+                if (vl_bit(g, S, D, b, z, y, q.x - 1)) ok &= vl_unite(P, (int)q.v, (int)(base + q.x - 1), gd.cap);
+                if (r) ok &= vl_unite(P, (int)q.v, (int)(base + q.x + 1), gd.cap);
             }
         }
     }
