@@ -317,6 +317,14 @@ int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int it
  * has no such step or labels with the pointer-jumping schedule. */
 int vlg_profile_step(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, const char *kind, int reps,
                      double *avg_ms, double *bytes);
+/* Measurement: the HBM reference.  Copies `bytes` (a multiple of width) from
+ * src_dev to dst_dev (device buffers, not overlapping) in width-byte units
+ * (8 or 16), non-temporal loads and stores, once as a warm-up and then
+ * `reps` times back to back between two HIP events on the context's stream;
+ * *avg_ms receives the mean time of one copy (bytes read + bytes written
+ * per copy).  Synchronises the stream. */
+int vlg_stream_copy(vlg_ctx *ctx, void *dst_dev, const void *src_dev, int64_t bytes, int width, int reps,
+                    double *avg_ms);
 
 /* Tunables of the executor.  Each has a default, may be forced for a
  * context, and is otherwise looked up per image shape class (ceil(log2 H),

@@ -296,6 +296,16 @@ def profile_step(ctx, f, img, kind, reps=20):
     return ms.value, b.value
 
 
+def stream_copy(ctx, dst, src, width=16, reps=5):
+    """vlg_stream_copy: mean ms of one copy of src into dst (device tensors of
+    equal byte size) with the library's non-temporal copy kernel."""
+    ms = ctypes.c_double()
+    nbytes = src.numel() * src.element_size()
+    _lib.call("vlg_stream_copy", ctx.handle, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+              nbytes, int(width), int(reps), ctypes.byref(ms))
+    return ms.value
+
+
 def ccl_counters(ctx):
     c = _lib.CclCounters()
     _lib.call("vlg_ccl_read_counters", ctx.handle, ctypes.byref(c))
@@ -431,6 +441,6 @@ def pack(mask):
 
 
 __all__ = ["create", "sync", "set_loop_cap", "set_mode", "load_image", "compile_formula", "formula_info", "formula_plan", "output_names",
-           "check", "check_all", "check_batch", "ccl_labels", "ccl_labels_noalloc", "ccl_labels_pj", "ccl_labels3", "load_volume", "ccl_counters", "profile", "profile_step", "set_tunable", "get_tunable", "autotune", "tune_save",
+           "check", "check_all", "check_batch", "ccl_labels", "ccl_labels_noalloc", "ccl_labels_pj", "ccl_labels3", "load_volume", "ccl_counters", "profile", "profile_step", "stream_copy", "set_tunable", "get_tunable", "autotune", "tune_save",
            "tune_load", "autotune_batch", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

@@ -1822,6 +1822,33 @@ int vlg_profile_step(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, co
     return check_status(c);
 }
 
+int vlg_stream_copy(vlg_ctx *c, void *dst_dev, const void *src_dev, int64_t bytes, int width, int reps,
+                    double *avg_ms) {
+    if (!c || !dst_dev || !src_dev || bytes <= 0 || reps < 1 || !avg_ms) return fail(VLG_EINVAL, "bad argument");
+    if ((width != 8 && width != 16) || bytes % width) return fail(VLG_EINVAL, "width must be 8 or 16 and divide bytes");
+    DeviceGuard dg(c->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(VLG_EHIP, "event create");
+    }
+    int rc = VLG_OK;
+    if (launch_stream_copy(c->stream, dst_dev, src_dev, bytes, width) != hipSuccess)  // warm-up
+        rc = fail(VLG_EHIP, "copy launch");
+    if (rc == VLG_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(VLG_EHIP, "event record");
+    for (int r = 0; r < reps && rc == VLG_OK; r++)
+        if (launch_stream_copy(c->stream, dst_dev, src_dev, bytes, width) != hipSuccess) rc = fail(VLG_EHIP, "copy launch");
+    float ms = 0.f;
+    if (rc == VLG_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(VLG_EHIP, "event timing");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == VLG_OK) *avg_ms = ms / reps;
+    return rc;
+}
+
 int vlg_set_tunable(vlg_ctx *c, int which, int value) {
     if (!c) return fail(VLG_EINVAL, "null context");
     if (which < 0 || which >= kNumTunables) return fail(VLG_EINVAL, "unknown tunable");

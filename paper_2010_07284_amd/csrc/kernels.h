@@ -268,6 +268,8 @@ struct SegTile {
 SegTile seg_tile(const Geo &g, int halo, int nregs);
 hipError_t launch_segment(hipStream_t s, const Geo &g, const SegProg &p);
 hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v);
+// bytes (a multiple of width) copied in width-byte units (8 or 16)
+hipError_t launch_stream_copy(hipStream_t s, void *dst, const void *src, int64_t bytes, int width);
 
 
 // ------------------------------------------------------------------ batches

@@ -1919,6 +1919,32 @@ hipError_t launch_arith(hipStream_t s, const Geo &g, const void *img, int64_t ch
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ measurement
+// Device-to-device copy for the HBM reference: each lane moves W-byte units
+// (8 or 16) in a grid-stride loop with non-temporal loads and stores, so
+// the copy streams past the caches like the large pixel-wise launches.
+namespace {
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_stream_copy(const T *__restrict__ src, T *__restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(glb(src) + i), glb(dst) + i);
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+}  // namespace
+
+hipError_t launch_stream_copy(hipStream_t s, void *dst, const void *src, int64_t bytes, int width) {
+    if (bytes <= 0) return hipSuccess;
+    if ((width != 8 && width != 16) || bytes % width) return hipErrorInvalidValue;
+    const int64_t n = bytes / width;
+    const int grid = grid_for(n, kThreads, 256 * 64);
+    if (width == 16)
+        k_stream_copy<u32x4><<<grid, kThreads, 0, s>>>((const u32x4 *)src, (u32x4 *)dst, n);
+    else
+        k_stream_copy<uint64_t><<<grid, kThreads, 0, s>>>((const uint64_t *)src, (uint64_t *)dst, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i64(hipStream_t s, unsigned long long *p, int n, unsigned long long v) {
     k_fill_i64<<<(n + 255) / 256, 256, 0, s>>>(p, n, v);
     return hipGetLastError();

@@ -102,3 +102,11 @@ def test_null_arguments_are_rejected():
     assert L.vlg_formula_info(None, None) == -1
     assert L.vlg_check(None, None, None, 0, None, 0, 1) == -1
     assert b"null" in L.vlg_last_error()
+
+
+def test_stream_copy_rejects_bad_arguments():
+    # rejected on the host before any device call
+    L = _lib.lib()
+    ms = ctypes.c_double()
+    assert L.vlg_stream_copy(None, None, None, 16, 16, 1, ctypes.byref(ms)) == -1
+    assert b"bad argument" in L.vlg_last_error()
