@@ -545,6 +545,77 @@ def bench_arith(vlg, lib, steps, check_oracle, side=4096):
     return res
 
 
+def ccl_merge_counts(vlg, lib, src, img):
+    """Cross-tile merge work per labelling: unions attempted and hook retries
+    (compare-and-swap losses plus re-walks), from the library's device
+    counters, for one fused evaluation of `src` on `img` and for the
+    labelling of a serpentine maze of the same size (one component crossing
+    every tile)."""
+    import torch
+    from synth import images
+    os.environ["VLG_CCL_COUNTERS"] = "1"
+    try:
+        ctx = vlg.create(0)
+    finally:
+        del os.environ["VLG_CCL_COUNTERS"]
+    C, H, W = img.shape
+    im = vlg.load_image(ctx, torch.from_numpy(img).to("cuda:0"))
+    f = vlg.compile_formula(ctx, src)
+    info = vlg.formula_info(f)
+    vlg.set_mode(ctx, "fused")
+    vlg.ccl_counters(ctx)  # clears them
+    vlg.check_all(ctx, f, im)
+    vlg.sync(ctx)
+    c = vlg.ccl_counters(ctx)
+    nl = max(1, info["labellings"])
+    res = {"labellings": info["labellings"], "merge_unions_per_labelling": round(c["merge_unions"] / nl),
+           "merge_retries_per_labelling": round(c["merge_retries"] / nl),
+           "launches_per_labelling": c["launches_per_ccl"]}
+    maze = (images.serpentine_maze(H, W) > 0).astype("uint8")
+    packed = torch.from_numpy(vlg.pack(maze)).to("cuda:0")
+    vlg.ccl_counters(ctx)
+    vlg.ccl_labels(ctx, packed, H, W)
+    vlg.sync(ctx)
+    c = vlg.ccl_counters(ctx)
+    res["maze"] = {"merge_unions": c["merge_unions"], "merge_retries": c["merge_retries"]}
+    log(f"[bench] labelling counters: {res}")
+    del im, f, ctx
+    return res
+
+
+def _oracle_serve_one(src, side, index):
+    import oracle
+    from synth import images
+    oracle.run(src, images.serve_image(index, side))
+    return 0
+
+
+def serve_cpu_baseline(formula_srcs, nodes, sides, max_side=2048):
+    """The oracle on the host cores for the serving mix, on a bounded sample:
+    every formula of the mix on every image of side <= max_side, one request
+    per worker process.  Reports pixel-node evaluations per second, and the
+    request rate that throughput gives for the mix (requests drawn uniformly
+    over images and formulas, as the serving leg draws them)."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = [(src, sd, i) for i, sd in enumerate(sides) if sd <= max_side for src in formula_srcs]
+    work = sum(sd * sd * n for i, sd in enumerate(sides) if sd <= max_side for n in nodes)
+    # largest requests first, so that the pool does not end on one of them
+    order = sorted(range(len(jobs)), key=lambda j: -jobs[j][1] * jobs[j][1] * nodes[j % len(nodes)])
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        pool.starmap(_oracle_serve_one, [jobs[j] for j in order])
+    t_cpu = time.perf_counter() - t0
+    rate = work / t_cpu
+    mean_work = sum(sd * sd * n for sd in sides for n in nodes) / (len(sides) * len(nodes))
+    return {"value": round(rate / 1e9, 4), "unit": "Gpixel-node evals/s", "cores": cores, "kind": "oracle",
+            "req_per_s_for_mix": round(rate / mean_work, 3),
+            "sample": f"{len(jobs)} requests: every formula on every image of side <= {max_side} "
+                      f"({work / 1e9:.1f} G pixel-node evaluations), one request per worker process on {cores} "
+                      f"processes of {cpu_model()}, {t_cpu:.1f} s; the mix rate divides by the mean request "
+                      f"({mean_work / 1e9:.2f} G pixel-node evaluations)"}
+
+
 def bench_serve(vlg, n_req, check_oracle, n_warm=200, seed=5, slots=4, budget=16 << 30, fracs=(0.5, 0.8, 0.95)):
     """Serving loop: Poisson arrivals over a pool of resident images (sides
     256 .. 8192, float32) and formulas (node counts log-uniform in [20, 2000]
@@ -561,7 +632,8 @@ def bench_serve(vlg, n_req, check_oracle, n_warm=200, seed=5, slots=4, budget=16
     sides = list(formulas.SERVE_SIDES)
     imgs = [vlg.load_image(ctx, torch.from_numpy(images.serve_image(i, sd)).to("cuda:0"))
             for i, sd in enumerate(sides)]
-    fs = [vlg.compile_formula(ctx, src) for src, _, _ in formulas.serve_formulas(seed)]
+    fsrc = [src for src, _, _ in formulas.serve_formulas(seed)]
+    fs = [vlg.compile_formula(ctx, src) for src in fsrc]
     nouts = [vlg.formula_info(f)["outputs"] for f in fs]
     nodes = [vlg.formula_info(f)["nodes"] for f in fs]
     digests = load_digests() if check_oracle else None
@@ -634,6 +706,9 @@ def bench_serve(vlg, n_req, check_oracle, n_warm=200, seed=5, slots=4, budget=16
     out["max_inflight"] = st["max_inflight"]
     out["peak_reserved_gib"] = round(st["peak_reserved_bytes"] / 2**30, 3)
     srv.close()
+    if check_oracle:
+        out["cpu_baseline_all_cores"] = serve_cpu_baseline(fsrc, nodes, sides)
+        log(f"[bench] serve oracle on the host cores: {out['cpu_baseline_all_cores']}")
     return out
 
 
@@ -798,6 +873,7 @@ def main():
                      "traffic": measured_traffic(f"ellipse_maze_{S}", dom_name, tile_rows)},
         "cpu_baseline": cpu,
     }
+    line["ccl_counters"] = ccl_merge_counts(vlg, lib, src, img)
     if not args.no_chain:
         line["chain"] = bench_chain(vlg, lib, 3, not args.skip_oracle)
     if not args.no_paper:

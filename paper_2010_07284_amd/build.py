@@ -19,7 +19,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 # device code: gfx950 only; packed fp32 instructions disabled
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["kernels.hip", "pj.hip", "vol.hip", "compiler.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "pj.hip", "vol.hip", "arith.hip", "compiler.cpp", "capi.cpp", "server.cpp"]
 
 
 def _compile(src):

@@ -387,10 +387,18 @@ double algorithmic_bytes(const Plan &P, const Step &s, const Geo &g, int dtype, 
     case SK::CclFlag: return nb;                                      // flags read
     case SK::CclGather: return ins({s.x, s.y, s.z}) + nb * 4.0 + mb;  // labels read
     case SK::CclReseed: return ins({s.x});                            // seed mask read
-    case SK::Arith: {  // every channel the program reads, once, and the mask
-        std::vector<int32_t> ch;
+    case SK::Arith: {
+        // every channel the program reads, once, and the mask; in a group
+        // (one launch) only the channels no earlier member reads
+        std::vector<int32_t> seen, ch;
+        const size_t si = (size_t)(&s - P.steps.data());
+        for (size_t k = si; s.group >= 0 && si < P.steps.size() && k-- > 0 && P.steps[k].group == s.group;)
+            for (const ArInstr &in : P.ariths[(size_t)P.steps[k].arith].ins)
+                if (in.op == AR_CHAN) seen.push_back(in.chan);
         for (const ArInstr &in : P.ariths[(size_t)s.arith].ins)
-            if (in.op == AR_CHAN && std::find(ch.begin(), ch.end(), in.chan) == ch.end()) ch.push_back(in.chan);
+            if (in.op == AR_CHAN && std::find(ch.begin(), ch.end(), in.chan) == ch.end() &&
+                std::find(seen.begin(), seen.end(), in.chan) == seen.end())
+                ch.push_back(in.chan);
         return npix * (dtype == VLG_U8 ? 1.0 : dtype == VLG_U16 ? 2.0 : 4.0) * (double)ch.size() + mb;
     }
     case SK::Segment: {                                               // loads + stores
@@ -445,28 +453,54 @@ int pj_label(vlg_ctx *c, hipStream_t s, const Geo &g, MRef b, const PjWork &w, i
     return VLG_OK;
 }
 
-// The kernel form of an Arith step's program.
-ArithLaunch arith_launch(const Plan &P, const Step &s) {
-    const ArProgram &pr = P.ariths[(size_t)s.arith];
-    ArithLaunch a;
+// The kernel form of the Arith steps si..sj (one group, or one step): their
+// programs, with the stack height before each instruction, and the distinct
+// channels they read.  out[] is left to the caller.  Programs beyond the
+// kernel's limits leave the group empty (n = 0), which the launcher rejects.
+static_assert(kArGroupProgs == kArithGroupProgs && kArGroupInstrs == kArithGroupIns && kArGroupChans == kArithChans &&
+                  kArMaxInstrs == kArithMax && kArMaxDepth == kArithDepth,
+              "the scheduler's arithmetic groups fit the kernel's");
+ArithGroup arith_group(const Plan &P, size_t si, size_t sj) {
+    ArithGroup a;
     std::memset(&a, 0, sizeof a);
-    a.n = (int32_t)pr.ins.size();
-    a.lhs_len = pr.lhs_len;
-    a.cmp = s.op;
-    for (size_t k = 0; k < pr.ins.size() && k < (size_t)kArithMax; k++) {
-        a.ins[k].op = pr.ins[k].op;
-        a.ins[k].c = pr.ins[k].c;
-        if (pr.ins[k].op == AR_PCT) {
-            a.ins[k].idx = pr.ins[k].pct;
-        } else if (pr.ins[k].op == AR_CHAN) {
-            // position of the channel among the distinct channels read
-            int c = 0;
-            while (c < a.nch && a.ch[c] != pr.ins[k].chan) c++;
-            if (c == a.nch && a.nch < kArithChans) a.ch[a.nch++] = pr.ins[k].chan;
-            a.ins[k].idx = c;  // kArithChans (invalid) past the limit: the launcher rejects it
-            if (c >= kArithChans) a.nch = kArithChans + 1;
+    bool bad = sj - si + 1 > (size_t)kArithGroupProgs;
+    int k = 0;
+    for (size_t t = si; t <= sj && !bad; t++) {
+        const Step &s = P.steps[t];
+        const ArProgram &pr = P.ariths[(size_t)s.arith];
+        const int p = (int)(t - si);
+        if (k + (int)pr.ins.size() > kArithGroupIns) {
+            bad = true;
+            break;
         }
+        a.lhs[p] = k;
+        a.rhs[p] = k + pr.lhs_len;
+        a.end[p] = k + (int)pr.ins.size();
+        a.cmp[p] = s.op;
+        int h = 0;  // stack height of the side being written
+        for (size_t i = 0; i < pr.ins.size() && !bad; i++, k++) {
+            if ((int)i == pr.lhs_len) h = 0;
+            ArithIns &in = a.ins[k];
+            in.op = pr.ins[i].op;
+            in.c = pr.ins[i].c;
+            in.depth = (uint8_t)std::min(h, 255);
+            if (in.op == AR_PCT) {
+                in.idx = pr.ins[i].pct;
+            } else if (in.op == AR_CHAN) {
+                // position of the channel among the distinct channels read
+                int c = 0;
+                while (c < a.nch && a.ch[c] != pr.ins[i].chan) c++;
+                if (c == a.nch) {
+                    if (a.nch == kArithChans) bad = true;
+                    else a.ch[a.nch++] = pr.ins[i].chan;
+                }
+                in.idx = c;
+            }
+            h += in.op <= AR_PCT ? 1 : in.op <= AR_ABS ? 0 : -1;
+        }
+        a.n = p + 1;
     }
+    if (bad) a.n = 0;
     return a;
 }
 
@@ -595,7 +629,12 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
             // a batched group: consecutive Logic (or Near) steps, one launch
             size_t sj = si;
             while (sj + 1 < P.steps.size() && sj + 1 < last && P.steps[sj + 1].group == s.group) sj++;
-            if (s.kind == SK::Logic) {
+            if (s.kind == SK::Arith) {
+                ArithGroup a = arith_group(P, si, sj);
+                for (size_t k = si; k <= sj && k - si < (size_t)kArithGroupProgs; k++)
+                    a.out[k - si] = slot_ptr(P.steps[k].out);
+                e = launch_arith(stream, g, img->dev, (int64_t)img->H * img->pitch, img->dtype, a, pct);
+            } else if (s.kind == SK::Logic) {
                 LogicBatch b;
                 b.n = (int)(sj - si + 1);
                 for (size_t k = si; k <= sj; k++) {
@@ -656,10 +695,12 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         case SK::Logic:
             e = launch_logic(stream, g, mref(s.x), mref(s.y), s.op, s.inv_out, slot_ptr(s.out));
             break;
-        case SK::Arith:
-            e = launch_arith(stream, g, img->dev, (int64_t)img->H * img->pitch, img->dtype, arith_launch(P, s), pct,
-                             slot_ptr(s.out));
+        case SK::Arith: {
+            ArithGroup a = arith_group(P, si, si);
+            a.out[0] = slot_ptr(s.out);
+            e = launch_arith(stream, g, img->dev, (int64_t)img->H * img->pitch, img->dtype, a, pct);
             break;
+        }
         case SK::Near:
             if (vol)
                 e = launch_near3(stream, g, vS, vD, mref(s.x), s.inv_out, mref(s.z), s.op, slot_ptr(s.out));
@@ -946,6 +987,25 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
     auto units = [&](int kind) { return hp[(size_t)kind * (n + 1) + n]; };
     auto bref = [](const Ref &r) { return BRef{r.slot, (uint32_t)(r.inv ? 1 : 0)}; };
 
+    // Arith steps si..sj: one launch per image (the arithmetic kernel has no
+    // batched form)
+    auto arith_images = [&](size_t si, size_t sj) -> hipError_t {
+        ArithGroup a = arith_group(P, si, sj);
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < n && e == hipSuccess; k++) {
+            const vlg_image *im = imgs[idx[k]];
+            char *wb = base + off[k];
+            for (size_t t = si; t <= sj && t - si < (size_t)kArithGroupProgs; t++) {
+                const int32_t o = P.steps[t].out;
+                a.out[t - si] = is_ext(o) ? ext[(size_t)k * nout + (size_t)ext_index(o)]
+                                          : (uint64_t *)(wb + lay[k].off_slots + (size_t)o * lay[k].mask_bytes);
+            }
+            e = launch_arith(c->stream, geo[k], im->dev, (int64_t)im->H * im->pitch, im->dtype, a,
+                             (const float *)(wb + lay[k].off_pct));
+        }
+        return e;
+    };
+
     auto enqueue_steps = [&]() -> int {
         for (size_t si = 0; si < P.steps.size(); si++) {
             const Step &s = P.steps[si];
@@ -953,7 +1013,9 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
             if (s.group >= 0) {
                 size_t sj = si;
                 while (sj + 1 < P.steps.size() && P.steps[sj + 1].group == s.group) sj++;
-                if (s.kind == SK::Logic) {
+                if (s.kind == SK::Arith) {
+                    e = arith_images(si, sj);
+                } else if (s.kind == SK::Logic) {
                     BLogic b;
                     std::memset(&b, 0, sizeof b);
                     b.n = (int)(sj - si + 1);
@@ -1036,19 +1098,9 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                 break;
             case SK::Segment:
                 return fail(VLG_EINVAL, "internal: the batched schedule has no segments");
-            case SK::Arith: {
-                // one launch per image: the arithmetic kernel has no batched form
-                const ArithLaunch al = arith_launch(P, s);
-                for (int k = 0; k < n && e == hipSuccess; k++) {
-                    const vlg_image *im = imgs[idx[k]];
-                    char *wb = base + off[k];
-                    uint64_t *o = is_ext(s.out) ? ext[(size_t)k * nout + (size_t)ext_index(s.out)]
-                                                : (uint64_t *)(wb + lay[k].off_slots + (size_t)s.out * lay[k].mask_bytes);
-                    e = launch_arith(c->stream, geo[k], im->dev, (int64_t)im->H * im->pitch, im->dtype, al,
-                                     (const float *)(wb + lay[k].off_pct), o);
-                }
+            case SK::Arith:
+                e = arith_images(si, si);
                 break;
-            }
             }
             if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
         }

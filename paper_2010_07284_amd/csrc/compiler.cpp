@@ -1092,6 +1092,38 @@ void schedule_fused(Lower &L, int lanes) {
             }
             finish(u);
         }
+        {
+            // this round's arithmetic atoms after its other steps (all of them
+            // were ready together, so none reads another), in groups that one
+            // launch evaluates: the channels are then read once per group
+            std::stable_partition(out.begin() + pct_round_start, out.end(),
+                                  [](const Step &x) { return x.kind != SK::Arith; });
+            std::ptrdiff_t i = pct_round_start;
+            while (i < (std::ptrdiff_t)out.size() && out[(size_t)i].kind != SK::Arith) i++;
+            while (i < (std::ptrdiff_t)out.size()) {
+                std::ptrdiff_t j = i;
+                int ins = 0;
+                std::vector<int32_t> chans;
+                for (; j < (std::ptrdiff_t)out.size() && j - i < kArGroupProgs; j++) {
+                    const ArProgram &pr = L.ariths[(size_t)out[(size_t)j].arith];
+                    std::vector<int32_t> ch = chans;
+                    for (const ArInstr &in : pr.ins)
+                        if (in.op == AR_CHAN && std::find(ch.begin(), ch.end(), in.chan) == ch.end())
+                            ch.push_back(in.chan);
+                    if (ins + (int)pr.ins.size() > kArGroupInstrs || (int)ch.size() > kArGroupChans) break;
+                    ins += (int)pr.ins.size();
+                    chans = std::move(ch);
+                }
+                if (j - i > 1) {
+                    group++;
+                    for (std::ptrdiff_t k = i; k < j; k++) {
+                        out[(size_t)k].group = group;
+                        out[(size_t)k].span = 1000000 + group;
+                    }
+                }
+                i = j;
+            }
+        }
         for (SK k : {SK::Logic, SK::Near}) {
             std::vector<int> r = ready([&](const Unit &x) { return !x.ccl && kind_of(x) == k; });
             for (size_t i = 0; i < r.size(); i++) {

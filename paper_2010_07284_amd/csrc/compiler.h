@@ -31,6 +31,9 @@ struct ArProgram {
 };
 constexpr int kArMaxInstrs = 32;  // per program (both sides)
 constexpr int kArMaxDepth = 8;    // evaluation stack per side
+// arithmetic atoms evaluated by one launch (fused schedules): at most this
+// many programs, instructions in all, and distinct channels read
+constexpr int kArGroupProgs = 8, kArGroupInstrs = 96, kArGroupChans = 8;
 
 struct Node {
     Op op;

@@ -154,27 +154,38 @@ hipError_t launch_ccl_labels(hipStream_t s, const Geo &g, MRef b, const CclWork 
                              int32_t *labels);
 hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint8_t *out);
 
-// Arithmetic atom: a postfix program over channel values, constants and
-// percentile scalars, evaluated per pixel in float32 (one rounding per
-// operation), ins[0, lhs_len) the left side, the rest the right side;
-// out = lhs CMP rhs (CMP 0 >, 1 <, 2 >=, 3 <=).  Op codes as ArOp in
-// compiler.h.  Stack depth at most 8 per side.
-constexpr int kArithMax = 32;
+// Arithmetic atoms (arith.hip): postfix programs over channel values,
+// constants and percentile scalars, evaluated per pixel in float32 (one
+// rounding per operation).  Program p of a launch is ins[lhs[p], rhs[p]) (the
+// left side) and ins[rhs[p], end[p]) (the right side); out[p] = lhs CMP rhs
+// (cmp[p]: 0 >, 1 <, 2 >=, 3 <=).  Op codes as ArOp in compiler.h.  depth is
+// the height of the side's evaluation stack before the instruction (at most
+// 8 after it).  Every program of a launch reads its channels from one set of
+// at most kArithChans distinct channels, loaded once per pixel for all of
+// them; outputs are written in program order.
+constexpr int kArithMax = 32;        // instructions per program (both sides)
+constexpr int kArithGroupIns = 96;   // instructions of all programs of a launch
+constexpr int kArithGroupProgs = 8;  // programs per launch
+constexpr int kArithDepth = 8;       // evaluation stack per side
 struct ArithIns {
     uint8_t op;
-    uint8_t pad[3];
-    int32_t idx;  // position in ArithLaunch::ch (AR_CHAN) or percentile scalar (AR_PCT)
+    uint8_t depth;
+    uint8_t pad[2];
+    int32_t idx;  // position in ArithGroup::ch (AR_CHAN) or percentile scalar (AR_PCT)
     float c;      // AR_CONST
 };
-constexpr int kArithChans = 8;  // distinct channels a program may read
-struct ArithLaunch {
-    int32_t n, lhs_len, cmp, nch;
+constexpr int kArithChans = 8;  // distinct channels the programs of a launch may read
+struct ArithGroup {
+    int32_t n, nch;
     int32_t ch[kArithChans];  // the distinct channels read (AR_CHAN idx = position here)
-    ArithIns ins[kArithMax];
+    int32_t lhs[kArithGroupProgs], rhs[kArithGroupProgs], end[kArithGroupProgs], cmp[kArithGroupProgs];
+    uint64_t *out[kArithGroupProgs];
+    ArithIns ins[kArithGroupIns];
 };
-// img: channel 0 of the image; chan_elems: elements per channel (H * pitch)
+// img: channel 0 of the image; chan_elems: elements per channel (H * pitch).
+// Rejects (hipErrorInvalidValue) a group whose programs break the limits above.
 hipError_t launch_arith(hipStream_t s, const Geo &g, const void *img, int64_t chan_elems, int dtype,
-                        const ArithLaunch &a, const float *pct, uint64_t *out);
+                        const ArithGroup &a, const float *pct);
 
 // Volumes (vol.hip): D slices of S rows; the Geo is that of the D*S-row mask.
 // N over the 26-neighbourhood: out = (N(x) ^ inv_out) OP z (zop 0 and, 1 or).

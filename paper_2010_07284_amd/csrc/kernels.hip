@@ -1580,89 +1580,6 @@ __global__ __launch_bounds__(kSegWideThreads) void k_segment_wide(Geo g, SegProg
     }
 }
 
-// ------------------------------------------------------------------ arithmetic
-// A wave evaluates four consecutive mask words: lane l takes pixel 64*w + l
-// of each.  Every channel the program reads is loaded for all four words
-// before any arithmetic (up to 32 loads in flight per lane).  The program is
-// the same for every lane (kernel argument), so each instruction is a uniform
-// branch; the evaluation stack is eight registers shifted on push and pop (no
-// indexed private memory).  No contraction into fused multiply-adds: each
-// operation rounds once, as the oracle's float32 does.
-enum : uint8_t { KA_CONST = 0, KA_CHAN, KA_PCT, KA_NEG, KA_ABS, KA_ADD, KA_SUB, KA_MUL, KA_DIV, KA_MIN, KA_MAX };
-constexpr int kArithWords = 4;  // mask words per wave
-
-__device__ __forceinline__ float arith_side(const ArithLaunch &a, int k0, int k1, const float (&v)[kArithChans],
-                                            const float *__restrict__ pct) {
-#pragma clang fp contract(off)
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f;
-    auto push = [&](float x) {
-        s7 = s6; s6 = s5; s5 = s4; s4 = s3; s3 = s2; s2 = s1; s1 = s0; s0 = x;
-    };
-    for (int k = k0; k < k1; k++) {
-        const ArithIns in = a.ins[k];
-        switch (in.op) {
-        case KA_CONST: push(in.c); break;
-        case KA_CHAN: {
-            float x = v[0];
-#pragma unroll
-            for (int c = 1; c < kArithChans; c++)
-                if (in.idx == c) x = v[c];
-            push(x);
-            break;
-        }
-        case KA_PCT: push(glb(pct)[in.idx]); break;
-        case KA_NEG: s0 = -s0; break;
-        case KA_ABS: s0 = fabsf(s0); break;
-        default: {
-            const float x = s1, y = s0;
-            float r;
-            switch (in.op) {
-            case KA_ADD: r = x + y; break;
-            case KA_SUB: r = x - y; break;
-            case KA_MUL: r = x * y; break;
-            case KA_DIV: r = x / y; break;
-            case KA_MIN: r = y < x ? y : x; break;
-            default: r = y > x ? y : x; break;  // KA_MAX
-            }
-            s0 = r; s1 = s2; s2 = s3; s3 = s4; s4 = s5; s5 = s6; s6 = s7;
-        }
-        }
-    }
-    return s0;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_arith(Geo g, const T *__restrict__ img, int64_t chan_elems, ArithLaunch a,
-                                                   const float *__restrict__ pct, uint64_t *__restrict__ out) {
-    const int64_t w0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * kArithWords;
-    if (w0 >= g.nwords) return;
-    const int lane = lane_id();
-    int64_t e[kArithWords];
-#pragma unroll
-    for (int j = 0; j < kArithWords; j++) {
-        const int64_t wi = w0 + j < g.nwords ? w0 + j : w0;
-        const uint32_t row = fdiv((uint32_t)wi, g.wpr_mul, g.wpr_shift), w = (uint32_t)wi - row * (uint32_t)g.wpr;
-        e[j] = (int64_t)row * g.wpr * 64 + (int64_t)w * 64 + lane;
-    }
-    float v[kArithWords][kArithChans];
-#pragma unroll
-    for (int c = 0; c < kArithChans; c++)
-#pragma unroll
-        for (int j = 0; j < kArithWords; j++)
-            v[j][c] = c < a.nch ? (float)glb(img)[(int64_t)a.ch[c] * chan_elems + e[j]] : 0.f;
-#pragma unroll
-    for (int j = 0; j < kArithWords; j++) {
-        const int64_t wi = w0 + j;
-        const float l = arith_side(a, 0, a.lhs_len, v[j], pct), r = arith_side(a, a.lhs_len, a.n, v[j], pct);
-        const bool b = a.cmp == 0 ? l > r : a.cmp == 1 ? l < r : a.cmp == 2 ? l >= r : l <= r;
-        const uint64_t word = __ballot(b);
-        if (lane == j && wi < g.nwords) {
-            const uint32_t row = fdiv((uint32_t)wi, g.wpr_mul, g.wpr_shift), w = (uint32_t)wi - row * (uint32_t)g.wpr;
-            glb(out)[wi] = word & (w == (uint32_t)g.wpr - 1 ? g.tail : ~0ull);
-        }
-    }
-}
-
 int ntiles_x(const Geo &g) { return (g.BW + kTileBW - 1) / kTileBW; }
 int ntiles_y(const Geo &g, int tbh) { return (g.BH + tbh - 1) / tbh; }
 
@@ -1899,23 +1816,6 @@ hipError_t launch_segment(hipStream_t s, const Geo &g, const SegProg &p) {
         if (t.lds_bytes > kSegLdsBudget) return hipErrorInvalidValue;
         k_segment<<<ntx * nty, kThreads, t.lds_bytes, s>>>(g, p, t.tr, t.tw, ntx);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_arith(hipStream_t s, const Geo &g, const void *img, int64_t chan_elems, int dtype,
-                        const ArithLaunch &a, const float *pct, uint64_t *out) {
-    if (g.nwords == 0) return hipSuccess;
-    if (a.n < 1 || a.n > kArithMax || a.lhs_len < 1 || a.lhs_len >= a.n || a.cmp < 0 || a.cmp > 3 || a.nch < 0 ||
-        a.nch > kArithChans)
-        return hipErrorInvalidValue;
-    const int64_t per_block = (int64_t)(kThreads / 64) * kArithWords;
-    const int64_t blocks = (g.nwords + per_block - 1) / per_block;
-    if (dtype == 1)
-        k_arith<uint8_t><<<(unsigned)blocks, kThreads, 0, s>>>(g, (const uint8_t *)img, chan_elems, a, pct, out);
-    else if (dtype == 2)
-        k_arith<uint16_t><<<(unsigned)blocks, kThreads, 0, s>>>(g, (const uint16_t *)img, chan_elems, a, pct, out);
-    else
-        k_arith<float><<<(unsigned)blocks, kThreads, 0, s>>>(g, (const float *)img, chan_elems, a, pct, out);
     return hipGetLastError();
 }
 
