@@ -249,7 +249,8 @@ struct Layout {
     bool vol = false;       // volume labelling: voxel parents (4 B) then flag bytes at off_glab
 };
 
-size_t vol_label_bytes(const Geo &g) { return align256((size_t)g.H * g.W * 4); }
+// the block parents of a volume labelling (vl_nblocks <= g.BH * g.BW)
+size_t vol_label_bytes(const Geo &g) { return align256((size_t)g.BH * g.BW * 4); }
 
 Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8, bool pj = false,
                   bool vol = false) {
@@ -267,7 +268,7 @@ Layout layout_for(const Plan &P, const Geo &g, bool stage_packed, bool stage_u8,
     L.pj = pj && !vol;
     L.vol = vol;
     L.lane_bytes = P.ccl_count == 0 ? 0
-                   : vol          ? vol_label_bytes(g) + align256((size_t)g.H * g.W)
+                   : vol          ? vol_label_bytes(g) + align256((size_t)g.BH * g.BW)
                    : L.pj         ? align256(pj_bytes(g))
                                   : align256(nb * 4) + align256(nb);
     L.off_gflag = off + (P.ccl_count > 0 ? align256(nb * 4) : 0);
@@ -711,7 +712,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
             if (L.vol) {
                 // the whole voxel labelling, then the seeds
                 e = launch_vl_label(stream, g, vS, vD, mref(s.x), vP, w.guard);
-                if (e == hipSuccess) e = launch_vl_clear_flags(stream, g, vflag);
+                if (e == hipSuccess) e = launch_vl_clear_flags(stream, g, vS, vD, vflag);
                 if (e == hipSuccess) e = launch_vl_seed(stream, g, vS, vD, mref(s.x), mref(s.y), mref(s.z), vP, vflag, 0);
             } else if (L.pj) {
                 // the whole labelling (host-waited rounds), then the seeds
@@ -1481,8 +1482,14 @@ int vlg_ccl_labels3(vlg_ctx *c, const uint64_t *mask_dev, int depth, int height,
     DeviceGuard dg(c->device);
     const Geo g = make_geo(depth * height, width);
     if (g.nwords == 0) return VLG_OK;
-    // the caller's label array is the parent array of the labelling
-    HIP_TRY(launch_vl_label(c->stream, g, height, depth, MRef{mask_dev, 0ull}, (int *)labels_dev, c->guard()));
+    // block parents and each component's smallest voxel in the workspace
+    const size_t pb = align256((size_t)vl_nblocks(g, height, depth) * 4);
+    int rc = ensure_ws(c, 2 * pb);
+    if (rc != VLG_OK) return rc;
+    int *P = (int *)c->ws, *canon = (int *)((char *)c->ws + pb);
+    const MRef b{mask_dev, 0ull};
+    HIP_TRY(launch_vl_label(c->stream, g, height, depth, b, P, c->guard()));
+    HIP_TRY(launch_vl_labels(c->stream, g, height, depth, b, P, canon, labels_dev));
     return VLG_OK;
 }
 

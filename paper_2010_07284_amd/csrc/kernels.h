@@ -191,10 +191,18 @@ hipError_t launch_arith(hipStream_t s, const Geo &g, const void *img, int64_t ch
 // N over the 26-neighbourhood: out = (N(x) ^ inv_out) OP z (zop 0 and, 1 or).
 hipError_t launch_near3(hipStream_t s, const Geo &g, int S, int D, MRef x, int inv_out, MRef z, int zop,
                         uint64_t *out);
-// 26-connected labelling of b: P[v] = the smallest voxel of v's component
-// (voxel index (z*S + y)*W + x), -1 for background; P has g.H * g.W entries.
+// 26-connected labelling of b over blocks of 2 x 2 x 2 voxels: P[k] = the
+// root block (the smallest block id) of block k's component, -1 for a block
+// without voxels of b; P has vl_nblocks entries, at most g.BH * g.BW (the
+// block count of the D*S-row mask).
+int64_t vl_nblocks(const Geo &g, int S, int D);
 hipError_t launch_vl_label(hipStream_t s, const Geo &g, int S, int D, MRef b, int *P, const LoopGuard &gd);
-hipError_t launch_vl_clear_flags(hipStream_t s, const Geo &g, uint8_t *flag);
+// labels[v] (voxel index (z*S + y)*W + x) = the smallest voxel of v's
+// component, -1 for background, from a labelling P; canon: vl_nblocks ints.
+hipError_t launch_vl_labels(hipStream_t s, const Geo &g, int S, int D, MRef b, const int *P, int *canon,
+                            int *labels);
+// flag: one byte per block
+hipError_t launch_vl_clear_flags(hipStream_t s, const Geo &g, int S, int D, uint8_t *flag);
 hipError_t launch_vl_seed(hipStream_t s, const Geo &g, int S, int D, MRef b, MRef y, MRef z, const int *P,
                           uint8_t *flag, int user);
 hipError_t launch_vl_reseed(hipStream_t s, const Geo &g, int S, int D, MRef sm, const int *P, uint8_t *flag,
