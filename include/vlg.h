@@ -362,7 +362,14 @@ int vlg_stream_copy(vlg_ctx *ctx, void *dst_dev, const void *src_dev, int64_t by
  *     as a graph (graph mode runs it launch by launch), and images need
  *     rows and columns below 65535.  vlg_check_batch always uses union-find.
  *   VLG_TUNE_PJ_RECONNECT: main iterations between reconnects of the
- *     pointer-jumping labelling, 1..64 (default 16). */
+ *     pointer-jumping labelling, 1..64 (default 16).
+ *   VLG_TUNE_ARITH: the kernel of arithmetic atoms.  VLG_ARITH_COMPILED
+ *     (default): the programs of a launch compiled with hipRTC into a
+ *     straight-line kernel the first time they run (about a second per
+ *     distinct group of programs, then kept until the process ends; a group
+ *     that does not compile runs on the interpreter).
+ *     VLG_ARITH_INTERPRETER: one precompiled kernel that decodes the
+ *     programs.  Both give the same bits. */
 #define VLG_TUNE_CCL_TILE_ROWS 0
 #define VLG_TUNE_NEAR_ROWS 1
 #define VLG_TUNE_BATCH_GRID 2
@@ -370,8 +377,11 @@ int vlg_stream_copy(vlg_ctx *ctx, void *dst_dev, const void *src_dev, int64_t by
 #define VLG_TUNE_FUSE_HALO 4
 #define VLG_TUNE_CCL_ALGO 5
 #define VLG_TUNE_PJ_RECONNECT 6
+#define VLG_TUNE_ARITH 7
 #define VLG_CCL_UNION_FIND 1      /* values of VLG_TUNE_CCL_ALGO */
 #define VLG_CCL_POINTER_JUMPING 2
+#define VLG_ARITH_INTERPRETER 1   /* values of VLG_TUNE_ARITH */
+#define VLG_ARITH_COMPILED 2
 /* Force `value` for every image (value 0 returns to table/default). */
 int vlg_set_tunable(vlg_ctx *ctx, int which, int value);
 /* The value used for an image of height x width on this context. */

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "compiler.h"
+#include "arith_jit.h"
 #include "kernels.h"
 #include "vlg.h"
 
@@ -158,9 +159,9 @@ struct GraphKey {
 };
 
 // Tunables (VLG_TUNE_*): a value of 0 means "not set" (default rule).
-constexpr int kNumTunables = 7;
-const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid", "ccl_lanes",
-                                                 "fuse_halo",     "ccl_algo",       "pj_reconnect"};
+constexpr int kNumTunables = 8;
+const char *const kTunableNames[kNumTunables] = {"ccl_tile_rows", "near_band_rows", "batch_grid",   "ccl_lanes",
+                                                 "fuse_halo",     "ccl_algo",       "pj_reconnect", "arith_kernel"};
 constexpr int kPjReconnectDefault = 16;
 
 bool tunable_valid(int which, int v) {
@@ -172,6 +173,7 @@ bool tunable_valid(int which, int v) {
     case VLG_TUNE_FUSE_HALO: return valid_fuse_halo(v);
     case VLG_TUNE_CCL_ALGO: return v == VLG_CCL_UNION_FIND || v == VLG_CCL_POINTER_JUMPING;
     case VLG_TUNE_PJ_RECONNECT: return v >= 1 && v <= 64;
+    case VLG_TUNE_ARITH: return v == VLG_ARITH_INTERPRETER || v == VLG_ARITH_COMPILED;
     }
     return false;
 }
@@ -317,6 +319,7 @@ int tuned_value(const vlg_ctx *c, int which, int H, int W) {
     case VLG_TUNE_BATCH_GRID: return kBatchGridDefault;
     case VLG_TUNE_CCL_LANES: return 1;
     case VLG_TUNE_FUSE_HALO: return kFuseHaloDefault;
+    case VLG_TUNE_ARITH: return VLG_ARITH_COMPILED;
     }
     return 0;
 }
@@ -505,6 +508,33 @@ ArithGroup arith_group(const Plan &P, size_t si, size_t sj) {
     return a;
 }
 
+// Launch the Arith group `a` with the kernel VLG_TUNE_ARITH selects for an
+// image of H x W: its compiled kernel (compiled on first use; see
+// prepare_arith), or the interpreter when that is selected or the group
+// does not compile.
+hipError_t arith_launch(const vlg_ctx *c, hipStream_t s, const Geo &g, int H, int W, const void *img,
+                        int64_t chan_elems, int dtype, const ArithGroup &a, const float *pct) {
+    if (a.n >= 1 && tuned_value(c, VLG_TUNE_ARITH, H, W) != VLG_ARITH_INTERPRETER) {
+        if (hipFunction_t fn = arith_jit_function(c->device, a, dtype, nullptr))
+            return launch_arith_jit(fn, s, g, img, chan_elems, a, pct);
+    }
+    return launch_arith(s, g, img, chan_elems, dtype, a, pct);
+}
+
+// Compile the Arith groups of P before anything is captured (compiling loads
+// a module, which stream capture must not see).
+void prepare_arith(const vlg_ctx *c, const Plan &P, int H, int W, int dtype) {
+    if (tuned_value(c, VLG_TUNE_ARITH, H, W) == VLG_ARITH_INTERPRETER) return;
+    for (size_t si = 0; si < P.steps.size(); si++) {
+        if (P.steps[si].kind != SK::Arith) continue;
+        size_t sj = si;
+        while (P.steps[si].group >= 0 && sj + 1 < P.steps.size() && P.steps[sj + 1].group == P.steps[si].group) sj++;
+        const ArithGroup a = arith_group(P, si, sj);
+        if (a.n >= 1) (void)arith_jit_function(c->device, a, dtype, nullptr);
+        si = sj;
+    }
+}
+
 using StepHook = void (*)(void *, size_t, bool);
 
 // Enqueue every step of P on the stream.  ext[k] is the packed device buffer
@@ -634,7 +664,8 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
                 ArithGroup a = arith_group(P, si, sj);
                 for (size_t k = si; k <= sj && k - si < (size_t)kArithGroupProgs; k++)
                     a.out[k - si] = slot_ptr(P.steps[k].out);
-                e = launch_arith(stream, g, img->dev, (int64_t)img->H * img->pitch, img->dtype, a, pct);
+                e = arith_launch(c, stream, g, img->H, img->W, img->dev, (int64_t)img->H * img->pitch, img->dtype, a,
+                                 pct);
             } else if (s.kind == SK::Logic) {
                 LogicBatch b;
                 b.n = (int)(sj - si + 1);
@@ -699,7 +730,7 @@ int enqueue_plan(vlg_ctx *c, const Plan &P, const vlg_image *img, const Layout &
         case SK::Arith: {
             ArithGroup a = arith_group(P, si, si);
             a.out[0] = slot_ptr(s.out);
-            e = launch_arith(stream, g, img->dev, (int64_t)img->H * img->pitch, img->dtype, a, pct);
+            e = arith_launch(c, stream, g, img->H, img->W, img->dev, (int64_t)img->H * img->pitch, img->dtype, a, pct);
             break;
         }
         case SK::Near:
@@ -823,6 +854,7 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
         return VLG_OK;
     };
 
+    prepare_arith(c, P, img->H, img->W, img->dtype);
     if (c->mode == VLG_MODE_GRAPH && !pj) {
         GraphKey key;
         key.v = {(uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)img->dev, (uintptr_t)img->H, (uintptr_t)img->W,
@@ -1001,7 +1033,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                 a.out[t - si] = is_ext(o) ? ext[(size_t)k * nout + (size_t)ext_index(o)]
                                           : (uint64_t *)(wb + lay[k].off_slots + (size_t)o * lay[k].mask_bytes);
             }
-            e = launch_arith(c->stream, geo[k], im->dev, (int64_t)im->H * im->pitch, im->dtype, a,
+            e = arith_launch(c, c->stream, geo[k], im->H, im->W, im->dev, (int64_t)im->H * im->pitch, im->dtype, a,
                              (const float *)(wb + lay[k].off_pct));
         }
         return e;

@@ -81,10 +81,11 @@ def test_cap_validation():
     assert e.value.code == -1
     vlg.set_loop_cap(ctx, 5)
     vlg.set_loop_cap(ctx, 0)
-    # concurrent labelling lanes are switched off: only one lane is accepted
-    vlg.set_tunable(ctx, "ccl_lanes", 1)
-    for lanes in (2, 4):
+    # labellings run together: 1, 2, 4 or 8 lanes, nothing else
+    for lanes in (1, 2, 4, 8):
+        vlg.set_tunable(ctx, "ccl_lanes", lanes)
+    for lanes in (3, 16, -1):
         with pytest.raises(vlg.VlgError) as e:
             vlg.set_tunable(ctx, "ccl_lanes", lanes)
-        assert e.value.code == -1 and "switched off" in str(e.value)
+        assert e.value.code == -1
     vlg.set_tunable(ctx, "ccl_lanes", 0)

@@ -1,5 +1,6 @@
-"""CPU model of the flatten pass of the voxel labelling (k_vl_flatten in
-vol.hip) under randomized thread schedules.
+"""CPU model of the flatten pass of the volume labelling (k_vb_flatten in
+vol.hip; it walks the same way over voxels in its first version and over
+2 x 2 x 2 blocks now) under randomized thread schedules.
 
 TEST INFRASTRUCTURE.  After the union pass every voxel's parent chain ends
 at its component's root; the flatten pass gives every voxel its root.  Each
