@@ -322,8 +322,9 @@ def profile(ctx, f, img, iters=5):
 
 
 TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2, "ccl_lanes": 3, "fuse_halo": 4,
-            "ccl_algo": 5, "pj_reconnect": 6}
+            "ccl_algo": 5, "pj_reconnect": 6, "arith_kernel": 7}
 CCL_UNION_FIND, CCL_POINTER_JUMPING = 1, 2
+ARITH_INTERPRETER, ARITH_COMPILED = 1, 2
 
 
 def set_tunable(ctx, name, value):

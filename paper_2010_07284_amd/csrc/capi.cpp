@@ -861,7 +861,7 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
                  (uintptr_t)img->dtype, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)c->ws,
                  (uintptr_t)tuning_for(c, img->H, img->W).ccl_tbh,
                  (uintptr_t)tuned_value(c, VLG_TUNE_NEAR_ROWS, img->H, img->W), (uintptr_t)c->loop_cap,
-                 (uintptr_t)img->D};
+                 (uintptr_t)img->D, (uintptr_t)tuned_value(c, VLG_TUNE_ARITH, img->H, img->W)};
         for (size_t k = 0; k < which.size(); k++) key.v.push_back((uintptr_t)outs[k]);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -1153,6 +1153,12 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
         return VLG_OK;
     };
 
+    for (int k = 0; k < n; k++) {
+        const vlg_image *im = imgs[idx[k]];
+        if (k == 0 || im->H != imgs[idx[k - 1]]->H || im->W != imgs[idx[k - 1]]->W ||
+            im->dtype != imgs[idx[k - 1]]->dtype)
+            prepare_arith(c, P, im->H, im->W, im->dtype);
+    }
     if (c->mode == VLG_MODE_GRAPH) {
         GraphKey key;
         key.v = {(uintptr_t)0xBA7C, (uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)c->ws, (uintptr_t)tbh,
@@ -1160,7 +1166,8 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
         for (int k = 0; k < n; k++) {
             const vlg_image *im = imgs[idx[k]];
             key.v.insert(key.v.end(), {(uintptr_t)im->dev, (uintptr_t)im->H, (uintptr_t)im->W,
-                                       (uintptr_t)im->dtype, (uintptr_t)im->pitch});
+                                       (uintptr_t)im->dtype, (uintptr_t)im->pitch,
+                                       (uintptr_t)tuned_value(c, VLG_TUNE_ARITH, im->H, im->W)});
             for (size_t o = 0; o < nout; o++) key.v.push_back((uintptr_t)outs[(size_t)idx[k] * nout + o]);
         }
         auto it = c->graphs.find(key);
@@ -1973,10 +1980,11 @@ int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int it
     // fits the plan of every candidate the tuner may try
     const std::vector<int> fuse_cands = {1, 4, 8, 16}, lane_cands = {1, 2, 4, 8};
     const Plan &P1 = f->plan(which, Mode::Fused, 1, 1);
-    bool has_near = false;
+    bool has_near = false, has_arith = false;
     int local_steps = 0;
     for (const Step &st : P1.steps) {
         has_near |= st.kind == SK::Near;
+        has_arith |= st.kind == SK::Arith;
         local_steps += st.kind == SK::Near || st.kind == SK::Logic;
     }
     const bool try_pj = P1.ccl_count > 0 && pj_shape_ok(img->H, img->W);
@@ -1995,6 +2003,7 @@ int vlg_autotune(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int it
     if (try_lanes) space.push_back({VLG_TUNE_CCL_LANES, lane_cands});
     if (local_steps >= 2) space.push_back({VLG_TUNE_FUSE_HALO, fuse_cands});
     if (has_near) space.push_back({VLG_TUNE_NEAR_ROWS, {4, 8, 16, 32}});
+    if (has_arith) space.push_back({VLG_TUNE_ARITH, {VLG_ARITH_COMPILED, VLG_ARITH_INTERPRETER}});
     int rc = ensure_ws(c, need);
     if (rc != VLG_OK) return rc;
     const std::pair<int, int> cls{log2_class(img->H), log2_class(img->W)};

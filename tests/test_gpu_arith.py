@@ -13,9 +13,14 @@ from tests.gpu_util import assert_same, gpu_run
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx():
-    return vlg.create()
+@pytest.fixture(scope="module", params=["compiled", "interpreter"])
+def ctx(request):
+    """Every test runs with both kernels of arithmetic atoms: the programs
+    compiled into a straight-line kernel, and the interpreter."""
+    c = vlg.create()
+    vlg.set_tunable(c, "arith_kernel",
+                    vlg.ARITH_COMPILED if request.param == "compiled" else vlg.ARITH_INTERPRETER)
+    return c
 
 
 def arith_src(rng):
@@ -71,3 +76,38 @@ def test_batch_with_arithmetic(ctx):
         got = [vlg.unpack(o, x.shape[1], x.shape[2]) for o in row]
         assert_same(src, x, got, tag=f"batch {x.shape}")
     del torch
+
+
+def full_group_src():
+    """Eleven arithmetic atoms over eight channels: stacks eight deep, every
+    operator, percentiles and constants; more programs and instructions than
+    one launch takes, so the fused schedule splits them over launches."""
+    I = [f"intensity(img, {c})" for c in range(8)]
+    deep = f"{I[0]} + ({I[1]} * ({I[2]} - ({I[3]} / ({I[4]} + ({I[5]} - ({I[6]} * {I[7]}))))))"
+    atoms = [
+        f"{deep} >. 0.3",
+        f"abs({I[0]} - {I[7]}) <=. min({I[3]}, 0.5)",
+        f"max({I[1]}, {I[2]}) / ({I[4]} + 2) >=. percentile(img, 5, 0.3)",
+        f"-{I[6]} * 3 <. {I[2]} - 1",
+        f"{I[3]} * {I[3]} - {I[4]} >. {I[5]} / 3",
+        f"min(max({I[0]}, {I[1]}), {I[2]}) <. max(min({I[3]}, {I[4]}), {I[5]})",
+        f"({I[6]} - {I[7]}) / ({I[6]} + {I[7]}) >=. 0.1",
+        f"abs(-{I[1]}) + abs({I[2]} - 0.25) <=. 1.5",
+        f"{I[4]} - percentile(img, 4, 0.7) >. {I[0]} * 0.125",
+        f"{deep} <=. {I[0]} * 2",
+        f"-({I[5]} - {I[3]}) >. -0.2",
+    ]
+    return "".join(f'output "a{k}" {a}\n' for k, a in enumerate(atoms))
+
+
+@pytest.mark.parametrize("mode", ["perop", "fused", "graph"])
+def test_full_groups(ctx, mode):
+    rng = np.random.default_rng(11)
+    img = (rng.random((8, 67, 203)) * 2 - 0.5).astype(np.float32)
+    src = full_group_src()
+    assert_same(src, img, gpu_run(ctx, src, img, mode=mode), tag=f"full groups {mode}")
+    if mode == "fused":
+        plan = vlg.formula_plan(vlg.compile_formula(ctx, src), "fused", 1)
+        groups = {st["group"] for st in plan["steps"] if st["kind"] == "arith"}
+        assert len([g for g in groups if g >= 0]) >= 2
+
