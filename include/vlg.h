@@ -307,14 +307,17 @@ typedef struct vlg_kernel_time {
 int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_kernel_time *out,
                 int max_out, int *n_out);
 /* Measurement of one kernel without per-launch events: enqueues the fused
- * schedule of every output of f on img up to and including its first
- * single (ungrouped) step of `kind` ("atoms", "logic", "near", "ccl_local",
- * "ccl_gather", "segment" or "arith": kinds whose repeated launch redoes
- * the same work on the same inputs), then that step `reps` times back to
- * back between two HIP events on the context's stream.  *avg_ms receives
- * the mean time of one launch of the step, *bytes its algorithmic bytes (as
- * in vlg_profile).  Synchronises the stream.  VLG_EINVAL when the schedule
- * has no such step or labels with the pointer-jumping schedule. */
+ * schedule (one labelling at a time) of every output of f on img up to and
+ * including its first single (ungrouped) step of `kind` ("atoms", "logic",
+ * "near", "ccl_local", "ccl_merge", "ccl_flag", "ccl_gather", "segment" or
+ * "arith"), then that step `reps` times back to back between two HIP events
+ * on the context's stream.  A merge or flag step repeated alone would find
+ * its work done, so for those the repeated unit starts at the labelling's
+ * tile-local pass, and the same unit without the step is timed too and
+ * subtracted.  *avg_ms receives the mean time of one launch of the step,
+ * *bytes its algorithmic bytes (as in vlg_profile).  Synchronises the
+ * stream.  VLG_EINVAL when the schedule has no such step or labels with the
+ * pointer-jumping schedule. */
 int vlg_profile_step(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, const char *kind, int reps,
                      double *avg_ms, double *bytes);
 /* Measurement: the HBM reference.  Copies `bytes` (a multiple of width) from
