@@ -372,6 +372,11 @@ __device__ __forceinline__ int lds_ld(int *p) {
 __device__ __forceinline__ int lane_prev(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
 }
+// Value of v in the next lane of the wave (DPP wave shift left by one; lane
+// 63 receives 0).
+__device__ __forceinline__ int lane_next(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+}
 
 // Union of a and b on the LDS forest L (L[x] <= x, a root is the smallest
 // entry of its set).  Both walks advance together, one path-halving step per
@@ -601,8 +606,8 @@ constexpr int ccl_local_threads() {
 }
 
 // Tile-local labelling of b: TBH block rows x 64 block columns (2*TBH x 128
-// pixels) per workgroup of NWAVES waves.  Wave v owns block rows v,
-// v+NWAVES, ... (RPW of them), one lane per block column, and keeps each
+// pixels) per workgroup of NWAVES waves.  Wave v owns the RPW consecutive
+// block rows RPW*v .. RPW*v+RPW-1, one lane per block column, and keeps each
 // row's block state in a register from the first phase to the last.  Horizontally
 // connected blocks form runs, found with a ballot and labelled by their first
 // block without any atomics.  Runs of consecutive rows are then united once
@@ -693,13 +698,13 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
         return;
     }
 
-    // rows: block bits, runs, seeds.  st[j] (row wave + NWAVES*j) = bits | run << 4 |
+    // rows: block bits, runs, seeds.  st[j] (row RPW*wave + j) = bits | run << 4 |
     // seed << 10 | (connected to the left block) << 11
     const int w = lane >> 5, sh = (lane & 31) * 2;
     uint32_t st[RPW];
 #pragma unroll
     for (int j = 0; j < RPW; j++) {
-        const int lby = wave + NWAVES * j, i = lby * TBW + lane;
+        const int lby = RPW * wave + j, i = lby * TBW + lane;
         const uint32_t bits = (uint32_t)((sb[2 * lby][w] >> sh) & 3) | ((uint32_t)((sb[2 * lby + 1][w] >> sh) & 3) << 2);
         uint32_t seed = 0;
         if (any & 2) {
@@ -724,13 +729,12 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
         const uint64_t upto = starts & (~0ull >> (63 - lane));
         const int run = upto ? 63 - __builtin_clzll(upto) : lane;
         st[j] = bits | ((uint32_t)run << 4) | (seed << 10) | (conn ? 1u << 11 : 0u);
-        sbr[i] = (uint16_t)(bits | ((uint32_t)run << 4));
+        if (j == RPW - 1) sbr[i] = (uint16_t)(bits | ((uint32_t)run << 4));  // read by the next wave's row 0
         sflag[i] = (uint8_t)(seed << 1);
         L[i] = bits ? lby * TBW + run : i;
     }
     auto st_bits = [](uint32_t s) { return s & 15u; };
     auto st_run = [](uint32_t s) { return (int)((s >> 4) & 63u); };
-    __syncthreads();
 
     // unite the runs of each row with the runs they touch in the row above.
     // The wave first lists the pairs of all its rows (at most three per lane
@@ -738,16 +742,18 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     // a row's unions are usually held by a few lanes (the run starts), and
     // taking them row by row in those lanes would chain the rows' union walks
     // one after another.  Pairs beyond the queue's capacity are united by
-    // their own lane at once.
+    // their own lane at once (after the barrier, when every entry of L is
+    // set).  The row above a wave's row j >= 1 is its row j-1, in registers
+    // (its neighbours' entries through DPP lane shifts), so those rows list
+    // their pairs before the barrier; only row 0 reads the row above, the
+    // previous wave's last row, from LDS after it.
     int npairs = 0;  // wave-uniform
     bool ok = true;  // no walk of this lane hit the loop cap
-#pragma unroll
-    for (int j = 0; j < RPW; j++) {
-        const int lby = wave + NWAVES * j, up = (lby - 1) * TBW + lane;
+    auto list_pairs = [&](int j, uint32_t ul, uint32_t uc, uint32_t ur) {
+        const int lby = RPW * wave + j;
         const uint32_t bits = st_bits(st[j]);
         int c0 = -1, c1 = -1, c2 = -1;
         if (lby > 0 && bits) {
-            const uint32_t ul = lane > 0 ? sbr[up - 1] : 0u, uc = sbr[up], ur = lane < 63 ? sbr[up + 1] : 0u;
             if ((bits & 1) && (ul & 8)) c0 = (int)(ul >> 4);
             if ((bits & 3) && (uc & 12)) c1 = (int)(uc >> 4);
             if ((bits & 2) && (ur & 4)) c2 = (int)(ur >> 4);
@@ -776,6 +782,23 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
             }
             npairs += __popcll(has);
         }
+    };
+    // (rows j >= 1 unite only blocks of this wave's rows, whose entries of L
+    // this wave has written: a wave-level handoff makes them visible)
+    wave_lds_handoff();
+#pragma unroll
+    for (int j = 1; j < RPW; j++) {
+        // block state of the row above: bits | run << 4, for lanes l-1, l, l+1
+        const uint32_t uc = st[j - 1] & 0x3FFu;
+        list_pairs(j, (uint32_t)lane_prev((int)uc), uc, (uint32_t)lane_next((int)uc));
+    }
+    __syncthreads();
+    {
+        const int up = (RPW * wave - 1) * TBW + lane;  // the previous wave's last row
+        const bool have = wave > 0;
+        const uint32_t ul = have && lane > 0 ? sbr[up - 1] : 0u, uc = have ? sbr[up] : 0u,
+                       ur = have && lane < 63 ? sbr[up + 1] : 0u;
+        list_pairs(0, ul, uc, ur);
     }
     wave_lds_handoff();  // the queue entries of every lane, then the reads
     for (int q = lane; q < (npairs < kPairQueue ? npairs : kPairQueue); q += 64) {
@@ -788,7 +811,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     // through their run start
 #pragma unroll
     for (int j = 0; j < RPW; j++) {
-        const int i = (wave + NWAVES * j) * TBW + lane;
+        const int i = (RPW * wave + j) * TBW + lane;
         if (st_bits(st[j]) && st_run(st[j]) == lane) L[i] = lds_root(L, i, gd.cap, ok);
     }
     __syncthreads();
@@ -798,10 +821,10 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     // bytes)
     int root[RPW];
 #pragma unroll
-    for (int j = 0; j < RPW; j++) root[j] = L[(wave + NWAVES * j) * TBW + st_run(st[j])];
+    for (int j = 0; j < RPW; j++) root[j] = L[(RPW * wave + j) * TBW + st_run(st[j])];
 #pragma unroll
     for (int j = 0; j < RPW; j++) {
-        const int lby = wave + NWAVES * j;
+        const int lby = RPW * wave + j;
         const uint32_t f = ((st[j] >> 9) & 2u) | ((lby == 0 || lby == TBH - 1 || lane == 0 || lane == TBW - 1) ? 1u : 0u);
         if (st_bits(st[j]) && f) {
             const int r = root[j];
@@ -812,7 +835,7 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
 
 #pragma unroll
     for (int j = 0; j < RPW; j++) {
-        const int lby = wave + NWAVES * j, i = lby * TBW + lane;
+        const int lby = RPW * wave + j, i = lby * TBW + lane;
         const int by = ty * TBH + lby, bx = tx * TBW + lane;
         if (by >= g.BH || bx >= g.BW) continue;
         const int64_t id = (int64_t)by * g.BW + bx;

@@ -10,7 +10,17 @@ a seeded scheduler picks which lane performs its next access, so the model
 explores interleavings of the lanes of all waves between the workgroup
 barriers (sequentially consistent per access, like one LDS per workgroup).
 
-Two resolution variants are modelled:
+Two row layouts are modelled:
+  "consecutive"  wave v owns block rows RPW*v .. RPW*v+RPW-1 (the shipped
+                 kernel): rows after a wave's first list their union pairs
+                 before the workgroup barrier (the row above is the wave's
+                 own), and the pairs that do not fit the queue are united by
+                 their lane at once, touching only the wave's own rows while
+                 the other waves may still write theirs; the first row lists
+                 its pairs after the barrier;
+  "interleaved"  wave v owns rows v, v+NW, ... and lists every pair after
+                 the barrier (the earlier layout).
+and two resolution variants:
   "own"    each run start is resolved by the lane of its own column (the
            shipped kernel);
   "queue"  the run starts of a wave's rows are listed in the wave's LDS queue
@@ -77,13 +87,14 @@ def reference_roots(bits):
 class Tile:
     """Shared state of one workgroup and the per-lane programs."""
 
-    def __init__(self, bits, nwaves, queue_cap=192, variant="own"):
+    def __init__(self, bits, nwaves, queue_cap=192, variant="own", layout="consecutive"):
         self.bits = bits
         self.TBH, self.TBW = bits.shape
         self.NW = nwaves
         self.RPW = self.TBH // nwaves
         self.cap = queue_cap
         self.variant = variant
+        self.layout = layout
         n = self.TBH * self.TBW
         self.L = list(range(n))
         self.sbr = [0] * n
@@ -109,15 +120,27 @@ class Tile:
                 self.sbr[i] = b | (r << 4)
                 self.L[i] = lby * TBW + r if b else i
 
+    def row_of(self, wave, j):
+        return self.RPW * wave + j if self.layout == "consecutive" else wave + self.NW * j
+
+    def listing_order(self):
+        """(j, before_barrier) in the order a wave lists its rows' pairs."""
+        if self.layout == "consecutive":
+            return [(j, True) for j in range(1, self.RPW)] + [(0, False)]
+        return [(j, False) for j in range(self.RPW)]
+
     # ---- the wave-collective parts (ballot/mbcnt) are deterministic
     def wave_pairs(self, wave):
         """Union pairs of a wave in queue order, and the overflow pairs of each
-        lane in program order (united at once by that lane)."""
+        lane in program order (united at once by that lane): those listed
+        before the barrier and those listed after it."""
         TBW = self.TBW
-        queue, overflow = [], {l: [] for l in range(TBW)}
+        queue = []
+        early = {l: [] for l in range(TBW)}
+        overflow = {l: [] for l in range(TBW)}
         npairs = 0
-        for j in range(self.RPW):
-            lby = wave + self.NW * j
+        for j, before in self.listing_order():
+            lby = self.row_of(wave, j)
             cs_all = []
             for lane in range(TBW):
                 b = int(self.bits[lby, lane])
@@ -157,9 +180,9 @@ class Tile:
                     if npairs < self.cap:
                         queue.append(pair)
                     else:
-                        overflow[lane].append(pair)
+                        (early if before else overflow)[lane].append(pair)
                     npairs += 1
-        return queue, overflow
+        return queue, early, overflow
 
     # ---- lane programs: yield before each LDS access
     def unite(self, a, b):
@@ -261,16 +284,27 @@ def run_phase(progs, waves_of, rng):
                         waiting.discard(j)
 
 
-def simulate(bits, nwaves, seed, variant="own", queue_cap=192):
+def simulate(bits, nwaves, seed, variant="own", queue_cap=192, layout="consecutive"):
     """Run the pass once under the schedule drawn from `seed`; returns the
     (TBH, 64) array of roots (-1 for background) it produces."""
     rng = np.random.default_rng(seed)
-    t = Tile(bits, nwaves, queue_cap=queue_cap, variant=variant)
+    t = Tile(bits, nwaves, queue_cap=queue_cap, variant=variant, layout=layout)
     TBW = t.TBW
-    # union phase
+    pairs = [t.wave_pairs(wave) for wave in range(nwaves)]
+    # before the barrier: overflow pairs of the rows listed there, every wave
+    # at once (each touches only its own rows of L)
     progs, waves_of = [], []
     for wave in range(nwaves):
-        queue, overflow = t.wave_pairs(wave)
+        queue, early, overflow = pairs[wave]
+        for lane in range(TBW):
+            if early[lane]:
+                progs.append(t.union_program(early[lane], []))
+                waves_of.append(wave)
+    run_phase(progs, waves_of, rng)
+    # union phase after the barrier
+    progs, waves_of = [], []
+    for wave in range(nwaves):
+        queue, early, overflow = pairs[wave]
         for lane in range(TBW):
             progs.append(t.union_program(overflow[lane], queue[lane::64]))
             waves_of.append(wave)
@@ -280,7 +314,7 @@ def simulate(bits, nwaves, seed, variant="own", queue_cap=192):
     for wave in range(nwaves):
         starts = []
         for j in range(t.RPW):
-            lby = wave + nwaves * j
+            lby = t.row_of(wave, j)
             for lane in range(TBW):
                 if t.bits[lby, lane] and t.run[lby, lane] == lane:
                     starts.append((lane, lby * TBW + lane))

@@ -22,21 +22,32 @@ def patterns(rng, tbh):
     yield diag
 
 
-@pytest.mark.parametrize("variant", ["own", "queue"])
+@pytest.mark.parametrize("layout,variant", [("consecutive", "own"), ("interleaved", "own"),
+                                            ("interleaved", "queue")])
 @pytest.mark.parametrize("tbh,nwaves", [(8, 4), (16, 4), (32, 8)])
-def test_protocol_under_random_schedules(variant, tbh, nwaves):
+def test_protocol_under_random_schedules(layout, variant, tbh, nwaves):
     rng = np.random.default_rng(tbh * 10 + nwaves)
     for p, px in enumerate(patterns(rng, tbh)):
         bits = M.tile_blocks(px)
         ref = M.reference_roots(bits)
         for s in range(2 if tbh == 32 else 3):
-            out = M.simulate(bits, nwaves, seed=1000 * p + s, variant=variant)
-            assert np.array_equal(out, ref), (variant, tbh, p, s)
+            out = M.simulate(bits, nwaves, seed=1000 * p + s, variant=variant, layout=layout)
+            assert np.array_equal(out, ref), (layout, variant, tbh, p, s)
 
 
 def test_overflow_pattern_overflows():
     stripes = np.zeros((32, 128), np.uint8)
     stripes[:, ::2] = 1
-    t = M.Tile(M.tile_blocks(stripes), 4)
-    queue, overflow = t.wave_pairs(1)  # rows 1, 5, 9, 13: 4 x 64 unions
+    t = M.Tile(M.tile_blocks(stripes), 4, layout="interleaved")
+    queue, early, overflow = t.wave_pairs(1)  # rows 1, 5, 9, 13: 4 x 64 unions
     assert len(queue) == 192 and sum(len(v) for v in overflow.values()) > 0
+    # eight rows per wave: rows 9 .. 15 (7 x 64 unions) are listed before the
+    # barrier, so the queue overflows there already
+    tall = np.zeros((64, 128), np.uint8)
+    tall[:, ::2] = 1
+    t = M.Tile(M.tile_blocks(tall), 4)
+    queue, early, overflow = t.wave_pairs(1)
+    assert len(queue) == 192 and sum(len(v) for v in early.values()) > 0
+    bits = M.tile_blocks(tall)
+    for s in range(2):
+        assert np.array_equal(M.simulate(bits, 4, seed=s), M.reference_roots(bits))
