@@ -518,77 +518,6 @@ __device__ int g_unite(VLG_GLOBAL int *L, int a, int b, int cap, bool &ok) {
     }
 }
 
-// Up to N unions of one lane walked in lockstep: every round issues the
-// parent loads of all unfinished unions together, then their grandparent
-// loads, so their global-memory latencies overlap instead of adding up
-// (each union is g_unite's: path halving on both ends, then a
-// compare-and-swap hook by priority that re-walks from the new parent when
-// it loses).  The order of a lane's unions does not matter: a union-find
-// reaches the same partition in any order.  `tries` counts hook attempts;
-// ok is cleared when the lane's rounds reach `cap` before all are done.
-template <int N>
-__device__ __forceinline__ void g_unite_n(VLG_GLOBAL int *L, int (&a)[N], int (&b)[N], int cap, int &tries,
-                                          bool &ok) {
-    bool on[N];
-#pragma unroll
-    for (int k = 0; k < N; k++) on[k] = a[k] >= 0;
-    for (int round = 0;; round++) {
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < N; k++) any |= on[k];
-        if (!any) return;
-        if (round >= cap) {
-            ok = false;
-            return;
-        }
-        int pa[N], pb[N], ga[N], gb[N];
-#pragma unroll
-        for (int k = 0; k < N; k++) {
-            pa[k] = on[k] ? L[a[k]] : 0;
-            pb[k] = on[k] ? L[b[k]] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < N; k++) {
-            ga[k] = on[k] && pa[k] != a[k] ? L[pa[k]] : pa[k];
-            gb[k] = on[k] && pb[k] != b[k] ? L[pb[k]] : pb[k];
-        }
-#pragma unroll
-        for (int k = 0; k < N; k++) {
-            if (!on[k]) continue;
-            if (pa[k] == a[k] && pb[k] == b[k]) {  // both roots
-                if (a[k] == b[k]) {
-                    on[k] = false;
-                    continue;
-                }
-                int hi = a[k], lo = b[k];
-                if (uf_prio(hi) < uf_prio(lo)) {
-                    hi = b[k];
-                    lo = a[k];
-                }
-                int old = hi;  // hook hi (larger priority) under lo if hi is still a root
-                tries++;
-                __hip_atomic_compare_exchange_strong(&L[hi], &old, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                if (old == hi) {
-                    on[k] = false;
-                } else {
-                    a[k] = old;
-                    b[k] = lo;
-                }
-                continue;
-            }
-            if (pa[k] != a[k]) {
-                if (ga[k] != pa[k]) L[a[k]] = ga[k];  // path halving
-                a[k] = ga[k];
-            }
-            if (pb[k] != b[k]) {
-                if (gb[k] != pb[k]) L[b[k]] = gb[k];
-                b[k] = gb[k];
-            }
-        }
-    }
-}
-
 __device__ __forceinline__ uint32_t block_bits_g(const Geo &g, const MRef &b, int by, int bx) {
     const int w = bx >> 5, sh = (bx & 31) * 2, y0 = 2 * by;
     const uint64_t keep = w == g.wpr - 1 ? g.tail : ~0ull;
@@ -900,105 +829,89 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
         const int r = 2 * by - r0, p = 2 * bx - 64 * w0, q = p >> 6, sh = p & 63;
         return (uint32_t)((win[r * 4 + q] >> sh) & 3) | ((uint32_t)((win[(r + 1) * 4 + q] >> sh) & 3) << 2);
     };
-    // this lane's unions: ua[k] with ub[k] (-1: none); 0..2 on the top row,
-    // 3..4 on its side column
-    int ua[5] = {-1, -1, -1, -1, -1}, ub[5] = {-1, -1, -1, -1, -1};
+    bool ok = true;  // no walk of this lane hit the loop cap
+    auto link = [&](int id, int nid) {
+        unions++;
+        tries += g_unite(glab, id, nid, gd.cap, ok);
+    };
+
     // top row: contacts with the row above (other tile): UL, U, UR
-    int tc[3] = {-1, -1, -1}, tp[3] = {-1, -1, -1}, tid_ = -1;
     if (by0 > 0 && by0 < g.BH) {
         const int by = by0, bx = bx0 + lane, id = by * g.BW + bx;
         const uint32_t bb = bx < g.BW ? bits(by, bx) : 0u;
-        tid_ = id;
+        int c[3] = {-1, -1, -1}, p[3] = {-1, -1, -1};
         if (bb) {
-            if (bx > 0 && (bb & 1) && (bits(by - 1, bx - 1) & 8)) tc[0] = id - g.BW - 1;
-            if ((bb & 3) && (bits(by - 1, bx) & 12)) tc[1] = id - g.BW;
-            if (bx + 1 < g.BW && (bb & 2) && (bits(by - 1, bx + 1) & 4)) tc[2] = id - g.BW + 1;
+            if (bx > 0 && (bb & 1) && (bits(by - 1, bx - 1) & 8)) c[0] = id - g.BW - 1;
+            if ((bb & 3) && (bits(by - 1, bx) & 12)) c[1] = id - g.BW;
+            if (bx + 1 < g.BW && (bb & 2) && (bits(by - 1, bx + 1) & 4)) c[2] = id - g.BW + 1;
             // predecessor on this border row: the left block, if connected
             if (lane > 0) {
                 const uint32_t lb = bits(by, bx - 1);
                 if ((bb & 5) && (lb & 10)) {
-                    if (bx - 1 > 0 && (lb & 1) && (bits(by - 1, bx - 2) & 8)) tp[0] = id - g.BW - 2;
-                    if ((lb & 3) && (bits(by - 1, bx - 1) & 12)) tp[1] = id - g.BW - 1;
-                    if ((lb & 2) && (bits(by - 1, bx) & 4)) tp[2] = id - g.BW;
+                    if (bx - 1 > 0 && (lb & 1) && (bits(by - 1, bx - 2) & 8)) p[0] = id - g.BW - 2;
+                    if ((lb & 3) && (bits(by - 1, bx - 1) & 12)) p[1] = id - g.BW - 1;
+                    if ((lb & 2) && (bits(by - 1, bx) & 4)) p[2] = id - g.BW;
                 }
             }
+        }
+        int pl[3], lc[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            pl[j] = p[j] >= 0 ? glab[p[j]] : -2;
+            lc[j] = c[j] >= 0 ? glab[c[j]] : -4;
+        }
+        const int my = bb ? glab[id] : -1;  // loaded with the others: the unions start from the labels
+        int done[2] = {-3, -3};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            if (c[j] < 0) continue;
+            if (lc[j] == pl[0] || lc[j] == pl[1] || lc[j] == pl[2] || lc[j] == done[0] || lc[j] == done[1]) continue;
+            done[j < 2 ? j : 1] = lc[j];
+            link(my, lc[j]);
         }
     }
     // side columns: lanes 0..TBH-1 the left column, lanes 32..32+TBH-1 the right
     const int lby = lane & 31, side = lane >> 5;
-    const int sby = by0 + lby;
-    int sc[2] = {-1, -1}, sp[2] = {-1, -1}, sid = -1;
-    if (lby < TBH && sby < g.BH) {
+    const int by = by0 + lby;
+    if (lby < TBH && by < g.BH) {
         if (side == 0 && bx0 > 0 && bx0 < g.BW) {
             // contacts in the column to the left (other tile): L, and UL below the top row
-            const int bx = bx0, id = sby * g.BW + bx;
-            const uint32_t bb = bits(sby, bx);
-            sid = id;
+            const int bx = bx0, id = by * g.BW + bx;
+            const uint32_t bb = bits(by, bx);
+            int c[2] = {-1, -1}, p[2] = {-1, -1};
             if (bb) {
-                if ((bb & 5) && (bits(sby, bx - 1) & 10)) sc[0] = id - 1;
-                if (lby > 0 && (bb & 1) && (bits(sby - 1, bx - 1) & 8)) sc[1] = id - g.BW - 1;
+                if ((bb & 5) && (bits(by, bx - 1) & 10)) c[0] = id - 1;
+                if (lby > 0 && (bb & 1) && (bits(by - 1, bx - 1) & 8)) c[1] = id - g.BW - 1;
                 // predecessor on this border column: the upper block, if connected
                 if (lby > 0) {
-                    const uint32_t ub_ = bits(sby - 1, bx);
-                    if ((bb & 3) && (ub_ & 12)) {
-                        if ((ub_ & 5) && (bits(sby - 1, bx - 1) & 10)) sp[0] = id - g.BW - 1;
-                        if (lby > 1 && (ub_ & 1) && (bits(sby - 2, bx - 1) & 8)) sp[1] = id - 2 * g.BW - 1;
+                    const uint32_t ub = bits(by - 1, bx);
+                    if ((bb & 3) && (ub & 12)) {
+                        if ((ub & 5) && (bits(by - 1, bx - 1) & 10)) p[0] = id - g.BW - 1;
+                        if (lby > 1 && (ub & 1) && (bits(by - 2, bx - 1) & 8)) p[1] = id - 2 * g.BW - 1;
                     }
                 }
             }
+            const int pl0 = p[0] >= 0 ? glab[p[0]] : -2, pl1 = p[1] >= 0 ? glab[p[1]] : -2;
+            const int lc0 = c[0] >= 0 ? glab[c[0]] : -4, lc1 = c[1] >= 0 ? glab[c[1]] : -4;
+            const int my = bb ? glab[id] : -1;
+            int first = -3;
+            if (c[0] >= 0 && lc0 != pl0 && lc0 != pl1) {
+                first = lc0;
+                link(my, lc0);
+            }
+            if (c[1] >= 0 && lc1 != pl0 && lc1 != pl1 && lc1 != first) link(my, lc1);
         } else if (side == 1 && lby > 0 && bx0 + TBW < g.BW) {
             // contact UR (tile to the right); redundant when the upper block is
             // connected to this block and to that same block (its right neighbour)
-            const int bx = bx0 + TBW - 1, id = sby * g.BW + bx;
-            const uint32_t bb = bits(sby, bx);
-            if ((bb & 2) && (bits(sby - 1, bx + 1) & 4)) {
-                const uint32_t ub_ = bits(sby - 1, bx), ur = bits(sby - 1, bx + 1);
-                const bool covered = (bb & 3) && (ub_ & 12) && (ur & 5) && (ub_ & 10);
-                if (!covered) {
-                    ua[3] = id;
-                    ub[3] = id - g.BW + 1;
-                }
+            const int bx = bx0 + TBW - 1, id = by * g.BW + bx;
+            const uint32_t bb = bits(by, bx);
+            if ((bb & 2) && (bits(by - 1, bx + 1) & 4)) {
+                const uint32_t ub = bits(by - 1, bx), ur = bits(by - 1, bx + 1);
+                const bool covered = (bb & 3) && (ub & 12) && (ur & 5) && (ub & 10);
+                if (!covered) link(id, id - g.BW + 1);
             }
         }
     }
-    // the labels of the candidates and predecessors, all loads together
-    int tpl[3], tlc[3], spl[2], slc[2];
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-        tpl[j] = tp[j] >= 0 ? glab[tp[j]] : -2;
-        tlc[j] = tc[j] >= 0 ? glab[tc[j]] : -4;
-    }
-#pragma unroll
-    for (int j = 0; j < 2; j++) {
-        spl[j] = sp[j] >= 0 ? glab[sp[j]] : -2;
-        slc[j] = sc[j] >= 0 ? glab[sc[j]] : -4;
-    }
-    // a candidate whose label the predecessor's candidates (or an earlier
-    // candidate) already carry is united through them
-    {
-        int done[2] = {-3, -3};
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            if (tc[j] < 0) continue;
-            if (tlc[j] == tpl[0] || tlc[j] == tpl[1] || tlc[j] == tpl[2] || tlc[j] == done[0] || tlc[j] == done[1])
-                continue;
-            done[j < 2 ? j : 1] = tlc[j];
-            ua[j] = tid_;
-            ub[j] = tc[j];
-        }
-    }
-    if (sc[0] >= 0 && slc[0] != spl[0] && slc[0] != spl[1]) {
-        ua[3] = sid;
-        ub[3] = sc[0];
-    }
-    if (sc[1] >= 0 && slc[1] != spl[0] && slc[1] != spl[1] && !(ua[3] == sid && slc[1] == slc[0])) {
-        ua[4] = sid;
-        ub[4] = sc[1];
-    }
-    bool ok = true;  // no walk of this lane hit the loop cap
-#pragma unroll
-    for (int k = 0; k < 5; k++) unions += ua[k] >= 0 ? 1 : 0;
-    g_unite_n<5>(glab, ua, ub, gd.cap, tries, ok);
     guard_report(gd, ok);
     wave_lds_handoff();  // the window is rewritten by the wave's next tile
 }
