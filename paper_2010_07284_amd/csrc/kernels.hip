@@ -60,6 +60,17 @@ __device__ __forceinline__ bool is_last_col(const Geo &g, int64_t i) {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup i to XCD
+// i mod 8), and each XCD has an L2 of its own.  The work item of workgroup b
+// of n: each XCD takes a contiguous range of items, so that neighbouring
+// tiles, which share the cache lines of their mask words, meet in one L2
+// instead of each line being fetched by several.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+    constexpr int X = 8;
+    const int per = n / X, rem = n % X, x = b % X, k = b / X;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 int grid_for(int64_t n, int per_block, int cap) {
     int64_t b = (n + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -787,8 +798,10 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     __syncthreads();  // the next tile of a persistent workgroup reuses the LDS
 }
 
-// Cross-tile merge, one wave per tile: blocks on the tile's top row, left
-// column and right column unite with their earlier neighbours in other tiles.
+// Cross-tile merge, two waves per tile (part 0 the top row, part 1 the side
+// columns, so that the two chains of dependent global accesses run side by
+// side): blocks on the tile's top row, left column and right column unite
+// with their earlier neighbours in other tiles.
 // A block skips a union that its connected predecessor along the same border
 // (left neighbour on the top row, upper neighbour on a side column) already
 // makes with the same tile-local component.
@@ -804,8 +817,8 @@ constexpr int merge_window_words() {
 }
 
 template <int TBH>
-__device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, int32_t *glab_, uint64_t *win,
-                               int &unions, int &tries, const LoopGuard &gd) {
+__device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, int part, int32_t *glab_,
+                               uint64_t *win, int &unions, int &tries, const LoopGuard &gd) {
     constexpr int TBW = 64, WN = merge_window_words<TBH>(), NL = (WN + 63) / 64;
     VLG_GLOBAL int32_t *glab = glb(glab_);
     const int lane = lane_id();
@@ -841,7 +854,7 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
     };
 
     // top row: contacts with the row above (other tile): UL, U, UR
-    if (by0 > 0 && by0 < g.BH) {
+    if (part == 0 && by0 > 0 && by0 < g.BH) {
         const int by = by0, bx = bx0 + lane, id = by * g.BW + bx;
         const uint32_t bb = bx < g.BW ? bits(by, bx) : 0u;
         int c[3] = {-1, -1, -1}, p[3] = {-1, -1, -1};
@@ -878,7 +891,7 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
     // side columns: lanes 0..TBH-1 the left column, lanes 32..32+TBH-1 the right
     const int lby = lane & 31, side = lane >> 5;
     const int by = by0 + lby;
-    if (lby < TBH && by < g.BH) {
+    if (part == 1 && lby < TBH && by < g.BH) {
         if (side == 0 && bx0 > 0 && bx0 < g.BW) {
             // contacts in the column to the left (other tile): L, and UL below the top row
             const int bx = bx0, id = by * g.BW + bx;
@@ -1153,16 +1166,18 @@ template <int TBH>
 __global__ __launch_bounds__(ccl_local_threads<TBH>()) void k_ccl_local(Geo g, MRef b, MRef y, MRef z, int ntx,
                                                         int32_t *__restrict__ glab,
                                                         uint8_t *__restrict__ gflag, LoopGuard gd) {
-    ccl_local_tile<TBH>(g, b, y, z, blockIdx.x % ntx, blockIdx.x / ntx, glab, gflag, gd);
+    const int tile = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    ccl_local_tile<TBH>(g, b, y, z, tile % ntx, tile / ntx, glab, gflag, gd);
 }
 
 template <int TBH>
 __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, int ntiles, int32_t *glab,
                                                         unsigned long long *counters, LoopGuard gd) {
     __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
-    const int wv = threadIdx.x >> 6, tile = blockIdx.x * (kThreads / 64) + wv;
+    const int wv = threadIdx.x >> 6;
+    const int w = xcd_contiguous((int)blockIdx.x, (int)gridDim.x) * (kThreads / 64) + wv, tile = w >> 1;
     int unions = 0, tries = 0;
-    if (tile < ntiles) ccl_merge_tile<TBH>(g, b, ntx, tile, glab, win[wv], unions, tries, gd);
+    if (tile < ntiles) ccl_merge_tile<TBH>(g, b, ntx, tile, w & 1, glab, win[wv], unions, tries, gd);
     if (counters && (unions | tries)) {
         atomicAdd(&counters[0], (unsigned long long)unions);
         atomicAdd(&counters[1], (unsigned long long)(tries - unions));
@@ -1200,8 +1215,8 @@ __global__ __launch_bounds__(kThreads) void k_ccl_reseed(Geo g, MRef sm, const i
 template <int TBH>
 __global__ __launch_bounds__(ccl_local_threads<TBH>()) void k_ccl_local_multi(Geo g, CclMulti m, int ntx,
                                                                               LoopGuard gd) {
-    const int l = (int)blockIdx.y;
-    ccl_local_tile<TBH>(g, m.b[l], m.y[l], m.z[l], blockIdx.x % ntx, blockIdx.x / ntx, m.glab[l], m.gflag[l], gd);
+    const int l = (int)blockIdx.y, tile = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    ccl_local_tile<TBH>(g, m.b[l], m.y[l], m.z[l], tile % ntx, tile / ntx, m.glab[l], m.gflag[l], gd);
 }
 
 template <int TBH>
@@ -1209,9 +1224,10 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge_multi(Geo g, CclMulti m,
                                                               unsigned long long *counters, LoopGuard gd) {
     __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
     const int l = (int)blockIdx.y;
-    const int wv = threadIdx.x >> 6, tile = blockIdx.x * (kThreads / 64) + wv;
+    const int wv = threadIdx.x >> 6;
+    const int w = xcd_contiguous((int)blockIdx.x, (int)gridDim.x) * (kThreads / 64) + wv, tile = w >> 1;
     int unions = 0, tries = 0;
-    if (tile < ntiles) ccl_merge_tile<TBH>(g, m.b[l], ntx, tile, m.glab[l], win[wv], unions, tries, gd);
+    if (tile < ntiles) ccl_merge_tile<TBH>(g, m.b[l], ntx, tile, w & 1, m.glab[l], win[wv], unions, tries, gd);
     if (counters && (unions | tries)) {
         atomicAdd(&counters[0], (unsigned long long)unions);
         atomicAdd(&counters[1], (unsigned long long)(tries - unions));
@@ -1398,10 +1414,10 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW, nty = (d.g.BH + TBH - 1) / TBH;
-        const int tile = (int)(u_ - a.prefix[ii]) * (kThreads / 64) + wv;
+        const int w = (int)(u_ - a.prefix[ii]) * (kThreads / 64) + wv, tile = w >> 1;
         if (tile < ntx * nty)
-            ccl_merge_tile<TBH>(d.g, bref(d, b), ntx, tile, (int32_t *)(d.ws + d.off_glab), win[wv], unions, tries,
-                                a.guard);
+            ccl_merge_tile<TBH>(d.g, bref(d, b), ntx, tile, w & 1, (int32_t *)(d.ws + d.off_glab), win[wv], unions,
+                                tries, a.guard);
     }
 }
 
@@ -1686,7 +1702,7 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
     if (g.nwords == 0) return hipSuccess;
     if (!valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
     const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh), ntiles = ntx * nty;
-    const int grid = (ntiles + kThreads / 64 - 1) / (kThreads / 64);  // one wave per tile
+    const int grid = (2 * ntiles + kThreads / 64 - 1) / (kThreads / 64);  // two waves per tile
     switch (w.tbh) {
     case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters, w.guard); break;
     case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters, w.guard); break;
@@ -1735,7 +1751,7 @@ hipError_t launch_ccl_merge_multi(hipStream_t s, const Geo &g, const CclMulti &m
     if (g.nwords == 0 || m.n == 0) return hipSuccess;
     if (m.n < 0 || m.n > kMaxMulti || !valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
     const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh), ntiles = ntx * nty;
-    const dim3 grid((unsigned)((ntiles + kThreads / 64 - 1) / (kThreads / 64)), (unsigned)m.n);
+    const dim3 grid((unsigned)((2 * ntiles + kThreads / 64 - 1) / (kThreads / 64)), (unsigned)m.n);
     switch (w.tbh) {
     case 8: k_ccl_merge_multi<8><<<grid, kThreads, 0, s>>>(g, m, ntx, ntiles, w.counters, w.guard); break;
     case 16: k_ccl_merge_multi<16><<<grid, kThreads, 0, s>>>(g, m, ntx, ntiles, w.counters, w.guard); break;
@@ -1891,7 +1907,7 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     case BK_LOGIC: return (g.nwords + kThreads * kLogicUnroll - 1) / (kThreads * kLogicUnroll);
     case BK_NEAR: return (near_tasks(g, kBatchNearRows) + kThreads / 64 - 1) / (kThreads / 64);
     case BK_TILES: return ntiles;
-    case BK_MERGE: return (ntiles + kThreads / 64 - 1) / (kThreads / 64);
+    case BK_MERGE: return (2 * ntiles + kThreads / 64 - 1) / (kThreads / 64);  // two waves per tile
     case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
     case BK_FLAG: return (nb + 16 * kThreads - 1) / (16 * kThreads);
     case BK_GATHER: {
