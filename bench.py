@@ -262,6 +262,15 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512, square=False):
         torch.cuda.synchronize()
         ms[mode] = (time.perf_counter() - t0) * 1e3 / steps
         log(f"[bench] batch {mode}: {ms[mode]:.3f} ms per batch")
+    # per-kind rates of the batched kernels: HIP events around every launch
+    # of the batched schedule (fused, no graph)
+    kb = {}
+    for k, (nl, t, b) in vlg.profile_batch(ctx, f, ims, iters=2).items():
+        kb[k] = {"launches_per_batch": nl // 2, "avg_launch_us": round(t / nl * 1e3, 2),
+                 "ms_per_batch": round(t / 2, 3),
+                 "achieved_gbs": round(b / (t / 1e3) / 1e9, 1) if t > 0 else None,
+                 "frac": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if t > 0 else None}
+    log(f"[bench] batch kernels: {kb}")
     px = sum(h * w for h, w in sizes)
     res = {"workload": f"uneven_batch_{n}{'_square' if square else ''}: {n} phantom images, "
                        f"{'square sides' if square else 'sides H, W'} U[128,2048], f32 x4 channels, "
@@ -271,7 +280,8 @@ def bench_batch(vlg, lib, steps, check_oracle, seed=4, n=512, square=False):
            "perop_ms": round(ms["perop"], 3), "fused_ms": round(ms["fused"], 3), "graph_ms": round(ms["graph"], 3),
            "speedup_graph_vs_perop": round(ms["perop"] / ms["graph"], 3),
            "gpixel_node_per_s": round(px * nodes / (ms["graph"] / 1e3) / 1e9, 3),
-           "images_per_s": round(n / (ms["graph"] / 1e3), 1), "cpu_baseline_all_cores": cpu}
+           "images_per_s": round(n / (ms["graph"] / 1e3), 1), "cpu_baseline_all_cores": cpu,
+           "kernels_with_per_launch_events": kb}
     del outs, ims
     torch.cuda.empty_cache()
     return res
@@ -303,6 +313,18 @@ def bench_pixelwise(vlg, iters, side=46080):
         res[k] = {"avg_launch_us": round(ms / n * 1e3, 2), "bytes_per_launch": round(b / n),
                   "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"[bench] pixelwise {k:8s} {ms / n * 1e3:9.1f} us/launch  {gbs:7.1f} GB/s  "
+            f"({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+    # each kernel launched back to back (the step alone, repeated): without
+    # the write-back of the previous kernel's output inside its time
+    for k in ("atoms", "near", "logic"):
+        try:
+            bb_ms, bb = vlg.profile_step(ctx, f, im, k, reps=iters)
+        except vlg.VlgError:
+            continue
+        gbs = bb / (bb_ms / 1e3) / 1e9
+        res[k]["back_to_back"] = {"avg_launch_us": round(bb_ms * 1e3, 1), "achieved_gbs": round(gbs, 1),
+                                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"[bench] pixelwise {k:8s} back to back {bb_ms * 1e3:9.1f} us/launch  {gbs:7.1f} GB/s  "
             f"({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
     # the whole pass (atom, N, connective): a launch that streams past the
     # last-level cache leaves the write-back of its output to the next one,

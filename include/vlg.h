@@ -306,6 +306,14 @@ typedef struct vlg_kernel_time {
 } vlg_kernel_time;
 int vlg_profile(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *img, int iters, vlg_kernel_time *out,
                 int max_out, int *n_out);
+/* The same per-kind table for the batched executor (vlg_check_batch in
+ * fused mode, no graph): HIP events around every launch of the batched
+ * schedule of every output of f on the n images (one pixel type, no
+ * volumes), `iters` times; bytes are the steps' algorithmic bytes summed over
+ * the images.  Outputs go to the library's own mask slots.  Synchronises the
+ * stream. */
+int vlg_profile_batch(vlg_ctx *ctx, const vlg_formula *f, const vlg_image *const *imgs, int n, int iters,
+                      vlg_kernel_time *out, int max_out, int *n_out);
 /* Measurement of one kernel without per-launch events: enqueues the fused
  * schedule (one labelling at a time) of every output of f on img up to and
  * including its first single (ungrouped) step of `kind` ("atoms", "logic",

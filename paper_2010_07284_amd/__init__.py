@@ -321,6 +321,16 @@ def profile(ctx, f, img, iters=5):
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
 
 
+def profile_batch(ctx, f, imgs, iters=3):
+    """vlg_profile_batch: per kernel kind {name: (launches, ms_total,
+    algorithmic_bytes)} of the batched schedule over the images."""
+    arr = (_lib.KernelTime * 16)()
+    n = ctypes.c_int()
+    harr = (ctypes.c_void_p * len(imgs))(*[im.handle.value for im in imgs])
+    _lib.call("vlg_profile_batch", ctx.handle, f.handle, harr, len(imgs), iters, arr, 16, ctypes.byref(n))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(n.value)}
+
+
 TUNABLES = {"ccl_tile_rows": 0, "near_band_rows": 1, "batch_grid": 2, "ccl_lanes": 3, "fuse_halo": 4,
             "ccl_algo": 5, "pj_reconnect": 6, "arith_kernel": 7}
 CCL_UNION_FIND, CCL_POINTER_JUMPING = 1, 2
@@ -442,6 +452,6 @@ def pack(mask):
 
 
 __all__ = ["create", "sync", "set_loop_cap", "set_mode", "load_image", "compile_formula", "formula_info", "formula_plan", "output_names",
-           "check", "check_all", "check_batch", "ccl_labels", "ccl_labels_noalloc", "ccl_labels_pj", "ccl_labels3", "load_volume", "ccl_counters", "profile", "profile_step", "stream_copy", "set_tunable", "get_tunable", "autotune", "tune_save",
+           "check", "check_all", "check_batch", "ccl_labels", "ccl_labels_noalloc", "ccl_labels_pj", "ccl_labels3", "load_volume", "ccl_counters", "profile", "profile_batch", "profile_step", "stream_copy", "set_tunable", "get_tunable", "autotune", "tune_save",
            "tune_load", "autotune_batch", "Server", "evaluation_bytes", "unpack", "pack", "VlgError",
            "LIB_PATH"]

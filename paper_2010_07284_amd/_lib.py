@@ -11,7 +11,7 @@ EXPORTS = [
     "vlg_image_shape", "vlg_compile_formula", "vlg_formula_info", "vlg_formula_output_name", "vlg_formula_plan",
     "vlg_formula_free", "vlg_check", "vlg_check_all", "vlg_check_batch", "vlg_ccl_labels", "vlg_ccl_labels_noalloc", "vlg_ccl_labels_pj",
     "vlg_load_volume", "vlg_image_shape3", "vlg_ccl_labels3", "vlg_profile_step", "vlg_stream_copy",
-    "vlg_ccl_read_counters", "vlg_profile", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune", "vlg_autotune_batch",
+    "vlg_ccl_read_counters", "vlg_profile", "vlg_profile_batch", "vlg_set_tunable", "vlg_get_tunable", "vlg_autotune", "vlg_autotune_batch",
     "vlg_tune_save", "vlg_tune_load", "vlg_server_create", "vlg_server_submit", "vlg_server_wait",
     "vlg_server_read_stats", "vlg_server_destroy", "vlg_evaluation_bytes", "vlg_last_error",
 ]
@@ -98,6 +98,7 @@ def lib():
             "vlg_stream_copy": ([P, P, P, I64, I, I, P], I),
             "vlg_ccl_read_counters": ([P, P], I),
             "vlg_profile": ([P, P, P, I, P, I, P], I),
+            "vlg_profile_batch": ([P, P, P, I, I, P, I, P], I),
             "vlg_set_tunable": ([P, I, I], I),
             "vlg_get_tunable": ([P, I, I, I, P], I),
             "vlg_autotune": ([P, P, P, I, P, I, P], I),

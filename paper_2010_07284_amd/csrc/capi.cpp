@@ -908,8 +908,13 @@ int run(vlg_ctx *c, vlg_formula *f, const vlg_image *img, const std::vector<int>
 // labelling arrays, percentile state) and a descriptor; the batch kernels
 // walk the concatenated units of all images.  Descriptors, output tables,
 // percentile ranks and unit prefix sums are uploaded before the steps run.
+// hook (optional): called around every launch of a step or group (before:
+// its first step, after: its last), for per-step timing; no graph is
+// captured then.  bytes (optional): receives each step's algorithmic bytes
+// summed over the images.
 int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const std::vector<int> &idx,
-              void *const *outs, int fmt, int where) {
+              void *const *outs, int fmt, int where, StepHook hook = nullptr, void *hook_ctx = nullptr,
+              std::vector<double> *bytes = nullptr) {
     const size_t nout = f->dag.outputs.size();
     std::vector<int> all(nout);
     for (size_t i = 0; i < nout; i++) all[i] = (int)i;
@@ -1039,13 +1044,28 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
         return e;
     };
 
+    if (bytes) {
+        bytes->assign(P.steps.size(), 0.0);
+        for (size_t si = 0; si < P.steps.size(); si++)
+            for (int k = 0; k < n; k++) (*bytes)[si] += algorithmic_bytes(P, P.steps[si], geo[k], dtype, tbh);
+    }
     auto enqueue_steps = [&]() -> int {
         for (size_t si = 0; si < P.steps.size(); si++) {
             const Step &s = P.steps[si];
             hipError_t e = hipSuccess;
+            if (hook) hook(hook_ctx, si, true);
             if (s.group >= 0) {
                 size_t sj = si;
                 while (sj + 1 < P.steps.size() && P.steps[sj + 1].group == s.group) sj++;
+                if (hook && sj > si) {
+                    // the group is timed as a whole: attribute it to its last step
+                    hook(hook_ctx, si, false);
+                    for (size_t k = si + 1; k < sj; k++) {
+                        hook(hook_ctx, k, true);
+                        hook(hook_ctx, k, false);
+                    }
+                    hook(hook_ctx, sj, true);
+                }
                 if (s.kind == SK::Arith) {
                     e = arith_images(si, sj);
                 } else if (s.kind == SK::Logic) {
@@ -1068,6 +1088,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                     e = launch_b_near(c->stream, args(BK_NEAR), units(BK_NEAR), b);
                 }
                 if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+                if (hook) hook(hook_ctx, sj, false);
                 si = sj;
                 continue;
             }
@@ -1136,6 +1157,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
                 break;
             }
             if (e != hipSuccess) return fail(VLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+            if (hook) hook(hook_ctx, si, false);
         }
         if (fmt == VLG_U8MASK) {
             for (int k = 0; k < n; k++)
@@ -1159,7 +1181,7 @@ int run_batch(vlg_ctx *c, vlg_formula *f, const vlg_image *const *imgs, const st
             im->dtype != imgs[idx[k - 1]]->dtype)
             prepare_arith(c, P, im->H, im->W, im->dtype);
     }
-    if (c->mode == VLG_MODE_GRAPH) {
+    if (c->mode == VLG_MODE_GRAPH && !hook) {
         GraphKey key;
         key.v = {(uintptr_t)0xBA7C, (uintptr_t)f->serial, (uintptr_t)&P, (uintptr_t)c->ws, (uintptr_t)tbh,
                  (uintptr_t)grid_cap, (uintptr_t)fmt, (uintptr_t)where, (uintptr_t)n, (uintptr_t)c->loop_cap};
@@ -1859,6 +1881,80 @@ int vlg_profile(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, int ite
     for (size_t i = 0; i < kinds.size() && (int)i < max_out; i++) out[i] = kinds[i];
     *n_out = (int)kinds.size();
     return VLG_OK;
+}
+
+int vlg_profile_batch(vlg_ctx *c, const vlg_formula *cf, const vlg_image *const *imgs, int n, int iters,
+                      vlg_kernel_time *out, int max_out, int *n_out) {
+    if (!c || !cf || !imgs || n < 1 || !out || !n_out || iters < 1) return fail(VLG_EINVAL, "bad argument");
+    vlg_formula *f = const_cast<vlg_formula *>(cf);
+    const int dtype = imgs[0] ? imgs[0]->dtype : 0;
+    for (int i = 0; i < n; i++) {
+        if (!imgs[i]) return fail(VLG_EINVAL, "null image in batch");
+        if (imgs[i]->D > 1) return fail(VLG_EINVAL, "volumes are not batched");
+        if (f->max_chan >= imgs[i]->C) return fail(VLG_ESHAPE, "formula uses a channel an image lacks");
+        if (imgs[i]->dtype != dtype) return fail(VLG_EINVAL, "batch profiling needs one pixel type");
+        if (imgs[i]->device != c->device) return fail(VLG_EINVAL, "image lives on another device");
+    }
+    DeviceGuard dg(c->device);
+    *n_out = 0;
+    const size_t nout = f->dag.outputs.size();
+    std::vector<int> all(nout), idx((size_t)n);
+    for (size_t i = 0; i < nout; i++) all[i] = (int)i;
+    for (int i = 0; i < n; i++) idx[(size_t)i] = i;
+    const Plan &P = f->plan(all, Mode::Fused);
+    if (P.steps.empty()) return VLG_OK;
+    std::vector<void *> outs((size_t)n * nout, nullptr);
+    std::vector<hipEvent_t> ev(2 * P.steps.size(), nullptr);
+    int rc = VLG_OK;
+    for (auto &e : ev)
+        if (rc == VLG_OK && hipEventCreate(&e) != hipSuccess) rc = fail(VLG_EHIP, "event create");
+    struct Tr {
+        std::vector<hipEvent_t> *ev;
+        hipStream_t s;
+    } tr{&ev, c->stream};
+    auto hook = [](void *p, size_t si, bool before) {
+        Tr *t = (Tr *)p;
+        (void)hipEventRecord((*t->ev)[2 * si + (before ? 0 : 1)], t->s);
+    };
+    std::vector<double> ms(P.steps.size(), 0.0), bytes;
+    for (int it = 0; it < iters && rc == VLG_OK; it++) {
+        rc = run_batch(c, f, imgs, idx, outs.data(), VLG_PACKED64, VLG_DEVICE, hook, &tr, &bytes);
+        if (rc != VLG_OK) break;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            rc = fail(VLG_EHIP, "synchronize failed");
+            break;
+        }
+        for (size_t si = 0; si < P.steps.size(); si++) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[2 * si], ev[2 * si + 1]) == hipSuccess) ms[si] += t;
+        }
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != VLG_OK) return rc;
+    std::vector<vlg_kernel_time> kinds;
+    for (size_t si = 0; si < P.steps.size(); si++) {
+        const char *nm = kind_name(P.steps[si].kind);
+        auto it = std::find_if(kinds.begin(), kinds.end(),
+                               [&](const vlg_kernel_time &k) { return std::strcmp(k.name, nm) == 0; });
+        if (it == kinds.end()) {
+            vlg_kernel_time k;
+            std::memset(&k, 0, sizeof k);
+            std::snprintf(k.name, sizeof k.name, "%s", nm);
+            kinds.push_back(k);
+            it = kinds.end() - 1;
+        }
+        // a batched group is one launch, timed as a whole on its last step
+        const bool grouped_not_last = P.steps[si].group >= 0 && si + 1 < P.steps.size() &&
+                                      P.steps[si + 1].group == P.steps[si].group;
+        if (!grouped_not_last) it->launches += iters;
+        it->ms += ms[si];
+        it->bytes += iters * (si < bytes.size() ? bytes[si] : 0.0);
+    }
+    std::sort(kinds.begin(), kinds.end(), [](const vlg_kernel_time &a, const vlg_kernel_time &b) { return a.ms > b.ms; });
+    for (size_t k = 0; k < kinds.size() && (int)k < max_out; k++) out[k] = kinds[k];
+    *n_out = (int)std::min(kinds.size(), (size_t)max_out);
+    return check_status(c);
 }
 
 int vlg_profile_step(vlg_ctx *c, const vlg_formula *cf, const vlg_image *img, const char *kind, int reps,

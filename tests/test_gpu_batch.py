@@ -228,3 +228,25 @@ def test_batch_grid_sizes(ctx, grid):
         vlg.set_tunable(ctx, "batch_grid", 0)
     for (h, w), img, g in zip(sizes, imgs, got):
         assert_same(src, img, g, tag=f"{h}x{w} grid={grid}")
+
+
+def test_batch_profile_counts_every_launch(ctx):
+    # vlg_profile_batch: per kind, launches of the batched schedule and their
+    # algorithmic bytes summed over the images; the batch still evaluates to
+    # the oracle's masks afterwards
+    import paper_2010_07284_amd as vlg
+    src = formulas.segmentation_dag(4)
+    sizes = [(190, 257), (64, 65), (301, 77)]
+    imgs = [images.phantom_image(np.random.default_rng([11, i]), h, w) for i, (h, w) in enumerate(sizes)]
+    vlg.set_mode(ctx, "fused")
+    f = vlg.compile_formula(ctx, src)
+    ims = [vlg.load_image(ctx, im) for im in imgs]
+    prof = vlg.profile_batch(ctx, f, ims, iters=2)
+    plan = vlg.formula_plan(f, "fused", 1)
+    assert {"atoms", "ccl_local", "ccl_merge", "ccl_gather"} <= set(prof)
+    for name, (n, ms, b) in prof.items():
+        assert n > 0 and n % 2 == 0 and ms > 0 and b >= 0, name
+    assert prof["ccl_local"][0] == 2 * sum(1 for st in plan["steps"] if st["kind"] == "ccl_local")
+    got = run_batch(ctx, src, imgs, "graph")
+    for (h, w), img, g in zip(sizes, imgs, got):
+        assert_same(src, img, g, tag=f"after profile {h}x{w}")
