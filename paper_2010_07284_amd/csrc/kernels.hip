@@ -798,12 +798,10 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
     __syncthreads();  // the next tile of a persistent workgroup reuses the LDS
 }
 
-// Cross-tile merge, four waves (one workgroup) per tile: parts 0, 1, 2 make
-// the top row's unions with its upper-left, upper and upper-right candidates,
-// part 3 those of the side columns, so that at most two unions of a lane
-// follow one another (each a chain of dependent global accesses): blocks on
-// the tile's top row, left column and right column unite with their earlier
-// neighbours in other tiles.
+// Cross-tile merge, two waves per tile (part 0 the top row, part 1 the side
+// columns, so that the two chains of dependent global accesses run side by
+// side): blocks on the tile's top row, left column and right column unite
+// with their earlier neighbours in other tiles.
 // A block skips a union that its connected predecessor along the same border
 // (left neighbour on the top row, upper neighbour on a side column) already
 // makes with the same tile-local component.
@@ -813,7 +811,6 @@ __device__ void ccl_local_tile(const Geo &g, const MRef &b, const MRef &y, const
 // any border block or its neighbours and predecessors touch), all loads in
 // flight at once.  Each lane then derives the block bits it needs from LDS and
 // loads the labels of its candidates and predecessors together before uniting.
-static_assert(kThreads == 256, "the merge gives the four waves of a workgroup the four parts of a tile");
 template <int TBH>
 constexpr int merge_window_words() {
     return (2 * TBH + 4) * 4;
@@ -833,9 +830,8 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
         int64_t idx[NL];
 #pragma unroll
         for (int k = 0; k < NL; k++) {
-            // the top-row parts need only the window's first six pixel rows
             const int i = lane + 64 * k, r = r0 + i / 4, w = w0 + (i & 3);
-            const bool ok = i < (part < 3 ? 24 : WN) && r >= 0 && r < g.H && w >= 0 && w < g.wpr;
+            const bool ok = i < WN && r >= 0 && r < g.H && w >= 0 && w < g.wpr;
             idx[k] = ok ? (int64_t)r * g.wpr + w : -1;
             v[k] = b.p ? glb(b.p)[ok ? idx[k] : 0] : 0ull;
         }
@@ -857,11 +853,8 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
         tries += g_unite(glab, id, nid, gd.cap, ok);
     };
 
-    // top row: contacts with the row above (other tile): UL, U, UR; part j
-    // makes the union with candidate j (the skip tests are the same in the
-    // three parts: a label shared with an earlier candidate or with the left
-    // neighbour's candidates is united by that one)
-    if (part < 3 && by0 > 0 && by0 < g.BH) {
+    // top row: contacts with the row above (other tile): UL, U, UR
+    if (part == 0 && by0 > 0 && by0 < g.BH) {
         const int by = by0, bx = bx0 + lane, id = by * g.BW + bx;
         const uint32_t bb = bx < g.BW ? bits(by, bx) : 0u;
         int c[3] = {-1, -1, -1}, p[3] = {-1, -1, -1};
@@ -892,13 +885,13 @@ __device__ void ccl_merge_tile(const Geo &g, const MRef &b, int ntx, int tile, i
             if (c[j] < 0) continue;
             if (lc[j] == pl[0] || lc[j] == pl[1] || lc[j] == pl[2] || lc[j] == done[0] || lc[j] == done[1]) continue;
             done[j < 2 ? j : 1] = lc[j];
-            if (j == part) link(my, lc[j]);
+            link(my, lc[j]);
         }
     }
     // side columns: lanes 0..TBH-1 the left column, lanes 32..32+TBH-1 the right
     const int lby = lane & 31, side = lane >> 5;
     const int by = by0 + lby;
-    if (part == 3 && lby < TBH && by < g.BH) {
+    if (part == 1 && lby < TBH && by < g.BH) {
         if (side == 0 && bx0 > 0 && bx0 < g.BW) {
             // contacts in the column to the left (other tile): L, and UL below the top row
             const int bx = bx0, id = by * g.BW + bx;
@@ -1182,9 +1175,9 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, 
                                                         unsigned long long *counters, LoopGuard gd) {
     __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
     const int wv = threadIdx.x >> 6;
-    const int tile = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);  // four waves per tile
+    const int w = xcd_contiguous((int)blockIdx.x, (int)gridDim.x) * (kThreads / 64) + wv, tile = w >> 1;
     int unions = 0, tries = 0;
-    if (tile < ntiles) ccl_merge_tile<TBH>(g, b, ntx, tile, wv, glab, win[wv], unions, tries, gd);
+    if (tile < ntiles) ccl_merge_tile<TBH>(g, b, ntx, tile, w & 1, glab, win[wv], unions, tries, gd);
     if (counters && (unions | tries)) {
         atomicAdd(&counters[0], (unsigned long long)unions);
         atomicAdd(&counters[1], (unsigned long long)(tries - unions));
@@ -1232,9 +1225,9 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge_multi(Geo g, CclMulti m,
     __shared__ uint64_t win[kThreads / 64][merge_window_words<TBH>()];
     const int l = (int)blockIdx.y;
     const int wv = threadIdx.x >> 6;
-    const int tile = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);  // four waves per tile
+    const int w = xcd_contiguous((int)blockIdx.x, (int)gridDim.x) * (kThreads / 64) + wv, tile = w >> 1;
     int unions = 0, tries = 0;
-    if (tile < ntiles) ccl_merge_tile<TBH>(g, m.b[l], ntx, tile, wv, m.glab[l], win[wv], unions, tries, gd);
+    if (tile < ntiles) ccl_merge_tile<TBH>(g, m.b[l], ntx, tile, w & 1, m.glab[l], win[wv], unions, tries, gd);
     if (counters && (unions | tries)) {
         atomicAdd(&counters[0], (unsigned long long)unions);
         atomicAdd(&counters[1], (unsigned long long)(tries - unions));
@@ -1421,9 +1414,9 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_merge(BatchArgs a, BRef b) {
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
         const int ntx = (d.g.BW + kTileBW - 1) / kTileBW, nty = (d.g.BH + TBH - 1) / TBH;
-        const int tile = (int)(u_ - a.prefix[ii]);  // four waves per tile
+        const int w = (int)(u_ - a.prefix[ii]) * (kThreads / 64) + wv, tile = w >> 1;
         if (tile < ntx * nty)
-            ccl_merge_tile<TBH>(d.g, bref(d, b), ntx, tile, wv, (int32_t *)(d.ws + d.off_glab), win[wv], unions,
+            ccl_merge_tile<TBH>(d.g, bref(d, b), ntx, tile, w & 1, (int32_t *)(d.ws + d.off_glab), win[wv], unions,
                                 tries, a.guard);
     }
 }
@@ -1709,7 +1702,7 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
     if (g.nwords == 0) return hipSuccess;
     if (!valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
     const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh), ntiles = ntx * nty;
-    const int grid = ntiles;  // four waves (one workgroup) per tile
+    const int grid = (2 * ntiles + kThreads / 64 - 1) / (kThreads / 64);  // two waves per tile
     switch (w.tbh) {
     case 8: k_ccl_merge<8><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters, w.guard); break;
     case 16: k_ccl_merge<16><<<grid, kThreads, 0, s>>>(g, b, ntx, ntiles, w.glab, w.counters, w.guard); break;
@@ -1758,7 +1751,7 @@ hipError_t launch_ccl_merge_multi(hipStream_t s, const Geo &g, const CclMulti &m
     if (g.nwords == 0 || m.n == 0) return hipSuccess;
     if (m.n < 0 || m.n > kMaxMulti || !valid_tile_bh(w.tbh)) return hipErrorInvalidValue;
     const int ntx = ntiles_x(g), nty = ntiles_y(g, w.tbh), ntiles = ntx * nty;
-    const dim3 grid((unsigned)ntiles, (unsigned)m.n);  // four waves (one workgroup) per tile
+    const dim3 grid((unsigned)((2 * ntiles + kThreads / 64 - 1) / (kThreads / 64)), (unsigned)m.n);
     switch (w.tbh) {
     case 8: k_ccl_merge_multi<8><<<grid, kThreads, 0, s>>>(g, m, ntx, ntiles, w.counters, w.guard); break;
     case 16: k_ccl_merge_multi<16><<<grid, kThreads, 0, s>>>(g, m, ntx, ntiles, w.counters, w.guard); break;
@@ -1914,7 +1907,7 @@ int64_t batch_units(const Geo &g, int kind, int tbh) {
     case BK_LOGIC: return (g.nwords + kThreads * kLogicUnroll - 1) / (kThreads * kLogicUnroll);
     case BK_NEAR: return (near_tasks(g, kBatchNearRows) + kThreads / 64 - 1) / (kThreads / 64);
     case BK_TILES: return ntiles;
-    case BK_MERGE: return ntiles;  // four waves (one workgroup) per tile
+    case BK_MERGE: return (2 * ntiles + kThreads / 64 - 1) / (kThreads / 64);  // two waves per tile
     case BK_BLOCKS: return (nb + kThreads - 1) / kThreads;
     case BK_FLAG: return (nb + 16 * kThreads - 1) / (16 * kThreads);
     case BK_GATHER: {
