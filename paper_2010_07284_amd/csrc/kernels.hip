@@ -23,8 +23,8 @@ namespace {
 
 constexpr int kThreads = 256;
 // channel elements per batched histogram unit: large enough that flushing a
-// workgroup's LDS histograms (2048 bins per selection, global atomics that
-// all units of an image aim at the same addresses) stays small next to the reads
+// workgroup's LDS histograms (up to 8192 bins, global atomics that all units
+// of an image aim at the same addresses) stays small next to the reads
 constexpr int64_t kPctUnit = 262144;
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t shift) {
@@ -2007,14 +2007,22 @@ hipError_t launch_b_ccl_reseed(hipStream_t s, const BatchArgs &a, int64_t total,
 // (negatives complemented, positives with the sign bit set) or the uint8
 // values.  Each pass histograms one digit of the keys that agree with the
 // digits chosen so far, then a single workgroup finds the bucket holding rank
-// k.  float32 uses digits of 11, 11 and 10 bits; uint8 one digit of 8 bits.
+// k.  float32 uses digits of 13, 10 and 9 bits (the first pass has a single
+// group, so its histogram takes the LDS of all four); uint8 one digit of 8
+// bits, uint16 two.
 namespace vlg {
 namespace {
 
+// Selections of a pass whose digits chosen so far agree share one
+// histogram: that of the first of them in the step, whose slot is `src`.
+// Passes 0 and 2 count into `a`, pass 1 into `b`, so the selection of pass 1
+// can clear `a` while others still read `b`.
 struct PctState {
-    uint32_t prefix, mask, k, pad;
-    uint32_t hist[2048];
+    uint32_t prefix, mask, k, src;
+    uint32_t a[8192];
+    uint32_t b[1024];
 };
+static_assert(sizeof(PctState) <= kPctStateBytes, "percentile state");
 
 __device__ __forceinline__ uint32_t f32_key(float f) {
     const uint32_t u = __float_as_uint(f);
@@ -2026,13 +2034,15 @@ __device__ __forceinline__ float key_f32(uint32_t k) {
     return __uint_as_float(u);
 }
 
-__device__ void pct_init_wg(PctState *st_, uint32_t k) {
+__device__ void pct_init_wg(PctState *st_, uint32_t k, int slot) {
     VLG_GLOBAL PctState *st = glb(st_);
-    for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->hist[i] = 0;
+    for (int i = threadIdx.x; i < 8192; i += blockDim.x) st->a[i] = 0;
+    for (int i = threadIdx.x; i < 1024; i += blockDim.x) st->b[i] = 0;
     if (threadIdx.x == 0) {
         st->prefix = 0;
         st->mask = 0;
         st->k = k;
+        st->src = (uint32_t)slot;
     }
 }
 
@@ -2047,7 +2057,8 @@ template <> struct Vec4<uint16_t> { typedef uint16_t type __attribute__((ext_vec
 // stride and i1 are multiples of 1024 or of the pitch, so four consecutive
 // elements share a row), for the n selections st[0..n): selections whose
 // digits chosen so far agree share one LDS histogram (in the first pass all
-// of them do), then every selection's histogram is added into its state.
+// of them do), which is then added into the state of the group's first
+// selection.
 // The streaming part of a histogram pass over elements [i0, i1): MG is the
 // number of groups the group test has to try (one in every first pass).
 template <typename T, int MG, bool NT>
@@ -2104,10 +2115,11 @@ __device__ __forceinline__ void pct_hist_stream(const Geo &g, const T *__restric
 }
 
 template <typename T, bool NT>
-__device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState *const *st, int n, int shift,
-                               int bins, int64_t i0, int64_t i1, int64_t stride, uint32_t (*h)[2048]) {
+__device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState *const *st, const int32_t *slot,
+                               int n, int pass, int shift, int bins, int64_t i0, int64_t i1, int64_t stride,
+                               uint32_t (*h)[2048]) {
     __shared__ uint32_t gpre[kMaxPctSel], gmask[kMaxPctSel];
-    __shared__ int rep[kMaxPctSel], ngroups;
+    __shared__ int rep[kMaxPctSel], first[kMaxPctSel], ngroups;
     if (threadIdx.x == 0) {
         int m = 0;
         for (int j = 0; j < n; j++) {
@@ -2118,11 +2130,14 @@ __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState
             if (r < 0) {
                 gpre[m] = p;
                 gmask[m] = mk;
+                first[m] = j;
                 r = m++;
             }
             rep[j] = r;
         }
         ngroups = m;
+        // (every workgroup writes the same values)
+        for (int j = 0; j < n; j++) glb(st[j])->src = (uint32_t)slot[first[rep[j]]];
     }
     __syncthreads();
     // the group table in registers: the histogram atomics below write LDS, so
@@ -2134,30 +2149,36 @@ __device__ void pct_hist_range(const Geo &g, const T *__restrict__ img, PctState
         pre[q] = q < m ? gpre[q] : 0u;
         msk[q] = q < m ? gmask[q] : 0u;
     }
-    for (int q = 0; q < m; q++)
-        for (int i = threadIdx.x; i < bins; i += kThreads) h[q][i] = 0;
+    // group q's bins at q * 2048 (a single group may take all 8192)
+    uint32_t *hh = &h[0][0];
+    for (int i = threadIdx.x; i < (m - 1) * 2048 + bins; i += kThreads) hh[i] = 0;
     __syncthreads();
     if (m == 1)
         pct_hist_stream<T, 1, NT>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
     else
         pct_hist_stream<T, kMaxPctSel, NT>(g, img, m, pre, msk, shift, bins, i0, i1, stride, h);
     __syncthreads();
-    for (int j = 0; j < n; j++)
+    // each group's histogram into its first selection's state
+    for (int q = 0; q < m; q++) {
+        VLG_GLOBAL uint32_t *gh = pass == 1 ? glb(st[first[q]])->b : glb(st[first[q]])->a;
         for (int i = threadIdx.x; i < bins; i += kThreads) {
-            const uint32_t cnt = h[rep[j]][i];
-            if (cnt) __hip_atomic_fetch_add(&glb(st[j])->hist[i], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t cnt = hh[q * 2048 + i];
+            if (cnt) __hip_atomic_fetch_add(&gh[i], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    }
     __syncthreads();
 }
 
 // one workgroup of 256 threads: find the bucket holding rank k
-__device__ void pct_select_wg(PctState *st_, int shift, int bins, int last, int is_int, float *result_,
-                              uint32_t *part) {
+// (src: the state whose histogram the selection shares in this pass)
+__device__ void pct_select_wg(PctState *st_, const PctState *src, int pass, int shift, int bins, int last,
+                              int is_int, float *result_, uint32_t *part) {
     VLG_GLOBAL PctState *st = glb(st_);
     VLG_GLOBAL float *result = glb(result_);
+    const VLG_GLOBAL uint32_t *hist = pass == 1 ? glb(src)->b : glb(src)->a;
     const int per = bins / kThreads;
     uint32_t local = 0;
-    for (int j = 0; j < per; j++) local += st->hist[threadIdx.x * per + j];
+    for (int j = 0; j < per; j++) local += hist[threadIdx.x * per + j];
     part[threadIdx.x] = local;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -2165,14 +2186,16 @@ __device__ void pct_select_wg(PctState *st_, int shift, int bins, int last, int 
         int t = 0;
         while (t < kThreads - 1 && acc + part[t] <= k) acc += part[t++];
         int b = t * per;
-        while (b < t * per + per - 1 && acc + st->hist[b] <= k) acc += st->hist[b++];
+        while (b < t * per + per - 1 && acc + hist[b] <= k) acc += hist[b++];
         st->k = k - acc;
         st->prefix |= (uint32_t)b << shift;
         st->mask |= (uint32_t)(bins - 1) << shift;
         if (last) *result = is_int ? (float)st->prefix : key_f32(st->prefix);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2048; i += kThreads) st->hist[i] = 0;
+    // `a` is read only by the selections of passes 0 and 2: after pass 1 it
+    // is cleared for pass 2
+    if (pass == 1)
+        for (int i = threadIdx.x; i < 8192; i += kThreads) st->a[i] = 0;
     __syncthreads();
 }
 
@@ -2180,24 +2203,31 @@ __device__ __forceinline__ PctState *sstate(void *states, int slot) {
     return (PctState *)((char *)states + (size_t)slot * kPctStateBytes);
 }
 
-__global__ void k_pct_init(PctSel sel, void *states) { pct_init_wg(sstate(states, sel.slot[blockIdx.x]), sel.k[blockIdx.x]); }
+__global__ void k_pct_init(PctSel sel, void *states) {
+    pct_init_wg(sstate(states, sel.slot[blockIdx.x]), sel.k[blockIdx.x], sel.slot[blockIdx.x]);
+}
 
 template <typename T, bool NT>
 __global__ __launch_bounds__(kThreads) void k_pct_hist(Geo g, const T *__restrict__ img, PctSel sel, void *states,
-                                                       int shift, int bins) {
+                                                       int pass, int shift, int bins) {
     __shared__ uint32_t h[kMaxPctSel][2048];
     PctState *st[kMaxPctSel];
     for (int j = 0; j < sel.n; j++) st[j] = sstate(states, sel.slot[j]);
-    const int64_t n = (int64_t)g.H * g.wpr * 64;
-    pct_hist_range<T, NT>(g, img, st, sel.n, shift, bins, (int64_t)blockIdx.x * (kThreads * 4), n,
-                   (int64_t)gridDim.x * (kThreads * 4), h);
+    // one contiguous range of whole chunks per workgroup: neighbouring
+    // pixels share bins, so the histogram a workgroup adds into the state has
+    // fewer nonzero bins than that of a strided range
+    const int64_t n = (int64_t)g.H * g.wpr * 64, chunks = (n + kThreads * 4 - 1) / (kThreads * 4);
+    const int64_t per = (chunks + gridDim.x - 1) / gridDim.x * (kThreads * 4);
+    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    pct_hist_range<T, NT>(g, img, st, sel.slot, sel.n, pass, shift, bins, i0, i1, kThreads * 4, h);
 }
 
-__global__ __launch_bounds__(kThreads) void k_pct_select(PctSel sel, void *states, int shift, int bins, int last,
-                                                         int is_int, float *results) {
+__global__ __launch_bounds__(kThreads) void k_pct_select(PctSel sel, void *states, int pass, int shift, int bins,
+                                                         int last, int is_int, float *results) {
     __shared__ uint32_t part[kThreads];
     const int slot = sel.slot[blockIdx.x];
-    pct_select_wg(sstate(states, slot), shift, bins, last, is_int, results + slot, part);
+    PctState *st = sstate(states, slot);
+    pct_select_wg(st, sstate(states, (int)glb(st)->src), pass, shift, bins, last, is_int, results + slot, part);
 }
 
 // batch variants: state and result of percentile slot p live in each image's workspace
@@ -2210,14 +2240,15 @@ __global__ void kb_pct_init(BatchArgs a, PctSel sel) {
     for (int64_t u = ur.begin; u < ur.end; u++) {
         const int ii = ur.img(u);
         for (int j = 0; j < sel.n; j++) {
-            pct_init_wg(bstate(a.imgs[ii], sel.slot[j]), a.imgs[ii].ranks[sel.slot[j]]);
+            pct_init_wg(bstate(a.imgs[ii], sel.slot[j]), a.imgs[ii].ranks[sel.slot[j]], sel.slot[j]);
             __syncthreads();
         }
     }
 }
 
 template <typename T, bool NT>
-__global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, PctSel sel, int shift, int bins) {
+__global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, PctSel sel, int pass, int shift,
+                                                        int bins) {
     __shared__ uint32_t h[kMaxPctSel][2048];
     UnitRange ur(a.prefix, a.n);
     for (int64_t u = ur.begin; u < ur.end; u++) {
@@ -2228,20 +2259,23 @@ __global__ __launch_bounds__(kThreads) void kb_pct_hist(BatchArgs a, int chan, P
         const int64_t i0 = (u - a.prefix[ii]) * kPctUnit;
         const int64_t n = (int64_t)d.g.H * d.g.wpr * 64;
         const int64_t i1 = i0 + kPctUnit < n ? i0 + kPctUnit : n;
-        pct_hist_range<T, NT>(d.g, (const T *)(d.img + (int64_t)chan * d.chan_bytes), st, sel.n, shift, bins, i0, i1,
+        pct_hist_range<T, NT>(d.g, (const T *)(d.img + (int64_t)chan * d.chan_bytes), st, sel.slot, sel.n, pass, shift,
+                              bins, i0, i1,
                        kThreads * 4, h);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void kb_pct_select(BatchArgs a, PctSel sel, int shift, int bins, int last,
-                                                          int is_int) {
+__global__ __launch_bounds__(kThreads) void kb_pct_select(BatchArgs a, PctSel sel, int pass, int shift, int bins,
+                                                          int last, int is_int) {
     __shared__ uint32_t part[kThreads];
     const int slot = sel.slot[blockIdx.y];
     UnitRange ur(a.prefix, a.n);
     for (int64_t u = ur.begin; u < ur.end; u++) {
         const int ii = ur.img(u);
         const BImg d = a.imgs[ii];  // by value (see UnitRange)
-        pct_select_wg(bstate(d, slot), shift, bins, last, is_int, (float *)(d.ws + d.off_pct) + slot, part);
+        PctState *st = bstate(d, slot);
+        pct_select_wg(st, bstate(d, (int)glb(st)->src), pass, shift, bins, last, is_int,
+                      (float *)(d.ws + d.off_pct) + slot, part);
     }
 }
 
@@ -2255,28 +2289,28 @@ hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int 
     if (n == 0) return hipGetLastError();
     const int grid = grid_for(n, kThreads * 64, 2048);
     if (dtype == 1) {
-        if (n > kStreamBytes) k_pct_hist<uint8_t, true><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
-        else k_pct_hist<uint8_t, false><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 256);
-        k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, 0, 256, 1, 1, results);
+        if (n > kStreamBytes) k_pct_hist<uint8_t, true><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 0, 256);
+        else k_pct_hist<uint8_t, false><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 0, 256);
+        k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, 0, 0, 256, 1, 1, results);
         return hipGetLastError();
     }
     if (dtype == 2) {  // uint16: two 8-bit digits
         for (int p = 0; p < 2; p++) {
             if (2 * n > kStreamBytes)
-                k_pct_hist<uint16_t, true><<<grid, kThreads, 0, s>>>(g, (const uint16_t *)chan, sel, states, 8 - 8 * p, 256);
+                k_pct_hist<uint16_t, true><<<grid, kThreads, 0, s>>>(g, (const uint16_t *)chan, sel, states, p, 8 - 8 * p, 256);
             else
-                k_pct_hist<uint16_t, false><<<grid, kThreads, 0, s>>>(g, (const uint16_t *)chan, sel, states, 8 - 8 * p, 256);
-            k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, 8 - 8 * p, 256, p == 1, 1, results);
+                k_pct_hist<uint16_t, false><<<grid, kThreads, 0, s>>>(g, (const uint16_t *)chan, sel, states, p, 8 - 8 * p, 256);
+            k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, p, 8 - 8 * p, 256, p == 1, 1, results);
         }
         return hipGetLastError();
     }
-    const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
+    const int shifts[3] = {19, 9, 0}, bins[3] = {8192, 1024, 512};
     for (int p = 0; p < 3; p++) {
         if (4 * n > kStreamBytes)
-            k_pct_hist<float, true><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, shifts[p], bins[p]);
+            k_pct_hist<float, true><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, p, shifts[p], bins[p]);
         else
-            k_pct_hist<float, false><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, shifts[p], bins[p]);
-        k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, shifts[p], bins[p], p == 2, 0, results);
+            k_pct_hist<float, false><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, p, shifts[p], bins[p]);
+        k_pct_select<<<sel.n, kThreads, 0, s>>>(sel, states, p, shifts[p], bins[p], p == 2, 0, results);
     }
     return hipGetLastError();
 }
@@ -2291,24 +2325,24 @@ hipError_t launch_b_percentile(hipStream_t s, const BatchArgs &one, int64_t tota
     // a histogram unit is kPctUnit channel elements
     const bool nt = total_hist * kPctUnit * (hist.dtype == 1 ? 1 : hist.dtype == 2 ? 2 : 4) > kStreamBytes;
     if (hist.dtype == 1) {
-        if (nt) kb_pct_hist<uint8_t, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
-        else kb_pct_hist<uint8_t, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 256);
-        kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, 0, 256, 1, 1);
+        if (nt) kb_pct_hist<uint8_t, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 0, 256);
+        else kb_pct_hist<uint8_t, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, 0, 0, 256);
+        kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, 0, 0, 256, 1, 1);
         return hipGetLastError();
     }
     if (hist.dtype == 2) {  // uint16: two 8-bit digits
         for (int p = 0; p < 2; p++) {
-            if (nt) kb_pct_hist<uint16_t, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, 8 - 8 * p, 256);
-            else kb_pct_hist<uint16_t, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, 8 - 8 * p, 256);
-            kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, 8 - 8 * p, 256, p == 1, 1);
+            if (nt) kb_pct_hist<uint16_t, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, p, 8 - 8 * p, 256);
+            else kb_pct_hist<uint16_t, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, p, 8 - 8 * p, 256);
+            kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, p, 8 - 8 * p, 256, p == 1, 1);
         }
         return hipGetLastError();
     }
-    const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
+    const int shifts[3] = {19, 9, 0}, bins[3] = {8192, 1024, 512};
     for (int p = 0; p < 3; p++) {
-        if (nt) kb_pct_hist<float, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, shifts[p], bins[p]);
-        else kb_pct_hist<float, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, shifts[p], bins[p]);
-        kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, shifts[p], bins[p], p == 2, 0);
+        if (nt) kb_pct_hist<float, true><<<gh, kThreads, 0, s>>>(hist, chan, sel, p, shifts[p], bins[p]);
+        else kb_pct_hist<float, false><<<gh, kThreads, 0, s>>>(hist, chan, sel, p, shifts[p], bins[p]);
+        kb_pct_select<<<gs, kThreads, 0, s>>>(one, sel, p, shifts[p], bins[p], p == 2, 0);
     }
     return hipGetLastError();
 }
