@@ -1460,81 +1460,96 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_reseed(BatchArgs a, BRef sm, 
 #undef VLG_BATCH_IMG
 
 // ------------------------------------------------------------------ segments
-// Register r of the extended tile is sreg[r * NI + i], i = row * RW + col,
-// with image row r0 + row and image word w0 + col.
-__global__ __launch_bounds__(kThreads) void k_segment(Geo g, SegProg p, int TR, int TW, int ntx) {
-    extern __shared__ uint64_t sreg[];
-    const int RR = TR + 2 * p.halo, RW = TW + 2, NI = RR * RW;
-    const int tx = (int)(blockIdx.x % ntx), ty = (int)(blockIdx.x / ntx);
-    const int r0 = ty * TR - p.halo, w0 = tx * TW - 1;
-    const int tid = (int)threadIdx.x;
+// Lane tiles: one wave (a workgroup of its own) per tile of one word column
+// and 64 rows, the halo above and below included; lane l takes row r0 + l of
+// every register as three words, the column and its two neighbours.  The
+// registers live in LDS, each lane reading and writing only its own entries,
+// so no instruction needs a barrier; N takes the rows above and below from
+// the adjacent lanes by DPP.  64 - 2 * halo rows are stored.  The neighbour
+// words lose one bit per N at their far edge and the edge lanes one row, all
+// within the halo.
+//   LOAD    dst = ptr[a]
+//   AND/OR  dst = ((a ^ ia) OP (b ^ ib)) ^ io
+//   NEAR_*  dst = (N(a ^ ia) ^ io) OP (b ^ ib), N over the image's pixels only
+//           (operand words outside the image and padding bits are background)
+//   STORE   ptr[dst] = a ^ ia over the tile's centre (padding bits cleared)
+__device__ __forceinline__ uint64_t lane_prev64(uint64_t v) {
+    return (uint64_t)(uint32_t)lane_prev((int)(uint32_t)v) | ((uint64_t)(uint32_t)lane_prev((int)(v >> 32)) << 32);
+}
+__device__ __forceinline__ uint64_t lane_next64(uint64_t v) {
+    return (uint64_t)(uint32_t)lane_next((int)(uint32_t)v) | ((uint64_t)(uint32_t)lane_next((int)(v >> 32)) << 32);
+}
+
+__global__ __launch_bounds__(64) void k_segment_lane(Geo g, SegProg p, int nty) {
+    extern __shared__ uint64_t lreg[];  // [register][word l, c, r][lane]
+    const int tile = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x, TR = 64 - 2 * p.halo;
+    const int tx = tile % g.wpr, ty = tile / g.wpr;
+    const int row = ty * TR - p.halo + lane;
+    const bool rin = row >= 0 && row < g.H;
+    // the image's pixels among the lane's three words (background elsewhere)
+    const uint64_t ml = rin && tx >= 1 ? ~0ull : 0ull;
+    const uint64_t mc = rin ? (tx == g.wpr - 1 ? g.tail : ~0ull) : 0ull;
+    const uint64_t mr = rin && tx + 1 < g.wpr ? (tx + 1 == g.wpr - 1 ? g.tail : ~0ull) : 0ull;
+    auto at = [&](int x, int w) -> uint64_t & { return lreg[(x * 3 + w) * 64 + lane]; };
     // the leading loads, all in flight together
     int nl = 0;
     while (nl < p.nins && p.ins[nl].op == SEG_LOAD) nl++;
-    for (int i = tid; i < NI; i += kThreads) {
-        const int row = r0 + i / RW, w = w0 + i % RW;
-        const bool in = row >= 0 && row < g.H && w >= 0 && w < g.wpr;
-        const int64_t idx = in ? (int64_t)row * g.wpr + w : 0;
-        uint64_t v[kSegMaxRegs];
+    {
+        const int64_t base = rin ? (int64_t)row * g.wpr + tx : 0;
+        uint64_t v[kSegMaxRegs][3];
 #pragma unroll
         for (int j = 0; j < kSegMaxRegs; j++)
-            if (j < nl) v[j] = in ? glb(p.ptr[p.ins[j].a])[idx] : 0ull;
+            if (j < nl) {
+                const VLG_GLOBAL uint64_t *src = glb(p.ptr[p.ins[j].a]);
+                v[j][0] = ml ? src[base - 1] : 0ull;
+                v[j][1] = rin ? src[base] : 0ull;
+                v[j][2] = mr ? src[base + 1] : 0ull;
+            }
 #pragma unroll
         for (int j = 0; j < kSegMaxRegs; j++)
-            if (j < nl) sreg[p.ins[j].dst * NI + i] = v[j];
+            if (j < nl)
+                for (int w = 0; w < 3; w++) at(p.ins[j].dst, w) = v[j][w];
     }
-    __syncthreads();
     for (int k = nl; k < p.nins; k++) {
         const SegIns in = p.ins[k];
         const uint64_t ia = (in.inv & 1) ? ~0ull : 0ull, ib = (in.inv & 2) ? ~0ull : 0ull,
                        io = (in.inv & 4) ? ~0ull : 0ull;
-        const uint64_t *A = in.a != kSegNone ? sreg + in.a * NI : nullptr;
-        const uint64_t *B = in.b != kSegNone ? sreg + in.b * NI : nullptr;
+        const bool ha = in.a != kSegNone, hb = in.b != kSegNone;  // (kSegNone: the all-zero mask)
         if (in.op == SEG_STORE) {
-            // every thread stores the register entries it owns (the same
-            // entries it writes in every other instruction), so a later
-            // instruction that reuses the register needs no barrier first
-            VLG_GLOBAL uint64_t *out = glb(p.ptr[in.dst]);
-            for (int i = tid; i < NI; i += kThreads) {
-                const int rr = i / RW, cc = i - rr * RW;
-                if (rr < p.halo || rr >= p.halo + TR || cc < 1 || cc > TW) continue;
-                const int row = r0 + rr, w = w0 + cc;
-                if (row >= g.H || w >= g.wpr) continue;
-                const uint64_t v = (A ? A[i] : 0ull) ^ ia;
-                out[(int64_t)row * g.wpr + w] = w == g.wpr - 1 ? (v & g.tail) : v;
+            if (lane >= p.halo && lane < p.halo + TR && rin) {
+                const uint64_t v = (ha ? at(in.a, 1) : 0ull) ^ ia;
+                glb(p.ptr[in.dst])[(int64_t)row * g.wpr + tx] = tx == g.wpr - 1 ? (v & g.tail) : v;
             }
             continue;
         }
-        uint64_t *D = sreg + in.dst * NI;
+        const uint64_t al = (ha ? at(in.a, 0) : 0ull) ^ ia, ac = (ha ? at(in.a, 1) : 0ull) ^ ia,
+                       ar = (ha ? at(in.a, 2) : 0ull) ^ ia;
+        const uint64_t bl = (hb ? at(in.b, 0) : 0ull) ^ ib, bc = (hb ? at(in.b, 1) : 0ull) ^ ib,
+                       br = (hb ? at(in.b, 2) : 0ull) ^ ib;
+        uint64_t dl, dc, dr;
         if (in.op == SEG_AND || in.op == SEG_OR) {
-            for (int i = tid; i < NI; i += kThreads) {
-                const uint64_t x = (A ? A[i] : 0ull) ^ ia, y = (B ? B[i] : 0ull) ^ ib;
-                D[i] = (in.op == SEG_OR ? (x | y) : (x & y)) ^ io;
-            }
+            const bool o = in.op == SEG_OR;
+            dl = (o ? (al | bl) : (al & bl)) ^ io;
+            dc = (o ? (ac | bc) : (ac & bc)) ^ io;
+            dr = (o ? (ar | br) : (ar & br)) ^ io;
         } else {
-            // N over the image's pixels only: operand words outside the image
-            // and padding bits count as background
-            for (int i = tid; i < NI; i += kThreads) {
-                const int rr = i / RW, cc = i - rr * RW;
-                auto val = [&](int r, int c) -> uint64_t {
-                    const int row = r0 + r, w = w0 + c;
-                    if (r < 0 || r >= RR || c < 0 || c >= RW || row < 0 || row >= g.H || w < 0 || w >= g.wpr)
-                        return 0ull;
-                    const uint64_t v = (A ? A[r * RW + c] : 0ull) ^ ia;
-                    return w == g.wpr - 1 ? (v & g.tail) : v;
-                };
-                uint64_t n = 0;
-#pragma unroll
-                for (int dr = -1; dr <= 1; dr++) {
-                    const uint64_t c = val(rr + dr, cc), l = val(rr + dr, cc - 1), r = val(rr + dr, cc + 1);
-                    n |= c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
-                }
-                n ^= io;
-                const uint64_t z = (B ? B[i] : 0ull) ^ ib;
-                D[i] = in.op == SEG_NEAR_OR ? (n | z) : (n & z);
-            }
+            // N over the image's pixels only
+            const uint64_t xl = al & ml, xc = ac & mc, xr = ar & mr;
+            const uint64_t hl = xl | (xl << 1) | (xl >> 1) | (xc << 63);
+            const uint64_t hc = xc | (xc << 1) | (xc >> 1) | (xl >> 63) | (xr << 63);
+            const uint64_t hr = xr | (xr << 1) | (xr >> 1) | (xc >> 63);
+            const uint64_t nl_ = (hl | lane_prev64(hl) | lane_next64(hl)) ^ io;
+            const uint64_t nc = (hc | lane_prev64(hc) | lane_next64(hc)) ^ io;
+            const uint64_t nr = (hr | lane_prev64(hr) | lane_next64(hr)) ^ io;
+            const bool o = in.op == SEG_NEAR_OR;
+            dl = o ? (nl_ | bl) : (nl_ & bl);
+            dc = o ? (nc | bc) : (nc & bc);
+            dr = o ? (nr | br) : (nr & br);
         }
-        __syncthreads();
+        at(in.dst, 0) = dl;
+        at(in.dst, 1) = dc;
+        at(in.dst, 2) = dr;
     }
 }
 
@@ -1542,7 +1557,7 @@ __global__ __launch_bounds__(kThreads) void k_segment(Geo g, SegProg p, int TR, 
 // each side), so lane l of every wave owns column l of the rows it is given
 // (rows wave, wave + 8, ...); left and right neighbour words come from the
 // adjacent lanes, the rows above and below from LDS.  Row r of register x is
-// sreg[x * NI + r * 64 + lane].  Same instruction semantics as k_segment.
+// sreg[x * NI + r * 64 + lane].  Same instruction semantics as k_segment_lane.
 constexpr int kSegWideThreads = 512;
 constexpr int kSegWideWaves = kSegWideThreads / 64;
 constexpr int kSegWideTW = 62;
@@ -1818,10 +1833,14 @@ hipError_t launch_unpack(hipStream_t s, const Geo &g, const uint64_t *mask, uint
 // Tile of a segment: the shape with the least halo overhead among those that
 // fit the LDS budget and leave at least kMinSegTiles tiles (or the most tiles
 // when no shape leaves that many).  Wide tiles (62 words, k_segment_wide)
-// count only the words of the image they cover.
+// count only the words of the image they cover.  When a narrow shape (1-16
+// words) wins, the segment runs on lane tiles instead (k_segment_lane: one
+// word column, 64 - 2 * halo rows per wave), which replaced narrow LDS tiles.
 constexpr size_t kSegLdsBudget = 48 * 1024;
 constexpr size_t kSegWideLdsBudget = 64 * 1024;
 constexpr int64_t kMinSegTiles = 1024;
+// lane tiles store at least 16 of their 64 rows
+constexpr int kLaneSegMaxHalo = 24;
 SegTile seg_tile(const Geo &g, int halo, int nregs) {
     SegTile best{4, 1, 0};
     double best_score = -1.0;
@@ -1855,12 +1874,15 @@ hipError_t launch_segment(hipStream_t s, const Geo &g, const SegProg &p) {
         return hipErrorInvalidValue;
     const SegTile t = seg_tile(g, p.halo, p.nregs);
     const int ntx = (g.wpr + t.tw - 1) / t.tw, nty = (g.H + t.tr - 1) / t.tr;
-    if (t.tw == kSegWideTW) {
+    if (t.tw != kSegWideTW) {
+        // lane tiles: one wave per word column and 64 - 2 * halo rows
+        if (p.halo > kLaneSegMaxHalo) return hipErrorInvalidValue;
+        const int lnty = (g.H + (64 - 2 * p.halo) - 1) / (64 - 2 * p.halo);
+        const size_t lds = (size_t)p.nregs * 3 * 64 * 8;
+        k_segment_lane<<<(int)((int64_t)g.wpr * lnty), 64, lds, s>>>(g, p, lnty);
+    } else {
         if (t.lds_bytes > kSegWideLdsBudget) return hipErrorInvalidValue;
         k_segment_wide<<<ntx * nty, kSegWideThreads, t.lds_bytes, s>>>(g, p, t.tr, ntx);
-    } else {
-        if (t.lds_bytes > kSegLdsBudget) return hipErrorInvalidValue;
-        k_segment<<<ntx * nty, kThreads, t.lds_bytes, s>>>(g, p, t.tr, t.tw, ntx);
     }
     return hipGetLastError();
 }

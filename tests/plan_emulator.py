@@ -12,11 +12,12 @@ segment programs can be checked against the oracle on the CPU:
   near                  (N(x ^ ix) ^ io) OP (z ^ iz) over the image's pixels
   ccl_local/gather/...  labelling of the passable mask with 8-connectivity
                         (scipy), seed flags per labelling user
-  segment               the tile program of k_segment: tiles of TR rows x TW
-                        words chosen as the launcher chooses them, extended by
-                        the halo rows and one word on each side, registers
-                        per tile, the same operand masking, stores of the tile
-                        centre only
+  segment               the tile program of the segment kernels: tiles of TR
+                        rows x TW words chosen as the launcher chooses them
+                        (wide tiles of 62 words, or lane tiles of one word and
+                        64 - 2 halo rows), extended by the halo rows and one
+                        word on each side, registers per tile, the same
+                        operand masking, stores of the tile centre only
 
 Nothing here is shared with the library or the oracle.
 """
@@ -259,7 +260,8 @@ class Emulator:
 
 def seg_tile(g, halo, nregs, budget=48 * 1024, wide_budget=64 * 1024, min_tiles=1024):
     """The launcher's tile choice for a segment (same rule, restated): wide
-    tiles of 62 words in 64-word LDS rows, or narrow tiles of 1-16 words."""
+    tiles of 62 words in 64-word LDS rows, or, where a narrow shape of 1-16
+    words scores best, lane tiles of one word and 64 - 2 halo rows."""
     best, best_score = (4, 1), -1.0
 
     def consider(tr, tw, useful_w, rw):
@@ -279,4 +281,4 @@ def seg_tile(g, halo, nregs, budget=48 * 1024, wide_budget=64 * 1024, min_tiles=
         for tr in (4, 8, 16, 32):
             if nregs * (tr + 2 * halo) * (tw + 2) * 8 <= budget:
                 consider(tr, tw, tw, tw + 2)
-    return best
+    return best if best[1] == 62 else (64 - 2 * halo, 1)
