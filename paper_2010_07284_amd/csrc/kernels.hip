@@ -1482,7 +1482,9 @@ __device__ __forceinline__ uint64_t lane_next64(uint64_t v) {
 
 __global__ __launch_bounds__(64) void k_segment_lane(Geo g, SegProg p, int nty) {
     extern __shared__ uint64_t lreg[];  // [register][word l, c, r][lane]
-    const int tile = (int)blockIdx.x;
+    // each XCD takes a contiguous range of tiles, so the neighbour words and
+    // halo rows that adjacent tiles load again come from that XCD's L2
+    const int tile = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
     const int lane = (int)threadIdx.x, TR = 64 - 2 * p.halo;
     const int tx = tile % g.wpr, ty = tile / g.wpr;
     const int row = ty * TR - p.halo + lane;
