@@ -961,17 +961,21 @@ __device__ __forceinline__ void ccl_flag_walk(VLG_GLOBAL int32_t *glab, VLG_GLOB
 // of their flag bytes, then a walk for each border-touching local root among
 // them (bit0 of its byte).  A byte that another walker rewrites after the
 // load is either a final root (the walk ends at once) or unchanged.
-__device__ __forceinline__ void ccl_flag16(int32_t *glab_, uint8_t *gflag_, int64_t nb, int64_t i0, int cap,
+template <int N>
+__device__ __forceinline__ void ccl_flag_n(int32_t *glab_, uint8_t *gflag_, int64_t nb, int64_t i0, int cap,
                                            bool &ok) {
+    static_assert(N == 4 || N == 16, "4 or 16 blocks per thread");
     VLG_GLOBAL int32_t *glab = glb(glab_);
     VLG_GLOBAL uint8_t *gflag = glb(gflag_);
     uint64_t lo = 0, hi = 0;
-    if (i0 + 16 <= nb && ((uintptr_t)(gflag_ + i0) & 7) == 0) {
+    if (N == 16 && i0 + 16 <= nb && ((uintptr_t)(gflag_ + i0) & 7) == 0) {
         const VLG_GLOBAL uint64_t *q = (const VLG_GLOBAL uint64_t *)(gflag + i0);
         lo = q[0];
         hi = q[1];
+    } else if (N == 4 && i0 + 4 <= nb && ((uintptr_t)(gflag_ + i0) & 3) == 0) {
+        lo = *(const VLG_GLOBAL uint32_t *)(gflag + i0);
     } else {
-        for (int k = 0; k < 16 && i0 + k < nb; k++) {
+        for (int k = 0; k < N && i0 + k < nb; k++) {
             const uint64_t v = gflag[i0 + k];
             if (k < 8)
                 lo |= v << (8 * k);
@@ -1184,11 +1188,17 @@ __global__ __launch_bounds__(kThreads) void k_ccl_merge(Geo g, MRef b, int ntx, 
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag, LoopGuard gd) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads * 16;
+// per: blocks per thread, 4 on small images (more threads walk at once) or 16
+__global__ __launch_bounds__(kThreads) void k_ccl_flag(int64_t nblocks, int32_t *glab, uint8_t *gflag, LoopGuard gd,
+                                                       int per) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads * per;
     bool ok = true;
-    for (int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 16; i0 < nblocks; i0 += stride)
-        ccl_flag16(glab, gflag, nblocks, i0, gd.cap, ok);
+    for (int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * per; i0 < nblocks; i0 += stride) {
+        if (per == 4)
+            ccl_flag_n<4>(glab, gflag, nblocks, i0, gd.cap, ok);
+        else
+            ccl_flag_n<16>(glab, gflag, nblocks, i0, gd.cap, ok);
+    }
     guard_report(gd, ok);
 }
 
@@ -1239,7 +1249,7 @@ __global__ __launch_bounds__(kThreads) void k_ccl_flag_multi(int64_t nblocks, Cc
     const int64_t stride = (int64_t)gridDim.x * kThreads * 16;
     bool ok = true;
     for (int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 16; i0 < nblocks; i0 += stride)
-        ccl_flag16(m.glab[l], m.gflag[l], nblocks, i0, gd.cap, ok);
+        ccl_flag_n<16>(m.glab[l], m.gflag[l], nblocks, i0, gd.cap, ok);
     guard_report(gd, ok);
 }
 
@@ -1426,7 +1436,7 @@ __global__ __launch_bounds__(kThreads) void kb_ccl_flag(BatchArgs a) {
     VLG_BATCH_LOOP(a) {
         VLG_BATCH_IMG(a)
         const int64_t i0 = ((u_ - a.prefix[ii]) * kThreads + threadIdx.x) * 16, nb = (int64_t)d.g.BH * d.g.BW;
-        if (i0 < nb) ccl_flag16((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), nb, i0, a.guard.cap, ok);
+        if (i0 < nb) ccl_flag_n<16>((int32_t *)(d.ws + d.off_glab), (uint8_t *)(d.ws + d.off_gflag), nb, i0, a.guard.cap, ok);
     }
     guard_report(a.guard, ok);
 }
@@ -1731,7 +1741,10 @@ hipError_t launch_ccl_merge(hipStream_t s, const Geo &g, MRef b, const CclWork &
 hipError_t launch_ccl_flag(hipStream_t s, const Geo &g, const CclWork &w) {
     if (g.nwords == 0) return hipSuccess;
     const int64_t nb = (int64_t)g.BH * g.BW;
-    k_ccl_flag<<<grid_for((nb + 15) / 16, kThreads, 65536), kThreads, 0, s>>>(nb, w.glab, w.gflag, w.guard);
+    // four blocks per thread unless sixteen still give 1024 workgroups
+    const int per = nb >= (int64_t)16 * kThreads * 1024 ? 16 : 4;
+    k_ccl_flag<<<grid_for((nb + per - 1) / per, kThreads, 65536), kThreads, 0, s>>>(nb, w.glab, w.gflag, w.guard,
+                                                                                    per);
     return hipGetLastError();
 }
 
