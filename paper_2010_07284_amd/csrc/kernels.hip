@@ -2324,7 +2324,9 @@ hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int 
     k_pct_init<<<sel.n, kThreads, 0, s>>>(sel, states);
     const int64_t n = (int64_t)g.H * g.wpr * 64;
     if (n == 0) return hipGetLastError();
-    const int grid = grid_for(n, kThreads * 64, 2048);
+    // at least 32 chunks of 1024 elements per workgroup, so that clearing and
+    // adding its histogram (up to 8192 bins) stays small next to its reads
+    const int grid = grid_for(n, kThreads * 4 * 32, 2048);
     if (dtype == 1) {
         if (n > kStreamBytes) k_pct_hist<uint8_t, true><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 0, 256);
         else k_pct_hist<uint8_t, false><<<grid, kThreads, 0, s>>>(g, (const uint8_t *)chan, sel, states, 0, 0, 256);
