@@ -378,7 +378,7 @@ namespace vlg {
 // select over order-preserving uint32 keys, several ranks of one channel per
 // pass over it.  Slot p has kPctStateBytes of device state at
 // states + p * kPctStateBytes; its value is written to results[p].
-constexpr size_t kPctStateBytes = 37120;
+constexpr size_t kPctStateBytes = 41216;
 hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int dtype, const PctSel &sel,
                              void *states, float *results);
 }  // namespace vlg

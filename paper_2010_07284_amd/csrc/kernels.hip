@@ -2044,9 +2044,11 @@ hipError_t launch_b_ccl_reseed(hipStream_t s, const BatchArgs &a, int64_t total,
 // (negatives complemented, positives with the sign bit set) or the uint8
 // values.  Each pass histograms one digit of the keys that agree with the
 // digits chosen so far, then a single workgroup finds the bucket holding rank
-// k.  float32 uses digits of 13, 10 and 9 bits (the first pass has a single
-// group, so its histogram takes the LDS of all four); uint8 one digit of 8
-// bits, uint16 two.
+// k.  float32 uses digits of 13, 10 and 9 bits in batches (the first pass
+// has a single group, so its histogram takes the LDS of all four) and 11, 11
+// and 10 bits on single images (whose workgroups read fewer elements, so a
+// wider histogram to clear and add costs more than its fewer LDS conflicts
+// save); uint8 one digit of 8 bits, uint16 two.
 namespace vlg {
 namespace {
 
@@ -2057,7 +2059,7 @@ namespace {
 struct PctState {
     uint32_t prefix, mask, k, src;
     uint32_t a[8192];
-    uint32_t b[1024];
+    uint32_t b[2048];
 };
 static_assert(sizeof(PctState) <= kPctStateBytes, "percentile state");
 
@@ -2074,7 +2076,7 @@ __device__ __forceinline__ float key_f32(uint32_t k) {
 __device__ void pct_init_wg(PctState *st_, uint32_t k, int slot) {
     VLG_GLOBAL PctState *st = glb(st_);
     for (int i = threadIdx.x; i < 8192; i += blockDim.x) st->a[i] = 0;
-    for (int i = threadIdx.x; i < 1024; i += blockDim.x) st->b[i] = 0;
+    for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->b[i] = 0;
     if (threadIdx.x == 0) {
         st->prefix = 0;
         st->mask = 0;
@@ -2343,7 +2345,7 @@ hipError_t launch_percentile(hipStream_t s, const Geo &g, const void *chan, int 
         }
         return hipGetLastError();
     }
-    const int shifts[3] = {19, 9, 0}, bins[3] = {8192, 1024, 512};
+    const int shifts[3] = {21, 10, 0}, bins[3] = {2048, 2048, 1024};
     for (int p = 0; p < 3; p++) {
         if (4 * n > kStreamBytes)
             k_pct_hist<float, true><<<grid, kThreads, 0, s>>>(g, (const float *)chan, sel, states, p, shifts[p], bins[p]);
