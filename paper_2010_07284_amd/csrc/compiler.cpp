@@ -1093,7 +1093,7 @@ void schedule_fused(Lower &L, int lanes) {
             finish(u);
         }
         {
-            // this round's arithmetic atoms after its other steps (all of them
+            // this scheduling round's arithmetic atoms after its other steps (all of them
             // were ready together, so none reads another), in groups that one
             // launch evaluates: the channels are then read once per group
             std::stable_partition(out.begin() + pct_round_start, out.end(),
